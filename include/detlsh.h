@@ -1,0 +1,242 @@
+/*
+ * detlsh.h - C ABI of the MI355X (gfx950) DET-LSH indexing-and-query library.
+ *
+ * DET-LSH (Wei, Peng, Lee, Palpanas; PVLDB 17(9), 2024) answers c^2-k-ANN
+ * queries (Def. 2, Sec. 3.1) over a set D of n points in R^d under Euclidean
+ * distance.  The library implements its hot path on one GPU:
+ *
+ *   encoding phase  (Sec. 4.1, Eq. 1, Alg. 1, Alg. 2)  L*K Gaussian projections,
+ *                   equal-frequency breakpoints from a sample, uint8 region codes
+ *   indexing phase  (Sec. 4.2, Alg. 3)                  one DE-Tree per projected
+ *                   space, stored as leaf runs of a permutation of the points
+ *   query phase     (Sec. 4.3, Alg. 4-7, Sec. 5.2)      range query with region
+ *                   lower bounds over the L spaces, growing radius, exact
+ *                   verification of the candidates and top-k
+ *
+ * General conventions
+ *  - Every function returns detlsh_status; DETLSH_OK == 0.  On failure the
+ *    thread-local message returned by detlsh_last_error() says why.  No C++
+ *    exception crosses this interface.
+ *  - "device" pointers are HIP device allocations of the current device (for
+ *    example torch CUDA tensors on ROCm); "host" pointers are ordinary memory.
+ *    A host pointer where a device pointer is required gives DETLSH_EINVAL.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call that
+ *    takes a stream returns only after its results are complete (it
+ *    synchronises `stream`), so inputs may be freed and outputs read as soon
+ *    as it returns.
+ *  - Matrices are row-major and densely packed unless stated otherwise.
+ *  - An index is read-only after it is built: any number of threads may call
+ *    detlsh_query on it concurrently, each with its own stream; every call
+ *    allocates its own workspace.  detlsh_free must not race with queries.
+ */
+#ifndef DETLSH_H
+#define DETLSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct detlsh_index_s* detlsh_index;
+
+typedef enum {
+    DETLSH_OK = 0,
+    DETLSH_EINVAL = 1,      /* an argument is out of range or of the wrong kind   */
+    DETLSH_ENOMEM = 2,      /* device or host memory could not be allocated       */
+    DETLSH_EBUSY = 3,       /* a wait timed out (serving)                         */
+    DETLSH_EDEVICE = 4,     /* a HIP call failed; the message names it            */
+    DETLSH_ECANCELED = 5,   /* the request was cancelled (serving)                */
+    DETLSH_EINTERNAL = 6    /* an internal invariant failed                        */
+} detlsh_status;
+
+/* Verification precision of a query (Sec. 4.3 exact verification). */
+enum {
+    DETLSH_FP32 = 0,        /* candidate distances in FP32, direct differences   */
+    DETLSH_BF16_RERANK = 1  /* BF16 distances (FP32 accumulate) keep the best
+                               rerank_mult*k, which are re-ranked exactly in FP32 */
+};
+
+/* Initial radius policy of Alg. 7. */
+enum {
+    DETLSH_RMIN_MAGIC = 0,  /* the smallest radius that satisfies both conditions of
+                               the "magic" r_min of Sec. 5.2: |S(r_min)| >= beta*n+k
+                               and |S(r_min/c)| < beta*n+k                         */
+    DETLSH_RMIN_FIXED = 1   /* Alg. 7 from the caller's r_min, radius r_min*c^t   */
+};
+
+/* ------------------------------------------------------------------------ */
+/* index build                                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t seed;              /* seed of the library's own draws of A and of the
+                                   sample when the two pointers below are NULL   */
+    int32_t max_leaf;           /* DE-Tree leaf capacity (Alg. 3 max_size); 0 -> 256 */
+    int32_t keep_bf16;          /* 1: keep a BF16 copy of X for DETLSH_BF16_RERANK */
+    int32_t proj_bf16;          /* 1: projection GEMM with BF16 inputs, FP32 sums  */
+    int32_t reserved;
+    const float* A;             /* host, (L*K) x d, row i*K+j = hash h_ij of Eq. 1,
+                                   entries N(0,1); NULL -> drawn from `seed`       */
+    const int64_t* sample_ids;  /* host, floor(sample_frac*n) distinct ids in [0,n)
+                                   used to choose breakpoints (Alg. 1); NULL ->
+                                   drawn uniformly without replacement from seed */
+} detlsh_build_opts;
+
+/*
+ * Build an index over X (device, n x d FP32).  Encoding phase (Sec. 4.1):
+ * projects every point with the L*K hashes h_ij(o) = a_ij . o (Eq. 1), selects
+ * N_r+1 breakpoints per projected dimension from the projections of
+ * floor(sample_frac*n) sampled points (evaluated in IEEE double) by sorting them (equal-frequency rule of
+ * Sec. 4.1, B(z) = the max(1, floor((z-1) n_s / N_r))-th smallest sampled value,
+ * B(1) = minimum, B(N_r+1) = maximum) and gives every coordinate the code
+ * #{z in 2..N_r : B(z) <= h} (Alg. 2; a value equal to a breakpoint belongs to
+ * the upper region).  Indexing phase (Alg. 3): for each of the L projected
+ * spaces, the points are ordered into leaf runs of a DE-Tree whose root has
+ * one child per vector of first code bits and whose overfull nodes are split
+ * on the dimension whose next bit divides them most evenly (Sec. 4.2).
+ *
+ * Limits (else DETLSH_EINVAL): n >= 1, d >= 1, K in {4, 8, 16, 32} and
+ * L in {1, 2, 4, 8} with L*K <= 64,
+ * N_r a power of two in [2, 256], 0 < sample_frac <= 1 with
+ * floor(sample_frac*n) >= N_r, n < 2^31.
+ * X is copied: the caller may free it when the call returns.  On success
+ * *out owns all of its device memory until detlsh_free.
+ */
+detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L,
+                                 int32_t K, int32_t N_r, double sample_frac,
+                                 const detlsh_build_opts* opts, void* stream,
+                                 detlsh_index* out);
+
+/*
+ * Build an index from given encoding-phase results instead of computing them:
+ * A (host, (L*K) x d), B (host, (L*K) x (N_r+1), B[e][z-1] = B_e(z)) and the
+ * codes (host, n x (L*K) uint8, column e = i*K + j).  The DE-Trees are built
+ * from the codes as in detlsh_build_index.  Used to feed the query phase with
+ * an encoding computed elsewhere.  Same limits and ownership as above.
+ */
+detlsh_status detlsh_index_import(const float* X, int64_t n, int32_t d, int32_t L,
+                                  int32_t K, int32_t N_r, const float* A,
+                                  const float* B, const uint8_t* codes,
+                                  const detlsh_build_opts* opts, void* stream,
+                                  detlsh_index* out);
+
+typedef struct {
+    int64_t n;
+    int32_t d, L, K, N_r;
+    int64_t n_s;                 /* breakpoint sample size                         */
+    int32_t max_leaf;
+    int32_t has_bf16;
+    int64_t n_leaves[8];         /* leaf runs per tree (first L entries valid)     */
+    size_t device_bytes;         /* device memory owned by the index               */
+} detlsh_info;
+
+detlsh_status detlsh_index_info(detlsh_index idx, detlsh_info* out);
+
+/*
+ * Copy encoding results to host buffers (any pointer may be NULL to skip it):
+ * A ((L*K) x d), B ((L*K) x (N_r+1)), codes (n x (L*K), column e = i*K+j) and
+ * the sample ids (n_s).
+ */
+detlsh_status detlsh_export(detlsh_index idx, float* A, float* B, uint8_t* codes,
+                            int64_t* sample_ids);
+
+/*
+ * Copy DE-Tree `tree` (0-based) to host buffers: perm (n ids in leaf order),
+ * leaf_start (n_leaves + 1 offsets into perm), leaf_lo / leaf_hi (n_leaves x K
+ * lowest / highest region code of each leaf's node, i.e. its bit prefixes).
+ * `cap` is the capacity of the leaf arrays in leaves; DETLSH_EINVAL if short.
+ */
+detlsh_status detlsh_export_tree(detlsh_index idx, int32_t tree, int32_t* perm,
+                                 int32_t* leaf_start, uint8_t* leaf_lo,
+                                 uint8_t* leaf_hi, int64_t cap);
+
+/*
+ * Projected coordinates of nq rows (device, nq x d) with the index's hashes:
+ * out (device, nq x (L*K) FP32), h_ij(q) = a_ij . q (Eq. 1).
+ */
+detlsh_status detlsh_project(detlsh_index idx, const float* Q, int64_t nq, float* out,
+                             void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* query                                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t precision;          /* DETLSH_FP32 (default) or DETLSH_BF16_RERANK       */
+    int32_t rerank_mult;        /* BF16 form keeps rerank_mult*k for the FP32 rerank;
+                                   0 -> 4                                             */
+    int32_t rmin_policy;        /* DETLSH_RMIN_MAGIC (default) or DETLSH_RMIN_FIXED  */
+    int32_t max_rounds;         /* FIXED: radius rounds before S = D; 0 -> 64        */
+    double r_min;               /* FIXED: initial radius, > 0                        */
+    size_t workspace_bytes;     /* per-call workspace budget; 0 -> 4 GiB             */
+} detlsh_query_opts;
+
+/*
+ * c^2-k-ANN query (Alg. 7) for nq rows of Q (device, nq x d FP32).
+ *
+ * The candidate predicate of tree i at radius r is LB_i(q,o)^2 <= (eps r)^2,
+ * where LB_i is the distance from the projected query to the cell of o in the
+ * i-th projected space (the box between the breakpoints around o's regions,
+ * Sec. 4.3; the lowest region is open below, the highest open above) and
+ * eps = sqrt(chi^2_{alpha1}(K)), alpha1 = e^{-1/L} (Lemma 3, Eq. 2).  Trees are
+ * added to S in order 1..L; the query stops as soon as
+ * |S| >= N_S = k + ceil(beta*n) (checked after every tree) or, after all L
+ * trees, when k points of S lie within c*r; otherwise r <- c*r.  Under
+ * DETLSH_RMIN_MAGIC the start radius is the smallest one satisfying both
+ * conditions of the magic r_min (Sec. 5.2), so the query ends in its first
+ * round.  If N_S >= n, S = D.
+ *
+ * out_ids (device, nq x k int64) and out_dists (device, nq x k FP32) receive
+ * the k members of S nearest to each query, ascending by (distance, id);
+ * N_S is computed in IEEE double from the double `beta` as k + ceil(beta*n);
+ * distances are Euclidean (not squared).  Limits: 1 <= k <= min(n, 1024)
+ * (BF16 form: rerank_mult*k <= 1024), c > 1, 0 <= beta <= 1, nq >= 0 (0 is a
+ * no-op), FIXED needs r_min > 0.
+ */
+detlsh_status detlsh_query(detlsh_index idx, const float* Q, int64_t nq, int32_t k,
+                           double c, double beta, const detlsh_query_opts* opts,
+                           int64_t* out_ids, float* out_dists, void* stream);
+
+/*
+ * detlsh_query with every intermediate exposed, for step-by-step checks.
+ * Qp (device, nq x (L*K) FP32) replaces the query projections when not NULL.
+ * For each query t it writes: cand_counts[t] = |S|; cand_ids[t*cand_cap + s]
+ * (device int32, s < min(|S|, cand_cap)) the members of S in no particular
+ * order;
+ * first_tree[t*cand_cap + s] the 1-based first tree whose range query
+ * admitted that member; thr[t] = the squared projected radius (eps r)^2 at
+ * which the query stopped; stop_tree[t] = tree after which it stopped
+ * (1-based); rounds[t] = radius rounds used.  Any of these pointers may be
+ * NULL.  Results are identical to detlsh_query's.
+ */
+detlsh_status detlsh_query_debug(detlsh_index idx, const float* Qp, const float* Q,
+                                 int64_t nq, int32_t k, double c, double beta,
+                                 const detlsh_query_opts* opts, int32_t* cand_ids,
+                                 int64_t cand_cap, int64_t* cand_counts,
+                                 int32_t* first_tree, float* thr, int32_t* stop_tree,
+                                 int32_t* rounds, int64_t* out_ids, float* out_dists,
+                                 void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* kernel timing                                                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * While enabled, every kernel launch of the library is bracketed by HIP events
+ * on the launch stream and its duration added to a per-kernel total.
+ * detlsh_profile_read copies up to `max` entries (name, launches, total ms)
+ * and returns their number in *count.  Process-wide; reset with `reset`.
+ */
+detlsh_status detlsh_profile_enable(int32_t on, int32_t reset);
+detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double* total_ms,
+                                  int32_t max, int32_t* count);
+
+void detlsh_free(detlsh_index idx);
+const char* detlsh_last_error(void);   /* thread-local; valid until the next call */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DETLSH_H */

@@ -1,0 +1,210 @@
+"""DET-LSH indexing-and-query hot path on one MI355X (gfx950).
+
+Python binding of the C ABI in include/detlsh.h.  It only marshals arguments:
+torch supplies device memory and the current stream; every step of the method
+runs in the HIP kernels of libdetlsh.so.  Nothing here computes on the CPU.
+
+    import paper_2406_10938_amd as dl
+    idx = dl.build_index(X, L=4, K=16, N_r=256, sample_frac=0.01)
+    ids, dists = idx.query(Q, k=10, c=1.5, beta=0.1)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import BF16_RERANK, FP32, RMIN_FIXED, RMIN_MAGIC, DetlshError, check, lib
+
+__all__ = ["build_index", "import_index", "Index", "DetlshError", "FP32", "BF16_RERANK", "RMIN_MAGIC",
+           "RMIN_FIXED", "profile_enable", "profile_read"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(x, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.asarray(x, np.float32))
+    if x.device.type != "cuda":
+        x = x.to("cuda")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return x.contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep):
+    o = _lib.BuildOpts()
+    o.seed = int(seed)
+    o.max_leaf = int(max_leaf)
+    o.keep_bf16 = int(bool(keep_bf16))
+    o.proj_bf16 = int(bool(proj_bf16))
+    if A is not None:
+        a = np.ascontiguousarray(A, np.float32)
+        keep.append(a)
+        o.A = a.ctypes.data_as(C.POINTER(C.c_float))
+    if sample_ids is not None:
+        s = np.ascontiguousarray(sample_ids, np.int64)
+        keep.append(s)
+        o.sample_ids = s.ctypes.data_as(C.POINTER(C.c_int64))
+    return o
+
+
+def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes):
+    o = _lib.QueryOpts()
+    o.precision = int(precision)
+    o.rerank_mult = int(rerank_mult)
+    o.rmin_policy = int(rmin_policy)
+    o.r_min = float(r_min)
+    o.max_rounds = int(max_rounds)
+    o.workspace_bytes = int(workspace_bytes)
+    return o
+
+
+class Index:
+    """A built DET-LSH index resident in HBM (owned by the library)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().detlsh_free(self._h)
+            self._h = None
+
+    @property
+    def info(self) -> dict:
+        inf = _lib.Info()
+        check(lib().detlsh_index_info(self._h, C.byref(inf)))
+        return {"n": inf.n, "d": inf.d, "L": inf.L, "K": inf.K, "N_r": inf.N_r, "n_s": inf.n_s,
+                "max_leaf": inf.max_leaf, "has_bf16": bool(inf.has_bf16),
+                "n_leaves": list(inf.n_leaves[:inf.L]), "device_bytes": inf.device_bytes}
+
+    def project(self, Q):
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        inf = self.info
+        out = torch.empty((Q.shape[0], inf["L"] * inf["K"]), dtype=torch.float32, device=Q.device)
+        check(lib().detlsh_project(self._h, _ptr(Q), Q.shape[0], _ptr(out), _stream_ptr()))
+        return out
+
+    def query(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC,
+              r_min=0.0, max_rounds=0, workspace_bytes=0):
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        nq = Q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes)
+        check(lib().detlsh_query(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
+                                 _ptr(dists), _stream_ptr()))
+        return ids, dists
+
+    def query_debug(self, Q, k, c=1.5, beta=0.1, Qp=None, cand_cap=None, precision=FP32, rerank_mult=4,
+                    rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0):
+        """Query that also returns S, first trees, thr, stop tree and rounds."""
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        nq = Q.shape[0]
+        inf = self.info
+        cap = int(cand_cap or inf["n"])
+        dev = Q.device
+        ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        cand = torch.full((nq, cap), -1, dtype=torch.int32, device=dev)
+        counts = torch.zeros(nq, dtype=torch.int64, device=dev)
+        first = torch.zeros((nq, cap), dtype=torch.int32, device=dev)
+        thr = torch.zeros(nq, dtype=torch.float32, device=dev)
+        stop = torch.zeros(nq, dtype=torch.int32, device=dev)
+        rounds = torch.zeros(nq, dtype=torch.int32, device=dev)
+        qp_ptr = C.c_void_p(0)
+        if Qp is not None:
+            Qp = _dev_f32(Qp, "Qp")
+            qp_ptr = _ptr(Qp)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes)
+        check(lib().detlsh_query_debug(self._h, qp_ptr, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o),
+                                       _ptr(cand), cap, _ptr(counts), _ptr(first), _ptr(thr), _ptr(stop),
+                                       _ptr(rounds), _ptr(ids), _ptr(dists), _stream_ptr()))
+        return {"ids": ids, "dists": dists, "cand": cand, "counts": counts, "first_tree": first, "thr": thr,
+                "stop_tree": stop, "rounds": rounds}
+
+    def export(self):
+        """Host copies of A, B, codes (n x L*K) and the sample ids."""
+        inf = self.info
+        LK = inf["L"] * inf["K"]
+        A = np.empty((LK, inf["d"]), np.float32)
+        B = np.empty((LK, inf["N_r"] + 1), np.float32)
+        codes = np.empty((inf["n"], LK), np.uint8)
+        sample = np.empty(max(inf["n_s"], 1), np.int64)
+        check(lib().detlsh_export(self._h, A.ctypes.data_as(C.c_void_p), B.ctypes.data_as(C.c_void_p),
+                                  codes.ctypes.data_as(C.c_void_p), sample.ctypes.data_as(C.c_void_p)))
+        return {"A": A, "B": B, "codes": codes, "sample_ids": sample[:inf["n_s"]]}
+
+    def tree(self, i):
+        """DE-Tree i as (perm, leaf_start, leaf_lo, leaf_hi) host arrays."""
+        inf = self.info
+        nl = inf["n_leaves"][i]
+        perm = np.empty(inf["n"], np.int32)
+        start = np.empty(nl + 1, np.int32)
+        lo = np.empty((max(nl, 1), inf["K"]), np.uint8)
+        hi = np.empty((max(nl, 1), inf["K"]), np.uint8)
+        check(lib().detlsh_export_tree(self._h, int(i), perm.ctypes.data_as(C.c_void_p),
+                                       start.ctypes.data_as(C.c_void_p), lo.ctypes.data_as(C.c_void_p),
+                                       hi.ctypes.data_as(C.c_void_p), max(nl, 1)))
+        return perm, start, lo[:nl], hi[:nl]
+
+
+def build_index(X, L=4, K=16, N_r=256, sample_frac=0.01, A=None, sample_ids=None, seed=0, max_leaf=256,
+                keep_bf16=False, proj_bf16=False) -> Index:
+    """Encoding and indexing phases over X (n x d float32, device or host)."""
+    X = _dev_f32(X, "X")
+    keep = []
+    o = _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep)
+    h = C.c_void_p()
+    check(lib().detlsh_build_index(_ptr(X), X.shape[0], X.shape[1], int(L), int(K), int(N_r), float(sample_frac),
+                                   C.byref(o), _stream_ptr(), C.byref(h)))
+    return Index(h)
+
+
+def import_index(X, A, B, codes, L, K, N_r, max_leaf=256, keep_bf16=False) -> Index:
+    """Index from given projection matrix, breakpoints and codes (host arrays)."""
+    X = _dev_f32(X, "X")
+    A = np.ascontiguousarray(A, np.float32)
+    B = np.ascontiguousarray(B, np.float32)
+    codes = np.ascontiguousarray(codes, np.uint8)
+    keep = []
+    o = _build_opts(0, max_leaf, keep_bf16, False, None, None, keep)
+    h = C.c_void_p()
+    check(lib().detlsh_index_import(_ptr(X), X.shape[0], X.shape[1], int(L), int(K), int(N_r),
+                                    A.ctypes.data_as(C.c_void_p), B.ctypes.data_as(C.c_void_p),
+                                    codes.ctypes.data_as(C.c_void_p), C.byref(o), _stream_ptr(), C.byref(h)))
+    return Index(h)
+
+
+def profile_enable(on=True, reset=True):
+    check(lib().detlsh_profile_enable(int(on), int(reset)))
+
+
+def profile_read() -> dict:
+    names = (C.c_char_p * 32)()
+    launches = (C.c_int64 * 32)()
+    ms = (C.c_double * 32)()
+    cnt = C.c_int32()
+    check(lib().detlsh_profile_read(names, launches, ms, 32, C.byref(cnt)))
+    return {names[i].decode(): {"launches": launches[i], "ms": ms[i]} for i in range(cnt.value)}

@@ -1,0 +1,64 @@
+// Internal device helpers shared by the library's kernels (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DL_WAVE 64
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// Order-preserving map between FP32 and uint32 (total order of finite floats,
+// -0 < +0 is irrelevant here because keys only compare).
+__device__ __forceinline__ uint32_t dl_f2key(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float dl_key2f(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ int dl_lane() { return __lane_id(); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int dl_rank_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t dl_ballot(bool p) { return __ballot(p); }
+
+// Lanes of this wave whose 8-bit `digit` equals this lane's, among lanes where
+// `valid` holds.
+__device__ __forceinline__ uint64_t dl_match8(uint32_t digit, bool valid) {
+    uint64_t m = dl_ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        uint64_t bb = dl_ballot(((digit >> b) & 1u) != 0);
+        m &= ((digit >> b) & 1u) ? bb : ~bb;
+    }
+    return m;
+}
+
+// Read a value from lane `src` of this wave.
+__device__ __forceinline__ uint32_t dl_shfl_u32(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+
+template <typename T>
+__device__ __forceinline__ T dl_wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float dl_bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+// Round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t dl_f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}

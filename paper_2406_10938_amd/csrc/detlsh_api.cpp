@@ -1,0 +1,708 @@
+// C ABI of the library: argument checks, index ownership, orchestration of the
+// build and query kernels, kernel timing.  See include/detlsh.h.
+#include "detlsh.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+namespace {
+
+thread_local std::string g_err;
+
+detlsh_status fail(detlsh_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HCHECK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(DETLSH_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+// Device allocation owned by a scope or an index.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    hipError_t alloc(size_t b) {
+        release();
+        bytes = b ? b : 4;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) { p = nullptr; bytes = 0; }
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+
+const char* kTimerNames[T_COUNT] = {"project_sample", "breakpoints", "project_encode", "tree_build",
+                                    "project_queries", "guess",      "range_filter",   "select",
+                                    "verify_topk",     "to_bf16"};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    int64_t launches[T_COUNT] = {};
+    double ms[T_COUNT] = {};
+    struct Pending { int id; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+};
+Profiler g_prof;
+
+void prof_resolve() {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& p : g_prof.pending) {
+        float t = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+            g_prof.launches[p.id] += 1;
+            g_prof.ms[p.id] += t;
+        }
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_prof.pending.clear();
+}
+
+// splitmix64 / Box-Muller draws for the library's own A and sample
+struct HostRng {
+    uint64_t s;
+    explicit HostRng(uint64_t seed) : s(seed ^ 0x9E3779B97F4A7C15ull) {}
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+    double normal() {
+        const double u1 = uniform(), u2 = uniform();
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    }
+};
+
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+constexpr int kGuessMax = 16384;
+
+}  // namespace
+
+DlTimer::DlTimer(int id_, hipStream_t st_) : id(id_), st(st_) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        on = g_prof.on;
+    }
+    if (!on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, st);
+}
+
+DlTimer::~DlTimer() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({id, a, b});
+}
+
+// ---------------------------------------------------------------------------
+// index
+// ---------------------------------------------------------------------------
+
+struct detlsh_index_s {
+    int device = 0;
+    int64_t n = 0;
+    int32_t d = 0, L = 0, K = 0, N_r = 0, LK = 0;
+    int64_t n_s = 0;
+    int32_t max_leaf = 256;
+    int32_t proj_bf16 = 0;
+    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes;
+    std::vector<int64_t> sample_ids;
+    std::vector<float> A_host;
+    int64_t n_leaves[8] = {};
+    int32_t* leaf_start[8] = {};
+    uint8_t* leaf_lo[8] = {};
+    uint8_t* leaf_hi[8] = {};
+    ~detlsh_index_s() {
+        for (int i = 0; i < 8; ++i) {
+            if (leaf_start[i]) (void)hipFree(leaf_start[i]);
+            if (leaf_lo[i]) (void)hipFree(leaf_lo[i]);
+            if (leaf_hi[i]) (void)hipFree(leaf_hi[i]);
+        }
+    }
+    size_t bytes() const {
+        size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
+                   scodes.bytes;
+        for (int i = 0; i < L; ++i) b += (size_t)(n_leaves[i] + 1) * 4 + 2 * (size_t)n_leaves[i] * K;
+        return b;
+    }
+};
+
+namespace {
+
+detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_r) {
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(DETLSH_EINVAL, "n must be in [1, 2^31), got %lld", (long long)n);
+    if (d < 1) return fail(DETLSH_EINVAL, "d must be >= 1, got %d", d);
+    if (!dl_supported_lk(L, K))
+        return fail(DETLSH_EINVAL,
+                    "unsupported (L, K) = (%d, %d): K in {4,8,16,32}, L in {1,2,4,8}, L*K <= 64", L, K);
+    if (N_r < 2 || N_r > 256 || (N_r & (N_r - 1)))
+        return fail(DETLSH_EINVAL, "N_r must be a power of two in [2, 256], got %d", N_r);
+    return DETLSH_OK;
+}
+
+// Shared tail of build and import: BF16 copies, trees.
+detlsh_status finish_index(detlsh_index_s* ix, hipStream_t st) {
+    for (int i = 0; i < ix->L; ++i) {
+        DevBuf tmp;
+        HCHECK(tmp.alloc(dl_tree_tmp_bytes(ix->n, ix->K)));
+        DlTimer tm(T_TREE, st);
+        HCHECK(dl_build_tree(ix->codes.as<uint8_t>() + (int64_t)i * ix->n * ix->K, ix->n, ix->K, ix->N_r,
+                             ix->max_leaf, ix->perm.as<int32_t>() + (int64_t)i * ix->n,
+                             ix->scodes.as<uint8_t>() + (int64_t)i * ix->n * ix->K, tmp.p, st, &ix->n_leaves[i],
+                             &ix->leaf_start[i], &ix->leaf_lo[i], &ix->leaf_hi[i]));
+        HCHECK(hipStreamSynchronize(st));
+    }
+    return DETLSH_OK;
+}
+
+detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_build_opts* opts, hipStream_t st) {
+    const int64_t nd = ix->n * ix->d;
+    HCHECK(ix->X.alloc((size_t)nd * 4));
+    HCHECK(hipMemcpyAsync(ix->X.p, X, (size_t)nd * 4, hipMemcpyDeviceToDevice, st));
+    const bool want_bf = opts && (opts->keep_bf16 || opts->proj_bf16);
+    if (want_bf) {
+        HCHECK(ix->Xbf.alloc((size_t)nd * 2));
+        DlTimer tm(T_BF16, st);
+        HCHECK(dl_launch_to_bf16(ix->X.as<float>(), ix->Xbf.as<uint16_t>(), nd, st));
+    }
+    HCHECK(ix->A.alloc((size_t)ix->LK * ix->d * 4));
+    HCHECK(hipMemcpyAsync(ix->A.p, ix->A_host.data(), (size_t)ix->LK * ix->d * 4, hipMemcpyHostToDevice, st));
+    std::vector<uint16_t> abf((size_t)ix->LK * ix->d);
+    for (size_t t = 0; t < abf.size(); ++t) abf[t] = host_bf16(ix->A_host[t]);
+    HCHECK(ix->Abf.alloc(abf.size() * 2));
+    HCHECK(hipMemcpyAsync(ix->Abf.p, abf.data(), abf.size() * 2, hipMemcpyHostToDevice, st));
+    HCHECK(ix->B.alloc((size_t)ix->LK * (ix->N_r + 1) * 4));
+    HCHECK(ix->E.alloc((size_t)ix->LK * (ix->N_r + 1) * 4));
+    HCHECK(ix->codes.alloc((size_t)ix->n * ix->LK));
+    HCHECK(ix->perm.alloc((size_t)ix->n * ix->L * 4));
+    HCHECK(ix->scodes.alloc((size_t)ix->n * ix->LK));
+    HCHECK(hipStreamSynchronize(st));   // abf leaves scope
+    return DETLSH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* detlsh_last_error(void) { return g_err.c_str(); }
+
+detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_r,
+                                 double sample_frac, const detlsh_build_opts* opts, void* stream,
+                                 detlsh_index* out) {
+    g_err.clear();
+    if (!out) return fail(DETLSH_EINVAL, "out is NULL");
+    *out = nullptr;
+    detlsh_status s = check_shape(n, d, L, K, N_r);
+    if (s) return s;
+    if (!(sample_frac > 0.0 && sample_frac <= 1.0))
+        return fail(DETLSH_EINVAL, "sample_frac must be in (0, 1], got %g", sample_frac);
+    const int64_t n_s = (int64_t)std::floor(sample_frac * (double)n);
+    if (n_s < N_r) return fail(DETLSH_EINVAL, "sample size floor(sample_frac*n) = %lld < N_r = %d", (long long)n_s, N_r);
+    if (!is_device_ptr(X)) return fail(DETLSH_EINVAL, "X must be a device pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    auto* ix = new (std::nothrow) detlsh_index_s();
+    if (!ix) return fail(DETLSH_ENOMEM, "host allocation failed");
+    std::unique_ptr<detlsh_index_s> guard(ix);
+    HCHECK(hipGetDevice(&ix->device));
+    ix->n = n; ix->d = d; ix->L = L; ix->K = K; ix->N_r = N_r; ix->LK = L * K; ix->n_s = n_s;
+    ix->max_leaf = (opts && opts->max_leaf > 0) ? opts->max_leaf : 256;
+    ix->proj_bf16 = (opts && opts->proj_bf16) ? 1 : 0;
+    const uint64_t seed = opts ? opts->seed : 0;
+
+    ix->A_host.resize((size_t)ix->LK * d);
+    if (opts && opts->A) {
+        std::memcpy(ix->A_host.data(), opts->A, ix->A_host.size() * 4);
+    } else {
+        HostRng rng(seed);
+        for (auto& v : ix->A_host) v = (float)rng.normal();
+    }
+    ix->sample_ids.resize((size_t)n_s);
+    if (opts && opts->sample_ids) {
+        std::memcpy(ix->sample_ids.data(), opts->sample_ids, (size_t)n_s * 8);
+        for (int64_t t = 0; t < n_s; ++t)
+            if (ix->sample_ids[t] < 0 || ix->sample_ids[t] >= n)
+                return fail(DETLSH_EINVAL, "sample_ids[%lld] = %lld out of [0, n)", (long long)t,
+                            (long long)ix->sample_ids[t]);
+    } else {
+        // Floyd's sampling without replacement
+        HostRng rng(seed + 0x5A17);
+        std::unordered_set<int64_t> chosen;
+        chosen.reserve((size_t)n_s * 2);
+        int64_t w = 0;
+        for (int64_t j = n - n_s; j < n; ++j) {
+            const int64_t t = (int64_t)(rng.next() % (uint64_t)(j + 1));
+            const int64_t pick = chosen.count(t) ? j : t;
+            chosen.insert(pick);
+            ix->sample_ids[w++] = pick;
+        }
+        std::sort(ix->sample_ids.begin(), ix->sample_ids.end());
+    }
+
+    s = alloc_common(ix, X, opts, st);
+    if (s) return s;
+
+    // breakpoints from the projected sample
+    {
+        DevBuf rows, Ps, tmp;
+        std::vector<int32_t> r32(ix->sample_ids.begin(), ix->sample_ids.end());
+        HCHECK(rows.alloc((size_t)n_s * 4));
+        HCHECK(hipMemcpyAsync(rows.p, r32.data(), (size_t)n_s * 4, hipMemcpyHostToDevice, st));
+        HCHECK(Ps.alloc((size_t)n_s * ix->LK * 4));
+        ProjectArgs pa;
+        pa.X = ix->X.as<float>(); pa.Xbf = ix->Xbf.as<uint16_t>(); pa.rows = rows.as<int32_t>();
+        pa.M = n_s; pa.d = d; pa.A = ix->A.as<float>(); pa.Abf = ix->Abf.as<uint16_t>(); pa.N = ix->LK;
+        pa.bf16 = ix->proj_bf16; pa.Pout = Ps.as<float>(); pa.ldp = n_s;
+        {
+            DlTimer tm(T_PROJECT_SAMPLE, st);
+            HCHECK(dl_launch_project(pa, PROJ_COLMAJOR, st));
+        }
+        HCHECK(tmp.alloc(dl_breakpoint_tmp_bytes(n_s, ix->LK)));
+        {
+            DlTimer tm(T_BREAKPOINTS, st);
+            HCHECK(dl_breakpoints(Ps.as<float>(), n_s, ix->LK, N_r, ix->B.as<float>(), ix->E.as<float>(), tmp.p, st));
+        }
+        HCHECK(hipStreamSynchronize(st));
+    }
+    // encode every point
+    {
+        ProjectArgs pa;
+        pa.X = ix->X.as<float>(); pa.Xbf = ix->Xbf.as<uint16_t>(); pa.M = n; pa.d = d;
+        pa.A = ix->A.as<float>(); pa.Abf = ix->Abf.as<uint16_t>(); pa.N = ix->LK; pa.bf16 = ix->proj_bf16;
+        pa.E = ix->E.as<float>(); pa.N_r = N_r; pa.K = K; pa.codes = ix->codes.as<uint8_t>(); pa.n_codes = n;
+        DlTimer tm(T_ENCODE, st);
+        HCHECK(dl_launch_project(pa, PROJ_ENCODE, st));
+    }
+    s = finish_index(ix, st);
+    if (s) return s;
+    if (!(opts && opts->keep_bf16) && !ix->proj_bf16) ix->Xbf.release();
+    HCHECK(hipStreamSynchronize(st));
+    prof_resolve();
+    *out = guard.release();
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_index_import(const float* X, int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_r,
+                                  const float* A, const float* B, const uint8_t* codes,
+                                  const detlsh_build_opts* opts, void* stream, detlsh_index* out) {
+    g_err.clear();
+    if (!out) return fail(DETLSH_EINVAL, "out is NULL");
+    *out = nullptr;
+    detlsh_status s = check_shape(n, d, L, K, N_r);
+    if (s) return s;
+    if (!A || !B || !codes) return fail(DETLSH_EINVAL, "A, B and codes are required (host pointers)");
+    if (is_device_ptr(A) || is_device_ptr(B) || is_device_ptr(codes))
+        return fail(DETLSH_EINVAL, "A, B and codes must be host pointers");
+    if (!is_device_ptr(X)) return fail(DETLSH_EINVAL, "X must be a device pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto* ix = new (std::nothrow) detlsh_index_s();
+    if (!ix) return fail(DETLSH_ENOMEM, "host allocation failed");
+    std::unique_ptr<detlsh_index_s> guard(ix);
+    HCHECK(hipGetDevice(&ix->device));
+    ix->n = n; ix->d = d; ix->L = L; ix->K = K; ix->N_r = N_r; ix->LK = L * K; ix->n_s = 0;
+    ix->max_leaf = (opts && opts->max_leaf > 0) ? opts->max_leaf : 256;
+    ix->A_host.assign(A, A + (size_t)ix->LK * d);
+    s = alloc_common(ix, X, opts, st);
+    if (s) return s;
+    const int N1 = N_r + 1;
+    for (int e = 0; e < ix->LK; ++e)
+        for (int z = 1; z < N1; ++z)
+            if (!(B[(size_t)e * N1 + z] >= B[(size_t)e * N1 + z - 1]))
+                return fail(DETLSH_EINVAL, "B row %d is not non-decreasing at %d", e, z);
+    HCHECK(hipMemcpyAsync(ix->B.p, B, (size_t)ix->LK * N1 * 4, hipMemcpyHostToDevice, st));
+    HCHECK(dl_edges_from_breakpoints(ix->B.as<float>(), ix->E.as<float>(), ix->LK, N_r, st));
+    // codes: n x LK (column e = i*K + j) -> [L][n][K]
+    std::vector<uint8_t> t((size_t)n * ix->LK);
+    for (int64_t o = 0; o < n; ++o)
+        for (int i = 0; i < L; ++i)
+            for (int j = 0; j < K; ++j) {
+                const uint8_t c = codes[(size_t)o * ix->LK + i * K + j];
+                if (c >= N_r) return fail(DETLSH_EINVAL, "code %d of point %lld >= N_r", (int)c, (long long)o);
+                t[((size_t)i * n + o) * K + j] = c;
+            }
+    HCHECK(hipMemcpyAsync(ix->codes.p, t.data(), t.size(), hipMemcpyHostToDevice, st));
+    HCHECK(hipStreamSynchronize(st));
+    s = finish_index(ix, st);
+    if (s) return s;
+    if (!(opts && opts->keep_bf16)) ix->Xbf.release();
+    HCHECK(hipStreamSynchronize(st));
+    prof_resolve();
+    *out = guard.release();
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_index_info(detlsh_index ix, detlsh_info* o) {
+    g_err.clear();
+    if (!ix || !o) return fail(DETLSH_EINVAL, "NULL argument");
+    std::memset(o, 0, sizeof *o);
+    o->n = ix->n; o->d = ix->d; o->L = ix->L; o->K = ix->K; o->N_r = ix->N_r; o->n_s = ix->n_s;
+    o->max_leaf = ix->max_leaf;
+    o->has_bf16 = ix->Xbf.p != nullptr;
+    for (int i = 0; i < ix->L && i < 8; ++i) o->n_leaves[i] = ix->n_leaves[i];
+    o->device_bytes = ix->bytes();
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_export(detlsh_index ix, float* A, float* B, uint8_t* codes, int64_t* sample_ids) {
+    g_err.clear();
+    if (!ix) return fail(DETLSH_EINVAL, "NULL index");
+    HCHECK(hipSetDevice(ix->device));
+    if (A) std::memcpy(A, ix->A_host.data(), ix->A_host.size() * 4);
+    if (B) HCHECK(hipMemcpy(B, ix->B.p, (size_t)ix->LK * (ix->N_r + 1) * 4, hipMemcpyDeviceToHost));
+    if (codes) {
+        std::vector<uint8_t> t((size_t)ix->n * ix->LK);
+        HCHECK(hipMemcpy(t.data(), ix->codes.p, t.size(), hipMemcpyDeviceToHost));
+        for (int i = 0; i < ix->L; ++i)
+            for (int64_t o = 0; o < ix->n; ++o)
+                for (int j = 0; j < ix->K; ++j)
+                    codes[(size_t)o * ix->LK + i * ix->K + j] = t[((size_t)i * ix->n + o) * ix->K + j];
+    }
+    if (sample_ids && !ix->sample_ids.empty())
+        std::memcpy(sample_ids, ix->sample_ids.data(), ix->sample_ids.size() * 8);
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_export_tree(detlsh_index ix, int32_t tree, int32_t* perm, int32_t* leaf_start,
+                                 uint8_t* leaf_lo, uint8_t* leaf_hi, int64_t cap) {
+    g_err.clear();
+    if (!ix) return fail(DETLSH_EINVAL, "NULL index");
+    if (tree < 0 || tree >= ix->L) return fail(DETLSH_EINVAL, "tree %d out of [0, %d)", tree, ix->L);
+    const int64_t nl = ix->n_leaves[tree];
+    if ((leaf_start || leaf_lo || leaf_hi) && cap < nl)
+        return fail(DETLSH_EINVAL, "leaf capacity %lld < %lld leaves", (long long)cap, (long long)nl);
+    HCHECK(hipSetDevice(ix->device));
+    if (perm) HCHECK(hipMemcpy(perm, ix->perm.as<int32_t>() + (int64_t)tree * ix->n, (size_t)ix->n * 4, hipMemcpyDeviceToHost));
+    if (leaf_start) HCHECK(hipMemcpy(leaf_start, ix->leaf_start[tree], (size_t)(nl + 1) * 4, hipMemcpyDeviceToHost));
+    if (leaf_lo) HCHECK(hipMemcpy(leaf_lo, ix->leaf_lo[tree], (size_t)nl * ix->K, hipMemcpyDeviceToHost));
+    if (leaf_hi) HCHECK(hipMemcpy(leaf_hi, ix->leaf_hi[tree], (size_t)nl * ix->K, hipMemcpyDeviceToHost));
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_project(detlsh_index ix, const float* Q, int64_t nq, float* out, void* stream) {
+    g_err.clear();
+    if (!ix) return fail(DETLSH_EINVAL, "NULL index");
+    if (nq < 0) return fail(DETLSH_EINVAL, "nq < 0");
+    if (nq == 0) return DETLSH_OK;
+    if (!is_device_ptr(Q) || !is_device_ptr(out)) return fail(DETLSH_EINVAL, "Q and out must be device pointers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ProjectArgs pa;
+    pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK; pa.Pout = out;
+    {
+        DlTimer tm(T_QPROJECT, st);
+        HCHECK(dl_launch_project(pa, PROJ_ROWMAJOR, st));
+    }
+    HCHECK(hipStreamSynchronize(st));
+    prof_resolve();
+    return DETLSH_OK;
+}
+
+void detlsh_free(detlsh_index ix) { delete ix; }
+
+detlsh_status detlsh_profile_enable(int32_t on, int32_t reset) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    if (reset) {
+        for (int i = 0; i < T_COUNT; ++i) { g_prof.launches[i] = 0; g_prof.ms[i] = 0; }
+    }
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double* total_ms, int32_t max,
+                                  int32_t* count) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    int c = 0;
+    for (int i = 0; i < T_COUNT && c < max; ++i, ++c) {
+        if (names) names[c] = kTimerNames[i];
+        if (launches) launches[c] = g_prof.launches[i];
+        if (total_ms) total_ms[c] = g_prof.ms[i];
+    }
+    if (count) *count = c;
+    return DETLSH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// query
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct QueryPlan {
+    uint64_t N_S = 0;
+    bool all = false;       // S = D
+    int G = 0;
+    uint64_t rank = 0;
+    int64_t cap = 0;
+};
+
+QueryPlan plan_query(int64_t n, int k, double beta, int L) {
+    QueryPlan p;
+    p.N_S = (uint64_t)k + (uint64_t)std::ceil(beta * (double)n);
+    if (p.N_S >= (uint64_t)n) {
+        p.all = true;
+        p.cap = n;
+        return p;
+    }
+    p.G = (int)std::min<int64_t>(n, kGuessMax);
+    if (p.G == n) {
+        p.rank = p.N_S;
+        p.cap = n;
+        return p;
+    }
+    const double pr = (double)p.N_S / (double)n;
+    const double G = p.G;
+    double r = std::ceil(G * pr + 5.0 * std::sqrt(G * pr * (1.0 - pr))) + 1.0;
+    if (r > G) r = G;
+    if (r < 1) r = 1;
+    p.rank = (uint64_t)r;
+    const double pg = r / G;
+    double cf = pg + 6.0 * std::sqrt(pg * (1.0 - pg) / G) + 1e-4;
+    int64_t cap = (int64_t)std::ceil((double)n * cf) + 1024;
+    if (cap > n) cap = n;
+    if ((uint64_t)cap < p.N_S) cap = (int64_t)p.N_S;
+    p.cap = cap;
+    (void)L;
+    return p;
+}
+
+struct Debug {
+    int32_t* cand_ids = nullptr;
+    int64_t cand_cap = 0;
+    int64_t* cand_counts = nullptr;
+    int32_t* first_tree = nullptr;
+    float* thr = nullptr;
+    int32_t* stop_tree = nullptr;
+    int32_t* rounds = nullptr;
+};
+
+size_t per_query_bytes(int64_t cap, int L) { return (size_t)cap * (4 + 4 + 4 * (size_t)L + 8) + 64; }
+
+// Runs queries [q0, q0+nq) through the pipeline with the given plan.  When
+// `force_all_candidates`, every point is a candidate (threshold +inf).
+detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, int64_t q0, int64_t nq, int k,
+                          const QueryPlan& plan, bool force_all_candidates, size_t budget, int64_t* out_ids,
+                          float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
+    const int64_t cap = force_all_candidates ? ix->n : plan.cap;
+    const size_t pq = per_query_bytes(cap, ix->L);
+    int64_t nqc = (int64_t)(budget / pq);
+    if (nqc < 1) nqc = 1;
+    if (nqc > nq) nqc = nq;
+    if (nqc > 65535) nqc = 65535;
+    DevBuf ws;
+    if (ws.alloc(pq * (size_t)nqc) != hipSuccess)
+        return fail(DETLSH_ENOMEM, "query workspace of %zu bytes", pq * (size_t)nqc);
+    char* p = ws.as<char>();
+    auto take = [&](size_t b) { char* r = p; p += (b + 255) & ~(size_t)255; return r; };
+    QueryArgs a;
+    a.L = ix->L; a.K = ix->K; a.N_r = ix->N_r; a.d = ix->d; a.n = ix->n;
+    a.E = ix->E.as<float>(); a.codes = ix->codes.as<uint8_t>(); a.X = ix->X.as<float>(); a.Xbf = ix->Xbf.as<uint16_t>();
+    a.Q = Q; a.Qp = Qp; a.G = plan.G; a.guess_rank = plan.rank; a.N_S = plan.N_S; a.k = k; a.cap = cap;
+    a.all_n = plan.all ? ix->n : 0;
+    a.gthr = reinterpret_cast<float*>(take((size_t)nqc * 4));
+    a.counts = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
+    a.status = reinterpret_cast<int32_t*>(take((size_t)nqc * 4));
+    a.s_count = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
+    a.thr = reinterpret_cast<float*>(take((size_t)nqc * 4));
+    a.stop = reinterpret_cast<int32_t*>(take((size_t)nqc * 4));
+    a.cand_id = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
+    a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
+    a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * ix->L));
+    a.ws = reinterpret_cast<uint64_t*>(take((size_t)nqc * cap * 8));
+    a.out_ids = out_ids; a.out_d = out_d;
+    std::vector<float> inf_host;
+    std::vector<uint32_t> sc_host;
+    for (int64_t c0 = 0; c0 < nq; c0 += nqc) {
+        const int cnt = (int)std::min<int64_t>(nqc, nq - c0);
+        a.q0 = q0 + c0;
+        a.nqc = cnt;
+        if (!plan.all) {
+            HCHECK(hipMemsetAsync(a.counts, 0, (size_t)cnt * 4, st));
+            if (force_all_candidates) {
+                inf_host.assign(cnt, INFINITY);
+                HCHECK(hipMemcpyAsync(a.gthr, inf_host.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, st));
+            } else {
+                DlTimer tm(T_GUESS, st);
+                HCHECK(dl_launch_guess(a, st));
+            }
+            {
+                DlTimer tm(T_FILTER, st);
+                HCHECK(dl_launch_filter(a, st));
+            }
+            {
+                DlTimer tm(T_SELECT, st);
+                HCHECK(dl_launch_select(a, st));
+            }
+        } else {
+            HCHECK(hipMemsetAsync(a.status, 0, (size_t)cnt * 4, st));
+        }
+        {
+            DlTimer tm(T_VERIFY, st);
+            HCHECK(dl_launch_verify(a, st));
+        }
+        HCHECK(hipMemcpyAsync(status_host.data() + c0, a.status, (size_t)cnt * 4, hipMemcpyDeviceToHost, st));
+        if (dbg.cand_ids || dbg.cand_counts || dbg.first_tree || dbg.thr || dbg.stop_tree || dbg.rounds) {
+            HCHECK(hipStreamSynchronize(st));
+            sc_host.resize(cnt);
+            HCHECK(hipMemcpy(sc_host.data(), a.s_count, (size_t)cnt * 4, hipMemcpyDeviceToHost));
+            std::vector<int64_t> c64(cnt);
+            for (int t = 0; t < cnt; ++t) c64[t] = plan.all ? ix->n : (int64_t)sc_host[t];
+            const int64_t gq = q0 + c0;
+            if (dbg.cand_counts)
+                HCHECK(hipMemcpy(dbg.cand_counts + gq, c64.data(), (size_t)cnt * 8, hipMemcpyHostToDevice));
+            if (!plan.all) {
+                const int64_t w = std::min<int64_t>(dbg.cand_cap, cap);
+                if (dbg.cand_ids && w > 0)
+                    HCHECK(hipMemcpy2D(dbg.cand_ids + gq * dbg.cand_cap, dbg.cand_cap * 4, a.cand_id, cap * 4,
+                                       w * 4, cnt, hipMemcpyDeviceToDevice));
+                if (dbg.first_tree && w > 0)
+                    HCHECK(hipMemcpy2D(dbg.first_tree + gq * dbg.cand_cap, dbg.cand_cap * 4, a.cand_m, cap * 4,
+                                       w * 4, cnt, hipMemcpyDeviceToDevice));
+                if (dbg.thr) HCHECK(hipMemcpy(dbg.thr + gq, a.thr, (size_t)cnt * 4, hipMemcpyDeviceToDevice));
+                if (dbg.stop_tree) HCHECK(hipMemcpy(dbg.stop_tree + gq, a.stop, (size_t)cnt * 4, hipMemcpyDeviceToDevice));
+            }
+            if (dbg.rounds) {
+                std::vector<int32_t> one(cnt, 1);
+                HCHECK(hipMemcpy(dbg.rounds + gq, one.data(), (size_t)cnt * 4, hipMemcpyHostToDevice));
+            }
+        }
+    }
+    HCHECK(hipStreamSynchronize(st));
+    return DETLSH_OK;
+}
+
+detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, int64_t nq, int32_t k, double c,
+                         double beta, const detlsh_query_opts* opts, int64_t* out_ids, float* out_d,
+                         const Debug& dbg, hipStream_t st) {
+    g_err.clear();
+    if (!ix) return fail(DETLSH_EINVAL, "NULL index");
+    if (nq < 0) return fail(DETLSH_EINVAL, "nq < 0");
+    if (k < 1 || (int64_t)k > ix->n || k > 1024)
+        return fail(DETLSH_EINVAL, "k must be in [1, min(n, 1024)], got %d", k);
+    if (!(c > 1.0)) return fail(DETLSH_EINVAL, "c must be > 1, got %g", c);
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(DETLSH_EINVAL, "beta must be in [0, 1], got %g", beta);
+    const int precision = opts ? opts->precision : DETLSH_FP32;
+    const int policy = opts ? opts->rmin_policy : DETLSH_RMIN_MAGIC;
+    if (precision != DETLSH_FP32) return fail(DETLSH_EINVAL, "precision %d is not available", precision);
+    if (policy != DETLSH_RMIN_MAGIC) return fail(DETLSH_EINVAL, "r_min policy %d is not available", policy);
+    if (nq == 0) return DETLSH_OK;
+    if (!is_device_ptr(Q)) return fail(DETLSH_EINVAL, "Q must be a device pointer");
+    if (!is_device_ptr(out_ids) || !is_device_ptr(out_d)) return fail(DETLSH_EINVAL, "outputs must be device pointers");
+    if (Qp_in && !is_device_ptr(Qp_in)) return fail(DETLSH_EINVAL, "Qp must be a device pointer");
+    HCHECK(hipSetDevice(ix->device));
+    const size_t budget = (opts && opts->workspace_bytes) ? opts->workspace_bytes : ((size_t)4 << 30);
+
+    DevBuf qpbuf;
+    const float* Qp = Qp_in;
+    if (!Qp) {
+        HCHECK(qpbuf.alloc((size_t)nq * ix->LK * 4));
+        ProjectArgs pa;
+        pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK; pa.Pout = qpbuf.as<float>();
+        DlTimer tm(T_QPROJECT, st);
+        HCHECK(dl_launch_project(pa, PROJ_ROWMAJOR, st));
+        Qp = qpbuf.as<float>();
+    }
+    const QueryPlan plan = plan_query(ix->n, k, beta, ix->L);
+    std::vector<int32_t> status((size_t)nq, 0);
+    detlsh_status s = run_queries(ix, Q, Qp, 0, nq, k, plan, false, budget, out_ids, out_d, dbg, status, st);
+    if (s) { prof_resolve(); return s; }
+    // queries whose candidate count missed [N_S, cap]: every point a candidate
+    for (int64_t q = 0; q < nq; ++q) {
+        if (status[q] == 0) continue;
+        std::vector<int32_t> st1(1, 0);
+        s = run_queries(ix, Q, Qp, q, 1, k, plan, true, budget, out_ids, out_d, dbg, st1, st);
+        if (s) { prof_resolve(); return s; }
+        if (st1[0] != 0) { prof_resolve(); return fail(DETLSH_EINTERNAL, "query %lld: fallback failed", (long long)q); }
+    }
+    prof_resolve();
+    (void)c;
+    return DETLSH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+detlsh_status detlsh_query(detlsh_index ix, const float* Q, int64_t nq, int32_t k, double c, double beta,
+                           const detlsh_query_opts* opts, int64_t* out_ids, float* out_dists, void* stream) {
+    Debug dbg;
+    return query_impl(ix, nullptr, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg,
+                      static_cast<hipStream_t>(stream));
+}
+
+detlsh_status detlsh_query_debug(detlsh_index ix, const float* Qp, const float* Q, int64_t nq, int32_t k, double c,
+                                 double beta, const detlsh_query_opts* opts, int32_t* cand_ids, int64_t cand_cap,
+                                 int64_t* cand_counts, int32_t* first_tree, float* thr, int32_t* stop_tree,
+                                 int32_t* rounds, int64_t* out_ids, float* out_dists, void* stream) {
+    Debug dbg;
+    dbg.cand_ids = cand_ids; dbg.cand_cap = cand_cap; dbg.cand_counts = cand_counts; dbg.first_tree = first_tree;
+    dbg.thr = thr; dbg.stop_tree = stop_tree; dbg.rounds = rounds;
+    if ((cand_ids || first_tree) && cand_cap < 1) return fail(DETLSH_EINVAL, "cand_cap must be >= 1");
+    for (const void* p : {(const void*)cand_ids, (const void*)cand_counts, (const void*)first_tree, (const void*)thr,
+                          (const void*)stop_tree, (const void*)rounds})
+        if (p && !is_device_ptr(p)) return fail(DETLSH_EINVAL, "debug outputs must be device pointers");
+    return query_impl(ix, Qp, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal host-side interface between the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+// ---- projection (k_project.hip) ----
+enum { PROJ_COLMAJOR = 0, PROJ_ROWMAJOR = 1, PROJ_ENCODE = 2 };
+
+struct ProjectArgs {
+    const float* X = nullptr;        // M x d (or rows gathered through `rows`)
+    const uint16_t* Xbf = nullptr;   // BF16 copy when bf16
+    const int32_t* rows = nullptr;
+    int64_t M = 0;
+    int d = 0;
+    const float* A = nullptr;        // N x d
+    const uint16_t* Abf = nullptr;
+    int N = 0;
+    int bf16 = 0;
+    float* Pout = nullptr;
+    int64_t ldp = 0;
+    const float* E = nullptr;        // [N][N_r+1] edge table
+    int N_r = 0;
+    int K = 0;
+    uint8_t* codes = nullptr;        // [L][n][K]
+    int64_t n_codes = 0;
+};
+
+hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st);
+hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st);
+
+// ---- sorting and scans (k_sort.hip) ----
+size_t dl_scan_tmp_bytes(int64_t n);
+hipError_t dl_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
+                             hipStream_t st);
+size_t dl_radix_tmp_bytes(int64_t n);
+hipError_t dl_radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int lo_bit, int hi_bit, void* tmp,
+                               hipStream_t st);
+size_t dl_breakpoint_tmp_bytes(int64_t n_s, int N);
+hipError_t dl_breakpoints(const float* Ps, int64_t n_s, int N, int N_r, float* B, float* E, void* tmp,
+                          hipStream_t st);
+hipError_t dl_edges_from_breakpoints(const float* B, float* E, int N, int N_r, hipStream_t st);
+
+// ---- trees (k_tree.hip) ----
+size_t dl_tree_tmp_bytes(int64_t n, int K);
+hipError_t dl_build_tree(const uint8_t* codes_i, int64_t n, int K, int N_r, int max_leaf, int32_t* perm,
+                         uint8_t* scodes, void* tmp, hipStream_t st, int64_t* n_leaves, int32_t** leaf_start,
+                         uint8_t** leaf_lo, uint8_t** leaf_hi);
+
+// ---- query (k_query.hip) ----
+struct QueryArgs {
+    int L = 0, K = 0, N_r = 0, d = 0;
+    int64_t n = 0;
+    const float* E = nullptr;
+    const uint8_t* codes = nullptr;
+    const float* X = nullptr;
+    const uint16_t* Xbf = nullptr;
+    const float* Q = nullptr;        // all queries, nq x d
+    const float* Qp = nullptr;       // all projected queries, nq x L*K
+    int64_t q0 = 0;                  // first query of the chunk
+    int nqc = 0;                     // queries in the chunk
+    int G = 0;                       // guess subset size
+    uint64_t guess_rank = 0;
+    uint64_t N_S = 0;
+    int k = 0;
+    int64_t cap = 0;                 // candidate slots per query
+    int64_t all_n = 0;               // > 0: S = D (every point), skip filter/select
+    // workspace (per chunk, indexed by query within the chunk)
+    float* gthr = nullptr;
+    uint32_t* counts = nullptr;
+    int32_t* cand_id = nullptr;
+    float* cand_m = nullptr;
+    float* cand_lb = nullptr;
+    int32_t* status = nullptr;
+    uint32_t* s_count = nullptr;
+    float* thr = nullptr;
+    int32_t* stop = nullptr;
+    uint64_t* ws = nullptr;
+    // outputs (all queries)
+    int64_t* out_ids = nullptr;
+    float* out_d = nullptr;
+};
+
+bool dl_supported_lk(int L, int K);
+size_t dl_guess_smem(int L, int K, int N_r, int G);
+size_t dl_verify_smem(int d);
+hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_filter(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_verify(const QueryArgs& a, hipStream_t st);
+
+// ---- kernel timing (detlsh_api.cpp) ----
+struct DlTimer {
+    int id;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    DlTimer(int id_, hipStream_t st_);
+    ~DlTimer();
+};
+enum {
+    T_PROJECT_SAMPLE = 0, T_BREAKPOINTS, T_ENCODE, T_TREE, T_QPROJECT, T_GUESS, T_FILTER, T_SELECT,
+    T_VERIFY, T_BF16, T_COUNT
+};

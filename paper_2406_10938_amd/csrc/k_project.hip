@@ -1,0 +1,248 @@
+// Projection of rows onto the L*K Gaussian hashes (Eq. 1) as an MFMA GEMM,
+// with three epilogues: projected values column-major (breakpoint sample),
+// row-major (queries), or the region codes of Alg. 2 found by binary search
+// over the breakpoint table held in LDS.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int kRowsPerWave = 32;                  // two 16-row MFMA blocks
+constexpr int kRowsPerBlock = 4 * kRowsPerWave;   // 4 waves
+
+enum { EPI_COLMAJOR = 0, EPI_ROWMAJOR = 1, EPI_ENCODE = 2 };
+
+template <bool ALIGNED>
+__device__ __forceinline__ floatx4 load4(const float* __restrict__ p, int k, int d) {
+    floatx4 r;
+    if (ALIGNED && k + 4 <= d) {
+        float4 v = *reinterpret_cast<const float4*>(p + k);
+        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? p[k + t] : 0.0f;
+    }
+    return r;
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ shortx4 load4bf(const uint16_t* __restrict__ p, int k, int d) {
+    shortx4 r;
+    if (ALIGNED && k + 4 <= d) {
+        uint2 v = *reinterpret_cast<const uint2*>(p + k);
+        r[0] = (short)(v.x & 0xffff); r[1] = (short)(v.x >> 16);
+        r[2] = (short)(v.y & 0xffff); r[3] = (short)(v.y >> 16);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? (short)p[k + t] : (short)0;
+    }
+    return r;
+}
+
+// Rows r of X (or rows[r] when `rows` is given) times A^T; A is N x d, N <= 16*NT.
+// Accumulator layout of v_mfma_f32_16x16x4f32: lane l holds P[4*(l/16)+v][l%16].
+// The reduction index of MFMA step s inside a 16-wide chunk at k0 is
+// k0 + 4*(l/16) + s for both operands, so each lane reads 4 consecutive values.
+template <int NT, int EPI, bool ALIGNED, bool BF16>
+__global__ __launch_bounds__(256) void project_kernel(
+    const float* __restrict__ X, const uint16_t* __restrict__ Xbf,
+    const int32_t* __restrict__ rows, int64_t M, int d,
+    const float* __restrict__ A, const uint16_t* __restrict__ Abf, int N,
+    float* __restrict__ Pout, int64_t ldp,
+    const float* __restrict__ E, int N_r, int K, uint8_t* __restrict__ codes, int64_t n_codes)
+{
+    extern __shared__ unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15;
+    const int kq = lane >> 4;
+    const int64_t R0 = (int64_t)blockIdx.x * kRowsPerBlock;
+
+    float* sE = reinterpret_cast<float*>(smem);
+    uint8_t* sC = smem + (size_t)N * (N_r + 1) * sizeof(float);
+    if (EPI == EPI_ENCODE) {
+        const int tot = N * (N_r + 1);
+        for (int t = threadIdx.x; t < tot; t += blockDim.x) sE[t] = E[t];
+    }
+
+    int64_t src[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        int64_t r = R0 + wave * kRowsPerWave + rb * 16 + m;
+        if (r >= M) r = M - 1;
+        src[rb] = rows ? (int64_t)rows[r] : r;
+    }
+
+    floatx4 acc[2][NT];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[rb][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    if (!BF16) {
+        const float* xr0 = X + src[0] * (int64_t)d;
+        const float* xr1 = X + src[1] * (int64_t)d;
+        for (int k0 = 0; k0 < d; k0 += 16) {
+            const int kk = k0 + 4 * kq;
+            floatx4 xv0 = load4<ALIGNED>(xr0, kk, d);
+            floatx4 xv1 = load4<ALIGNED>(xr1, kk, d);
+            floatx4 av[NT];
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = ct * 16 + m;
+                if (c < N) av[ct] = load4<ALIGNED>(A + (int64_t)c * d, kk, d);
+                else av[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv0[s], av[ct][s], acc[0][ct], 0, 0, 0);
+                    acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv1[s], av[ct][s], acc[1][ct], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        // v_mfma_f32_16x16x16bf16_1k: lane l supplies 4 consecutive reduction
+        // elements k0 + 4*(l/16) .. +3 of its row (A operand) / column (B operand).
+        const uint16_t* xr0 = Xbf + src[0] * (int64_t)d;
+        const uint16_t* xr1 = Xbf + src[1] * (int64_t)d;
+        for (int k0 = 0; k0 < d; k0 += 16) {
+            const int kk = k0 + 4 * kq;
+            shortx4 xv0 = load4bf<ALIGNED>(xr0, kk, d);
+            shortx4 xv1 = load4bf<ALIGNED>(xr1, kk, d);
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int c = ct * 16 + m;
+                shortx4 av = (c < N) ? load4bf<ALIGNED>(Abf + (int64_t)c * d, kk, d)
+                                     : shortx4{0, 0, 0, 0};
+                acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv0, av, acc[0][ct], 0, 0, 0);
+                acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv1, av, acc[1][ct], 0, 0, 0);
+            }
+        }
+    }
+
+    if (EPI == EPI_COLMAJOR || EPI == EPI_ROWMAJOR) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = R0 + wave * kRowsPerWave + rb * 16 + 4 * kq + v;
+                    const int e = ct * 16 + m;
+                    if (r < M && e < N) {
+                        if (EPI == EPI_COLMAJOR) Pout[(int64_t)e * ldp + r] = acc[rb][ct][v];
+                        else Pout[r * N + e] = acc[rb][ct][v];
+                    }
+                }
+        return;
+    }
+
+    // EPI_ENCODE: code = max b in [0, N_r-1] with E[e][b] <= h, where
+    // E[e][0] = -inf and E[e][b] = B_e(b+1): the number of interior
+    // breakpoints B(2..N_r) that are <= h (a tie goes to the upper region).
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rl = wave * kRowsPerWave + rb * 16 + 4 * kq + v;
+                const int e = ct * 16 + m;
+                if (e < N) {
+                    const float h = acc[rb][ct][v];
+                    const float* Ee = sE + e * (N_r + 1);
+                    int pos = 0;
+                    for (int s = N_r >> 1; s > 0; s >>= 1)
+                        if (Ee[pos + s] <= h) pos += s;
+                    sC[rl * 64 + e] = (uint8_t)pos;
+                }
+            }
+    __syncthreads();
+    // codes layout [L][n][K]: the tile of tree i is rows R0.. contiguous K-byte words
+    const int L = N / K;
+    const int64_t rows_here = (M - R0 < kRowsPerBlock) ? (M - R0) : kRowsPerBlock;
+    const int words_per_tree = (int)(rows_here * K / 4);
+    for (int i = 0; i < L; ++i) {
+        uint32_t* dst = reinterpret_cast<uint32_t*>(codes + ((int64_t)i * n_codes + R0) * K);
+        for (int w = threadIdx.x; w < words_per_tree; w += blockDim.x) {
+            const int byte = w * 4;
+            const int rl = byte / K;
+            const int j = byte % K;
+            const uint8_t* sp = sC + rl * 64 + i * K + j;
+            dst[w] = (uint32_t)sp[0] | ((uint32_t)sp[1] << 8) | ((uint32_t)sp[2] << 16) |
+                     ((uint32_t)sp[3] << 24);
+        }
+    }
+}
+
+template <int NT, int EPI>
+hipError_t launch_nt(const ProjectArgs& a, hipStream_t st) {
+    const int64_t blocks = (a.M + kRowsPerBlock - 1) / kRowsPerBlock;
+    size_t shm = 0;
+    if (EPI == EPI_ENCODE) shm = (size_t)a.N * (a.N_r + 1) * sizeof(float) + kRowsPerBlock * 64;
+    const bool aligned = (a.d % 4) == 0;
+    dim3 grid((unsigned)blocks), block(256);
+    if (a.bf16) {
+        if (aligned)
+            hipLaunchKernelGGL((project_kernel<NT, EPI, true, true>), grid, block, shm, st, a.X, a.Xbf,
+                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
+                               a.codes, a.n_codes);
+        else
+            hipLaunchKernelGGL((project_kernel<NT, EPI, false, true>), grid, block, shm, st, a.X, a.Xbf,
+                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
+                               a.codes, a.n_codes);
+    } else {
+        if (aligned)
+            hipLaunchKernelGGL((project_kernel<NT, EPI, true, false>), grid, block, shm, st, a.X, a.Xbf,
+                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
+                               a.codes, a.n_codes);
+        else
+            hipLaunchKernelGGL((project_kernel<NT, EPI, false, false>), grid, block, shm, st, a.X, a.Xbf,
+                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
+                               a.codes, a.n_codes);
+    }
+    return hipGetLastError();
+}
+
+template <int EPI>
+hipError_t launch_epi(const ProjectArgs& a, hipStream_t st) {
+    const int nt = (a.N + 15) / 16;
+    switch (nt) {
+        case 1: return launch_nt<1, EPI>(a, st);
+        case 2: return launch_nt<2, EPI>(a, st);
+        case 3: return launch_nt<3, EPI>(a, st);
+        default: return launch_nt<4, EPI>(a, st);
+    }
+}
+
+}  // namespace
+
+hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st) {
+    if (a.M <= 0) return hipSuccess;
+    switch (mode) {
+        case PROJ_COLMAJOR: return launch_epi<EPI_COLMAJOR>(a, st);
+        case PROJ_ROWMAJOR: return launch_epi<EPI_ROWMAJOR>(a, st);
+        default: return launch_epi<EPI_ENCODE>(a, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 -> BF16 copy (round to nearest even)
+// ---------------------------------------------------------------------------
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < cnt; i += stride) y[i] = dl_f32_to_bf16(x[i]);
+}
+
+hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    int64_t blocks = (cnt + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, y, cnt);
+    return hipGetLastError();
+}

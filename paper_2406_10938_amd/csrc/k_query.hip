@@ -1,0 +1,557 @@
+// Query phase (Sec. 4.3, Alg. 4-7, Sec. 5.2) on the GPU.
+//
+// The candidate predicate of tree i is LB_i(q,o)^2 <= (eps r)^2 where LB_i is
+// the distance from the projected query to the cell of o (the box between the
+// breakpoints around o's regions, open at the two outer ends).  With
+// m(o)^2 = min_i LB_i(o)^2, the union of the L range queries at radius r is
+// {o : m(o)^2 <= (eps r)^2}; Alg. 7 adds trees in order and stops once
+// |S| >= N_S = k + ceil(beta n).  Started at the smallest radius that meets both
+// magic-radius conditions of Sec. 5.2, (eps r)^2 = thr = the N_S-th smallest
+// m^2, the query ends after tree i* = min{i : |U_i| >= N_S}, U_i = the union of
+// trees 1..i, with S = U_{i*}.
+//
+// Pipeline per chunk of queries:
+//   guess_kernel   per query, m^2 over a fixed subset of G points and a rank
+//                  chosen so that {m^2 <= g} holds N_S..cap points w.h.p.
+//   filter_kernel  one lane per point, every query of the chunk: the cell
+//                  bounds of the point (lo, hi per dimension) stay in
+//                  registers, each lower bound is (q - med3(q, lo, hi))^2
+//                  summed over the K dimensions; hits are compacted with a
+//                  wave ballot and one atomic per wave and query
+//   select_kernel  exact thr among the compacted candidates (radix select),
+//                  tree-prefix counts give i*, S is compacted in place
+//   verify_kernel  exact FP32 squared distances of S by direct differences
+//                  (half a wave per row), then top-k by (distance, id)
+// A query whose candidate count falls outside [N_S, cap] is flagged and run
+// again by the host with every point a candidate.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+struct SelectShared;
+}
+size_t dl_guess_smem(int L, int K, int N_r, int G);
+
+namespace {
+
+constexpr uint64_t kGuessMul = 2654435761ull;   // prime > 2^31: t -> t*a mod n is a bijection
+
+// ---------------------------------------------------------------------------
+// cell bounds and lower bounds
+// ---------------------------------------------------------------------------
+
+template <int L, int K>
+__device__ __forceinline__ void load_cell(const uint8_t* __restrict__ codes, int64_t n, int64_t o,
+                                          const float* __restrict__ E, int ldE, float (&lo)[L * K],
+                                          float (&hi)[L * K]) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(codes + ((int64_t)i * n + o) * K);
+        uint32_t words[K / 4];
+        if constexpr (K % 16 == 0) {
+#pragma unroll
+            for (int c = 0; c < K / 16; ++c) {
+                uint4 v = reinterpret_cast<const uint4*>(w)[c];
+                words[4 * c] = v.x; words[4 * c + 1] = v.y; words[4 * c + 2] = v.z; words[4 * c + 3] = v.w;
+            }
+        } else if constexpr (K == 8) {
+            uint2 v = reinterpret_cast<const uint2*>(w)[0];
+            words[0] = v.x; words[1] = v.y;
+        } else {
+            words[0] = w[0];
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = i * K + j;
+            const uint32_t code = (words[j >> 2] >> (8 * (j & 3))) & 0xffu;
+            lo[e] = E[e * ldE + code];
+            hi[e] = E[e * ldE + code + 1];
+        }
+    }
+}
+
+// LB_i^2 = sum_j (q_j - clamp(q_j, lo_j, hi_j))^2, j ascending.
+template <int L, int K>
+__device__ __forceinline__ float cell_lbs(const float* __restrict__ qp, const float (&lo)[L * K],
+                                          const float (&hi)[L * K], float (&lb)[L]) {
+    float m = INFINITY;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = i * K + j;
+            const float q = qp[e];
+            const float p = __builtin_amdgcn_fmed3f(q, lo[e], hi[e]);
+            const float dd = q - p;
+            acc = fmaf(dd, dd, acc);
+        }
+        lb[i] = acc;
+        m = fminf(m, acc);
+    }
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// block-level selection helpers (256 threads)
+// ---------------------------------------------------------------------------
+
+// Given hist[0..nbins) (nbins multiple of 256) and a 1-based rank r, find the
+// bin d with cum(<d) < r <= cum(<=d).  Results in *d_out, *before_out,
+// *total_out (sum of all bins).  Uses scratch[0..257].
+__device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* scratch, int* d_out,
+                         uint64_t* before_out, uint64_t* total_out) {
+    const int per = nbins / 256;
+    const int tid = threadIdx.x;
+    uint32_t s = 0;
+    for (int b = 0; b < per; ++b) s += hist[tid * per + b];
+    scratch[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t run = 0;
+        int sel = -1;
+        uint64_t before = 0;
+        for (int t = 0; t < 256; ++t) {
+            const uint64_t nx = run + scratch[t];
+            if (sel < 0 && nx >= r) {
+                uint64_t rr = run;
+                for (int b = 0; b < per; ++b) {
+                    const uint32_t c = hist[t * per + b];
+                    if (rr + c >= r) { sel = t * per + b; before = rr; break; }
+                    rr += c;
+                }
+            }
+            run = nx;
+        }
+        *d_out = sel;
+        *before_out = before;
+        *total_out = run;
+    }
+    __syncthreads();
+}
+
+// Value of the r-th smallest (1-based) non-negative float among vals[0..m)
+// (global or LDS), by three radix passes (12, 12, 8 bits) over the bit pattern.
+struct SelectShared {
+    uint32_t hist[4096];
+    uint32_t scratch[260];
+    int d;
+    uint64_t before, total;
+};
+
+__device__ float select_rank_f32(const float* vals, int64_t m, uint64_t r, SelectShared& sh) {
+    uint32_t prefix = 0;
+    int known = 0;
+    const int nb_tab[3] = {12, 12, 8};
+    for (int p = 0; p < 3; ++p) {
+        const int nbits = nb_tab[p];
+        const int shift = 32 - known - nbits;
+        for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < m; i += 256) {
+            const uint32_t u = __float_as_uint(vals[i]);
+            if (known == 0 || (u >> (32 - known)) == prefix)
+                atomicAdd(&sh.hist[(u >> shift) & ((1u << nbits) - 1u)], 1u);
+        }
+        __syncthreads();
+        find_bin(sh.hist, 4096, r, sh.scratch, &sh.d, &sh.before, &sh.total);
+        r -= sh.before;
+        prefix = (prefix << nbits) | (uint32_t)sh.d;
+        known += nbits;
+        __syncthreads();
+    }
+    return __uint_as_float(prefix);
+}
+
+// The k smallest of m unique 64-bit keys in buf (global), sorted ascending into
+// out[0..k).  Radix descent on 12-bit digits; as soon as the keys sharing the
+// current prefix fit in LDS they are sorted there.
+constexpr int kCandCap = 1024;
+constexpr int kOutCap = 1024;
+
+struct TopkShared {
+    uint32_t hist[4096];
+    uint32_t scratch[260];
+    uint64_t cand[kCandCap];
+    uint64_t out[kOutCap];
+    int d;
+    uint64_t before, total;
+    uint32_t ncand, nout;
+};
+
+__device__ void bitonic_sort_u64(uint64_t* a, int cnt) {
+    int n2 = 1;
+    while (n2 < cnt) n2 <<= 1;
+    for (int i = cnt + threadIdx.x; i < n2; i += 256) a[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= n2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n2 / 2; i += 256) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = ((lo & size) == 0);
+                const uint64_t x = a[lo], y = a[hi];
+                if ((x > y) == up) { a[lo] = y; a[hi] = x; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ void topk_u64(const uint64_t* buf, int64_t m, int k, TopkShared& sh) {
+    uint64_t prefix = 0;
+    int known = 0;
+    uint64_t need = (uint64_t)k;
+    if (threadIdx.x == 0) sh.nout = 0;
+    __syncthreads();
+    while (true) {
+        const int nbits = (64 - known) < 12 ? (64 - known) : 12;
+        const int shift = 64 - known - nbits;
+        for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < m; i += 256) {
+            const uint64_t key = buf[i];
+            if (known == 0 || (key >> (64 - known)) == prefix)
+                atomicAdd(&sh.hist[(uint32_t)(key >> shift) & ((1u << nbits) - 1u)], 1u);
+        }
+        __syncthreads();
+        find_bin(sh.hist, 4096, need, sh.scratch, &sh.d, &sh.before, &sh.total);
+        const uint64_t M = sh.total;
+        if (M <= (uint64_t)kCandCap) {
+            if (threadIdx.x == 0) sh.ncand = 0;
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < m; i += 256) {
+                const uint64_t key = buf[i];
+                if (known == 0 || (key >> (64 - known)) == prefix) sh.cand[atomicAdd(&sh.ncand, 1u)] = key;
+            }
+            __syncthreads();
+            bitonic_sort_u64(sh.cand, (int)M);
+            const uint32_t base = sh.nout;
+            for (uint64_t j = threadIdx.x; j < need; j += 256) sh.out[base + j] = sh.cand[j];
+            __syncthreads();
+            if (threadIdx.x == 0) sh.nout = base + (uint32_t)need;
+            __syncthreads();
+            break;
+        }
+        const uint32_t dsel = (uint32_t)sh.d;
+        for (int64_t i = threadIdx.x; i < m; i += 256) {
+            const uint64_t key = buf[i];
+            if ((known == 0 || (key >> (64 - known)) == prefix) &&
+                ((uint32_t)(key >> shift) & ((1u << nbits) - 1u)) < dsel)
+                sh.out[atomicAdd(&sh.nout, 1u)] = key;
+        }
+        need -= sh.before;
+        prefix = (prefix << nbits) | dsel;
+        known += nbits;
+        __syncthreads();
+    }
+    bitonic_sort_u64(sh.out, (int)sh.nout);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+template <int L, int K>
+__global__ __launch_bounds__(256) void guess_kernel(const float* __restrict__ E, int N_r,
+                                                    const uint8_t* __restrict__ codes, int64_t n, int G,
+                                                    const float* __restrict__ Qp, int64_t q0,
+                                                    uint64_t rank, float* __restrict__ gthr)
+{
+    extern __shared__ unsigned char smem[];
+    constexpr int LK = L * K;
+    const int ldE = N_r + 1;
+    float* sE = reinterpret_cast<float*>(smem);
+    float* sm = sE + LK * ldE;
+    SelectShared& sh = *reinterpret_cast<SelectShared*>(sm + ((G + 1) & ~1));
+    for (int t = threadIdx.x; t < LK * ldE; t += 256) sE[t] = E[t];
+    __syncthreads();
+    const float* qp = Qp + (q0 + blockIdx.x) * LK;
+    for (int t = threadIdx.x; t < G; t += 256) {
+        const int64_t o = (G == n) ? (int64_t)t : (int64_t)(((uint64_t)t * kGuessMul) % (uint64_t)n);
+        float lo[LK], hi[LK], lb[L];
+        load_cell<L, K>(codes, n, o, sE, ldE, lo, hi);
+        sm[t] = cell_lbs<L, K>(qp, lo, hi, lb);
+    }
+    __syncthreads();
+    const float g = select_rank_f32(sm, G, rank, sh);
+    if (threadIdx.x == 0) gthr[blockIdx.x] = g;
+}
+
+template <int L, int K>
+__global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E, int N_r,
+                                                     const uint8_t* __restrict__ codes, int64_t n,
+                                                     const float* __restrict__ Qp, int64_t q0, int nqc,
+                                                     int q_per_block, const float* __restrict__ gthr,
+                                                     uint32_t* __restrict__ counts, int64_t cap,
+                                                     int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
+                                                     float* __restrict__ cand_lb)
+{
+    constexpr int LK = L * K;
+    const int ldE = N_r + 1;
+    const int64_t o_raw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = o_raw < n;
+    const int64_t o = valid ? o_raw : n - 1;
+    const int lane = threadIdx.x & 63;
+    float lo[LK], hi[LK];
+    load_cell<L, K>(codes, n, o, E, ldE, lo, hi);
+    const int ta = blockIdx.y * q_per_block;
+    const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
+    for (int t = ta; t < tb; ++t) {
+        const float* qp = Qp + (q0 + t) * LK;
+        float lb[L];
+        const float m = cell_lbs<L, K>(qp, lo, hi, lb);
+        const bool hit = valid && (m <= gthr[t]);
+        const uint64_t mask = dl_ballot(hit);
+        if (mask == 0) continue;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counts[t], (uint32_t)__popcll(mask));
+        base = dl_shfl_u32(base, leader);
+        if (hit) {
+            const int64_t idx = (int64_t)base + dl_rank_below(mask);
+            if (idx < cap) {
+                const int64_t at = (int64_t)t * cap + idx;
+                cand_id[at] = (int32_t)o;
+                cand_m[at] = m;
+#pragma unroll
+                for (int i = 0; i < L; ++i) cand_lb[((int64_t)t * L + i) * cap + idx] = lb[i];
+            }
+        }
+    }
+}
+
+// Block-wide exclusive prefix of a 0/1 flag over 256 threads; returns the
+// prefix and writes the block total to *tot.
+__device__ __forceinline__ uint32_t block_flag_prefix(bool f, uint32_t* wtot, uint32_t* tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t msk = dl_ballot(f);
+    const uint32_t r = (uint32_t)dl_rank_below(msk);
+    if (lane == 0) wtot[wave] = (uint32_t)__popcll(msk);
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) pre += wtot[w];
+        all += wtot[w];
+    }
+    *tot = all;
+    __syncthreads();
+    return pre + r;
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict__ counts, int64_t cap,
+                                                     uint64_t N_S, int32_t* __restrict__ cand_id,
+                                                     float* __restrict__ cand_m, const float* __restrict__ cand_lb,
+                                                     int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
+                                                     float* __restrict__ thr_out, int32_t* __restrict__ stop_out)
+{
+    __shared__ SelectShared sh;
+    __shared__ uint32_t tc[8];
+    __shared__ uint32_t wtot[4];
+    const int t = blockIdx.x;
+    const uint64_t cnt = counts[t];
+    if (cnt < N_S || cnt > (uint64_t)cap) {
+        if (threadIdx.x == 0) { status[t] = 1; s_count[t] = 0; }
+        return;
+    }
+    const float* mv = cand_m + (int64_t)t * cap;
+    const float thr = select_rank_f32(mv, (int64_t)cnt, N_S, sh);
+    // |U_i| for i = 1..L: entries whose prefix minimum over trees 1..i is <= thr
+    if (threadIdx.x < 8) tc[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t loc[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) loc[i] = 0;
+    for (int64_t s = threadIdx.x; s < (int64_t)cnt; s += 256) {
+        float pm = INFINITY;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            pm = fminf(pm, cand_lb[((int64_t)t * L + i) * cap + s]);
+            loc[i] += (pm <= thr) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const uint32_t v = dl_wave_sum(loc[i]);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&tc[i], v);
+    }
+    __syncthreads();
+    int istop = L;
+    for (int i = 0; i < L; ++i)
+        if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
+    // in-place stable compaction of S = U_{istop}; first admitting tree kept in cand_m
+    int32_t* ids = cand_id + (int64_t)t * cap;
+    int32_t* ftree = reinterpret_cast<int32_t*>(cand_m + (int64_t)t * cap);
+    uint32_t out = 0;
+    for (int64_t c0 = 0; c0 < (int64_t)cnt; c0 += 256) {
+        const int64_t s = c0 + threadIdx.x;
+        bool mem = false;
+        int32_t id = 0, ft = 0;
+        if (s < (int64_t)cnt) {
+            id = ids[s];
+            for (int i = 0; i < L; ++i) {
+                if (ft == 0 && cand_lb[((int64_t)t * L + i) * cap + s] <= thr) ft = i + 1;
+            }
+            mem = (ft != 0 && ft <= istop);
+        }
+        uint32_t tot;
+        const uint32_t pre = block_flag_prefix(mem, wtot, &tot);
+        if (mem) {
+            ids[out + pre] = id;
+            ftree[out + pre] = ft;
+        }
+        out += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        status[t] = 0;
+        s_count[t] = out;
+        thr_out[t] = thr;
+        stop_out[t] = istop;
+    }
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(256) void verify_kernel(const float* __restrict__ X, int d,
+                                                     const float* __restrict__ Q, int64_t q0,
+                                                     const int32_t* __restrict__ cand_id, int64_t cap,
+                                                     const uint32_t* __restrict__ s_count,
+                                                     const int32_t* __restrict__ status, int64_t all_n,
+                                                     uint64_t* __restrict__ ws, int k,
+                                                     int64_t* __restrict__ out_ids, float* __restrict__ out_d)
+{
+    extern __shared__ unsigned char smem[];
+    TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
+    float* sq = reinterpret_cast<float*>(smem + sizeof(TopkShared));
+    const int t = blockIdx.x;
+    if (all_n == 0 && status[t] != 0) return;
+    const int64_t q = q0 + t;
+    for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
+    __syncthreads();
+    const int64_t m = all_n ? all_n : (int64_t)s_count[t];
+    const int32_t* ids = cand_id + (int64_t)t * cap;
+    uint64_t* buf = ws + (int64_t)t * cap;
+    const int hl = threadIdx.x & 31;
+    const int hw = threadIdx.x >> 5;
+    for (int64_t s = hw; s < m; s += 8) {
+        const int64_t id = all_n ? s : (int64_t)ids[s];
+        const float* x = X + id * d;
+        float acc = 0.0f;
+        for (int c = 4 * hl; c < d; c += 128) {
+            if (ALIGNED && c + 4 <= d) {
+                const float4 v = *reinterpret_cast<const float4*>(x + c);
+                float df = v.x - sq[c];     acc = fmaf(df, df, acc);
+                df = v.y - sq[c + 1];       acc = fmaf(df, df, acc);
+                df = v.z - sq[c + 2];       acc = fmaf(df, df, acc);
+                df = v.w - sq[c + 3];       acc = fmaf(df, df, acc);
+            } else {
+                for (int u = 0; u < 4; ++u)
+                    if (c + u < d) { const float df = x[c + u] - sq[c + u]; acc = fmaf(df, df, acc); }
+            }
+        }
+#pragma unroll
+        for (int o2 = 16; o2 > 0; o2 >>= 1) acc += __shfl_xor(acc, o2, 32);
+        if (hl == 0) buf[s] = ((uint64_t)__float_as_uint(acc) << 32) | (uint64_t)(uint32_t)id;
+    }
+    __threadfence_block();
+    __syncthreads();
+    topk_u64(buf, m, k, sh);
+    for (int j = threadIdx.x; j < k; j += 256) {
+        const uint64_t key = sh.out[j];
+        out_ids[q * k + j] = (int64_t)(uint32_t)(key & 0xffffffffu);
+        out_d[q * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over (L, K)
+// ---------------------------------------------------------------------------
+
+template <int L, int K>
+hipError_t launch_guess_lk(const QueryArgs& a, hipStream_t st) {
+    const size_t shm = dl_guess_smem(L, K, a.N_r, a.G);
+    hipLaunchKernelGGL((guess_kernel<L, K>), dim3(a.nqc), dim3(256), shm, st, a.E, a.N_r, a.codes, a.n, a.G,
+                       a.Qp, a.q0, a.guess_rank, a.gthr);
+    return hipGetLastError();
+}
+
+template <int L, int K>
+hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
+    const int64_t pb = (a.n + 255) / 256;
+    int ny = 1;
+    // enough blocks to fill the machine several times over
+    while (pb * ny < 4096 && ny < a.nqc) ny *= 2;
+    if (ny > a.nqc) ny = a.nqc;
+    const int qpb = (a.nqc + ny - 1) / ny;
+    hipLaunchKernelGGL((filter_kernel<L, K>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E, a.N_r,
+                       a.codes, a.n, a.Qp, a.q0, a.nqc, qpb, a.gthr, a.counts, a.cap, a.cand_id, a.cand_m,
+                       a.cand_lb);
+    return hipGetLastError();
+}
+
+#define DL_LK_DISPATCH(FN)                                        \
+    switch (a.L * 100 + a.K) {                                    \
+        case 104: return FN<1, 4>(a, st);                         \
+        case 204: return FN<2, 4>(a, st);                         \
+        case 404: return FN<4, 4>(a, st);                         \
+        case 804: return FN<8, 4>(a, st);                         \
+        case 108: return FN<1, 8>(a, st);                         \
+        case 208: return FN<2, 8>(a, st);                         \
+        case 408: return FN<4, 8>(a, st);                         \
+        case 808: return FN<8, 8>(a, st);                         \
+        case 116: return FN<1, 16>(a, st);                        \
+        case 216: return FN<2, 16>(a, st);                        \
+        case 416: return FN<4, 16>(a, st);                        \
+        case 132: return FN<1, 32>(a, st);                        \
+        case 232: return FN<2, 32>(a, st);                        \
+        default: return hipErrorInvalidValue;                     \
+    }
+
+template <int L>
+hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((select_kernel<L>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
+                       a.cand_m, a.cand_lb, a.status, a.s_count, a.thr, a.stop);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t dl_guess_smem(int L, int K, int N_r, int G) {
+    return (size_t)L * K * (N_r + 1) * 4 + (size_t)((G + 1) & ~1) * 4 + sizeof(SelectShared) + 64;
+}
+
+bool dl_supported_lk(int L, int K) {
+    switch (L * 100 + K) {
+        case 104: case 204: case 404: case 804: case 108: case 208: case 408: case 808:
+        case 116: case 216: case 416: case 132: case 232: return true;
+        default: return false;
+    }
+}
+
+
+hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st) { DL_LK_DISPATCH(launch_guess_lk) }
+hipError_t dl_launch_filter(const QueryArgs& a, hipStream_t st) { DL_LK_DISPATCH(launch_filter_lk) }
+
+hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
+    switch (a.L) {
+        case 1: return launch_select_l<1>(a, st);
+        case 2: return launch_select_l<2>(a, st);
+        case 4: return launch_select_l<4>(a, st);
+        case 8: return launch_select_l<8>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t dl_launch_verify(const QueryArgs& a, hipStream_t st) {
+    const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
+    if (a.d % 4 == 0)
+        hipLaunchKernelGGL((verify_kernel<true>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, a.cand_id,
+                           a.cap, a.s_count, a.status, a.all_n, a.ws, a.k, a.out_ids, a.out_d);
+    else
+        hipLaunchKernelGGL((verify_kernel<false>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0,
+                           a.cand_id, a.cap, a.s_count, a.status, a.all_n, a.ws, a.k, a.out_ids, a.out_d);
+    return hipGetLastError();
+}
+
+size_t dl_verify_smem(int d) { return sizeof(TopkShared) + (size_t)d * 4 + 64; }

@@ -1,0 +1,302 @@
+// DE-Tree construction (Alg. 3, Sec. 4.2) as sorted leaf runs.
+//
+// Per tree: points are radix-sorted by their root key (the first bit of every
+// dimension's code: one root child per key), which makes every root child a
+// contiguous run of a permutation.  Runs holding more than max_leaf points are
+// split, one workgroup per run, depth first: a node is cut in two on the
+// dimension whose next code bit divides its points most evenly (ties to the
+// lowest dimension), zeros first, stable.  A node whose prefixes are complete
+// stays a leaf.  Leaves are written as (start offset, per-dimension lowest and
+// highest region code of the node's bit prefixes).
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int kMaxK = 32;
+constexpr int kStack = 288;
+
+__global__ void root_key_kernel(const uint8_t* __restrict__ codes_i, int64_t n, int K, int bits,
+                                uint32_t* __restrict__ key, uint32_t* __restrict__ val)
+{
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; o < n; o += stride) {
+        const uint8_t* c = codes_i + o * K;
+        uint32_t k = 0;
+        for (int j = 0; j < K; ++j) k = (k << 1) | ((c[j] >> (bits - 1)) & 1u);
+        key[o] = k;
+        val[o] = (uint32_t)o;
+    }
+}
+
+// perm[r] = val[r]; sorted code words scodes[r] = codes_i[perm[r]]; run-start flags.
+__global__ void gather_runs_kernel(const uint8_t* __restrict__ codes_i, const uint32_t* __restrict__ key,
+                                   const uint32_t* __restrict__ val, int64_t n, int K,
+                                   int32_t* __restrict__ perm, uint8_t* __restrict__ scodes,
+                                   uint32_t* __restrict__ flag)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; r < n; r += stride) {
+        const uint32_t o = val[r];
+        perm[r] = (int32_t)o;
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(codes_i + (int64_t)o * K);
+        uint32_t* d = reinterpret_cast<uint32_t*>(scodes + r * K);
+        for (int w = 0; w < K / 4; ++w) d[w] = s[w];
+        flag[r] = (r == 0 || key[r] != key[r - 1]) ? 1u : 0u;
+    }
+}
+
+__global__ void run_starts_kernel(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                                  int64_t n, int32_t* __restrict__ run_start, uint32_t nruns)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; r < n; r += stride)
+        if (flag[r]) run_start[idx[r]] = (int32_t)r;
+    if (blockIdx.x == 0 && threadIdx.x == 0) run_start[nruns] = (int32_t)n;
+}
+
+struct Node {
+    int32_t a, b;
+    uint8_t plen[kMaxK];
+};
+
+// One workgroup per root run.  Leaf records go to slots [s, s + nleaf) of the
+// run's own position range (a run of m points has at most m leaves).
+__global__ __launch_bounds__(256) void split_runs_kernel(
+    const int32_t* __restrict__ run_start, int32_t* __restrict__ perm, uint8_t* __restrict__ scodes,
+    int32_t* __restrict__ tperm, uint8_t* __restrict__ tcodes, int K, int bits, int max_leaf,
+    int32_t* __restrict__ rec_start, uint8_t* __restrict__ rec_plen, uint32_t* __restrict__ nleaf)
+{
+    __shared__ Node stack[kStack];
+    __shared__ int sp;
+    __shared__ uint32_t ones[kMaxK];
+    __shared__ uint32_t wsum[4];
+    __shared__ int cnt_leaf;
+    __shared__ Node cur;
+    __shared__ int best_j;
+
+    const int q = blockIdx.x;
+    const int32_t s = run_start[q];
+    const int32_t t = run_start[q + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    if (t - s <= max_leaf) {
+        if (tid == 0) {
+            rec_start[s] = s;
+            for (int j = 0; j < K; ++j) rec_plen[(int64_t)s * K + j] = 1;
+            nleaf[q] = 1;
+        }
+        return;
+    }
+    if (tid == 0) {
+        sp = 1;
+        stack[0].a = s;
+        stack[0].b = t;
+        for (int j = 0; j < kMaxK; ++j) stack[0].plen[j] = 1;
+        cnt_leaf = 0;
+    }
+    __syncthreads();
+    while (true) {
+        if (tid == 0) {
+            if (sp > 0) cur = stack[--sp];
+            else cur.a = -1;
+        }
+        __syncthreads();
+        if (cur.a < 0) break;
+        const int a = cur.a, b = cur.b, size = b - a;
+        bool all_full = true;
+        for (int j = 0; j < K; ++j) all_full = all_full && (cur.plen[j] >= bits);
+        if (size <= max_leaf || all_full) {
+            if (tid == 0) {
+                const int slot = s + cnt_leaf;
+                rec_start[slot] = a;
+                for (int j = 0; j < K; ++j) rec_plen[(int64_t)slot * K + j] = cur.plen[j];
+                ++cnt_leaf;
+            }
+            __syncthreads();
+            continue;
+        }
+        // count ones of the next bit of every open dimension
+        if (tid < kMaxK) ones[tid] = 0;
+        __syncthreads();
+        uint32_t loc[kMaxK];
+        for (int j = 0; j < K; ++j) loc[j] = 0;
+        for (int r = a + tid; r < b; r += 256) {
+            const uint8_t* c = scodes + (int64_t)r * K;
+            for (int j = 0; j < K; ++j)
+                if (cur.plen[j] < bits) loc[j] += (c[j] >> (bits - 1 - cur.plen[j])) & 1u;
+        }
+        for (int j = 0; j < K; ++j) {
+            uint32_t v = dl_wave_sum(loc[j]);
+            if (lane == 0 && v) atomicAdd(&ones[j], v);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int bj = -1;
+            long long bg = 0;
+            for (int j = 0; j < K; ++j) {
+                if (cur.plen[j] >= bits) continue;
+                long long g = 2LL * (long long)ones[j] - size;
+                if (g < 0) g = -g;
+                if (bj < 0 || g < bg) { bj = j; bg = g; }
+            }
+            best_j = bj;
+        }
+        __syncthreads();
+        const int j = best_j;
+        const int sh = bits - 1 - cur.plen[j];
+        const int nz = size - (int)ones[j];
+        // stable partition of [a, b) by the bit: zeros to [a, a+nz), ones after
+        uint32_t zbase = 0, obase = 0;
+        for (int c0 = a; c0 < b; c0 += 256) {
+            const int r = c0 + tid;
+            const bool valid = r < b;
+            uint32_t bit = 0;
+            if (valid) bit = (scodes[(int64_t)r * K + j] >> sh) & 1u;
+            const uint64_t om = dl_ballot(valid && bit);
+            const uint64_t zm = dl_ballot(valid && !bit);
+            const int orank = dl_rank_below(om), zrank = dl_rank_below(zm);
+            if (lane == 0) wsum[wave] = (uint32_t)__popcll(om) | ((uint32_t)__popcll(zm) << 16);
+            __syncthreads();
+            uint32_t opre = 0, zpre = 0, otot = 0, ztot = 0;
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t o = wsum[w] & 0xffffu, z = wsum[w] >> 16;
+                if (w < wave) { opre += o; zpre += z; }
+                otot += o; ztot += z;
+            }
+            if (valid) {
+                const int64_t dst = bit ? (int64_t)a + nz + obase + opre + orank
+                                        : (int64_t)a + zbase + zpre + zrank;
+                tperm[dst] = perm[r];
+                const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K);
+                uint32_t* dw = reinterpret_cast<uint32_t*>(tcodes + dst * K);
+                for (int w = 0; w < K / 4; ++w) dw[w] = sw[w];
+            }
+            obase += otot;
+            zbase += ztot;
+            __syncthreads();
+        }
+        for (int r = a + tid; r < b; r += 256) {
+            perm[r] = tperm[r];
+            const uint32_t* sw = reinterpret_cast<const uint32_t*>(tcodes + (int64_t)r * K);
+            uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)r * K);
+            for (int w = 0; w < K / 4; ++w) dw[w] = sw[w];
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) {
+            Node c1 = cur;
+            c1.plen[j] = (uint8_t)(cur.plen[j] + 1);
+            // push the ones child first so that the zeros child is visited first
+            if (b - (a + nz) > 0 && sp < kStack) { Node o = c1; o.a = a + nz; o.b = b; stack[sp++] = o; }
+            if (nz > 0 && sp < kStack) { Node z = c1; z.a = a; z.b = a + nz; stack[sp++] = z; }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) nleaf[q] = (uint32_t)cnt_leaf;
+}
+
+__global__ void leaf_table_kernel(const int32_t* __restrict__ run_start, const uint32_t* __restrict__ nleaf,
+                                  const uint32_t* __restrict__ loff, uint32_t nruns,
+                                  const int32_t* __restrict__ rec_start, const uint8_t* __restrict__ rec_plen,
+                                  const uint8_t* __restrict__ scodes, int K, int bits, int64_t n,
+                                  int32_t* __restrict__ leaf_start, uint8_t* __restrict__ leaf_lo,
+                                  uint8_t* __restrict__ leaf_hi, uint32_t total_leaves)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; q < nruns; q += stride) {
+        const int32_t s = run_start[q];
+        const uint32_t m = nleaf[q];
+        const uint32_t base = loff[q];
+        for (uint32_t t = 0; t < m; ++t) {
+            const int32_t st = rec_start[s + t];
+            leaf_start[base + t] = st;
+            for (int j = 0; j < K; ++j) {
+                const int pl = rec_plen[(int64_t)(s + t) * K + j];
+                const int free_bits = bits - pl;
+                const int lo = (scodes[(int64_t)st * K + j] >> free_bits) << free_bits;
+                leaf_lo[(int64_t)(base + t) * K + j] = (uint8_t)lo;
+                leaf_hi[(int64_t)(base + t) * K + j] = (uint8_t)(lo + (1 << free_bits) - 1);
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) leaf_start[total_leaves] = (int32_t)n;
+}
+
+inline unsigned grid_for(int64_t n, int block = 256) {
+    int64_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+size_t dl_tree_tmp_bytes(int64_t n, int K) {
+    // key, val, flag, idx, nleaf, loff (u32 x n each), tperm (i32 x n), tcodes (n*K),
+    // rec_start (n), rec_plen (n*K), run_start (n+1), radix/scan scratch
+    return (size_t)n * (4 * 9 + 2 * K) + dl_radix_tmp_bytes(n) + dl_scan_tmp_bytes(n) + 4096;
+}
+
+// Builds one tree.  Device outputs: perm[n], scodes[n*K]; the leaf table is
+// allocated here (cudaMalloc-style) and returned through *leaf_*.
+hipError_t dl_build_tree(const uint8_t* codes_i, int64_t n, int K, int N_r, int max_leaf, int32_t* perm,
+                         uint8_t* scodes, void* tmp, hipStream_t st, int64_t* n_leaves,
+                         int32_t** leaf_start, uint8_t** leaf_lo, uint8_t** leaf_hi) {
+    int bits = 0;
+    while ((1 << bits) < N_r) ++bits;
+    char* p = static_cast<char*>(tmp);
+    auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) & ~(size_t)255; return r; };
+    uint32_t* key = reinterpret_cast<uint32_t*>(take(n * 4));
+    uint32_t* val = reinterpret_cast<uint32_t*>(take(n * 4));
+    uint32_t* flag = reinterpret_cast<uint32_t*>(take(n * 4));
+    uint32_t* idx = reinterpret_cast<uint32_t*>(take(n * 4));
+    uint32_t* nleaf = reinterpret_cast<uint32_t*>(take(n * 4 + 4));
+    uint32_t* loff = reinterpret_cast<uint32_t*>(take(n * 4 + 4));
+    int32_t* tperm = reinterpret_cast<int32_t*>(take(n * 4));
+    uint8_t* tcodes = reinterpret_cast<uint8_t*>(take(n * K));
+    int32_t* rec_start = reinterpret_cast<int32_t*>(take(n * 4));
+    uint8_t* rec_plen = reinterpret_cast<uint8_t*>(take(n * K));
+    int32_t* run_start = reinterpret_cast<int32_t*>(take((n + 1) * 4));
+    uint32_t* totals = reinterpret_cast<uint32_t*>(take(64));
+    void* scratch = take(dl_radix_tmp_bytes(n) + dl_scan_tmp_bytes(n));
+
+    if (bits < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(root_key_kernel, dim3(grid_for(n)), dim3(256), 0, st, codes_i, n, K, bits, key, val);
+    hipError_t e = dl_radix_sort_pairs(key, val, n, 0, ((K + 7) / 8) * 8, scratch, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gather_runs_kernel, dim3(grid_for(n)), dim3(256), 0, st, codes_i, key, val, n, K, perm,
+                       scodes, flag);
+    e = dl_exclusive_scan(flag, idx, n, reinterpret_cast<uint32_t*>(scratch), totals, st);
+    if (e != hipSuccess) return e;
+    uint32_t nruns = 0;
+    e = hipMemcpyAsync(&nruns, totals, 4, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(run_starts_kernel, dim3(grid_for(n)), dim3(256), 0, st, flag, idx, n, run_start, nruns);
+    hipLaunchKernelGGL(split_runs_kernel, dim3(nruns), dim3(256), 0, st, run_start, perm, scodes, tperm, tcodes,
+                       K, bits, max_leaf, rec_start, rec_plen, nleaf);
+    e = dl_exclusive_scan(nleaf, loff, nruns, reinterpret_cast<uint32_t*>(scratch), totals + 1, st);
+    if (e != hipSuccess) return e;
+    uint32_t nl = 0;
+    e = hipMemcpyAsync(&nl, totals + 1, 4, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    *n_leaves = nl;
+    e = hipMalloc(leaf_start, (size_t)(nl + 1) * 4);
+    if (e != hipSuccess) return e;
+    e = hipMalloc(leaf_lo, (size_t)nl * K + 4);
+    if (e != hipSuccess) return e;
+    e = hipMalloc(leaf_hi, (size_t)nl * K + 4);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(leaf_table_kernel, dim3(grid_for(nruns)), dim3(256), 0, st, run_start, nleaf, loff, nruns,
+                       rec_start, rec_plen, scodes, K, bits, n, *leaf_start, *leaf_lo, *leaf_hi, nl);
+    return hipGetLastError();
+}

@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every symbol that include/detlsh.h
+declares; the ctypes binding declares exactly those (no compute calls: these
+run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "detlsh.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(detlsh_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("detlsh_build_index", "detlsh_query", "detlsh_free", "detlsh_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2406_10938_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2406_10938_amd import build as b
+        b.build(verbose=False)
+    so = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(so, name), name
+
+
+def test_binding_matches_header():
+    from paper_2406_10938_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_struct_layouts():
+    from paper_2406_10938_amd import _lib
+    assert ctypes.sizeof(_lib.BuildOpts) == 8 + 4 * 4 + 8 + 8
+    assert ctypes.sizeof(_lib.QueryOpts) == 4 * 4 + 8 + 8
+    assert ctypes.sizeof(_lib.Info) == 8 + 4 * 4 + 8 + 4 + 4 + 8 * 8 + 8
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_2406_10938_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()

@@ -1,0 +1,265 @@
+"""GPU parity of every step of the hot path against the FP64 oracle, through
+the C ABI, on seeded inputs that span several tiles and a ragged tail.
+
+Tolerances (BASELINE the benchmark spec): projected coordinates within 1e-5 of the
+dot product's magnitude sum_l |a_l o_l|; codes bit-exact except coordinates
+that close to a breakpoint (counted); candidate sets bit-exact when fed the
+oracle's codes, breakpoints and projected queries, except points whose FP64
+bound lies within 1e-5 relative of the stop threshold (counted); ids bit-exact
+except distance near-ties; distances within 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import gpu_util as U
+from oracle import detlsh_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2406_10938_amd as dl
+    dl._lib.lib()
+    return dl
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def t(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+# --------------------------------------------------------------------------
+# step a1: projection (MFMA GEMM)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,L,K", [(1000, 128, 4, 16), (777, 100, 4, 16), (513, 37, 2, 8),
+                                     (300, 960, 4, 16), (129, 96, 1, 32), (2000, 24, 8, 8)])
+def test_projection_parity(dl, n, d, L, K):
+    say(f"projection n={n} d={d} L={L} K={K}")
+    c = U.case(n=n, d=d, L=L, K=K, N_r=16, frac=0.2, nq=5, seed=n + d)
+    idx = dl.build_index(c["X"], L, K, 16, 0.2, A=c["A"], sample_ids=c["sample"])
+    got = idx.project(t(c["X"])).cpu().numpy().astype(np.float64)
+    ref = O.project(c["X"], c["A"])
+    tol = U.REL * U.proj_scale(c["X"], c["A"])
+    assert np.all(np.abs(got - ref) <= tol), np.abs(got - ref).max()
+
+
+@pytest.mark.parametrize("n,d", [(5000, 128), (3001, 96)])
+def test_bf16_projection_close(dl, n, d):
+    """The BF16 projection form rounds inputs to BF16 (8-bit mantissa); its
+    error is bounded by 2^-8 of the magnitude sum (not a parity claim)."""
+    say(f"bf16 projection n={n} d={d}")
+    c = U.case(n=n, d=d, N_r=64, frac=0.1, seed=7)
+    idx = dl.build_index(c["X"], 4, 16, 64, 0.1, A=c["A"], sample_ids=c["sample"], proj_bf16=True)
+    ex = idx.export()
+    assert ex["codes"].shape == (n, 64)
+    B_ref = O.breakpoints_by_sort(O.project(c["X"], c["A"])[c["sample"]], 64)
+    scale = U.proj_scale(c["X"][c["sample"]], c["A"]).max(axis=0)
+    assert np.all(np.abs(ex["B"] - B_ref) <= (2.0 ** -7) * scale[:, None])
+
+
+# --------------------------------------------------------------------------
+# steps a2 + a3: breakpoints (sample sort) and codes (binary search in LDS)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,N_r,frac,L,K", [(10_000, 128, 256, 0.1, 4, 16), (4097, 64, 64, 0.25, 4, 16),
+                                              (3000, 32, 16, 0.1, 2, 8), (2500, 48, 4, 0.05, 8, 4),
+                                              (20_000, 16, 256, 0.02, 1, 32)])
+def test_breakpoints_and_codes(dl, n, d, N_r, frac, L, K):
+    say(f"breakpoints/codes n={n} d={d} N_r={N_r} frac={frac} L={L} K={K}")
+    c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=frac, seed=n % 97)
+    idx = dl.build_index(c["X"], L, K, N_r, frac, A=c["A"], sample_ids=c["sample"])
+    ex = idx.export()
+    assert np.array_equal(ex["sample_ids"], c["sample"])
+    P, B_ref, codes_ref = U.oracle_encoding(c)
+    scale = U.proj_scale(c["X"], c["A"])
+    colscale = scale[c["sample"]].max(axis=0)
+    assert np.all(np.abs(ex["B"] - B_ref) <= U.REL * colscale[:, None])
+    assert np.all(np.diff(ex["B"], axis=1) >= 0)
+    nbad, hard = U.code_mismatches(P, scale, B_ref, ex["B"].astype(np.float64), codes_ref, ex["codes"])
+    say(f"  codes differing: {nbad} of {codes_ref.size}, all within tolerance of a breakpoint: {hard == 0}")
+    assert hard == 0
+
+
+# --------------------------------------------------------------------------
+# step a4: DE-Trees as leaf runs
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,K,N_r,max_leaf,kind", [(6000, 16, 64, 16, "mixture"), (20_000, 8, 16, 64, "mixture"),
+                                                   (5000, 4, 4, 8, "smallint"), (3000, 32, 256, 4, "mixture")])
+def test_tree_runs_match_oracle_tree(dl, n, K, N_r, max_leaf, kind):
+    say(f"trees n={n} K={K} N_r={N_r} max_leaf={max_leaf} kind={kind}")
+    L = 2
+    c = U.case(n=n, d=32, L=L, K=K, N_r=N_r, frac=0.2, kind=kind, seed=3)
+    idx = dl.build_index(c["X"], L, K, N_r, 0.2, A=c["A"], sample_ids=c["sample"], max_leaf=max_leaf)
+    codes = idx.export()["codes"]
+    bits = int(np.log2(N_r))
+    for i in range(L):
+        perm, start, lo, hi = idx.tree(i)
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        assert start[0] == 0 and start[-1] == n and np.all(np.diff(start) > 0)
+        ci = codes[:, i * K:(i + 1) * K].astype(np.int64)
+        got = set()
+        for t in range(len(start) - 1):
+            ids = perm[start[t]:start[t + 1]]
+            assert np.all(ci[ids] >= lo[t]) and np.all(ci[ids] <= hi[t])
+            width = hi[t].astype(int) - lo[t].astype(int) + 1
+            if len(ids) > max_leaf:
+                assert np.all(width == 1)
+            got.add((tuple(sorted(ids.tolist())), tuple(lo[t]), tuple(hi[t])))
+        ref = set()
+        for lf in O.build_tree(ci, N_r, max_leaf):
+            ref.add((tuple(lf.ids.tolist()), tuple(lf.lo.tolist()), tuple(lf.hi.tolist())))
+        assert got == ref
+        assert bits >= 1
+
+
+# --------------------------------------------------------------------------
+# steps a5 + a6 fed the oracle's encoding: candidate sets, ids, distances
+# --------------------------------------------------------------------------
+
+def _fed_oracle_case(dl, c, k, beta, **qkw):
+    P, B, codes = U.oracle_encoding(c)
+    B32 = B.astype(np.float32)
+    idx = dl.import_index(c["X"], c["A"], B32, codes, c["L"], c["K"], c["N_r"])
+    Qp32 = O.project(c["Q"], c["A"]).astype(np.float32)
+    r = idx.query_debug(t(c["Q"]), k, 1.5, beta, Qp=t(Qp32), **qkw)
+    r = {kk: v.cpu().numpy() for kk, v in r.items()}
+    border_total = tie_total = 0
+    for qi in range(len(c["Q"])):
+        ref = U.oracle_query(c["X"], c["Q"][qi], Qp32[qi], codes, B32, c["L"], c["K"], k, beta)
+        cnt = int(r["counts"][qi])
+        S_gpu = set(r["cand"][qi, :cnt].tolist())
+        S_ref = set(ref.S.tolist())
+        if S_gpu != S_ref:
+            border = U.borderline_points(Qp32[qi], codes, B32, c["L"], c["K"], ref.thr)
+            sym = S_gpu ^ S_ref
+            assert sym <= border, f"query {qi}: {len(sym - border)} non-borderline differences"
+            border_total += len(sym)
+            continue
+        assert abs(float(r["thr"][qi]) - ref.thr) <= U.REL * max(ref.thr, 1e-30)
+        assert int(r["stop_tree"][qi]) == ref.stop_tree
+        ft = dict(zip(r["cand"][qi, :cnt].tolist(), r["first_tree"][qi, :cnt].tolist()))
+        assert all(ft[o] == f for o, f in zip(ref.S.tolist(), ref.first_tree.tolist()))
+        tie_total += U.compare_result(ref.ids, ref.dists, c["X"], c["Q"][qi], r["ids"][qi], r["dists"][qi],
+                                      ref.S, k)
+    say(f"  borderline candidate differences: {border_total}; near-tie id differences: {tie_total}")
+    return r
+
+
+@pytest.mark.parametrize("n,d,N_r,k,beta,kind", [(10_000, 128, 256, 10, 0.1, "mixture"),
+                                                 (7001, 64, 64, 50, 0.05, "integer"),
+                                                 (3000, 40, 16, 10, 0.2, "mixture"),
+                                                 (20_000, 32, 256, 100, 0.01, "integer")])
+def test_candidates_and_results_fed_oracle_encoding(dl, n, d, N_r, k, beta, kind):
+    say(f"fed-oracle query n={n} d={d} N_r={N_r} k={k} beta={beta} kind={kind}")
+    c = U.case(n=n, d=d, N_r=N_r, frac=0.1, kind=kind, nq=12, seed=11)
+    _fed_oracle_case(dl, c, k, beta)
+
+
+@pytest.mark.parametrize("L,K", [(1, 16), (2, 32), (8, 8), (4, 4), (1, 4), (2, 8)])
+def test_fed_oracle_other_tree_shapes(dl, L, K):
+    say(f"fed-oracle query L={L} K={K}")
+    c = U.case(n=5000, d=48, L=L, K=K, N_r=32, frac=0.1, nq=8, seed=L * 10 + K)
+    _fed_oracle_case(dl, c, 10, 0.1)
+
+
+def test_ties_and_fallback_path(dl):
+    """Few regions and small-integer data: massive ties in the bounds, so the
+    candidate count of the guessed threshold overflows and the query is rerun
+    with every point a candidate; results still equal the oracle's."""
+    say("ties/fallback n=20000 N_r=2 K=4 L=2")
+    c = U.case(n=20_000, d=12, L=2, K=4, N_r=2, frac=0.05, kind="smallint", nq=6, seed=5)
+    _fed_oracle_case(dl, c, 10, 0.1)
+
+
+def test_beta_one_is_brute_force(dl):
+    say("beta=1 brute force n=2500")
+    c = U.case(n=2500, d=72, N_r=16, frac=0.1, kind="integer", nq=10, seed=9)
+    idx = dl.build_index(c["X"], 4, 16, 16, 0.1, A=c["A"], sample_ids=c["sample"])
+    ids, dists = idx.query(t(c["Q"]), 25, 1.5, 1.0)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    for qi in range(len(c["Q"])):
+        ref_ids, ref_d2 = O.brute_force_knn(c["X"], c["Q"][qi], 25)
+        assert np.array_equal(ids[qi], ref_ids)
+        np.testing.assert_allclose(dists[qi], np.sqrt(ref_d2), rtol=U.REL)
+
+
+def test_k_equals_n_and_tiny_n(dl):
+    say("tiny n=64 k=64")
+    c = U.case(n=64, d=9, L=1, K=4, N_r=4, frac=1.0, nq=3, seed=2)
+    idx = dl.build_index(c["X"], 1, 4, 4, 1.0, A=c["A"], sample_ids=c["sample"])
+    ids, dists = idx.query(t(c["Q"]), 64, 1.5, 0.5)
+    ids = ids.cpu().numpy()
+    for qi in range(3):
+        ref_ids, _ = O.brute_force_knn(c["X"], c["Q"][qi], 64)
+        assert np.array_equal(ids[qi], ref_ids)
+
+
+# --------------------------------------------------------------------------
+# whole path on the GPU's own encoding (a1..a6)
+# --------------------------------------------------------------------------
+
+def test_end_to_end_against_oracle_on_gpu_encoding(dl):
+    say("end-to-end C1 shape n=10000 d=128")
+    import synth
+    cfg = synth.config("C1")
+    X = synth.make_data(cfg)
+    Q = synth.make_queries(cfg)[:30]
+    A = synth.projection_matrix(4, 16, 128, cfg.index_seed)
+    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
+    idx = dl.build_index(X, 4, 16, 256, cfg.sample_frac, A=A, sample_ids=sample)
+    ex = idx.export()
+    Qp = idx.project(t(Q)).cpu().numpy()
+    r = idx.query_debug(t(Q), 10, 1.5, 0.1, Qp=t(Qp))
+    ids = r["ids"].cpu().numpy()
+    d = r["dists"].cpu().numpy()
+    for qi in range(len(Q)):
+        ref = U.oracle_query(X, Q[qi], Qp[qi], ex["codes"], ex["B"], 4, 16, 10, 0.1)
+        S_gpu = set(r["cand"][qi, :int(r["counts"][qi])].cpu().numpy().tolist())
+        sym = S_gpu ^ set(ref.S.tolist())
+        assert sym <= U.borderline_points(Qp[qi], ex["codes"], ex["B"], 4, 16, ref.thr)
+        if not sym:
+            U.compare_result(ref.ids, ref.dists, X, Q[qi], ids[qi], d[qi], ref.S, 10)
+
+
+def test_determinism_and_batch_independence(dl):
+    """Bitwise-identical results on reruns and whether a query runs alone or
+    inside a larger batch (P12)."""
+    say("determinism n=20000")
+    c = U.case(n=20_000, d=64, N_r=256, frac=0.05, nq=40, seed=21)
+    idx = dl.build_index(c["X"], 4, 16, 256, 0.05, A=c["A"], sample_ids=c["sample"])
+    Q = t(c["Q"])
+    a_ids, a_d = idx.query(Q, 10, 1.5, 0.1)
+    b_ids, b_d = idx.query(Q, 10, 1.5, 0.1)
+    assert np.array_equal(a_ids.cpu().numpy(), b_ids.cpu().numpy())
+    assert np.array_equal(a_d.cpu().numpy(), b_d.cpu().numpy())
+    for qi in (0, 17, 39):
+        s_ids, s_d = idx.query(Q[qi:qi + 1], 10, 1.5, 0.1)
+        assert np.array_equal(s_ids.cpu().numpy()[0], a_ids.cpu().numpy()[qi])
+        assert np.array_equal(s_d.cpu().numpy()[0], a_d.cpu().numpy()[qi])
+
+
+def test_argument_errors(dl):
+    say("argument errors")
+    c = U.case(n=500, d=16, N_r=16, frac=0.2, nq=2, seed=1)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        dl.build_index(c["X"], 3, 16, 16, 0.2)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        dl.build_index(c["X"], 4, 16, 24, 0.2)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        dl.build_index(c["X"], 4, 16, 256, 0.2)          # n_s < N_r
+    idx = dl.build_index(c["X"], 4, 16, 16, 0.2, A=c["A"], sample_ids=c["sample"])
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        idx.query(t(c["Q"]), 0, 1.5, 0.1)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        idx.query(t(c["Q"]), 10, 1.0, 0.1)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        idx.query(t(c["Q"]), 10, 1.5, 1.5)
