@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the DET-LSH hot path on one MI355X.
+
+One step = the whole hot path over one batch: build the index over the
+SIFT-shaped set (n = 1,000,000, d = 128, integers in [0, 255]; L = 4, K = 16,
+N_r = 256, 1% breakpoint sample) and answer 10,000 queries from the same
+generator (k = 10, c = 1.5, beta = 0.1) with plain FP32 verification.  Inputs
+are resident in HBM before the timed region.  `value` is the whole-step
+throughput in queries/s (build included); the query-only rate and the build
+rate are reported beside it.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build uses one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-ops/s without packed FP32: 39.32 T
+FP32_MFMA_PEAK = 157.3           # TFLOP/s dense
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ground_truth_kth(X, Q, k, chunk=1000):
+    """Exact k-th nearest distance per query (recall reading: a returned point
+    counts when its distance is <= this).  FP32 products of integers < 2^24 are
+    exact; candidates are re-measured in float64."""
+    import torch
+    xn = (X.double() ** 2).sum(1).float()
+    out = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+    for s in range(0, Q.shape[0], chunk):
+        q = Q[s:s + chunk]
+        d2 = xn[None, :] - 2.0 * (q @ X.T) + (q.double() ** 2).sum(1).float()[:, None]
+        cand = torch.topk(d2, k + 32, dim=1, largest=False).indices
+        exact = ((X[cand].double() - q[:, None, :].double()) ** 2).sum(-1)
+        out[s:s + chunk] = torch.sort(exact, dim=1).values[:, k - 1].sqrt()
+    return out
+
+
+def recall_at_k(X, Q, ids, k, kth):
+    import torch
+    d = ((X[ids].double() - Q[:, None, :].double()) ** 2).sum(-1).sqrt()
+    hit = (d <= kth[:, None] * (1 + 1e-12)).sum(1).clamp(max=k)
+    return float(hit.double().mean() / k)
+
+
+def cpu_baseline(X_host, Q_host, A, sample, cfg, k, beta, nq_total, n_queries):
+    """The FP64 oracle on the host cores (one BLAS thread): full-n build, then
+    `n_queries` queries; scaled to whole-job queries/s."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import detlsh_oracle as O
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        idx = O.build_index(X_host, A, sample, cfg.L, cfg.K, cfg.N_r)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for qi in range(n_queries):
+            qp = O.project(Q_host[qi:qi + 1], A)[0]
+            O.query_magic(X_host, Q_host[qi], qp, idx.codes, idx.B, cfg.L, cfg.K, k, beta)
+        t_q = (time.perf_counter() - t0) / n_queries
+    total = t_build + nq_total * t_q
+    return {"value": nq_total / total, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, 1 thread: full build over n={X_host.shape[0]} "
+                       f"({t_build:.2f} s) + {n_queries} of the {nq_total} queries "
+                       f"({t_q * 1e3:.1f} ms each), scaled to the whole step"),
+            "build_s": t_build, "query_ms": t_q * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--beta", type=float, default=None)
+    ap.add_argument("--cpu-queries", type=int, default=6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the index and query batch fit one MI355X; see DESIGN.md for sharding).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2406_10938_amd as dl
+    import synth
+    torch.backends.cuda.matmul.allow_tf32 = False
+
+    cfg = synth.config("C2")
+    nq = args.nq or cfg.nq
+    k = args.k
+    beta = cfg.beta if args.beta is None else args.beta
+    log(f"[bench] generating C2: n={cfg.n} d={cfg.d} nq={nq}")
+    X_host = synth.make_data(cfg)
+    Q_host = synth.make_queries(cfg, nq=nq)
+    A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
+    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = torch.from_numpy(X_host).to(dev)
+    Q = torch.from_numpy(Q_host).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
+        ids, dists = idx.query(Q, k, cfg.c, beta)
+        return idx, ids, dists
+
+    log(f"[bench] warmup x{args.warmup}")
+    idx = ids = dists = None
+    for _ in range(args.warmup):
+        if idx is not None:
+            idx.free()
+        idx, ids, dists = step()
+    torch.cuda.synchronize()
+    recall = None
+    if not args.no_recall:
+        log("[bench] ground truth for recall@k")
+        if ids is None:
+            idx, ids, dists = step()
+        kth = ground_truth_kth(X, Q, k)
+        recall = recall_at_k(X, Q, ids, k, kth)
+        log(f"[bench] recall@{k} = {recall:.4f}")
+    if idx is not None:
+        idx.free()
+
+    dl.profile_enable(True, reset=True)
+    log(f"[bench] timed x{args.steps}")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    build_s = 0.0
+    for _ in range(args.steps):
+        tb = time.perf_counter()
+        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
+        build_s += time.perf_counter() - tb
+        ids, dists = idx.query(Q, k, cfg.c, beta)
+        idx.free()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    dl.profile_enable(False, reset=False)
+    prof = dl.profile_read()
+    ms_per_step = ms_total / args.steps
+    value = nq * args.steps / (ms_total / 1e3)
+    build_ms = build_s * 1e3 / args.steps
+    query_ms = ms_per_step - build_ms
+
+    # roofline of the dominant kernel (largest total time in the timed region)
+    n, LK, L, K, d = cfg.n, cfg.L * cfg.K, cfg.L, cfg.K, cfg.d
+    N_S = k + math.ceil(beta * n)
+    kernels = {}
+    for name, v in prof.items():
+        if v["launches"]:
+            kernels[name] = {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "total_ms": v["ms"]}
+    dom = max(kernels, key=lambda s: kernels[s]["total_ms"])
+    avg_s = kernels[dom]["avg_ms"] / 1e3
+    launches_per_step = kernels[dom]["launches"] / args.steps
+    if dom == "range_filter":
+        # VALU lane-ops per (query, point): 3 per (tree, dim) + 1 per tree
+        ops = (3 * LK + L) * n * (nq / launches_per_step)
+        roof = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
+    elif dom == "verify_topk":
+        byts = N_S * d * 4 * (nq / launches_per_step)
+        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif dom == "project_encode":
+        fl = 2.0 * n * LK * d
+        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = (roof["achieved"] / roof["peak"]) if roof["achieved"] else None
+    roof["traffic"] = None
+    roof["kernel"] = dom
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] oracle on host cores ({args.cpu_queries} queries)")
+        cpu = cpu_baseline(X_host, Q_host, A, sample, cfg, k, beta, nq, args.cpu_queries)
+
+    out = {
+        "metric": "QPS @ recall@10>=0.9 (plain FP32 vs BF16+rerank); build Mpts/s; p50/p99 latency",
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "SIFT-shaped n=1,000,000 d=128, 10,000 queries, k=10 c=1.5 beta=0.1, "
+                               "L=4 K=16 N_r=256, 1% sample; step = build + query batch",
+                   "n": n, "d": d, "nq": nq, "k": k, "beta": beta, "L": L, "K": K, "N_r": cfg.N_r,
+                   "precision": "fp32"},
+        "recall_at_k": recall,
+        "query_qps": nq / (query_ms / 1e3) if query_ms > 0 else None,
+        "build_mpts_s": n / (build_ms / 1e3) / 1e6,
+        "build_ms": build_ms,
+        "query_ms": query_ms,
+        "wall_s": wall,
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

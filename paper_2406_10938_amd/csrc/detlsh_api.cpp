@@ -537,7 +537,7 @@ struct Debug {
     int32_t* rounds = nullptr;
 };
 
-size_t per_query_bytes(int64_t cap, int L) { return (size_t)cap * (4 + 4 + 4 * (size_t)L + 8) + 64; }
+size_t per_query_bytes(int64_t cap, int L) { return (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256; }
 
 // Runs queries [q0, q0+nq) through the pipeline with the given plan.  When
 // `force_all_candidates`, every point is a candidate (threshold +inf).
@@ -568,6 +568,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.stop = reinterpret_cast<int32_t*>(take((size_t)nqc * 4));
     a.cand_id = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
+    a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * ix->L));
     a.ws = reinterpret_cast<uint64_t*>(take((size_t)nqc * cap * 8));
     a.out_ids = out_ids; a.out_d = out_d;
@@ -617,7 +618,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
                     HCHECK(hipMemcpy2D(dbg.cand_ids + gq * dbg.cand_cap, dbg.cand_cap * 4, a.cand_id, cap * 4,
                                        w * 4, cnt, hipMemcpyDeviceToDevice));
                 if (dbg.first_tree && w > 0)
-                    HCHECK(hipMemcpy2D(dbg.first_tree + gq * dbg.cand_cap, dbg.cand_cap * 4, a.cand_m, cap * 4,
+                    HCHECK(hipMemcpy2D(dbg.first_tree + gq * dbg.cand_cap, dbg.cand_cap * 4, a.cand_ft, cap * 4,
                                        w * 4, cnt, hipMemcpyDeviceToDevice));
                 if (dbg.thr) HCHECK(hipMemcpy(dbg.thr + gq, a.thr, (size_t)cnt * 4, hipMemcpyDeviceToDevice));
                 if (dbg.stop_tree) HCHECK(hipMemcpy(dbg.stop_tree + gq, a.stop, (size_t)cnt * 4, hipMemcpyDeviceToDevice));

@@ -69,7 +69,8 @@ struct QueryArgs {
     float* gthr = nullptr;
     uint32_t* counts = nullptr;
     int32_t* cand_id = nullptr;
-    float* cand_m = nullptr;
+    float* cand_m = nullptr;         // m^2 = min over trees of the bounds
+    int32_t* cand_ft = nullptr;      // first admitting tree of each member of S
     float* cand_lb = nullptr;
     int32_t* status = nullptr;
     uint32_t* s_count = nullptr;

@@ -139,7 +139,8 @@ struct SelectShared {
     uint64_t before, total;
 };
 
-__device__ float select_rank_f32(const float* vals, int64_t m, uint64_t r, SelectShared& sh) {
+template <typename Get>
+__device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& sh) {
     uint32_t prefix = 0;
     int known = 0;
     const int nb_tab[3] = {12, 12, 8};
@@ -149,7 +150,7 @@ __device__ float select_rank_f32(const float* vals, int64_t m, uint64_t r, Selec
         for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
         __syncthreads();
         for (int64_t i = threadIdx.x; i < m; i += 256) {
-            const uint32_t u = __float_as_uint(vals[i]);
+            const uint32_t u = __float_as_uint(get(i));
             if (known == 0 || (u >> (32 - known)) == prefix)
                 atomicAdd(&sh.hist[(u >> shift) & ((1u << nbits) - 1u)], 1u);
         }
@@ -274,9 +275,38 @@ __global__ __launch_bounds__(256) void guess_kernel(const float* __restrict__ E,
         sm[t] = cell_lbs<L, K>(qp, lo, hi, lb);
     }
     __syncthreads();
-    const float g = select_rank_f32(sm, G, rank, sh);
+    const float g = select_rank_f32([&](int64_t i) { return sm[i]; }, G, rank, sh);
     if (threadIdx.x == 0) gthr[blockIdx.x] = g;
 }
+
+// Candidates are written as id and the L per-tree bounds (AoS, L floats per
+// slot).  Inside a group of kGroup queries each wave appends its hits to its
+// own LDS list (offsets from ballot and popcount, no atomics); at the end of
+// the group one atomic per query reserves the block's slots and the lists are
+// copied out contiguously.
+constexpr int kGroup = 8;
+
+template <int L>
+__device__ __forceinline__ void store_lbs(float* __restrict__ dst, const float (&lb)[L]) {
+    if constexpr (L % 4 == 0) {
+#pragma unroll
+        for (int c = 0; c < L / 4; ++c)
+            reinterpret_cast<float4*>(dst)[c] = make_float4(lb[4 * c], lb[4 * c + 1], lb[4 * c + 2], lb[4 * c + 3]);
+    } else if constexpr (L == 2) {
+        reinterpret_cast<float2*>(dst)[0] = make_float2(lb[0], lb[1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < L; ++i) dst[i] = lb[i];
+    }
+}
+
+template <int L>
+struct FilterShared {
+    int32_t ids[4][kGroup][64];
+    float lbs[4][kGroup][64][L];
+    uint32_t wc[4][kGroup];
+    uint32_t gb[kGroup];
+};
 
 template <int L, int K>
 __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E, int N_r,
@@ -288,36 +318,63 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
                                                      float* __restrict__ cand_lb)
 {
     constexpr int LK = L * K;
+    __shared__ FilterShared<L> sh;
     const int ldE = N_r + 1;
     const int64_t o_raw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = o_raw < n;
     const int64_t o = valid ? o_raw : n - 1;
     const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     float lo[LK], hi[LK];
     load_cell<L, K>(codes, n, o, E, ldE, lo, hi);
+    __builtin_amdgcn_s_waitcnt(0);   // settle the cell bounds once, outside the query loop
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
-    for (int t = ta; t < tb; ++t) {
-        const float* qp = Qp + (q0 + t) * LK;
-        float lb[L];
-        const float m = cell_lbs<L, K>(qp, lo, hi, lb);
-        const bool hit = valid && (m <= gthr[t]);
-        const uint64_t mask = dl_ballot(hit);
-        if (mask == 0) continue;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&counts[t], (uint32_t)__popcll(mask));
-        base = dl_shfl_u32(base, leader);
-        if (hit) {
-            const int64_t idx = (int64_t)base + dl_rank_below(mask);
-            if (idx < cap) {
-                const int64_t at = (int64_t)t * cap + idx;
-                cand_id[at] = (int32_t)o;
-                cand_m[at] = m;
+    for (int tg = ta; tg < tb; tg += kGroup) {
+        const int ng = (tb - tg < kGroup) ? tb - tg : kGroup;
+#pragma unroll 1
+        for (int g = 0; g < ng; ++g) {
+            const int t = tg + g;
+            const float* qp = Qp + (q0 + t) * LK;
+            float lb[L];
+            const float m = cell_lbs<L, K>(qp, lo, hi, lb);
+            const bool hit = valid && (m <= gthr[t]);
+            const uint64_t mask = dl_ballot(hit);
+            if (hit) {
+                const int pos = dl_rank_below(mask);
+                sh.ids[wave][g][pos] = (int32_t)o;
 #pragma unroll
-                for (int i = 0; i < L; ++i) cand_lb[((int64_t)t * L + i) * cap + idx] = lb[i];
+                for (int i = 0; i < L; ++i) sh.lbs[wave][g][pos][i] = lb[i];
+            }
+            if (lane == 0) sh.wc[wave][g] = (uint32_t)__popcll(mask);
+        }
+        __syncthreads();
+        if (threadIdx.x < ng) {
+            const int g = threadIdx.x;
+            const uint32_t tot = sh.wc[0][g] + sh.wc[1][g] + sh.wc[2][g] + sh.wc[3][g];
+            sh.gb[g] = tot ? atomicAdd(&counts[tg + g], tot) : 0u;
+        }
+        __syncthreads();
+        for (int g = 0; g < ng; ++g) {
+            const uint32_t c = sh.wc[wave][g];
+            if (c == 0) continue;
+            uint32_t off = sh.gb[g];
+            for (int w = 0; w < wave; ++w) off += sh.wc[w][g];
+            for (uint32_t j = lane; j < c; j += 64) {
+                const int64_t idx = (int64_t)off + j;
+                if (idx < cap) {
+                    const int64_t at = (int64_t)(tg + g) * cap + idx;
+                    cand_id[at] = sh.ids[wave][g][j];
+                    float lb[L];
+                    float m = INFINITY;
+#pragma unroll
+                    for (int i = 0; i < L; ++i) { lb[i] = sh.lbs[wave][g][j][i]; m = fminf(m, lb[i]); }
+                    cand_m[at] = m;
+                    store_lbs<L>(cand_lb + at * L, lb);
+                }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -340,9 +397,27 @@ __device__ __forceinline__ uint32_t block_flag_prefix(bool f, uint32_t* wtot, ui
 }
 
 template <int L>
+__device__ __forceinline__ void load_lbs(const float* __restrict__ src, float (&lb)[L]) {
+    if constexpr (L % 4 == 0) {
+#pragma unroll
+        for (int c = 0; c < L / 4; ++c) {
+            const float4 v = reinterpret_cast<const float4*>(src)[c];
+            lb[4 * c] = v.x; lb[4 * c + 1] = v.y; lb[4 * c + 2] = v.z; lb[4 * c + 3] = v.w;
+        }
+    } else if constexpr (L == 2) {
+        const float2 v = reinterpret_cast<const float2*>(src)[0];
+        lb[0] = v.x; lb[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < L; ++i) lb[i] = src[i];
+    }
+}
+
+template <int L>
 __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict__ counts, int64_t cap,
                                                      uint64_t N_S, int32_t* __restrict__ cand_id,
-                                                     float* __restrict__ cand_m, const float* __restrict__ cand_lb,
+                                                     const float* __restrict__ cand_m,
+                                                     int32_t* __restrict__ cand_ft, const float* __restrict__ cand_lb,
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
                                                      float* __restrict__ thr_out, int32_t* __restrict__ stop_out)
 {
@@ -355,8 +430,9 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
         if (threadIdx.x == 0) { status[t] = 1; s_count[t] = 0; }
         return;
     }
-    const float* mv = cand_m + (int64_t)t * cap;
-    const float thr = select_rank_f32(mv, (int64_t)cnt, N_S, sh);
+    const float* lbt = cand_lb + (int64_t)t * cap * L;
+    const float* mt = cand_m + (int64_t)t * cap;
+    const float thr = select_rank_f32([&](int64_t s) { return mt[s]; }, (int64_t)cnt, N_S, sh);
     // |U_i| for i = 1..L: entries whose prefix minimum over trees 1..i is <= thr
     if (threadIdx.x < 8) tc[threadIdx.x] = 0;
     __syncthreads();
@@ -364,10 +440,12 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
 #pragma unroll
     for (int i = 0; i < L; ++i) loc[i] = 0;
     for (int64_t s = threadIdx.x; s < (int64_t)cnt; s += 256) {
+        float lb[L];
+        load_lbs<L>(lbt + s * L, lb);
         float pm = INFINITY;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            pm = fminf(pm, cand_lb[((int64_t)t * L + i) * cap + s]);
+            pm = fminf(pm, lb[i]);
             loc[i] += (pm <= thr) ? 1u : 0u;
         }
     }
@@ -380,9 +458,9 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     int istop = L;
     for (int i = 0; i < L; ++i)
         if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
-    // in-place stable compaction of S = U_{istop}; first admitting tree kept in cand_m
+    // in-place stable compaction of S = U_{istop}, with each member's first admitting tree
     int32_t* ids = cand_id + (int64_t)t * cap;
-    int32_t* ftree = reinterpret_cast<int32_t*>(cand_m + (int64_t)t * cap);
+    int32_t* ftree = cand_ft + (int64_t)t * cap;
     uint32_t out = 0;
     for (int64_t c0 = 0; c0 < (int64_t)cnt; c0 += 256) {
         const int64_t s = c0 + threadIdx.x;
@@ -390,9 +468,11 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
         int32_t id = 0, ft = 0;
         if (s < (int64_t)cnt) {
             id = ids[s];
-            for (int i = 0; i < L; ++i) {
-                if (ft == 0 && cand_lb[((int64_t)t * L + i) * cap + s] <= thr) ft = i + 1;
-            }
+            float lb[L];
+            load_lbs<L>(lbt + s * L, lb);
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i)
+                if (lb[i] <= thr) ft = i + 1;
             mem = (ft != 0 && ft <= istop);
         }
         uint32_t tot;
@@ -434,25 +514,49 @@ __global__ __launch_bounds__(256) void verify_kernel(const float* __restrict__ X
     uint64_t* buf = ws + (int64_t)t * cap;
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
-    for (int64_t s = hw; s < m; s += 8) {
-        const int64_t id = all_n ? s : (int64_t)ids[s];
-        const float* x = X + id * d;
-        float acc = 0.0f;
+    constexpr int R = 4;                       // rows in flight per half-wave
+    for (int64_t s0 = (int64_t)hw * R; s0 < m; s0 += 8 * R) {
+        int64_t id[R];
+        float acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t s = s0 + r;
+            id[r] = (s < m) ? (all_n ? s : (int64_t)ids[s]) : -1;
+            acc[r] = 0.0f;
+        }
         for (int c = 4 * hl; c < d; c += 128) {
             if (ALIGNED && c + 4 <= d) {
-                const float4 v = *reinterpret_cast<const float4*>(x + c);
-                float df = v.x - sq[c];     acc = fmaf(df, df, acc);
-                df = v.y - sq[c + 1];       acc = fmaf(df, df, acc);
-                df = v.z - sq[c + 2];       acc = fmaf(df, df, acc);
-                df = v.w - sq[c + 3];       acc = fmaf(df, df, acc);
+                float4 v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    v[r] = (id[r] >= 0) ? *reinterpret_cast<const float4*>(X + id[r] * d + c)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float q0v = sq[c], q1v = sq[c + 1], q2v = sq[c + 2], q3v = sq[c + 3];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float df = v[r].x - q0v; acc[r] = fmaf(df, df, acc[r]);
+                    df = v[r].y - q1v;       acc[r] = fmaf(df, df, acc[r]);
+                    df = v[r].z - q2v;       acc[r] = fmaf(df, df, acc[r]);
+                    df = v[r].w - q3v;       acc[r] = fmaf(df, df, acc[r]);
+                }
             } else {
-                for (int u = 0; u < 4; ++u)
-                    if (c + u < d) { const float df = x[c + u] - sq[c + u]; acc = fmaf(df, df, acc); }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (id[r] < 0) continue;
+                    const float* x = X + id[r] * d;
+                    for (int u = 0; u < 4; ++u)
+                        if (c + u < d) { const float df = x[c + u] - sq[c + u]; acc[r] = fmaf(df, df, acc[r]); }
+                }
             }
         }
 #pragma unroll
-        for (int o2 = 16; o2 > 0; o2 >>= 1) acc += __shfl_xor(acc, o2, 32);
-        if (hl == 0) buf[s] = ((uint64_t)__float_as_uint(acc) << 32) | (uint64_t)(uint32_t)id;
+        for (int r = 0; r < R; ++r) {
+            float a2 = acc[r];
+#pragma unroll
+            for (int o2 = 16; o2 > 0; o2 >>= 1) a2 += __shfl_xor(a2, o2, 32);
+            if (hl == 0 && id[r] >= 0)
+                buf[s0 + r] = ((uint64_t)__float_as_uint(a2) << 32) | (uint64_t)(uint32_t)id[r];
+        }
     }
     __threadfence_block();
     __syncthreads();
@@ -511,7 +615,7 @@ hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
 template <int L>
 hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((select_kernel<L>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
-                       a.cand_m, a.cand_lb, a.status, a.s_count, a.thr, a.stop);
+                       a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop);
     return hipGetLastError();
 }
 
