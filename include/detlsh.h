@@ -171,6 +171,9 @@ typedef struct {
     int32_t max_rounds;         /* FIXED: radius rounds before S = D; 0 -> 64        */
     double r_min;               /* FIXED: initial radius, > 0                        */
     size_t workspace_bytes;     /* per-call workspace budget; 0 -> 4 GiB             */
+    int32_t verify;             /* candidate verification: 0 automatic, 1 gathered
+                                   rows of S, 2 masked dense MFMA over all rows     */
+    int32_t reserved;
 } detlsh_query_opts;
 
 /*
@@ -192,8 +195,17 @@ typedef struct {
  * the k members of S nearest to each query, ascending by (distance, id);
  * N_S is computed in IEEE double from the double `beta` as k + ceil(beta*n);
  * distances are Euclidean (not squared).  Limits: 1 <= k <= min(n, 1024)
- * (BF16 form: rerank_mult*k <= 1024), c > 1, 0 <= beta <= 1, nq >= 0 (0 is a
- * no-op), FIXED needs r_min > 0.
+ * (BF16 form: rerank_mult*k <= 1024, needs an index built with keep_bf16),
+ * c > 1, 0 <= beta <= 1, nq >= 0 (0 is a no-op), FIXED needs r_min > 0.
+ *
+ * Verification (both forms give the top-k of S by FP32 distance computed by
+ * direct differences, ties by id): the gathered form reads the rows of S; the
+ * masked dense form computes q.o for every row with MFMA, keeps members of S
+ * whose ||q||^2 + ||o||^2 - 2 q.o lies within an upper bound of the k-th
+ * distance plus the FP32 rounding bound of that expression, and re-ranks those
+ * few exactly.  DETLSH_BF16_RERANK runs the dense products in BF16 (FP32
+ * accumulation), keeps members within the (rerank_mult*k)-th exact distance of
+ * a subset of S, and re-ranks them exactly in FP32.
  */
 detlsh_status detlsh_query(detlsh_index idx, const float* Q, int64_t nq, int32_t k,
                            double c, double beta, const detlsh_query_opts* opts,

@@ -63,8 +63,9 @@ def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep):
     return o
 
 
-def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes):
+def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify=0):
     o = _lib.QueryOpts()
+    o.verify = {"auto": 0, "gather": 1, "dense": 2}.get(verify, verify)
     o.precision = int(precision)
     o.rerank_mult = int(rerank_mult)
     o.rmin_policy = int(rmin_policy)
@@ -105,19 +106,19 @@ class Index:
         return out
 
     def query(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC,
-              r_min=0.0, max_rounds=0, workspace_bytes=0):
+              r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto"):
         torch = _torch()
         Q = _dev_f32(Q, "Q")
         nq = Q.shape[0]
         ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
         dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify)
         check(lib().detlsh_query(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
                                  _ptr(dists), _stream_ptr()))
         return ids, dists
 
     def query_debug(self, Q, k, c=1.5, beta=0.1, Qp=None, cand_cap=None, precision=FP32, rerank_mult=4,
-                    rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0):
+                    rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto"):
         """Query that also returns S, first trees, thr, stop tree and rounds."""
         torch = _torch()
         Q = _dev_f32(Q, "Q")
@@ -137,7 +138,7 @@ class Index:
         if Qp is not None:
             Qp = _dev_f32(Qp, "Qp")
             qp_ptr = _ptr(Qp)
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify)
         check(lib().detlsh_query_debug(self._h, qp_ptr, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o),
                                        _ptr(cand), cap, _ptr(counts), _ptr(first), _ptr(thr), _ptr(stop),
                                        _ptr(rounds), _ptr(ids), _ptr(dists), _stream_ptr()))

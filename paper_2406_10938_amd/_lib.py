@@ -37,6 +37,8 @@ class QueryOpts(C.Structure):
         ("max_rounds", C.c_int32),
         ("r_min", C.c_double),
         ("workspace_bytes", C.c_size_t),
+        ("verify", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -53,6 +53,39 @@ __device__ __forceinline__ T dl_wave_sum(T v) {
     return v;
 }
 
+__device__ __forceinline__ float dl_bf16_to_f32(uint16_t h);
+__device__ __forceinline__ uint16_t dl_f32_to_bf16(float f);
+
+// Four consecutive elements p[k..k+3] (zero beyond d); vector load when the
+// rows are 16-byte aligned.
+template <bool ALIGNED>
+__device__ __forceinline__ floatx4 load4(const float* __restrict__ p, int k, int d) {
+    floatx4 r;
+    if (ALIGNED && k + 4 <= d) {
+        float4 v = *reinterpret_cast<const float4*>(p + k);
+        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? p[k + t] : 0.0f;
+    }
+    return r;
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ shortx4 load4bf(const uint16_t* __restrict__ p, int k, int d) {
+    shortx4 r;
+    if (ALIGNED && k + 4 <= d) {
+        uint2 v = *reinterpret_cast<const uint2*>(p + k);
+        r[0] = (short)(v.x & 0xffff); r[1] = (short)(v.x >> 16);
+        r[2] = (short)(v.y & 0xffff); r[3] = (short)(v.y >> 16);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? (short)p[k + t] : (short)0;
+    }
+    return r;
+}
+
+
 __device__ __forceinline__ float dl_bf16_to_f32(uint16_t h) {
     return __uint_as_float(((uint32_t)h) << 16);
 }

@@ -80,7 +80,8 @@ struct DevBuf {
 
 const char* kTimerNames[T_COUNT] = {"project_sample", "breakpoints", "project_encode", "tree_build",
                                     "project_queries", "guess",      "range_filter",   "select",
-                                    "verify_topk",     "to_bf16"};
+                                    "verify_topk",     "to_bf16",     "tau",            "dense_verify",
+                                    "rerank_topk"};
 
 struct Profiler {
     std::mutex mu;
@@ -166,7 +167,7 @@ struct detlsh_index_s {
     int64_t n_s = 0;
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
-    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes;
+    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf;
     std::vector<int64_t> sample_ids;
     std::vector<float> A_host;
     int64_t n_leaves[8] = {};
@@ -182,7 +183,7 @@ struct detlsh_index_s {
     }
     size_t bytes() const {
         size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
-                   scodes.bytes;
+                   scodes.bytes + xn.bytes + xn_bf.bytes;
         for (int i = 0; i < L; ++i) b += (size_t)(n_leaves[i] + 1) * 4 + 2 * (size_t)n_leaves[i] * K;
         return b;
     }
@@ -201,8 +202,12 @@ detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_
     return DETLSH_OK;
 }
 
-// Shared tail of build and import: BF16 copies, trees.
-detlsh_status finish_index(detlsh_index_s* ix, hipStream_t st) {
+// Shared tail of build and import: row norms, trees.
+detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
+    HCHECK(ix->xn.alloc((size_t)ix->n * 4));
+    if (keep_bf16) HCHECK(ix->xn_bf.alloc((size_t)ix->n * 4));
+    HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(),
+                               keep_bf16 ? ix->xn_bf.as<float>() : nullptr, st));
     for (int i = 0; i < ix->L; ++i) {
         DevBuf tmp;
         HCHECK(tmp.alloc(dl_tree_tmp_bytes(ix->n, ix->K)));
@@ -334,9 +339,9 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
         DlTimer tm(T_ENCODE, st);
         HCHECK(dl_launch_project(pa, PROJ_ENCODE, st));
     }
-    s = finish_index(ix, st);
+    s = finish_index(ix, opts && opts->keep_bf16, st);
     if (s) return s;
-    if (!(opts && opts->keep_bf16) && !ix->proj_bf16) ix->Xbf.release();
+    if (!(opts && opts->keep_bf16)) ix->Xbf.release();
     HCHECK(hipStreamSynchronize(st));
     prof_resolve();
     *out = guard.release();
@@ -383,7 +388,7 @@ detlsh_status detlsh_index_import(const float* X, int64_t n, int32_t d, int32_t 
             }
     HCHECK(hipMemcpyAsync(ix->codes.p, t.data(), t.size(), hipMemcpyHostToDevice, st));
     HCHECK(hipStreamSynchronize(st));
-    s = finish_index(ix, st);
+    s = finish_index(ix, opts && opts->keep_bf16, st);
     if (s) return s;
     if (!(opts && opts->keep_bf16)) ix->Xbf.release();
     HCHECK(hipStreamSynchronize(st));
@@ -495,6 +500,11 @@ struct QueryPlan {
     int G = 0;
     uint64_t rank = 0;
     int64_t cap = 0;
+    bool dense = false;     // masked dense MFMA verification
+    bool bf16 = false;      // BF16 products, rerank of rerank_mult*k
+    int kprime = 0;         // rank of the distance bound tau
+    int64_t T = 0;          // members of S used for tau
+    int64_t cap_sv = 0;     // survivor slots per query
 };
 
 QueryPlan plan_query(int64_t n, int k, double beta, int L) {
@@ -537,7 +547,11 @@ struct Debug {
     int32_t* rounds = nullptr;
 };
 
-size_t per_query_bytes(int64_t cap, int L) { return (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256; }
+size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d) {
+    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256;
+    if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
+    return b;
+}
 
 // Runs queries [q0, q0+nq) through the pipeline with the given plan.  When
 // `force_all_candidates`, every point is a candidate (threshold +inf).
@@ -545,7 +559,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
                           const QueryPlan& plan, bool force_all_candidates, size_t budget, int64_t* out_ids,
                           float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
     const int64_t cap = force_all_candidates ? ix->n : plan.cap;
-    const size_t pq = per_query_bytes(cap, ix->L);
+    const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d);
     int64_t nqc = (int64_t)(budget / pq);
     if (nqc < 1) nqc = 1;
     if (nqc > nq) nqc = nq;
@@ -571,6 +585,22 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * ix->L));
     a.ws = reinterpret_cast<uint64_t*>(take((size_t)nqc * cap * 8));
+    if (plan.dense) {
+        a.W = (ix->n + 63) / 64;
+        a.bm = reinterpret_cast<uint64_t*>(take((size_t)nqc * a.W * 8));
+        a.tau = reinterpret_cast<float*>(take((size_t)nqc * 4));
+        a.qn = reinterpret_cast<float*>(take((size_t)nqc * 4));
+        a.svc = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
+        a.cap_sv = plan.cap_sv;
+        a.sv = reinterpret_cast<int32_t*>(take((size_t)nqc * plan.cap_sv * 4));
+        a.dense_bf16 = plan.bf16 ? 1 : 0;
+        if (plan.bf16) a.Qbf = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->d * 2));
+        a.xn = ix->xn.as<float>();
+        a.xn_bf = ix->xn_bf.as<float>();
+        // |approx - exact| <= (2 gamma_d + 4u)(|q|^2 + |o|^2) for the norm expression and the
+        // direct-difference reference, gamma_d = d u / (1 - d u), u = 2^-24
+        a.margin_c = plan.bf16 ? 0.0f : (float)((4.0 * ix->d + 16.0) * std::ldexp(1.0, -24));
+    }
     a.out_ids = out_ids; a.out_d = out_d;
     std::vector<float> inf_host;
     std::vector<uint32_t> sc_host;
@@ -598,9 +628,27 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         } else {
             HCHECK(hipMemsetAsync(a.status, 0, (size_t)cnt * 4, st));
         }
-        {
+        if (plan.dense && !plan.all) {
+            {
+                DlTimer tm(T_TAU, st);
+                HCHECK(dl_launch_tau(a, plan.T, plan.kprime, st));
+            }
+            HCHECK(hipMemsetAsync(a.svc, 0, (size_t)cnt * 4, st));
+            {
+                DlTimer tm(T_DENSE, st);
+                HCHECK(dl_launch_dense(a, st));
+            }
+            {
+                DlTimer tm(T_FINAL, st);
+                HCHECK(dl_launch_final(a, st));
+            }
+            {
+                DlTimer tm(T_VERIFY, st);   // survivor overflow: gathered verification of S
+                HCHECK(dl_launch_verify(a, 2, st));
+            }
+        } else {
             DlTimer tm(T_VERIFY, st);
-            HCHECK(dl_launch_verify(a, st));
+            HCHECK(dl_launch_verify(a, 0, st));
         }
         HCHECK(hipMemcpyAsync(status_host.data() + c0, a.status, (size_t)cnt * 4, hipMemcpyDeviceToHost, st));
         if (dbg.cand_ids || dbg.cand_counts || dbg.first_tree || dbg.thr || dbg.stop_tree || dbg.rounds) {
@@ -645,7 +693,15 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     if (!(beta >= 0.0 && beta <= 1.0)) return fail(DETLSH_EINVAL, "beta must be in [0, 1], got %g", beta);
     const int precision = opts ? opts->precision : DETLSH_FP32;
     const int policy = opts ? opts->rmin_policy : DETLSH_RMIN_MAGIC;
-    if (precision != DETLSH_FP32) return fail(DETLSH_EINVAL, "precision %d is not available", precision);
+    const int verify = opts ? opts->verify : 0;
+    const int rmult = (opts && opts->rerank_mult > 0) ? opts->rerank_mult : 4;
+    if (precision != DETLSH_FP32 && precision != DETLSH_BF16_RERANK)
+        return fail(DETLSH_EINVAL, "precision %d is not defined", precision);
+    if (precision == DETLSH_BF16_RERANK && !ix->Xbf.p)
+        return fail(DETLSH_EINVAL, "the BF16 form needs an index built with keep_bf16");
+    if (precision == DETLSH_BF16_RERANK && (int64_t)rmult * k > 1024)
+        return fail(DETLSH_EINVAL, "rerank_mult*k = %lld exceeds 1024", (long long)rmult * k);
+    if (verify < 0 || verify > 2) return fail(DETLSH_EINVAL, "verify mode %d is not defined", verify);
     if (policy != DETLSH_RMIN_MAGIC) return fail(DETLSH_EINVAL, "r_min policy %d is not available", policy);
     if (nq == 0) return DETLSH_OK;
     if (!is_device_ptr(Q)) return fail(DETLSH_EINVAL, "Q must be a device pointer");
@@ -664,17 +720,23 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
         HCHECK(dl_launch_project(pa, PROJ_ROWMAJOR, st));
         Qp = qpbuf.as<float>();
     }
-    const QueryPlan plan = plan_query(ix->n, k, beta, ix->L);
+    QueryPlan plan = plan_query(ix->n, k, beta, ix->L);
+    const bool bf16 = precision == DETLSH_BF16_RERANK;
+    plan.dense = !plan.all && (verify == 2 || (verify == 0 && (ix->n >= 65536 || bf16)));
+    plan.bf16 = bf16 && plan.dense;
+    plan.kprime = (int)std::min<uint64_t>(plan.N_S, (uint64_t)(bf16 ? rmult * k : k));
+    plan.T = std::max<int64_t>(2048, 32 * (int64_t)plan.kprime);
+    plan.cap_sv = std::max<int64_t>(32768, 64 * (int64_t)plan.kprime);
     std::vector<int32_t> status((size_t)nq, 0);
     detlsh_status s = run_queries(ix, Q, Qp, 0, nq, k, plan, false, budget, out_ids, out_d, dbg, status, st);
     if (s) { prof_resolve(); return s; }
     // queries whose candidate count missed [N_S, cap]: every point a candidate
     for (int64_t q = 0; q < nq; ++q) {
-        if (status[q] == 0) continue;
+        if (status[q] != 1) continue;
         std::vector<int32_t> st1(1, 0);
         s = run_queries(ix, Q, Qp, q, 1, k, plan, true, budget, out_ids, out_d, dbg, st1, st);
         if (s) { prof_resolve(); return s; }
-        if (st1[0] != 0) { prof_resolve(); return fail(DETLSH_EINTERNAL, "query %lld: fallback failed", (long long)q); }
+        if (st1[0] == 1) { prof_resolve(); return fail(DETLSH_EINTERNAL, "query %lld: fallback failed", (long long)q); }
     }
     prof_resolve();
     (void)c;

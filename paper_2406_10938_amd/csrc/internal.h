@@ -28,6 +28,7 @@ struct ProjectArgs {
 
 hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st);
 hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st);
+hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, hipStream_t st);
 
 // ---- sorting and scans (k_sort.hip) ----
 size_t dl_scan_tmp_bytes(int64_t n);
@@ -77,6 +78,19 @@ struct QueryArgs {
     float* thr = nullptr;
     int32_t* stop = nullptr;
     uint64_t* ws = nullptr;
+    // masked dense verification
+    uint64_t* bm = nullptr;          // per query, ceil(n/64) words: bit o = o in S
+    int64_t W = 0;
+    float* tau = nullptr;            // per query upper bound on the k'-th squared distance
+    float* qn = nullptr;             // per query squared norm
+    uint16_t* Qbf = nullptr;         // chunk's queries in BF16 (dense_bf16)
+    const float* xn = nullptr;       // squared norms of the rows
+    const float* xn_bf = nullptr;    // squared norms of the BF16 rows
+    int dense_bf16 = 0;
+    float margin_c = 0.f;
+    uint32_t* svc = nullptr;         // survivors per query
+    int32_t* sv = nullptr;
+    int64_t cap_sv = 0;
     // outputs (all queries)
     int64_t* out_ids = nullptr;
     float* out_d = nullptr;
@@ -88,7 +102,10 @@ size_t dl_verify_smem(int d);
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_filter(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st);
-hipError_t dl_launch_verify(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st);
+hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st);
+hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_final(const QueryArgs& a, hipStream_t st);
 
 // ---- kernel timing (detlsh_api.cpp) ----
 struct DlTimer {
@@ -100,5 +117,5 @@ struct DlTimer {
 };
 enum {
     T_PROJECT_SAMPLE = 0, T_BREAKPOINTS, T_ENCODE, T_TREE, T_QPROJECT, T_GUESS, T_FILTER, T_SELECT,
-    T_VERIFY, T_BF16, T_COUNT
+    T_VERIFY, T_BF16, T_TAU, T_DENSE, T_FINAL, T_COUNT
 };

@@ -12,33 +12,6 @@ constexpr int kRowsPerBlock = 4 * kRowsPerWave;   // 4 waves
 
 enum { EPI_COLMAJOR = 0, EPI_ROWMAJOR = 1, EPI_ENCODE = 2 };
 
-template <bool ALIGNED>
-__device__ __forceinline__ floatx4 load4(const float* __restrict__ p, int k, int d) {
-    floatx4 r;
-    if (ALIGNED && k + 4 <= d) {
-        float4 v = *reinterpret_cast<const float4*>(p + k);
-        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
-    } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? p[k + t] : 0.0f;
-    }
-    return r;
-}
-
-template <bool ALIGNED>
-__device__ __forceinline__ shortx4 load4bf(const uint16_t* __restrict__ p, int k, int d) {
-    shortx4 r;
-    if (ALIGNED && k + 4 <= d) {
-        uint2 v = *reinterpret_cast<const uint2*>(p + k);
-        r[0] = (short)(v.x & 0xffff); r[1] = (short)(v.x >> 16);
-        r[2] = (short)(v.y & 0xffff); r[3] = (short)(v.y >> 16);
-    } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? (short)p[k + t] : (short)0;
-    }
-    return r;
-}
-
 // Rows r of X (or rows[r] when `rows` is given) times A^T; A is N x d, N <= 16*NT.
 // Accumulator layout of v_mfma_f32_16x16x4f32: lane l holds P[4*(l/16)+v][l%16].
 // The reduction index of MFMA step s inside a 16-wide chunk at k0 is
@@ -232,6 +205,36 @@ hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // FP32 -> BF16 copy (round to nearest even)
 // ---------------------------------------------------------------------------
+
+// Squared norms of the rows (FP32 sums in a fixed order) and of their BF16
+// roundings, used by the masked dense verification.
+__global__ void row_norms_kernel(const float* __restrict__ X, int64_t n, int d, float* __restrict__ xn,
+                                 float* __restrict__ xn_bf)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int lane = threadIdx.x & 63;
+    const float* x = X + row * d;
+    float a = 0.f, b = 0.f;
+    for (int c = lane; c < d; c += 64) {
+        const float v = x[c];
+        a = fmaf(v, v, a);
+        const float w = dl_bf16_to_f32(dl_f32_to_bf16(v));
+        b = fmaf(w, w, b);
+    }
+    a = dl_wave_sum(a);
+    b = dl_wave_sum(b);
+    if (lane == 0) {
+        xn[row] = a;
+        if (xn_bf) xn_bf[row] = b;
+    }
+}
+
+hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, d, xn, xn_bf);
+    return hipGetLastError();
+}
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -315,7 +315,8 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
                                                      int q_per_block, const float* __restrict__ gthr,
                                                      uint32_t* __restrict__ counts, int64_t cap,
                                                      int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
-                                                     float* __restrict__ cand_lb)
+                                                     float* __restrict__ cand_lb, uint64_t* __restrict__ bm,
+                                                     int64_t W)
 {
     constexpr int LK = L * K;
     __shared__ FilterShared<L> sh;
@@ -346,7 +347,11 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
 #pragma unroll
                 for (int i = 0; i < L; ++i) sh.lbs[wave][g][pos][i] = lb[i];
             }
-            if (lane == 0) sh.wc[wave][g] = (uint32_t)__popcll(mask);
+            if (lane == 0) {
+                sh.wc[wave][g] = (uint32_t)__popcll(mask);
+                const int64_t word = (int64_t)blockIdx.x * 4 + wave;   // 64 consecutive points
+                if (bm && word < W) bm[(int64_t)t * W + word] = mask;
+            }
         }
         __syncthreads();
         if (threadIdx.x < ng) {
@@ -419,7 +424,8 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                                                      const float* __restrict__ cand_m,
                                                      int32_t* __restrict__ cand_ft, const float* __restrict__ cand_lb,
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
-                                                     float* __restrict__ thr_out, int32_t* __restrict__ stop_out)
+                                                     float* __restrict__ thr_out, int32_t* __restrict__ stop_out,
+                                                     uint64_t* __restrict__ bm, int64_t W)
 {
     __shared__ SelectShared sh;
     __shared__ uint32_t tc[8];
@@ -474,6 +480,7 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
             for (int i = L - 1; i >= 0; --i)
                 if (lb[i] <= thr) ft = i + 1;
             mem = (ft != 0 && ft <= istop);
+            if (!mem && bm) atomicAnd((unsigned long long*)&bm[(int64_t)t * W + (id >> 6)], ~(1ull << (id & 63)));
         }
         uint32_t tot;
         const uint32_t pre = block_flag_prefix(mem, wtot, &tot);
@@ -492,36 +499,22 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     }
 }
 
+// Exact FP32 squared distances (direct differences, half a wave per row, R
+// rows in flight) of the rows listed for one query, written as 64-bit keys
+// (distance bits, id) to buf.
 template <bool ALIGNED>
-__global__ __launch_bounds__(256) void verify_kernel(const float* __restrict__ X, int d,
-                                                     const float* __restrict__ Q, int64_t q0,
-                                                     const int32_t* __restrict__ cand_id, int64_t cap,
-                                                     const uint32_t* __restrict__ s_count,
-                                                     const int32_t* __restrict__ status, int64_t all_n,
-                                                     uint64_t* __restrict__ ws, int k,
-                                                     int64_t* __restrict__ out_ids, float* __restrict__ out_d)
-{
-    extern __shared__ unsigned char smem[];
-    TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
-    float* sq = reinterpret_cast<float*>(smem + sizeof(TopkShared));
-    const int t = blockIdx.x;
-    if (all_n == 0 && status[t] != 0) return;
-    const int64_t q = q0 + t;
-    for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
-    __syncthreads();
-    const int64_t m = all_n ? all_n : (int64_t)s_count[t];
-    const int32_t* ids = cand_id + (int64_t)t * cap;
-    uint64_t* buf = ws + (int64_t)t * cap;
+__device__ void gather_keys(const float* __restrict__ X, int d, const float* sq, const int32_t* __restrict__ ids,
+                            int64_t m, uint64_t* __restrict__ buf) {
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
-    constexpr int R = 4;                       // rows in flight per half-wave
+    constexpr int R = 4;
     for (int64_t s0 = (int64_t)hw * R; s0 < m; s0 += 8 * R) {
         int64_t id[R];
         float acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t s = s0 + r;
-            id[r] = (s < m) ? (all_n ? s : (int64_t)ids[s]) : -1;
+            id[r] = (s < m) ? (ids ? (int64_t)ids[s] : s) : -1;
             acc[r] = 0.0f;
         }
         for (int c = 4 * hl; c < d; c += 128) {
@@ -560,11 +553,198 @@ __global__ __launch_bounds__(256) void verify_kernel(const float* __restrict__ X
     }
     __threadfence_block();
     __syncthreads();
+}
+
+// Top-k by (FP32 distance, id) over a per-query list of point ids (or over all
+// n points when `all_n`).  Modes:
+//   out_ids != null : write the k results of query q0+t (Euclidean distances)
+//   tau != null     : write tau[t] = squared distance of the k-th smallest
+// Queries are processed when status[t] == want.  When `sv_check`, a list with
+// more than `sv_cap` or fewer than k entries marks the query status 2 instead.
+template <bool ALIGNED>
+__global__ __launch_bounds__(256) void gather_topk_kernel(
+    const float* __restrict__ X, int d, const float* __restrict__ Q, int64_t q0,
+    const int32_t* __restrict__ list, int64_t ld_list, const uint32_t* __restrict__ counts, int64_t use_max,
+    int64_t all_n, int32_t* __restrict__ status, int want, int sv_check, int64_t sv_cap,
+    uint64_t* __restrict__ ws, int64_t ld_ws, int k,
+    int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau)
+{
+    extern __shared__ unsigned char smem[];
+    TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
+    float* sq = reinterpret_cast<float*>(smem + sizeof(TopkShared));
+    const int t = blockIdx.x;
+    if (!all_n && status[t] != want) return;
+    int64_t m = all_n ? all_n : (int64_t)counts[t];
+    if (sv_check) {
+        if (m > sv_cap || m < k) {
+            if (threadIdx.x == 0) status[t] = 2;
+            return;
+        }
+    }
+    if (use_max > 0 && m > use_max) m = use_max;
+    if (m < k) return;                 // cannot happen for S (|S| >= N_S >= k)
+    const int64_t q = q0 + t;
+    for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
+    __syncthreads();
+    uint64_t* buf = ws + (int64_t)t * ld_ws;
+    gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf);
     topk_u64(buf, m, k, sh);
+    if (tau) {
+        if (threadIdx.x == 0) tau[t] = __uint_as_float((uint32_t)(sh.out[k - 1] >> 32));
+        return;
+    }
     for (int j = threadIdx.x; j < k; j += 256) {
         const uint64_t key = sh.out[j];
         out_ids[q * k + j] = (int64_t)(uint32_t)(key & 0xffffffffu);
         out_d[q * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// masked dense verification on MFMA
+// ---------------------------------------------------------------------------
+
+constexpr int kDQ = 128;   // queries per workgroup tile (4 waves: 2 query halves x 2 point halves)
+constexpr int kDP = 64;    // points per tile (one bitmap word per query)
+
+// Squared norms of the chunk's queries (of their BF16 roundings when bf16) and
+// the BF16 copy of the chunk's rows.
+__global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, int d, int bf16,
+                             float* __restrict__ qn, uint16_t* __restrict__ Qbf)
+{
+    const int t = blockIdx.x;
+    if (t >= nqc) return;
+    const float* q = Q + (q0 + t) * (int64_t)d;
+    float acc = 0.f;
+    for (int c = threadIdx.x; c < d; c += 64) {
+        float v = q[c];
+        if (bf16) {
+            const uint16_t h = dl_f32_to_bf16(v);
+            Qbf[(int64_t)t * d + c] = h;
+            v = dl_bf16_to_f32(h);
+        }
+        acc = fmaf(v, v, acc);
+    }
+    acc = dl_wave_sum(acc);
+    if (threadIdx.x == 0) qn[t] = acc;
+}
+
+// Every (query, point) pair of a 128 x 64 tile gets its dot product from
+// MFMA (v_mfma_f32_16x16x4f32, or 16x16x16bf16_1k for BF16 inputs); members of
+// S whose distance ||q||^2 + ||o||^2 - 2 q.o is within tau + margin join the
+// query's survivor list.  Lane layout as in the projection GEMM: lane l gives
+// query row l%16 (A) and point row l%16 (B) at reduction index k0+4*(l/16)+s;
+// accumulator v of lane l is (query 4*(l/16)+v, point l%16).
+template <bool BF16, bool ALIGNED>
+__global__ __launch_bounds__(256) void dense_verify_kernel(
+    const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
+    const float* __restrict__ Q, const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int64_t q0,
+    int nqc, const uint64_t* __restrict__ bm, int64_t W, const float* __restrict__ tau,
+    const int32_t* __restrict__ status, float margin_c, uint32_t* __restrict__ svc, int32_t* __restrict__ sv,
+    int64_t cap_sv, int gx, int64_t gy, int64_t ntiles, int64_t tiles_per_split)
+{
+    __shared__ uint64_t bw[kDQ];
+    __shared__ float sqn[kDQ], stau[kDQ];
+    __shared__ float sxn[kDP];
+    // XCD-aware order: consecutive workgroups go to consecutive XCDs, so all
+    // query tiles of one point split are placed on the same XCD (shared L2).
+    const int64_t lid = blockIdx.x;
+    const int xcd = (int)(lid & 7);
+    const int64_t r = lid >> 3;
+    const int qtile = (int)(r % gx);
+    const int64_t split = xcd + 8 * (r / gx);
+    if (split >= gy) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int qh = wave & 1, ph = wave >> 1;
+    const int qt0 = qtile * kDQ;
+    for (int i = threadIdx.x; i < kDQ; i += 256) {
+        const int t = qt0 + i;
+        const bool ok = t < nqc && status[t] == 0;
+        sqn[i] = ok ? qn[t] : 0.f;
+        stau[i] = ok ? tau[t] : -INFINITY;
+    }
+    const float* qrow[4];
+    const uint16_t* qrowb[4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        int t = qt0 + 64 * qh + 16 * qb + m;
+        if (t >= nqc) t = nqc - 1;
+        qrow[qb] = Q + (q0 + t) * (int64_t)d;
+        qrowb[qb] = BF16 ? Qbf + (int64_t)t * d : nullptr;
+    }
+    const int64_t tb = split * tiles_per_split;
+    const int64_t te = (tb + tiles_per_split < ntiles) ? tb + tiles_per_split : ntiles;
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t p0 = tile * kDP;
+        __syncthreads();
+        if (threadIdx.x < kDQ) {
+            const int t = qt0 + threadIdx.x;
+            bw[threadIdx.x] = (t < nqc && tile < W) ? bm[(int64_t)t * W + tile] : 0ull;
+        } else if (threadIdx.x < kDQ + kDP) {
+            const int64_t p = p0 + threadIdx.x - kDQ;
+            sxn[threadIdx.x - kDQ] = (p < n) ? xn[p] : 0.f;
+        }
+        __syncthreads();
+        floatx4 acc[4][2];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) acc[qb][pb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        int64_t prow[2];
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+            int64_t p = p0 + 32 * ph + 16 * pb + m;
+            prow[pb] = (p < n) ? p : n - 1;
+        }
+        if (!BF16) {
+            for (int k0 = 0; k0 < d; k0 += 16) {
+                const int kk = k0 + 4 * kq;
+                floatx4 qv[4], xv[2];
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb) qv[qb] = load4<ALIGNED>(qrow[qb], kk, d);
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) xv[pb] = load4<ALIGNED>(X + prow[pb] * d, kk, d);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                        for (int pb = 0; pb < 2; ++pb)
+                            acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[qb][s], xv[pb][s], acc[qb][pb],
+                                                                                0, 0, 0);
+            }
+        } else {
+            for (int k0 = 0; k0 < d; k0 += 16) {
+                const int kk = k0 + 4 * kq;
+                shortx4 qv[4], xv[2];
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb) qv[qb] = load4bf<ALIGNED>(qrowb[qb], kk, d);
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) xv[pb] = load4bf<ALIGNED>(Xbf + prow[pb] * d, kk, d);
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb)
+                        acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qv[qb], xv[pb], acc[qb][pb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int qi = 64 * qh + 16 * qb + 4 * kq + v;
+                    const int pi = 32 * ph + 16 * pb + m;
+                    if (!((bw[qi] >> pi) & 1ull)) continue;
+                    const float a2 = sqn[qi] + sxn[pi] - 2.0f * acc[qb][pb][v];
+                    if (a2 <= stau[qi] + margin_c * (sqn[qi] + sxn[pi])) {
+                        const int t = qt0 + qi;
+                        const uint32_t slot = atomicAdd(&svc[t], 1u);
+                        if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
+                    }
+                }
     }
 }
 
@@ -590,7 +770,7 @@ hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
     const int qpb = (a.nqc + ny - 1) / ny;
     hipLaunchKernelGGL((filter_kernel<L, K>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E, a.N_r,
                        a.codes, a.n, a.Qp, a.q0, a.nqc, qpb, a.gthr, a.counts, a.cap, a.cand_id, a.cand_m,
-                       a.cand_lb);
+                       a.cand_lb, a.bm, a.W);
     return hipGetLastError();
 }
 
@@ -615,7 +795,7 @@ hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
 template <int L>
 hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((select_kernel<L>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
-                       a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop);
+                       a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W);
     return hipGetLastError();
 }
 
@@ -647,15 +827,63 @@ hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
     }
 }
 
-hipError_t dl_launch_verify(const QueryArgs& a, hipStream_t st) {
+template <bool AL>
+hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
+                            int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st) {
     const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
-    if (a.d % 4 == 0)
-        hipLaunchKernelGGL((verify_kernel<true>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, a.cand_id,
-                           a.cap, a.s_count, a.status, a.all_n, a.ws, a.k, a.out_ids, a.out_d);
-    else
-        hipLaunchKernelGGL((verify_kernel<false>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0,
-                           a.cand_id, a.cap, a.s_count, a.status, a.all_n, a.ws, a.k, a.out_ids, a.out_d);
+    hipLaunchKernelGGL((gather_topk_kernel<AL>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
+                       counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
+                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau);
     return hipGetLastError();
+}
+
+hipError_t launch_gather(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
+                         int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st) {
+    if (a.d % 4 == 0) return launch_gather_al<true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st);
+    return launch_gather_al<false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st);
+}
+
+// Gathered verification of the whole of S (or D) for queries with status `want`.
+hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st) {
+    return launch_gather(a, a.cand_id, a.cap, a.s_count, 0, want, 0, a.k, nullptr, st);
+}
+
+// tau[t] = k'-th smallest exact distance over the first T members of S.
+hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st) {
+    hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, T, 0, 0, kprime, a.tau, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qprep_kernel, dim3(a.nqc), dim3(64), 0, st, a.Q, a.q0, a.nqc, a.d, a.dense_bf16, a.qn, a.Qbf);
+    return hipGetLastError();
+}
+
+hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
+    const int64_t ntiles = (a.n + kDP - 1) / kDP;
+    const int gx = (a.nqc + kDQ - 1) / kDQ;
+    // about 8 workgroups per CU in total; the split count is a multiple of 8 (one per XCD)
+    int64_t gy = (2048 + gx - 1) / gx;
+    gy = ((gy + 7) / 8) * 8;
+    if (gy > ((ntiles + 7) / 8) * 8) gy = ((ntiles + 7) / 8) * 8;
+    const int64_t tps = (ntiles + gy - 1) / gy;
+    const int64_t blocks = 8 * ((gy + 7) / 8) * gx;
+    const bool al = (a.d % 4) == 0;
+    const float* xn = a.dense_bf16 ? a.xn_bf : a.xn;
+#define DL_DENSE(BF, AL)                                                                                       \
+    hipLaunchKernelGGL((dense_verify_kernel<BF, AL>), dim3((unsigned)blocks), dim3(256), 0, st, a.X, a.Xbf, xn, a.n, \
+                       a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv,   \
+                       a.cap_sv, gx, gy, ntiles, tps)
+    if (a.dense_bf16) {
+        if (al) DL_DENSE(true, true); else DL_DENSE(true, false);
+    } else {
+        if (al) DL_DENSE(false, true); else DL_DENSE(false, false);
+    }
+#undef DL_DENSE
+    return hipGetLastError();
+}
+
+// Exact rerank of the survivors: top-k by FP32 direct distances; a survivor
+// list that overflowed or holds fewer than k entries marks the query status 2.
+hipError_t dl_launch_final(const QueryArgs& a, hipStream_t st) {
+    return launch_gather(a, a.sv, a.cap_sv, a.svc, 0, 0, 1, a.k, nullptr, st);
 }
 
 size_t dl_verify_smem(int d) { return sizeof(TopkShared) + (size_t)d * 4 + 64; }

@@ -41,7 +41,7 @@ def test_binding_matches_header():
 def test_struct_layouts():
     from paper_2406_10938_amd import _lib
     assert ctypes.sizeof(_lib.BuildOpts) == 8 + 4 * 4 + 8 + 8
-    assert ctypes.sizeof(_lib.QueryOpts) == 4 * 4 + 8 + 8
+    assert ctypes.sizeof(_lib.QueryOpts) == 4 * 4 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_lib.Info) == 8 + 4 * 4 + 8 + 4 + 4 + 8 * 8 + 8
 
 

@@ -263,3 +263,56 @@ def test_argument_errors(dl):
         idx.query(t(c["Q"]), 10, 1.0, 0.1)
     with pytest.raises(dl.DetlshError, match="EINVAL"):
         idx.query(t(c["Q"]), 10, 1.5, 1.5)
+
+
+# --------------------------------------------------------------------------
+# masked dense MFMA verification and the BF16 + rerank form
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,kind,k,nq", [(70_001, 128, "integer", 10, 150), (66_000, 37, "mixture", 20, 130),
+                                           (80_000, 96, "mixture", 100, 64), (65_600, 200, "mixture", 1, 257)])
+def test_dense_verification_equals_gathered(dl, n, d, kind, k, nq):
+    """Survivors of the dense pass are re-ranked with the same FP32 direct
+    distances as the gathered pass, so both return identical ids and bits."""
+    say(f"dense vs gathered n={n} d={d} kind={kind} k={k} nq={nq}")
+    c = U.case(n=n, d=d, N_r=256, frac=0.01, kind=kind, nq=nq, seed=31)
+    idx = dl.build_index(c["X"], 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"])
+    Q = t(c["Q"])
+    g_ids, g_d = idx.query(Q, k, 1.5, 0.1, verify="gather")
+    d_ids, d_d = idx.query(Q, k, 1.5, 0.1, verify="dense")
+    assert np.array_equal(g_ids.cpu().numpy(), d_ids.cpu().numpy())
+    assert np.array_equal(g_d.cpu().numpy(), d_d.cpu().numpy())
+    ex = idx.export()
+    Qp = idx.project(Q).cpu().numpy()
+    r = idx.query_debug(Q[:4], k, 1.5, 0.1, Qp=t(Qp[:4]), verify="dense")
+    for qi in range(4):
+        ref = U.oracle_query(c["X"], c["Q"][qi], Qp[qi], ex["codes"], ex["B"], 4, 16, k, 0.1)
+        S_gpu = set(r["cand"][qi, :int(r["counts"][qi])].cpu().numpy().tolist())
+        sym = S_gpu ^ set(ref.S.tolist())
+        assert sym <= U.borderline_points(Qp[qi], ex["codes"], ex["B"], 4, 16, ref.thr)
+        if not sym:
+            U.compare_result(ref.ids, ref.dists, c["X"], c["Q"][qi], r["ids"][qi].cpu().numpy(),
+                             r["dists"][qi].cpu().numpy(), ref.S, k)
+
+
+@pytest.mark.parametrize("n,d,k", [(70_000, 128, 10), (66_000, 96, 25)])
+def test_bf16_rerank_form(dl, n, d, k):
+    """BF16 products with FP32 accumulation keep candidates by the rerank
+    bound; the returned distances are exact FP32 distances of the returned
+    ids and the ids agree with the FP32 form at recall >= 0.98."""
+    say(f"bf16 rerank n={n} d={d} k={k}")
+    c = U.case(n=n, d=d, N_r=256, frac=0.01, kind="mixture", nq=100, seed=41)
+    idx = dl.build_index(c["X"], 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=True)
+    Q = t(c["Q"])
+    f_ids, f_d = idx.query(Q, k, 1.5, 0.1)
+    b_ids, b_d = idx.query(Q, k, 1.5, 0.1, precision=dl.BF16_RERANK, rerank_mult=4)
+    f_ids, b_ids, b_d = f_ids.cpu().numpy(), b_ids.cpu().numpy(), b_d.cpu().numpy()
+    agree = np.mean([len(set(a) & set(b)) / k for a, b in zip(f_ids, b_ids)])
+    say(f"  BF16+rerank agreement with FP32: {agree:.4f}")
+    assert agree >= 0.98
+    for qi in range(0, 100, 7):
+        exact = np.sqrt(O.sq_dists(c["X"][b_ids[qi]], c["Q"][qi]))
+        np.testing.assert_allclose(b_d[qi], exact, rtol=U.REL)
+        assert np.all(np.diff(b_d[qi]) >= 0)
+    with pytest.raises(dl.DetlshError, match="keep_bf16"):
+        dl.build_index(c["X"][:5000], 4, 16, 256, 0.1).query(Q[:2], k, 1.5, 0.1, precision=dl.BF16_RERANK)
