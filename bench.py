@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -117,6 +119,14 @@ def main():
     X = torch.from_numpy(X_host).to(dev)
     Q = torch.from_numpy(Q_host).to(dev)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
 
     def step():
         idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
