@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true", help="skip timing the BF16+rerank form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -128,10 +129,28 @@ def main():
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
 
-    def step():
-        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
-        ids, dists = idx.query(Q, k, cfg.c, beta)
+    def step(bf16=False):
+        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=bf16)
+        ids, dists = idx.query(Q, k, cfg.c, beta, precision=dl.BF16_RERANK if bf16 else dl.FP32)
         return idx, ids, dists
+
+    def timed(bf16, steps):
+        """`steps` whole steps between two events on the launch stream."""
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        bsum = 0.0
+        last = None
+        for _ in range(steps):
+            tb = time.perf_counter()
+            ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=bf16)
+            bsum += time.perf_counter() - tb
+            last = ix.query(Q, k, cfg.c, beta, precision=dl.BF16_RERANK if bf16 else dl.FP32)
+            ix.free()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), bsum, last
 
     log(f"[bench] warmup x{args.warmup}")
     idx = ids = dists = None
@@ -153,22 +172,9 @@ def main():
 
     dl.profile_enable(True, reset=True)
     log(f"[bench] timed x{args.steps}")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    build_s = 0.0
-    for _ in range(args.steps):
-        tb = time.perf_counter()
-        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
-        build_s += time.perf_counter() - tb
-        ids, dists = idx.query(Q, k, cfg.c, beta)
-        idx.free()
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms_total, build_s, _ = timed(False, args.steps)
     wall = time.perf_counter() - t0
-    ms_total = ev0.elapsed_time(ev1)
     dl.profile_enable(False, reset=False)
     prof = dl.profile_read()
     ms_per_step = ms_total / args.steps
@@ -193,6 +199,9 @@ def main():
     elif dom == "verify_topk":
         byts = N_S * d * 4 * (nq / launches_per_step)
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif dom == "dense_verify":
+        fl = 2.0 * n * d * (nq / launches_per_step)
+        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s"}
     elif dom == "project_encode":
         fl = 2.0 * n * LK * d
         roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s"}
@@ -201,6 +210,19 @@ def main():
     roof["frac"] = (roof["achieved"] / roof["peak"]) if roof["achieved"] else None
     roof["traffic"] = None
     roof["kernel"] = dom
+
+    bf = None
+    if not args.no_bf16:
+        log(f"[bench] BF16+rerank form: warmup x{args.warmup}, timed x{args.steps}")
+        for _ in range(args.warmup):
+            ixb, ids_b, _ = step(True)
+            ixb.free()
+        ms_b, bs_b, (ids_b, _) = timed(True, args.steps)
+        rec_b = recall_at_k(X, Q, ids_b, k, kth) if recall is not None else None
+        bf = {"value": nq * args.steps / (ms_b / 1e3), "unit": "queries/s", "ms_per_step": ms_b / args.steps,
+              "build_ms": bs_b * 1e3 / args.steps, "recall_at_k": rec_b, "rerank_mult": 4,
+              "dtype": "bf16 products, fp32 accumulate and rerank"}
+        log(f"[bench] BF16+rerank: {bf['value']:.0f} q/s, recall {rec_b}")
 
     cpu = None
     if not args.no_cpu:
@@ -233,6 +255,7 @@ def main():
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "bf16_rerank": bf,
     }
     print(json.dumps(out), flush=True)
 

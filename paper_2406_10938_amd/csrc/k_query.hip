@@ -634,8 +634,16 @@ __global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, i
 // S whose distance ||q||^2 + ||o||^2 - 2 q.o is within tau + margin join the
 // query's survivor list.  Lane layout as in the projection GEMM: lane l gives
 // query row l%16 (A) and point row l%16 (B) at reduction index k0+4*(l/16)+s;
-// accumulator v of lane l is (query 4*(l/16)+v, point l%16).
-template <bool BF16, bool ALIGNED>
+// accumulator v of lane l is (query 4*(l/16)+v, point l%16).  With QLDS the
+// workgroup's 128 query rows stay in LDS (rows padded by 16 bytes against bank
+// conflicts) for the whole point range; only the point rows stream from L2.
+struct DenseQuery {
+    uint64_t bits;   // membership word of the current 64-point tile
+    float qn;        // squared norm
+    float tau;       // bound on the k'-th squared distance (-inf: skip)
+};
+
+template <bool BF16, bool ALIGNED, bool QLDS, int KS>
 __global__ __launch_bounds__(256) void dense_verify_kernel(
     const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
     const float* __restrict__ Q, const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int64_t q0,
@@ -643,8 +651,8 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     const int32_t* __restrict__ status, float margin_c, uint32_t* __restrict__ svc, int32_t* __restrict__ sv,
     int64_t cap_sv, int gx, int64_t gy, int64_t ntiles, int64_t tiles_per_split)
 {
-    __shared__ uint64_t bw[kDQ];
-    __shared__ float sqn[kDQ], stau[kDQ];
+    extern __shared__ unsigned char dsm[];
+    __shared__ DenseQuery sqd[kDQ];
     __shared__ float sxn[kDP];
     // XCD-aware order: consecutive workgroups go to consecutive XCDs, so all
     // query tiles of one point split are placed on the same XCD (shared L2).
@@ -658,29 +666,63 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     const int m = lane & 15, kq = lane >> 4;
     const int qh = wave & 1, ph = wave >> 1;
     const int qt0 = qtile * kDQ;
-    for (int i = threadIdx.x; i < kDQ; i += 256) {
-        const int t = qt0 + i;
-        const bool ok = t < nqc && status[t] == 0;
-        sqn[i] = ok ? qn[t] : 0.f;
-        stau[i] = ok ? tau[t] : -INFINITY;
+    const int ldq = BF16 ? d + 8 : d + 4;      // LDS row stride in elements
+    float* sQ = reinterpret_cast<float*>(dsm);
+    uint16_t* sQb = reinterpret_cast<uint16_t*>(dsm);
+    if (QLDS) {
+        for (int i = wave; i < kDQ; i += 4) {
+            int t = qt0 + i;
+            if (t >= nqc) t = nqc - 1;
+            if (BF16) {
+                const uint16_t* src = Qbf + (int64_t)t * d;
+                for (int c = lane; c < d; c += 64) sQb[i * ldq + c] = src[c];
+            } else {
+                const float* src = Q + (q0 + t) * (int64_t)d;
+                for (int c = lane; c < d; c += 64) sQ[i * ldq + c] = src[c];
+            }
+        }
     }
     const float* qrow[4];
     const uint16_t* qrowb[4];
 #pragma unroll
     for (int qb = 0; qb < 4; ++qb) {
-        int t = qt0 + 64 * qh + 16 * qb + m;
+        const int i = 64 * qh + 16 * qb + m;
+        int t = qt0 + i;
         if (t >= nqc) t = nqc - 1;
-        qrow[qb] = Q + (q0 + t) * (int64_t)d;
-        qrowb[qb] = BF16 ? Qbf + (int64_t)t * d : nullptr;
+        qrow[qb] = QLDS ? sQ + i * ldq : Q + (q0 + t) * (int64_t)d;
+        qrowb[qb] = QLDS ? sQb + i * ldq : (BF16 ? Qbf + (int64_t)t * d : nullptr);
     }
     const int64_t tb = split * tiles_per_split;
     const int64_t te = (tb + tiles_per_split < ntiles) ? tb + tiles_per_split : ntiles;
+    // KS > 0: all d <= 16*KS reduction elements of the lane's two point rows are
+    // held in registers, and the next tile's rows are loaded during this tile.
+    floatx4 xc[KS > 0 ? KS : 1][2], xnx[KS > 0 ? KS : 1][2];
+    shortx4 bc[KS > 0 ? KS : 1][2], bnx[KS > 0 ? KS : 1][2];
+    auto load_rows = [&](int64_t tile, floatx4 (&xf)[KS > 0 ? KS : 1][2], shortx4 (&xb)[KS > 0 ? KS : 1][2]) {
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+            int64_t p = tile * kDP + 32 * ph + 16 * pb + m;
+            if (p >= n) p = n - 1;
+#pragma unroll
+            for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) {
+                if (BF16) xb[ks][pb] = load4bf<ALIGNED>(Xbf + p * d, 16 * ks + 4 * kq, d);
+                else xf[ks][pb] = load4<ALIGNED>(X + p * d, 16 * ks + 4 * kq, d);
+            }
+        }
+    };
+    if (KS > 0 && tb < te) load_rows(tb, xc, bc);
     for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t p0 = tile * kDP;
+        if (KS > 0 && tile + 1 < te) load_rows(tile + 1, xnx, bnx);
         __syncthreads();
         if (threadIdx.x < kDQ) {
             const int t = qt0 + threadIdx.x;
-            bw[threadIdx.x] = (t < nqc && tile < W) ? bm[(int64_t)t * W + tile] : 0ull;
+            const bool ok = t < nqc && status[t] == 0;
+            DenseQuery dq;
+            dq.bits = (ok && tile < W) ? bm[(int64_t)t * W + tile] : 0ull;
+            dq.qn = ok ? qn[t] : 0.f;
+            dq.tau = ok ? tau[t] : -INFINITY;
+            sqd[threadIdx.x] = dq;
         } else if (threadIdx.x < kDQ + kDP) {
             const int64_t p = p0 + threadIdx.x - kDQ;
             sxn[threadIdx.x - kDQ] = (p < n) ? xn[p] : 0.f;
@@ -698,53 +740,108 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
             prow[pb] = (p < n) ? p : n - 1;
         }
         if (!BF16) {
-            for (int k0 = 0; k0 < d; k0 += 16) {
+            auto step = [&](int k0, const floatx4 (&xv)[2]) {
                 const int kk = k0 + 4 * kq;
-                floatx4 qv[4], xv[2];
+                floatx4 qv[4];
 #pragma unroll
-                for (int qb = 0; qb < 4; ++qb) qv[qb] = load4<ALIGNED>(qrow[qb], kk, d);
+                for (int qb = 0; qb < 4; ++qb) {
+                    if (QLDS) {
+                        if (kk < d) {
+                            const float4 v = *reinterpret_cast<const float4*>(qrow[qb] + kk);
+                            qv[qb] = floatx4{v.x, v.y, v.z, v.w};
+                        } else {
+                            qv[qb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        }
+                    } else {
+                        qv[qb] = load4<ALIGNED>(qrow[qb], kk, d);
+                    }
+                }
 #pragma unroll
-                for (int pb = 0; pb < 2; ++pb) xv[pb] = load4<ALIGNED>(X + prow[pb] * d, kk, d);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
+                for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
                     for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
                         for (int pb = 0; pb < 2; ++pb)
-                            acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[qb][s], xv[pb][s], acc[qb][pb],
+                            acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[qb][s2], xv[pb][s2], acc[qb][pb],
                                                                                 0, 0, 0);
+            };
+            if (KS > 0) {
+#pragma unroll
+                for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) step(16 * ks, xc[ks]);
+            } else {
+                for (int k0 = 0; k0 < d; k0 += 16) {
+                    floatx4 xv[2];
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb) xv[pb] = load4<ALIGNED>(X + prow[pb] * d, k0 + 4 * kq, d);
+                    step(k0, xv);
+                }
             }
         } else {
-            for (int k0 = 0; k0 < d; k0 += 16) {
+            auto step = [&](int k0, const shortx4 (&xv)[2]) {
                 const int kk = k0 + 4 * kq;
-                shortx4 qv[4], xv[2];
+                shortx4 qv[4];
 #pragma unroll
-                for (int qb = 0; qb < 4; ++qb) qv[qb] = load4bf<ALIGNED>(qrowb[qb], kk, d);
-#pragma unroll
-                for (int pb = 0; pb < 2; ++pb) xv[pb] = load4bf<ALIGNED>(Xbf + prow[pb] * d, kk, d);
+                for (int qb = 0; qb < 4; ++qb) {
+                    if (QLDS) {
+                        if (kk < d) {
+                            const uint2 v = *reinterpret_cast<const uint2*>(qrowb[qb] + kk);
+                            qv[qb] = shortx4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff),
+                                             (short)(v.y >> 16)};
+                        } else {
+                            qv[qb] = shortx4{0, 0, 0, 0};
+                        }
+                    } else {
+                        qv[qb] = load4bf<ALIGNED>(qrowb[qb], kk, d);
+                    }
+                }
 #pragma unroll
                 for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
                     for (int pb = 0; pb < 2; ++pb)
                         acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qv[qb], xv[pb], acc[qb][pb], 0, 0, 0);
+            };
+            if (KS > 0) {
+#pragma unroll
+                for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) step(16 * ks, bc[ks]);
+            } else {
+                for (int k0 = 0; k0 < d; k0 += 16) {
+                    shortx4 xv[2];
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb) xv[pb] = load4bf<ALIGNED>(Xbf + prow[pb] * d, k0 + 4 * kq, d);
+                    step(k0, xv);
+                }
             }
         }
+        if (KS > 0) {
+#pragma unroll
+            for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks)
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) {
+                    if (BF16) bc[ks][pb] = bnx[ks][pb];
+                    else xc[ks][pb] = xnx[ks][pb];
+                }
+        }
+        const int pi0 = 32 * ph + m;
+        const float xn0 = sxn[pi0], xn1 = sxn[pi0 + 16];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int pb = 0; pb < 2; ++pb)
+            for (int v = 0; v < 4; ++v) {
+                const int qi = 64 * qh + 16 * qb + 4 * kq + v;
+                const DenseQuery dq = sqd[qi];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int qi = 64 * qh + 16 * qb + 4 * kq + v;
-                    const int pi = 32 * ph + 16 * pb + m;
-                    if (!((bw[qi] >> pi) & 1ull)) continue;
-                    const float a2 = sqn[qi] + sxn[pi] - 2.0f * acc[qb][pb][v];
-                    if (a2 <= stau[qi] + margin_c * (sqn[qi] + sxn[pi])) {
+                for (int pb = 0; pb < 2; ++pb) {
+                    const int pi = pi0 + 16 * pb;
+                    if (!((dq.bits >> pi) & 1ull)) continue;
+                    const float nsum = dq.qn + (pb ? xn1 : xn0);
+                    const float a2 = fmaf(-2.0f, acc[qb][pb][v], nsum);
+                    if (a2 <= fmaf(margin_c, nsum, dq.tau)) {
                         const int t = qt0 + qi;
                         const uint32_t slot = atomicAdd(&svc[t], 1u);
                         if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
                     }
                 }
+            }
     }
 }
 
@@ -763,8 +860,9 @@ hipError_t launch_guess_lk(const QueryArgs& a, hipStream_t st) {
 template <int L, int K>
 hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
     const int64_t pb = (a.n + 255) / 256;
-    int ny = 1;
-    // enough blocks to fill the machine several times over
+    // about 64 queries per workgroup (measured best at n = 10^6, d = 128:
+    // shorter blocks balance better), and enough blocks to fill the machine
+    int ny = (a.nqc + 63) / 64;
     while (pb * ny < 4096 && ny < a.nqc) ny *= 2;
     if (ny > a.nqc) ny = a.nqc;
     const int qpb = (a.nqc + ny - 1) / ny;
@@ -867,14 +965,30 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     const int64_t blocks = 8 * ((gy + 7) / 8) * gx;
     const bool al = (a.d % 4) == 0;
     const float* xn = a.dense_bf16 ? a.xn_bf : a.xn;
-#define DL_DENSE(BF, AL)                                                                                       \
-    hipLaunchKernelGGL((dense_verify_kernel<BF, AL>), dim3((unsigned)blocks), dim3(256), 0, st, a.X, a.Xbf, xn, a.n, \
-                       a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv,   \
-                       a.cap_sv, gx, gy, ntiles, tps)
+#define DL_DENSE(BF, AL, QL, KS)                                                                               \
+    hipLaunchKernelGGL((dense_verify_kernel<BF, AL, QL, KS>), dim3((unsigned)blocks), dim3(256), shm, st, a.X,     \
+                       a.Xbf, xn, a.n, a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, \
+                       a.svc, a.sv, a.cap_sv, gx, gy, ntiles, tps)
+    // the query tile stays in LDS when it fits in 80 KB; point rows of up to
+    // 128 elements stay in registers
+    const size_t qbytes = (size_t)kDQ * (a.dense_bf16 ? (a.d + 8) * 2 : (a.d + 4) * 4);
+    const bool qlds = al && qbytes <= 80 * 1024;
+    const size_t shm = qlds ? qbytes : 0;
+    const int ks = (a.d + 15) / 16;
     if (a.dense_bf16) {
-        if (al) DL_DENSE(true, true); else DL_DENSE(true, false);
+        if (qlds && ks <= 4) DL_DENSE(true, true, true, 4);
+        else if (qlds && ks <= 6) DL_DENSE(true, true, true, 6);
+        else if (qlds && ks <= 8) DL_DENSE(true, true, true, 8);
+        else if (qlds) DL_DENSE(true, true, true, 0);
+        else if (al) DL_DENSE(true, true, false, 0);
+        else DL_DENSE(true, false, false, 0);
     } else {
-        if (al) DL_DENSE(false, true); else DL_DENSE(false, false);
+        if (qlds && ks <= 4) DL_DENSE(false, true, true, 4);
+        else if (qlds && ks <= 6) DL_DENSE(false, true, true, 6);
+        else if (qlds && ks <= 8) DL_DENSE(false, true, true, 8);
+        else if (qlds) DL_DENSE(false, true, true, 0);
+        else if (al) DL_DENSE(false, true, false, 0);
+        else DL_DENSE(false, false, false, 0);
     }
 #undef DL_DENSE
     return hipGetLastError();
