@@ -168,7 +168,7 @@ typedef struct {
     int32_t rerank_mult;        /* BF16 form keeps rerank_mult*k for the FP32 rerank;
                                    0 -> 4                                             */
     int32_t rmin_policy;        /* DETLSH_RMIN_MAGIC (default) or DETLSH_RMIN_FIXED  */
-    int32_t max_rounds;         /* FIXED: radius rounds before S = D; 0 -> 64        */
+    int32_t max_rounds;         /* FIXED: radius rounds (1..64) before S = D; 0 -> 64 */
     double r_min;               /* FIXED: initial radius, > 0                        */
     size_t workspace_bytes;     /* per-call workspace budget; 0 -> 4 GiB             */
     int32_t verify;             /* candidate verification: 0 automatic, 1 gathered
@@ -189,7 +189,10 @@ typedef struct {
  * trees, when k points of S lie within c*r; otherwise r <- c*r.  Under
  * DETLSH_RMIN_MAGIC the start radius is the smallest one satisfying both
  * conditions of the magic r_min (Sec. 5.2), so the query ends in its first
- * round.  If N_S >= n, S = D.
+ * round.  If N_S >= n, S = D (MAGIC).  Under DETLSH_RMIN_FIXED the radii are
+ * r_t = r_min c^t (t < max_rounds); a query that meets neither condition within
+ * max_rounds rounds is answered over S = D; verification is the gathered FP32
+ * form.
  *
  * out_ids (device, nq x k int64) and out_dists (device, nq x k FP32) receive
  * the k members of S nearest to each query, ascending by (distance, id);

@@ -505,7 +505,29 @@ struct QueryPlan {
     int kprime = 0;         // rank of the distance bound tau
     int64_t T = 0;          // members of S used for tau
     int64_t cap_sv = 0;     // survivor slots per query
+    bool fixed = false;     // printed radius ladder from r_min
+    int rounds = 0;         // radius rounds before S = D
+    const float* rad2 = nullptr;
+    const float* c2 = nullptr;
 };
+
+// chi^2_alpha(K): Pr[Y > x] = alpha for Y ~ chi^2(K), K even, by bisection on the
+// closed form Pr[Y > x] = exp(-x/2) sum_{i<K/2} (x/2)^i / i!  (Lemma 2).
+double chi2_upper_quantile_even(double alpha, int K) {
+    auto sf = [K](double x) {
+        const double h = 0.5 * x;
+        double term = 1.0, s = 1.0;
+        for (int i = 1; i < K / 2; ++i) { term *= h / i; s += term; }
+        return std::exp(-h) * s;
+    };
+    double lo = 0.0, hi = 1.0;
+    while (sf(hi) > alpha) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sf(mid) > alpha) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
 
 QueryPlan plan_query(int64_t n, int k, double beta, int L) {
     QueryPlan p;
@@ -558,7 +580,7 @@ size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d)
 detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, int64_t q0, int64_t nq, int k,
                           const QueryPlan& plan, bool force_all_candidates, size_t budget, int64_t* out_ids,
                           float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
-    const int64_t cap = force_all_candidates ? ix->n : plan.cap;
+    const int64_t cap = (force_all_candidates || plan.fixed) ? ix->n : plan.cap;
     const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d);
     int64_t nqc = (int64_t)(budget / pq);
     if (nqc < 1) nqc = 1;
@@ -580,6 +602,11 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.s_count = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
     a.thr = reinterpret_cast<float*>(take((size_t)nqc * 4));
     a.stop = reinterpret_cast<int32_t*>(take((size_t)nqc * 4));
+    int32_t* a_rounds = reinterpret_cast<int32_t*>(take((size_t)nqc * 4));
+    a.fixed = plan.fixed ? 1 : 0;
+    a.rad2 = plan.rad2;
+    a.c2 = plan.c2;
+    a.T = plan.rounds;
     a.cand_id = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
     a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
@@ -608,7 +635,23 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         const int cnt = (int)std::min<int64_t>(nqc, nq - c0);
         a.q0 = q0 + c0;
         a.nqc = cnt;
-        if (!plan.all) {
+        if (plan.fixed) {
+            HCHECK(hipMemsetAsync(a.counts, 0, (size_t)cnt * 4, st));
+            inf_host.assign(cnt, (float)((double)plan.rounds * ix->L));   // every point that ever enters
+            HCHECK(hipMemcpyAsync(a.gthr, inf_host.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, st));
+            {
+                DlTimer tm(T_FILTER, st);
+                HCHECK(dl_launch_filter(a, st));
+            }
+            {
+                DlTimer tm(T_SELECT, st);
+                HCHECK(dl_launch_select(a, st));
+            }
+            {
+                DlTimer tm(T_VERIFY, st);
+                HCHECK(dl_launch_fixed_finish(a, a_rounds, st));
+            }
+        } else if (!plan.all) {
             HCHECK(hipMemsetAsync(a.counts, 0, (size_t)cnt * 4, st));
             if (force_all_candidates) {
                 inf_host.assign(cnt, INFINITY);
@@ -628,7 +671,9 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         } else {
             HCHECK(hipMemsetAsync(a.status, 0, (size_t)cnt * 4, st));
         }
-        if (plan.dense && !plan.all) {
+        if (plan.fixed) {
+            // verified by the finishing kernel
+        } else if (plan.dense && !plan.all) {
             {
                 DlTimer tm(T_TAU, st);
                 HCHECK(dl_launch_tau(a, plan.T, plan.kprime, st));
@@ -672,8 +717,12 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
                 if (dbg.stop_tree) HCHECK(hipMemcpy(dbg.stop_tree + gq, a.stop, (size_t)cnt * 4, hipMemcpyDeviceToDevice));
             }
             if (dbg.rounds) {
-                std::vector<int32_t> one(cnt, 1);
-                HCHECK(hipMemcpy(dbg.rounds + gq, one.data(), (size_t)cnt * 4, hipMemcpyHostToDevice));
+                if (plan.fixed) {
+                    HCHECK(hipMemcpy(dbg.rounds + gq, a_rounds, (size_t)cnt * 4, hipMemcpyDeviceToDevice));
+                } else {
+                    std::vector<int32_t> one(cnt, 1);
+                    HCHECK(hipMemcpy(dbg.rounds + gq, one.data(), (size_t)cnt * 4, hipMemcpyHostToDevice));
+                }
             }
         }
     }
@@ -702,7 +751,13 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     if (precision == DETLSH_BF16_RERANK && (int64_t)rmult * k > 1024)
         return fail(DETLSH_EINVAL, "rerank_mult*k = %lld exceeds 1024", (long long)rmult * k);
     if (verify < 0 || verify > 2) return fail(DETLSH_EINVAL, "verify mode %d is not defined", verify);
-    if (policy != DETLSH_RMIN_MAGIC) return fail(DETLSH_EINVAL, "r_min policy %d is not available", policy);
+    if (policy != DETLSH_RMIN_MAGIC && policy != DETLSH_RMIN_FIXED)
+        return fail(DETLSH_EINVAL, "r_min policy %d is not defined", policy);
+    const int rounds = (opts && opts->max_rounds > 0) ? opts->max_rounds : 64;
+    if (policy == DETLSH_RMIN_FIXED) {
+        if (!(opts && opts->r_min > 0.0)) return fail(DETLSH_EINVAL, "FIXED r_min needs r_min > 0");
+        if (rounds > 64) return fail(DETLSH_EINVAL, "max_rounds must be <= 64, got %d", rounds);
+    }
     if (nq == 0) return DETLSH_OK;
     if (!is_device_ptr(Q)) return fail(DETLSH_EINVAL, "Q must be a device pointer");
     if (!is_device_ptr(out_ids) || !is_device_ptr(out_d)) return fail(DETLSH_EINVAL, "outputs must be device pointers");
@@ -721,8 +776,30 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
         Qp = qpbuf.as<float>();
     }
     QueryPlan plan = plan_query(ix->n, k, beta, ix->L);
+    DevBuf ladder;
+    if (policy == DETLSH_RMIN_FIXED) {
+        // radii r_t = r_min c^t (formed by repeated multiplication), squared
+        // projected radius (eps r_t)^2 and squared verification radius (c r_t)^2
+        const double eps = std::sqrt(chi2_upper_quantile_even(std::exp(-1.0 / ix->L), ix->K));
+        std::vector<float> tab(2 * (size_t)rounds);
+        double r = opts->r_min;
+        for (int t = 0; t < rounds; ++t) {
+            tab[t] = (float)((eps * r) * (eps * r));
+            tab[rounds + t] = (float)((c * r) * (c * r));
+            r *= c;
+        }
+        HCHECK(ladder.alloc(tab.size() * 4));
+        HCHECK(hipMemcpyAsync(ladder.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st));
+        HCHECK(hipStreamSynchronize(st));
+        plan.fixed = true;
+        plan.all = false;
+        plan.rounds = rounds;
+        plan.rad2 = ladder.as<float>();
+        plan.c2 = ladder.as<float>() + rounds;
+        plan.cap = ix->n;
+    }
     const bool bf16 = precision == DETLSH_BF16_RERANK;
-    plan.dense = !plan.all && (verify == 2 || (verify == 0 && (ix->n >= 65536 || bf16)));
+    plan.dense = !plan.all && !plan.fixed && (verify == 2 || (verify == 0 && (ix->n >= 65536 || bf16)));
     plan.bf16 = bf16 && plan.dense;
     plan.kprime = (int)std::min<uint64_t>(plan.N_S, (uint64_t)(bf16 ? rmult * k : k));
     plan.T = std::max<int64_t>(2048, 32 * (int64_t)plan.kprime);
@@ -731,7 +808,18 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     detlsh_status s = run_queries(ix, Q, Qp, 0, nq, k, plan, false, budget, out_ids, out_d, dbg, status, st);
     if (s) { prof_resolve(); return s; }
     // queries whose candidate count missed [N_S, cap]: every point a candidate
+    QueryPlan all_plan = plan;
+    all_plan.all = true;
+    all_plan.fixed = false;
+    all_plan.dense = false;
+    all_plan.cap = ix->n;
     for (int64_t q = 0; q < nq; ++q) {
+        if (status[q] == 3) {
+            std::vector<int32_t> st1(1, 0);
+            s = run_queries(ix, Q, Qp, q, 1, k, all_plan, false, budget, out_ids, out_d, dbg, st1, st);
+            if (s) { prof_resolve(); return s; }
+            continue;
+        }
         if (status[q] != 1) continue;
         std::vector<int32_t> st1(1, 0);
         s = run_queries(ix, Q, Qp, q, 1, k, plan, true, budget, out_ids, out_d, dbg, st1, st);

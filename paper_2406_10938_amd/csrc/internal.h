@@ -91,6 +91,11 @@ struct QueryArgs {
     uint32_t* svc = nullptr;         // survivors per query
     int32_t* sv = nullptr;
     int64_t cap_sv = 0;
+    // printed radius ladder (FIXED r_min)
+    int fixed = 0;
+    const float* rad2 = nullptr;     // (eps r_min c^t)^2, t < T
+    const float* c2 = nullptr;       // (c r_min c^t)^2, t < T
+    int T = 0;
     // outputs (all queries)
     int64_t* out_ids = nullptr;
     float* out_d = nullptr;
@@ -106,6 +111,7 @@ hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st);
 hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st);
 hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_final(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_fixed_finish(const QueryArgs& a, int32_t* rounds, hipStream_t st);
 
 // ---- kernel timing (detlsh_api.cpp) ----
 struct DlTimer {

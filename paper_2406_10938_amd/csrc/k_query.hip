@@ -303,12 +303,31 @@ __device__ __forceinline__ void store_lbs(float* __restrict__ dst, const float (
 template <int L>
 struct FilterShared {
     int32_t ids[4][kGroup][64];
+    float key[4][kGroup][64];
     float lbs[4][kGroup][64][L];
     uint32_t wc[4][kGroup];
     uint32_t gb[kGroup];
 };
 
-template <int L, int K>
+// Entry step of a point under the printed radius ladder (Alg. 7 from a given
+// r_min): in round t tree i admits o when LB_i^2 <= rad2[t] = (eps r_min c^t)^2;
+// steps are numbered s = t*L + i (trees 1-based), so S after step s is
+// {o : e(o) <= s} with e(o) = min_i (t_i(o) L + i).  Points admitted in no
+// round below T get +inf.
+template <int L>
+__device__ __forceinline__ float entry_step(const float (&lb)[L], const float* __restrict__ rad2, int T) {
+    float e = INFINITY;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        int pos = 0;                          // number of radii < lb[i]
+        for (int st = 32; st > 0; st >>= 1)
+            if (pos + st <= T && rad2[pos + st - 1] < lb[i]) pos += st;
+        if (pos < T) e = fminf(e, (float)(pos * L + i + 1));
+    }
+    return e;
+}
+
+template <int L, int K, bool FIXED>
 __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E, int N_r,
                                                      const uint8_t* __restrict__ codes, int64_t n,
                                                      const float* __restrict__ Qp, int64_t q0, int nqc,
@@ -316,10 +335,15 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
                                                      uint32_t* __restrict__ counts, int64_t cap,
                                                      int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
                                                      float* __restrict__ cand_lb, uint64_t* __restrict__ bm,
-                                                     int64_t W)
+                                                     int64_t W, const float* __restrict__ rad2, int T)
 {
     constexpr int LK = L * K;
     __shared__ FilterShared<L> sh;
+    __shared__ float srad[64];
+    if (FIXED) {
+        if (threadIdx.x < T) srad[threadIdx.x] = rad2[threadIdx.x];
+        __syncthreads();
+    }
     const int ldE = N_r + 1;
     const int64_t o_raw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = o_raw < n;
@@ -338,12 +362,14 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
             const int t = tg + g;
             const float* qp = Qp + (q0 + t) * LK;
             float lb[L];
-            const float m = cell_lbs<L, K>(qp, lo, hi, lb);
+            float m = cell_lbs<L, K>(qp, lo, hi, lb);
+            if (FIXED) m = entry_step<L>(lb, srad, T);   // the key is the entry step
             const bool hit = valid && (m <= gthr[t]);
             const uint64_t mask = dl_ballot(hit);
             if (hit) {
                 const int pos = dl_rank_below(mask);
                 sh.ids[wave][g][pos] = (int32_t)o;
+                sh.key[wave][g][pos] = m;
 #pragma unroll
                 for (int i = 0; i < L; ++i) sh.lbs[wave][g][pos][i] = lb[i];
             }
@@ -371,10 +397,9 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
                     const int64_t at = (int64_t)(tg + g) * cap + idx;
                     cand_id[at] = sh.ids[wave][g][j];
                     float lb[L];
-                    float m = INFINITY;
 #pragma unroll
-                    for (int i = 0; i < L; ++i) { lb[i] = sh.lbs[wave][g][j][i]; m = fminf(m, lb[i]); }
-                    cand_m[at] = m;
+                    for (int i = 0; i < L; ++i) lb[i] = sh.lbs[wave][g][j][i];
+                    cand_m[at] = sh.key[wave][g][j];
                     store_lbs<L>(cand_lb + at * L, lb);
                 }
             }
@@ -418,7 +443,7 @@ __device__ __forceinline__ void load_lbs(const float* __restrict__ src, float (&
     }
 }
 
-template <int L>
+template <int L, bool FIXED>
 __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict__ counts, int64_t cap,
                                                      uint64_t N_S, int32_t* __restrict__ cand_id,
                                                      const float* __restrict__ cand_m,
@@ -432,8 +457,44 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     __shared__ uint32_t wtot[4];
     const int t = blockIdx.x;
     const uint64_t cnt = counts[t];
-    if (cnt < N_S || cnt > (uint64_t)cap) {
+    if ((!FIXED && cnt < N_S) || cnt > (uint64_t)cap) {
         if (threadIdx.x == 0) { status[t] = 1; s_count[t] = 0; }
+        return;
+    }
+    if (FIXED) {
+        // condition 1 step s1 = N_S-th smallest entry step (none if fewer
+        // points ever enter); S1 = {e <= s1} compacted with its entry steps
+        const float* et = cand_m + (int64_t)t * cap;
+        float s1 = INFINITY;
+        if (cnt >= N_S) s1 = select_rank_f32([&](int64_t s) { return et[s]; }, (int64_t)cnt, N_S, sh);
+        int32_t* ids = cand_id + (int64_t)t * cap;
+        int32_t* ev = cand_ft + (int64_t)t * cap;
+        uint32_t out = 0;
+        for (int64_t c0 = 0; c0 < (int64_t)cnt; c0 += 256) {
+            const int64_t s = c0 + threadIdx.x;
+            bool mem = false;
+            int32_t id = 0;
+            float e = 0.f;
+            if (s < (int64_t)cnt) {
+                id = ids[s];
+                e = et[s];
+                mem = e <= s1;
+            }
+            uint32_t tot;
+            const uint32_t pre = block_flag_prefix(mem, wtot, &tot);
+            if (mem) {
+                ids[out + pre] = id;
+                ev[out + pre] = (int32_t)e;
+            }
+            out += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            status[t] = 0;
+            s_count[t] = out;
+            thr_out[t] = s1;
+            stop_out[t] = 0;
+        }
         return;
     }
     const float* lbt = cand_lb + (int64_t)t * cap * L;
@@ -567,7 +628,7 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     const int32_t* __restrict__ list, int64_t ld_list, const uint32_t* __restrict__ counts, int64_t use_max,
     int64_t all_n, int32_t* __restrict__ status, int want, int sv_check, int64_t sv_cap,
     uint64_t* __restrict__ ws, int64_t ld_ws, int k,
-    int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau)
+    int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau, int keys_only)
 {
     extern __shared__ unsigned char smem[];
     TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
@@ -582,12 +643,13 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
         }
     }
     if (use_max > 0 && m > use_max) m = use_max;
-    if (m < k) return;                 // cannot happen for S (|S| >= N_S >= k)
+    if (m < k && !keys_only) return;   // cannot happen for S (|S| >= N_S >= k)
     const int64_t q = q0 + t;
     for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
     __syncthreads();
     uint64_t* buf = ws + (int64_t)t * ld_ws;
     gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf);
+    if (keys_only) return;
     topk_u64(buf, m, k, sh);
     if (tau) {
         if (threadIdx.x == 0) tau[t] = __uint_as_float((uint32_t)(sh.out[k - 1] >> 32));
@@ -846,6 +908,111 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// end of the printed radius ladder (FIXED r_min)
+// ---------------------------------------------------------------------------
+
+// Inputs per query: S1 = {e <= s1} (ids, entry steps e, exact squared
+// distances as 64-bit keys, all aligned).  Condition 2 of round t holds when
+// #{o : e(o) <= (t+1)L and d^2(o) <= (c r_t)^2} >= k; a point counts from round
+// max(t_e, t_d) on (t_e = (e-1)/L, t_d = first t with (c r_t)^2 >= d^2), so one
+// histogram over that round gives every round's count.  The stop step is
+// s* = min(s1, s2); S = {e <= s*}; its top-k by (distance, id) is the result.
+// No stop within T rounds marks the query status 3 (answered over D).
+__global__ __launch_bounds__(256) void fixed_finish_kernel(
+    uint32_t* __restrict__ s_count, int32_t* __restrict__ cand_id, int32_t* __restrict__ cand_e, int64_t cap,
+    const float* __restrict__ s1v, uint64_t* __restrict__ ws, const float* __restrict__ rad2,
+    const float* __restrict__ c2, int T, int L, int k, int64_t q0, int32_t* __restrict__ status,
+    int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ thr_out,
+    int32_t* __restrict__ stop_out, int32_t* __restrict__ rounds_out)
+{
+    __shared__ TopkShared sh;
+    __shared__ uint32_t hist[64];
+    __shared__ float sc2[64];
+    __shared__ int sstar;
+    __shared__ uint32_t wtot[4];
+    const int t = blockIdx.x;
+    if (status[t] != 0) return;
+    const int64_t m = s_count[t];
+    int32_t* ids = cand_id + (int64_t)t * cap;
+    int32_t* ev = cand_e + (int64_t)t * cap;
+    uint64_t* buf = ws + (int64_t)t * cap;
+    if (threadIdx.x < 64) {
+        hist[threadIdx.x] = 0;
+        sc2[threadIdx.x] = (threadIdx.x < T) ? c2[threadIdx.x] : INFINITY;
+    }
+    __syncthreads();
+    for (int64_t s = threadIdx.x; s < m; s += 256) {
+        const int e = ev[s];
+        const float d2 = __uint_as_float((uint32_t)(buf[s] >> 32));
+        int td = 0;                                   // first round with (c r_t)^2 >= d^2
+        for (int st = 32; st > 0; st >>= 1)
+            if (td + st <= T && sc2[td + st - 1] < d2) td += st;
+        const int te = (e - 1) / L;
+        const int tau = te > td ? te : td;
+        if (tau < T) atomicAdd(&hist[tau], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float s1 = s1v[t];
+        long long best = (s1 < INFINITY) ? (long long)s1 : -1;
+        uint32_t cum = 0;
+        for (int r = 0; r < T; ++r) {
+            cum += hist[r];
+            if (cum >= (uint32_t)k) {
+                const long long s2 = (long long)(r + 1) * L;
+                if (best < 0 || s2 < best) best = s2;
+                break;
+            }
+        }
+        sstar = (int)best;
+    }
+    __syncthreads();
+    const int ss = sstar;
+    if (ss < 0) {
+        if (threadIdx.x == 0) status[t] = 3;
+        return;
+    }
+    // S = {e <= s*}: compact ids, first trees and keys in place
+    uint32_t out = 0;
+    for (int64_t c0 = 0; c0 < m; c0 += 256) {
+        const int64_t s = c0 + threadIdx.x;
+        bool mem = false;
+        int32_t id = 0, e = 0;
+        uint64_t key = 0;
+        if (s < m) {
+            id = ids[s];
+            e = ev[s];
+            key = buf[s];
+            mem = e <= ss;
+        }
+        uint32_t tot;
+        const uint32_t pre = block_flag_prefix(mem, wtot, &tot);
+        if (mem) {
+            ids[out + pre] = id;
+            ev[out + pre] = (e - 1) % L + 1;
+            buf[out + pre] = key;
+        }
+        out += tot;
+        __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    topk_u64(buf, out, k, sh);
+    const int64_t q = q0 + t;
+    for (int j = threadIdx.x; j < k; j += 256) {
+        const uint64_t key = sh.out[j];
+        out_ids[q * k + j] = (int64_t)(uint32_t)(key & 0xffffffffu);
+        out_d[q * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+    }
+    if (threadIdx.x == 0) {
+        s_count[t] = out;
+        thr_out[t] = rad2[(ss - 1) / L];
+        stop_out[t] = (ss - 1) % L + 1;
+        rounds_out[t] = (ss - 1) / L + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over (L, K)
 // ---------------------------------------------------------------------------
 
@@ -857,8 +1024,8 @@ hipError_t launch_guess_lk(const QueryArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int L, int K>
-hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
+template <int L, int K, bool FIXED>
+hipError_t launch_filter_lkf(const QueryArgs& a, hipStream_t st) {
     const int64_t pb = (a.n + 255) / 256;
     // about 64 queries per workgroup (measured best at n = 10^6, d = 128:
     // shorter blocks balance better), and enough blocks to fill the machine
@@ -866,11 +1033,18 @@ hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
     while (pb * ny < 4096 && ny < a.nqc) ny *= 2;
     if (ny > a.nqc) ny = a.nqc;
     const int qpb = (a.nqc + ny - 1) / ny;
-    hipLaunchKernelGGL((filter_kernel<L, K>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E, a.N_r,
-                       a.codes, a.n, a.Qp, a.q0, a.nqc, qpb, a.gthr, a.counts, a.cap, a.cand_id, a.cand_m,
-                       a.cand_lb, a.bm, a.W);
+    hipLaunchKernelGGL((filter_kernel<L, K, FIXED>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
+                       a.N_r, a.codes, a.n, a.Qp, a.q0, a.nqc, qpb, a.gthr, a.counts, a.cap, a.cand_id, a.cand_m,
+                       a.cand_lb, a.bm, a.W, a.rad2, a.T);
     return hipGetLastError();
 }
+
+template <int L, int K>
+hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
+    if (a.fixed) return launch_filter_lkf<L, K, true>(a, st);
+    return launch_filter_lkf<L, K, false>(a, st);
+}
+
 
 #define DL_LK_DISPATCH(FN)                                        \
     switch (a.L * 100 + a.K) {                                    \
@@ -892,7 +1066,12 @@ hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
 
 template <int L>
 hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((select_kernel<L>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
+    if (a.fixed) {
+        hipLaunchKernelGGL((select_kernel<L, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
+                           a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((select_kernel<L, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
                        a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W);
     return hipGetLastError();
 }
@@ -927,18 +1106,21 @@ hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
 
 template <bool AL>
 hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
-                            int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st) {
+                            int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
+                            int keys_only = 0) {
     const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
     hipLaunchKernelGGL((gather_topk_kernel<AL>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
                        counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
-                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau);
+                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only);
     return hipGetLastError();
 }
 
 hipError_t launch_gather(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
-                         int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st) {
-    if (a.d % 4 == 0) return launch_gather_al<true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st);
-    return launch_gather_al<false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st);
+                         int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
+                         int keys_only = 0) {
+    if (a.d % 4 == 0)
+        return launch_gather_al<true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only);
+    return launch_gather_al<false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only);
 }
 
 // Gathered verification of the whole of S (or D) for queries with status `want`.
@@ -998,6 +1180,16 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
 // list that overflowed or holds fewer than k entries marks the query status 2.
 hipError_t dl_launch_final(const QueryArgs& a, hipStream_t st) {
     return launch_gather(a, a.sv, a.cap_sv, a.svc, 0, 0, 1, a.k, nullptr, st);
+}
+
+// FIXED r_min: exact distances of S1, then the finishing kernel.
+hipError_t dl_launch_fixed_finish(const QueryArgs& a, int32_t* rounds, hipStream_t st) {
+    hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, 0, 0, 0, a.k, nullptr, st, 1);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fixed_finish_kernel, dim3(a.nqc), dim3(256), 0, st, a.s_count, a.cand_id, a.cand_ft, a.cap,
+                       a.thr, a.ws, a.rad2, a.c2, a.T, a.L, a.k, a.q0, a.status, a.out_ids, a.out_d, a.thr, a.stop,
+                       rounds);
+    return hipGetLastError();
 }
 
 size_t dl_verify_smem(int d) { return sizeof(TopkShared) + (size_t)d * 4 + 64; }

@@ -316,3 +316,70 @@ def test_bf16_rerank_form(dl, n, d, k):
         assert np.all(np.diff(b_d[qi]) >= 0)
     with pytest.raises(dl.DetlshError, match="keep_bf16"):
         dl.build_index(c["X"][:5000], 4, 16, 256, 0.1).query(Q[:2], k, 1.5, 0.1, precision=dl.BF16_RERANK)
+
+
+# --------------------------------------------------------------------------
+# the printed radius ladder from a given r_min (Alg. 7), both stop conditions
+# --------------------------------------------------------------------------
+
+def _ladder_borderline(lb, eps, r_min, c, rounds, rel=1e-5):
+    """Points whose bound lies within rel of one of the ladder's radii."""
+    r = r_min
+    out = set()
+    for _ in range(rounds):
+        rad2 = (eps * r) ** 2
+        near = np.abs(lb - rad2) <= rel * rad2
+        out |= set(np.flatnonzero(near.any(axis=1)).tolist())
+        r *= c
+    return out
+
+
+@pytest.mark.parametrize("c,div,beta,k,kind", [(1.5, 40.0, 0.1, 10, "mixture"), (2.0, 40.0, 0.1, 10, "integer"),
+                                                (1.5, 5.0, 0.05, 25, "mixture"), (1.5, 40.0, 0.99, 5, "mixture")])
+def test_fixed_ladder_fed_oracle_encoding(dl, c, div, beta, k, kind):
+    say(f"fixed ladder c={c} r_min=r*/{div} beta={beta} k={k} kind={kind}")
+    cc = U.case(n=6000, d=48, N_r=64, frac=0.1, kind=kind, nq=10, seed=61)
+    P, B, codes = U.oracle_encoding(cc)
+    B32 = B.astype(np.float32)
+    idx = dl.import_index(cc["X"], cc["A"], B32, codes, 4, 16, 64)
+    Qp32 = O.project(cc["Q"], cc["A"]).astype(np.float32)
+    eps = O.epsilon(4, 16)
+    stops = {1: 0, 2: 0}
+    for qi in range(len(cc["Q"])):
+        qp = Qp32[qi].astype(np.float64)
+        mg = O.query_magic(cc["X"], cc["Q"][qi], qp, codes, B32.astype(np.float64), 4, 16, k, min(beta, 0.5))
+        r_min = float(np.sqrt(max(mg.thr, 1e-12)) / eps / div)
+        ref = O.query_fixed(cc["X"], cc["Q"][qi], qp, codes, B32.astype(np.float64), 4, 16, k, beta, c, r_min, eps)
+        r = idx.query_debug(t(cc["Q"][qi:qi + 1]), k, c, beta, Qp=t(Qp32[qi:qi + 1]), rmin_policy=dl.RMIN_FIXED,
+                            r_min=r_min, max_rounds=64)
+        S = set(r["cand"][0, :int(r["counts"][0])].cpu().numpy().tolist())
+        if S != set(ref.S.tolist()):
+            lb = O.lower_bounds(qp, codes, B32.astype(np.float64), 4, 16)
+            assert S ^ set(ref.S.tolist()) <= _ladder_borderline(lb, eps, r_min, c, ref.rounds + 1)
+            continue
+        assert int(r["rounds"][0]) == ref.rounds and int(r["stop_tree"][0]) == ref.stop_tree
+        assert float(r["thr"][0]) == pytest.approx(ref.thr, rel=1e-6)
+        ft = dict(zip(r["cand"][0, :len(S)].cpu().numpy().tolist(), r["first_tree"][0, :len(S)].cpu().numpy().tolist()))
+        assert all(ft[o] == f for o, f in zip(ref.S.tolist(), ref.first_tree.tolist()))
+        U.compare_result(ref.ids, ref.dists, cc["X"], cc["Q"][qi], r["ids"][0].cpu().numpy(),
+                         r["dists"][0].cpu().numpy(), ref.S, k)
+        stops[ref.stop_cond] += 1
+        if div >= 40:
+            assert ref.rounds >= 2
+    say(f"  stops by condition 1 / 2: {stops}")
+    if beta > 0.9:
+        assert stops[2] > 0
+
+
+def test_fixed_ladder_without_stop_is_answered_over_D(dl):
+    """One round from a tiny radius admits nothing: the query is answered over
+    all points (exact k-NN)."""
+    say("fixed ladder, no stop within max_rounds")
+    cc = U.case(n=3000, d=32, N_r=16, frac=0.1, kind="integer", nq=4, seed=62)
+    idx = dl.build_index(cc["X"], 4, 16, 16, 0.1, A=cc["A"], sample_ids=cc["sample"])
+    ids, dists = idx.query(t(cc["Q"]), 7, 1.5, 0.1, rmin_policy=dl.RMIN_FIXED, r_min=1e-6, max_rounds=1)
+    for qi in range(4):
+        ref_ids, _ = O.brute_force_knn(cc["X"], cc["Q"][qi], 7)
+        assert np.array_equal(ids[qi].cpu().numpy(), ref_ids)
+    with pytest.raises(dl.DetlshError, match="r_min"):
+        idx.query(t(cc["Q"]), 7, 1.5, 0.1, rmin_policy=dl.RMIN_FIXED, r_min=0.0)
