@@ -27,7 +27,9 @@
  *  - Matrices are row-major and densely packed unless stated otherwise.
  *  - An index is read-only after it is built: any number of threads may call
  *    detlsh_query on it concurrently, each with its own stream; every call
- *    allocates its own workspace.  detlsh_free must not race with queries.
+ *    allocates its own workspace (a server, below, allocates once instead).
+ *    detlsh_free must not race with queries, and every server on the index
+ *    must be destroyed first.
  */
 #ifndef DETLSH_H
 #define DETLSH_H
@@ -233,6 +235,84 @@ detlsh_status detlsh_query_debug(detlsh_index idx, const float* Qp, const float*
                                  int32_t* first_tree, float* thr, int32_t* stop_tree,
                                  int32_t* rounds, int64_t* out_ids, float* out_dists,
                                  void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* serving: continuous batching over a fixed device workspace               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A server answers many independent query requests (each an Alg. 7 query of
+ * nq rows, as detlsh_query) on one index without allocating device memory per
+ * request.  It owns `slots` worker threads, each with its own HIP stream of
+ * default priority and an equal share of one workspace of workspace_bytes
+ * allocated at creation.  Requests are taken in arrival order; when a slot
+ * becomes free it forms a batch from the oldest waiting request and appends
+ * the waiting queries of later requests with the same (k, c, beta, options),
+ * up to max_batch queries or as many as its workspace holds (continuous
+ * batching).  A request larger than that is served in pieces, possibly on
+ * several slots at once.  Every query's result is independent of the batch it
+ * ran in: a request returns bit-identical ids and distances alone or in a mix.
+ *
+ * detlsh_server_create: slots in [1, 16] (0 -> 2), max_batch in [1, 65535]
+ *   (0 -> 1024), workspace_bytes >= 1 MiB.  ENOMEM if the workspace cannot be
+ *   allocated.  The index must outlive the server.
+ */
+typedef struct detlsh_server_s* detlsh_server;
+
+detlsh_status detlsh_server_create(detlsh_index idx, size_t workspace_bytes, int32_t slots,
+                                   int32_t max_batch, detlsh_server* out);
+
+/*
+ * Queue a request.  Q (device, nq x d FP32), out_ids (device, nq x k int64)
+ * and out_dists (device, nq x k FP32) must stay valid until detlsh_server_wait
+ * has returned something other than DETLSH_EBUSY for the ticket.  The server
+ * reads Q on its own streams: the work that writes Q must be complete when
+ * submit is called, and the outputs are complete when wait returns DETLSH_OK.  opts is
+ * copied (NULL -> FP32, MAGIC; its workspace_bytes is ignored).  Arguments are
+ * checked here as detlsh_query checks them: an invalid request gets
+ * DETLSH_EINVAL and no ticket, a request of which not one query fits a slot's
+ * workspace gets DETLSH_ENOMEM; neither affects other requests.  nq == 0 is
+ * accepted and completes at once.  *ticket identifies the request.
+ */
+detlsh_status detlsh_server_submit(detlsh_server srv, const float* Q, int64_t nq, int32_t k,
+                                   double c, double beta, const detlsh_query_opts* opts,
+                                   int64_t* out_ids, float* out_dists, uint64_t* ticket);
+
+typedef struct {
+    double t_submit;            /* CLOCK_MONOTONIC seconds: accepted by submit     */
+    double t_start;             /* its first queries began on a slot               */
+    double t_end;               /* its last results were complete in HBM           */
+    int32_t batches;            /* batches that served its queries                 */
+    int32_t max_batch_requests; /* most requests sharing one of those batches      */
+    int64_t max_batch_queries;  /* most queries in one of those batches            */
+} detlsh_request_info;
+
+/*
+ * Wait up to timeout_us microseconds (< 0: no limit, 0: poll) for a request.
+ * Returns DETLSH_EBUSY if it is still running (the ticket stays valid);
+ * otherwise the request's own status (DETLSH_OK, DETLSH_ECANCELED, or the
+ * error of the batch that failed it, with its message in detlsh_last_error),
+ * fills *info when info is not NULL, and releases the ticket.  DETLSH_EINVAL
+ * for an unknown ticket.
+ */
+detlsh_status detlsh_server_wait(detlsh_server srv, uint64_t ticket, int64_t timeout_us,
+                                 detlsh_request_info* info);
+
+/*
+ * Cancel a request: queries not yet started are dropped, queries already on a
+ * slot finish, and the request then reports DETLSH_ECANCELED (its outputs
+ * partly written).  DETLSH_OK if the cancellation took effect, DETLSH_EBUSY if
+ * the request had already finished (wait reports its own status),
+ * DETLSH_EINVAL for an unknown ticket.
+ */
+detlsh_status detlsh_server_cancel(detlsh_server srv, uint64_t ticket);
+
+/*
+ * Stop the server: requests not yet started are cancelled, running batches
+ * finish, the threads are joined and the workspace freed.  Tickets not waited
+ * for are discarded.  Must not race with other calls on the same server.
+ */
+void detlsh_server_destroy(detlsh_server srv);
 
 /* ------------------------------------------------------------------------ */
 /* kernel timing                                                            */

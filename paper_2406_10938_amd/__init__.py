@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import BF16_RERANK, FP32, RMIN_FIXED, RMIN_MAGIC, DetlshError, check, lib
 
-__all__ = ["build_index", "import_index", "Index", "DetlshError", "FP32", "BF16_RERANK", "RMIN_MAGIC",
+__all__ = ["build_index", "import_index", "Index", "Server", "DetlshError", "FP32", "BF16_RERANK", "RMIN_MAGIC",
            "RMIN_FIXED", "profile_enable", "profile_read"]
 
 
@@ -169,6 +169,71 @@ class Index:
                                        start.ctypes.data_as(C.c_void_p), lo.ctypes.data_as(C.c_void_p),
                                        hi.ctypes.data_as(C.c_void_p), max(nl, 1)))
         return perm, start, lo[:nl], hi[:nl]
+
+
+class Server:
+    """Continuous-batching query server over one index (detlsh_server_* in the C ABI).
+
+    submit() returns a ticket at once; wait(ticket) returns (ids, dists, info)
+    when the request's results are complete.  The server allocates its device
+    workspace once, at construction.
+    """
+
+    def __init__(self, index: Index, workspace_bytes: int, slots: int = 2, max_batch: int = 1024):
+        self._index = index   # the index must outlive the server
+        h = C.c_void_p()
+        check(lib().detlsh_server_create(index._h, int(workspace_bytes), int(slots), int(max_batch), C.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().detlsh_server_destroy(self._h)
+            self._h = None
+            self._live = {}
+
+    def submit(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC, r_min=0.0,
+               max_rounds=0, verify="auto", sync=True) -> int:
+        """Queue Q (nq x d) for k-ANN; the server reads Q on its own streams, so
+        with sync=True the current stream is synchronised first."""
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        nq = Q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, 0, verify)
+        t = C.c_uint64()
+        check(lib().detlsh_server_submit(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
+                                         _ptr(dists), C.byref(t)))
+        self._live[t.value] = (Q, ids, dists)
+        return t.value
+
+    def wait(self, ticket, timeout=None):
+        """(ids, dists, info) of a finished request; None if `timeout` seconds
+        passed first.  Raises DetlshError with the request's status on failure."""
+        us = -1 if timeout is None else int(timeout * 1e6)
+        inf = _lib.RequestInfo()
+        st = lib().detlsh_server_wait(self._h, int(ticket), us, C.byref(inf))
+        if st == _lib.EBUSY:
+            return None
+        bufs = self._live.pop(int(ticket), None)
+        check(st)
+        info = {"t_submit": inf.t_submit, "t_start": inf.t_start, "t_end": inf.t_end, "batches": inf.batches,
+                "max_batch_requests": inf.max_batch_requests, "max_batch_queries": inf.max_batch_queries}
+        return bufs[1], bufs[2], info
+
+    def cancel(self, ticket) -> bool:
+        """True if the cancellation took effect, False if the request had finished."""
+        st = lib().detlsh_server_cancel(self._h, int(ticket))
+        if st == _lib.EBUSY:
+            return False
+        check(st)
+        return True
 
 
 def build_index(X, L=4, K=16, N_r=256, sample_frac=0.01, A=None, sample_ids=None, seed=0, max_leaf=256,

@@ -54,6 +54,17 @@ class Info(C.Structure):
     ]
 
 
+class RequestInfo(C.Structure):
+    _fields_ = [
+        ("t_submit", C.c_double),
+        ("t_start", C.c_double),
+        ("t_end", C.c_double),
+        ("batches", C.c_int32),
+        ("max_batch_requests", C.c_int32),
+        ("max_batch_queries", C.c_int64),
+    ]
+
+
 # name -> (restype, argtypes); every symbol here is declared in include/detlsh.h
 P = C.c_void_p
 SIGNATURES = {
@@ -72,6 +83,12 @@ SIGNATURES = {
     "detlsh_profile_enable": (C.c_int, [C.c_int32, C.c_int32]),
     "detlsh_profile_read": (C.c_int, [C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.c_int32, C.POINTER(C.c_int32)]),
+    "detlsh_server_create": (C.c_int, [P, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(P)]),
+    "detlsh_server_submit": (C.c_int, [P, P, C.c_int64, C.c_int32, C.c_double, C.c_double, C.POINTER(QueryOpts),
+                                       P, P, C.POINTER(C.c_uint64)]),
+    "detlsh_server_wait": (C.c_int, [P, C.c_uint64, C.c_int64, C.POINTER(RequestInfo)]),
+    "detlsh_server_cancel": (C.c_int, [P, C.c_uint64]),
+    "detlsh_server_destroy": (None, [P]),
     "detlsh_free": (None, [P]),
     "detlsh_last_error": (C.c_char_p, []),
 }

@@ -15,6 +15,7 @@
 #include <unordered_set>
 #include <vector>
 
+#include "api_internal.h"
 #include "internal.h"
 
 // ---------------------------------------------------------------------------
@@ -577,19 +578,44 @@ size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d)
 
 // Runs queries [q0, q0+nq) through the pipeline with the given plan.  When
 // `force_all_candidates`, every point is a candidate (threshold +inf).
+// Device memory handed to the query path.  With p == NULL the path allocates
+// up to `bytes` itself; otherwise it works inside [p, p + bytes) and allocates
+// nothing.
+struct Arena {
+    char* p = nullptr;
+    size_t bytes = 0;
+    char* take(size_t b) {
+        const size_t a = (b + 255) & ~(size_t)255;
+        if (a > bytes) return nullptr;
+        char* r = p;
+        p += a;
+        bytes -= a;
+        return r;
+    }
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, int64_t q0, int64_t nq, int k,
-                          const QueryPlan& plan, bool force_all_candidates, size_t budget, int64_t* out_ids,
+                          const QueryPlan& plan, bool force_all_candidates, const Arena& arena, int64_t* out_ids,
                           float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
     const int64_t cap = (force_all_candidates || plan.fixed) ? ix->n : plan.cap;
     const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d);
-    int64_t nqc = (int64_t)(budget / pq);
-    if (nqc < 1) nqc = 1;
+    int64_t nqc = (int64_t)(arena.bytes / pq);
+    if (nqc < 1) {
+        if (arena.p)
+            return fail(DETLSH_ENOMEM, "workspace of %zu bytes holds no query (%zu bytes each)", arena.bytes, pq);
+        nqc = 1;
+    }
     if (nqc > nq) nqc = nq;
     if (nqc > 65535) nqc = 65535;
-    DevBuf ws;
-    if (ws.alloc(pq * (size_t)nqc) != hipSuccess)
-        return fail(DETLSH_ENOMEM, "query workspace of %zu bytes", pq * (size_t)nqc);
-    char* p = ws.as<char>();
+    DevBuf own;
+    char* p = arena.p;
+    if (!p) {
+        if (own.alloc(pq * (size_t)nqc) != hipSuccess)
+            return fail(DETLSH_ENOMEM, "query workspace of %zu bytes", pq * (size_t)nqc);
+        p = own.as<char>();
+    }
     auto take = [&](size_t b) { char* r = p; p += (b + 255) & ~(size_t)255; return r; };
     QueryArgs a;
     a.L = ix->L; a.K = ix->K; a.N_r = ix->N_r; a.d = ix->d; a.n = ix->n;
@@ -730,106 +756,204 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     return DETLSH_OK;
 }
 
-detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, int64_t nq, int32_t k, double c,
-                         double beta, const detlsh_query_opts* opts, int64_t* out_ids, float* out_d,
-                         const Debug& dbg, hipStream_t st) {
-    g_err.clear();
+// Scalar checks of a query call and its plan (no device pointers touched).
+struct QuerySetup {
+    int precision = DETLSH_FP32;
+    int policy = DETLSH_RMIN_MAGIC;
+    int verify = 0;
+    int rmult = 4;
+    int rounds = 64;
+    QueryPlan plan;
+    std::vector<float> ladder;   // FIXED: (eps r_t)^2 then (c r_t)^2, t < rounds
+};
+
+detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, double c, double beta,
+                          const detlsh_query_opts* opts, QuerySetup& s) {
     if (!ix) return fail(DETLSH_EINVAL, "NULL index");
     if (nq < 0) return fail(DETLSH_EINVAL, "nq < 0");
     if (k < 1 || (int64_t)k > ix->n || k > 1024)
         return fail(DETLSH_EINVAL, "k must be in [1, min(n, 1024)], got %d", k);
     if (!(c > 1.0)) return fail(DETLSH_EINVAL, "c must be > 1, got %g", c);
     if (!(beta >= 0.0 && beta <= 1.0)) return fail(DETLSH_EINVAL, "beta must be in [0, 1], got %g", beta);
-    const int precision = opts ? opts->precision : DETLSH_FP32;
-    const int policy = opts ? opts->rmin_policy : DETLSH_RMIN_MAGIC;
-    const int verify = opts ? opts->verify : 0;
-    const int rmult = (opts && opts->rerank_mult > 0) ? opts->rerank_mult : 4;
-    if (precision != DETLSH_FP32 && precision != DETLSH_BF16_RERANK)
-        return fail(DETLSH_EINVAL, "precision %d is not defined", precision);
-    if (precision == DETLSH_BF16_RERANK && !ix->Xbf.p)
+    s.precision = opts ? opts->precision : DETLSH_FP32;
+    s.policy = opts ? opts->rmin_policy : DETLSH_RMIN_MAGIC;
+    s.verify = opts ? opts->verify : 0;
+    s.rmult = (opts && opts->rerank_mult > 0) ? opts->rerank_mult : 4;
+    if (s.precision != DETLSH_FP32 && s.precision != DETLSH_BF16_RERANK)
+        return fail(DETLSH_EINVAL, "precision %d is not defined", s.precision);
+    if (s.precision == DETLSH_BF16_RERANK && !ix->Xbf.p)
         return fail(DETLSH_EINVAL, "the BF16 form needs an index built with keep_bf16");
-    if (precision == DETLSH_BF16_RERANK && (int64_t)rmult * k > 1024)
-        return fail(DETLSH_EINVAL, "rerank_mult*k = %lld exceeds 1024", (long long)rmult * k);
-    if (verify < 0 || verify > 2) return fail(DETLSH_EINVAL, "verify mode %d is not defined", verify);
-    if (policy != DETLSH_RMIN_MAGIC && policy != DETLSH_RMIN_FIXED)
-        return fail(DETLSH_EINVAL, "r_min policy %d is not defined", policy);
-    const int rounds = (opts && opts->max_rounds > 0) ? opts->max_rounds : 64;
-    if (policy == DETLSH_RMIN_FIXED) {
+    if (s.precision == DETLSH_BF16_RERANK && (int64_t)s.rmult * k > 1024)
+        return fail(DETLSH_EINVAL, "rerank_mult*k = %lld exceeds 1024", (long long)s.rmult * k);
+    if (s.verify < 0 || s.verify > 2) return fail(DETLSH_EINVAL, "verify mode %d is not defined", s.verify);
+    if (s.policy != DETLSH_RMIN_MAGIC && s.policy != DETLSH_RMIN_FIXED)
+        return fail(DETLSH_EINVAL, "r_min policy %d is not defined", s.policy);
+    s.rounds = (opts && opts->max_rounds > 0) ? opts->max_rounds : 64;
+    if (s.policy == DETLSH_RMIN_FIXED) {
         if (!(opts && opts->r_min > 0.0)) return fail(DETLSH_EINVAL, "FIXED r_min needs r_min > 0");
-        if (rounds > 64) return fail(DETLSH_EINVAL, "max_rounds must be <= 64, got %d", rounds);
+        if (s.rounds > 64) return fail(DETLSH_EINVAL, "max_rounds must be <= 64, got %d", s.rounds);
     }
+    QueryPlan& plan = s.plan;
+    plan = plan_query(ix->n, k, beta, ix->L);
+    if (s.policy == DETLSH_RMIN_FIXED) {
+        // radii r_t = r_min c^t (formed by repeated multiplication), squared
+        // projected radius (eps r_t)^2 and squared verification radius (c r_t)^2
+        const double eps = std::sqrt(chi2_upper_quantile_even(std::exp(-1.0 / ix->L), ix->K));
+        s.ladder.assign(2 * (size_t)s.rounds, 0.f);
+        double r = opts->r_min;
+        for (int t = 0; t < s.rounds; ++t) {
+            s.ladder[t] = (float)((eps * r) * (eps * r));
+            s.ladder[s.rounds + t] = (float)((c * r) * (c * r));
+            r *= c;
+        }
+        plan.fixed = true;
+        plan.all = false;
+        plan.rounds = s.rounds;
+        plan.cap = ix->n;
+    }
+    const bool bf16 = s.precision == DETLSH_BF16_RERANK;
+    plan.dense = !plan.all && !plan.fixed && (s.verify == 2 || (s.verify == 0 && (ix->n >= 65536 || bf16)));
+    plan.bf16 = bf16 && plan.dense;
+    plan.kprime = (int)std::min<uint64_t>(plan.N_S, (uint64_t)(bf16 ? s.rmult * k : k));
+    plan.T = std::max<int64_t>(2048, 32 * (int64_t)plan.kprime);
+    plan.cap_sv = std::max<int64_t>(32768, 64 * (int64_t)plan.kprime);
+    return DETLSH_OK;
+}
+
+// Plans of the two per-query fallbacks: S = D when the ladder never stops
+// (status 3), every point a candidate when |S| left [N_S, cap] (status 1).
+QueryPlan all_points_plan(const QueryPlan& plan, int64_t n) {
+    QueryPlan a = plan;
+    a.all = true;
+    a.fixed = false;
+    a.dense = false;
+    a.cap = n;
+    return a;
+}
+
+// Bytes of arena that query_impl needs for nq queries in one pass (plus one
+// query of either fallback).
+size_t query_arena_bytes(const detlsh_index_s* ix, const QuerySetup& s, int64_t nq, bool with_qp) {
+    const QueryPlan& plan = s.plan;
+    const int64_t cap = plan.fixed ? ix->n : plan.cap;
+    size_t run = per_query_bytes(cap, ix->L, plan, ix->n, ix->d) * (size_t)nq;
+    const size_t fb = std::max(per_query_bytes(ix->n, ix->L, plan, ix->n, ix->d),
+                               per_query_bytes(ix->n, ix->L, all_points_plan(plan, ix->n), ix->n, ix->d));
+    size_t b = std::max(run, fb);
+    if (with_qp) b += align256((size_t)nq * ix->LK * 4);
+    if (!s.ladder.empty()) b += align256(s.ladder.size() * 4);
+    return b;
+}
+
+detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, int64_t nq, int32_t k, double c,
+                         double beta, const detlsh_query_opts* opts, int64_t* out_ids, float* out_d,
+                         const Debug& dbg, const Arena* ext, hipStream_t st) {
+    g_err.clear();
+    QuerySetup s;
+    if (detlsh_status e = setup_query(ix, nq, k, c, beta, opts, s)) return e;
     if (nq == 0) return DETLSH_OK;
     if (!is_device_ptr(Q)) return fail(DETLSH_EINVAL, "Q must be a device pointer");
     if (!is_device_ptr(out_ids) || !is_device_ptr(out_d)) return fail(DETLSH_EINVAL, "outputs must be device pointers");
     if (Qp_in && !is_device_ptr(Qp_in)) return fail(DETLSH_EINVAL, "Qp must be a device pointer");
     HCHECK(hipSetDevice(ix->device));
-    const size_t budget = (opts && opts->workspace_bytes) ? opts->workspace_bytes : ((size_t)4 << 30);
+    QueryPlan& plan = s.plan;
 
-    DevBuf qpbuf;
+    // query projections and the FIXED ladder come from the arena when one is
+    // given, else from allocations of this call
+    Arena arena;
+    if (ext) {
+        arena = *ext;
+    } else {
+        arena.bytes = (opts && opts->workspace_bytes) ? opts->workspace_bytes : ((size_t)4 << 30);
+    }
+    DevBuf qpbuf, ladder;
     const float* Qp = Qp_in;
     if (!Qp) {
-        HCHECK(qpbuf.alloc((size_t)nq * ix->LK * 4));
+        float* qp = nullptr;
+        if (ext) {
+            qp = reinterpret_cast<float*>(arena.take((size_t)nq * ix->LK * 4));
+            if (!qp) return fail(DETLSH_ENOMEM, "workspace too small for %lld query projections", (long long)nq);
+        } else {
+            HCHECK(qpbuf.alloc((size_t)nq * ix->LK * 4));
+            qp = qpbuf.as<float>();
+        }
         ProjectArgs pa;
-        pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK; pa.Pout = qpbuf.as<float>();
+        pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK; pa.Pout = qp;
         DlTimer tm(T_QPROJECT, st);
         HCHECK(dl_launch_project(pa, PROJ_ROWMAJOR, st));
-        Qp = qpbuf.as<float>();
+        Qp = qp;
     }
-    QueryPlan plan = plan_query(ix->n, k, beta, ix->L);
-    DevBuf ladder;
-    if (policy == DETLSH_RMIN_FIXED) {
-        // radii r_t = r_min c^t (formed by repeated multiplication), squared
-        // projected radius (eps r_t)^2 and squared verification radius (c r_t)^2
-        const double eps = std::sqrt(chi2_upper_quantile_even(std::exp(-1.0 / ix->L), ix->K));
-        std::vector<float> tab(2 * (size_t)rounds);
-        double r = opts->r_min;
-        for (int t = 0; t < rounds; ++t) {
-            tab[t] = (float)((eps * r) * (eps * r));
-            tab[rounds + t] = (float)((c * r) * (c * r));
-            r *= c;
+    if (plan.fixed) {
+        float* lad = nullptr;
+        if (ext) {
+            lad = reinterpret_cast<float*>(arena.take(s.ladder.size() * 4));
+            if (!lad) return fail(DETLSH_ENOMEM, "workspace too small for the radius ladder");
+        } else {
+            HCHECK(ladder.alloc(s.ladder.size() * 4));
+            lad = ladder.as<float>();
         }
-        HCHECK(ladder.alloc(tab.size() * 4));
-        HCHECK(hipMemcpyAsync(ladder.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st));
+        HCHECK(hipMemcpyAsync(lad, s.ladder.data(), s.ladder.size() * 4, hipMemcpyHostToDevice, st));
         HCHECK(hipStreamSynchronize(st));
-        plan.fixed = true;
-        plan.all = false;
-        plan.rounds = rounds;
-        plan.rad2 = ladder.as<float>();
-        plan.c2 = ladder.as<float>() + rounds;
-        plan.cap = ix->n;
+        plan.rad2 = lad;
+        plan.c2 = lad + s.rounds;
     }
-    const bool bf16 = precision == DETLSH_BF16_RERANK;
-    plan.dense = !plan.all && !plan.fixed && (verify == 2 || (verify == 0 && (ix->n >= 65536 || bf16)));
-    plan.bf16 = bf16 && plan.dense;
-    plan.kprime = (int)std::min<uint64_t>(plan.N_S, (uint64_t)(bf16 ? rmult * k : k));
-    plan.T = std::max<int64_t>(2048, 32 * (int64_t)plan.kprime);
-    plan.cap_sv = std::max<int64_t>(32768, 64 * (int64_t)plan.kprime);
+    Arena run_arena = arena;
+    if (!ext) run_arena.p = nullptr;
     std::vector<int32_t> status((size_t)nq, 0);
-    detlsh_status s = run_queries(ix, Q, Qp, 0, nq, k, plan, false, budget, out_ids, out_d, dbg, status, st);
-    if (s) { prof_resolve(); return s; }
-    // queries whose candidate count missed [N_S, cap]: every point a candidate
-    QueryPlan all_plan = plan;
-    all_plan.all = true;
-    all_plan.fixed = false;
-    all_plan.dense = false;
-    all_plan.cap = ix->n;
+    detlsh_status e = run_queries(ix, Q, Qp, 0, nq, k, plan, false, run_arena, out_ids, out_d, dbg, status, st);
+    if (e) { prof_resolve(); return e; }
+    const QueryPlan all_plan = all_points_plan(plan, ix->n);
     for (int64_t q = 0; q < nq; ++q) {
         if (status[q] == 3) {
             std::vector<int32_t> st1(1, 0);
-            s = run_queries(ix, Q, Qp, q, 1, k, all_plan, false, budget, out_ids, out_d, dbg, st1, st);
-            if (s) { prof_resolve(); return s; }
+            e = run_queries(ix, Q, Qp, q, 1, k, all_plan, false, run_arena, out_ids, out_d, dbg, st1, st);
+            if (e) { prof_resolve(); return e; }
             continue;
         }
         if (status[q] != 1) continue;
         std::vector<int32_t> st1(1, 0);
-        s = run_queries(ix, Q, Qp, q, 1, k, plan, true, budget, out_ids, out_d, dbg, st1, st);
-        if (s) { prof_resolve(); return s; }
+        e = run_queries(ix, Q, Qp, q, 1, k, plan, true, run_arena, out_ids, out_d, dbg, st1, st);
+        if (e) { prof_resolve(); return e; }
         if (st1[0] == 1) { prof_resolve(); return fail(DETLSH_EINTERNAL, "query %lld: fallback failed", (long long)q); }
     }
     prof_resolve();
-    (void)c;
     return DETLSH_OK;
 }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// entry points for the serving loop (api_internal.h)
+// ---------------------------------------------------------------------------
+
+detlsh_status dl_error(detlsh_status s, const char* msg) { return fail(s, "%s", msg); }
+
+bool dl_is_device_ptr(const void* p) { return is_device_ptr(p); }
+
+int dl_index_device(detlsh_index ix) { return ix->device; }
+
+int32_t dl_index_dim(detlsh_index ix) { return ix->d; }
+
+detlsh_status dl_query_check(detlsh_index ix, int64_t nq, int32_t k, double c, double beta,
+                             const detlsh_query_opts* opts, size_t* bytes_one_pass) {
+    QuerySetup s;
+    if (detlsh_status e = setup_query(ix, nq, k, c, beta, opts, s)) return e;
+    if (bytes_one_pass) *bytes_one_pass = query_arena_bytes(ix, s, nq, true);
+    return DETLSH_OK;
+}
+
+detlsh_status dl_query_in_arena(detlsh_index ix, const float* Q, int64_t nq, int32_t k, double c, double beta,
+                                const detlsh_query_opts* opts, int64_t* out_ids, float* out_dists, void* arena,
+                                size_t arena_bytes, hipStream_t st) {
+    Debug dbg;
+    Arena a;
+    a.p = static_cast<char*>(arena);
+    a.bytes = arena_bytes;
+    if (!a.p) return fail(DETLSH_EINVAL, "NULL arena");
+    return query_impl(ix, nullptr, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, &a, st);
+}
+
+namespace {
 
 }  // namespace
 
@@ -838,7 +962,7 @@ extern "C" {
 detlsh_status detlsh_query(detlsh_index ix, const float* Q, int64_t nq, int32_t k, double c, double beta,
                            const detlsh_query_opts* opts, int64_t* out_ids, float* out_dists, void* stream) {
     Debug dbg;
-    return query_impl(ix, nullptr, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg,
+    return query_impl(ix, nullptr, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, nullptr,
                       static_cast<hipStream_t>(stream));
 }
 
@@ -853,7 +977,8 @@ detlsh_status detlsh_query_debug(detlsh_index ix, const float* Qp, const float* 
     for (const void* p : {(const void*)cand_ids, (const void*)cand_counts, (const void*)first_tree, (const void*)thr,
                           (const void*)stop_tree, (const void*)rounds})
         if (p && !is_device_ptr(p)) return fail(DETLSH_EINVAL, "debug outputs must be device pointers");
-    return query_impl(ix, Qp, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, static_cast<hipStream_t>(stream));
+    return query_impl(ix, Qp, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, nullptr,
+                      static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -43,6 +43,22 @@ def test_struct_layouts():
     assert ctypes.sizeof(_lib.BuildOpts) == 8 + 4 * 4 + 8 + 8
     assert ctypes.sizeof(_lib.QueryOpts) == 4 * 4 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_lib.Info) == 8 + 4 * 4 + 8 + 4 + 4 + 8 * 8 + 8
+    assert ctypes.sizeof(_lib.RequestInfo) == 3 * 8 + 4 + 4 + 8
+
+
+def test_server_rejects_null_handles_without_a_device():
+    """The serving entry points check their handles before any HIP call."""
+    from paper_2406_10938_amd import _lib
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+    assert L.detlsh_server_create(None, 1 << 30, 2, 64, ctypes.byref(out)) == _lib.EINVAL
+    assert out.value is None
+    assert b"NULL index" in L.detlsh_last_error()
+    t = ctypes.c_uint64(7)
+    assert L.detlsh_server_submit(None, None, 1, 10, 1.5, 0.1, None, None, None, ctypes.byref(t)) == _lib.EINVAL
+    assert L.detlsh_server_wait(None, 1, 0, None) == _lib.EINVAL
+    assert L.detlsh_server_cancel(None, 1) == _lib.EINVAL
+    L.detlsh_server_destroy(None)
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
