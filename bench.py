@@ -80,6 +80,103 @@ def cpu_baseline(X_host, Q_host, A, sample, cfg, k, beta, nq_total, n_queries):
             "build_s": t_build, "query_ms": t_q * 1e3}
 
 
+def serve_load(dl, torch, idx, Qpool, reqs, rate, form, workspace, slots, max_batch):
+    """Serve the request stream through a detlsh server.  rate = None submits
+    every request at once (closed-loop backlog: saturation); otherwise Poisson
+    arrivals at `rate` requests/s.  Latency of a request = completion of its
+    last result minus its scheduled arrival (submitter lag included)."""
+    import queue
+    import threading
+    srv = dl.Server(idx, workspace_bytes=workspace, slots=slots, max_batch=max_batch)
+    nreq = len(reqs["nq"])
+    prec = dl.BF16_RERANK if form == "bf16" else dl.FP32
+    tickets = queue.Queue()
+    results = [None] * nreq
+
+    def waiter():
+        for _ in range(nreq):
+            i, t, t_arr = tickets.get()
+            ids, d, info = srv.wait(t)
+            results[i] = (t_arr, info, ids)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    torch.cuda.synchronize()
+    t0 = time.monotonic() + 0.01
+    arrivals = t0 + (np.cumsum(reqs["gaps"]) / rate if rate else np.zeros(nreq))
+    for i in range(nreq):
+        if rate:
+            dt = arrivals[i] - time.monotonic()
+            if dt > 0:
+                time.sleep(dt)
+        q0, nq = int(reqs["q0"][i]), int(reqs["nq"][i])
+        t = srv.submit(Qpool[q0:q0 + nq], int(reqs["k"][i]), float(reqs["c"][i]), 0.1, precision=prec, sync=False)
+        tickets.put((i, t, float(arrivals[i]) if rate else time.monotonic()))
+    th.join()
+    srv.close()
+    lat = np.array([r[1]["t_end"] - r[0] for r in results])
+    t_first = min(r[0] for r in results)
+    t_last = max(r[1]["t_end"] for r in results)
+    nq_tot = int(reqs["nq"].sum())
+    return {"offered_req_s": rate, "requests": nreq, "queries": nq_tot,
+            "qps": nq_tot / (t_last - t_first), "req_s": nreq / (t_last - t_first),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_batch_queries": float(np.mean([r[1]["max_batch_queries"] for r in results])),
+            "mean_batch_requests": float(np.mean([r[1]["max_batch_requests"] for r in results]))}, results
+
+
+def serve_bench(dl, torch, nreq, loads=(0.5, 0.8, 1.1), slots=3, max_batch=512, pool=8192, log_prefix="[serve]"):
+    """Serving form on the resident 256-d mixture index (n = 1,000,000):
+    saturation by a closed-loop backlog, then Poisson arrivals at the given
+    fractions of it, for plain FP32 and BF16 + rerank."""
+    import synth
+    cfg = synth.config("C5")
+    dev = torch.device("cuda:0")
+    log(f"{log_prefix} generating the 256-d mixture: n={cfg.n}, query pool {pool}")
+    X = torch.from_numpy(synth.make_data(cfg)).to(dev)
+    Qpool = torch.from_numpy(synth.make_queries(cfg, nq=pool)).to(dev)
+    A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
+    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
+    tb = time.perf_counter()
+    idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
+    build_s = time.perf_counter() - tb
+    reqs = synth.request_stream(nreq, pool, cfg.arrival_seed)
+    log(f"{log_prefix} ground truth of the query pool")
+    kth = ground_truth_kth(X, Qpool, 10)
+    workspace = slots * (max_batch * 5_200_000 + (64 << 20))
+    out = {"workload": f"256-d Gaussian mixture n={cfg.n}, L=4 K=16 N_r=256, 1% sample, beta=0.1; "
+                       f"{nreq} requests, nq log-uniform 1..256, k in {{1,10,100}}, c in {{1.5,2.0}}",
+           "slots": slots, "max_batch": max_batch, "workspace_bytes": workspace, "build_s": build_s, "forms": {}}
+    for form in ("fp32", "bf16"):
+        warm = {key: v[:min(64, nreq)] for key, v in reqs.items()}
+        serve_load(dl, torch, idx, Qpool, warm, None, form, workspace, slots, max_batch)
+        sat, res = serve_load(dl, torch, idx, Qpool, reqs, None, form, workspace, slots, max_batch)
+        # recall@10 of the served results of every request with k >= 10 (first 10 ids)
+        hits = tot = 0
+        for i, (_, _, ids) in enumerate(res):
+            if int(reqs["k"][i]) < 10:
+                continue
+            q0, nq = int(reqs["q0"][i]), int(reqs["nq"][i])
+            q = Qpool[q0:q0 + nq]
+            d = ((X[ids[:, :10]].double() - q[:, None, :].double()) ** 2).sum(-1).sqrt()
+            hits += int((d <= kth[q0:q0 + nq, None] * (1 + 1e-12)).sum())
+            tot += 10 * nq
+        rec = hits / tot if tot else None
+        log(f"{log_prefix} {form}: saturation {sat['qps']:.0f} q/s ({sat['req_s']:.0f} req/s), recall@10 {rec}")
+        f = {"saturation": sat, "recall_at_10": rec, "loads": []}
+        for frac in loads:
+            r, _ = serve_load(dl, torch, idx, Qpool, reqs, frac * sat["req_s"], form, workspace, slots, max_batch)
+            r["load_frac"] = frac
+            log(f"{log_prefix} {form} at {frac}x: {r['qps']:.0f} q/s, p50 {r['p50_ms']:.2f} ms, "
+                f"p99 {r['p99_ms']:.2f} ms, mean batch {r['mean_batch_queries']:.0f} queries")
+            f["loads"].append(r)
+        out["forms"][form] = f
+    idx.free()
+    del X, Qpool
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +189,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip timing the BF16+rerank form")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-form block")
+    ap.add_argument("--serve-requests", type=int, default=1500)
+    ap.add_argument("--serve-only", action="store_true", help="print only the serving-form block")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -105,6 +205,9 @@ def main():
     import paper_2406_10938_amd as dl
     import synth
     torch.backends.cuda.matmul.allow_tf32 = False
+    if args.serve_only:
+        print(json.dumps(serve_bench(dl, torch, args.serve_requests)), flush=True)
+        return
 
     cfg = synth.config("C2")
     nq = args.nq or cfg.nq
@@ -224,6 +327,12 @@ def main():
               "dtype": "bf16 products, fp32 accumulate and rerank"}
         log(f"[bench] BF16+rerank: {bf['value']:.0f} q/s, recall {rec_b}")
 
+    serving = None
+    if not args.no_serve:
+        del X, Q
+        torch.cuda.empty_cache()
+        serving = serve_bench(dl, torch, args.serve_requests)
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] oracle on host cores ({args.cpu_queries} queries)")
@@ -256,6 +365,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "bf16_rerank": bf,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -247,7 +247,8 @@ detlsh_status detlsh_query_debug(detlsh_index idx, const float* Qp, const float*
  * default priority and an equal share of one workspace of workspace_bytes
  * allocated at creation.  Requests are taken in arrival order; when a slot
  * becomes free it forms a batch from the oldest waiting request and appends
- * the waiting queries of later requests with the same (k, c, beta, options),
+ * the waiting queries of later requests with the same (k, beta, options, and
+ * c under DETLSH_RMIN_FIXED; under MAGIC, c does not enter the computation),
  * up to max_batch queries or as many as its workspace holds (continuous
  * batching).  A request larger than that is served in pieces, possibly on
  * several slots at once.  Every query's result is independent of the batch it

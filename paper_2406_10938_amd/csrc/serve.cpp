@@ -49,12 +49,15 @@ detlsh_status errf(detlsh_status s, const char* fmt, ...) {
 }
 
 // Query parameters; requests merge into one batch only when these are equal.
+// Under the MAGIC start radius the query stops in its first round and c never
+// enters the computation, so c is compared only for the FIXED ladder.
 struct Params {
     int32_t k = 0;
     double c = 0, beta = 0;
     detlsh_query_opts o{};
     bool same(const Params& p) const {
-        return k == p.k && c == p.c && beta == p.beta && o.precision == p.o.precision &&
+        const bool c_ok = o.rmin_policy == DETLSH_RMIN_MAGIC || c == p.c;
+        return k == p.k && c_ok && beta == p.beta && o.precision == p.o.precision &&
                o.rerank_mult == p.o.rerank_mult && o.rmin_policy == p.o.rmin_policy &&
                o.max_rounds == p.o.max_rounds && o.r_min == p.o.r_min && o.verify == p.o.verify;
     }

@@ -283,3 +283,23 @@ def _host_rows(cfg, n, data_seed, rows_seed):
     if cfg.name == "C5":
         return gaussian_mixture(n, cfg.d, 256, 5.0, 1.0, data_seed, rows_seed)
     raise KeyError(cfg.name)
+
+
+# --------------------------------------------------------------------------
+# serving request stream
+# --------------------------------------------------------------------------
+
+def request_stream(nreq: int, pool: int, seed: int, max_nq: int = 256, ks=(1, 10, 100), cs=(1.5, 2.0)):
+    """Seeded serving requests: nq = floor(exp(U(0, ln(max_nq+1)))) clamped to
+    [1, max_nq] (log-uniform, mean about 46 for 256), k and c uniform over
+    their sets, a start row q0 uniform in the query pool, and unit-rate
+    exponential inter-arrival gaps (scale them by 1/rate for Poisson arrivals).
+    Returns a dict of numpy arrays."""
+    rng = np.random.default_rng(seed)
+    nq = np.floor(np.exp(rng.uniform(0.0, np.log(max_nq + 1), nreq))).astype(np.int64)
+    nq = np.clip(nq, 1, max_nq)
+    k = rng.choice(np.asarray(ks, np.int64), nreq)
+    c = rng.choice(np.asarray(cs, np.float64), nreq)
+    q0 = rng.integers(0, pool - nq + 1)
+    gaps = rng.exponential(1.0, nreq)
+    return {"nq": nq, "k": k, "c": c, "q0": q0, "gaps": gaps}
