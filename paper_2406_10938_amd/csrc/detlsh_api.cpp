@@ -168,7 +168,8 @@ struct detlsh_index_s {
     int64_t n_s = 0;
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
-    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf;
+    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes;
+    int32_t G = 0;                // guess subset size, min(n, kGuessMax)
     std::vector<int64_t> sample_ids;
     std::vector<float> A_host;
     int64_t n_leaves[8] = {};
@@ -184,7 +185,7 @@ struct detlsh_index_s {
     }
     size_t bytes() const {
         size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
-                   scodes.bytes + xn.bytes + xn_bf.bytes;
+                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes;
         for (int i = 0; i < L; ++i) b += (size_t)(n_leaves[i] + 1) * 4 + 2 * (size_t)n_leaves[i] * K;
         return b;
     }
@@ -209,6 +210,9 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     if (keep_bf16) HCHECK(ix->xn_bf.alloc((size_t)ix->n * 4));
     HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(),
                                keep_bf16 ? ix->xn_bf.as<float>() : nullptr, st));
+    ix->G = (int32_t)std::min<int64_t>(ix->n, kGuessMax);
+    HCHECK(ix->gcodes.alloc((size_t)ix->G * ix->LK));
+    HCHECK(dl_launch_pack_sample(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->G, ix->gcodes.as<uint8_t>(), st));
     for (int i = 0; i < ix->L; ++i) {
         DevBuf tmp;
         HCHECK(tmp.alloc(dl_tree_tmp_bytes(ix->n, ix->K)));
@@ -571,7 +575,7 @@ struct Debug {
 };
 
 size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d) {
-    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256;
+    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256 + (size_t)p.G * 4;
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
 }
@@ -620,7 +624,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     QueryArgs a;
     a.L = ix->L; a.K = ix->K; a.N_r = ix->N_r; a.d = ix->d; a.n = ix->n;
     a.E = ix->E.as<float>(); a.codes = ix->codes.as<uint8_t>(); a.X = ix->X.as<float>(); a.Xbf = ix->Xbf.as<uint16_t>();
-    a.Q = Q; a.Qp = Qp; a.G = plan.G; a.guess_rank = plan.rank; a.N_S = plan.N_S; a.k = k; a.cap = cap;
+    a.Q = Q; a.Qp = Qp; a.G = plan.G; a.gcodes = ix->gcodes.as<uint8_t>(); a.guess_rank = plan.rank; a.N_S = plan.N_S; a.k = k; a.cap = cap;
     a.all_n = plan.all ? ix->n : 0;
     a.gthr = reinterpret_cast<float*>(take((size_t)nqc * 4));
     a.counts = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
@@ -633,6 +637,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.rad2 = plan.rad2;
     a.c2 = plan.c2;
     a.T = plan.rounds;
+    if (plan.G > 0) a.gm = reinterpret_cast<float*>(take((size_t)nqc * plan.G * 4));
     a.cand_id = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
     a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));

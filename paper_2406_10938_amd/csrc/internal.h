@@ -61,6 +61,8 @@ struct QueryArgs {
     int64_t q0 = 0;                  // first query of the chunk
     int nqc = 0;                     // queries in the chunk
     int G = 0;                       // guess subset size
+    const uint8_t* gcodes = nullptr; // codes of the guess subset, [L][G][K]
+    float* gm = nullptr;             // nqc x G guess values
     uint64_t guess_rank = 0;
     uint64_t N_S = 0;
     int k = 0;
@@ -102,9 +104,11 @@ struct QueryArgs {
 };
 
 bool dl_supported_lk(int L, int K);
-size_t dl_guess_smem(int L, int K, int N_r, int G);
 size_t dl_verify_smem(int d);
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
+// Packs the codes of the guess subset (G = min(n, 16384) points) as [L][G][K].
+hipError_t dl_launch_pack_sample(const uint8_t* codes, int64_t n, int L, int K, int G, uint8_t* out,
+                                 hipStream_t st);
 hipError_t dl_launch_filter(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st);

@@ -28,11 +28,6 @@
 #include "internal.h"
 
 namespace {
-struct SelectShared;
-}
-size_t dl_guess_smem(int L, int K, int N_r, int G);
-
-namespace {
 
 constexpr uint64_t kGuessMul = 2654435761ull;   // prime > 2^31: t -> t*a mod n is a bijection
 
@@ -98,35 +93,47 @@ __device__ __forceinline__ float cell_lbs(const float* __restrict__ qp, const fl
 
 // Given hist[0..nbins) (nbins multiple of 256) and a 1-based rank r, find the
 // bin d with cum(<d) < r <= cum(<=d).  Results in *d_out, *before_out,
-// *total_out (sum of all bins).  Uses scratch[0..257].
+// *total_out (sum of all bins; d = -1 when r exceeds it).  Each thread sums
+// its run of nbins/256 bins, a block scan of those sums finds the one thread
+// whose run holds rank r, and it walks its run.  Uses scratch[0..3].
 __device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* scratch, int* d_out,
                          uint64_t* before_out, uint64_t* total_out) {
     const int per = nbins / 256;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     uint32_t s = 0;
     for (int b = 0; b < per; ++b) s += hist[tid * per + b];
-    scratch[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        uint64_t run = 0;
-        int sel = -1;
-        uint64_t before = 0;
-        for (int t = 0; t < 256; ++t) {
-            const uint64_t nx = run + scratch[t];
-            if (sel < 0 && nx >= r) {
-                uint64_t rr = run;
-                for (int b = 0; b < per; ++b) {
-                    const uint32_t c = hist[t * per + b];
-                    if (rr + c >= r) { sel = t * per + b; before = rr; break; }
-                    rr += c;
-                }
-            }
-            run = nx;
-        }
-        *d_out = sel;
-        *before_out = before;
-        *total_out = run;
+    uint32_t inc = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = dl_shfl_u32(inc, lane >= off ? lane - off : lane);
+        if (lane >= off) inc += y;
     }
+    if (lane == 63) scratch[wave] = inc;
+    if (tid == 0) {
+        *d_out = -1;
+        *before_out = 0;
+    }
+    __syncthreads();
+    uint64_t wbase = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) wbase += scratch[w];
+        tot += scratch[w];
+    }
+    const uint64_t excl = wbase + inc - s;
+    if (r > excl && r <= excl + s) {
+        uint64_t rr = excl;
+        for (int b = 0; b < per; ++b) {
+            const uint32_t c = hist[tid * per + b];
+            if (rr + c >= r) {
+                *d_out = tid * per + b;
+                *before_out = rr;
+                break;
+            }
+            rr += c;
+        }
+    }
+    if (tid == 0) *total_out = tot;
     __syncthreads();
 }
 
@@ -149,11 +156,17 @@ __device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& s
         const int shift = 32 - known - nbits;
         for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
         __syncthreads();
-        for (int64_t i = threadIdx.x; i < m; i += 256) {
-            const uint32_t u = __float_as_uint(get(i));
+        auto count = [&](uint32_t u) {
             if (known == 0 || (u >> (32 - known)) == prefix)
                 atomicAdd(&sh.hist[(u >> shift) & ((1u << nbits) - 1u)], 1u);
+        };
+        int64_t i = threadIdx.x;
+        for (; i + 768 < m; i += 1024) {   // four loads in flight per thread
+            const uint32_t u0 = __float_as_uint(get(i)), u1 = __float_as_uint(get(i + 256));
+            const uint32_t u2 = __float_as_uint(get(i + 512)), u3 = __float_as_uint(get(i + 768));
+            count(u0); count(u1); count(u2); count(u3);
         }
+        for (; i < m; i += 256) count(__float_as_uint(get(i)));
         __syncthreads();
         find_bin(sh.hist, 4096, r, sh.scratch, &sh.d, &sh.before, &sh.total);
         r -= sh.before;
@@ -253,29 +266,54 @@ __device__ void topk_u64(const uint64_t* buf, int64_t m, int k, TopkShared& sh) 
 // kernels
 // ---------------------------------------------------------------------------
 
-template <int L, int K>
-__global__ __launch_bounds__(256) void guess_kernel(const float* __restrict__ E, int N_r,
-                                                    const uint8_t* __restrict__ codes, int64_t n, int G,
-                                                    const float* __restrict__ Qp, int64_t q0,
-                                                    uint64_t rank, float* __restrict__ gthr)
+// Copy of the codes of the G guess points, packed as [L][G][K]: point p is
+// o = p a mod n (a bijection of [0, n) for n < 2^31 since a is a prime above
+// 2^31), or p itself when G = n.
+__global__ __launch_bounds__(256) void pack_sample_kernel(const uint8_t* __restrict__ codes, int64_t n, int L, int K,
+                                                          int G, uint8_t* __restrict__ out)
 {
-    extern __shared__ unsigned char smem[];
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)L * G) return;
+    const int i = (int)(t / G);
+    const int p = (int)(t % G);
+    const int64_t o = ((int64_t)G == n) ? (int64_t)p : (int64_t)(((uint64_t)p * kGuessMul) % (uint64_t)n);
+    const uint8_t* src = codes + ((int64_t)i * n + o) * K;
+    uint8_t* dst = out + ((int64_t)i * G + p) * K;
+    for (int j = 0; j < K; ++j) dst[j] = src[j];
+}
+
+// m^2 of every guess point for the queries [blockIdx.y*q_per_block, ...):
+// one lane per point, its cell bounds in registers, gm[t*G + p].
+template <int L, int K>
+__global__ __launch_bounds__(256) void guess_scan_kernel(const float* __restrict__ E, int N_r,
+                                                         const uint8_t* __restrict__ gcodes, int G,
+                                                         const float* __restrict__ Qp, int64_t q0, int nqc,
+                                                         int q_per_block, float* __restrict__ gm)
+{
     constexpr int LK = L * K;
     const int ldE = N_r + 1;
-    float* sE = reinterpret_cast<float*>(smem);
-    float* sm = sE + LK * ldE;
-    SelectShared& sh = *reinterpret_cast<SelectShared*>(sm + ((G + 1) & ~1));
-    for (int t = threadIdx.x; t < LK * ldE; t += 256) sE[t] = E[t];
-    __syncthreads();
-    const float* qp = Qp + (q0 + blockIdx.x) * LK;
-    for (int t = threadIdx.x; t < G; t += 256) {
-        const int64_t o = (G == n) ? (int64_t)t : (int64_t)(((uint64_t)t * kGuessMul) % (uint64_t)n);
-        float lo[LK], hi[LK], lb[L];
-        load_cell<L, K>(codes, n, o, sE, ldE, lo, hi);
-        sm[t] = cell_lbs<L, K>(qp, lo, hi, lb);
+    const int p_raw = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = p_raw < G;
+    const int p = valid ? p_raw : G - 1;
+    float lo[LK], hi[LK];
+    load_cell<L, K>(gcodes, G, p, E, ldE, lo, hi);
+    const int ta = blockIdx.y * q_per_block;
+    const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
+#pragma unroll 1
+    for (int t = ta; t < tb; ++t) {
+        float lb[L];
+        const float m = cell_lbs<L, K>(Qp + (q0 + t) * LK, lo, hi, lb);
+        if (valid) gm[(int64_t)t * G + p] = m;
     }
-    __syncthreads();
-    const float g = select_rank_f32([&](int64_t i) { return sm[i]; }, G, rank, sh);
+}
+
+// gthr[t] = the rank-th smallest of the query's G guess values.
+__global__ __launch_bounds__(256) void guess_select_kernel(const float* __restrict__ gm, int G, uint64_t rank,
+                                                           float* __restrict__ gthr)
+{
+    __shared__ SelectShared sh;
+    const float* src = gm + (int64_t)blockIdx.x * G;
+    const float g = select_rank_f32([&](int64_t i) { return src[i]; }, G, rank, sh);
     if (threadIdx.x == 0) gthr[blockIdx.x] = g;
 }
 
@@ -500,21 +538,37 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     const float* lbt = cand_lb + (int64_t)t * cap * L;
     const float* mt = cand_m + (int64_t)t * cap;
     const float thr = select_rank_f32([&](int64_t s) { return mt[s]; }, (int64_t)cnt, N_S, sh);
-    // |U_i| for i = 1..L: entries whose prefix minimum over trees 1..i is <= thr
+    // first admitting tree f(o) = min{i : LB_i^2 <= thr} (0: none) of every
+    // entry, kept in cand_ft; |U_i| for i = 1..L counts the entries with
+    // 0 < f(o) <= i
+    int32_t* ids = cand_id + (int64_t)t * cap;
+    int32_t* ftree = cand_ft + (int64_t)t * cap;
     if (threadIdx.x < 8) tc[threadIdx.x] = 0;
     __syncthreads();
     uint32_t loc[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) loc[i] = 0;
-    for (int64_t s = threadIdx.x; s < (int64_t)cnt; s += 256) {
-        float lb[L];
-        load_lbs<L>(lbt + s * L, lb);
-        float pm = INFINITY;
+    auto first_tree = [&](const float (&lb)[L]) {
+        int ft = 0;
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            pm = fminf(pm, lb[i]);
-            loc[i] += (pm <= thr) ? 1u : 0u;
-        }
+        for (int i = L - 1; i >= 0; --i)
+            if (lb[i] <= thr) ft = i + 1;
+#pragma unroll
+        for (int i = 0; i < L; ++i) loc[i] += (ft != 0 && ft <= i + 1) ? 1u : 0u;
+        return ft;
+    };
+    int64_t s = threadIdx.x;
+    for (; s + 256 < (int64_t)cnt; s += 512) {   // two rows in flight per thread
+        float la[L], lc[L];
+        load_lbs<L>(lbt + s * L, la);
+        load_lbs<L>(lbt + (s + 256) * L, lc);
+        ftree[s] = first_tree(la);
+        ftree[s + 256] = first_tree(lc);
+    }
+    for (; s < (int64_t)cnt; s += 256) {
+        float la[L];
+        load_lbs<L>(lbt + s * L, la);
+        ftree[s] = first_tree(la);
     }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -525,9 +579,8 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     int istop = L;
     for (int i = 0; i < L; ++i)
         if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
-    // in-place stable compaction of S = U_{istop}, with each member's first admitting tree
-    int32_t* ids = cand_id + (int64_t)t * cap;
-    int32_t* ftree = cand_ft + (int64_t)t * cap;
+    // in-place stable compaction of S = U_{istop}, with each member's first
+    // admitting tree (every entry's f(o) was written above by this thread)
     uint32_t out = 0;
     for (int64_t c0 = 0; c0 < (int64_t)cnt; c0 += 256) {
         const int64_t s = c0 + threadIdx.x;
@@ -535,11 +588,7 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
         int32_t id = 0, ft = 0;
         if (s < (int64_t)cnt) {
             id = ids[s];
-            float lb[L];
-            load_lbs<L>(lbt + s * L, lb);
-#pragma unroll
-            for (int i = L - 1; i >= 0; --i)
-                if (lb[i] <= thr) ft = i + 1;
+            ft = ftree[s];
             mem = (ft != 0 && ft <= istop);
             if (!mem && bm) atomicAnd((unsigned long long*)&bm[(int64_t)t * W + (id >> 6)], ~(1ull << (id & 63)));
         }
@@ -1018,9 +1067,17 @@ __global__ __launch_bounds__(256) void fixed_finish_kernel(
 
 template <int L, int K>
 hipError_t launch_guess_lk(const QueryArgs& a, hipStream_t st) {
-    const size_t shm = dl_guess_smem(L, K, a.N_r, a.G);
-    hipLaunchKernelGGL((guess_kernel<L, K>), dim3(a.nqc), dim3(256), shm, st, a.E, a.N_r, a.codes, a.n, a.G,
-                       a.Qp, a.q0, a.guess_rank, a.gthr);
+    const int pb = (a.G + 255) / 256;
+    int ny = 2048 / pb;
+    if (ny < 1) ny = 1;
+    if (ny > a.nqc) ny = a.nqc;
+    const int qpb = (a.nqc + ny - 1) / ny;
+    ny = (a.nqc + qpb - 1) / qpb;
+    hipLaunchKernelGGL((guess_scan_kernel<L, K>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E, a.N_r,
+                       a.gcodes, a.G, a.Qp, a.q0, a.nqc, qpb, a.gm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(guess_select_kernel, dim3(a.nqc), dim3(256), 0, st, a.gm, a.G, a.guess_rank, a.gthr);
     return hipGetLastError();
 }
 
@@ -1078,8 +1135,12 @@ hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
 
 }  // namespace
 
-size_t dl_guess_smem(int L, int K, int N_r, int G) {
-    return (size_t)L * K * (N_r + 1) * 4 + (size_t)((G + 1) & ~1) * 4 + sizeof(SelectShared) + 64;
+hipError_t dl_launch_pack_sample(const uint8_t* codes, int64_t n, int L, int K, int G, uint8_t* out,
+                                 hipStream_t st) {
+    const int64_t tot = (int64_t)L * G;
+    hipLaunchKernelGGL(pack_sample_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, codes, n, L, K, G,
+                       out);
+    return hipGetLastError();
 }
 
 bool dl_supported_lk(int L, int K) {
