@@ -748,10 +748,20 @@ __global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, i
 // accumulator v of lane l is (query 4*(l/16)+v, point l%16).  With QLDS the
 // workgroup's 128 query rows stay in LDS (rows padded by 16 bytes against bank
 // conflicts) for the whole point range; only the point rows stream from L2.
-struct DenseQuery {
-    uint64_t bits;   // membership word of the current 64-point tile
-    float qn;        // squared norm
-    float tau;       // bound on the k'-th squared distance (-inf: skip)
+// Survivors are appended to per-query LDS lists (no global atomics in the
+// inner loop); lists are double-buffered by epochs of kEpoch tiles and each
+// epoch's lists are flushed with one global atomic per query while the next
+// epoch runs.  A list that fills up sends further survivors straight to HBM.
+constexpr int kSvl = 8;
+constexpr int kEpoch = 4;
+
+struct DenseShared {
+    float qn[kDQ];
+    float tau[kDQ];             // bound on the k'-th squared distance (-inf: skip)
+    uint64_t bits[2][kDQ];      // membership words of the current / next tile
+    float xn[2][kDP];
+    uint32_t cnt[2][kDQ];
+    int32_t list[2][kDQ][kSvl];
 };
 
 template <bool BF16, bool ALIGNED, bool QLDS, int KS>
@@ -763,8 +773,7 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     int64_t cap_sv, int gx, int64_t gy, int64_t ntiles, int64_t tiles_per_split)
 {
     extern __shared__ unsigned char dsm[];
-    __shared__ DenseQuery sqd[kDQ];
-    __shared__ float sxn[kDP];
+    __shared__ DenseShared sh;
     // XCD-aware order: consecutive workgroups go to consecutive XCDs, so all
     // query tiles of one point split are placed on the same XCD (shared L2).
     const int64_t lid = blockIdx.x;
@@ -805,10 +814,39 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     }
     const int64_t tb = split * tiles_per_split;
     const int64_t te = (tb + tiles_per_split < ntiles) ? tb + tiles_per_split : ntiles;
+    // per-query constants, and the membership words / point norms of the first tile
+    const int tq = qt0 + (int)threadIdx.x;
+    const bool qok = threadIdx.x < kDQ && tq < nqc && status[tq] == 0;
+    if (threadIdx.x < kDQ) {
+        sh.qn[threadIdx.x] = qok ? qn[tq] : 0.f;
+        sh.tau[threadIdx.x] = qok ? tau[tq] : -INFINITY;
+        sh.cnt[0][threadIdx.x] = 0;
+        sh.cnt[1][threadIdx.x] = 0;
+    }
+    auto fetch_meta = [&](int64_t tile, uint64_t& bits, float& pxn) {
+        if (threadIdx.x < kDQ) {
+            bits = (qok && tile < W) ? bm[(int64_t)tq * W + tile] : 0ull;
+        } else if (threadIdx.x < kDQ + kDP) {
+            const int64_t p = tile * kDP + threadIdx.x - kDQ;
+            pxn = (p < n) ? xn[p] : 0.f;
+        }
+    };
+    auto store_meta = [&](int buf, uint64_t bits, float pxn) {
+        if (threadIdx.x < kDQ) sh.bits[buf][threadIdx.x] = bits;
+        else if (threadIdx.x < kDQ + kDP) sh.xn[buf][threadIdx.x - kDQ] = pxn;
+    };
+    uint64_t nbits = 0;
+    float nxn = 0.f;
+    if (tb < te) {
+        fetch_meta(tb, nbits, nxn);
+        store_meta(0, nbits, nxn);
+    }
     // KS > 0: all d <= 16*KS reduction elements of the lane's two point rows are
-    // held in registers, and the next tile's rows are loaded during this tile.
-    floatx4 xc[KS > 0 ? KS : 1][2], xnx[KS > 0 ? KS : 1][2];
-    shortx4 bc[KS > 0 ? KS : 1][2], bnx[KS > 0 ? KS : 1][2];
+    // held in registers; the next tile's rows are loaded into the same
+    // registers as soon as the products of this tile are issued, and arrive
+    // during the epilogue and the barrier.
+    floatx4 xc[KS > 0 ? KS : 1][2];
+    shortx4 bc[KS > 0 ? KS : 1][2];
     auto load_rows = [&](int64_t tile, floatx4 (&xf)[KS > 0 ? KS : 1][2], shortx4 (&xb)[KS > 0 ? KS : 1][2]) {
 #pragma unroll
         for (int pb = 0; pb < 2; ++pb) {
@@ -822,23 +860,13 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
         }
     };
     if (KS > 0 && tb < te) load_rows(tb, xc, bc);
+    __syncthreads();
     for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t j = tile - tb;
+        const int cur = (int)(j & 1);
+        const int ep = (int)((j / kEpoch) & 1);
         const int64_t p0 = tile * kDP;
-        if (KS > 0 && tile + 1 < te) load_rows(tile + 1, xnx, bnx);
-        __syncthreads();
-        if (threadIdx.x < kDQ) {
-            const int t = qt0 + threadIdx.x;
-            const bool ok = t < nqc && status[t] == 0;
-            DenseQuery dq;
-            dq.bits = (ok && tile < W) ? bm[(int64_t)t * W + tile] : 0ull;
-            dq.qn = ok ? qn[t] : 0.f;
-            dq.tau = ok ? tau[t] : -INFINITY;
-            sqd[threadIdx.x] = dq;
-        } else if (threadIdx.x < kDQ + kDP) {
-            const int64_t p = p0 + threadIdx.x - kDQ;
-            sxn[threadIdx.x - kDQ] = (p < n) ? xn[p] : 0.f;
-        }
-        __syncthreads();
+        if (tile + 1 < te) fetch_meta(tile + 1, nbits, nxn);
         floatx4 acc[4][2];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
@@ -923,36 +951,48 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
                 }
             }
         }
-        if (KS > 0) {
-#pragma unroll
-            for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks)
-#pragma unroll
-                for (int pb = 0; pb < 2; ++pb) {
-                    if (BF16) bc[ks][pb] = bnx[ks][pb];
-                    else xc[ks][pb] = xnx[ks][pb];
-                }
-        }
+        if (KS > 0 && tile + 1 < te) load_rows(tile + 1, xc, bc);
         const int pi0 = 32 * ph + m;
-        const float xn0 = sxn[pi0], xn1 = sxn[pi0 + 16];
+        const float xn0 = sh.xn[cur][pi0], xn1 = sh.xn[cur][pi0 + 16];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int qi = 64 * qh + 16 * qb + 4 * kq + v;
-                const DenseQuery dq = sqd[qi];
+                const uint64_t bits = sh.bits[cur][qi];
+                const float dqn = sh.qn[qi], dtau = sh.tau[qi];
 #pragma unroll
                 for (int pb = 0; pb < 2; ++pb) {
                     const int pi = pi0 + 16 * pb;
-                    if (!((dq.bits >> pi) & 1ull)) continue;
-                    const float nsum = dq.qn + (pb ? xn1 : xn0);
+                    if (!((bits >> pi) & 1ull)) continue;
+                    const float nsum = dqn + (pb ? xn1 : xn0);
                     const float a2 = fmaf(-2.0f, acc[qb][pb][v], nsum);
-                    if (a2 <= fmaf(margin_c, nsum, dq.tau)) {
-                        const int t = qt0 + qi;
-                        const uint32_t slot = atomicAdd(&svc[t], 1u);
-                        if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
+                    if (a2 <= fmaf(margin_c, nsum, dtau)) {
+                        const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
+                        if (s < (uint32_t)kSvl) {
+                            sh.list[ep][qi][s] = (int32_t)(p0 + pi);
+                        } else {
+                            const int t = qt0 + qi;
+                            const uint32_t slot = atomicAdd(&svc[t], 1u);
+                            if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
+                        }
                     }
                 }
             }
+        if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
+        __syncthreads();
+        // the epoch's lists are complete: flush them (the next epoch appends to
+        // the other buffer; this one is reused only after another barrier)
+        if (((j + 1) % kEpoch == 0 || tile + 1 == te) && threadIdx.x < kDQ) {
+            const uint32_t c = sh.cnt[ep][threadIdx.x];
+            if (c > 0) {
+                const uint32_t cl = c < (uint32_t)kSvl ? c : (uint32_t)kSvl;
+                const uint32_t base = atomicAdd(&svc[tq], cl);
+                for (uint32_t s = 0; s < cl; ++s)
+                    if ((int64_t)(base + s) < cap_sv) sv[(int64_t)tq * cap_sv + base + s] = sh.list[ep][threadIdx.x][s];
+                sh.cnt[ep][threadIdx.x] = 0;
+            }
+        }
     }
 }
 
