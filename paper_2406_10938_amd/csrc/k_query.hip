@@ -764,6 +764,57 @@ struct DenseShared {
     int32_t list[2][kDQ][kSvl];
 };
 
+// Screen of one tile's products: a member of S whose ||q||^2 + ||o||^2 - 2 q.o
+// is within the query's bound joins its survivor list (LDS, epoch buffer ep;
+// straight to HBM when the list is full).
+__device__ __forceinline__ void dense_screen(const floatx4 (&acc)[4][2], DenseShared& sh, int cur, int ep, int qh,
+                                             int ph, int m, int kq, int64_t p0, int qt0, float margin_c,
+                                             uint32_t* __restrict__ svc, int32_t* __restrict__ sv, int64_t cap_sv) {
+    const int pi0 = 32 * ph + m;
+    const float xn0 = sh.xn[cur][pi0], xn1 = sh.xn[cur][pi0 + 16];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int qi = 64 * qh + 16 * qb + 4 * kq + v;
+            const uint64_t bits = sh.bits[cur][qi];
+            const float dqn = sh.qn[qi], dtau = sh.tau[qi];
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) {
+                const int pi = pi0 + 16 * pb;
+                if (!((bits >> pi) & 1ull)) continue;
+                const float nsum = dqn + (pb ? xn1 : xn0);
+                const float a2 = fmaf(-2.0f, acc[qb][pb][v], nsum);
+                if (a2 <= fmaf(margin_c, nsum, dtau)) {
+                    const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
+                    if (s < (uint32_t)kSvl) {
+                        sh.list[ep][qi][s] = (int32_t)(p0 + pi);
+                    } else {
+                        const int t = qt0 + qi;
+                        const uint32_t slot = atomicAdd(&svc[t], 1u);
+                        if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
+                    }
+                }
+            }
+        }
+}
+
+// After a barrier that follows an epoch's last screen: one global atomic per
+// query reserves the slots of its list, which is copied out and cleared (the
+// next epoch appends to the other buffer; this one is reused only after
+// another barrier).
+__device__ __forceinline__ void dense_flush(DenseShared& sh, int ep, int tq, uint32_t* __restrict__ svc,
+                                            int32_t* __restrict__ sv, int64_t cap_sv) {
+    if (threadIdx.x >= kDQ) return;
+    const uint32_t c = sh.cnt[ep][threadIdx.x];
+    if (c == 0) return;
+    const uint32_t cl = c < (uint32_t)kSvl ? c : (uint32_t)kSvl;
+    const uint32_t base = atomicAdd(&svc[tq], cl);
+    for (uint32_t s = 0; s < cl; ++s)
+        if ((int64_t)(base + s) < cap_sv) sv[(int64_t)tq * cap_sv + base + s] = sh.list[ep][threadIdx.x][s];
+    sh.cnt[ep][threadIdx.x] = 0;
+}
+
 template <bool BF16, bool ALIGNED, bool QLDS, int KS>
 __global__ __launch_bounds__(256) void dense_verify_kernel(
     const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
@@ -952,46 +1003,203 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
             }
         }
         if (KS > 0 && tile + 1 < te) load_rows(tile + 1, xc, bc);
-        const int pi0 = 32 * ph + m;
-        const float xn0 = sh.xn[cur][pi0], xn1 = sh.xn[cur][pi0 + 16];
+        dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
+        if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
+        __syncthreads();
+        if ((j + 1) % kEpoch == 0 || tile + 1 == te) dense_flush(sh, ep, tq, svc, sv, cap_sv);
+    }
+}
+
+// Large d: the 128 query rows do not stay in LDS; the workgroup streams them
+// through LDS in chunks of DC reduction elements (64 FP32 or 128 BF16) for
+// every point tile.  While one chunk's products are issued, the next chunk's
+// query rows and point rows are loaded into registers; two barriers per chunk
+// hand the staged rows over.  Reduction order, screen and survivor lists are
+// those of dense_verify_kernel.
+template <bool BF16>
+struct KcShape {
+    static constexpr int DC = BF16 ? 128 : 64;   // reduction elements per chunk
+    static constexpr int LD = DC + (BF16 ? 8 : 4);   // LDS row stride in elements (+16 bytes)
+    static constexpr int EB = BF16 ? 2 : 4;       // bytes per element
+    static constexpr int VE = 16 / EB;            // elements per 16-byte vector
+    static constexpr int VPR = DC / VE;           // vectors per row of a chunk
+    static constexpr int SV = kDQ * VPR / 256;    // staged vectors per thread
+    static constexpr int CK = DC / 16;            // 16-element MFMA steps per chunk
+};
+
+template <bool BF16, bool ALIGNED>
+__global__ __launch_bounds__(256) void dense_verify_kc_kernel(
+    const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
+    const float* __restrict__ Q, const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int64_t q0,
+    int nqc, const uint64_t* __restrict__ bm, int64_t W, const float* __restrict__ tau,
+    const int32_t* __restrict__ status, float margin_c, uint32_t* __restrict__ svc, int32_t* __restrict__ sv,
+    int64_t cap_sv, int gx, int64_t gy, int64_t ntiles, int64_t tiles_per_split)
+{
+    using S = KcShape<BF16>;
+    __shared__ DenseShared sh;
+    __shared__ __attribute__((aligned(16))) unsigned char sqc[kDQ * S::LD * S::EB];
+    const int64_t lid = blockIdx.x;
+    const int xcd = (int)(lid & 7);
+    const int64_t r = lid >> 3;
+    const int qtile = (int)(r % gx);
+    const int64_t split = xcd + 8 * (r / gx);
+    if (split >= gy) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int qh = wave & 1, ph = wave >> 1;
+    const int qt0 = qtile * kDQ;
+    const int nchunk = (d + S::DC - 1) / S::DC;
+    const int64_t tb = split * tiles_per_split;
+    const int64_t te = (tb + tiles_per_split < ntiles) ? tb + tiles_per_split : ntiles;
+    const int tq = qt0 + (int)threadIdx.x;
+    const bool qok = threadIdx.x < kDQ && tq < nqc && status[tq] == 0;
+    if (threadIdx.x < kDQ) {
+        sh.qn[threadIdx.x] = qok ? qn[tq] : 0.f;
+        sh.tau[threadIdx.x] = qok ? tau[tq] : -INFINITY;
+        sh.cnt[0][threadIdx.x] = 0;
+        sh.cnt[1][threadIdx.x] = 0;
+    }
+    auto fetch_meta = [&](int64_t tile, uint64_t& bits, float& pxn) {
+        if (threadIdx.x < kDQ) {
+            bits = (qok && tile < W) ? bm[(int64_t)tq * W + tile] : 0ull;
+        } else if (threadIdx.x < kDQ + kDP) {
+            const int64_t p = tile * kDP + threadIdx.x - kDQ;
+            pxn = (p < n) ? xn[p] : 0.f;
+        }
+    };
+    auto store_meta = [&](int buf, uint64_t bits, float pxn) {
+        if (threadIdx.x < kDQ) sh.bits[buf][threadIdx.x] = bits;
+        else if (threadIdx.x < kDQ + kDP) sh.xn[buf][threadIdx.x - kDQ] = pxn;
+    };
+    // staged query vectors: thread t holds vectors t + 256 i of the chunk
+    uint4 stg[S::SV];
+    auto stage_load = [&](int c) {
+#pragma unroll
+        for (int i = 0; i < S::SV; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            const int row = idx / S::VPR, v = idx % S::VPR;
+            int t = qt0 + row;
+            if (t >= nqc) t = nqc - 1;
+            const int k = c * S::DC + v * S::VE;
+            if (BF16) {
+                const uint16_t* src = Qbf + (int64_t)t * d;
+                const shortx4 a = load4bf<ALIGNED>(src, k, d), b = load4bf<ALIGNED>(src, k + 4, d);
+                stg[i] = make_uint4((uint32_t)(uint16_t)a[0] | ((uint32_t)(uint16_t)a[1] << 16),
+                                    (uint32_t)(uint16_t)a[2] | ((uint32_t)(uint16_t)a[3] << 16),
+                                    (uint32_t)(uint16_t)b[0] | ((uint32_t)(uint16_t)b[1] << 16),
+                                    (uint32_t)(uint16_t)b[2] | ((uint32_t)(uint16_t)b[3] << 16));
+            } else {
+                const floatx4 a = load4<ALIGNED>(Q + (q0 + t) * (int64_t)d, k, d);
+                stg[i] = make_uint4(__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]),
+                                    __float_as_uint(a[3]));
+            }
+        }
+    };
+    auto stage_store = [&]() {
+#pragma unroll
+        for (int i = 0; i < S::SV; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            const int row = idx / S::VPR, v = idx % S::VPR;
+            *reinterpret_cast<uint4*>(sqc + ((size_t)row * S::LD + (size_t)v * S::VE) * S::EB) = stg[i];
+        }
+    };
+    floatx4 xc[S::CK][2], xnx[S::CK][2];
+    shortx4 bc[S::CK][2], bnx[S::CK][2];
+    auto load_x = [&](int64_t tile, int c, floatx4 (&xf)[S::CK][2], shortx4 (&xb)[S::CK][2]) {
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+            int64_t p = tile * kDP + 32 * ph + 16 * pb + m;
+            if (p >= n) p = n - 1;
+#pragma unroll
+            for (int ks = 0; ks < S::CK; ++ks) {
+                const int k = c * S::DC + 16 * ks + 4 * kq;
+                if (BF16) xb[ks][pb] = load4bf<ALIGNED>(Xbf + p * d, k, d);
+                else xf[ks][pb] = load4<ALIGNED>(X + p * d, k, d);
+            }
+        }
+    };
+    uint64_t nbits = 0;
+    float nxn = 0.f;
+    if (tb < te) {
+        fetch_meta(tb, nbits, nxn);
+        store_meta(0, nbits, nxn);
+        stage_load(0);
+        load_x(tb, 0, xc, bc);
+        stage_store();
+    }
+    __syncthreads();
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t j = tile - tb;
+        const int cur = (int)(j & 1);
+        const int ep = (int)((j / kEpoch) & 1);
+        const int64_t p0 = tile * kDP;
+        if (tile + 1 < te) fetch_meta(tile + 1, nbits, nxn);
+        floatx4 acc[4][2];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int qi = 64 * qh + 16 * qb + 4 * kq + v;
-                const uint64_t bits = sh.bits[cur][qi];
-                const float dqn = sh.qn[qi], dtau = sh.tau[qi];
+            for (int pb = 0; pb < 2; ++pb) acc[qb][pb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < nchunk; ++c) {
+            const bool last = c + 1 == nchunk;
+            const bool more = !last || tile + 1 < te;
+            if (more) {
+                stage_load(last ? 0 : c + 1);
+                load_x(last ? tile + 1 : tile, last ? 0 : c + 1, xnx, bnx);
+            }
 #pragma unroll
-                for (int pb = 0; pb < 2; ++pb) {
-                    const int pi = pi0 + 16 * pb;
-                    if (!((bits >> pi) & 1ull)) continue;
-                    const float nsum = dqn + (pb ? xn1 : xn0);
-                    const float a2 = fmaf(-2.0f, acc[qb][pb][v], nsum);
-                    if (a2 <= fmaf(margin_c, nsum, dtau)) {
-                        const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
-                        if (s < (uint32_t)kSvl) {
-                            sh.list[ep][qi][s] = (int32_t)(p0 + pi);
-                        } else {
-                            const int t = qt0 + qi;
-                            const uint32_t slot = atomicAdd(&svc[t], 1u);
-                            if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
-                        }
+            for (int ks = 0; ks < S::CK; ++ks) {
+                if (BF16) {
+                    const uint16_t* sq = reinterpret_cast<const uint16_t*>(sqc);
+                    shortx4 qv[4];
+#pragma unroll
+                    for (int qb = 0; qb < 4; ++qb) {
+                        const int i = 64 * qh + 16 * qb + m;
+                        const uint2 v = *reinterpret_cast<const uint2*>(sq + i * S::LD + 16 * ks + 4 * kq);
+                        qv[qb] = shortx4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff),
+                                         (short)(v.y >> 16)};
                     }
+#pragma unroll
+                    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                        for (int pb = 0; pb < 2; ++pb)
+                            acc[qb][pb] =
+                                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qv[qb], bc[ks][pb], acc[qb][pb], 0, 0, 0);
+                } else {
+                    const float* sq = reinterpret_cast<const float*>(sqc);
+                    floatx4 qv[4];
+#pragma unroll
+                    for (int qb = 0; qb < 4; ++qb) {
+                        const int i = 64 * qh + 16 * qb + m;
+                        const float4 v = *reinterpret_cast<const float4*>(sq + i * S::LD + 16 * ks + 4 * kq);
+                        qv[qb] = floatx4{v.x, v.y, v.z, v.w};
+                    }
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                            for (int pb = 0; pb < 2; ++pb)
+                                acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[qb][s2], xc[ks][pb][s2],
+                                                                                    acc[qb][pb], 0, 0, 0);
                 }
             }
-        if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
-        __syncthreads();
-        // the epoch's lists are complete: flush them (the next epoch appends to
-        // the other buffer; this one is reused only after another barrier)
-        if (((j + 1) % kEpoch == 0 || tile + 1 == te) && threadIdx.x < kDQ) {
-            const uint32_t c = sh.cnt[ep][threadIdx.x];
-            if (c > 0) {
-                const uint32_t cl = c < (uint32_t)kSvl ? c : (uint32_t)kSvl;
-                const uint32_t base = atomicAdd(&svc[tq], cl);
-                for (uint32_t s = 0; s < cl; ++s)
-                    if ((int64_t)(base + s) < cap_sv) sv[(int64_t)tq * cap_sv + base + s] = sh.list[ep][threadIdx.x][s];
-                sh.cnt[ep][threadIdx.x] = 0;
+            __syncthreads();   // every wave is done with this chunk's query rows
+            if (more) {
+                stage_store();
+#pragma unroll
+                for (int ks = 0; ks < S::CK; ++ks)
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb) {
+                        if (BF16) bc[ks][pb] = bnx[ks][pb];
+                        else xc[ks][pb] = xnx[ks][pb];
+                    }
             }
+            if (last) {
+                dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
+                if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
+            }
+            __syncthreads();   // next chunk staged; the tile's survivor lists complete
+            if (last && ((j + 1) % kEpoch == 0 || tile + 1 == te)) dense_flush(sh, ep, tq, svc, sv, cap_sv);
         }
     }
 }
@@ -1252,26 +1460,40 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((dense_verify_kernel<BF, AL, QL, KS>), dim3((unsigned)blocks), dim3(256), shm, st, a.X,     \
                        a.Xbf, xn, a.n, a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, \
                        a.svc, a.sv, a.cap_sv, gx, gy, ntiles, tps)
-    // the query tile stays in LDS when it fits in 80 KB; point rows of up to
-    // 128 elements stay in registers
+    // the query tile stays in LDS when it fits in 80 KB and point rows of up to
+    // 128 elements stay in registers; otherwise the query rows stream through
+    // LDS in chunks
     const size_t qbytes = (size_t)kDQ * (a.dense_bf16 ? (a.d + 8) * 2 : (a.d + 4) * 4);
     const bool qlds = al && qbytes <= 80 * 1024;
     const size_t shm = qlds ? qbytes : 0;
     const int ks = (a.d + 15) / 16;
-    if (a.dense_bf16) {
-        if (qlds && ks <= 4) DL_DENSE(true, true, true, 4);
-        else if (qlds && ks <= 6) DL_DENSE(true, true, true, 6);
-        else if (qlds && ks <= 8) DL_DENSE(true, true, true, 8);
-        else if (qlds) DL_DENSE(true, true, true, 0);
-        else if (al) DL_DENSE(true, true, false, 0);
-        else DL_DENSE(true, false, false, 0);
+    if (qlds && ks <= 8) {
+        if (a.dense_bf16) {
+            if (ks <= 4) DL_DENSE(true, true, true, 4);
+            else if (ks <= 6) DL_DENSE(true, true, true, 6);
+            else DL_DENSE(true, true, true, 8);
+        } else {
+            if (ks <= 4) DL_DENSE(false, true, true, 4);
+            else if (ks <= 6) DL_DENSE(false, true, true, 6);
+            else DL_DENSE(false, true, true, 8);
+        }
     } else {
-        if (qlds && ks <= 4) DL_DENSE(false, true, true, 4);
-        else if (qlds && ks <= 6) DL_DENSE(false, true, true, 6);
-        else if (qlds && ks <= 8) DL_DENSE(false, true, true, 8);
-        else if (qlds) DL_DENSE(false, true, true, 0);
-        else if (al) DL_DENSE(false, true, false, 0);
-        else DL_DENSE(false, false, false, 0);
+#define DL_DENSE_KC(BF, AL)                                                                                    \
+    hipLaunchKernelGGL((dense_verify_kc_kernel<BF, AL>), dim3((unsigned)blocks), dim3(256), 0, st, a.X, a.Xbf, xn,  \
+                       a.n, a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv,  \
+                       a.cap_sv, gx, gy, ntiles, tps)
+        // BF16: the query tile in LDS with point rows streamed per step, or
+        // both from L2, measured faster than the chunked stream (whose 128-element
+        // chunks are too short to hide their two barriers at the BF16 rate)
+        if (a.dense_bf16) {
+            if (qlds) DL_DENSE(true, true, true, 0);
+            else if (al) DL_DENSE(true, true, false, 0);
+            else DL_DENSE(true, false, false, 0);
+        } else {
+            if (al) DL_DENSE_KC(false, true);
+            else DL_DENSE_KC(false, false);
+        }
+#undef DL_DENSE_KC
     }
 #undef DL_DENSE
     return hipGetLastError();

@@ -270,7 +270,8 @@ def test_argument_errors(dl):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,d,kind,k,nq", [(70_001, 128, "integer", 10, 150), (66_000, 37, "mixture", 20, 130),
-                                           (80_000, 96, "mixture", 100, 64), (65_600, 200, "mixture", 1, 257)])
+                                           (80_000, 96, "mixture", 100, 64), (65_600, 200, "mixture", 1, 257),
+                                           (65_857, 300, "mixture", 10, 140), (65_536, 962, "integer", 5, 70)])
 def test_dense_verification_equals_gathered(dl, n, d, kind, k, nq):
     """Survivors of the dense pass are re-ranked with the same FP32 direct
     distances as the gathered pass, so both return identical ids and bits."""
@@ -295,7 +296,7 @@ def test_dense_verification_equals_gathered(dl, n, d, kind, k, nq):
                              r["dists"][qi].cpu().numpy(), ref.S, k)
 
 
-@pytest.mark.parametrize("n,d,k", [(70_000, 128, 10), (66_000, 96, 25)])
+@pytest.mark.parametrize("n,d,k", [(70_000, 128, 10), (66_000, 96, 25), (66_000, 300, 10), (65_600, 960, 10)])
 def test_bf16_rerank_form(dl, n, d, k):
     """BF16 products with FP32 accumulation keep candidates by the rerank
     bound; the returned distances are exact FP32 distances of the returned
