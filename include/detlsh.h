@@ -68,6 +68,15 @@ enum {
     DETLSH_RMIN_FIXED = 1   /* Alg. 7 from the caller's r_min, radius r_min*c^t   */
 };
 
+/* Projection of the encoding phase. */
+enum {
+    DETLSH_PROJ_GAUSSIAN = 0,  /* the L*K hashes h_ij(o) = a_ij . o of Eq. 1, a ~ N(0,1)^d */
+    DETLSH_PROJ_PAA = 1        /* DET-ONLY (Sec. 6.1): one space (L = 1) of K PAA segment
+                                  means, segment j averaging coordinates
+                                  [j*floor(d/K), (j+1)*floor(d/K)); needs d >= K and
+                                  ignores A                                          */
+};
+
 /* ------------------------------------------------------------------------ */
 /* index build                                                              */
 /* ------------------------------------------------------------------------ */
@@ -78,7 +87,7 @@ typedef struct {
     int32_t max_leaf;           /* DE-Tree leaf capacity (Alg. 3 max_size); 0 -> 256 */
     int32_t keep_bf16;          /* 1: keep a BF16 copy of X for DETLSH_BF16_RERANK */
     int32_t proj_bf16;          /* 1: projection GEMM with BF16 inputs, FP32 sums  */
-    int32_t reserved;
+    int32_t projection;         /* DETLSH_PROJ_GAUSSIAN (0) or DETLSH_PROJ_PAA (1)  */
     const float* A;             /* host, (L*K) x d, row i*K+j = hash h_ij of Eq. 1,
                                    entries N(0,1); NULL -> drawn from `seed`       */
     const int64_t* sample_ids;  /* host, floor(sample_frac*n) distinct ids in [0,n)
@@ -215,6 +224,45 @@ typedef struct {
 detlsh_status detlsh_query(detlsh_index idx, const float* Q, int64_t nq, int32_t k,
                            double c, double beta, const detlsh_query_opts* opts,
                            int64_t* out_ids, float* out_dists, void* stream);
+
+/*
+ * (r, c)-ANN query (Alg. 6) for nq rows of Q (device, nq x d FP32) with one
+ * search radius r >= 0: the L spaces are visited in order, space i adding the
+ * points whose cell lies within eps*r of the projected query (the predicate of
+ * detlsh_query); as soon as |S| >= ceil(beta*n) + 1 (the paper's beta*n + 1)
+ * the point of S nearest to the query is returned; after all L spaces it is
+ * returned if some point of S lies within c*r; otherwise nothing.
+ * out_ids (device, nq int64) receives the point or -1 for nothing, out_dists
+ * (device, nq FP32) its Euclidean distance or +inf.  Ties by the smaller id.
+ * opts may be NULL; its precision must be DETLSH_FP32 (verification is the
+ * gathered FP32 form); its radius fields are ignored.  Limits: r >= 0,
+ * c > 1, 0 <= beta <= 1.
+ */
+detlsh_status detlsh_query_rc(detlsh_index idx, const float* Q, int64_t nq, double r, double c,
+                              double beta, const detlsh_query_opts* opts, int64_t* out_ids,
+                              float* out_dists, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* persistence                                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Write the index to a file (checkpoint): a header (n, d, L, K, N_r, n_s,
+ * max_leaf, BF16 options), then A, B, the sample ids, the codes and X, and a
+ * 64-bit checksum of the payload.  Derived arrays (trees, norms, BF16 copies,
+ * the guess subset) are not stored; detlsh_index_load rebuilds them from the
+ * codes, so a loaded index answers every query bit-identically.  path is a
+ * host string; an existing file is replaced.  DETLSH_EINVAL if the file cannot
+ * be written.
+ */
+detlsh_status detlsh_index_save(detlsh_index idx, const char* path);
+
+/*
+ * Read an index written by detlsh_index_save onto the current device.
+ * DETLSH_EINVAL for a file that is missing, truncated, of another format or
+ * whose checksum does not match; DETLSH_ENOMEM if it does not fit.
+ */
+detlsh_status detlsh_index_load(const char* path, void* stream, detlsh_index* out);
 
 /*
  * detlsh_query with every intermediate exposed, for step-by-step checks.

@@ -23,6 +23,9 @@ Everything is float64 NumPy.  Every function follows one passage of the paper:
   query_magic             Alg. 7 started at the smallest radius satisfying both
                           conditions of the "magic" r_min of Sec. 5.2 (R10)
   query_fixed             Alg. 7 literally, from a caller-given r_min
+  query_rc                Alg. 6, the (r, c)-ANN query with one search radius
+  paa_matrix              PAA segment means of DET-ONLY (Sec. 6.1), the L = 1
+                          projection that replaces the Gaussian hashes
   epsilon, beta_theory    Lemma 3 / Eq. 2
   brute_force_knn         Def. 2 with o_i* exact; ties broken by id (R13)
 
@@ -439,6 +442,58 @@ def query_fixed(X, q, qp, codes, B, L, K, k, beta, c, r_min, eps=None, max_round
             return QueryResult(ids, np.sqrt(d2), S, rad2, L, t + 1, first[S], 2)
         r *= c
     raise RuntimeError("radius ladder did not terminate")
+
+
+@dataclass
+class RcResult:
+    id: int                  # nearest point of S, or -1 when nothing is returned
+    dist: float              # its Euclidean distance, or +inf
+    S: np.ndarray            # candidate ids at the end, ascending
+    stop_tree: int           # tree after which |S| reached beta*n + 1 (0: not reached)
+    cond: int                # 1: |S| reached beta*n + 1, 2: a point of S within c r, 0: nothing
+
+
+def query_rc(X, q, qp, codes, B, L, K, r, c, beta, eps=None):
+    """The (r, c)-ANN query of Alg. 6: the L projected spaces are visited in
+    order; space i adds every point whose cell lies within eps*r of the
+    projected query (the range query of Alg. 4/5 with the R7 predicate); as soon
+    as S holds beta*n + 1 points (read as ceil(beta*n) + 1, R9 with k = 1) the
+    point of S nearest to q is returned.  After all L spaces, the nearest point
+    of S is returned if some point of S lies within c*r of q; otherwise nothing."""
+    X = np.asarray(X, np.float64)
+    n = X.shape[0]
+    if eps is None:
+        eps = epsilon(L, K)
+    need = n_stop(n, 1, beta)
+    lb = lower_bounds(qp, codes, B, L, K)
+    d2 = sq_dists(X, q)
+    rad2 = (eps * float(r)) ** 2
+    inS = np.zeros(n, bool)
+    for i in range(1, L + 1):
+        inS |= lb[:, i - 1] <= rad2
+        if int(inS.sum()) >= need:
+            S = np.flatnonzero(inS)
+            ids, dd = top_k(S, d2[S], 1)
+            return RcResult(int(ids[0]), float(np.sqrt(dd[0])), S, i, 1)
+    S = np.flatnonzero(inS)
+    if S.size and bool((d2[S] <= (c * float(r)) ** 2).any()):
+        ids, dd = top_k(S, d2[S], 1)
+        return RcResult(int(ids[0]), float(np.sqrt(dd[0])), S, 0, 2)
+    return RcResult(-1, math.inf, S, 0, 0)
+
+
+def paa_matrix(d: int, K: int) -> np.ndarray:
+    """Piecewise Aggregate Approximation used by DET-ONLY: K segments of
+    floor(d/K) consecutive coordinates each; row j averages segment j (the
+    d - K*floor(d/K) trailing coordinates belong to no segment).  As a
+    projection matrix it turns Eq. 1's h_j(o) = a_j . o into segment means."""
+    w = d // K
+    if w < 1:
+        raise ValueError("PAA needs d >= K")
+    A = np.zeros((K, d), np.float64)
+    for j in range(K):
+        A[j, j * w:(j + 1) * w] = 1.0 / w
+    return A
 
 
 def entry_steps(lb, eps, r_min, c, L, rounds):

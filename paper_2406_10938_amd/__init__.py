@@ -15,10 +15,10 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BF16_RERANK, FP32, RMIN_FIXED, RMIN_MAGIC, DetlshError, check, lib
+from ._lib import BF16_RERANK, FP32, PROJ_GAUSSIAN, PROJ_PAA, RMIN_FIXED, RMIN_MAGIC, DetlshError, check, lib
 
-__all__ = ["build_index", "import_index", "Index", "Server", "DetlshError", "FP32", "BF16_RERANK", "RMIN_MAGIC",
-           "RMIN_FIXED", "profile_enable", "profile_read"]
+__all__ = ["build_index", "import_index", "load_index", "Index", "Server", "DetlshError", "FP32", "BF16_RERANK",
+           "RMIN_MAGIC", "RMIN_FIXED", "PROJ_GAUSSIAN", "PROJ_PAA", "profile_enable", "profile_read"]
 
 
 def _torch():
@@ -46,8 +46,9 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep):
+def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, projection=PROJ_GAUSSIAN):
     o = _lib.BuildOpts()
+    o.projection = {"gaussian": PROJ_GAUSSIAN, "paa": PROJ_PAA}.get(projection, projection)
     o.seed = int(seed)
     o.max_leaf = int(max_leaf)
     o.keep_bf16 = int(bool(keep_bf16))
@@ -116,6 +117,22 @@ class Index:
         check(lib().detlsh_query(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
                                  _ptr(dists), _stream_ptr()))
         return ids, dists
+
+    def query_rc(self, Q, r, c=1.5, beta=0.1):
+        """(r, c)-ANN query (Alg. 6): per query the nearest point of S, or id -1
+        and distance +inf when the algorithm returns nothing."""
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        nq = Q.shape[0]
+        ids = torch.empty(nq, dtype=torch.int64, device=Q.device)
+        dists = torch.empty(nq, dtype=torch.float32, device=Q.device)
+        check(lib().detlsh_query_rc(self._h, _ptr(Q), nq, float(r), float(c), float(beta), None, _ptr(ids),
+                                    _ptr(dists), _stream_ptr()))
+        return ids, dists
+
+    def save(self, path):
+        """Write the index to `path` (rebuilt bit-identically by load_index)."""
+        check(lib().detlsh_index_save(self._h, str(path).encode()))
 
     def query_debug(self, Q, k, c=1.5, beta=0.1, Qp=None, cand_cap=None, precision=FP32, rerank_mult=4,
                     rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto"):
@@ -237,11 +254,12 @@ class Server:
 
 
 def build_index(X, L=4, K=16, N_r=256, sample_frac=0.01, A=None, sample_ids=None, seed=0, max_leaf=256,
-                keep_bf16=False, proj_bf16=False) -> Index:
-    """Encoding and indexing phases over X (n x d float32, device or host)."""
+                keep_bf16=False, proj_bf16=False, projection="gaussian") -> Index:
+    """Encoding and indexing phases over X (n x d float32, device or host).
+    projection="paa" with L=1 is DET-ONLY (PAA segment means)."""
     X = _dev_f32(X, "X")
     keep = []
-    o = _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep)
+    o = _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, projection)
     h = C.c_void_p()
     check(lib().detlsh_build_index(_ptr(X), X.shape[0], X.shape[1], int(L), int(K), int(N_r), float(sample_frac),
                                    C.byref(o), _stream_ptr(), C.byref(h)))
@@ -260,6 +278,13 @@ def import_index(X, A, B, codes, L, K, N_r, max_leaf=256, keep_bf16=False) -> In
     check(lib().detlsh_index_import(_ptr(X), X.shape[0], X.shape[1], int(L), int(K), int(N_r),
                                     A.ctypes.data_as(C.c_void_p), B.ctypes.data_as(C.c_void_p),
                                     codes.ctypes.data_as(C.c_void_p), C.byref(o), _stream_ptr(), C.byref(h)))
+    return Index(h)
+
+
+def load_index(path) -> Index:
+    """Index written by Index.save, on the current device."""
+    h = C.c_void_p()
+    check(lib().detlsh_index_load(str(path).encode(), _stream_ptr(), C.byref(h)))
     return Index(h)
 
 

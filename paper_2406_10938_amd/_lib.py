@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdetlsh.so")
 OK, EINVAL, ENOMEM, EBUSY, EDEVICE, ECANCELED, EINTERNAL = range(7)
 FP32, BF16_RERANK = 0, 1
 RMIN_MAGIC, RMIN_FIXED = 0, 1
+PROJ_GAUSSIAN, PROJ_PAA = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBUSY", 4: "EDEVICE", 5: "ECANCELED", 6: "EINTERNAL"}
 
@@ -23,7 +24,7 @@ class BuildOpts(C.Structure):
         ("max_leaf", C.c_int32),
         ("keep_bf16", C.c_int32),
         ("proj_bf16", C.c_int32),
-        ("reserved", C.c_int32),
+        ("projection", C.c_int32),
         ("A", C.POINTER(C.c_float)),
         ("sample_ids", C.POINTER(C.c_int64)),
     ]
@@ -80,6 +81,10 @@ SIGNATURES = {
                                P]),
     "detlsh_query_debug": (C.c_int, [P, P, P, C.c_int64, C.c_int32, C.c_double, C.c_double,
                                      C.POINTER(QueryOpts), P, C.c_int64, P, P, P, P, P, P, P, P]),
+    "detlsh_query_rc": (C.c_int, [P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(QueryOpts), P,
+                                  P, P]),
+    "detlsh_index_save": (C.c_int, [P, C.c_char_p]),
+    "detlsh_index_load": (C.c_int, [C.c_char_p, P, C.POINTER(P)]),
     "detlsh_profile_enable": (C.c_int, [C.c_int32, C.c_int32]),
     "detlsh_profile_read": (C.c_int, [C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.c_int32, C.POINTER(C.c_int32)]),

@@ -226,10 +226,13 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     return DETLSH_OK;
 }
 
+// X == NULL: ix->X and ix->codes are already allocated and filled (index load).
 detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_build_opts* opts, hipStream_t st) {
     const int64_t nd = ix->n * ix->d;
-    HCHECK(ix->X.alloc((size_t)nd * 4));
-    HCHECK(hipMemcpyAsync(ix->X.p, X, (size_t)nd * 4, hipMemcpyDeviceToDevice, st));
+    if (X) {
+        HCHECK(ix->X.alloc((size_t)nd * 4));
+        HCHECK(hipMemcpyAsync(ix->X.p, X, (size_t)nd * 4, hipMemcpyDeviceToDevice, st));
+    }
     const bool want_bf = opts && (opts->keep_bf16 || opts->proj_bf16);
     if (want_bf) {
         HCHECK(ix->Xbf.alloc((size_t)nd * 2));
@@ -244,7 +247,7 @@ detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_buil
     HCHECK(hipMemcpyAsync(ix->Abf.p, abf.data(), abf.size() * 2, hipMemcpyHostToDevice, st));
     HCHECK(ix->B.alloc((size_t)ix->LK * (ix->N_r + 1) * 4));
     HCHECK(ix->E.alloc((size_t)ix->LK * (ix->N_r + 1) * 4));
-    HCHECK(ix->codes.alloc((size_t)ix->n * ix->LK));
+    if (X) HCHECK(ix->codes.alloc((size_t)ix->n * ix->LK));
     HCHECK(ix->perm.alloc((size_t)ix->n * ix->L * 4));
     HCHECK(ix->scodes.alloc((size_t)ix->n * ix->LK));
     HCHECK(hipStreamSynchronize(st));   // abf leaves scope
@@ -281,8 +284,19 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
     ix->proj_bf16 = (opts && opts->proj_bf16) ? 1 : 0;
     const uint64_t seed = opts ? opts->seed : 0;
 
+    const int projection = opts ? opts->projection : DETLSH_PROJ_GAUSSIAN;
+    if (projection != DETLSH_PROJ_GAUSSIAN && projection != DETLSH_PROJ_PAA)
+        return fail(DETLSH_EINVAL, "projection %d is not defined", projection);
+    if (projection == DETLSH_PROJ_PAA && (L != 1 || d < K))
+        return fail(DETLSH_EINVAL, "the PAA projection needs L = 1 and d >= K, got L = %d, d = %d, K = %d", L, d, K);
     ix->A_host.resize((size_t)ix->LK * d);
-    if (opts && opts->A) {
+    if (projection == DETLSH_PROJ_PAA) {
+        // DET-ONLY: row j averages the j-th segment of floor(d/K) coordinates
+        const int w = d / K;
+        std::fill(ix->A_host.begin(), ix->A_host.end(), 0.0f);
+        for (int j = 0; j < K; ++j)
+            for (int c = j * w; c < (j + 1) * w; ++c) ix->A_host[(size_t)j * d + c] = (float)(1.0 / w);
+    } else if (opts && opts->A) {
         std::memcpy(ix->A_host.data(), opts->A, ix->A_host.size() * 4);
     } else {
         HostRng rng(seed);
@@ -396,6 +410,179 @@ detlsh_status detlsh_index_import(const float* X, int64_t n, int32_t d, int32_t 
     s = finish_index(ix, opts && opts->keep_bf16, st);
     if (s) return s;
     if (!(opts && opts->keep_bf16)) ix->Xbf.release();
+    HCHECK(hipStreamSynchronize(st));
+    prof_resolve();
+    *out = guard.release();
+    return DETLSH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// persistence: header, A, B, sample ids, codes ([L][n][K]), X, checksum
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+constexpr char kMagic[8] = {'D', 'E', 'T', 'L', 'S', 'H', 'I', 'X'};
+constexpr uint32_t kFormat = 1;
+
+struct FileHeader {
+    char magic[8];
+    uint32_t format;
+    uint32_t header_bytes;
+    int64_t n;
+    int32_t d, L, K, N_r;
+    int64_t n_s;
+    int32_t max_leaf, keep_bf16, proj_bf16, reserved;
+};
+
+// 64-bit checksum of the payload: FNV-1a over 8-byte words (tail bytes zero-padded).
+struct Checksum {
+    uint64_t h = 0xcbf29ce484222325ull;
+    uint8_t tail[8];
+    int nt = 0;
+    void add(const void* p, size_t b) {
+        const uint8_t* c = static_cast<const uint8_t*>(p);
+        while (b && nt) { tail[nt++] = *c++; --b; if (nt == 8) { word(tail); nt = 0; } }
+        while (b >= 8) { word(c); c += 8; b -= 8; }
+        while (b) { tail[nt++] = *c++; --b; }
+    }
+    void word(const uint8_t* w) {
+        uint64_t v;
+        std::memcpy(&v, w, 8);
+        h = (h ^ v) * 0x100000001b3ull;
+    }
+    uint64_t done() {
+        if (nt) { std::memset(tail + nt, 0, 8 - nt); word(tail); nt = 0; }
+        return h;
+    }
+};
+
+struct File {
+    FILE* f = nullptr;
+    ~File() { if (f) fclose(f); }
+};
+
+constexpr size_t kChunk = (size_t)64 << 20;
+
+// Writes `bytes` from a device or host buffer through a host staging chunk.
+detlsh_status put(File& fp, Checksum& ck, const void* src, size_t bytes, bool device) {
+    std::vector<uint8_t> buf;
+    const uint8_t* s8 = static_cast<const uint8_t*>(src);
+    for (size_t off = 0; off < bytes; off += kChunk) {
+        const size_t b = std::min(kChunk, bytes - off);
+        const uint8_t* p = s8 + off;
+        if (device) {
+            buf.resize(b);
+            HCHECK(hipMemcpy(buf.data(), p, b, hipMemcpyDeviceToHost));
+            p = buf.data();
+        }
+        ck.add(p, b);
+        if (fwrite(p, 1, b, fp.f) != b) return fail(DETLSH_EINVAL, "write failed");
+    }
+    return DETLSH_OK;
+}
+
+detlsh_status get(File& fp, Checksum& ck, void* dst, size_t bytes, bool device) {
+    std::vector<uint8_t> buf;
+    uint8_t* d8 = static_cast<uint8_t*>(dst);
+    for (size_t off = 0; off < bytes; off += kChunk) {
+        const size_t b = std::min(kChunk, bytes - off);
+        uint8_t* p = device ? (buf.resize(b), buf.data()) : d8 + off;
+        if (fread(p, 1, b, fp.f) != b) return fail(DETLSH_EINVAL, "the file is truncated");
+        ck.add(p, b);
+        if (device) HCHECK(hipMemcpy(d8 + off, p, b, hipMemcpyHostToDevice));
+    }
+    return DETLSH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+detlsh_status detlsh_index_save(detlsh_index ix, const char* path) {
+    g_err.clear();
+    if (!ix || !path) return fail(DETLSH_EINVAL, "NULL argument");
+    HCHECK(hipSetDevice(ix->device));
+    FileHeader h{};
+    std::memcpy(h.magic, kMagic, 8);
+    h.format = kFormat;
+    h.header_bytes = sizeof(FileHeader);
+    h.n = ix->n; h.d = ix->d; h.L = ix->L; h.K = ix->K; h.N_r = ix->N_r; h.n_s = ix->n_s;
+    h.max_leaf = ix->max_leaf; h.keep_bf16 = ix->Xbf.p ? 1 : 0; h.proj_bf16 = ix->proj_bf16;
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        File fp;
+        fp.f = fopen(tmp.c_str(), "wb");
+        if (!fp.f) return fail(DETLSH_EINVAL, "cannot open %s for writing", tmp.c_str());
+        if (fwrite(&h, sizeof h, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "write failed");
+        Checksum ck;
+        detlsh_status s;
+        if ((s = put(fp, ck, ix->A_host.data(), ix->A_host.size() * 4, false))) return s;
+        if ((s = put(fp, ck, ix->B.p, (size_t)ix->LK * (ix->N_r + 1) * 4, true))) return s;
+        if ((s = put(fp, ck, ix->sample_ids.data(), ix->sample_ids.size() * 8, false))) return s;
+        if ((s = put(fp, ck, ix->codes.p, (size_t)ix->n * ix->LK, true))) return s;
+        if ((s = put(fp, ck, ix->X.p, (size_t)ix->n * ix->d * 4, true))) return s;
+        const uint64_t sum = ck.done();
+        if (fwrite(&sum, 8, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "write failed");
+        if (fflush(fp.f) != 0) return fail(DETLSH_EINVAL, "write failed");
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return fail(DETLSH_EINVAL, "cannot replace %s", path);
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_index_load(const char* path, void* stream, detlsh_index* out) {
+    g_err.clear();
+    if (!out || !path) return fail(DETLSH_EINVAL, "NULL argument");
+    *out = nullptr;
+    File fp;
+    fp.f = fopen(path, "rb");
+    if (!fp.f) return fail(DETLSH_EINVAL, "cannot open %s", path);
+    FileHeader h{};
+    if (fread(&h, sizeof h, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "the file is truncated");
+    if (std::memcmp(h.magic, kMagic, 8) != 0 || h.format != kFormat || h.header_bytes != sizeof(FileHeader))
+        return fail(DETLSH_EINVAL, "%s is not an index file of this format", path);
+    detlsh_status s = check_shape(h.n, h.d, h.L, h.K, h.N_r);
+    if (s) return s;
+    if (h.n_s < 0 || h.n_s > h.n || h.max_leaf < 1) return fail(DETLSH_EINVAL, "corrupt header");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto* ix = new (std::nothrow) detlsh_index_s();
+    if (!ix) return fail(DETLSH_ENOMEM, "host allocation failed");
+    std::unique_ptr<detlsh_index_s> guard(ix);
+    HCHECK(hipGetDevice(&ix->device));
+    ix->n = h.n; ix->d = h.d; ix->L = h.L; ix->K = h.K; ix->N_r = h.N_r; ix->LK = h.L * h.K; ix->n_s = h.n_s;
+    ix->max_leaf = h.max_leaf;
+    ix->proj_bf16 = h.proj_bf16 ? 1 : 0;
+    Checksum ck;
+    ix->A_host.resize((size_t)ix->LK * ix->d);
+    if ((s = get(fp, ck, ix->A_host.data(), ix->A_host.size() * 4, false))) return s;
+    std::vector<float> B((size_t)ix->LK * (ix->N_r + 1));
+    if ((s = get(fp, ck, B.data(), B.size() * 4, false))) return s;
+    ix->sample_ids.resize((size_t)ix->n_s);
+    if ((s = get(fp, ck, ix->sample_ids.data(), ix->sample_ids.size() * 8, false))) return s;
+    if (ix->X.alloc((size_t)ix->n * ix->d * 4) != hipSuccess) return fail(DETLSH_ENOMEM, "X does not fit");
+    if (ix->codes.alloc((size_t)ix->n * ix->LK) != hipSuccess) return fail(DETLSH_ENOMEM, "codes do not fit");
+    if ((s = get(fp, ck, ix->codes.p, (size_t)ix->n * ix->LK, true))) return s;
+    if ((s = get(fp, ck, ix->X.p, (size_t)ix->n * ix->d * 4, true))) return s;
+    uint64_t sum = 0;
+    if (fread(&sum, 8, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "the file is truncated");
+    if (sum != ck.done()) return fail(DETLSH_EINVAL, "checksum mismatch: %s is corrupt", path);
+    const int N1 = ix->N_r + 1;
+    for (int e = 0; e < ix->LK; ++e)
+        for (int z = 1; z < N1; ++z)
+            if (!(B[(size_t)e * N1 + z] >= B[(size_t)e * N1 + z - 1]))
+                return fail(DETLSH_EINVAL, "breakpoint row %d is not non-decreasing", e);
+    detlsh_build_opts o{};
+    o.keep_bf16 = h.keep_bf16;
+    o.max_leaf = h.max_leaf;
+    s = alloc_common(ix, nullptr, &o, st);
+    if (s) return s;
+    HCHECK(hipMemcpyAsync(ix->B.p, B.data(), B.size() * 4, hipMemcpyHostToDevice, st));
+    HCHECK(dl_edges_from_breakpoints(ix->B.as<float>(), ix->E.as<float>(), ix->LK, ix->N_r, st));
+    HCHECK(hipStreamSynchronize(st));
+    s = finish_index(ix, h.keep_bf16 != 0, st);
+    if (s) return s;
     HCHECK(hipStreamSynchronize(st));
     prof_resolve();
     *out = guard.release();
@@ -773,7 +960,7 @@ struct QuerySetup {
 };
 
 detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, double c, double beta,
-                          const detlsh_query_opts* opts, QuerySetup& s) {
+                          const detlsh_query_opts* opts, QuerySetup& s, bool rc = false) {
     if (!ix) return fail(DETLSH_EINVAL, "NULL index");
     if (nq < 0) return fail(DETLSH_EINVAL, "nq < 0");
     if (k < 1 || (int64_t)k > ix->n || k > 1024)
@@ -795,7 +982,11 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
         return fail(DETLSH_EINVAL, "r_min policy %d is not defined", s.policy);
     s.rounds = (opts && opts->max_rounds > 0) ? opts->max_rounds : 64;
     if (s.policy == DETLSH_RMIN_FIXED) {
-        if (!(opts && opts->r_min > 0.0)) return fail(DETLSH_EINVAL, "FIXED r_min needs r_min > 0");
+        if (rc) {
+            if (!(opts && opts->r_min >= 0.0)) return fail(DETLSH_EINVAL, "the search radius must be >= 0");
+        } else if (!(opts && opts->r_min > 0.0)) {
+            return fail(DETLSH_EINVAL, "FIXED r_min needs r_min > 0");
+        }
         if (s.rounds > 64) return fail(DETLSH_EINVAL, "max_rounds must be <= 64, got %d", s.rounds);
     }
     QueryPlan& plan = s.plan;
@@ -850,12 +1041,15 @@ size_t query_arena_bytes(const detlsh_index_s* ix, const QuerySetup& s, int64_t 
     return b;
 }
 
+// rc: the (r, c)-ANN query of Alg. 6 (one round of the FIXED ladder, k = 1):
+// a query that meets neither stop condition returns nothing (-1, +inf)
+// instead of being answered over S = D.
 detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, int64_t nq, int32_t k, double c,
                          double beta, const detlsh_query_opts* opts, int64_t* out_ids, float* out_d,
-                         const Debug& dbg, const Arena* ext, hipStream_t st) {
+                         const Debug& dbg, const Arena* ext, hipStream_t st, bool rc = false) {
     g_err.clear();
     QuerySetup s;
-    if (detlsh_status e = setup_query(ix, nq, k, c, beta, opts, s)) return e;
+    if (detlsh_status e = setup_query(ix, nq, k, c, beta, opts, s, rc)) return e;
     if (nq == 0) return DETLSH_OK;
     if (!is_device_ptr(Q)) return fail(DETLSH_EINVAL, "Q must be a device pointer");
     if (!is_device_ptr(out_ids) || !is_device_ptr(out_d)) return fail(DETLSH_EINVAL, "outputs must be device pointers");
@@ -909,6 +1103,14 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     if (e) { prof_resolve(); return e; }
     const QueryPlan all_plan = all_points_plan(plan, ix->n);
     for (int64_t q = 0; q < nq; ++q) {
+        if (status[q] == 3 && rc) {
+            static const int64_t none = -1;
+            static const float far = INFINITY;
+            HCHECK(hipMemcpyAsync(out_ids + q, &none, 8, hipMemcpyHostToDevice, st));
+            HCHECK(hipMemcpyAsync(out_d + q, &far, 4, hipMemcpyHostToDevice, st));
+            HCHECK(hipStreamSynchronize(st));
+            continue;
+        }
         if (status[q] == 3) {
             std::vector<int32_t> st1(1, 0);
             e = run_queries(ix, Q, Qp, q, 1, k, all_plan, false, run_arena, out_ids, out_d, dbg, st1, st);
@@ -969,6 +1171,23 @@ detlsh_status detlsh_query(detlsh_index ix, const float* Q, int64_t nq, int32_t 
     Debug dbg;
     return query_impl(ix, nullptr, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, nullptr,
                       static_cast<hipStream_t>(stream));
+}
+
+detlsh_status detlsh_query_rc(detlsh_index ix, const float* Q, int64_t nq, double r, double c, double beta,
+                              const detlsh_query_opts* opts, int64_t* out_ids, float* out_dists, void* stream) {
+    g_err.clear();
+    if (opts && opts->precision != DETLSH_FP32)
+        return fail(DETLSH_EINVAL, "the (r, c)-ANN query verifies in FP32 only");
+    if (!(r >= 0.0) || !std::isfinite(r)) return fail(DETLSH_EINVAL, "the search radius must be finite and >= 0");
+    detlsh_query_opts o{};
+    if (opts) o = *opts;
+    o.precision = DETLSH_FP32;
+    o.rmin_policy = DETLSH_RMIN_FIXED;
+    o.r_min = r;
+    o.max_rounds = 1;
+    Debug dbg;
+    return query_impl(ix, nullptr, Q, nq, 1, c, beta, &o, out_ids, out_dists, dbg, nullptr,
+                      static_cast<hipStream_t>(stream), true);
 }
 
 detlsh_status detlsh_query_debug(detlsh_index ix, const float* Qp, const float* Q, int64_t nq, int32_t k, double c,

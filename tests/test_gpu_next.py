@@ -1,0 +1,181 @@
+"""GPU parity of the rows beyond the c^2-k-ANN path: the (r, c)-ANN query of
+Alg. 6, DET-ONLY's PAA projection (Sec. 6.1) and index save/load, through the
+C ABI against the FP64 oracle.
+
+Tolerances as for the main path: candidate membership may differ only for
+points whose FP64 bound lies within 1e-5 relative of (eps r)^2, and the answer
+only when a point's distance lies within 1e-5 relative of c*r or of the
+returned distance (near-ties); distances within 1e-5 relative.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gpu_util as U
+from oracle import detlsh_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2406_10938_amd as dl
+    dl._lib.lib()
+    return dl
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def t(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def _rc_borderline(X, q, qp, codes, B, L, K, r, c, eps):
+    lb = O.lower_bounds(np.asarray(qp, np.float64), codes, np.asarray(B, np.float64), L, K)
+    rad2 = (eps * r) ** 2
+    near_lb = np.abs(lb - rad2) <= U.REL * max(rad2, 1e-30)
+    d2 = O.sq_dists(X, q)
+    near_c = np.abs(d2 - (c * r) ** 2) <= U.REL * max((c * r) ** 2, 1e-30)
+    return bool(near_lb.any() or near_c.any())
+
+
+@pytest.mark.parametrize("c,kind", [(1.5, "mixture"), (2.0, "integer")])
+def test_rc_query_matches_oracle(dl, c, kind):
+    say(f"(r,c)-ANN c={c} kind={kind}")
+    cc = U.case(n=6000, d=48, N_r=64, frac=0.1, kind=kind, nq=16, seed=71)
+    idx = dl.build_index(cc["X"], 4, 16, 64, 0.1, A=cc["A"], sample_ids=cc["sample"])
+    ex = idx.export()
+    Q = t(cc["Q"])
+    Qp = idx.project(Q).cpu().numpy()
+    eps = O.epsilon(4, 16)
+    nn = np.array([math.sqrt(O.sq_dists(cc["X"], q).min()) for q in cc["Q"]])
+    conds = {0: 0, 1: 0, 2: 0}
+    skipped = 0
+    for scale in (0.25, 0.6, 1.0, 1.7):
+        for qi in range(len(cc["Q"])):
+            r = float(nn[qi] * scale)
+            ids, d = idx.query_rc(Q[qi:qi + 1], r, c, 0.1)
+            ref = O.query_rc(cc["X"], cc["Q"][qi], Qp[qi].astype(np.float64), ex["codes"],
+                             ex["B"].astype(np.float64), 4, 16, r, c, 0.1, eps)
+            if _rc_borderline(cc["X"], cc["Q"][qi], Qp[qi], ex["codes"], ex["B"], 4, 16, r, c, eps):
+                skipped += 1
+                continue
+            conds[ref.cond] += 1
+            got_id, got_d = int(ids.cpu()[0]), float(d.cpu()[0])
+            if ref.id < 0:
+                assert got_id == -1 and math.isinf(got_d), (qi, scale)
+                continue
+            assert got_d == pytest.approx(ref.dist, rel=U.REL, abs=1e-6)
+            if got_id != ref.id:   # only at a distance tie
+                assert abs(math.sqrt(O.sq_dists(cc["X"][[got_id]], cc["Q"][qi])[0]) - ref.dist) <= 1e-5 * ref.dist
+    say(f"  answers by condition (0 = nothing): {conds}; borderline cases skipped: {skipped}")
+    assert conds[0] > 0 and conds[1] + conds[2] > 0
+
+
+def test_rc_query_batched_equals_single(dl):
+    cc = U.case(n=5000, d=32, N_r=64, frac=0.1, nq=40, seed=72)
+    idx = dl.build_index(cc["X"], 4, 16, 64, 0.1, A=cc["A"], sample_ids=cc["sample"])
+    Q = t(cc["Q"])
+    r = float(np.median([math.sqrt(O.sq_dists(cc["X"], q).min()) for q in cc["Q"]]))
+    ids, d = idx.query_rc(Q, r, 1.5, 0.1)
+    for qi in (0, 13, 39):
+        i1, d1 = idx.query_rc(Q[qi:qi + 1], r, 1.5, 0.1)
+        assert int(i1.cpu()[0]) == int(ids.cpu()[qi])
+        assert float(d1.cpu()[0]) == float(d.cpu()[qi]) or (math.isinf(float(d1.cpu()[0])) and
+                                                           math.isinf(float(d.cpu()[qi])))
+
+
+def test_rc_zero_radius_and_errors(dl):
+    cc = U.case(n=4000, d=32, N_r=256, frac=0.1, nq=4, seed=73)
+    idx = dl.build_index(cc["X"], 4, 16, 256, 0.1, A=cc["A"], sample_ids=cc["sample"])
+    ids, d = idx.query_rc(t(cc["Q"]), 0.0, 1.5, 0.1)
+    assert np.all(ids.cpu().numpy() == -1) and np.all(np.isinf(d.cpu().numpy()))
+    own = t(cc["X"][[17, 250]])
+    ids, d = idx.query_rc(own, 0.0, 1.5, 0.1)
+    assert ids.cpu().numpy().tolist() == [17, 250] and np.all(d.cpu().numpy() == 0)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        idx.query_rc(own, -1.0, 1.5, 0.1)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        idx.query_rc(own, 1.0, 1.0, 0.1)
+
+
+@pytest.mark.parametrize("d,kind", [(128, "integer"), (100, "mixture")])
+def test_det_only_paa_matches_oracle(dl, d, kind):
+    """DET-ONLY: one space of K = 16 PAA segment means; projection, codes and
+    answers against the oracle's PAA on the GPU's encoding."""
+    say(f"DET-ONLY d={d} kind={kind}")
+    cc = U.case(n=8000, d=d, L=1, K=16, N_r=256, frac=0.1, kind=kind, nq=10, seed=74)
+    idx = dl.build_index(cc["X"], 1, 16, 256, 0.1, sample_ids=cc["sample"], projection="paa")
+    ex = idx.export()
+    A_ref = O.paa_matrix(d, 16)
+    assert np.array_equal(ex["A"], A_ref.astype(np.float32))
+    P = O.project(cc["X"], A_ref)
+    Pscale = U.proj_scale(cc["X"], A_ref)
+    Qp = idx.project(t(cc["Q"])).cpu().numpy()
+    Qp_ref = O.project(cc["Q"], A_ref)
+    assert np.all(np.abs(Qp - Qp_ref) <= U.REL * U.proj_scale(cc["Q"], A_ref) + 1e-30)
+    B_ref = O.breakpoints_by_sort(P[cc["sample"]], 256)
+    codes_ref = O.encode(P, B_ref)
+    nbad, hard = U.code_mismatches(P, Pscale, B_ref, ex["B"].astype(np.float64), codes_ref, ex["codes"])
+    say(f"  code mismatches {nbad} (non-borderline {hard})")
+    assert hard == 0
+    r = idx.query_debug(t(cc["Q"]), 10, 1.5, 0.1, Qp=t(Qp))
+    for qi in range(len(cc["Q"])):
+        ref = U.oracle_query(cc["X"], cc["Q"][qi], Qp[qi], ex["codes"], ex["B"], 1, 16, 10, 0.1)
+        S_gpu = set(r["cand"][qi, :int(r["counts"][qi])].cpu().numpy().tolist())
+        sym = S_gpu ^ set(ref.S.tolist())
+        assert sym <= U.borderline_points(Qp[qi], ex["codes"], ex["B"], 1, 16, ref.thr)
+        if not sym:
+            U.compare_result(ref.ids, ref.dists, cc["X"], cc["Q"][qi], r["ids"][qi].cpu().numpy(),
+                             r["dists"][qi].cpu().numpy(), ref.S, 10)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        dl.build_index(cc["X"], 4, 16, 256, 0.1, projection="paa")
+
+
+def test_save_load_roundtrip(dl, tmp_path):
+    say("save / load")
+    cc = U.case(n=9000, d=40, N_r=128, frac=0.05, kind="mixture", nq=30, seed=75)
+    idx = dl.build_index(cc["X"], 4, 16, 128, 0.05, A=cc["A"], sample_ids=cc["sample"], keep_bf16=True,
+                         max_leaf=64)
+    path = tmp_path / "index.detlsh"
+    idx.save(path)
+    back = dl.load_index(path)
+    a, b = idx.export(), back.export()
+    for key in ("A", "B", "codes", "sample_ids"):
+        assert np.array_equal(a[key], b[key]), key
+    assert idx.info["n_leaves"] == back.info["n_leaves"] and back.info["has_bf16"] and back.info["max_leaf"] == 64
+    for i in range(4):
+        for x, y in zip(idx.tree(i), back.tree(i)):
+            assert np.array_equal(x, y)
+    Q = t(cc["Q"])
+    for kw in ({}, {"precision": dl.BF16_RERANK}, {"rmin_policy": dl.RMIN_FIXED, "r_min": 0.5}):
+        i1, d1 = idx.query(Q, 10, 1.5, 0.1, **kw)
+        i2, d2 = back.query(Q, 10, 1.5, 0.1, **kw)
+        assert np.array_equal(i1.cpu().numpy(), i2.cpu().numpy())
+        assert np.array_equal(d1.cpu().numpy(), d2.cpu().numpy())
+    # a flipped byte, a truncated file, another format and a missing file are refused
+    raw = bytearray(path.read_bytes())
+    bad = tmp_path / "flipped.detlsh"
+    raw2 = bytearray(raw)
+    raw2[len(raw2) // 2] ^= 0x40
+    bad.write_bytes(bytes(raw2))
+    with pytest.raises(dl.DetlshError, match="checksum"):
+        dl.load_index(bad)
+    short = tmp_path / "short.detlsh"
+    short.write_bytes(bytes(raw[: len(raw) - 100]))
+    with pytest.raises(dl.DetlshError, match="truncated"):
+        dl.load_index(short)
+    other = tmp_path / "other.detlsh"
+    other.write_bytes(b"NOTANIDX" + bytes(raw[8:200]))
+    with pytest.raises(dl.DetlshError, match="format"):
+        dl.load_index(other)
+    with pytest.raises(dl.DetlshError, match="cannot open"):
+        dl.load_index(tmp_path / "missing.detlsh")
+    assert not os.path.exists(str(path) + ".tmp")
