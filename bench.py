@@ -279,6 +279,91 @@ def precision_bench(dl, torch, name, steps, warmup, ks):
     return out
 
 
+def next_rows_bench(dl, torch, steps, warmup):
+    """The rows beyond the c^2-k-ANN path on the SIFT-shaped set: DET-ONLY
+    (one PAA space) against DET-LSH, the (r, c)-ANN query (Alg. 6) at the median
+    nearest-neighbour distance, and save / load of the index."""
+    import tempfile
+
+    import synth
+    cfg = synth.config("C2")
+    dev = torch.device("cuda:0")
+    log("[next] generating C2")
+    X_host = synth.make_data(cfg)
+    Q_host = synth.make_queries(cfg)
+    X = torch.from_numpy(X_host).to(dev)
+    Q = torch.from_numpy(Q_host).to(dev)
+    A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
+    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
+    kth = ground_truth_kth(X, Q, 10)
+    nn = ground_truth_kth(X, Q, 1)
+    out = {"workload": "SIFT-shaped n=1,000,000 d=128, 10,000 queries"}
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    for name, kw in (("det_lsh", dict(L=cfg.L, A=A)), ("det_only", dict(L=1, projection="paa"))):
+        tb, ix = timed(lambda: dl.build_index(X, kw["L"], cfg.K, cfg.N_r, cfg.sample_frac, sample_ids=sample,
+                                              **{k: v for k, v in kw.items() if k != "L"}))
+        tq, (ids, _) = timed(lambda: ix.query(Q, 10, cfg.c, cfg.beta))
+        rec = recall_at_k(X, Q, ids, 10, kth)
+        out[name] = {"L": kw["L"], "build_ms": tb * 1e3, "build_mpts_s": cfg.n / tb / 1e6, "qps": cfg.nq / tq,
+                     "recall_at_10": rec}
+        log(f"[next] {name}: build {tb * 1e3:.1f} ms, {cfg.nq / tq:.0f} q/s, recall@10 {rec:.4f}")
+        if name == "det_lsh":
+            idx = ix
+        else:
+            ix.free()
+    r = float(nn.median())
+    for c in (1.5, 2.0):
+        tq, (ids, dists) = timed(lambda: idx.query_rc(Q, r, c, cfg.beta))
+        got = ids >= 0
+        ok = got & (dists.double() <= c * r * (1 + 1e-12))
+        has = nn <= r
+        out[f"rc_c{c}"] = {"r": r, "qps": cfg.nq / tq, "answered": float(got.double().mean()),
+                           "within_cr": float(ok.double().mean()),
+                           "within_cr_given_point_within_r": float((ok & has).double().sum() / has.double().sum())}
+        log(f"[next] (r,c)-ANN c={c} r={r:.2f}: {cfg.nq / tq:.0f} q/s, answered {float(got.double().mean()):.3f}")
+    # insertion into the built index: batches of SIFT-shaped rows from their own seed
+    ins = {}
+    for m in (10_000, 100_000):
+        Xn = torch.from_numpy(synth.sift_like(m, cfg.d, 7000 + m)).to(dev)
+        ixi = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ixi.insert(Xn)
+        torch.cuda.synchronize()
+        ti = time.perf_counter() - t0
+        ins[str(m)] = {"seconds": ti, "points_per_s": m / ti, "n_after": ixi.info["n"]}
+        log(f"[next] insert {m} into {cfg.n}: {ti * 1e3:.1f} ms, {m / ti / 1e6:.2f} M points/s")
+        ixi.free()
+    out["insert"] = ins
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "c2.detlsh")
+        t0 = time.perf_counter()
+        idx.save(path)
+        ts = time.perf_counter() - t0
+        size = os.path.getsize(path)
+        t0 = time.perf_counter()
+        back = dl.load_index(path)
+        tl = time.perf_counter() - t0
+        same = bool(torch.equal(back.query(Q[:256], 10, cfg.c, cfg.beta)[0], idx.query(Q[:256], 10, cfg.c,
+                                                                                      cfg.beta)[0]))
+        back.free()
+    out["save_load"] = {"bytes": size, "save_s": ts, "load_s": tl, "save_gb_s": size / ts / 1e9,
+                        "load_gb_s": size / tl / 1e9, "identical_answers": same}
+    log(f"[next] save {size / 1e6:.0f} MB in {ts:.2f} s, load in {tl:.2f} s, identical {same}")
+    idx.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,7 +381,7 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="print only the serving-form block")
     ap.add_argument("--beta-sweep", action="store_true",
                     help="also run the beta grid for QPS at recall@10 >= 0.9 (query only, both forms)")
-    ap.add_argument("--workload", choices=["c3", "c4"], default=None,
+    ap.add_argument("--workload", choices=["c3", "c4", "next"], default=None,
                     help="print only the named precision-form workload (d=960 copula / n=10^7 mixture)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (counter calibration)")
@@ -313,6 +398,9 @@ def main():
     torch.backends.cuda.matmul.allow_tf32 = False
     if args.serve_only:
         print(json.dumps(serve_bench(dl, torch, args.serve_requests)), flush=True)
+        return
+    if args.workload == "next":
+        print(json.dumps(next_rows_bench(dl, torch, args.steps, args.warmup)), flush=True)
         return
     if args.workload:
         name = args.workload.upper()

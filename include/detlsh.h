@@ -243,6 +243,21 @@ detlsh_status detlsh_query_rc(detlsh_index idx, const float* Q, int64_t nq, doub
                               float* out_dists, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* incremental insertion                                                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Append m points (X_new: device, m x d FP32) to the index; they get ids
+ * n .. n+m-1.  The encoding is frozen: the new points are projected with the
+ * index's A and encoded against its breakpoints (Alg. 2), the DE-Trees are
+ * rebuilt over all codes (bulk build, so the index equals one imported with
+ * the concatenated codes), and derived arrays follow.  X_new is copied.  Must
+ * not run concurrently with queries or servers on the index.  Limits: m >= 0
+ * (0 is a no-op), n + m < 2^31; DETLSH_ENOMEM leaves the index unchanged.
+ */
+detlsh_status detlsh_insert(detlsh_index idx, const float* X_new, int64_t m, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* persistence                                                              */
 /* ------------------------------------------------------------------------ */
 

@@ -24,6 +24,8 @@ Everything is float64 NumPy.  Every function follows one passage of the paper:
                           conditions of the "magic" r_min of Sec. 5.2 (R10)
   query_fixed             Alg. 7 literally, from a caller-given r_min
   query_rc                Alg. 6, the (r, c)-ANN query with one search radius
+  insert                  points added after the encoding phase (Alg. 3 inserts
+                          point by point; the breakpoints stay as built)
   paa_matrix              PAA segment means of DET-ONLY (Sec. 6.1), the L = 1
                           projection that replaces the Gaussian hashes
   epsilon, beta_theory    Lemma 3 / Eq. 2
@@ -529,6 +531,15 @@ class Index:
     L: int
     K: int
     N_r: int
+
+
+def insert(idx: Index, X_new) -> Index:
+    """Points added after the encoding phase: they are projected with the same
+    hashes and encoded against the existing breakpoints (Alg. 2), and their
+    codes join the index (the trees, built from codes by Alg. 3, take them in
+    like any other point)."""
+    new = encode(project(X_new, idx.A), idx.B)
+    return Index(idx.A, idx.B, np.concatenate([idx.codes, new]), idx.L, idx.K, idx.N_r)
 
 
 def build_index(X, A, sample, L, K, N_r):

@@ -130,6 +130,11 @@ class Index:
                                     _ptr(dists), _stream_ptr()))
         return ids, dists
 
+    def insert(self, X_new):
+        """Append rows (ids n..n+m-1), encoded with the frozen breakpoints."""
+        X_new = _dev_f32(X_new, "X_new")
+        check(lib().detlsh_insert(self._h, _ptr(X_new), X_new.shape[0], _stream_ptr()))
+
     def save(self, path):
         """Write the index to `path` (rebuilt bit-identically by load_index)."""
         check(lib().detlsh_index_save(self._h, str(path).encode()))

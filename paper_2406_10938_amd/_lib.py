@@ -83,6 +83,7 @@ SIGNATURES = {
                                      C.POINTER(QueryOpts), P, C.c_int64, P, P, P, P, P, P, P, P]),
     "detlsh_query_rc": (C.c_int, [P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(QueryOpts), P,
                                   P, P]),
+    "detlsh_insert": (C.c_int, [P, P, C.c_int64, P]),
     "detlsh_index_save": (C.c_int, [P, C.c_char_p]),
     "detlsh_index_load": (C.c_int, [C.c_char_p, P, C.POINTER(P)]),
     "detlsh_profile_enable": (C.c_int, [C.c_int32, C.c_int32]),

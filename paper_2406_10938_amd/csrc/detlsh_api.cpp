@@ -501,6 +501,68 @@ detlsh_status get(File& fp, Checksum& ck, void* dst, size_t bytes, bool device) 
 
 extern "C" {
 
+detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void* stream) {
+    g_err.clear();
+    if (!ix) return fail(DETLSH_EINVAL, "NULL index");
+    if (m < 0) return fail(DETLSH_EINVAL, "m < 0");
+    if (m == 0) return DETLSH_OK;
+    if (ix->n + m >= ((int64_t)1 << 31)) return fail(DETLSH_EINVAL, "n + m must stay below 2^31");
+    if (!is_device_ptr(X_new)) return fail(DETLSH_EINVAL, "X_new must be a device pointer");
+    HCHECK(hipSetDevice(ix->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n0 = ix->n, n1 = n0 + m;
+    const int d = ix->d;
+    const bool keep_bf16 = ix->Xbf.p != nullptr;
+    // new arrays first: on failure the index is untouched
+    DevBuf X, codes, Xbf, newbf;
+    if (X.alloc((size_t)n1 * d * 4) != hipSuccess || codes.alloc((size_t)n1 * ix->LK) != hipSuccess ||
+        (keep_bf16 && Xbf.alloc((size_t)n1 * d * 2) != hipSuccess) ||
+        (ix->proj_bf16 && !keep_bf16 && newbf.alloc((size_t)m * d * 2) != hipSuccess))
+        return fail(DETLSH_ENOMEM, "no room for %lld more points", (long long)m);
+    HCHECK(hipMemcpyAsync(X.p, ix->X.p, (size_t)n0 * d * 4, hipMemcpyDeviceToDevice, st));
+    HCHECK(hipMemcpyAsync(X.as<float>() + n0 * d, X_new, (size_t)m * d * 4, hipMemcpyDeviceToDevice, st));
+    // codes [L][n][K]: each tree's block grows from n0 to n1 words
+    HCHECK(hipMemcpy2DAsync(codes.p, (size_t)n1 * ix->K, ix->codes.p, (size_t)n0 * ix->K, (size_t)n0 * ix->K,
+                            ix->L, hipMemcpyDeviceToDevice, st));
+    const uint16_t* bf_new = nullptr;
+    if (keep_bf16) {
+        HCHECK(hipMemcpyAsync(Xbf.p, ix->Xbf.p, (size_t)n0 * d * 2, hipMemcpyDeviceToDevice, st));
+        HCHECK(dl_launch_to_bf16(X.as<float>() + n0 * d, Xbf.as<uint16_t>() + n0 * d, m * d, st));
+        bf_new = Xbf.as<uint16_t>() + n0 * d;
+    } else if (ix->proj_bf16) {
+        HCHECK(dl_launch_to_bf16(X.as<float>() + n0 * d, newbf.as<uint16_t>(), m * d, st));
+        bf_new = newbf.as<uint16_t>();
+    }
+    {
+        ProjectArgs pa;
+        pa.X = X.as<float>() + n0 * d; pa.Xbf = bf_new; pa.M = m; pa.d = d;
+        pa.A = ix->A.as<float>(); pa.Abf = ix->Abf.as<uint16_t>(); pa.N = ix->LK; pa.bf16 = ix->proj_bf16;
+        pa.E = ix->E.as<float>(); pa.N_r = ix->N_r; pa.K = ix->K;
+        pa.codes = codes.as<uint8_t>() + n0 * ix->K; pa.n_codes = n1;   // rows n0.. of every tree block
+        DlTimer tm(T_ENCODE, st);
+        HCHECK(dl_launch_project(pa, PROJ_ENCODE, st));
+    }
+    HCHECK(hipStreamSynchronize(st));
+    std::swap(ix->X.p, X.p); std::swap(ix->X.bytes, X.bytes);
+    std::swap(ix->codes.p, codes.p); std::swap(ix->codes.bytes, codes.bytes);
+    if (keep_bf16) { std::swap(ix->Xbf.p, Xbf.p); std::swap(ix->Xbf.bytes, Xbf.bytes); }
+    ix->n = n1;
+    for (int i = 0; i < 8; ++i) {
+        if (ix->leaf_start[i]) (void)hipFree(ix->leaf_start[i]);
+        if (ix->leaf_lo[i]) (void)hipFree(ix->leaf_lo[i]);
+        if (ix->leaf_hi[i]) (void)hipFree(ix->leaf_hi[i]);
+        ix->leaf_start[i] = nullptr; ix->leaf_lo[i] = nullptr; ix->leaf_hi[i] = nullptr;
+        ix->n_leaves[i] = 0;
+    }
+    HCHECK(ix->perm.alloc((size_t)n1 * ix->L * 4));
+    HCHECK(ix->scodes.alloc((size_t)n1 * ix->LK));
+    detlsh_status s = finish_index(ix, keep_bf16, st);
+    if (s) return s;
+    HCHECK(hipStreamSynchronize(st));
+    prof_resolve();
+    return DETLSH_OK;
+}
+
 detlsh_status detlsh_index_save(detlsh_index ix, const char* path) {
     g_err.clear();
     if (!ix || !path) return fail(DETLSH_EINVAL, "NULL argument");

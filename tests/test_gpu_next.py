@@ -179,3 +179,57 @@ def test_save_load_roundtrip(dl, tmp_path):
     with pytest.raises(dl.DetlshError, match="cannot open"):
         dl.load_index(tmp_path / "missing.detlsh")
     assert not os.path.exists(str(path) + ".tmp")
+
+
+@pytest.mark.parametrize("keep_bf16", [False, True])
+def test_insert_equals_import_of_the_union(dl, keep_bf16):
+    """Points inserted after the build are encoded against the frozen
+    breakpoints (codes bit-exact with the oracle's except borderline
+    coordinates); the index then equals one imported from the concatenated
+    codes: same trees and bit-identical answers.  Two batches = one batch."""
+    say(f"insert keep_bf16={keep_bf16}")
+    cc = U.case(n=9000, d=48, N_r=128, frac=0.1, kind="mixture", nq=24, seed=76)
+    n1 = 6000
+    X1, X2 = cc["X"][:n1], cc["X"][n1:]
+    sample = cc["sample"][cc["sample"] < n1][: max(128, int(0.1 * n1))]
+    build = dict(A=cc["A"], sample_ids=sample, keep_bf16=keep_bf16)
+    idx = dl.build_index(X1, 4, 16, 128, len(sample) / n1, **build)
+    before = idx.export()
+    idx.insert(X2[:1234])
+    idx.insert(X2[1234:])
+    one = dl.build_index(X1, 4, 16, 128, len(sample) / n1, **build)
+    one.insert(X2)
+    ex = idx.export()
+    assert idx.info["n"] == 9000 and np.array_equal(ex["B"], before["B"])
+    assert np.array_equal(ex["codes"][:n1], before["codes"])
+    assert np.array_equal(ex["codes"], one.export()["codes"])
+    P2 = O.project(X2, cc["A"])
+    ref = O.encode(P2, ex["B"].astype(np.float64))
+    nbad, hard = U.code_mismatches(P2, U.proj_scale(X2, cc["A"]), ex["B"].astype(np.float64),
+                                   ex["B"].astype(np.float64), ref, ex["codes"][n1:])
+    say(f"  new-point code mismatches {nbad} (non-borderline {hard})")
+    assert hard == 0
+    imp = dl.import_index(cc["X"], cc["A"], ex["B"], ex["codes"], 4, 16, 128, keep_bf16=keep_bf16)
+    assert idx.info["n_leaves"] == imp.info["n_leaves"]
+    for i in range(4):
+        for x, y in zip(idx.tree(i), imp.tree(i)):
+            assert np.array_equal(x, y)
+    Q = t(cc["Q"])
+    forms = [{}] + ([{"precision": dl.BF16_RERANK}] if keep_bf16 else [])
+    for kw in forms:
+        a = idx.query(Q, 10, 1.5, 0.1, **kw)
+        b = imp.query(Q, 10, 1.5, 0.1, **kw)
+        assert all(np.array_equal(u.cpu().numpy(), v.cpu().numpy()) for u, v in zip(a, b))
+    # and against the oracle on that encoding
+    Qp = idx.project(Q).cpu().numpy()
+    r = idx.query_debug(Q, 10, 1.5, 0.1, Qp=t(Qp))
+    for qi in range(len(cc["Q"])):
+        ref_q = U.oracle_query(cc["X"], cc["Q"][qi], Qp[qi], ex["codes"], ex["B"], 4, 16, 10, 0.1)
+        S_gpu = set(r["cand"][qi, :int(r["counts"][qi])].cpu().numpy().tolist())
+        sym = S_gpu ^ set(ref_q.S.tolist())
+        assert sym <= U.borderline_points(Qp[qi], ex["codes"], ex["B"], 4, 16, ref_q.thr)
+        if not sym:
+            U.compare_result(ref_q.ids, ref_q.dists, cc["X"], cc["Q"][qi], r["ids"][qi].cpu().numpy(),
+                             r["dists"][qi].cpu().numpy(), ref_q.S, 10)
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        dl._lib.check(dl._lib.lib().detlsh_insert(idx._h, X2.ctypes.data_as(dl.C.c_void_p), 5, None))

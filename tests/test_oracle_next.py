@@ -145,3 +145,32 @@ def test_planted_paa_window_off_by_one_is_caught(monkeypatch):
     monkeypatch.setattr(O, "paa_matrix", paa_shifted)
     with pytest.raises(AssertionError):
         test_paa_rows_are_segment_means()
+
+
+def test_insert_with_frozen_breakpoints():
+    """Inserted points are encoded against the built breakpoints: in any split
+    the codes equal one encoding of the union with those breakpoints, the
+    breakpoints stay, and the rebuilt trees partition all points."""
+    X, idx, _ = make_problem(n=1500, d=24, K=8, N_r=16, frac=0.2, seed=8)
+    new = synth.gaussian_mixture(700, X.shape[1], 8, 3.0, 1.0, 508, rows_seed=908)
+    one = O.insert(idx, new)
+    two = O.insert(O.insert(idx, new[:300]), new[300:])
+    assert np.array_equal(one.codes, two.codes) and np.array_equal(one.B, idx.B)
+    union = O.encode(O.project(np.concatenate([X, new]), idx.A), idx.B)
+    assert np.array_equal(one.codes, union)
+    trees = O.build_trees(one.codes, one.L, one.K, one.N_r, 32)
+    for leaves in trees:
+        ids = np.sort(np.concatenate([lf.ids for lf in leaves]))
+        assert np.array_equal(ids, np.arange(len(union)))
+
+
+def test_planted_insert_with_refreshed_breakpoints_is_caught(monkeypatch):
+    real = O.insert
+
+    def refreshed(idx, X_new):
+        out = real(idx, X_new)
+        B = O.breakpoints_by_sort(O.project(X_new, idx.A), idx.N_r)
+        return O.Index(idx.A, B, out.codes, idx.L, idx.K, idx.N_r)
+    monkeypatch.setattr(O, "insert", refreshed)
+    with pytest.raises(AssertionError):
+        test_insert_with_frozen_breakpoints()
