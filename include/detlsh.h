@@ -184,8 +184,19 @@ typedef struct {
     size_t workspace_bytes;     /* per-call workspace budget; 0 -> 4 GiB             */
     int32_t verify;             /* candidate verification: 0 automatic, 1 gathered
                                    rows of S, 2 masked dense MFMA over all rows     */
-    int32_t reserved;
+    int32_t granularity;        /* DETLSH_POINT (0): a point enters by its cell's
+                                   bound; DETLSH_LEAF (1): by its DE-Tree leaf's box
+                                   (the query-phase optimisation; MAGIC only)       */
 } detlsh_query_opts;
+
+/* Candidate granularity of the range query. */
+enum {
+    DETLSH_POINT = 0,
+    DETLSH_LEAF = 1             /* a leaf whose bound is within the radius gives all
+                                   its points; the stop tree's leaves are taken in
+                                   order of (bound, smallest point id) until |S|
+                                   reaches N_S, so the query may stop inside a tree */
+};
 
 /*
  * c^2-k-ANN query (Alg. 7) for nq rows of Q (device, nq x d FP32).

@@ -23,6 +23,9 @@ Everything is float64 NumPy.  Every function follows one passage of the paper:
   query_magic             Alg. 7 started at the smallest radius satisfying both
                           conditions of the "magic" r_min of Sec. 5.2 (R10)
   query_fixed             Alg. 7 literally, from a caller-given r_min
+  query_magic_leaf        Alg. 7 with the query-phase optimisation of the
+                          experiments (leaves admitted whole by their bound, in
+                          bound order, condition 1 checked after every leaf)
   query_rc                Alg. 6, the (r, c)-ANN query with one search radius
   insert                  points added after the encoding phase (Alg. 3 inserts
                           point by point; the breakpoints stay as built)
@@ -410,6 +413,65 @@ def query_magic(X, q, qp, codes, B, L, K, k, beta):
     S = np.flatnonzero(first <= stop)
     ids, d2 = top_k(S, sq_dists(X[S], q), k)
     return QueryResult(ids, np.sqrt(d2), S, thr, stop, 1, first[S], 1)
+
+
+def leaf_bounds(qp, trees, B, L, K):
+    """Per point and tree: the squared bound of the point's leaf box (R6 on the
+    leaf's prefix box) and the smallest id of that leaf."""
+    n = sum(len(lf.ids) for lf in trees[0])
+    lb = np.full((n, L), math.inf)
+    leafmin = np.zeros((n, L), np.int64)
+    for i in range(L):
+        qi, Bi = np.asarray(qp, np.float64)[i * K:(i + 1) * K], B[i * K:(i + 1) * K]
+        for lf in trees[i]:
+            lb[lf.ids, i] = node_lb2(qi, lf.lo, lf.hi, Bi)
+            leafmin[lf.ids, i] = int(lf.ids.min())
+    return lb, leafmin
+
+
+def leaf_queue(qp_i, leaves, B_i, radius2):
+    """The admitted leaves of one tree (bound within the radius) in the order a
+    priority queue on the bound releases them (ties by smallest point id)."""
+    queue = []
+    for lf in leaves:
+        b = node_lb2(qp_i, lf.lo, lf.hi, B_i)
+        if b <= radius2:
+            queue.append((b, int(lf.ids.min()), lf.ids))
+    queue.sort(key=lambda e: (e[0], e[1]))
+    return [ids for _, _, ids in queue]
+
+
+def query_magic_leaf(X, q, qp, codes, B, trees, L, K, k, beta):
+    """Alg. 7 with the optimisation of the query phase: a leaf whose lower
+    bound is within the radius contributes all its points (relaxed candidate
+    test), the admitted leaves of a tree are taken in ascending order of their
+    bound (a priority queue; ties by the leaf's smallest point id), and
+    condition 1 is checked after every leaf, so the query can stop inside a
+    tree.  Started from the magic radius on leaf bounds (R10 with the leaf box
+    in place of the cell): the smallest radius at which the union of admitted
+    leaves over the L trees holds N_S points."""
+    X = np.asarray(X, np.float64)
+    n = X.shape[0]
+    N_S = n_stop(n, k, beta)
+    if N_S >= n:
+        S = np.arange(n)
+        ids, d2 = top_k(S, sq_dists(X[S], q), k)
+        return QueryResult(ids, np.sqrt(d2), S, math.inf, L, 1, np.ones(n, np.int64), 0)
+    lb, _ = leaf_bounds(qp, trees, B, L, K)
+    thr = float(np.sort(lb.min(axis=1), kind="stable")[N_S - 1])
+    inS = np.zeros(n, bool)
+    first = np.full(n, L + 1, np.int64)
+    for i in range(1, L + 1):
+        qi, Bi = np.asarray(qp, np.float64)[(i - 1) * K:i * K], B[(i - 1) * K:i * K]
+        for ids in leaf_queue(qi, trees[i - 1], Bi, thr):
+            new = ids[~inS[ids]]
+            inS[new] = True
+            first[new] = i
+            if int(inS.sum()) >= N_S:
+                S = np.flatnonzero(inS)
+                top, d2 = top_k(S, sq_dists(X[S], q), k)
+                return QueryResult(top, np.sqrt(d2), S, thr, i, 1, first[S], 1)
+    raise AssertionError("the magic radius admits N_S points")
 
 
 def query_fixed(X, q, qp, codes, B, L, K, k, beta, c, r_min, eps=None, max_rounds=10_000):

@@ -64,8 +64,10 @@ def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, proje
     return o
 
 
-def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify=0):
+def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify=0,
+                granularity="point"):
     o = _lib.QueryOpts()
+    o.granularity = {"point": 0, "leaf": 1}.get(granularity, granularity)
     o.verify = {"auto": 0, "gather": 1, "dense": 2}.get(verify, verify)
     o.precision = int(precision)
     o.rerank_mult = int(rerank_mult)
@@ -107,13 +109,13 @@ class Index:
         return out
 
     def query(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC,
-              r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto"):
+              r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto", granularity="point"):
         torch = _torch()
         Q = _dev_f32(Q, "Q")
         nq = Q.shape[0]
         ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
         dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity)
         check(lib().detlsh_query(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
                                  _ptr(dists), _stream_ptr()))
         return ids, dists
@@ -140,7 +142,8 @@ class Index:
         check(lib().detlsh_index_save(self._h, str(path).encode()))
 
     def query_debug(self, Q, k, c=1.5, beta=0.1, Qp=None, cand_cap=None, precision=FP32, rerank_mult=4,
-                    rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto"):
+                    rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto",
+                    granularity="point"):
         """Query that also returns S, first trees, thr, stop tree and rounds."""
         torch = _torch()
         Q = _dev_f32(Q, "Q")
@@ -160,7 +163,7 @@ class Index:
         if Qp is not None:
             Qp = _dev_f32(Qp, "Qp")
             qp_ptr = _ptr(Qp)
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity)
         check(lib().detlsh_query_debug(self._h, qp_ptr, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o),
                                        _ptr(cand), cap, _ptr(counts), _ptr(first), _ptr(thr), _ptr(stop),
                                        _ptr(rounds), _ptr(ids), _ptr(dists), _stream_ptr()))
@@ -218,7 +221,7 @@ class Server:
             self._live = {}
 
     def submit(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC, r_min=0.0,
-               max_rounds=0, verify="auto", sync=True) -> int:
+               max_rounds=0, verify="auto", granularity="point", sync=True) -> int:
         """Queue Q (nq x d) for k-ANN; the server reads Q on its own streams, so
         with sync=True the current stream is synchronised first."""
         torch = _torch()
@@ -228,7 +231,7 @@ class Server:
         dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         if sync:
             torch.cuda.current_stream().synchronize()
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, 0, verify)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, 0, verify, granularity)
         t = C.c_uint64()
         check(lib().detlsh_server_submit(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
                                          _ptr(dists), C.byref(t)))

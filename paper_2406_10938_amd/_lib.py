@@ -39,7 +39,7 @@ class QueryOpts(C.Structure):
         ("r_min", C.c_double),
         ("workspace_bytes", C.c_size_t),
         ("verify", C.c_int32),
-        ("reserved", C.c_int32),
+        ("granularity", C.c_int32),
     ]
 
 

@@ -168,7 +168,7 @@ struct detlsh_index_s {
     int64_t n_s = 0;
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
-    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes;
+    DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
     int32_t G = 0;                // guess subset size, min(n, kGuessMax)
     std::vector<int64_t> sample_ids;
     std::vector<float> A_host;
@@ -185,7 +185,7 @@ struct detlsh_index_s {
     }
     size_t bytes() const {
         size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
-                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes;
+                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes + leaf_of.bytes + gleaf.bytes;
         for (int i = 0; i < L; ++i) b += (size_t)(n_leaves[i] + 1) * 4 + 2 * (size_t)n_leaves[i] * K;
         return b;
     }
@@ -223,6 +223,14 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
                              &ix->leaf_start[i], &ix->leaf_lo[i], &ix->leaf_hi[i]));
         HCHECK(hipStreamSynchronize(st));
     }
+    // point -> leaf of every tree, and the leaves of the guess subset
+    HCHECK(ix->leaf_of.alloc((size_t)ix->n * ix->L * 4));
+    HCHECK(ix->gleaf.alloc((size_t)ix->G * ix->L * 4));
+    for (int i = 0; i < ix->L; ++i)
+        HCHECK(dl_launch_leaf_of(ix->perm.as<int32_t>() + (int64_t)i * ix->n, ix->leaf_start[i], ix->n_leaves[i],
+                                 ix->n, ix->leaf_of.as<int32_t>() + (int64_t)i * ix->n, st));
+    HCHECK(dl_launch_pack_sample_leaves(ix->leaf_of.as<int32_t>(), ix->n, ix->L, ix->G, ix->gleaf.as<int32_t>(), st));
+    HCHECK(hipStreamSynchronize(st));
     return DETLSH_OK;
 }
 
@@ -760,6 +768,7 @@ struct QueryPlan {
     int64_t T = 0;          // members of S used for tau
     int64_t cap_sv = 0;     // survivor slots per query
     bool fixed = false;     // printed radius ladder from r_min
+    bool leaf = false;      // leaf-granularity candidates
     int rounds = 0;         // radius rounds before S = D
     const float* rad2 = nullptr;
     const float* c2 = nullptr;
@@ -873,7 +882,16 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     QueryArgs a;
     a.L = ix->L; a.K = ix->K; a.N_r = ix->N_r; a.d = ix->d; a.n = ix->n;
     a.E = ix->E.as<float>(); a.codes = ix->codes.as<uint8_t>(); a.X = ix->X.as<float>(); a.Xbf = ix->Xbf.as<uint16_t>();
-    a.Q = Q; a.Qp = Qp; a.G = plan.G; a.gcodes = ix->gcodes.as<uint8_t>(); a.guess_rank = plan.rank; a.N_S = plan.N_S; a.k = k; a.cap = cap;
+    a.Q = Q; a.Qp = Qp; a.G = plan.G; a.gcodes = ix->gcodes.as<uint8_t>(); a.guess_rank = plan.rank;
+    a.leaf = plan.leaf ? 1 : 0;
+    a.gleaf = ix->gleaf.as<int32_t>();
+    a.lt.leaf_of = ix->leaf_of.as<int32_t>();
+    a.lt.perm = ix->perm.as<int32_t>();
+    for (int i = 0; i < ix->L && i < 8; ++i) {
+        a.lt.start[i] = ix->leaf_start[i];
+        a.lt.lo[i] = ix->leaf_lo[i];
+        a.lt.hi[i] = ix->leaf_hi[i];
+    } a.N_S = plan.N_S; a.k = k; a.cap = cap;
     a.all_n = plan.all ? ix->n : 0;
     a.gthr = reinterpret_cast<float*>(take((size_t)nqc * 4));
     a.counts = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
@@ -1040,6 +1058,10 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
     if (s.precision == DETLSH_BF16_RERANK && (int64_t)s.rmult * k > 1024)
         return fail(DETLSH_EINVAL, "rerank_mult*k = %lld exceeds 1024", (long long)s.rmult * k);
     if (s.verify < 0 || s.verify > 2) return fail(DETLSH_EINVAL, "verify mode %d is not defined", s.verify);
+    const int gran = opts ? opts->granularity : DETLSH_POINT;
+    if (gran != DETLSH_POINT && gran != DETLSH_LEAF) return fail(DETLSH_EINVAL, "granularity %d is not defined", gran);
+    if (gran == DETLSH_LEAF && s.policy != DETLSH_RMIN_MAGIC)
+        return fail(DETLSH_EINVAL, "leaf granularity is defined for the magic radius only");
     if (s.policy != DETLSH_RMIN_MAGIC && s.policy != DETLSH_RMIN_FIXED)
         return fail(DETLSH_EINVAL, "r_min policy %d is not defined", s.policy);
     s.rounds = (opts && opts->max_rounds > 0) ? opts->max_rounds : 64;
@@ -1053,6 +1075,7 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
     }
     QueryPlan& plan = s.plan;
     plan = plan_query(ix->n, k, beta, ix->L);
+    plan.leaf = gran == DETLSH_LEAF;
     if (s.policy == DETLSH_RMIN_FIXED) {
         // radii r_t = r_min c^t (formed by repeated multiplication), squared
         // projected radius (eps r_t)^2 and squared verification radius (c r_t)^2

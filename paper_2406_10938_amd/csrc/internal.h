@@ -49,6 +49,17 @@ hipError_t dl_build_tree(const uint8_t* codes_i, int64_t n, int K, int N_r, int 
                          uint8_t** leaf_lo, uint8_t** leaf_hi);
 
 // ---- query (k_query.hip) ----
+// Leaf tables of the L DE-Trees: leaf_of[i*n + o] is the leaf of point o in
+// tree i; start[i] (leaves+1 offsets into perm + i*n), lo[i]/hi[i] (leaves x K
+// region codes of the leaf's prefix box).
+struct LeafTabs {
+    const int32_t* leaf_of = nullptr;
+    const int32_t* perm = nullptr;
+    const int32_t* start[8] = {};
+    const uint8_t* lo[8] = {};
+    const uint8_t* hi[8] = {};
+};
+
 struct QueryArgs {
     int L = 0, K = 0, N_r = 0, d = 0;
     int64_t n = 0;
@@ -62,6 +73,9 @@ struct QueryArgs {
     int nqc = 0;                     // queries in the chunk
     int G = 0;                       // guess subset size
     const uint8_t* gcodes = nullptr; // codes of the guess subset, [L][G][K]
+    const int32_t* gleaf = nullptr;  // leaves of the guess subset, [L][G]
+    int leaf = 0;                    // candidates by leaf boxes (leaf granularity)
+    LeafTabs lt;
     float* gm = nullptr;             // nqc x G guess values
     uint64_t guess_rank = 0;
     uint64_t N_S = 0;
@@ -106,6 +120,12 @@ struct QueryArgs {
 bool dl_supported_lk(int L, int K);
 size_t dl_verify_smem(int d);
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
+// leaf_of of one tree: out[perm[p]] = the leaf whose run holds position p.
+hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* out,
+                             hipStream_t st);
+// Leaves of the guess subset: out[i*G + p] = leaf_of[i*n + o_p].
+hipError_t dl_launch_pack_sample_leaves(const int32_t* leaf_of, int64_t n, int L, int G, int32_t* out,
+                                        hipStream_t st);
 // Packs the codes of the guess subset (G = min(n, 16384) points) as [L][G][K].
 hipError_t dl_launch_pack_sample(const uint8_t* codes, int64_t n, int L, int K, int G, uint8_t* out,
                                  hipStream_t st);

@@ -87,6 +87,34 @@ __device__ __forceinline__ float cell_lbs(const float* __restrict__ qp, const fl
     return m;
 }
 
+// Leaf granularity: the bounds of point o in every tree are those of its
+// leaf's prefix box, regions lo..hi of each dimension (leaf ids [L][stride]).
+template <int L, int K>
+__device__ __forceinline__ void load_box(const LeafTabs& lt, const int32_t* __restrict__ leaf_ids, int64_t stride,
+                                         int64_t o, const float* __restrict__ E, int ldE, float (&lo)[L * K],
+                                         float (&hi)[L * K]) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int64_t lf = leaf_ids[(int64_t)i * stride + o];
+        const uint32_t* wl = reinterpret_cast<const uint32_t*>(lt.lo[i] + lf * K);
+        const uint32_t* wh = reinterpret_cast<const uint32_t*>(lt.hi[i] + lf * K);
+        uint32_t a[K / 4], b[K / 4];
+#pragma unroll
+        for (int c = 0; c < K / 4; ++c) {
+            a[c] = wl[c];
+            b[c] = wh[c];
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int e = i * K + j;
+            const uint32_t cl = (a[j >> 2] >> (8 * (j & 3))) & 0xffu;
+            const uint32_t ch = (b[j >> 2] >> (8 * (j & 3))) & 0xffu;
+            lo[e] = E[e * ldE + cl];
+            hi[e] = E[e * ldE + ch + 1];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // block-level selection helpers (256 threads)
 // ---------------------------------------------------------------------------
@@ -137,8 +165,8 @@ __device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* 
     __syncthreads();
 }
 
-// Value of the r-th smallest (1-based) non-negative float among vals[0..m)
-// (global or LDS), by three radix passes (12, 12, 8 bits) over the bit pattern.
+// The r-th smallest (1-based) of m 32-bit keys get(0..m), by three radix
+// passes (12, 12, 8 bits).
 struct SelectShared {
     uint32_t hist[4096];
     uint32_t scratch[260];
@@ -147,7 +175,7 @@ struct SelectShared {
 };
 
 template <typename Get>
-__device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& sh) {
+__device__ uint32_t select_rank_u32(Get get, int64_t m, uint64_t r, SelectShared& sh) {
     uint32_t prefix = 0;
     int known = 0;
     const int nb_tab[3] = {12, 12, 8};
@@ -162,11 +190,10 @@ __device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& s
         };
         int64_t i = threadIdx.x;
         for (; i + 768 < m; i += 1024) {   // four loads in flight per thread
-            const uint32_t u0 = __float_as_uint(get(i)), u1 = __float_as_uint(get(i + 256));
-            const uint32_t u2 = __float_as_uint(get(i + 512)), u3 = __float_as_uint(get(i + 768));
+            const uint32_t u0 = get(i), u1 = get(i + 256), u2 = get(i + 512), u3 = get(i + 768);
             count(u0); count(u1); count(u2); count(u3);
         }
-        for (; i < m; i += 256) count(__float_as_uint(get(i)));
+        for (; i < m; i += 256) count(get(i));
         __syncthreads();
         find_bin(sh.hist, 4096, r, sh.scratch, &sh.d, &sh.before, &sh.total);
         r -= sh.before;
@@ -174,7 +201,14 @@ __device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& s
         known += nbits;
         __syncthreads();
     }
-    return __uint_as_float(prefix);
+    return prefix;
+}
+
+// Value of the r-th smallest (1-based) non-negative float among get(0..m):
+// radix selection on the bit patterns, which order like the values.
+template <typename Get>
+__device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& sh) {
+    return __uint_as_float(select_rank_u32([&](int64_t i) { return __float_as_uint(get(i)); }, m, r, sh));
 }
 
 // The k smallest of m unique 64-bit keys in buf (global), sorted ascending into
@@ -284,11 +318,12 @@ __global__ __launch_bounds__(256) void pack_sample_kernel(const uint8_t* __restr
 
 // m^2 of every guess point for the queries [blockIdx.y*q_per_block, ...):
 // one lane per point, its cell bounds in registers, gm[t*G + p].
-template <int L, int K>
+template <int L, int K, bool LEAF>
 __global__ __launch_bounds__(256) void guess_scan_kernel(const float* __restrict__ E, int N_r,
                                                          const uint8_t* __restrict__ gcodes, int G,
                                                          const float* __restrict__ Qp, int64_t q0, int nqc,
-                                                         int q_per_block, float* __restrict__ gm)
+                                                         int q_per_block, float* __restrict__ gm,
+                                                         const int32_t* __restrict__ gleaf, LeafTabs lt)
 {
     constexpr int LK = L * K;
     const int ldE = N_r + 1;
@@ -296,7 +331,8 @@ __global__ __launch_bounds__(256) void guess_scan_kernel(const float* __restrict
     const bool valid = p_raw < G;
     const int p = valid ? p_raw : G - 1;
     float lo[LK], hi[LK];
-    load_cell<L, K>(gcodes, G, p, E, ldE, lo, hi);
+    if (LEAF) load_box<L, K>(lt, gleaf, G, p, E, ldE, lo, hi);
+    else load_cell<L, K>(gcodes, G, p, E, ldE, lo, hi);
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
 #pragma unroll 1
@@ -365,7 +401,7 @@ __device__ __forceinline__ float entry_step(const float (&lb)[L], const float* _
     return e;
 }
 
-template <int L, int K, bool FIXED>
+template <int L, int K, bool FIXED, bool LEAF>
 __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E, int N_r,
                                                      const uint8_t* __restrict__ codes, int64_t n,
                                                      const float* __restrict__ Qp, int64_t q0, int nqc,
@@ -373,7 +409,7 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
                                                      uint32_t* __restrict__ counts, int64_t cap,
                                                      int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
                                                      float* __restrict__ cand_lb, uint64_t* __restrict__ bm,
-                                                     int64_t W, const float* __restrict__ rad2, int T)
+                                                     int64_t W, const float* __restrict__ rad2, int T, LeafTabs lt)
 {
     constexpr int LK = L * K;
     __shared__ FilterShared<L> sh;
@@ -389,7 +425,8 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     float lo[LK], hi[LK];
-    load_cell<L, K>(codes, n, o, E, ldE, lo, hi);
+    if (LEAF) load_box<L, K>(lt, lt.leaf_of, n, o, E, ldE, lo, hi);
+    else load_cell<L, K>(codes, n, o, E, ldE, lo, hi);
     __builtin_amdgcn_s_waitcnt(0);   // settle the cell bounds once, outside the query loop
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
@@ -481,14 +518,14 @@ __device__ __forceinline__ void load_lbs(const float* __restrict__ src, float (&
     }
 }
 
-template <int L, bool FIXED>
+template <int L, bool FIXED, bool LEAF>
 __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict__ counts, int64_t cap,
                                                      uint64_t N_S, int32_t* __restrict__ cand_id,
                                                      const float* __restrict__ cand_m,
                                                      int32_t* __restrict__ cand_ft, const float* __restrict__ cand_lb,
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
                                                      float* __restrict__ thr_out, int32_t* __restrict__ stop_out,
-                                                     uint64_t* __restrict__ bm, int64_t W)
+                                                     uint64_t* __restrict__ bm, int64_t W, LeafTabs lt, int64_t n)
 {
     __shared__ SelectShared sh;
     __shared__ uint32_t tc[8];
@@ -579,6 +616,35 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     int istop = L;
     for (int i = 0; i < L; ++i)
         if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
+    // Leaf granularity: the stop tree's admitted leaves are taken in order of
+    // (bound, smallest point id of the leaf) until |S| reaches N_S, so of the
+    // entries first admitted by tree istop those up to the key of the
+    // N'-th one (N' = N_S - |U_{istop-1}|) belong to S, whole leaves at a time.
+    uint32_t khi = 0xffffffffu, klo = 0xffffffffu;
+    auto bound_bits = [&](int64_t s) { return __float_as_uint(lbt[s * L + istop - 1]); };
+    auto leaf_min = [&](int32_t id) -> uint32_t {
+        const int64_t base = (int64_t)(istop - 1) * n;
+        const int32_t lf = lt.leaf_of[base + id];
+        return (uint32_t)lt.perm[base + lt.start[istop - 1][lf]];
+    };
+    if (LEAF) {
+        const uint64_t before = istop >= 2 ? (uint64_t)tc[istop - 2] : 0;
+        const uint64_t np = N_S - before;
+        khi = select_rank_u32([&](int64_t s) { return ftree[s] == istop ? bound_bits(s) : 0xffffffffu; },
+                              (int64_t)cnt, np, sh);
+        uint32_t below = 0;
+        for (int64_t s = threadIdx.x; s < (int64_t)cnt; s += 256)
+            below += (ftree[s] == istop && bound_bits(s) < khi) ? 1u : 0u;
+        below = dl_wave_sum(below);
+        if (threadIdx.x < 8) tc[threadIdx.x] = 0;   // reused as a block total
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) atomicAdd(&tc[0], below);
+        __syncthreads();
+        const uint64_t r2 = np - tc[0];
+        klo = select_rank_u32([&](int64_t s) {
+            return (ftree[s] == istop && bound_bits(s) == khi) ? leaf_min(ids[s]) : 0xffffffffu;
+        }, (int64_t)cnt, r2, sh);
+    }
     // in-place stable compaction of S = U_{istop}, with each member's first
     // admitting tree (every entry's f(o) was written above by this thread)
     uint32_t out = 0;
@@ -590,6 +656,10 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
             id = ids[s];
             ft = ftree[s];
             mem = (ft != 0 && ft <= istop);
+            if (LEAF && ft == istop) {
+                const uint32_t b = bound_bits(s);
+                mem = b < khi || (b == khi && leaf_min(id) <= klo);
+            }
             if (!mem && bm) atomicAnd((unsigned long long*)&bm[(int64_t)t * W + (id >> 6)], ~(1ull << (id & 63)));
         }
         uint32_t tot;
@@ -1321,15 +1391,19 @@ hipError_t launch_guess_lk(const QueryArgs& a, hipStream_t st) {
     if (ny > a.nqc) ny = a.nqc;
     const int qpb = (a.nqc + ny - 1) / ny;
     ny = (a.nqc + qpb - 1) / qpb;
-    hipLaunchKernelGGL((guess_scan_kernel<L, K>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E, a.N_r,
-                       a.gcodes, a.G, a.Qp, a.q0, a.nqc, qpb, a.gm);
+    if (a.leaf)
+        hipLaunchKernelGGL((guess_scan_kernel<L, K, true>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
+                           a.N_r, a.gcodes, a.G, a.Qp, a.q0, a.nqc, qpb, a.gm, a.gleaf, a.lt);
+    else
+        hipLaunchKernelGGL((guess_scan_kernel<L, K, false>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
+                           a.N_r, a.gcodes, a.G, a.Qp, a.q0, a.nqc, qpb, a.gm, a.gleaf, a.lt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(guess_select_kernel, dim3(a.nqc), dim3(256), 0, st, a.gm, a.G, a.guess_rank, a.gthr);
     return hipGetLastError();
 }
 
-template <int L, int K, bool FIXED>
+template <int L, int K, bool FIXED, bool LEAF>
 hipError_t launch_filter_lkf(const QueryArgs& a, hipStream_t st) {
     const int64_t pb = (a.n + 255) / 256;
     // about 64 queries per workgroup (measured best at n = 10^6, d = 128:
@@ -1338,16 +1412,17 @@ hipError_t launch_filter_lkf(const QueryArgs& a, hipStream_t st) {
     while (pb * ny < 4096 && ny < a.nqc) ny *= 2;
     if (ny > a.nqc) ny = a.nqc;
     const int qpb = (a.nqc + ny - 1) / ny;
-    hipLaunchKernelGGL((filter_kernel<L, K, FIXED>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
+    hipLaunchKernelGGL((filter_kernel<L, K, FIXED, LEAF>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
                        a.N_r, a.codes, a.n, a.Qp, a.q0, a.nqc, qpb, a.gthr, a.counts, a.cap, a.cand_id, a.cand_m,
-                       a.cand_lb, a.bm, a.W, a.rad2, a.T);
+                       a.cand_lb, a.bm, a.W, a.rad2, a.T, a.lt);
     return hipGetLastError();
 }
 
 template <int L, int K>
 hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
-    if (a.fixed) return launch_filter_lkf<L, K, true>(a, st);
-    return launch_filter_lkf<L, K, false>(a, st);
+    if (a.fixed) return launch_filter_lkf<L, K, true, false>(a, st);
+    if (a.leaf) return launch_filter_lkf<L, K, false, true>(a, st);
+    return launch_filter_lkf<L, K, false, false>(a, st);
 }
 
 
@@ -1372,16 +1447,69 @@ hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
 template <int L>
 hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     if (a.fixed) {
-        hipLaunchKernelGGL((select_kernel<L, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
-                           a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W);
+        hipLaunchKernelGGL((select_kernel<L, true, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
+                           a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
+                           a.lt, a.n);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((select_kernel<L, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S, a.cand_id,
-                       a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W);
+    if (a.leaf) {
+        hipLaunchKernelGGL((select_kernel<L, false, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
+                           a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
+                           a.lt, a.n);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((select_kernel<L, false, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
+                       a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W, a.lt,
+                       a.n);
     return hipGetLastError();
 }
 
 }  // namespace
+
+namespace {
+
+__global__ __launch_bounds__(256) void leaf_of_kernel(const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ start, int64_t nleaves, int64_t n,
+                                                      int32_t* __restrict__ out)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int64_t lo = 0, hi = nleaves - 1;   // the last leaf whose run starts at or before p
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    out[perm[p]] = (int32_t)lo;
+}
+
+__global__ __launch_bounds__(256) void pack_sample_leaves_kernel(const int32_t* __restrict__ leaf_of, int64_t n,
+                                                                 int L, int G, int32_t* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)L * G) return;
+    const int i = (int)(t / G);
+    const int p = (int)(t % G);
+    const int64_t o = ((int64_t)G == n) ? (int64_t)p : (int64_t)(((uint64_t)p * kGuessMul) % (uint64_t)n);
+    out[t] = leaf_of[(int64_t)i * n + o];
+}
+
+}  // namespace
+
+hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* out,
+                             hipStream_t st) {
+    if (nleaves < 1 || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(leaf_of_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, start, nleaves, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t dl_launch_pack_sample_leaves(const int32_t* leaf_of, int64_t n, int L, int G, int32_t* out,
+                                        hipStream_t st) {
+    const int64_t tot = (int64_t)L * G;
+    hipLaunchKernelGGL(pack_sample_leaves_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, leaf_of, n,
+                       L, G, out);
+    return hipGetLastError();
+}
 
 hipError_t dl_launch_pack_sample(const uint8_t* codes, int64_t n, int L, int K, int G, uint8_t* out,
                                  hipStream_t st) {

@@ -59,7 +59,8 @@ struct Params {
         const bool c_ok = o.rmin_policy == DETLSH_RMIN_MAGIC || c == p.c;
         return k == p.k && c_ok && beta == p.beta && o.precision == p.o.precision &&
                o.rerank_mult == p.o.rerank_mult && o.rmin_policy == p.o.rmin_policy &&
-               o.max_rounds == p.o.max_rounds && o.r_min == p.o.r_min && o.verify == p.o.verify;
+               o.max_rounds == p.o.max_rounds && o.r_min == p.o.r_min && o.verify == p.o.verify &&
+               o.granularity == p.o.granularity;
     }
 };
 
@@ -336,7 +337,6 @@ detlsh_status detlsh_server_submit(detlsh_server srv, const float* Q, int64_t nq
     P.beta = beta;
     if (opts) P.o = *opts;
     P.o.workspace_bytes = 0;
-    P.o.reserved = 0;
     if (detlsh_status s = dl_query_check(srv->ix, nq, k, c, beta, &P.o, nullptr)) return s;
     if (nq > 0) {
         if (!dl_is_device_ptr(Q)) return errf(DETLSH_EINVAL, "Q must be a device pointer");

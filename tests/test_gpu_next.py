@@ -233,3 +233,63 @@ def test_insert_equals_import_of_the_union(dl, keep_bf16):
                              r["dists"][qi].cpu().numpy(), ref_q.S, 10)
     with pytest.raises(dl.DetlshError, match="EINVAL"):
         dl._lib.check(dl._lib.lib().detlsh_insert(idx._h, X2.ctypes.data_as(dl.C.c_void_p), 5, None))
+
+
+def _leaf_borderline(qp, trees, B, L, K, thr):
+    lb, _ = O.leaf_bounds(np.asarray(qp, np.float64), trees, np.asarray(B, np.float64), L, K)
+    m = lb.min(axis=1)
+    return set(np.flatnonzero(np.abs(m - thr) <= U.REL * max(thr, 1e-30)).tolist()), lb
+
+
+@pytest.mark.parametrize("max_leaf,kind,k,beta", [(32, "mixture", 10, 0.1), (8, "integer", 10, 0.05),
+                                                  (256, "mixture", 25, 0.1)])
+def test_leaf_granularity_matches_oracle(dl, max_leaf, kind, k, beta):
+    """Leaf boxes as the candidate test, the stop tree's leaves by (bound,
+    smallest id): candidate sets, stop tree, first trees and answers against
+    the oracle on the GPU's encoding and trees."""
+    say(f"leaf granularity max_leaf={max_leaf} kind={kind} k={k} beta={beta}")
+    cc = U.case(n=6000, d=48, N_r=64, frac=0.1, kind=kind, nq=10, seed=77)
+    idx = dl.build_index(cc["X"], 4, 16, 64, 0.1, A=cc["A"], sample_ids=cc["sample"], max_leaf=max_leaf)
+    ex = idx.export()
+    trees = O.build_trees(ex["codes"], 4, 16, 64, max_leaf)
+    for i in range(4):
+        perm, start, lo, hi = idx.tree(i)
+        assert len(start) - 1 == len(trees[i])
+        gpu = {tuple(perm[start[j]:start[j + 1]].tolist()) for j in range(len(start) - 1)}
+        assert gpu == {tuple(lf.ids.tolist()) for lf in trees[i]}   # same leaves, ids ascending in each
+    Q = t(cc["Q"])
+    Qp = idx.project(Q).cpu().numpy()
+    r = idx.query_debug(Q, k, 1.5, beta, Qp=t(Qp), granularity="leaf")
+    plain = idx.query(Q, k, 1.5, beta, granularity="leaf")
+    assert np.array_equal(plain[0].cpu().numpy(), r["ids"].cpu().numpy())
+    border_total = 0
+    for qi in range(len(cc["Q"])):
+        ref = O.query_magic_leaf(cc["X"], cc["Q"][qi], Qp[qi].astype(np.float64), ex["codes"],
+                                 ex["B"].astype(np.float64), trees, 4, 16, k, beta)
+        cnt = int(r["counts"][qi])
+        S = set(r["cand"][qi, :cnt].cpu().numpy().tolist())
+        if S != set(ref.S.tolist()):
+            border, _ = _leaf_borderline(Qp[qi], trees, ex["B"], 4, 16, ref.thr)
+            assert border, f"query {qi}: candidate sets differ without a borderline point"
+            border_total += 1
+            continue
+        assert int(r["stop_tree"][qi]) == ref.stop_tree
+        assert float(r["thr"][qi]) == pytest.approx(ref.thr, rel=U.REL)
+        ft = dict(zip(r["cand"][qi, :cnt].cpu().numpy().tolist(), r["first_tree"][qi, :cnt].cpu().numpy().tolist()))
+        assert all(ft[o] == f for o, f in zip(ref.S.tolist(), ref.first_tree.tolist()))
+        U.compare_result(ref.ids, ref.dists, cc["X"], cc["Q"][qi], r["ids"][qi].cpu().numpy(),
+                         r["dists"][qi].cpu().numpy(), ref.S, k)
+    say(f"  queries with borderline candidate differences: {border_total}")
+    with pytest.raises(dl.DetlshError, match="EINVAL"):
+        idx.query(Q, k, 1.5, beta, granularity="leaf", rmin_policy=dl.RMIN_FIXED, r_min=1.0)
+
+
+def test_leaf_granularity_dense_equals_gathered(dl):
+    say("leaf granularity dense vs gathered n=70000")
+    cc = U.case(n=70_000, d=64, N_r=256, frac=0.01, kind="mixture", nq=90, seed=78)
+    idx = dl.build_index(cc["X"], 4, 16, 256, 0.01, A=cc["A"], sample_ids=cc["sample"])
+    Q = t(cc["Q"])
+    g = idx.query(Q, 10, 1.5, 0.1, verify="gather", granularity="leaf")
+    d = idx.query(Q, 10, 1.5, 0.1, verify="dense", granularity="leaf")
+    assert np.array_equal(g[0].cpu().numpy(), d[0].cpu().numpy())
+    assert np.array_equal(g[1].cpu().numpy(), d[1].cpu().numpy())

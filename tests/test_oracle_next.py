@@ -174,3 +174,73 @@ def test_planted_insert_with_refreshed_breakpoints_is_caught(monkeypatch):
     monkeypatch.setattr(O, "insert", refreshed)
     with pytest.raises(AssertionError):
         test_insert_with_frozen_breakpoints()
+
+
+# --------------------------------------------------------------------------
+# leaf-granularity query (the query-phase optimisation)
+# --------------------------------------------------------------------------
+
+def _leaf_case(seed=10, n=1800, max_leaf=16, kind="mixture"):
+    X, idx, _ = make_problem(n=n, d=24, L=4, K=8, N_r=32, frac=0.2, seed=seed, kind=kind)
+    trees = O.build_trees(idx.codes, idx.L, idx.K, idx.N_r, max_leaf)
+    Qs = synth.gaussian_mixture(6, X.shape[1], 8, 3.0, 1.0, 500 + seed, rows_seed=950 + seed)
+    return X, idx, trees, Qs
+
+
+@pytest.mark.parametrize("max_leaf", [4, 16, 64])
+def test_leaf_query_magic_radius_and_stop(max_leaf):
+    """At the magic radius the admitted leaves of all trees hold N_S points and
+    at any smaller radius fewer; the query stops inside one leaf's worth of
+    N_S; the leaves taken from the stop tree are a prefix in bound order; the
+    answer is brute force over S."""
+    X, idx, trees, Qs = _leaf_case(max_leaf=max_leaf)
+    N_S = O.n_stop(len(X), 10, 0.1)
+    biggest = max(len(lf.ids) for t in trees for lf in t)
+    for q in Qs:
+        qp = O.project(q[None, :], idx.A)[0]
+        res = O.query_magic_leaf(X, q, qp, idx.codes, idx.B, trees, idx.L, idx.K, 10, 0.1)
+        lb, leafmin = O.leaf_bounds(qp, trees, idx.B, idx.L, idx.K)
+        m = lb.min(axis=1)
+        assert (m <= res.thr).sum() >= N_S
+        assert (m <= np.nextafter(res.thr, -np.inf)).sum() < N_S
+        assert N_S <= len(res.S) < N_S + biggest
+        i = res.stop_tree - 1
+        taken = np.isin(np.arange(len(X)), res.S)
+        new_here = res.first_tree == res.stop_tree
+        inside = set(zip(lb[res.S[new_here], i], leafmin[res.S[new_here], i]))
+        outside = [(lb[o, i], leafmin[o, i]) for o in np.flatnonzero(~taken) if lb[o, i] <= res.thr
+                   and not (lb[o, :i] <= res.thr).any()]
+        if inside and outside:
+            assert max(inside) < min(outside)
+        ids, d = brute_ids(X[res.S], q, 10)
+        assert np.array_equal(res.ids, res.S[ids])
+
+
+def test_leaf_bound_admits_a_superset_and_beta_one_is_brute_force():
+    X, idx, trees, Qs = _leaf_case(seed=11)
+    for q in Qs[:3]:
+        qp = O.project(q[None, :], idx.A)[0]
+        lb_leaf, _ = O.leaf_bounds(qp, trees, idx.B, idx.L, idx.K)
+        lb_cell = O.lower_bounds(qp, idx.codes, idx.B, idx.L, idx.K)
+        assert np.all(lb_leaf <= lb_cell * (1 + 1e-12) + 1e-12)
+        res = O.query_magic_leaf(X, q, qp, idx.codes, idx.B, trees, idx.L, idx.K, 10, 1.0)
+        ids, d = brute_ids(X, q, 10)
+        assert np.array_equal(res.ids, ids)
+
+
+def test_planted_cell_bound_in_the_leaf_queue_is_caught(monkeypatch):
+    """Admitting leaves by a member's cell bound instead of the leaf box bound
+    (the relaxation undone in one place) is caught."""
+    def cell_queue(qp_i, leaves, B_i, radius2):
+        lo, hi = O.region_bounds(B_i)
+        out = []
+        for lf in leaves:
+            c = lf.lo + (lf.hi - lf.lo) // 2
+            b = O.node_lb2(qp_i, c, c, B_i)
+            if b <= radius2:
+                out.append((b, int(lf.ids.min()), lf.ids))
+        out.sort(key=lambda e: (e[0], e[1]))
+        return [ids for _, _, ids in out]
+    monkeypatch.setattr(O, "leaf_queue", cell_queue)
+    with pytest.raises(AssertionError):
+        test_leaf_query_magic_radius_and_stop(16)
