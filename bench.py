@@ -321,6 +321,22 @@ def next_rows_bench(dl, torch, steps, warmup):
             idx = ix
         else:
             ix.free()
+    fine = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, max_leaf=16)
+    tq, (ids, _) = timed(lambda: fine.query(Q, 10, cfg.c, cfg.beta, granularity="leaf"))
+    out["leaf_max_leaf16_beta0.1"] = {"qps": cfg.nq / tq, "recall_at_10": recall_at_k(X, Q, ids, 10, kth)}
+    log(f"[next] leaf granularity, max_leaf 16: {cfg.nq / tq:.0f} q/s recall "
+        f"{out['leaf_max_leaf16_beta0.1']['recall_at_10']:.4f}")
+    fine.free()
+    for gran in ("leaf",):
+        for beta in (cfg.beta, 0.05):
+            tq, (ids, _) = timed(lambda: idx.query(Q, 10, cfg.c, beta, granularity=gran))
+            rec = recall_at_k(X, Q, ids, 10, kth)
+            tq0, (ids0, _) = timed(lambda: idx.query(Q, 10, cfg.c, beta))
+            rec0 = recall_at_k(X, Q, ids0, 10, kth)
+            out[f"{gran}_beta{beta}"] = {"qps": cfg.nq / tq, "recall_at_10": rec, "point_qps": cfg.nq / tq0,
+                                         "point_recall_at_10": rec0}
+            log(f"[next] {gran} granularity beta={beta}: {cfg.nq / tq:.0f} q/s recall {rec:.4f} "
+                f"(point: {cfg.nq / tq0:.0f} q/s recall {rec0:.4f})")
     r = float(nn.median())
     for c in (1.5, 2.0):
         tq, (ids, dists) = timed(lambda: idx.query_rc(Q, r, c, cfg.beta))
