@@ -832,6 +832,8 @@ struct Debug {
     int32_t* rounds = nullptr;
 };
 
+int64_t round4(int64_t v) { return (v + 3) & ~(int64_t)3; }
+
 size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d) {
     size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256 + (size_t)p.G * 4;
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
@@ -861,7 +863,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, int64_t q0, int64_t nq, int k,
                           const QueryPlan& plan, bool force_all_candidates, const Arena& arena, int64_t* out_ids,
                           float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
-    const int64_t cap = (force_all_candidates || plan.fixed) ? ix->n : plan.cap;
+    // candidate rows start 16-byte aligned (vector loads in the selection)
+    const int64_t cap = round4((force_all_candidates || plan.fixed) ? ix->n : plan.cap);
     const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d);
     int64_t nqc = (int64_t)(arena.bytes / pq);
     if (nqc < 1) {
@@ -1116,10 +1119,10 @@ QueryPlan all_points_plan(const QueryPlan& plan, int64_t n) {
 // query of either fallback).
 size_t query_arena_bytes(const detlsh_index_s* ix, const QuerySetup& s, int64_t nq, bool with_qp) {
     const QueryPlan& plan = s.plan;
-    const int64_t cap = plan.fixed ? ix->n : plan.cap;
+    const int64_t cap = round4(plan.fixed ? ix->n : plan.cap);
     size_t run = per_query_bytes(cap, ix->L, plan, ix->n, ix->d) * (size_t)nq;
-    const size_t fb = std::max(per_query_bytes(ix->n, ix->L, plan, ix->n, ix->d),
-                               per_query_bytes(ix->n, ix->L, all_points_plan(plan, ix->n), ix->n, ix->d));
+    const size_t fb = std::max(per_query_bytes(round4(ix->n), ix->L, plan, ix->n, ix->d),
+                               per_query_bytes(round4(ix->n), ix->L, all_points_plan(plan, ix->n), ix->n, ix->d));
     size_t b = std::max(run, fb);
     if (with_qp) b += align256((size_t)nq * ix->LK * 4);
     if (!s.ladder.empty()) b += align256(s.ladder.size() * 4);

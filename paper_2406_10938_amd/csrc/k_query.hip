@@ -204,6 +204,44 @@ __device__ uint32_t select_rank_u32(Get get, int64_t m, uint64_t r, SelectShared
     return prefix;
 }
 
+// The same selection over a contiguous, 16-byte aligned array of 32-bit keys,
+// read four keys per load (eight in flight per thread).
+__device__ uint32_t select_rank_u32v(const uint32_t* __restrict__ arr, int64_t m, uint64_t r, SelectShared& sh) {
+    const uint4* a4 = reinterpret_cast<const uint4*>(arr);
+    const int64_t m4 = m >> 2;
+    uint32_t prefix = 0;
+    int known = 0;
+    const int nb_tab[3] = {12, 12, 8};
+    for (int p = 0; p < 3; ++p) {
+        const int nbits = nb_tab[p];
+        const int shift = 32 - known - nbits;
+        for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
+        __syncthreads();
+        auto count = [&](uint32_t u) {
+            if (known == 0 || (u >> (32 - known)) == prefix)
+                atomicAdd(&sh.hist[(u >> shift) & ((1u << nbits) - 1u)], 1u);
+        };
+        int64_t i = threadIdx.x;
+        for (; i + 256 < m4; i += 512) {
+            const uint4 v = a4[i], w = a4[i + 256];
+            count(v.x); count(v.y); count(v.z); count(v.w);
+            count(w.x); count(w.y); count(w.z); count(w.w);
+        }
+        for (; i < m4; i += 256) {
+            const uint4 v = a4[i];
+            count(v.x); count(v.y); count(v.z); count(v.w);
+        }
+        for (int64_t t = 4 * m4 + threadIdx.x; t < m; t += 256) count(arr[t]);
+        __syncthreads();
+        find_bin(sh.hist, 4096, r, sh.scratch, &sh.d, &sh.before, &sh.total);
+        r -= sh.before;
+        prefix = (prefix << nbits) | (uint32_t)sh.d;
+        known += nbits;
+        __syncthreads();
+    }
+    return prefix;
+}
+
 // Value of the r-th smallest (1-based) non-negative float among get(0..m):
 // radix selection on the bit patterns, which order like the values.
 template <typename Get>
@@ -348,8 +386,8 @@ __global__ __launch_bounds__(256) void guess_select_kernel(const float* __restri
                                                            float* __restrict__ gthr)
 {
     __shared__ SelectShared sh;
-    const float* src = gm + (int64_t)blockIdx.x * G;
-    const float g = select_rank_f32([&](int64_t i) { return src[i]; }, G, rank, sh);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(gm + (int64_t)blockIdx.x * G);
+    const float g = __uint_as_float(select_rank_u32v(src, G, rank, sh));
     if (threadIdx.x == 0) gthr[blockIdx.x] = g;
 }
 
@@ -501,6 +539,28 @@ __device__ __forceinline__ uint32_t block_flag_prefix(bool f, uint32_t* wtot, ui
     return pre + r;
 }
 
+// Block-wide exclusive prefix of per-thread counts over 256 threads (all
+// lanes active); returns the prefix and writes the block total to *tot.
+__device__ __forceinline__ uint32_t block_count_prefix(uint32_t c, uint32_t* wtot, uint32_t* tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = dl_shfl_u32(incl, lane >= o ? lane - o : lane);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wave) pre += wtot[w];
+        all += wtot[w];
+    }
+    *tot = all;
+    __syncthreads();
+    return pre + incl - c;
+}
+
 template <int L>
 __device__ __forceinline__ void load_lbs(const float* __restrict__ src, float (&lb)[L]) {
     if constexpr (L % 4 == 0) {
@@ -645,31 +705,59 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
             return (ftree[s] == istop && bound_bits(s) == khi) ? leaf_min(ids[s]) : 0xffffffffu;
         }, (int64_t)cnt, r2, sh);
     }
-    // in-place stable compaction of S = U_{istop}, with each member's first
-    // admitting tree (every entry's f(o) was written above by this thread)
+    // in-place stable compaction of S = U_{istop} with each member's first
+    // admitting tree: thread t takes entries 4t..4t+3 of each 1024-entry step
+    // (16-byte loads; rows start 16-byte aligned), a block scan of the member
+    // counts places them.  The barrier in the scan separates every read of a
+    // step from its writes, which land at or before the entries read.
     uint32_t out = 0;
-    for (int64_t c0 = 0; c0 < (int64_t)cnt; c0 += 256) {
-        const int64_t s = c0 + threadIdx.x;
-        bool mem = false;
-        int32_t id = 0, ft = 0;
-        if (s < (int64_t)cnt) {
-            id = ids[s];
-            ft = ftree[s];
-            mem = (ft != 0 && ft <= istop);
-            if (LEAF && ft == istop) {
-                const uint32_t b = bound_bits(s);
-                mem = b < khi || (b == khi && leaf_min(id) <= klo);
+    for (int64_t c0 = 0; c0 < (int64_t)cnt; c0 += 1024) {
+        const int64_t s0 = c0 + 4 * (int64_t)threadIdx.x;
+        int32_t idv[4] = {0, 0, 0, 0}, ftv[4] = {0, 0, 0, 0};
+        if (s0 + 3 < (int64_t)cnt) {
+            const int4 a4 = *reinterpret_cast<const int4*>(ids + s0);
+            const int4 f4 = *reinterpret_cast<const int4*>(ftree + s0);
+            idv[0] = a4.x; idv[1] = a4.y; idv[2] = a4.z; idv[3] = a4.w;
+            ftv[0] = f4.x; ftv[1] = f4.y; ftv[2] = f4.z; ftv[3] = f4.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (s0 + j < (int64_t)cnt) {
+                    idv[j] = ids[s0 + j];
+                    ftv[j] = ftree[s0 + j];
+                }
+        }
+        bool memv[4];
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t s = s0 + j;
+            bool mem = false;
+            if (s < (int64_t)cnt) {
+                const int32_t ft = ftv[j];
+                mem = (ft != 0 && ft <= istop);
+                if (LEAF && ft == istop) {
+                    const uint32_t b = bound_bits(s);
+                    mem = b < khi || (b == khi && leaf_min(idv[j]) <= klo);
+                }
+                if (!mem && bm) {
+                    const int32_t id = idv[j];
+                    atomicAnd((unsigned long long*)&bm[(int64_t)t * W + (id >> 6)], ~(1ull << (id & 63)));
+                }
             }
-            if (!mem && bm) atomicAnd((unsigned long long*)&bm[(int64_t)t * W + (id >> 6)], ~(1ull << (id & 63)));
+            memv[j] = mem;
+            c += mem ? 1u : 0u;
         }
         uint32_t tot;
-        const uint32_t pre = block_flag_prefix(mem, wtot, &tot);
-        if (mem) {
-            ids[out + pre] = id;
-            ftree[out + pre] = ft;
-        }
+        uint32_t w = out + block_count_prefix(c, wtot, &tot);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (memv[j]) {
+                ids[w] = idv[j];
+                ftree[w] = ftv[j];
+                ++w;
+            }
         out += tot;
-        __syncthreads();
     }
     if (threadIdx.x == 0) {
         status[t] = 0;
