@@ -272,6 +272,16 @@ def precision_bench(dl, torch, name, steps, warmup, ks):
 
             r = beta_grid_run(run, cfg.beta)
             r.update({"k": k, "form": form})
+            best = r["at_recall_0.9"]
+            if best is not None:
+                dl.profile_enable(True, reset=True)
+                idx.query(Q, k, cfg.c, best["beta"], precision=prec)
+                torch.cuda.synchronize()
+                dl.profile_enable(False, reset=False)
+                r["kernels_at_best"] = {name: {"launches": v["launches"], "total_ms": v["ms"]}
+                                        for name, v in dl.profile_read().items() if v["launches"]}
+                log(f"[{name}] k={k} {form} kernels at beta={best['beta']}: " +
+                    ", ".join(f"{kn} {kv['total_ms']:.1f} ms" for kn, kv in r["kernels_at_best"].items()))
             out["results"].append(r)
     idx.free()
     del X, Q

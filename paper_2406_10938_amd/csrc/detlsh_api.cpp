@@ -1099,7 +1099,10 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
     plan.dense = !plan.all && !plan.fixed && (s.verify == 2 || (s.verify == 0 && (ix->n >= 65536 || bf16)));
     plan.bf16 = bf16 && plan.dense;
     plan.kprime = (int)std::min<uint64_t>(plan.N_S, (uint64_t)(bf16 ? s.rmult * k : k));
-    plan.T = std::max<int64_t>(2048, 32 * (int64_t)plan.kprime);
+    // tau reads T rows and the re-rank about k' |S| / T survivors: T = sqrt(k' N_S)
+    // balances the two gathers (at least 2048 and 32 k')
+    plan.T = std::max<int64_t>({2048, 32 * (int64_t)plan.kprime,
+                                (int64_t)std::ceil(std::sqrt((double)plan.kprime * (double)plan.N_S))});
     plan.cap_sv = std::max<int64_t>(32768, 64 * (int64_t)plan.kprime);
     return DETLSH_OK;
 }

@@ -1168,25 +1168,41 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     }
 }
 
-// Large d: the 128 query rows do not stay in LDS; the workgroup streams them
-// through LDS in chunks of DC reduction elements (64 FP32 or 128 BF16) for
-// every point tile.  While one chunk's products are issued, the next chunk's
-// query rows and point rows are loaded into registers; two barriers per chunk
-// hand the staged rows over.  Reduction order, screen and survivor lists are
-// those of dense_verify_kernel.
+// Large d: neither the 128 query rows nor the point rows stay resident.  For
+// every point tile the workgroup streams both through LDS in chunks of DC
+// reduction elements (64 FP32 or 128 BF16): the next chunk's query and point
+// vectors are loaded into registers while the current chunk's products are
+// issued from LDS, and two barriers per chunk hand them over.  Reduction
+// order, screen and survivor lists are those of dense_verify_kernel.
 template <bool BF16>
 struct KcShape {
-    static constexpr int DC = BF16 ? 128 : 64;   // reduction elements per chunk
+    static constexpr int DC = BF16 ? 128 : 64;       // reduction elements per chunk
     static constexpr int LD = DC + (BF16 ? 8 : 4);   // LDS row stride in elements (+16 bytes)
-    static constexpr int EB = BF16 ? 2 : 4;       // bytes per element
-    static constexpr int VE = 16 / EB;            // elements per 16-byte vector
-    static constexpr int VPR = DC / VE;           // vectors per row of a chunk
-    static constexpr int SV = kDQ * VPR / 256;    // staged vectors per thread
-    static constexpr int CK = DC / 16;            // 16-element MFMA steps per chunk
+    static constexpr int EB = BF16 ? 2 : 4;           // bytes per element
+    static constexpr int VE = 16 / EB;                // elements per 16-byte vector
+    static constexpr int VPR = DC / VE;               // vectors per row of a chunk (16)
+    static constexpr int SQ = kDQ * VPR / 256;        // staged query vectors per thread (8)
+    static constexpr int SX = kDP * VPR / 256;        // staged point vectors per thread (4)
+    static constexpr int CK = DC / 16;                // 16-element MFMA steps per chunk
 };
 
 template <bool BF16, bool ALIGNED>
-__global__ __launch_bounds__(256) void dense_verify_kc_kernel(
+__device__ __forceinline__ uint4 load_vec16(const float* __restrict__ X, const uint16_t* __restrict__ Xbf,
+                                            int64_t row, int d, int k) {
+    if (BF16) {
+        const uint16_t* src = Xbf + row * d;
+        const shortx4 a = load4bf<ALIGNED>(src, k, d), b = load4bf<ALIGNED>(src, k + 4, d);
+        return make_uint4((uint32_t)(uint16_t)a[0] | ((uint32_t)(uint16_t)a[1] << 16),
+                          (uint32_t)(uint16_t)a[2] | ((uint32_t)(uint16_t)a[3] << 16),
+                          (uint32_t)(uint16_t)b[0] | ((uint32_t)(uint16_t)b[1] << 16),
+                          (uint32_t)(uint16_t)b[2] | ((uint32_t)(uint16_t)b[3] << 16));
+    }
+    const floatx4 a = load4<ALIGNED>(X + row * d, k, d);
+    return make_uint4(__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]), __float_as_uint(a[3]));
+}
+
+template <bool BF16, bool ALIGNED>
+__global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
     const float* __restrict__ Q, const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int64_t q0,
     int nqc, const uint64_t* __restrict__ bm, int64_t W, const float* __restrict__ tau,
@@ -1196,6 +1212,7 @@ __global__ __launch_bounds__(256) void dense_verify_kc_kernel(
     using S = KcShape<BF16>;
     __shared__ DenseShared sh;
     __shared__ __attribute__((aligned(16))) unsigned char sqc[kDQ * S::LD * S::EB];
+    __shared__ __attribute__((aligned(16))) unsigned char sxc[kDP * S::LD * S::EB];
     const int64_t lid = blockIdx.x;
     const int xcd = (int)(lid & 7);
     const int64_t r = lid >> 3;
@@ -1229,51 +1246,40 @@ __global__ __launch_bounds__(256) void dense_verify_kc_kernel(
         if (threadIdx.x < kDQ) sh.bits[buf][threadIdx.x] = bits;
         else if (threadIdx.x < kDQ + kDP) sh.xn[buf][threadIdx.x - kDQ] = pxn;
     };
-    // staged query vectors: thread t holds vectors t + 256 i of the chunk
-    uint4 stg[S::SV];
-    auto stage_load = [&](int c) {
+    // staged vectors: thread t holds query vectors t + 256 i and point vectors t + 256 i
+    uint4 sgq[S::SQ], sgx[S::SX];
+    auto stage_load = [&](int64_t tile, int c) {
 #pragma unroll
-        for (int i = 0; i < S::SV; ++i) {
+        for (int i = 0; i < S::SQ; ++i) {
             const int idx = (int)threadIdx.x + 256 * i;
             const int row = idx / S::VPR, v = idx % S::VPR;
             int t = qt0 + row;
             if (t >= nqc) t = nqc - 1;
             const int k = c * S::DC + v * S::VE;
-            if (BF16) {
-                const uint16_t* src = Qbf + (int64_t)t * d;
-                const shortx4 a = load4bf<ALIGNED>(src, k, d), b = load4bf<ALIGNED>(src, k + 4, d);
-                stg[i] = make_uint4((uint32_t)(uint16_t)a[0] | ((uint32_t)(uint16_t)a[1] << 16),
-                                    (uint32_t)(uint16_t)a[2] | ((uint32_t)(uint16_t)a[3] << 16),
-                                    (uint32_t)(uint16_t)b[0] | ((uint32_t)(uint16_t)b[1] << 16),
-                                    (uint32_t)(uint16_t)b[2] | ((uint32_t)(uint16_t)b[3] << 16));
-            } else {
-                const floatx4 a = load4<ALIGNED>(Q + (q0 + t) * (int64_t)d, k, d);
-                stg[i] = make_uint4(__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]),
-                                    __float_as_uint(a[3]));
-            }
+            sgq[i] = BF16 ? load_vec16<true, ALIGNED>(nullptr, Qbf, t, d, k)
+                          : load_vec16<false, ALIGNED>(Q + q0 * (int64_t)d, nullptr, t, d, k);
+        }
+#pragma unroll
+        for (int i = 0; i < S::SX; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            const int row = idx / S::VPR, v = idx % S::VPR;
+            int64_t p = tile * kDP + row;
+            if (p >= n) p = n - 1;
+            sgx[i] = load_vec16<BF16, ALIGNED>(X, Xbf, p, d, c * S::DC + v * S::VE);
         }
     };
     auto stage_store = [&]() {
 #pragma unroll
-        for (int i = 0; i < S::SV; ++i) {
+        for (int i = 0; i < S::SQ; ++i) {
             const int idx = (int)threadIdx.x + 256 * i;
             const int row = idx / S::VPR, v = idx % S::VPR;
-            *reinterpret_cast<uint4*>(sqc + ((size_t)row * S::LD + (size_t)v * S::VE) * S::EB) = stg[i];
+            *reinterpret_cast<uint4*>(sqc + ((size_t)row * S::LD + (size_t)v * S::VE) * S::EB) = sgq[i];
         }
-    };
-    floatx4 xc[S::CK][2], xnx[S::CK][2];
-    shortx4 bc[S::CK][2], bnx[S::CK][2];
-    auto load_x = [&](int64_t tile, int c, floatx4 (&xf)[S::CK][2], shortx4 (&xb)[S::CK][2]) {
 #pragma unroll
-        for (int pb = 0; pb < 2; ++pb) {
-            int64_t p = tile * kDP + 32 * ph + 16 * pb + m;
-            if (p >= n) p = n - 1;
-#pragma unroll
-            for (int ks = 0; ks < S::CK; ++ks) {
-                const int k = c * S::DC + 16 * ks + 4 * kq;
-                if (BF16) xb[ks][pb] = load4bf<ALIGNED>(Xbf + p * d, k, d);
-                else xf[ks][pb] = load4<ALIGNED>(X + p * d, k, d);
-            }
+        for (int i = 0; i < S::SX; ++i) {
+            const int idx = (int)threadIdx.x + 256 * i;
+            const int row = idx / S::VPR, v = idx % S::VPR;
+            *reinterpret_cast<uint4*>(sxc + ((size_t)row * S::LD + (size_t)v * S::VE) * S::EB) = sgx[i];
         }
     };
     uint64_t nbits = 0;
@@ -1281,8 +1287,7 @@ __global__ __launch_bounds__(256) void dense_verify_kc_kernel(
     if (tb < te) {
         fetch_meta(tb, nbits, nxn);
         store_meta(0, nbits, nxn);
-        stage_load(0);
-        load_x(tb, 0, xc, bc);
+        stage_load(tb, 0);
         stage_store();
     }
     __syncthreads();
@@ -1300,36 +1305,42 @@ __global__ __launch_bounds__(256) void dense_verify_kc_kernel(
         for (int c = 0; c < nchunk; ++c) {
             const bool last = c + 1 == nchunk;
             const bool more = !last || tile + 1 < te;
-            if (more) {
-                stage_load(last ? 0 : c + 1);
-                load_x(last ? tile + 1 : tile, last ? 0 : c + 1, xnx, bnx);
-            }
-#pragma unroll
+            if (more) stage_load(last ? tile + 1 : tile, last ? 0 : c + 1);
+#pragma unroll 2
             for (int ks = 0; ks < S::CK; ++ks) {
+                const int ko = 16 * ks + 4 * kq;
                 if (BF16) {
                     const uint16_t* sq = reinterpret_cast<const uint16_t*>(sqc);
-                    shortx4 qv[4];
+                    const uint16_t* sx = reinterpret_cast<const uint16_t*>(sxc);
+                    auto unpack = [](uint2 v) {
+                        return shortx4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff),
+                                       (short)(v.y >> 16)};
+                    };
+                    shortx4 qv[4], xv[2];
 #pragma unroll
-                    for (int qb = 0; qb < 4; ++qb) {
-                        const int i = 64 * qh + 16 * qb + m;
-                        const uint2 v = *reinterpret_cast<const uint2*>(sq + i * S::LD + 16 * ks + 4 * kq);
-                        qv[qb] = shortx4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff),
-                                         (short)(v.y >> 16)};
-                    }
+                    for (int qb = 0; qb < 4; ++qb)
+                        qv[qb] = unpack(*reinterpret_cast<const uint2*>(sq + (64 * qh + 16 * qb + m) * S::LD + ko));
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb)
+                        xv[pb] = unpack(*reinterpret_cast<const uint2*>(sx + (32 * ph + 16 * pb + m) * S::LD + ko));
 #pragma unroll
                     for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
                         for (int pb = 0; pb < 2; ++pb)
-                            acc[qb][pb] =
-                                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qv[qb], bc[ks][pb], acc[qb][pb], 0, 0, 0);
+                            acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qv[qb], xv[pb], acc[qb][pb], 0, 0, 0);
                 } else {
                     const float* sq = reinterpret_cast<const float*>(sqc);
-                    floatx4 qv[4];
+                    const float* sx = reinterpret_cast<const float*>(sxc);
+                    floatx4 qv[4], xv[2];
 #pragma unroll
                     for (int qb = 0; qb < 4; ++qb) {
-                        const int i = 64 * qh + 16 * qb + m;
-                        const float4 v = *reinterpret_cast<const float4*>(sq + i * S::LD + 16 * ks + 4 * kq);
+                        const float4 v = *reinterpret_cast<const float4*>(sq + (64 * qh + 16 * qb + m) * S::LD + ko);
                         qv[qb] = floatx4{v.x, v.y, v.z, v.w};
+                    }
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb) {
+                        const float4 v = *reinterpret_cast<const float4*>(sx + (32 * ph + 16 * pb + m) * S::LD + ko);
+                        xv[pb] = floatx4{v.x, v.y, v.z, v.w};
                     }
 #pragma unroll
                     for (int s2 = 0; s2 < 4; ++s2)
@@ -1337,21 +1348,12 @@ __global__ __launch_bounds__(256) void dense_verify_kc_kernel(
                         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
                             for (int pb = 0; pb < 2; ++pb)
-                                acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[qb][s2], xc[ks][pb][s2],
+                                acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qv[qb][s2], xv[pb][s2],
                                                                                     acc[qb][pb], 0, 0, 0);
                 }
             }
-            __syncthreads();   // every wave is done with this chunk's query rows
-            if (more) {
-                stage_store();
-#pragma unroll
-                for (int ks = 0; ks < S::CK; ++ks)
-#pragma unroll
-                    for (int pb = 0; pb < 2; ++pb) {
-                        if (BF16) bc[ks][pb] = bnx[ks][pb];
-                        else xc[ks][pb] = xnx[ks][pb];
-                    }
-            }
+            __syncthreads();   // every wave is done with this chunk's rows
+            if (more) stage_store();
             if (last) {
                 dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
                 if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
@@ -1676,35 +1678,26 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((dense_verify_kernel<BF, AL, QL, KS>), dim3((unsigned)blocks), dim3(256), shm, st, a.X,     \
                        a.Xbf, xn, a.n, a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, \
                        a.svc, a.sv, a.cap_sv, gx, gy, ntiles, tps)
-    // the query tile stays in LDS when it fits in 80 KB and point rows of up to
-    // 128 elements stay in registers; otherwise the query rows stream through
-    // LDS in chunks
-    const size_t qbytes = (size_t)kDQ * (a.dense_bf16 ? (a.d + 8) * 2 : (a.d + 4) * 4);
+    // FP32 with d <= 128: the query tile stays in LDS (when it fits in 80 KB)
+    // and the point rows in registers; otherwise (larger d, and the BF16 form,
+    // whose products are cheap enough that operand traffic decides) both
+    // operands stream through LDS in chunks
+    const size_t qbytes = (size_t)kDQ * (a.d + 4) * 4;
     const bool qlds = al && qbytes <= 80 * 1024;
     const size_t shm = qlds ? qbytes : 0;
     const int ks = (a.d + 15) / 16;
-    if (qlds && ks <= 8) {
-        if (a.dense_bf16) {
-            if (ks <= 4) DL_DENSE(true, true, true, 4);
-            else if (ks <= 6) DL_DENSE(true, true, true, 6);
-            else DL_DENSE(true, true, true, 8);
-        } else {
-            if (ks <= 4) DL_DENSE(false, true, true, 4);
-            else if (ks <= 6) DL_DENSE(false, true, true, 6);
-            else DL_DENSE(false, true, true, 8);
-        }
+    if (!a.dense_bf16 && qlds && ks <= 8) {
+        if (ks <= 4) DL_DENSE(false, true, true, 4);
+        else if (ks <= 6) DL_DENSE(false, true, true, 6);
+        else DL_DENSE(false, true, true, 8);
     } else {
 #define DL_DENSE_KC(BF, AL)                                                                                    \
     hipLaunchKernelGGL((dense_verify_kc_kernel<BF, AL>), dim3((unsigned)blocks), dim3(256), 0, st, a.X, a.Xbf, xn,  \
                        a.n, a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv,  \
                        a.cap_sv, gx, gy, ntiles, tps)
-        // BF16: the query tile in LDS with point rows streamed per step, or
-        // both from L2, measured faster than the chunked stream (whose 128-element
-        // chunks are too short to hide their two barriers at the BF16 rate)
         if (a.dense_bf16) {
-            if (qlds) DL_DENSE(true, true, true, 0);
-            else if (al) DL_DENSE(true, true, false, 0);
-            else DL_DENSE(true, false, false, 0);
+            if (al) DL_DENSE_KC(true, true);
+            else DL_DENSE_KC(true, false);
         } else {
             if (al) DL_DENSE_KC(false, true);
             else DL_DENSE_KC(false, false);
