@@ -1248,9 +1248,13 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     };
     // staged vectors: thread t holds query vectors t + 256 i and point vectors t + 256 i
     uint4 sgq[S::SQ], sgx[S::SX];
-    auto stage_load = [&](int64_t tile, int c) {
+    // with one chunk the query rows stay in LDS for the whole point range and
+    // only the point rows are staged per tile
+    const bool q_resident = nchunk == 1;
+    auto stage_load = [&](int64_t tile, int c, bool with_q) {
 #pragma unroll
         for (int i = 0; i < S::SQ; ++i) {
+            if (!with_q) break;
             const int idx = (int)threadIdx.x + 256 * i;
             const int row = idx / S::VPR, v = idx % S::VPR;
             int t = qt0 + row;
@@ -1268,9 +1272,10 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
             sgx[i] = load_vec16<BF16, ALIGNED>(X, Xbf, p, d, c * S::DC + v * S::VE);
         }
     };
-    auto stage_store = [&]() {
+    auto stage_store = [&](bool with_q) {
 #pragma unroll
         for (int i = 0; i < S::SQ; ++i) {
+            if (!with_q) break;
             const int idx = (int)threadIdx.x + 256 * i;
             const int row = idx / S::VPR, v = idx % S::VPR;
             *reinterpret_cast<uint4*>(sqc + ((size_t)row * S::LD + (size_t)v * S::VE) * S::EB) = sgq[i];
@@ -1287,8 +1292,8 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     if (tb < te) {
         fetch_meta(tb, nbits, nxn);
         store_meta(0, nbits, nxn);
-        stage_load(tb, 0);
-        stage_store();
+        stage_load(tb, 0, true);
+        stage_store(true);
     }
     __syncthreads();
     for (int64_t tile = tb; tile < te; ++tile) {
@@ -1305,9 +1310,11 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
         for (int c = 0; c < nchunk; ++c) {
             const bool last = c + 1 == nchunk;
             const bool more = !last || tile + 1 < te;
-            if (more) stage_load(last ? tile + 1 : tile, last ? 0 : c + 1);
+            if (more) stage_load(last ? tile + 1 : tile, last ? 0 : c + 1, !q_resident);
+            // steps past d would multiply staged zeros: a short last chunk stops early
+            const int nks = min(S::CK, (d - c * S::DC + 15) / 16);
 #pragma unroll 2
-            for (int ks = 0; ks < S::CK; ++ks) {
+            for (int ks = 0; ks < nks; ++ks) {
                 const int ko = 16 * ks + 4 * kq;
                 if (BF16) {
                     const uint16_t* sq = reinterpret_cast<const uint16_t*>(sqc);
@@ -1353,7 +1360,7 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
                 }
             }
             __syncthreads();   // every wave is done with this chunk's rows
-            if (more) stage_store();
+            if (more) stage_store(!q_resident);
             if (last) {
                 dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
                 if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
