@@ -440,7 +440,7 @@ __device__ __forceinline__ float entry_step(const float (&lb)[L], const float* _
 }
 
 template <int L, int K, bool FIXED, bool LEAF>
-__global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E, int N_r,
+__global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict__ E, int N_r,
                                                      const uint8_t* __restrict__ codes, int64_t n,
                                                      const float* __restrict__ Qp, int64_t q0, int nqc,
                                                      int q_per_block, const float* __restrict__ gthr,
@@ -499,20 +499,27 @@ __global__ __launch_bounds__(256) void filter_kernel(const float* __restrict__ E
             sh.gb[g] = tot ? atomicAdd(&counts[tg + g], tot) : 0u;
         }
         __syncthreads();
-        for (int g = 0; g < ng; ++g) {
-            const uint32_t c = sh.wc[wave][g];
-            if (c == 0) continue;
-            uint32_t off = sh.gb[g];
-            for (int w = 0; w < wave; ++w) off += sh.wc[w][g];
-            for (uint32_t j = lane; j < c; j += 64) {
+        // Wave w copies out the block's hits of queries w, w+4, ...: the slots
+        // of query g are wave 0's list, then wave 1's, ... (one lane per hit,
+        // contiguous stores), so a wave handles two short lists per group
+        // instead of eight lists of a few hits each.
+        for (int g = wave; g < ng; g += 4) {
+            const uint32_t p1 = sh.wc[0][g];
+            const uint32_t p2 = p1 + sh.wc[1][g];
+            const uint32_t p3 = p2 + sh.wc[2][g];
+            const uint32_t tot = p3 + sh.wc[3][g];
+            const uint32_t off = sh.gb[g];
+            for (uint32_t j = lane; j < tot; j += 64) {
+                const int w = (j >= p1) + (j >= p2) + (j >= p3);
+                const uint32_t pos = j - (w == 0 ? 0u : w == 1 ? p1 : w == 2 ? p2 : p3);
                 const int64_t idx = (int64_t)off + j;
                 if (idx < cap) {
                     const int64_t at = (int64_t)(tg + g) * cap + idx;
-                    cand_id[at] = sh.ids[wave][g][j];
+                    cand_id[at] = sh.ids[w][g][pos];
                     float lb[L];
 #pragma unroll
-                    for (int i = 0; i < L; ++i) lb[i] = sh.lbs[wave][g][j][i];
-                    cand_m[at] = sh.key[wave][g][j];
+                    for (int i = 0; i < L; ++i) lb[i] = sh.lbs[w][g][pos][i];
+                    cand_m[at] = sh.key[w][g][pos];
                     store_lbs<L>(cand_lb + at * L, lb);
                 }
             }
