@@ -27,7 +27,8 @@
  *  - Matrices are row-major and densely packed unless stated otherwise.
  *  - An index is read-only after it is built: any number of threads may call
  *    detlsh_query on it concurrently, each with its own stream; every call
- *    allocates its own workspace (a server, below, allocates once instead).
+ *    has a workspace of its own (allocated, or reused from an earlier call:
+ *    see detlsh_trim; a server, below, allocates once instead).
  *    detlsh_free must not race with queries, and every server on the index
  *    must be destroyed first.
  */
@@ -404,6 +405,16 @@ detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double*
                                   int32_t max, int32_t* count);
 
 void detlsh_free(detlsh_index idx);
+
+/*
+ * A detlsh_query call (also _rc and _debug) keeps its device workspace when it
+ * returns normally, and a later call on the same device takes the smallest
+ * idle one that is large enough (at most 4 stay idle per device; a call that
+ * fails frees its own).  detlsh_trim frees every idle workspace of the process
+ * on every device, giving that memory back; workspaces of running calls are
+ * not touched.  Any thread, any time.
+ */
+void detlsh_trim(void);
 const char* detlsh_last_error(void);   /* thread-local; valid until the next call */
 
 #ifdef __cplusplus

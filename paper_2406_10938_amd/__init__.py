@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import BF16_RERANK, FP32, PROJ_GAUSSIAN, PROJ_PAA, RMIN_FIXED, RMIN_MAGIC, DetlshError, check, lib
 
 __all__ = ["build_index", "import_index", "load_index", "Index", "Server", "DetlshError", "FP32", "BF16_RERANK",
-           "RMIN_MAGIC", "RMIN_FIXED", "PROJ_GAUSSIAN", "PROJ_PAA", "profile_enable", "profile_read"]
+           "RMIN_MAGIC", "RMIN_FIXED", "PROJ_GAUSSIAN", "PROJ_PAA", "profile_enable", "profile_read",
+           "trim"]
 
 
 def _torch():
@@ -294,6 +295,11 @@ def load_index(path) -> Index:
     h = C.c_void_p()
     check(lib().detlsh_index_load(str(path).encode(), _stream_ptr(), C.byref(h)))
     return Index(h)
+
+
+def trim():
+    """Free the idle query workspaces that earlier query calls left for reuse."""
+    lib().detlsh_trim()
 
 
 def profile_enable(on=True, reset=True):

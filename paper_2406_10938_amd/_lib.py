@@ -96,6 +96,7 @@ SIGNATURES = {
     "detlsh_server_cancel": (C.c_int, [P, C.c_uint64]),
     "detlsh_server_destroy": (None, [P]),
     "detlsh_free": (None, [P]),
+    "detlsh_trim": (None, []),
     "detlsh_last_error": (C.c_char_p, []),
 }
 

@@ -75,6 +75,87 @@ struct DevBuf {
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Query workspaces outlive the call that allocated them: a call that ends
+// normally (its stream synchronised, so no kernel still uses the buffer)
+// hands the buffer back, and a later call on the same device takes the
+// smallest idle one that is large enough instead of paying for hipMalloc and
+// a device-synchronising hipFree of gigabytes.  At most kWsIdle buffers per
+// device stay idle; detlsh_trim frees them all.  The cache is never
+// destroyed (no hipFree during static destruction, after the runtime may be
+// gone); the driver reclaims the memory at process exit.
+constexpr size_t kWsIdle = 4;
+
+struct WsCache {
+    std::mutex mu;
+    std::vector<std::pair<int, DevBuf*>> idle;   // (device, buffer)
+};
+WsCache& ws_cache() {
+    static WsCache* c = new WsCache;
+    return *c;
+}
+
+DevBuf* ws_take(int dev, size_t bytes) {
+    WsCache& c = ws_cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        size_t best = c.idle.size();
+        for (size_t i = 0; i < c.idle.size(); ++i)
+            if (c.idle[i].first == dev && c.idle[i].second->bytes >= bytes &&
+                (best == c.idle.size() || c.idle[i].second->bytes < c.idle[best].second->bytes))
+                best = i;
+        if (best < c.idle.size()) {
+            DevBuf* b = c.idle[best].second;
+            c.idle.erase(c.idle.begin() + (std::ptrdiff_t)best);
+            return b;
+        }
+    }
+    std::unique_ptr<DevBuf> b(new DevBuf);
+    if (b->alloc(bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        detlsh_trim();   // idle buffers of this process may be what fills the device
+        if (b->alloc(bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    return b.release();
+}
+
+void ws_give(int dev, DevBuf* b) {
+    WsCache& c = ws_cache();
+    DevBuf* drop = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.idle.emplace_back(dev, b);
+        size_t on_dev = 0, smallest = c.idle.size();
+        for (size_t i = 0; i < c.idle.size(); ++i)
+            if (c.idle[i].first == dev) {
+                ++on_dev;
+                if (smallest == c.idle.size() || c.idle[i].second->bytes < c.idle[smallest].second->bytes)
+                    smallest = i;
+            }
+        if (on_dev > kWsIdle) {
+            drop = c.idle[smallest].second;
+            c.idle.erase(c.idle.begin() + (std::ptrdiff_t)smallest);
+        }
+    }
+    delete drop;
+}
+
+// A workspace held by one call: returned to the cache when the call marks it
+// idle (its stream synchronised), freed otherwise (hipFree waits for the
+// device, so an error path cannot hand a busy buffer to another call).
+struct WsLease {
+    int dev = 0;
+    DevBuf* b = nullptr;
+    bool idle = false;
+    ~WsLease() {
+        if (!b) return;
+        if (idle) ws_give(dev, b);
+        else delete b;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // kernel timing
 // ---------------------------------------------------------------------------
@@ -726,6 +807,17 @@ detlsh_status detlsh_project(detlsh_index ix, const float* Q, int64_t nq, float*
 
 void detlsh_free(detlsh_index ix) { delete ix; }
 
+void detlsh_trim(void) {
+    std::vector<DevBuf*> drop;
+    {
+        WsCache& c = ws_cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (auto& e : c.idle) drop.push_back(e.second);
+        c.idle.clear();
+    }
+    for (DevBuf* b : drop) delete b;
+}
+
 detlsh_status detlsh_profile_enable(int32_t on, int32_t reset) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = on != 0;
@@ -874,12 +966,13 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     }
     if (nqc > nq) nqc = nq;
     if (nqc > 65535) nqc = 65535;
-    DevBuf own;
+    WsLease own;
     char* p = arena.p;
     if (!p) {
-        if (own.alloc(pq * (size_t)nqc) != hipSuccess)
-            return fail(DETLSH_ENOMEM, "query workspace of %zu bytes", pq * (size_t)nqc);
-        p = own.as<char>();
+        own.dev = ix->device;
+        own.b = ws_take(ix->device, pq * (size_t)nqc);
+        if (!own.b) return fail(DETLSH_ENOMEM, "query workspace of %zu bytes", pq * (size_t)nqc);
+        p = own.b->as<char>();
     }
     auto take = [&](size_t b) { char* r = p; p += (b + 255) & ~(size_t)255; return r; };
     QueryArgs a;
@@ -1028,6 +1121,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         }
     }
     HCHECK(hipStreamSynchronize(st));
+    own.idle = true;
     return DETLSH_OK;
 }
 

@@ -67,3 +67,11 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         _lib.lib()
+
+
+def test_trim_without_cached_workspaces():
+    """detlsh_trim with nothing cached makes no HIP call and is idempotent."""
+    from paper_2406_10938_amd import _lib
+    L = _lib.lib()
+    L.detlsh_trim()
+    L.detlsh_trim()

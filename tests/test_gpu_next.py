@@ -293,3 +293,29 @@ def test_leaf_granularity_dense_equals_gathered(dl):
     d = idx.query(Q, 10, 1.5, 0.1, verify="dense", granularity="leaf")
     assert np.array_equal(g[0].cpu().numpy(), d[0].cpu().numpy())
     assert np.array_equal(g[1].cpu().numpy(), d[1].cpu().numpy())
+
+
+def test_reused_workspace_gives_identical_results(dl):
+    """A query call leaves its workspace for reuse: a later call that takes a
+    used (and larger) buffer, and one after detlsh_trim has freed the cache,
+    return exactly what the first call returned."""
+    import torch
+    cc = U.case(n=20000, d=48, N_r=64, frac=0.05, nq=300, seed=91)
+    idx = dl.build_index(cc["X"], 4, 16, 64, 0.05, A=cc["A"], sample_ids=cc["sample"])
+    Q = t(cc["Q"])
+    dl.trim()
+    small = Q[:37].contiguous()
+    say("fresh small batch")
+    i0, d0 = idx.query(small, 10, 1.5, 0.1)
+    say("large batch in a small workspace (several chunks), then the small batch again")
+    i1, d1 = idx.query(Q, 10, 1.5, 0.1, workspace_bytes=64 << 20)
+    i2, d2 = idx.query(small, 10, 1.5, 0.1)
+    i3, d3 = idx.query(Q, 10, 1.5, 0.1)
+    dl.trim()
+    i4, d4 = idx.query(small, 10, 1.5, 0.1)
+    torch.cuda.synchronize()
+    for a, b in ((i0, i2), (i0, i4), (i1[:37], i0), (i3, i1)):
+        assert torch.equal(a, b)
+    for a, b in ((d0, d2), (d0, d4), (d1[:37], d0), (d3, d1)):
+        assert torch.equal(a, b)
+    idx.free()
