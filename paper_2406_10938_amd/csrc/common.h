@@ -56,14 +56,18 @@ __device__ __forceinline__ T dl_wave_sum(T v) {
 __device__ __forceinline__ float dl_bf16_to_f32(uint16_t h);
 __device__ __forceinline__ uint16_t dl_f32_to_bf16(float f);
 
-// Four consecutive elements p[k..k+3] (zero beyond d); vector load when the
-// rows are 16-byte aligned.
+// Four consecutive elements p[k..k+3] (zero beyond d).  ALIGNED: d and k are
+// multiples of 4 (rows 16-byte aligned), so the four lie all inside the row or
+// all beyond it, and one vector load from a clamped offset plus a select
+// covers both without a branch (a branch here splits the load stream and
+// forces waits at its join).
 template <bool ALIGNED>
 __device__ __forceinline__ floatx4 load4(const float* __restrict__ p, int k, int d) {
     floatx4 r;
-    if (ALIGNED && k + 4 <= d) {
-        float4 v = *reinterpret_cast<const float4*>(p + k);
-        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    if (ALIGNED) {
+        const bool in = k + 4 <= d;
+        const float4 v = *reinterpret_cast<const float4*>(p + (in ? k : 0));
+        r[0] = in ? v.x : 0.0f; r[1] = in ? v.y : 0.0f; r[2] = in ? v.z : 0.0f; r[3] = in ? v.w : 0.0f;
     } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t) r[t] = (k + t < d) ? p[k + t] : 0.0f;
@@ -74,8 +78,10 @@ __device__ __forceinline__ floatx4 load4(const float* __restrict__ p, int k, int
 template <bool ALIGNED>
 __device__ __forceinline__ shortx4 load4bf(const uint16_t* __restrict__ p, int k, int d) {
     shortx4 r;
-    if (ALIGNED && k + 4 <= d) {
-        uint2 v = *reinterpret_cast<const uint2*>(p + k);
+    if (ALIGNED) {
+        const bool in = k + 4 <= d;
+        uint2 v = *reinterpret_cast<const uint2*>(p + (in ? k : 0));
+        if (!in) v = make_uint2(0u, 0u);
         r[0] = (short)(v.x & 0xffff); r[1] = (short)(v.x >> 16);
         r[2] = (short)(v.y & 0xffff); r[3] = (short)(v.y >> 16);
     } else {

@@ -1063,17 +1063,19 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     // during the epilogue and the barrier.
     floatx4 xc[KS > 0 ? KS : 1][2];
     shortx4 bc[KS > 0 ? KS : 1][2];
-    auto load_rows = [&](int64_t tile, floatx4 (&xf)[KS > 0 ? KS : 1][2], shortx4 (&xb)[KS > 0 ? KS : 1][2]) {
+    auto load_step = [&](int64_t tile, int ks, floatx4 (&xf)[KS > 0 ? KS : 1][2],
+                         shortx4 (&xb)[KS > 0 ? KS : 1][2]) {
 #pragma unroll
         for (int pb = 0; pb < 2; ++pb) {
             int64_t p = tile * kDP + 32 * ph + 16 * pb + m;
             if (p >= n) p = n - 1;
-#pragma unroll
-            for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) {
-                if (BF16) xb[ks][pb] = load4bf<ALIGNED>(Xbf + p * d, 16 * ks + 4 * kq, d);
-                else xf[ks][pb] = load4<ALIGNED>(X + p * d, 16 * ks + 4 * kq, d);
-            }
+            if (BF16) xb[ks][pb] = load4bf<ALIGNED>(Xbf + p * d, 16 * ks + 4 * kq, d);
+            else xf[ks][pb] = load4<ALIGNED>(X + p * d, 16 * ks + 4 * kq, d);
         }
+    };
+    auto load_rows = [&](int64_t tile, floatx4 (&xf)[KS > 0 ? KS : 1][2], shortx4 (&xb)[KS > 0 ? KS : 1][2]) {
+#pragma unroll
+        for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) load_step(tile, ks, xf, xb);
     };
     if (KS > 0 && tb < te) load_rows(tb, xc, bc);
     __syncthreads();
@@ -1121,8 +1123,14 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
                                                                                 0, 0, 0);
             };
             if (KS > 0) {
+                // once step ks's products are issued its registers take the
+                // next tile's rows (a clamped, in-bounds reload on the last
+                // tile), so each load has most of a tile to arrive
 #pragma unroll
-                for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) step(16 * ks, xc[ks]);
+                for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) {
+                    step(16 * ks, xc[ks]);
+                    load_step(tile + 1, ks, xc, bc);
+                }
             } else {
                 for (int k0 = 0; k0 < d; k0 += 16) {
                     floatx4 xv[2];
@@ -1157,7 +1165,10 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
             };
             if (KS > 0) {
 #pragma unroll
-                for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) step(16 * ks, bc[ks]);
+                for (int ks = 0; ks < (KS > 0 ? KS : 1); ++ks) {
+                    step(16 * ks, bc[ks]);
+                    load_step(tile + 1, ks, xc, bc);
+                }
             } else {
                 for (int k0 = 0; k0 < d; k0 += 16) {
                     shortx4 xv[2];
@@ -1167,7 +1178,6 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
                 }
             }
         }
-        if (KS > 0 && tile + 1 < te) load_rows(tile + 1, xc, bc);
         dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
         if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
         __syncthreads();
