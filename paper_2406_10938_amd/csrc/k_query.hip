@@ -935,33 +935,42 @@ struct DenseShared {
 __device__ __forceinline__ void dense_screen(const floatx4 (&acc)[4][2], DenseShared& sh, int cur, int ep, int qh,
                                              int ph, int m, int kq, int64_t p0, int qt0, float margin_c,
                                              uint32_t* __restrict__ svc, int32_t* __restrict__ sv, int64_t cap_sv) {
-    const int pi0 = 32 * ph + m;
+    const int pi0 = 32 * ph + m;   // the lane's points: pi0 and pi0 + 16 (pi0 + 16 < 64)
     const float xn0 = sh.xn[cur][pi0], xn1 = sh.xn[cur][pi0 + 16];
+    // branch-free test of the lane's 32 products; bit 8 qb + 2 v + pb of hits
+    // marks a survivor (survivors are rare, so appends run only when the
+    // wave has any)
+    uint32_t hits = 0;
 #pragma unroll
     for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int qi = 64 * qh + 16 * qb + 4 * kq + v;
-            const uint64_t bits = sh.bits[cur][qi];
+            const uint32_t w = (uint32_t)(sh.bits[cur][qi] >> pi0);   // bit 0: point pi0, bit 16: pi0 + 16
             const float dqn = sh.qn[qi], dtau = sh.tau[qi];
 #pragma unroll
             for (int pb = 0; pb < 2; ++pb) {
-                const int pi = pi0 + 16 * pb;
-                if (!((bits >> pi) & 1ull)) continue;
                 const float nsum = dqn + (pb ? xn1 : xn0);
                 const float a2 = fmaf(-2.0f, acc[qb][pb][v], nsum);
-                if (a2 <= fmaf(margin_c, nsum, dtau)) {
-                    const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
-                    if (s < (uint32_t)kSvl) {
-                        sh.list[ep][qi][s] = (int32_t)(p0 + pi);
-                    } else {
-                        const int t = qt0 + qi;
-                        const uint32_t slot = atomicAdd(&svc[t], 1u);
-                        if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
-                    }
-                }
+                const bool h = ((w >> (16 * pb)) & 1u) != 0u && a2 <= fmaf(margin_c, nsum, dtau);
+                hits |= (h ? 1u : 0u) << (8 * qb + 2 * v + pb);
             }
         }
+    if (dl_ballot(hits != 0u) == 0ull) return;
+    while (hits) {
+        const int b = __builtin_ctz(hits);
+        hits &= hits - 1u;
+        const int qi = 64 * qh + 16 * (b >> 3) + 4 * kq + ((b >> 1) & 3);
+        const int pi = pi0 + 16 * (b & 1);
+        const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
+        if (s < (uint32_t)kSvl) {
+            sh.list[ep][qi][s] = (int32_t)(p0 + pi);
+        } else {
+            const int t = qt0 + qi;
+            const uint32_t slot = atomicAdd(&svc[t], 1u);
+            if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
+        }
+    }
 }
 
 // After a barrier that follows an epoch's last screen: one global atomic per
