@@ -168,10 +168,11 @@ __device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* 
 // The r-th smallest (1-based) of m 32-bit keys get(0..m), by three radix
 // passes (12, 12, 8 bits).
 struct SelectShared {
-    uint32_t hist[4096];
+    uint32_t hist[8192];        // 4096 bins, 8192 in the window selection's second pass
     uint32_t scratch[260];
     int d;
     uint64_t before, total;
+    uint32_t below;
 };
 
 template <typename Get>
@@ -247,6 +248,60 @@ __device__ uint32_t select_rank_u32v(const uint32_t* __restrict__ arr, int64_t m
 template <typename Get>
 __device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& sh) {
     return __uint_as_float(select_rank_u32([&](int64_t i) { return __float_as_uint(get(i)); }, m, r, sh));
+}
+
+// The same selection when every key is known to be <= hi: two passes over the
+// window of 2^25 key values that ends at hi (a 12-bit digit, then 13 bits);
+// keys below the window are only counted.  For bit patterns of non-negative
+// floats the window spans four binades below hi, so the first pass spreads
+// keys over many bins instead of the few that the top 12 bits (sign,
+// exponent, 3 mantissa bits) give.  When the r-th key is not inside the
+// window (it lies below, or keys exceed hi) the three-pass selection runs.
+constexpr uint32_t kSelWin = 1u << 25;
+
+template <typename Get>
+__device__ uint32_t select_rank_u32_upto(Get get, int64_t m, uint64_t r, uint32_t hi, SelectShared& sh) {
+    const uint32_t lo = hi >= kSelWin - 1u ? hi - (kSelWin - 1u) : 0u;
+    for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
+    if (threadIdx.x == 0) sh.below = 0;
+    __syncthreads();
+    uint32_t below = 0;
+    auto count1 = [&](uint32_t u) {
+        if (u < lo) ++below;
+        else if (u <= hi) atomicAdd(&sh.hist[(u - lo) >> 13], 1u);
+    };
+    int64_t i = threadIdx.x;
+    for (; i + 768 < m; i += 1024) {
+        const uint32_t u0 = get(i), u1 = get(i + 256), u2 = get(i + 512), u3 = get(i + 768);
+        count1(u0); count1(u1); count1(u2); count1(u3);
+    }
+    for (; i < m; i += 256) count1(get(i));
+    below = dl_wave_sum(below);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&sh.below, below);
+    __syncthreads();
+    const uint64_t nb = sh.below;
+    if (r <= nb) return select_rank_u32(get, m, r, sh);
+    find_bin(sh.hist, 4096, r - nb, sh.scratch, &sh.d, &sh.before, &sh.total);
+    if (sh.d < 0) return select_rank_u32(get, m, r, sh);
+    const uint64_t r2 = r - nb - sh.before;
+    const uint32_t base = lo + ((uint32_t)sh.d << 13);
+    __syncthreads();
+    for (int b = threadIdx.x; b < 8192; b += 256) sh.hist[b] = 0;
+    __syncthreads();
+    auto count2 = [&](uint32_t u) {
+        if (u >= base && u - base < 8192u) atomicAdd(&sh.hist[u - base], 1u);
+    };
+    i = threadIdx.x;
+    for (; i + 768 < m; i += 1024) {
+        const uint32_t u0 = get(i), u1 = get(i + 256), u2 = get(i + 512), u3 = get(i + 768);
+        count2(u0); count2(u1); count2(u2); count2(u3);
+    }
+    for (; i < m; i += 256) count2(get(i));
+    __syncthreads();
+    find_bin(sh.hist, 8192, r2, sh.scratch, &sh.d, &sh.before, &sh.total);
+    const uint32_t res = base + (uint32_t)sh.d;
+    __syncthreads();
+    return res;
 }
 
 // The k smallest of m unique 64-bit keys in buf (global), sorted ascending into
@@ -592,7 +647,8 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                                                      int32_t* __restrict__ cand_ft, const float* __restrict__ cand_lb,
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
                                                      float* __restrict__ thr_out, int32_t* __restrict__ stop_out,
-                                                     uint64_t* __restrict__ bm, int64_t W, LeafTabs lt, int64_t n)
+                                                     uint64_t* __restrict__ bm, int64_t W, LeafTabs lt, int64_t n,
+                                                     const float* __restrict__ gthr)
 {
     __shared__ SelectShared sh;
     __shared__ uint32_t tc[8];
@@ -641,7 +697,9 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     }
     const float* lbt = cand_lb + (int64_t)t * cap * L;
     const float* mt = cand_m + (int64_t)t * cap;
-    const float thr = select_rank_f32([&](int64_t s) { return mt[s]; }, (int64_t)cnt, N_S, sh);
+    // every candidate has m^2 <= its query's guess threshold
+    const float thr = __uint_as_float(select_rank_u32_upto([&](int64_t s) { return __float_as_uint(mt[s]); },
+                                                           (int64_t)cnt, N_S, __float_as_uint(gthr[t]), sh));
     // first admitting tree f(o) = min{i : LB_i^2 <= thr} (0: none) of every
     // entry, kept in cand_ft; |U_i| for i = 1..L counts the entries with
     // 0 < f(o) <= i
@@ -1572,18 +1630,18 @@ hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     if (a.fixed) {
         hipLaunchKernelGGL((select_kernel<L, true, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n);
+                           a.lt, a.n, a.gthr);
         return hipGetLastError();
     }
     if (a.leaf) {
         hipLaunchKernelGGL((select_kernel<L, false, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n);
+                           a.lt, a.n, a.gthr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((select_kernel<L, false, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                        a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W, a.lt,
-                       a.n);
+                       a.n, a.gthr);
     return hipGetLastError();
 }
 
