@@ -66,35 +66,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     }
 }
 
-// Exclusive scan of up to a few million uint32 in one workgroup of 1024 threads:
-// each thread scans a contiguous slice, the slice totals are scanned in LDS.
-__global__ __launch_bounds__(1024) void scan_single_kernel(const uint32_t* __restrict__ in,
-                                                           uint32_t* __restrict__ out, int64_t n,
-                                                           uint32_t* __restrict__ total)
-{
-    __shared__ uint32_t part[1024];
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t s = threadIdx.x * per;
-    const int64_t e = (s + per < n) ? s + per : n;
-    uint32_t acc = 0;
-    for (int64_t i = s; i < e; ++i) acc += in[i];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t t = (threadIdx.x >= o) ? part[threadIdx.x - o] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += t;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - acc;
-    for (int64_t i = s; i < e; ++i) {
-        uint32_t x = in[i];
-        out[i] = run;
-        run += x;
-    }
-    if (threadIdx.x == 1023 && total) *total = part[1023];
-}
-
 // Three-phase exclusive scan for large arrays: per-block sums, scan of sums,
 // per-block rescan with offset.
 constexpr int kScanBlock = 1024;
@@ -211,6 +182,32 @@ __global__ void edges_from_b_kernel(const float* __restrict__ B, float* __restri
 // ---------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------
+
+// Exclusive scan in one workgroup of 1024 threads: tiles of 4096 elements
+// (four consecutive per thread) are scanned block-wide in turn, with the
+// running total carried from tile to tile.  Every thread has read its
+// elements of a tile before the scan's barriers, so in == out is allowed.
+__global__ __launch_bounds__(1024) void scan_single_kernel(const uint32_t* in, uint32_t* out, int64_t n,
+                                                           uint32_t* __restrict__ total)
+{
+    __shared__ uint32_t sh[40];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < n; base += 4096) {
+        const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (i0 + j < n) ? in[i0 + j] : 0u;
+        uint32_t tot;
+        uint32_t run = block_excl_scan_1024(v[0] + v[1] + v[2] + v[3], sh, &tot) + carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < n) out[i0 + j] = run;
+            run += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
 
 size_t dl_scan_tmp_bytes(int64_t n) {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
