@@ -75,15 +75,16 @@ struct DevBuf {
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Query workspaces outlive the call that allocated them: a call that ends
-// normally (its stream synchronised, so no kernel still uses the buffer)
-// hands the buffer back, and a later call on the same device takes the
-// smallest idle one that is large enough instead of paying for hipMalloc and
-// a device-synchronising hipFree of gigabytes.  At most kWsIdle buffers per
-// device stay idle; detlsh_trim frees them all.  The cache is never
-// destroyed (no hipFree during static destruction, after the runtime may be
-// gone); the driver reclaims the memory at process exit.
-constexpr size_t kWsIdle = 4;
+// Device buffers outlive their owner where no kernel can still use them: a
+// query call that ends normally (its stream synchronised) hands its workspace
+// back, and so does an index at detlsh_free (no call may run on it then).  A
+// later allocation on the same device takes the smallest idle buffer that is
+// large enough (index arrays: at most twice the size asked for) instead of
+// paying for hipMalloc and a device-synchronising hipFree.  At most kWsIdle
+// buffers per device stay idle; detlsh_trim frees them all.  The cache is
+// never destroyed (no hipFree during static destruction, after the runtime
+// may be gone); the driver reclaims the memory at process exit.
+constexpr size_t kWsIdle = 32;
 
 struct WsCache {
     std::mutex mu;
@@ -94,21 +95,23 @@ WsCache& ws_cache() {
     return *c;
 }
 
-DevBuf* ws_take(int dev, size_t bytes) {
+// An idle buffer of bytes..max_bytes on `dev` (the smallest), or nullptr.
+DevBuf* ws_cached(int dev, size_t bytes, size_t max_bytes) {
     WsCache& c = ws_cache();
-    {
-        std::lock_guard<std::mutex> lk(c.mu);
-        size_t best = c.idle.size();
-        for (size_t i = 0; i < c.idle.size(); ++i)
-            if (c.idle[i].first == dev && c.idle[i].second->bytes >= bytes &&
-                (best == c.idle.size() || c.idle[i].second->bytes < c.idle[best].second->bytes))
-                best = i;
-        if (best < c.idle.size()) {
-            DevBuf* b = c.idle[best].second;
-            c.idle.erase(c.idle.begin() + (std::ptrdiff_t)best);
-            return b;
-        }
-    }
+    std::lock_guard<std::mutex> lk(c.mu);
+    size_t best = c.idle.size();
+    for (size_t i = 0; i < c.idle.size(); ++i)
+        if (c.idle[i].first == dev && c.idle[i].second->bytes >= bytes && c.idle[i].second->bytes <= max_bytes &&
+            (best == c.idle.size() || c.idle[i].second->bytes < c.idle[best].second->bytes))
+            best = i;
+    if (best == c.idle.size()) return nullptr;
+    DevBuf* b = c.idle[best].second;
+    c.idle.erase(c.idle.begin() + (std::ptrdiff_t)best);
+    return b;
+}
+
+DevBuf* ws_take(int dev, size_t bytes) {
+    if (DevBuf* b = ws_cached(dev, bytes, ~(size_t)0)) return b;
     std::unique_ptr<DevBuf> b(new DevBuf);
     if (b->alloc(bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -140,6 +143,37 @@ void ws_give(int dev, DevBuf* b) {
         }
     }
     delete drop;
+}
+
+// Allocation of an index array (current device `dev`): an idle cached buffer
+// of at most twice the size, else hipMalloc (after freeing the idle buffers
+// when the device is full).
+hipError_t pool_alloc(DevBuf& dst, size_t bytes, int dev) {
+    dst.release();
+    const size_t need = bytes ? bytes : 4;
+    if (DevBuf* b = ws_cached(dev, need, 2 * need)) {
+        dst.p = b->p;
+        dst.bytes = b->bytes;
+        b->p = nullptr;
+        b->bytes = 0;
+        delete b;
+        return hipSuccess;
+    }
+    if (dst.alloc(bytes) == hipSuccess) return hipSuccess;
+    (void)hipGetLastError();
+    detlsh_trim();
+    return dst.alloc(bytes);
+}
+
+// Hands an idle index array to the cache.
+void pool_give(DevBuf& src, int dev) {
+    if (!src.p) return;
+    DevBuf* b = new DevBuf;
+    b->p = src.p;
+    b->bytes = src.bytes;
+    src.p = nullptr;
+    src.bytes = 0;
+    ws_give(dev, b);
 }
 
 // A workspace held by one call: returned to the cache when the call marks it
@@ -258,6 +292,16 @@ struct detlsh_index_s {
     uint8_t* leaf_lo[8] = {};
     uint8_t* leaf_hi[8] = {};
     ~detlsh_index_s() {
+        // No call may run on the index now; a build that failed midway may
+        // still have kernels in flight, so the device is drained first (as
+        // hipFree would) before the arrays become reusable.
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        if (hipSetDevice(device) == hipSuccess) (void)hipDeviceSynchronize();
+        for (DevBuf* b : {&X, &Xbf, &A, &Abf, &B, &E, &codes, &perm, &scodes, &xn, &xn_bf, &gcodes, &leaf_of,
+                          &gleaf})
+            pool_give(*b, device);
+        if (have) (void)hipSetDevice(cur);
         for (int i = 0; i < 8; ++i) {
             if (leaf_start[i]) (void)hipFree(leaf_start[i]);
             if (leaf_lo[i]) (void)hipFree(leaf_lo[i]);
@@ -287,16 +331,16 @@ detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_
 
 // Shared tail of build and import: row norms, trees.
 detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
-    HCHECK(ix->xn.alloc((size_t)ix->n * 4));
-    if (keep_bf16) HCHECK(ix->xn_bf.alloc((size_t)ix->n * 4));
+    HCHECK(pool_alloc(ix->xn, (size_t)ix->n * 4, ix->device));
+    if (keep_bf16) HCHECK(pool_alloc(ix->xn_bf, (size_t)ix->n * 4, ix->device));
     HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(),
                                keep_bf16 ? ix->xn_bf.as<float>() : nullptr, st));
     ix->G = (int32_t)std::min<int64_t>(ix->n, kGuessMax);
-    HCHECK(ix->gcodes.alloc((size_t)ix->G * ix->LK));
+    HCHECK(pool_alloc(ix->gcodes, (size_t)ix->G * ix->LK, ix->device));
     HCHECK(dl_launch_pack_sample(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->G, ix->gcodes.as<uint8_t>(), st));
+    DevBuf tmp;   // reused by the trees in turn (each build ends with a synchronisation)
+    HCHECK(tmp.alloc(dl_tree_tmp_bytes(ix->n, ix->K)));
     for (int i = 0; i < ix->L; ++i) {
-        DevBuf tmp;
-        HCHECK(tmp.alloc(dl_tree_tmp_bytes(ix->n, ix->K)));
         DlTimer tm(T_TREE, st);
         HCHECK(dl_build_tree(ix->codes.as<uint8_t>() + (int64_t)i * ix->n * ix->K, ix->n, ix->K, ix->N_r,
                              ix->max_leaf, ix->perm.as<int32_t>() + (int64_t)i * ix->n,
@@ -305,8 +349,8 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
         HCHECK(hipStreamSynchronize(st));
     }
     // point -> leaf of every tree, and the leaves of the guess subset
-    HCHECK(ix->leaf_of.alloc((size_t)ix->n * ix->L * 4));
-    HCHECK(ix->gleaf.alloc((size_t)ix->G * ix->L * 4));
+    HCHECK(pool_alloc(ix->leaf_of, (size_t)ix->n * ix->L * 4, ix->device));
+    HCHECK(pool_alloc(ix->gleaf, (size_t)ix->G * ix->L * 4, ix->device));
     for (int i = 0; i < ix->L; ++i)
         HCHECK(dl_launch_leaf_of(ix->perm.as<int32_t>() + (int64_t)i * ix->n, ix->leaf_start[i], ix->n_leaves[i],
                                  ix->n, ix->leaf_of.as<int32_t>() + (int64_t)i * ix->n, st));
@@ -319,26 +363,26 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
 detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_build_opts* opts, hipStream_t st) {
     const int64_t nd = ix->n * ix->d;
     if (X) {
-        HCHECK(ix->X.alloc((size_t)nd * 4));
+        HCHECK(pool_alloc(ix->X, (size_t)nd * 4, ix->device));
         HCHECK(hipMemcpyAsync(ix->X.p, X, (size_t)nd * 4, hipMemcpyDeviceToDevice, st));
     }
     const bool want_bf = opts && (opts->keep_bf16 || opts->proj_bf16);
     if (want_bf) {
-        HCHECK(ix->Xbf.alloc((size_t)nd * 2));
+        HCHECK(pool_alloc(ix->Xbf, (size_t)nd * 2, ix->device));
         DlTimer tm(T_BF16, st);
         HCHECK(dl_launch_to_bf16(ix->X.as<float>(), ix->Xbf.as<uint16_t>(), nd, st));
     }
-    HCHECK(ix->A.alloc((size_t)ix->LK * ix->d * 4));
+    HCHECK(pool_alloc(ix->A, (size_t)ix->LK * ix->d * 4, ix->device));
     HCHECK(hipMemcpyAsync(ix->A.p, ix->A_host.data(), (size_t)ix->LK * ix->d * 4, hipMemcpyHostToDevice, st));
     std::vector<uint16_t> abf((size_t)ix->LK * ix->d);
     for (size_t t = 0; t < abf.size(); ++t) abf[t] = host_bf16(ix->A_host[t]);
-    HCHECK(ix->Abf.alloc(abf.size() * 2));
+    HCHECK(pool_alloc(ix->Abf, abf.size() * 2, ix->device));
     HCHECK(hipMemcpyAsync(ix->Abf.p, abf.data(), abf.size() * 2, hipMemcpyHostToDevice, st));
-    HCHECK(ix->B.alloc((size_t)ix->LK * (ix->N_r + 1) * 4));
-    HCHECK(ix->E.alloc((size_t)ix->LK * (ix->N_r + 1) * 4));
-    if (X) HCHECK(ix->codes.alloc((size_t)ix->n * ix->LK));
-    HCHECK(ix->perm.alloc((size_t)ix->n * ix->L * 4));
-    HCHECK(ix->scodes.alloc((size_t)ix->n * ix->LK));
+    HCHECK(pool_alloc(ix->B, (size_t)ix->LK * (ix->N_r + 1) * 4, ix->device));
+    HCHECK(pool_alloc(ix->E, (size_t)ix->LK * (ix->N_r + 1) * 4, ix->device));
+    if (X) HCHECK(pool_alloc(ix->codes, (size_t)ix->n * ix->LK, ix->device));
+    HCHECK(pool_alloc(ix->perm, (size_t)ix->n * ix->L * 4, ix->device));
+    HCHECK(pool_alloc(ix->scodes, (size_t)ix->n * ix->LK, ix->device));
     HCHECK(hipStreamSynchronize(st));   // abf leaves scope
     return DETLSH_OK;
 }
@@ -643,8 +687,8 @@ detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void
         ix->leaf_start[i] = nullptr; ix->leaf_lo[i] = nullptr; ix->leaf_hi[i] = nullptr;
         ix->n_leaves[i] = 0;
     }
-    HCHECK(ix->perm.alloc((size_t)n1 * ix->L * 4));
-    HCHECK(ix->scodes.alloc((size_t)n1 * ix->LK));
+    HCHECK(pool_alloc(ix->perm, (size_t)n1 * ix->L * 4, ix->device));
+    HCHECK(pool_alloc(ix->scodes, (size_t)n1 * ix->LK, ix->device));
     detlsh_status s = finish_index(ix, keep_bf16, st);
     if (s) return s;
     HCHECK(hipStreamSynchronize(st));

@@ -319,3 +319,43 @@ def test_reused_workspace_gives_identical_results(dl):
     for a, b in ((d0, d2), (d0, d4), (d1[:37], d0), (d3, d1)):
         assert torch.equal(a, b)
     idx.free()
+
+
+def test_rebuild_on_reused_index_memory_is_identical(dl):
+    """A freed index's arrays are cached and handed to the next build, still
+    holding the old contents: a rebuild over such memory (after an index of
+    another size and data filled it) equals the first build in every exported
+    array and in its answers, in the FP32, BF16+rerank and leaf forms."""
+    import torch
+    cc = U.case(n=20000, d=48, N_r=64, frac=0.05, nq=120, seed=93)
+    other = U.case(n=16000, d=48, N_r=64, frac=0.05, nq=10, seed=94, kind="integer")
+    Q = t(cc["Q"])
+
+    def build_and_answer():
+        idx = dl.build_index(cc["X"], 4, 16, 64, 0.05, A=cc["A"], sample_ids=cc["sample"], keep_bf16=True)
+        out = [idx.query(Q, 10, 1.5, 0.1), idx.query(Q, 10, 1.5, 0.1, precision=dl.BF16_RERANK),
+               idx.query(Q, 10, 1.5, 0.1, granularity="leaf")]
+        ex = idx.export()
+        trees = [idx.tree(i) for i in range(4)]
+        torch.cuda.synchronize()
+        idx.free()
+        return out, ex, trees
+
+    dl.trim()
+    say("first build on fresh memory")
+    out0, ex0, tr0 = build_and_answer()
+    say("an index of another size and data, freed into the cache")
+    idx2 = dl.build_index(other["X"], 4, 16, 64, 0.05, A=other["A"], sample_ids=other["sample"], keep_bf16=True)
+    idx2.query(t(other["Q"]), 10, 1.5, 0.1)
+    torch.cuda.synchronize()
+    idx2.free()
+    say("rebuild on the cached arrays")
+    out1, ex1, tr1 = build_and_answer()
+    for (i0, d0), (i1, d1) in zip(out0, out1):
+        assert torch.equal(i0, i1) and torch.equal(d0, d1)
+    for key in ("A", "B", "codes", "sample_ids"):
+        assert np.array_equal(ex0[key], ex1[key]), key
+    for a, b in zip(tr0, tr1):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    dl.trim()
