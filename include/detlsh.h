@@ -407,12 +407,14 @@ detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double*
 void detlsh_free(detlsh_index idx);
 
 /*
- * A detlsh_query call (also _rc and _debug) keeps its device workspace when it
- * returns normally, and a later call on the same device takes the smallest
- * idle one that is large enough (at most 4 stay idle per device; a call that
- * fails frees its own).  detlsh_trim frees every idle workspace of the process
- * on every device, giving that memory back; workspaces of running calls are
- * not touched.  Any thread, any time.
+ * Device memory is cached per device instead of freed: a detlsh_query call
+ * (also _rc and _debug) keeps its workspace when it returns normally (a call
+ * that fails frees its own), and detlsh_free drains the device and keeps the
+ * index's arrays.  Later calls take the smallest idle buffer that is large
+ * enough (a build: at most twice the size it needs); at most 32 stay idle per
+ * device.  detlsh_trim frees every idle buffer of the process on every
+ * device, giving that memory back; buffers in use are not touched.  Any
+ * thread, any time.  An allocation that fails trims the cache and retries.
  */
 void detlsh_trim(void);
 const char* detlsh_last_error(void);   /* thread-local; valid until the next call */
