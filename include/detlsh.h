@@ -182,7 +182,7 @@ typedef struct {
     int32_t rmin_policy;        /* DETLSH_RMIN_MAGIC (default) or DETLSH_RMIN_FIXED  */
     int32_t max_rounds;         /* FIXED: radius rounds (1..64) before S = D; 0 -> 64 */
     double r_min;               /* FIXED: initial radius, > 0                        */
-    size_t workspace_bytes;     /* per-call workspace budget; 0 -> 4 GiB             */
+    size_t workspace_bytes;     /* per-call workspace budget; 0 -> 8 GiB             */
     int32_t verify;             /* candidate verification: 0 automatic, 1 gathered
                                    rows of S, 2 masked dense MFMA over all rows     */
     int32_t granularity;        /* DETLSH_POINT (0): a point enters by its cell's

@@ -996,6 +996,8 @@ struct Arena {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+constexpr int64_t kQueryTile = 128;   // queries per workgroup tile of the dense verification
+
 detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, int64_t q0, int64_t nq, int k,
                           const QueryPlan& plan, bool force_all_candidates, const Arena& arena, int64_t* out_ids,
                           float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
@@ -1008,8 +1010,11 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
             return fail(DETLSH_ENOMEM, "workspace of %zu bytes holds no query (%zu bytes each)", arena.bytes, pq);
         nqc = 1;
     }
-    if (nqc > nq) nqc = nq;
     if (nqc > 65535) nqc = 65535;
+    // several chunks of 1024 or more queries: whole 128-query tiles of the
+    // dense pass in all but the last (at most 1/8 more chunks)
+    if (nqc >= nq) nqc = nq;
+    else if (nqc >= 8 * kQueryTile) nqc -= nqc % kQueryTile;
     WsLease own;
     char* p = arena.p;
     if (!p) {
@@ -1292,7 +1297,7 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     if (ext) {
         arena = *ext;
     } else {
-        arena.bytes = (opts && opts->workspace_bytes) ? opts->workspace_bytes : ((size_t)4 << 30);
+        arena.bytes = (opts && opts->workspace_bytes) ? opts->workspace_bytes : ((size_t)8 << 30);
     }
     DevBuf qpbuf, ladder;
     const float* Qp = Qp_in;
