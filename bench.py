@@ -407,8 +407,9 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="print only the serving-form block")
     ap.add_argument("--beta-sweep", action="store_true",
                     help="also run the beta grid for QPS at recall@10 >= 0.9 (query only, both forms)")
-    ap.add_argument("--workload", choices=["c3", "c4", "next"], default=None,
-                    help="print only the named precision-form workload (d=960 copula / n=10^7 mixture)")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "next"], default=None,
+                    help="print only the named workload's beta grid for both forms (c2: SIFT-shaped, k = 10 "
+                         "and 50; c3: d=960 copula; c4: n=10^7 mixture, k = 10 and 100; next: the extra rows)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -430,7 +431,7 @@ def main():
         return
     if args.workload:
         name = args.workload.upper()
-        ks = (10,) if name == "C3" else (10, 100)
+        ks = {"C2": (10, 50), "C3": (10,)}.get(name, (10, 100))
         print(json.dumps(precision_bench(dl, torch, name, args.steps, args.warmup, ks)), flush=True)
         return
 
@@ -457,8 +458,10 @@ def main():
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
 
+    # both forms build the BF16 copy of X: the FP32 form screens with BF16
+    # products against a bound widened by their rounding (exact FP32 results)
     def step(bf16=False):
-        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=bf16)
+        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
         ids, dists = idx.query(Q, k, cfg.c, beta, precision=dl.BF16_RERANK if bf16 else dl.FP32)
         return idx, ids, dists
 
@@ -472,7 +475,7 @@ def main():
         last = None
         for _ in range(steps):
             tb = time.perf_counter()
-            ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=bf16)
+            ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
             bsum += time.perf_counter() - tb
             last = ix.query(Q, k, cfg.c, beta, precision=dl.BF16_RERANK if bf16 else dl.FP32)
             ix.free()

@@ -184,7 +184,9 @@ typedef struct {
     double r_min;               /* FIXED: initial radius, > 0                        */
     size_t workspace_bytes;     /* per-call workspace budget; 0 -> 8 GiB             */
     int32_t verify;             /* candidate verification: 0 automatic, 1 gathered
-                                   rows of S, 2 masked dense MFMA over all rows     */
+                                   rows of S, 2 masked dense MFMA over all rows,
+                                   3 as 2 with BF16 products screening for the FP32
+                                   form (index built with keep_bf16; same results) */
     int32_t granularity;        /* DETLSH_POINT (0): a point enters by its cell's
                                    bound; DETLSH_LEAF (1): by its DE-Tree leaf's box
                                    (the query-phase optimisation; MAGIC only)       */

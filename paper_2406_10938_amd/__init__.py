@@ -69,7 +69,7 @@ def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspac
                 granularity="point"):
     o = _lib.QueryOpts()
     o.granularity = {"point": 0, "leaf": 1}.get(granularity, granularity)
-    o.verify = {"auto": 0, "gather": 1, "dense": 2}.get(verify, verify)
+    o.verify = {"auto": 0, "gather": 1, "dense": 2, "dense_bf16": 3}.get(verify, verify)
     o.precision = int(precision)
     o.rerank_mult = int(rerank_mult)
     o.rmin_policy = int(rmin_policy)

@@ -53,6 +53,12 @@ __device__ __forceinline__ T dl_wave_sum(T v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t dl_wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
 __device__ __forceinline__ float dl_bf16_to_f32(uint16_t h);
 __device__ __forceinline__ uint16_t dl_f32_to_bf16(float f);
 

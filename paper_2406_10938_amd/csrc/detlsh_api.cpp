@@ -285,6 +285,7 @@ struct detlsh_index_s {
     int32_t proj_bf16 = 0;
     DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
     int32_t G = 0;                // guess subset size, min(n, kGuessMax)
+    float xmax = 0.f;             // bound on the largest row norm ||o|| (slightly above it)
     std::vector<int64_t> sample_ids;
     std::vector<float> A_host;
     int64_t n_leaves[8] = {};
@@ -335,6 +336,19 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     if (keep_bf16) HCHECK(pool_alloc(ix->xn_bf, (size_t)ix->n * 4, ix->device));
     HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(),
                                keep_bf16 ? ix->xn_bf.as<float>() : nullptr, st));
+    {
+        DevBuf mx;
+        HCHECK(mx.alloc(4));
+        HCHECK(dl_launch_max_f32(ix->xn.as<float>(), ix->n, mx.as<uint32_t>(), st));
+        uint32_t bits = 0;
+        HCHECK(hipMemcpyAsync(&bits, mx.p, 4, hipMemcpyDeviceToHost, st));
+        HCHECK(hipStreamSynchronize(st));
+        float x2;
+        std::memcpy(&x2, &bits, 4);
+        // the FP32 squared norm is within (d + 2) 2^-24 of the exact one
+        ix->xmax = (float)(std::sqrt((double)x2 * (1.0 + (ix->d + 8.0) * std::ldexp(1.0, -24))) *
+                           (1.0 + std::ldexp(1.0, -20)));
+    }
     ix->G = (int32_t)std::min<int64_t>(ix->n, kGuessMax);
     HCHECK(pool_alloc(ix->gcodes, (size_t)ix->G * ix->LK, ix->device));
     HCHECK(dl_launch_pack_sample(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->G, ix->gcodes.as<uint8_t>(), st));
@@ -900,6 +914,7 @@ struct QueryPlan {
     int64_t cap = 0;
     bool dense = false;     // masked dense MFMA verification
     bool bf16 = false;      // BF16 products, rerank of rerank_mult*k
+    bool bf16_screen = false;  // FP32 form: BF16 products screen against a widened bound
     int kprime = 0;         // rank of the distance bound tau
     int64_t T = 0;          // members of S used for tau
     int64_t cap_sv = 0;     // survivor slots per query
@@ -1063,13 +1078,19 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         a.svc = reinterpret_cast<uint32_t*>(take((size_t)nqc * 4));
         a.cap_sv = plan.cap_sv;
         a.sv = reinterpret_cast<int32_t*>(take((size_t)nqc * plan.cap_sv * 4));
-        a.dense_bf16 = plan.bf16 ? 1 : 0;
-        if (plan.bf16) a.Qbf = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->d * 2));
+        a.dense_bf16 = (plan.bf16 || plan.bf16_screen) ? 1 : 0;
+        if (a.dense_bf16) a.Qbf = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->d * 2));
         a.xn = ix->xn.as<float>();
         a.xn_bf = ix->xn_bf.as<float>();
         // |approx - exact| <= (2 gamma_d + 4u)(|q|^2 + |o|^2) for the norm expression and the
-        // direct-difference reference, gamma_d = d u / (1 - d u), u = 2^-24
-        a.margin_c = plan.bf16 ? 0.0f : (float)((4.0 * ix->d + 16.0) * std::ldexp(1.0, -24));
+        // direct-difference reference, gamma_d = d u / (1 - d u), u = 2^-24.  The BF16 screen
+        // of the FP32 form takes twice that (no assumption on how the MFMA rounds its sums);
+        // the BF16 rounding of the operands is covered by the widened tau.
+        const double m32 = (4.0 * ix->d + 16.0) * std::ldexp(1.0, -24);
+        a.margin_c = plan.bf16 ? 0.0f : (float)(plan.bf16_screen ? 2.0 * m32 : m32);
+        a.widen_tau = plan.bf16_screen ? 1 : 0;
+        a.tau_rel = (float)((ix->d + 4.0) * std::ldexp(1.0, -24));
+        a.xmax = ix->xmax;
     }
     a.out_ids = out_ids; a.out_d = out_d;
     std::vector<float> inf_host;
@@ -1203,7 +1224,9 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
         return fail(DETLSH_EINVAL, "the BF16 form needs an index built with keep_bf16");
     if (s.precision == DETLSH_BF16_RERANK && (int64_t)s.rmult * k > 1024)
         return fail(DETLSH_EINVAL, "rerank_mult*k = %lld exceeds 1024", (long long)s.rmult * k);
-    if (s.verify < 0 || s.verify > 2) return fail(DETLSH_EINVAL, "verify mode %d is not defined", s.verify);
+    if (s.verify < 0 || s.verify > 3) return fail(DETLSH_EINVAL, "verify mode %d is not defined", s.verify);
+    if (s.verify == 3 && !ix->Xbf.p)
+        return fail(DETLSH_EINVAL, "verify mode 3 needs the index's BF16 copy (build with keep_bf16)");
     const int gran = opts ? opts->granularity : DETLSH_POINT;
     if (gran != DETLSH_POINT && gran != DETLSH_LEAF) return fail(DETLSH_EINVAL, "granularity %d is not defined", gran);
     if (gran == DETLSH_LEAF && s.policy != DETLSH_RMIN_MAGIC)
@@ -1239,8 +1262,10 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
         plan.cap = ix->n;
     }
     const bool bf16 = s.precision == DETLSH_BF16_RERANK;
-    plan.dense = !plan.all && !plan.fixed && (s.verify == 2 || (s.verify == 0 && (ix->n >= 65536 || bf16)));
+    plan.dense = !plan.all && !plan.fixed &&
+                 (s.verify == 2 || s.verify == 3 || (s.verify == 0 && (ix->n >= 65536 || bf16)));
     plan.bf16 = bf16 && plan.dense;
+    plan.bf16_screen = !bf16 && plan.dense && ix->Xbf.p && (s.verify == 3 || s.verify == 0);
     plan.kprime = (int)std::min<uint64_t>(plan.N_S, (uint64_t)(bf16 ? s.rmult * k : k));
     // tau reads T rows and the re-rank about k' |S| / T survivors: T = sqrt(k' N_S)
     // balances the two gathers (at least 2048 and 32 k')

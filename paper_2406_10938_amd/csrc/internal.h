@@ -29,6 +29,9 @@ struct ProjectArgs {
 hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st);
 hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st);
 hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, hipStream_t st);
+// Bit pattern of the largest of n non-negative floats into *out (which the
+// launch clears first).
+hipError_t dl_launch_max_f32(const float* v, int64_t n, uint32_t* out, hipStream_t st);
 
 // ---- sorting and scans (k_sort.hip) ----
 size_t dl_scan_tmp_bytes(int64_t n);
@@ -104,6 +107,11 @@ struct QueryArgs {
     const float* xn_bf = nullptr;    // squared norms of the BF16 rows
     int dense_bf16 = 0;
     float margin_c = 0.f;
+    // FP32 form screened with BF16 products: tau is widened per query to
+    // (sqrt(tau) (1 + tau_rel) + 2^-8 (1 + 2^-10) (||q|| + xmax))^2 (1 + 2^-20)
+    int widen_tau = 0;
+    float tau_rel = 0.f;
+    float xmax = 0.f;                // largest row norm ||o||
     uint32_t* svc = nullptr;         // survivors per query
     int32_t* sv = nullptr;
     int64_t cap_sv = 0;

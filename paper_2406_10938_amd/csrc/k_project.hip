@@ -236,6 +236,23 @@ hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, floa
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void max_f32_kernel(const float* __restrict__ v, int64_t n,
+                                                     uint32_t* __restrict__ out) {
+    uint32_t m = 0;   // non-negative floats order like their bit patterns
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = max(m, __float_as_uint(v[i]));
+    m = dl_wave_max_u32(m);
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+hipError_t dl_launch_max_f32(const float* v, int64_t n, uint32_t* out, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(out, 0, 4, st);
+    if (e != hipSuccess || n <= 0) return e;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(max_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
 __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;

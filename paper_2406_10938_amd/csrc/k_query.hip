@@ -942,16 +942,25 @@ constexpr int kDQ = 128;   // queries per workgroup tile (4 waves: 2 query halve
 constexpr int kDP = 64;    // points per tile (one bitmap word per query)
 
 // Squared norms of the chunk's queries (of their BF16 roundings when bf16) and
-// the BF16 copy of the chunk's rows.
+// the BF16 copy of the chunk's rows.  widen: the FP32 form screened with BF16
+// products.  A member o of S with FP32 distance d32(o)^2 <= tau must survive
+// the screen.  Its exact distance is D <= sqrt(tau) (1 + tau_rel) (tau_rel
+// bounds the relative error of the direct-difference sums), and the BF16
+// roundings move each vector by at most 2^-8 of its norm, so the distance of
+// the rounded pair is D_h <= D + 2^-8 (||q|| + ||o||) <= R with ||o|| <= xmax.
+// tau becomes R^2 (the last factors cover the rounding of this computation);
+// the screen's margin still covers the norm expression's own error.
 __global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, int d, int bf16,
-                             float* __restrict__ qn, uint16_t* __restrict__ Qbf)
+                             float* __restrict__ qn, uint16_t* __restrict__ Qbf, int widen,
+                             float* __restrict__ tau, float tau_rel, float xmax)
 {
     const int t = blockIdx.x;
     if (t >= nqc) return;
     const float* q = Q + (q0 + t) * (int64_t)d;
-    float acc = 0.f;
+    float acc = 0.f, ex = 0.f;
     for (int c = threadIdx.x; c < d; c += 64) {
         float v = q[c];
+        ex = fmaf(v, v, ex);
         if (bf16) {
             const uint16_t h = dl_f32_to_bf16(v);
             Qbf[(int64_t)t * d + c] = h;
@@ -960,7 +969,16 @@ __global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, i
         acc = fmaf(v, v, acc);
     }
     acc = dl_wave_sum(acc);
-    if (threadIdx.x == 0) qn[t] = acc;
+    ex = dl_wave_sum(ex);
+    if (threadIdx.x == 0) {
+        qn[t] = acc;
+        const float tv = tau[t];
+        if (widen && tv >= 0.f && tv < INFINITY) {
+            const float delta = 0x1.004p-8f * (sqrtf(ex) + xmax) + 0x1p-100f;
+            const float r = fmaf(sqrtf(tv), 1.0f + tau_rel, delta);
+            tau[t] = r * r * (1.0f + 0x1p-20f);
+        }
+    }
 }
 
 // Every (query, point) pair of a 128 x 64 tile gets its dot product from
@@ -1750,7 +1768,8 @@ hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st) {
 hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st) {
     hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, T, 0, 0, kprime, a.tau, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(qprep_kernel, dim3(a.nqc), dim3(64), 0, st, a.Q, a.q0, a.nqc, a.d, a.dense_bf16, a.qn, a.Qbf);
+    hipLaunchKernelGGL(qprep_kernel, dim3(a.nqc), dim3(64), 0, st, a.Q, a.q0, a.nqc, a.d, a.dense_bf16, a.qn, a.Qbf,
+                       a.widen_tau, a.tau, a.tau_rel, a.xmax);
     return hipGetLastError();
 }
 

@@ -296,6 +296,30 @@ def test_dense_verification_equals_gathered(dl, n, d, kind, k, nq):
                              r["dists"][qi].cpu().numpy(), ref.S, k)
 
 
+@pytest.mark.parametrize("n,d,kind,k,nq", [(70_001, 128, "integer", 10, 150), (66_000, 37, "mixture", 20, 130),
+                                           (80_000, 96, "mixture", 100, 64), (65_600, 200, "mixture", 1, 257),
+                                           (65_536, 962, "integer", 5, 70), (70_000, 128, "mixture", 50, 200)])
+def test_bf16_screen_gives_the_fp32_results(dl, n, d, kind, k, nq):
+    """The FP32 form may screen with BF16 products against a bound widened by
+    the BF16 rounding of both vectors; survivors are re-ranked with the same
+    FP32 direct distances, so ids and distance bits equal those of the
+    gathered pass and of the FP32-product screen."""
+    say(f"bf16 screen n={n} d={d} kind={kind} k={k} nq={nq}")
+    c = U.case(n=n, d=d, N_r=256, frac=0.01, kind=kind, nq=nq, seed=37)
+    idx = dl.build_index(c["X"], 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=True)
+    Q = t(c["Q"])
+    out = {v: idx.query(Q, k, 1.5, 0.1, verify=v) for v in ("gather", "dense", "dense_bf16", "auto")}
+    g_ids, g_d = (x.cpu().numpy() for x in out["gather"])
+    for v in ("dense", "dense_bf16", "auto"):
+        ids, dd = (x.cpu().numpy() for x in out[v])
+        assert np.array_equal(g_ids, ids), v
+        assert np.array_equal(g_d, dd), v
+    idx.free()
+    plain = dl.build_index(c["X"][:5000], 4, 16, 256, 0.1)
+    with pytest.raises(dl.DetlshError, match="keep_bf16"):
+        plain.query(Q[:2], k, 1.5, 0.1, verify="dense_bf16")
+
+
 @pytest.mark.parametrize("n,d,k", [(70_000, 128, 10), (66_000, 96, 25), (66_000, 300, 10), (65_600, 960, 10)])
 def test_bf16_rerank_form(dl, n, d, k):
     """BF16 products with FP32 accumulation keep candidates by the rerank
