@@ -603,7 +603,10 @@ def main():
         "config": {"workload": "SIFT-shaped n=1,000,000 d=128, 10,000 queries, k=10 c=1.5 beta=0.1, "
                                "L=4 K=16 N_r=256, 1% sample; step = build + query batch",
                    "n": n, "d": d, "nq": nq, "k": k, "beta": beta, "L": L, "K": K, "N_r": cfg.N_r,
-                   "precision": "fp32"},
+                   "precision": "fp32",
+                   "verification": "FP32 direct distances rank the members of S that survive a BF16-product "
+                                   "screen whose bound is widened by the BF16 rounding (results identical to "
+                                   "an all-FP32 pass)"},
         "recall_at_k": recall,
         "query_qps": nq / (query_ms / 1e3) if query_ms > 0 else None,
         "build_mpts_s": n / (build_ms / 1e3) / 1e6,
