@@ -257,28 +257,40 @@ __device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& s
 // keys over many bins instead of the few that the top 12 bits (sign,
 // exponent, 3 mantissa bits) give.  When the r-th key is not inside the
 // window (it lies below, or keys exceed hi) the three-pass selection runs.
+// The keys are a contiguous, 16-byte aligned array, read four per load with two
+// loads in flight per thread.
 constexpr uint32_t kSelWin = 1u << 25;
 
-template <typename Get>
-__device__ uint32_t select_rank_u32_upto(Get get, int64_t m, uint64_t r, uint32_t hi, SelectShared& sh) {
+__device__ uint32_t select_rank_u32_upto_v(const uint32_t* __restrict__ arr, int64_t m, uint64_t r, uint32_t hi,
+                                           SelectShared& sh) {
+    const uint4* a4 = reinterpret_cast<const uint4*>(arr);
+    const int64_t m4 = m >> 2;
+    auto pass = [&](auto count) {
+        int64_t i = threadIdx.x;
+        for (; i + 256 < m4; i += 512) {
+            const uint4 v = a4[i], w = a4[i + 256];
+            count(v.x); count(v.y); count(v.z); count(v.w);
+            count(w.x); count(w.y); count(w.z); count(w.w);
+        }
+        for (; i < m4; i += 256) {
+            const uint4 v = a4[i];
+            count(v.x); count(v.y); count(v.z); count(v.w);
+        }
+        for (int64_t t = 4 * m4 + threadIdx.x; t < m; t += 256) count(arr[t]);
+    };
     const uint32_t lo = hi >= kSelWin - 1u ? hi - (kSelWin - 1u) : 0u;
     for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
     if (threadIdx.x == 0) sh.below = 0;
     __syncthreads();
     uint32_t below = 0;
-    auto count1 = [&](uint32_t u) {
+    pass([&](uint32_t u) {
         if (u < lo) ++below;
         else if (u <= hi) atomicAdd(&sh.hist[(u - lo) >> 13], 1u);
-    };
-    int64_t i = threadIdx.x;
-    for (; i + 768 < m; i += 1024) {
-        const uint32_t u0 = get(i), u1 = get(i + 256), u2 = get(i + 512), u3 = get(i + 768);
-        count1(u0); count1(u1); count1(u2); count1(u3);
-    }
-    for (; i < m; i += 256) count1(get(i));
+    });
     below = dl_wave_sum(below);
     if ((threadIdx.x & 63) == 0) atomicAdd(&sh.below, below);
     __syncthreads();
+    auto get = [&](int64_t s) { return arr[s]; };
     const uint64_t nb = sh.below;
     if (r <= nb) return select_rank_u32(get, m, r, sh);
     find_bin(sh.hist, 4096, r - nb, sh.scratch, &sh.d, &sh.before, &sh.total);
@@ -288,15 +300,9 @@ __device__ uint32_t select_rank_u32_upto(Get get, int64_t m, uint64_t r, uint32_
     __syncthreads();
     for (int b = threadIdx.x; b < 8192; b += 256) sh.hist[b] = 0;
     __syncthreads();
-    auto count2 = [&](uint32_t u) {
+    pass([&](uint32_t u) {
         if (u >= base && u - base < 8192u) atomicAdd(&sh.hist[u - base], 1u);
-    };
-    i = threadIdx.x;
-    for (; i + 768 < m; i += 1024) {
-        const uint32_t u0 = get(i), u1 = get(i + 256), u2 = get(i + 512), u3 = get(i + 768);
-        count2(u0); count2(u1); count2(u2); count2(u3);
-    }
-    for (; i < m; i += 256) count2(get(i));
+    });
     __syncthreads();
     find_bin(sh.hist, 8192, r2, sh.scratch, &sh.d, &sh.before, &sh.total);
     const uint32_t res = base + (uint32_t)sh.d;
@@ -698,8 +704,8 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     const float* lbt = cand_lb + (int64_t)t * cap * L;
     const float* mt = cand_m + (int64_t)t * cap;
     // every candidate has m^2 <= its query's guess threshold
-    const float thr = __uint_as_float(select_rank_u32_upto([&](int64_t s) { return __float_as_uint(mt[s]); },
-                                                           (int64_t)cnt, N_S, __float_as_uint(gthr[t]), sh));
+    const float thr = __uint_as_float(select_rank_u32_upto_v(reinterpret_cast<const uint32_t*>(mt), (int64_t)cnt,
+                                                             N_S, __float_as_uint(gthr[t]), sh));
     // first admitting tree f(o) = min{i : LB_i^2 <= thr} (0: none) of every
     // entry, kept in cand_ft; |U_i| for i = 1..L counts the entries with
     // 0 < f(o) <= i
