@@ -1149,6 +1149,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
             }
             {
                 DlTimer tm(T_FINAL, st);
+                HCHECK(dl_launch_survivor_members(a, st));
                 HCHECK(dl_launch_final(a, st));
             }
             {

@@ -143,6 +143,9 @@ hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st);
 hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st);
 hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_final(const QueryArgs& a, hipStream_t st);
+// Point granularity: keeps only the members of S among the dense pass's
+// survivors (the bitmap holds the filter's hits, a superset of S).
+hipError_t dl_launch_survivor_members(const QueryArgs& a, hipStream_t st);
 hipError_t dl_launch_fixed_finish(const QueryArgs& a, int32_t* rounds, hipStream_t st);
 
 // ---- kernel timing (detlsh_api.cpp) ----

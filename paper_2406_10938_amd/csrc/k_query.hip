@@ -811,7 +811,7 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                     const uint32_t b = bound_bits(s);
                     mem = b < khi || (b == khi && leaf_min(idv[j]) <= klo);
                 }
-                if (!mem && bm) {
+                if (LEAF && !mem && bm) {
                     const int32_t id = idv[j];
                     atomicAnd((unsigned long long*)&bm[(int64_t)t * W + (id >> 6)], ~(1ull << (id & 63)));
                 }
@@ -938,6 +938,57 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
         out_ids[q * k + j] = (int64_t)(uint32_t)(key & 0xffffffffu);
         out_d[q * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
     }
+}
+
+// Point granularity leaves the membership bitmap as the filter wrote it (the
+// hits, m^2 <= guess threshold, a superset of S): clearing S's non-members
+// there took one global atomic each.  Instead the survivors of the dense
+// screen are tested here: each one's L bounds are recomputed by the filter's
+// own code from its codes and the query's projection (so bit for bit the same
+// values), and it is kept iff its first admitting tree f(o) = min{i : LB_i^2 <=
+// thr} exists and is at most the stop tree, the selection's own test.  The
+// list is compacted in place; an overflowed list is left for the fallback.
+template <int L, int K>
+__global__ __launch_bounds__(256) void survivor_members_kernel(const float* __restrict__ E, int N_r,
+                                                               const uint8_t* __restrict__ codes, int64_t n,
+                                                               const float* __restrict__ Qp, int64_t q0,
+                                                               const float* __restrict__ thr,
+                                                               const int32_t* __restrict__ stop,
+                                                               const int32_t* __restrict__ status,
+                                                               uint32_t* __restrict__ svc, int32_t* __restrict__ sv,
+                                                               int64_t cap_sv)
+{
+    __shared__ uint32_t wtot[4];
+    const int t = blockIdx.x;
+    if (status[t] != 0) return;
+    const uint32_t c = svc[t];
+    if ((int64_t)c > cap_sv) return;
+    const float th = thr[t];
+    const int istop = stop[t];
+    const float* qp = Qp + (q0 + t) * (int64_t)(L * K);
+    int32_t* list = sv + (int64_t)t * cap_sv;
+    uint32_t out = 0;
+    for (uint32_t c0 = 0; c0 < c; c0 += 256) {
+        const uint32_t s = c0 + threadIdx.x;
+        bool mem = false;
+        int32_t id = 0;
+        if (s < c) {
+            id = list[s];
+            float lo[L * K], hi[L * K], lb[L];
+            load_cell<L, K>(codes, n, id, E, N_r + 1, lo, hi);
+            (void)cell_lbs<L, K>(qp, lo, hi, lb);
+            int ft = 0;
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i)
+                if (lb[i] <= th) ft = i + 1;
+            mem = ft != 0 && ft <= istop;
+        }
+        uint32_t tot;
+        const uint32_t pre = block_flag_prefix(mem, wtot, &tot);   // its barriers order reads before writes
+        if (mem) list[out + pre] = id;
+        out += tot;
+    }
+    if (threadIdx.x == 0) svc[t] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -1735,6 +1786,18 @@ bool dl_supported_lk(int L, int K) {
 
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st) { DL_LK_DISPATCH(launch_guess_lk) }
 hipError_t dl_launch_filter(const QueryArgs& a, hipStream_t st) { DL_LK_DISPATCH(launch_filter_lk) }
+
+template <int L, int K>
+hipError_t launch_members_lk(const QueryArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((survivor_members_kernel<L, K>), dim3(a.nqc), dim3(256), 0, st, a.E, a.N_r, a.codes, a.n,
+                       a.Qp, a.q0, a.thr, a.stop, a.status, a.svc, a.sv, a.cap_sv);
+    return hipGetLastError();
+}
+
+hipError_t dl_launch_survivor_members(const QueryArgs& a, hipStream_t st) {
+    if (a.leaf) return hipSuccess;   // leaf granularity clears the bitmap in the selection
+    DL_LK_DISPATCH(launch_members_lk)
+}
 
 hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
     switch (a.L) {
