@@ -1044,6 +1044,10 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.E = ix->E.as<float>(); a.codes = ix->codes.as<uint8_t>(); a.X = ix->X.as<float>(); a.Xbf = ix->Xbf.as<uint16_t>();
     a.Q = Q; a.Qp = Qp; a.G = plan.G; a.gcodes = ix->gcodes.as<uint8_t>(); a.guess_rank = plan.rank;
     a.leaf = plan.leaf ? 1 : 0;
+    // the dense point path leaves S implicit in the candidate list unless the
+    // caller asked for the candidate dumps
+    const bool dumps = dbg.cand_ids || dbg.cand_counts || dbg.first_tree;
+    a.compact_s = (plan.dense && !plan.leaf && !plan.fixed && !dumps) ? 0 : 1;
     a.gleaf = ix->gleaf.as<int32_t>();
     a.lt.leaf_of = ix->leaf_of.as<int32_t>();
     a.lt.perm = ix->perm.as<int32_t>();

@@ -107,6 +107,9 @@ struct QueryArgs {
     const float* xn_bf = nullptr;    // squared norms of the BF16 rows
     int dense_bf16 = 0;
     float margin_c = 0.f;
+    // 0: the selection leaves S implicit in the candidate list (members are the
+    // entries with 1 <= f(o) <= the stop tree; dense point-granularity path)
+    int compact_s = 1;
     // FP32 form screened with BF16 products: tau is widened per query to
     // (sqrt(tau) (1 + tau_rel) + 2^-8 (1 + 2^-10) (||q|| + xmax))^2 (1 + 2^-20)
     int widen_tau = 0;

@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
                                                      float* __restrict__ thr_out, int32_t* __restrict__ stop_out,
                                                      uint64_t* __restrict__ bm, int64_t W, LeafTabs lt, int64_t n,
-                                                     const float* __restrict__ gthr)
+                                                     const float* __restrict__ gthr, int compact)
 {
     __shared__ SelectShared sh;
     __shared__ uint32_t tc[8];
@@ -747,6 +747,17 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     int istop = L;
     for (int i = 0; i < L; ++i)
         if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
+    if (!LEAF && !compact) {
+        // S stays implicit: the candidates with 1 <= f(o) <= istop (consumers
+        // filter the list; s_count is the list's length)
+        if (threadIdx.x == 0) {
+            status[t] = 0;
+            s_count[t] = (uint32_t)cnt;
+            thr_out[t] = thr;
+            stop_out[t] = istop;
+        }
+        return;
+    }
     // Leaf granularity: the stop tree's admitted leaves are taken in order of
     // (bound, smallest point id of the leaf) until |S| reaches N_S, so of the
     // entries first admitted by tree istop those up to the key of the
@@ -841,19 +852,32 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
 // Exact FP32 squared distances (direct differences, half a wave per row, R
 // rows in flight) of the rows listed for one query, written as 64-bit keys
 // (distance bits, id) to buf.
+// With `ft`, entry s is a member only if 1 <= ft[s] <= istop (an uncompacted
+// candidate list); other entries get the key (+inf, id) without a gather.
 template <bool ALIGNED>
 __device__ void gather_keys(const float* __restrict__ X, int d, const float* sq, const int32_t* __restrict__ ids,
-                            int64_t m, uint64_t* __restrict__ buf) {
+                            int64_t m, uint64_t* __restrict__ buf, const int32_t* __restrict__ ft = nullptr,
+                            int istop = 0) {
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
     constexpr int R = 4;
     for (int64_t s0 = (int64_t)hw * R; s0 < m; s0 += 8 * R) {
         int64_t id[R];
         float acc[R];
+        bool skip[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t s = s0 + r;
             id[r] = (s < m) ? (ids ? (int64_t)ids[s] : s) : -1;
+            skip[r] = false;
+            if (ft && id[r] >= 0) {
+                const int32_t f = ft[s];
+                if (f < 1 || f > istop) {
+                    skip[r] = true;
+                    if (hl == 0) buf[s] = (0x7f800000ull << 32) | (uint64_t)(uint32_t)id[r];
+                    id[r] = -1;
+                }
+            }
             acc[r] = 0.0f;
         }
         for (int c = 4 * hl; c < d; c += 128) {
@@ -886,7 +910,7 @@ __device__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
             float a2 = acc[r];
 #pragma unroll
             for (int o2 = 16; o2 > 0; o2 >>= 1) a2 += __shfl_xor(a2, o2, 32);
-            if (hl == 0 && id[r] >= 0)
+            if (hl == 0 && id[r] >= 0 && !skip[r])
                 buf[s0 + r] = ((uint64_t)__float_as_uint(a2) << 32) | (uint64_t)(uint32_t)id[r];
         }
     }
@@ -895,7 +919,8 @@ __device__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
 }
 
 // Top-k by (FP32 distance, id) over a per-query list of point ids (or over all
-// n points when `all_n`).  Modes:
+// n points when `all_n`); with `ftl` the list is a query's uncompacted
+// candidates and only entries with 1 <= ftl <= stops[t] count.  Modes:
 //   out_ids != null : write the k results of query q0+t (Euclidean distances)
 //   tau != null     : write tau[t] = squared distance of the k-th smallest
 // Queries are processed when status[t] == want.  When `sv_check`, a list with
@@ -906,7 +931,8 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     const int32_t* __restrict__ list, int64_t ld_list, const uint32_t* __restrict__ counts, int64_t use_max,
     int64_t all_n, int32_t* __restrict__ status, int want, int sv_check, int64_t sv_cap,
     uint64_t* __restrict__ ws, int64_t ld_ws, int k,
-    int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau, int keys_only)
+    int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau, int keys_only,
+    const int32_t* __restrict__ ftl, const int32_t* __restrict__ stops)
 {
     extern __shared__ unsigned char smem[];
     TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
@@ -926,7 +952,8 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
     __syncthreads();
     uint64_t* buf = ws + (int64_t)t * ld_ws;
-    gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf);
+    gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf,
+                         ftl ? ftl + (int64_t)t * ld_list : nullptr, stops ? stops[t] : 0);
     if (keys_only) return;
     topk_u64(buf, m, k, sh);
     if (tau) {
@@ -1705,18 +1732,18 @@ hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     if (a.fixed) {
         hipLaunchKernelGGL((select_kernel<L, true, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n, a.gthr);
+                           a.lt, a.n, a.gthr, a.compact_s);
         return hipGetLastError();
     }
     if (a.leaf) {
         hipLaunchKernelGGL((select_kernel<L, false, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n, a.gthr);
+                           a.lt, a.n, a.gthr, a.compact_s);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((select_kernel<L, false, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                        a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W, a.lt,
-                       a.n, a.gthr);
+                       a.n, a.gthr, a.compact_s);
     return hipGetLastError();
 }
 
@@ -1812,30 +1839,37 @@ hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
 template <bool AL>
 hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
                             int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
-                            int keys_only = 0) {
+                            int keys_only, bool members) {
     const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
     hipLaunchKernelGGL((gather_topk_kernel<AL>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
                        counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
-                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only);
+                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only,
+                       members ? a.cand_ft : nullptr, members ? a.stop : nullptr);
     return hipGetLastError();
 }
 
+// members: `list` is the uncompacted candidate list (cand_id), filtered by the
+// first admitting trees against the stop tree.
 hipError_t launch_gather(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
                          int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
-                         int keys_only = 0) {
+                         int keys_only = 0, bool members = false) {
     if (a.d % 4 == 0)
-        return launch_gather_al<true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only);
-    return launch_gather_al<false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only);
+        return launch_gather_al<true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only,
+                                      members);
+    return launch_gather_al<false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only,
+                                   members);
 }
 
 // Gathered verification of the whole of S (or D) for queries with status `want`.
 hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st) {
-    return launch_gather(a, a.cand_id, a.cap, a.s_count, 0, want, 0, a.k, nullptr, st);
+    return launch_gather(a, a.cand_id, a.cap, a.s_count, 0, want, 0, a.k, nullptr, st, 0, !a.compact_s);
 }
 
-// tau[t] = k'-th smallest exact distance over the first T members of S.
+// tau[t] = k'-th smallest exact distance over the members of S among the first
+// T entries of the list (all of them when S is compacted); +inf when fewer
+// than k' are members, which lets every member through the screen.
 hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st) {
-    hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, T, 0, 0, kprime, a.tau, st);
+    hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, T, 0, 0, kprime, a.tau, st, 0, !a.compact_s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(qprep_kernel, dim3(a.nqc), dim3(64), 0, st, a.Q, a.q0, a.nqc, a.d, a.dense_bf16, a.qn, a.Qbf,
                        a.widen_tau, a.tau, a.tau_rel, a.xmax);
