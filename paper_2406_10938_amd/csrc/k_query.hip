@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
     const bool valid = o_raw < n;
     const int64_t o = valid ? o_raw : n - 1;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar addressing
     float lo[LK], hi[LK];
     if (LEAF) load_box<L, K>(lt, lt.leaf_of, n, o, E, ldE, lo, hi);
     else load_cell<L, K>(codes, n, o, E, ldE, lo, hi);
