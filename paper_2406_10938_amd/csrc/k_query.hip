@@ -478,6 +478,7 @@ struct FilterShared {
     int32_t ids[4][kGroup][64];
     float key[4][kGroup][64];
     float lbs[4][kGroup][64][L];
+    uint64_t mask[4][kGroup];   // each wave's hit ballot per query of the group
     uint32_t wc[4][kGroup];
     uint32_t gb[kGroup];
 };
@@ -526,7 +527,12 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
     float lo[LK], hi[LK];
     if (LEAF) load_box<L, K>(lt, lt.leaf_of, n, o, E, ldE, lo, hi);
     else load_cell<L, K>(codes, n, o, E, ldE, lo, hi);
-    __builtin_amdgcn_s_waitcnt(0);   // settle the cell bounds once, outside the query loop
+    // settle the cell bounds once, outside the query loop: an empty use of
+    // every register makes the compiler wait for all the loads here (else it
+    // places its waits inside the loop, where they cost an issue slot each
+    // query)
+#pragma unroll
+    for (int e = 0; e < LK; ++e) asm volatile("" ::"v"(lo[e]), "v"(hi[e]));
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
     for (int tg = ta; tg < tb; tg += kGroup) {
@@ -538,7 +544,8 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
             float lb[L];
             float m = cell_lbs<L, K>(qp, lo, hi, lb);
             if (FIXED) m = entry_step<L>(lb, srad, T);   // the key is the entry step
-            const bool hit = valid && (m <= gthr[t]);
+            const float gt = gthr[t];
+            const bool hit = valid & (m <= gt);
             const uint64_t mask = dl_ballot(hit);
             if (hit) {
                 const int pos = dl_rank_below(mask);
@@ -547,17 +554,23 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
 #pragma unroll
                 for (int i = 0; i < L; ++i) sh.lbs[wave][g][pos][i] = lb[i];
             }
-            if (lane == 0) {
-                sh.wc[wave][g] = (uint32_t)__popcll(mask);
-                const int64_t word = (int64_t)blockIdx.x * 4 + wave;   // 64 consecutive points
-                if (bm && word < W) bm[(int64_t)t * W + word] = mask;
-            }
+            if (lane == 0) sh.mask[wave][g] = mask;   // counts and bitmap words follow from it at the flush
         }
         __syncthreads();
-        if (threadIdx.x < ng) {
+        if (threadIdx.x < ng) {                       // wave 0: one slot reservation per query
             const int g = threadIdx.x;
-            const uint32_t tot = sh.wc[0][g] + sh.wc[1][g] + sh.wc[2][g] + sh.wc[3][g];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t c = (uint32_t)__popcll(sh.mask[w][g]);
+                sh.wc[w][g] = c;
+                tot += c;
+            }
             sh.gb[g] = tot ? atomicAdd(&counts[tg + g], tot) : 0u;
+        } else if (threadIdx.x >= 64 && threadIdx.x < 64 + 4 * ng) {   // wave 1: the bitmap words
+            const int w = (threadIdx.x - 64) & 3, g = (threadIdx.x - 64) >> 2;
+            const int64_t word = (int64_t)blockIdx.x * 4 + w;   // 64 consecutive points
+            if (bm && word < W) bm[(int64_t)(tg + g) * W + word] = sh.mask[w][g];
         }
         __syncthreads();
         // Wave w copies out the block's hits of queries w, w+4, ...: the slots
