@@ -7,6 +7,7 @@
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Order-preserving map between FP32 and uint32 (total order of finite floats,
 // -0 < +0 is irrelevant here because keys only compare).
@@ -27,7 +28,7 @@ __device__ __forceinline__ int dl_rank_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ uint64_t dl_ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t dl_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Lanes of this wave whose 8-bit `digit` equals this lane's, among lanes where
 // `valid` holds.

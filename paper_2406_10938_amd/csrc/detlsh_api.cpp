@@ -1086,11 +1086,13 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         if (a.dense_bf16) a.Qbf = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->d * 2));
         a.xn = ix->xn.as<float>();
         a.xn_bf = ix->xn_bf.as<float>();
-        // |approx - exact| <= (2 gamma_d + 4u)(|q|^2 + |o|^2) for the norm expression and the
-        // direct-difference reference, gamma_d = d u / (1 - d u), u = 2^-24.  The BF16 screen
-        // of the FP32 form takes twice that (no assumption on how the MFMA rounds its sums);
-        // the BF16 rounding of the operands is covered by the widened tau.
-        const double m32 = (4.0 * ix->d + 16.0) * std::ldexp(1.0, -24);
+        // Screen margin in units of |q|^2 + |o|^2 (the shifted screen of the dense kernels):
+        // the dot product's rounding onto the shift, the norms', and the direct-difference
+        // distances that rank the survivors, about (5d + 12) u with u = 2^-24; (6d + 16) u is
+        // taken.  The BF16 screen of the FP32 form takes twice that (no assumption on how
+        // the MFMA rounds its sums); the BF16 rounding of the operands is covered by the
+        // widened tau.
+        const double m32 = (6.0 * ix->d + 16.0) * std::ldexp(1.0, -24);
         a.margin_c = plan.bf16 ? 0.0f : (float)(plan.bf16_screen ? 2.0 * m32 : m32);
         a.widen_tau = plan.bf16_screen ? 1 : 0;
         a.tau_rel = (float)((ix->d + 4.0) * std::ldexp(1.0, -24));

@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
     for (int tg = ta; tg < tb; tg += kGroup) {
-        const int ng = (tb - tg < kGroup) ? tb - tg : kGroup;
+        const int ng = __builtin_amdgcn_readfirstlane((tb - tg < kGroup) ? tb - tg : kGroup);
 #pragma unroll 1
         for (int g = 0; g < ng; ++g) {
             const int t = tg + g;
@@ -1093,23 +1093,37 @@ __global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, i
 constexpr int kSvl = 8;
 constexpr int kEpoch = 4;
 
+// The screen in shifted form.  The products start from -b(o) instead of 0,
+// so that acc = q.o - b(o), and o survives when acc >= a(q), with
+//   a(q) = ((1 - mc) ||q||^2 - tau) / 2,   b(o) = (1 - mc) ||o||^2 / 2,
+// i.e. ||q||^2 + ||o||^2 - 2 q.o <= tau + mc (||q||^2 + ||o||^2) rearranged:
+// one compare per product.  In units of ||q||^2 + ||o||^2 the margin mc
+// covers the dot product's rounding (now accumulated onto b(o) <= ||o||^2/2:
+// 2 gamma_{d+1}), the norms' (gamma_d), that of a, b and 1 - mc (a few u) and,
+// where tau is compared unwidened, the FP32 direct-difference distances that
+// rank the survivors (2 gamma_{d+3}): about (5d + 12) u in all.  The callers
+// pass (6d + 16) u, and twice that for BF16 products, whose operand rounding
+// is covered by the widened tau instead.
 struct DenseShared {
-    float qn[kDQ];
-    float tau[kDQ];             // bound on the k'-th squared distance (-inf: skip)
+    float aq[kDQ];              // a(q) per query (+inf: skip the query)
     uint64_t bits[2][kDQ];      // membership words of the current / next tile
-    float xn[2][kDP];
+    float xb[2][kDP];           // b(o) of the current / next tile's points
     uint32_t cnt[2][kDQ];
     int32_t list[2][kDQ][kSvl];
 };
 
-// Screen of one tile's products: a member of S whose ||q||^2 + ||o||^2 - 2 q.o
-// is within the query's bound joins its survivor list (LDS, epoch buffer ep;
-// straight to HBM when the list is full).
+__device__ __forceinline__ float dense_aq(float qn, float tau, float margin_c) {
+    return 0.5f * fmaf(1.0f - margin_c, qn, -tau);
+}
+__device__ __forceinline__ float dense_xb(float xn, float margin_c) { return 0.5f * (1.0f - margin_c) * xn; }
+
+// Screen of one tile's shifted products: a member of S with acc >= a(q)
+// joins its survivor list (LDS, epoch buffer ep; straight to HBM when the
+// list is full).
 __device__ __forceinline__ void dense_screen(const floatx4 (&acc)[4][2], DenseShared& sh, int cur, int ep, int qh,
-                                             int ph, int m, int kq, int64_t p0, int qt0, float margin_c,
+                                             int ph, int m, int kq, int64_t p0, int qt0,
                                              uint32_t* __restrict__ svc, int32_t* __restrict__ sv, int64_t cap_sv) {
     const int pi0 = 32 * ph + m;   // the lane's points: pi0 and pi0 + 16 (pi0 + 16 < 64)
-    const float xn0 = sh.xn[cur][pi0], xn1 = sh.xn[cur][pi0 + 16];
     // branch-free test of the lane's 32 products; bit 8 qb + 2 v + pb of hits
     // marks a survivor (survivors are rare, so appends run only when the
     // wave has any)
@@ -1120,12 +1134,10 @@ __device__ __forceinline__ void dense_screen(const floatx4 (&acc)[4][2], DenseSh
         for (int v = 0; v < 4; ++v) {
             const int qi = 64 * qh + 16 * qb + 4 * kq + v;
             const uint32_t w = (uint32_t)(sh.bits[cur][qi] >> pi0);   // bit 0: point pi0, bit 16: pi0 + 16
-            const float dqn = sh.qn[qi], dtau = sh.tau[qi];
+            const float a = sh.aq[qi];
 #pragma unroll
             for (int pb = 0; pb < 2; ++pb) {
-                const float nsum = dqn + (pb ? xn1 : xn0);
-                const float a2 = fmaf(-2.0f, acc[qb][pb][v], nsum);
-                const bool h = ((w >> (16 * pb)) & 1u) != 0u && a2 <= fmaf(margin_c, nsum, dtau);
+                const bool h = ((w >> (16 * pb)) & 1u) != 0u && acc[qb][pb][v] >= a;
                 hits |= (h ? 1u : 0u) << (8 * qb + 2 * v + pb);
             }
         }
@@ -1216,8 +1228,7 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     const int tq = qt0 + (int)threadIdx.x;
     const bool qok = threadIdx.x < kDQ && tq < nqc && status[tq] == 0;
     if (threadIdx.x < kDQ) {
-        sh.qn[threadIdx.x] = qok ? qn[tq] : 0.f;
-        sh.tau[threadIdx.x] = qok ? tau[tq] : -INFINITY;
+        sh.aq[threadIdx.x] = qok ? dense_aq(qn[tq], tau[tq], margin_c) : INFINITY;
         sh.cnt[0][threadIdx.x] = 0;
         sh.cnt[1][threadIdx.x] = 0;
     }
@@ -1231,7 +1242,7 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
     };
     auto store_meta = [&](int buf, uint64_t bits, float pxn) {
         if (threadIdx.x < kDQ) sh.bits[buf][threadIdx.x] = bits;
-        else if (threadIdx.x < kDQ + kDP) sh.xn[buf][threadIdx.x - kDQ] = pxn;
+        else if (threadIdx.x < kDQ + kDP) sh.xb[buf][threadIdx.x - kDQ] = dense_xb(pxn, margin_c);
     };
     uint64_t nbits = 0;
     float nxn = 0.f;
@@ -1271,7 +1282,10 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int pb = 0; pb < 2; ++pb) acc[qb][pb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int pb = 0; pb < 2; ++pb) {
+                const float b = -sh.xb[cur][32 * ph + 16 * pb + m];   // accumulator column m is point m
+                acc[qb][pb] = floatx4{b, b, b, b};
+            }
         int64_t prow[2];
 #pragma unroll
         for (int pb = 0; pb < 2; ++pb) {
@@ -1360,7 +1374,7 @@ __global__ __launch_bounds__(256) void dense_verify_kernel(
                 }
             }
         }
-        dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
+        dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, svc, sv, cap_sv);
         if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
         __syncthreads();
         if ((j + 1) % kEpoch == 0 || tile + 1 == te) dense_flush(sh, ep, tq, svc, sv, cap_sv);
@@ -1428,8 +1442,7 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     const int tq = qt0 + (int)threadIdx.x;
     const bool qok = threadIdx.x < kDQ && tq < nqc && status[tq] == 0;
     if (threadIdx.x < kDQ) {
-        sh.qn[threadIdx.x] = qok ? qn[tq] : 0.f;
-        sh.tau[threadIdx.x] = qok ? tau[tq] : -INFINITY;
+        sh.aq[threadIdx.x] = qok ? dense_aq(qn[tq], tau[tq], margin_c) : INFINITY;
         sh.cnt[0][threadIdx.x] = 0;
         sh.cnt[1][threadIdx.x] = 0;
     }
@@ -1443,7 +1456,7 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     };
     auto store_meta = [&](int buf, uint64_t bits, float pxn) {
         if (threadIdx.x < kDQ) sh.bits[buf][threadIdx.x] = bits;
-        else if (threadIdx.x < kDQ + kDP) sh.xn[buf][threadIdx.x - kDQ] = pxn;
+        else if (threadIdx.x < kDQ + kDP) sh.xb[buf][threadIdx.x - kDQ] = dense_xb(pxn, margin_c);
     };
     // staged vectors: thread t holds query vectors t + 256 i and point vectors t + 256 i
     uint4 sgq[S::SQ], sgx[S::SX];
@@ -1505,36 +1518,43 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int pb = 0; pb < 2; ++pb) acc[qb][pb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int pb = 0; pb < 2; ++pb) {
+                const float b = -sh.xb[cur][32 * ph + 16 * pb + m];   // accumulator column m is point m
+                acc[qb][pb] = floatx4{b, b, b, b};
+            }
         for (int c = 0; c < nchunk; ++c) {
             const bool last = c + 1 == nchunk;
             const bool more = !last || tile + 1 < te;
             if (more) stage_load(last ? tile + 1 : tile, last ? 0 : c + 1, !q_resident);
             // steps past d would multiply staged zeros: a short last chunk stops early
-            const int nks = min(S::CK, (d - c * S::DC + 15) / 16);
+            // (BF16: 32-element steps of v_mfma_f32_16x16x32_bf16, lane l giving
+            // elements 8(l/16)..+7 of its query row and of its point row; any
+            // assignment of elements to lanes gives the same sum when both
+            // operands use it)
+            const int kstep = BF16 ? 32 : 16;
+            const int nks = min(S::DC / kstep, (d - c * S::DC + kstep - 1) / kstep);
 #pragma unroll 2
             for (int ks = 0; ks < nks; ++ks) {
-                const int ko = 16 * ks + 4 * kq;
                 if (BF16) {
+                    const int ko = 32 * ks + 8 * kq;
                     const uint16_t* sq = reinterpret_cast<const uint16_t*>(sqc);
                     const uint16_t* sx = reinterpret_cast<const uint16_t*>(sxc);
-                    auto unpack = [](uint2 v) {
-                        return shortx4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff),
-                                       (short)(v.y >> 16)};
-                    };
-                    shortx4 qv[4], xv[2];
+                    bf16x8 qv[4], xv[2];
 #pragma unroll
                     for (int qb = 0; qb < 4; ++qb)
-                        qv[qb] = unpack(*reinterpret_cast<const uint2*>(sq + (64 * qh + 16 * qb + m) * S::LD + ko));
+                        qv[qb] = __builtin_bit_cast(
+                            bf16x8, *reinterpret_cast<const uint4*>(sq + (64 * qh + 16 * qb + m) * S::LD + ko));
 #pragma unroll
                     for (int pb = 0; pb < 2; ++pb)
-                        xv[pb] = unpack(*reinterpret_cast<const uint2*>(sx + (32 * ph + 16 * pb + m) * S::LD + ko));
+                        xv[pb] = __builtin_bit_cast(
+                            bf16x8, *reinterpret_cast<const uint4*>(sx + (32 * ph + 16 * pb + m) * S::LD + ko));
 #pragma unroll
                     for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
                         for (int pb = 0; pb < 2; ++pb)
-                            acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qv[qb], xv[pb], acc[qb][pb], 0, 0, 0);
+                            acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[qb], xv[pb], acc[qb][pb], 0, 0, 0);
                 } else {
+                    const int ko = 16 * ks + 4 * kq;
                     const float* sq = reinterpret_cast<const float*>(sqc);
                     const float* sx = reinterpret_cast<const float*>(sxc);
                     floatx4 qv[4], xv[2];
@@ -1561,7 +1581,7 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
             __syncthreads();   // every wave is done with this chunk's rows
             if (more) stage_store(!q_resident);
             if (last) {
-                dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, margin_c, svc, sv, cap_sv);
+                dense_screen(acc, sh, cur, ep, qh, ph, m, kq, p0, qt0, svc, sv, cap_sv);
                 if (tile + 1 < te) store_meta(cur ^ 1, nbits, nxn);
             }
             __syncthreads();   // next chunk staged; the tile's survivor lists complete
