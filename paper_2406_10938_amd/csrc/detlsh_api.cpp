@@ -986,7 +986,7 @@ struct Debug {
 int64_t round4(int64_t v) { return (v + 3) & ~(int64_t)3; }
 
 size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d) {
-    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8) + 64 * 256 + (size_t)p.G * 4;
+    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
 }
@@ -1072,6 +1072,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.cand_id = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
     a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
+    a.cand_f8 = reinterpret_cast<uint8_t*>(take((size_t)nqc * cap));
     a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * ix->L));
     a.ws = reinterpret_cast<uint64_t*>(take((size_t)nqc * cap * 8));
     if (plan.dense) {

@@ -91,6 +91,7 @@ struct QueryArgs {
     int32_t* cand_id = nullptr;
     float* cand_m = nullptr;         // m^2 = min over trees of the bounds
     int32_t* cand_ft = nullptr;      // first admitting tree of each member of S
+    uint8_t* cand_f8 = nullptr;      // first admitting tree of each candidate (implicit S)
     float* cand_lb = nullptr;
     int32_t* status = nullptr;
     uint32_t* s_count = nullptr;

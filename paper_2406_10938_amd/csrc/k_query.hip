@@ -667,7 +667,8 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
                                                      float* __restrict__ thr_out, int32_t* __restrict__ stop_out,
                                                      uint64_t* __restrict__ bm, int64_t W, LeafTabs lt, int64_t n,
-                                                     const float* __restrict__ gthr, int compact)
+                                                     const float* __restrict__ gthr, int compact,
+                                                     uint8_t* __restrict__ cand_f8)
 {
     __shared__ SelectShared sh;
     __shared__ uint32_t tc[8];
@@ -738,18 +739,30 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
         for (int i = 0; i < L; ++i) loc[i] += (ft != 0 && ft <= i + 1) ? 1u : 0u;
         return ft;
     };
+    // f(o) as int32 for the compaction, else (an implicit S, filtered by its
+    // readers) as one byte
+    const bool keep_ft = LEAF || compact;
+    uint8_t* ft8 = cand_f8 + (int64_t)t * cap;
     int64_t s = threadIdx.x;
     for (; s + 256 < (int64_t)cnt; s += 512) {   // two rows in flight per thread
         float la[L], lc[L];
         load_lbs<L>(lbt + s * L, la);
         load_lbs<L>(lbt + (s + 256) * L, lc);
-        ftree[s] = first_tree(la);
-        ftree[s + 256] = first_tree(lc);
+        const int fa = first_tree(la), fc = first_tree(lc);
+        if (keep_ft) {
+            ftree[s] = fa;
+            ftree[s + 256] = fc;
+        } else {
+            ft8[s] = (uint8_t)fa;
+            ft8[s + 256] = (uint8_t)fc;
+        }
     }
     for (; s < (int64_t)cnt; s += 256) {
         float la[L];
         load_lbs<L>(lbt + s * L, la);
-        ftree[s] = first_tree(la);
+        const int fa = first_tree(la);
+        if (keep_ft) ftree[s] = fa;
+        else ft8[s] = (uint8_t)fa;
     }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -865,11 +878,12 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
 // Exact FP32 squared distances (direct differences, half a wave per row, R
 // rows in flight) of the rows listed for one query, written as 64-bit keys
 // (distance bits, id) to buf.
-// With `ft`, entry s is a member only if 1 <= ft[s] <= istop (an uncompacted
-// candidate list); other entries get the key (+inf, id) without a gather.
+// With `ft` (one byte per entry), entry s is a member only if 1 <= ft[s] <=
+// istop (an uncompacted candidate list); other entries get the key (+inf, id)
+// without a gather.
 template <bool ALIGNED>
 __device__ void gather_keys(const float* __restrict__ X, int d, const float* sq, const int32_t* __restrict__ ids,
-                            int64_t m, uint64_t* __restrict__ buf, const int32_t* __restrict__ ft = nullptr,
+                            int64_t m, uint64_t* __restrict__ buf, const uint8_t* __restrict__ ft = nullptr,
                             int istop = 0) {
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
@@ -884,7 +898,7 @@ __device__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
             id[r] = (s < m) ? (ids ? (int64_t)ids[s] : s) : -1;
             skip[r] = false;
             if (ft && id[r] >= 0) {
-                const int32_t f = ft[s];
+                const int f = ft[s];
                 if (f < 1 || f > istop) {
                     skip[r] = true;
                     if (hl == 0) buf[s] = (0x7f800000ull << 32) | (uint64_t)(uint32_t)id[r];
@@ -945,7 +959,7 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     int64_t all_n, int32_t* __restrict__ status, int want, int sv_check, int64_t sv_cap,
     uint64_t* __restrict__ ws, int64_t ld_ws, int k,
     int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau, int keys_only,
-    const int32_t* __restrict__ ftl, const int32_t* __restrict__ stops)
+    const uint8_t* __restrict__ ftl, const int32_t* __restrict__ stops)
 {
     extern __shared__ unsigned char smem[];
     TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
@@ -1765,18 +1779,18 @@ hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     if (a.fixed) {
         hipLaunchKernelGGL((select_kernel<L, true, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n, a.gthr, a.compact_s);
+                           a.lt, a.n, a.gthr, a.compact_s, a.cand_f8);
         return hipGetLastError();
     }
     if (a.leaf) {
         hipLaunchKernelGGL((select_kernel<L, false, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n, a.gthr, a.compact_s);
+                           a.lt, a.n, a.gthr, a.compact_s, a.cand_f8);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((select_kernel<L, false, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                        a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W, a.lt,
-                       a.n, a.gthr, a.compact_s);
+                       a.n, a.gthr, a.compact_s, a.cand_f8);
     return hipGetLastError();
 }
 
@@ -1877,7 +1891,7 @@ hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_
     hipLaunchKernelGGL((gather_topk_kernel<AL>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
                        counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
                        tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only,
-                       members ? a.cand_ft : nullptr, members ? a.stop : nullptr);
+                       members ? a.cand_f8 : nullptr, members ? a.stop : nullptr);
     return hipGetLastError();
 }
 
