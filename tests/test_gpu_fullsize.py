@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size and launch configuration: the SIFT-shaped
 set (n = 10^6, d = 128), 10,000 queries, k = 10, beta = 0.1, default
-workspace (the same chunking as bench.py).  Sampled queries are recomputed by
+workspace (the same chunking as bench.py), index with its BF16 copy.  Sampled queries are recomputed by
 the FP64 oracle on the GPU's own encoding; every query is checked for the
 properties that hold at any size (|S| >= N_S, sorted results, distances equal
 to exact distances of the returned ids, determinism)."""
@@ -31,7 +31,8 @@ def c2():
     Xd = torch.from_numpy(X).cuda()
     Qd = torch.from_numpy(Q).cuda()
     print("full-size C2: build", flush=True)
-    idx = dl.build_index(Xd, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample)
+    # with the BF16 copy, as bench.py builds it: the FP32 form screens with BF16 products
+    idx = dl.build_index(Xd, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
     return dict(dl=dl, cfg=cfg, X=X, Q=Q, Xd=Xd, Qd=Qd, idx=idx)
 
 
@@ -76,3 +77,16 @@ def test_fullsize_properties_every_query(c2):
     assert np.all(counts >= N_S)
     assert np.all(r["stop_tree"].cpu().numpy() >= 1)
     assert np.array_equal(r["ids"].cpu().numpy(), ids.cpu().numpy())
+
+
+def test_fullsize_bf16_screen_equals_fp32_products(c2):
+    """Every one of the 10,000 answers of the FP32 form is bit-identical whether
+    the dense pass screens with BF16 products (the benchmark's path) or with
+    FP32 products."""
+    import torch
+    cfg, idx = c2["cfg"], c2["idx"]
+    print("full-size C2: BF16 screen vs FP32 products", flush=True)
+    a_ids, a_d = idx.query(c2["Qd"], 10, cfg.c, cfg.beta, verify="dense_bf16")
+    b_ids, b_d = idx.query(c2["Qd"], 10, cfg.c, cfg.beta, verify="dense")
+    assert torch.equal(a_ids, b_ids)
+    assert torch.equal(a_d, b_d)
