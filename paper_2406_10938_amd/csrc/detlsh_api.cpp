@@ -285,7 +285,7 @@ struct detlsh_index_s {
     int32_t proj_bf16 = 0;
     DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
     int32_t G = 0;                // guess subset size, min(n, kGuessMax)
-    float xmax = 0.f;             // bound on the largest row norm ||o|| (slightly above it)
+    float emax = 0.f;             // bound on the largest ||o - bf16(o)|| (slightly above it)
     std::vector<int64_t> sample_ids;
     std::vector<float> A_host;
     int64_t n_leaves[8] = {};
@@ -334,20 +334,26 @@ detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_
 detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     HCHECK(pool_alloc(ix->xn, (size_t)ix->n * 4, ix->device));
     if (keep_bf16) HCHECK(pool_alloc(ix->xn_bf, (size_t)ix->n * 4, ix->device));
-    HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(),
-                               keep_bf16 ? ix->xn_bf.as<float>() : nullptr, st));
-    {
-        DevBuf mx;
+    ix->emax = 0.f;
+    if (keep_bf16) {
+        // the largest BF16 rounding error ||o - bf16(o)|| of the rows (for the BF16 screen)
+        DevBuf xe, mx;
+        HCHECK(xe.alloc((size_t)ix->n * 4));
         HCHECK(mx.alloc(4));
-        HCHECK(dl_launch_max_f32(ix->xn.as<float>(), ix->n, mx.as<uint32_t>(), st));
+        HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), ix->xn_bf.as<float>(),
+                                   xe.as<float>(), st));
+        HCHECK(dl_launch_max_f32(xe.as<float>(), ix->n, mx.as<uint32_t>(), st));
         uint32_t bits = 0;
         HCHECK(hipMemcpyAsync(&bits, mx.p, 4, hipMemcpyDeviceToHost, st));
         HCHECK(hipStreamSynchronize(st));
-        float x2;
-        std::memcpy(&x2, &bits, 4);
-        // the FP32 squared norm is within (d + 2) 2^-24 of the exact one
-        ix->xmax = (float)(std::sqrt((double)x2 * (1.0 + (ix->d + 8.0) * std::ldexp(1.0, -24))) *
+        float e2;
+        std::memcpy(&e2, &bits, 4);
+        // each difference o_i - bf16(o_i) is exact; the FP32 sum of their squares is
+        // within (d + 2) 2^-24 of the exact one
+        ix->emax = (float)(std::sqrt((double)e2 * (1.0 + (ix->d + 8.0) * std::ldexp(1.0, -24))) *
                            (1.0 + std::ldexp(1.0, -20)));
+    } else {
+        HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), nullptr, nullptr, st));
     }
     ix->G = (int32_t)std::min<int64_t>(ix->n, kGuessMax);
     HCHECK(pool_alloc(ix->gcodes, (size_t)ix->G * ix->LK, ix->device));
@@ -1097,7 +1103,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         a.margin_c = plan.bf16 ? 0.0f : (float)(plan.bf16_screen ? 2.0 * m32 : m32);
         a.widen_tau = plan.bf16_screen ? 1 : 0;
         a.tau_rel = (float)((ix->d + 4.0) * std::ldexp(1.0, -24));
-        a.xmax = ix->xmax;
+        a.emax = ix->emax;
     }
     a.out_ids = out_ids; a.out_d = out_d;
     std::vector<float> inf_host;

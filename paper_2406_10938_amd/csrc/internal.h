@@ -28,7 +28,9 @@ struct ProjectArgs {
 
 hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st);
 hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st);
-hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, hipStream_t st);
+// xe (optional): squared norm of each row's BF16 rounding error.
+hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe,
+                               hipStream_t st);
 // Bit pattern of the largest of n non-negative floats into *out (which the
 // launch clears first).
 hipError_t dl_launch_max_f32(const float* v, int64_t n, uint32_t* out, hipStream_t st);
@@ -112,10 +114,10 @@ struct QueryArgs {
     // entries with 1 <= f(o) <= the stop tree; dense point-granularity path)
     int compact_s = 1;
     // FP32 form screened with BF16 products: tau is widened per query to
-    // (sqrt(tau) (1 + tau_rel) + 2^-8 (1 + 2^-10) (||q|| + xmax))^2 (1 + 2^-20)
+    // (sqrt(tau) (1 + tau_rel) + ||q - bf16(q)|| + emax)^2, times slack
     int widen_tau = 0;
     float tau_rel = 0.f;
-    float xmax = 0.f;                // largest row norm ||o||
+    float emax = 0.f;                // bound on the largest ||o - bf16(o)||
     uint32_t* svc = nullptr;         // survivors per query
     int32_t* sv = nullptr;
     int64_t cap_sv = 0;

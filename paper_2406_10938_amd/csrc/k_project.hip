@@ -206,33 +206,39 @@ hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st) {
 // FP32 -> BF16 copy (round to nearest even)
 // ---------------------------------------------------------------------------
 
-// Squared norms of the rows (FP32 sums in a fixed order) and of their BF16
-// roundings, used by the masked dense verification.
+// Squared norms of the rows (FP32 sums in a fixed order), of their BF16
+// roundings, and of the rounding errors x - bf16(x) (each difference exact),
+// used by the masked dense verification.
 __global__ void row_norms_kernel(const float* __restrict__ X, int64_t n, int d, float* __restrict__ xn,
-                                 float* __restrict__ xn_bf)
+                                 float* __restrict__ xn_bf, float* __restrict__ xe)
 {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;
     const int lane = threadIdx.x & 63;
     const float* x = X + row * d;
-    float a = 0.f, b = 0.f;
+    float a = 0.f, b = 0.f, e = 0.f;
     for (int c = lane; c < d; c += 64) {
         const float v = x[c];
         a = fmaf(v, v, a);
         const float w = dl_bf16_to_f32(dl_f32_to_bf16(v));
         b = fmaf(w, w, b);
+        const float r = v - w;
+        e = fmaf(r, r, e);
     }
     a = dl_wave_sum(a);
     b = dl_wave_sum(b);
+    e = dl_wave_sum(e);
     if (lane == 0) {
         xn[row] = a;
         if (xn_bf) xn_bf[row] = b;
+        if (xe) xe[row] = e;
     }
 }
 
-hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, hipStream_t st) {
+hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe,
+                               hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, d, xn, xn_bf);
+    hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, d, xn, xn_bf, xe);
     return hipGetLastError();
 }
 

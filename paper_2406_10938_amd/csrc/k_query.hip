@@ -1056,36 +1056,39 @@ constexpr int kDP = 64;    // points per tile (one bitmap word per query)
 // the BF16 copy of the chunk's rows.  widen: the FP32 form screened with BF16
 // products.  A member o of S with FP32 distance d32(o)^2 <= tau must survive
 // the screen.  Its exact distance is D <= sqrt(tau) (1 + tau_rel) (tau_rel
-// bounds the relative error of the direct-difference sums), and the BF16
-// roundings move each vector by at most 2^-8 of its norm, so the distance of
-// the rounded pair is D_h <= D + 2^-8 (||q|| + ||o||) <= R with ||o|| <= xmax.
-// tau becomes R^2 (the last factors cover the rounding of this computation);
-// the screen's margin still covers the norm expression's own error.
+// bounds the relative error of the direct-difference sums), and the distance
+// of the rounded pair is D_h <= D + ||q - bf16(q)|| + ||o - bf16(o)|| <= R,
+// with ||o - bf16(o)|| <= emax (the largest over the rows, from the build) and
+// ||q - bf16(q)|| measured here (each difference exact, the FP32 sum of
+// squares within (d + 2) 2^-24 of exact).  tau becomes R^2 (the last factors
+// cover the rounding of this computation); the screen's margin still covers
+// the norm expression's own error.
 __global__ void qprep_kernel(const float* __restrict__ Q, int64_t q0, int nqc, int d, int bf16,
                              float* __restrict__ qn, uint16_t* __restrict__ Qbf, int widen,
-                             float* __restrict__ tau, float tau_rel, float xmax)
+                             float* __restrict__ tau, float tau_rel, float emax)
 {
     const int t = blockIdx.x;
     if (t >= nqc) return;
     const float* q = Q + (q0 + t) * (int64_t)d;
-    float acc = 0.f, ex = 0.f;
+    float acc = 0.f, er = 0.f;
     for (int c = threadIdx.x; c < d; c += 64) {
         float v = q[c];
-        ex = fmaf(v, v, ex);
         if (bf16) {
             const uint16_t h = dl_f32_to_bf16(v);
             Qbf[(int64_t)t * d + c] = h;
-            v = dl_bf16_to_f32(h);
+            const float w = dl_bf16_to_f32(h);
+            er = fmaf(v - w, v - w, er);
+            v = w;
         }
         acc = fmaf(v, v, acc);
     }
     acc = dl_wave_sum(acc);
-    ex = dl_wave_sum(ex);
+    er = dl_wave_sum(er);
     if (threadIdx.x == 0) {
         qn[t] = acc;
         const float tv = tau[t];
         if (widen && tv >= 0.f && tv < INFINITY) {
-            const float delta = 0x1.004p-8f * (sqrtf(ex) + xmax) + 0x1p-100f;
+            const float delta = (1.0f + (float)(d + 8) * 0x1p-24f) * sqrtf(er) + emax + 0x1p-100f;
             const float r = fmaf(sqrtf(tv), 1.0f + tau_rel, delta);
             tau[t] = r * r * (1.0f + 0x1p-20f);
         }
@@ -1919,7 +1922,7 @@ hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t 
     hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, T, 0, 0, kprime, a.tau, st, 0, !a.compact_s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(qprep_kernel, dim3(a.nqc), dim3(64), 0, st, a.Q, a.q0, a.nqc, a.d, a.dense_bf16, a.qn, a.Qbf,
-                       a.widen_tau, a.tau, a.tau_rel, a.xmax);
+                       a.widen_tau, a.tau, a.tau_rel, a.emax);
     return hipGetLastError();
 }
 
