@@ -991,8 +991,14 @@ struct Debug {
 
 int64_t round4(int64_t v) { return (v + 3) & ~(int64_t)3; }
 
-size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d) {
-    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * (size_t)L + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
+// The dense point path leaves S implicit in the candidate list (unless the
+// caller asked for the candidate dumps); its candidates then carry one bound
+// (the minimum over trees 1..L-1) instead of L.
+bool implicit_s(const QueryPlan& p, bool dumps) { return p.dense && !p.leaf && !p.fixed && !dumps; }
+
+size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d, bool dumps = false) {
+    const size_t nb = implicit_s(p, dumps) ? 1 : (size_t)L;
+    size_t b = (size_t)cap * (4 + 4 + 4 + 4 * nb + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
 }
@@ -1024,7 +1030,8 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
                           float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
     // candidate rows start 16-byte aligned (vector loads in the selection)
     const int64_t cap = round4((force_all_candidates || plan.fixed) ? ix->n : plan.cap);
-    const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d);
+    const bool dumps = dbg.cand_ids || dbg.cand_counts || dbg.first_tree;
+    const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d, dumps);
     int64_t nqc = (int64_t)(arena.bytes / pq);
     if (nqc < 1) {
         if (arena.p)
@@ -1050,10 +1057,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.E = ix->E.as<float>(); a.codes = ix->codes.as<uint8_t>(); a.X = ix->X.as<float>(); a.Xbf = ix->Xbf.as<uint16_t>();
     a.Q = Q; a.Qp = Qp; a.G = plan.G; a.gcodes = ix->gcodes.as<uint8_t>(); a.guess_rank = plan.rank;
     a.leaf = plan.leaf ? 1 : 0;
-    // the dense point path leaves S implicit in the candidate list unless the
-    // caller asked for the candidate dumps
-    const bool dumps = dbg.cand_ids || dbg.cand_counts || dbg.first_tree;
-    a.compact_s = (plan.dense && !plan.leaf && !plan.fixed && !dumps) ? 0 : 1;
+    a.compact_s = implicit_s(plan, dumps) ? 0 : 1;
     a.gleaf = ix->gleaf.as<int32_t>();
     a.lt.leaf_of = ix->leaf_of.as<int32_t>();
     a.lt.perm = ix->perm.as<int32_t>();
@@ -1079,7 +1083,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
     a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_f8 = reinterpret_cast<uint8_t*>(take((size_t)nqc * cap));
-    a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * ix->L));
+    a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * (a.compact_s ? ix->L : 1)));
     a.ws = reinterpret_cast<uint64_t*>(take((size_t)nqc * cap * 8));
     if (plan.dense) {
         a.W = (ix->n + 63) / 64;

@@ -94,7 +94,7 @@ struct QueryArgs {
     float* cand_m = nullptr;         // m^2 = min over trees of the bounds
     int32_t* cand_ft = nullptr;      // first admitting tree of each member of S
     uint8_t* cand_f8 = nullptr;      // first admitting tree of each candidate (implicit S)
-    float* cand_lb = nullptr;
+    float* cand_lb = nullptr;        // L bounds per candidate; with an implicit S one: min over trees 1..L-1
     int32_t* status = nullptr;
     uint32_t* s_count = nullptr;
     float* thr = nullptr;

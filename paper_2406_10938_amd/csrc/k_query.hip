@@ -65,11 +65,12 @@ __device__ __forceinline__ void load_cell(const uint8_t* __restrict__ codes, int
     }
 }
 
-// LB_i^2 = sum_j (q_j - clamp(q_j, lo_j, hi_j))^2, j ascending.
+// LB_i^2 = sum_j (q_j - clamp(q_j, lo_j, hi_j))^2, j ascending.  Returns
+// m^2 = min_i LB_i^2; pm = min over trees 1..L-1 (+inf when L = 1), the
+// running minimum that m^2 extends by the last tree.
 template <int L, int K>
 __device__ __forceinline__ float cell_lbs(const float* __restrict__ qp, const float (&lo)[L * K],
-                                          const float (&hi)[L * K], float (&lb)[L]) {
-    float m = INFINITY;
+                                          const float (&hi)[L * K], float (&lb)[L], float& pm) {
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         float acc = 0.0f;
@@ -82,9 +83,19 @@ __device__ __forceinline__ float cell_lbs(const float* __restrict__ qp, const fl
             acc = fmaf(dd, dd, acc);
         }
         lb[i] = acc;
-        m = fminf(m, acc);
     }
-    return m;
+    float run = lb[0];
+#pragma unroll
+    for (int i = 1; i < L - 1; ++i) run = fminf(run, lb[i]);
+    pm = L > 1 ? run : INFINITY;
+    return L > 1 ? fminf(run, lb[L - 1]) : lb[0];
+}
+
+template <int L, int K>
+__device__ __forceinline__ float cell_lbs(const float* __restrict__ qp, const float (&lo)[L * K],
+                                          const float (&hi)[L * K], float (&lb)[L]) {
+    float pm;
+    return cell_lbs<L, K>(qp, lo, hi, lb, pm);
 }
 
 // Leaf granularity: the bounds of point o in every tree are those of its
@@ -452,8 +463,10 @@ __global__ __launch_bounds__(256) void guess_select_kernel(const float* __restri
     if (threadIdx.x == 0) gthr[blockIdx.x] = g;
 }
 
-// Candidates are written as id and the L per-tree bounds (AoS, L floats per
-// slot).  Inside a group of kGroup queries each wave appends its hits to its
+// Candidates are written as id, key and either the L per-tree bounds (AoS, L
+// floats per slot) or, when S stays implicit (PREFIX), one float per slot:
+// the minimum over trees 1..L-1, which with the key decides the stop trees
+// L-1 and L (a smaller stop tree is settled by stop_exact_kernel).  Inside a group of kGroup queries each wave appends its hits to its
 // own LDS list (offsets from ballot and popcount, no atomics); at the end of
 // the group one atomic per query reserves the block's slots and the lists are
 // copied out contiguously.
@@ -473,11 +486,11 @@ __device__ __forceinline__ void store_lbs(float* __restrict__ dst, const float (
     }
 }
 
-template <int L>
+template <int NB>
 struct FilterShared {
     int32_t ids[4][kGroup][64];
     float key[4][kGroup][64];
-    float lbs[4][kGroup][64][L];
+    float lbs[4][kGroup][64][NB];
     uint64_t mask[4][kGroup];   // each wave's hit ballot per query of the group
     uint32_t wc[4][kGroup];
     uint32_t gb[kGroup];
@@ -501,7 +514,7 @@ __device__ __forceinline__ float entry_step(const float (&lb)[L], const float* _
     return e;
 }
 
-template <int L, int K, bool FIXED, bool LEAF>
+template <int L, int K, bool FIXED, bool LEAF, bool PREFIX>
 __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict__ E, int N_r,
                                                      const uint8_t* __restrict__ codes, int64_t n,
                                                      const float* __restrict__ Qp, int64_t q0, int nqc,
@@ -512,7 +525,8 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
                                                      int64_t W, const float* __restrict__ rad2, int T, LeafTabs lt)
 {
     constexpr int LK = L * K;
-    __shared__ FilterShared<L> sh;
+    constexpr int NB = PREFIX ? 1 : L;
+    __shared__ FilterShared<NB> sh;
     __shared__ float srad[64];
     if (FIXED) {
         if (threadIdx.x < T) srad[threadIdx.x] = rad2[threadIdx.x];
@@ -541,8 +555,8 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
         for (int g = 0; g < ng; ++g) {
             const int t = tg + g;
             const float* qp = Qp + (q0 + t) * LK;
-            float lb[L];
-            float m = cell_lbs<L, K>(qp, lo, hi, lb);
+            float lb[L], pm;
+            float m = cell_lbs<L, K>(qp, lo, hi, lb, pm);
             if (FIXED) m = entry_step<L>(lb, srad, T);   // the key is the entry step
             const float gt = gthr[t];
             const bool hit = valid & (m <= gt);
@@ -551,8 +565,12 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
                 const int pos = dl_rank_below(mask);
                 sh.ids[wave][g][pos] = (int32_t)o;
                 sh.key[wave][g][pos] = m;
+                if (PREFIX) {
+                    sh.lbs[wave][g][pos][0] = pm;
+                } else {
 #pragma unroll
-                for (int i = 0; i < L; ++i) sh.lbs[wave][g][pos][i] = lb[i];
+                    for (int i = 0; i < NB; ++i) sh.lbs[wave][g][pos][i] = lb[i];
+                }
             }
             if (lane == 0) sh.mask[wave][g] = mask;   // counts and bitmap words follow from it at the flush
         }
@@ -590,11 +608,15 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
                 if (idx < cap) {
                     const int64_t at = (int64_t)(tg + g) * cap + idx;
                     cand_id[at] = sh.ids[w][g][pos];
-                    float lb[L];
-#pragma unroll
-                    for (int i = 0; i < L; ++i) lb[i] = sh.lbs[w][g][pos][i];
                     cand_m[at] = sh.key[w][g][pos];
-                    store_lbs<L>(cand_lb + at * L, lb);
+                    if (PREFIX) {
+                        cand_lb[at] = sh.lbs[w][g][pos][0];
+                    } else {
+                        float lb[L];
+#pragma unroll
+                        for (int i = 0; i < L; ++i) lb[i] = sh.lbs[w][g][pos][i];
+                        store_lbs<L>(cand_lb + at * L, lb);
+                    }
                 }
             }
         }
@@ -720,6 +742,64 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     // every candidate has m^2 <= its query's guess threshold
     const float thr = __uint_as_float(select_rank_u32_upto_v(reinterpret_cast<const uint32_t*>(mt), (int64_t)cnt,
                                                              N_S, __float_as_uint(gthr[t]), sh));
+    if (!LEAF && !compact) {
+        // S stays implicit: the candidates with 1 <= f(o) <= istop (consumers
+        // filter the list; s_count is the list's length).  Entry s holds m^2
+        // and pm = min over trees 1..L-1, so f(o) <= L-1 iff pm <= thr and
+        // f(o) <= L iff m^2 <= thr: the byte kept per entry is 0, L-1 or L,
+        // which decides membership for the stop trees L-1 and L.  When
+        // |U_{L-1}| >= N_S and L >= 3 a smaller stop tree is possible: the
+        // stop is left at -1 for stop_exact_kernel.
+        const float* pmt = cand_lb + (int64_t)t * cap;
+        uint8_t* ft8 = cand_f8 + (int64_t)t * cap;
+        uint32_t u = 0;   // |U_{L-1}|
+        for (int64_t s0 = 4 * (int64_t)threadIdx.x; s0 < (int64_t)cnt; s0 += 1024) {
+            const bool whole = s0 + 3 < (int64_t)cnt;
+            float mv[4], pv[4];
+            if (whole) {   // rows start 16-byte aligned
+                const float4 a4 = *reinterpret_cast<const float4*>(mt + s0);
+                const float4 b4 = *reinterpret_cast<const float4*>(pmt + s0);
+                mv[0] = a4.x; mv[1] = a4.y; mv[2] = a4.z; mv[3] = a4.w;
+                pv[0] = b4.x; pv[1] = b4.y; pv[2] = b4.z; pv[3] = b4.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool in = s0 + j < (int64_t)cnt;
+                    mv[j] = in ? mt[s0 + j] : INFINITY;
+                    pv[j] = in ? pmt[s0 + j] : INFINITY;
+                }
+            }
+            uint32_t packed = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool early = L > 1 && pv[j] <= thr;
+                u += early ? 1u : 0u;
+                const uint32_t f = mv[j] <= thr ? (early ? (uint32_t)(L - 1) : (uint32_t)L) : 0u;
+                packed |= f << (8 * j);
+            }
+            if (whole) {
+                *reinterpret_cast<uint32_t*>(ft8 + s0) = packed;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (s0 + j < (int64_t)cnt) ft8[s0 + j] = (uint8_t)(packed >> (8 * j));
+            }
+        }
+        u = dl_wave_sum(u);
+        if (threadIdx.x == 0) tc[0] = 0;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) atomicAdd(&tc[0], u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int istop = L;
+            if (L > 1 && (uint64_t)tc[0] >= N_S) istop = (L == 2) ? 1 : -1;
+            status[t] = 0;
+            s_count[t] = (uint32_t)cnt;
+            thr_out[t] = thr;
+            stop_out[t] = istop;
+        }
+        return;
+    }
     // first admitting tree f(o) = min{i : LB_i^2 <= thr} (0: none) of every
     // entry, kept in cand_ft; |U_i| for i = 1..L counts the entries with
     // 0 < f(o) <= i
@@ -739,30 +819,19 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
         for (int i = 0; i < L; ++i) loc[i] += (ft != 0 && ft <= i + 1) ? 1u : 0u;
         return ft;
     };
-    // f(o) as int32 for the compaction, else (an implicit S, filtered by its
-    // readers) as one byte
-    const bool keep_ft = LEAF || compact;
-    uint8_t* ft8 = cand_f8 + (int64_t)t * cap;
     int64_t s = threadIdx.x;
     for (; s + 256 < (int64_t)cnt; s += 512) {   // two rows in flight per thread
         float la[L], lc[L];
         load_lbs<L>(lbt + s * L, la);
         load_lbs<L>(lbt + (s + 256) * L, lc);
         const int fa = first_tree(la), fc = first_tree(lc);
-        if (keep_ft) {
-            ftree[s] = fa;
-            ftree[s + 256] = fc;
-        } else {
-            ft8[s] = (uint8_t)fa;
-            ft8[s + 256] = (uint8_t)fc;
-        }
+        ftree[s] = fa;
+        ftree[s + 256] = fc;
     }
     for (; s < (int64_t)cnt; s += 256) {
         float la[L];
         load_lbs<L>(lbt + s * L, la);
-        const int fa = first_tree(la);
-        if (keep_ft) ftree[s] = fa;
-        else ft8[s] = (uint8_t)fa;
+        ftree[s] = first_tree(la);
     }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -773,17 +842,6 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     int istop = L;
     for (int i = 0; i < L; ++i)
         if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
-    if (!LEAF && !compact) {
-        // S stays implicit: the candidates with 1 <= f(o) <= istop (consumers
-        // filter the list; s_count is the list's length)
-        if (threadIdx.x == 0) {
-            status[t] = 0;
-            s_count[t] = (uint32_t)cnt;
-            thr_out[t] = thr;
-            stop_out[t] = istop;
-        }
-        return;
-    }
     // Leaf granularity: the stop tree's admitted leaves are taken in order of
     // (bound, smallest point id of the leaf) until |S| reaches N_S, so of the
     // entries first admitted by tree istop those up to the key of the
@@ -872,6 +930,61 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
         s_count[t] = out;
         thr_out[t] = thr;
         stop_out[t] = istop;
+    }
+}
+
+// The stop tree of a query whose first L-1 trees already admit N_S entries
+// at thr (stop left at -1 by the selection): the L bounds of each entry are
+// recomputed by the filter's own code from its codes and the query's
+// projection (so bit for bit the values the filter had), f(o) is written
+// exactly, and the stop tree is the smallest i with |U_i| >= N_S.  Every other
+// query's block returns at once.
+template <int L, int K>
+__global__ __launch_bounds__(256) void stop_exact_kernel(const float* __restrict__ E, int N_r,
+                                                         const uint8_t* __restrict__ codes, int64_t n,
+                                                         const float* __restrict__ Qp, int64_t q0,
+                                                         const uint32_t* __restrict__ counts, int64_t cap,
+                                                         uint64_t N_S, const int32_t* __restrict__ cand_id,
+                                                         const float* __restrict__ thr,
+                                                         const int32_t* __restrict__ status,
+                                                         int32_t* __restrict__ stop, uint8_t* __restrict__ cand_f8)
+{
+    __shared__ uint32_t tc[L];
+    const int t = blockIdx.x;
+    if (status[t] != 0 || stop[t] >= 0) return;
+    const int64_t cnt = counts[t];
+    const float th = thr[t];
+    const float* qp = Qp + (q0 + t) * (int64_t)(L * K);
+    const int32_t* ids = cand_id + (int64_t)t * cap;
+    uint8_t* ft8 = cand_f8 + (int64_t)t * cap;
+    if (threadIdx.x < L) tc[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t loc[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) loc[i] = 0;
+    for (int64_t s = threadIdx.x; s < cnt; s += 256) {
+        float lo[L * K], hi[L * K], lb[L];
+        load_cell<L, K>(codes, n, ids[s], E, N_r + 1, lo, hi);
+        (void)cell_lbs<L, K>(qp, lo, hi, lb);
+        int ft = 0;
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i)
+            if (lb[i] <= th) ft = i + 1;
+#pragma unroll
+        for (int i = 0; i < L; ++i) loc[i] += (ft != 0 && ft <= i + 1) ? 1u : 0u;
+        ft8[s] = (uint8_t)ft;
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const uint32_t v = dl_wave_sum(loc[i]);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&tc[i], v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int istop = L;
+        for (int i = 0; i < L; ++i)
+            if ((uint64_t)tc[i] >= N_S) { istop = i + 1; break; }
+        stop[t] = istop;
     }
 }
 
@@ -1736,7 +1849,7 @@ hipError_t launch_guess_lk(const QueryArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int L, int K, bool FIXED, bool LEAF>
+template <int L, int K, bool FIXED, bool LEAF, bool PREFIX>
 hipError_t launch_filter_lkf(const QueryArgs& a, hipStream_t st) {
     const int64_t pb = (a.n + 255) / 256;
     // about 64 queries per workgroup (measured best at n = 10^6, d = 128:
@@ -1745,7 +1858,7 @@ hipError_t launch_filter_lkf(const QueryArgs& a, hipStream_t st) {
     while (pb * ny < 4096 && ny < a.nqc) ny *= 2;
     if (ny > a.nqc) ny = a.nqc;
     const int qpb = (a.nqc + ny - 1) / ny;
-    hipLaunchKernelGGL((filter_kernel<L, K, FIXED, LEAF>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
+    hipLaunchKernelGGL((filter_kernel<L, K, FIXED, LEAF, PREFIX>), dim3((unsigned)pb, (unsigned)ny), dim3(256), 0, st, a.E,
                        a.N_r, a.codes, a.n, a.Qp, a.q0, a.nqc, qpb, a.gthr, a.counts, a.cap, a.cand_id, a.cand_m,
                        a.cand_lb, a.bm, a.W, a.rad2, a.T, a.lt);
     return hipGetLastError();
@@ -1753,9 +1866,10 @@ hipError_t launch_filter_lkf(const QueryArgs& a, hipStream_t st) {
 
 template <int L, int K>
 hipError_t launch_filter_lk(const QueryArgs& a, hipStream_t st) {
-    if (a.fixed) return launch_filter_lkf<L, K, true, false>(a, st);
-    if (a.leaf) return launch_filter_lkf<L, K, false, true>(a, st);
-    return launch_filter_lkf<L, K, false, false>(a, st);
+    if (a.fixed) return launch_filter_lkf<L, K, true, false, false>(a, st);
+    if (a.leaf) return launch_filter_lkf<L, K, false, true, false>(a, st);
+    if (!a.compact_s) return launch_filter_lkf<L, K, false, false, true>(a, st);
+    return launch_filter_lkf<L, K, false, false, false>(a, st);
 }
 
 
@@ -1796,6 +1910,15 @@ hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
                        a.n, a.gthr, a.compact_s, a.cand_f8);
     return hipGetLastError();
 }
+
+template <int L, int K>
+hipError_t launch_stop_exact_lk(const QueryArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((stop_exact_kernel<L, K>), dim3(a.nqc), dim3(256), 0, st, a.E, a.N_r, a.codes, a.n, a.Qp,
+                       a.q0, a.counts, a.cap, a.N_S, a.cand_id, a.thr, a.status, a.stop, a.cand_f8);
+    return hipGetLastError();
+}
+
+hipError_t launch_stop_exact(const QueryArgs& a, hipStream_t st) { DL_LK_DISPATCH(launch_stop_exact_lk) }
 
 }  // namespace
 
@@ -1877,13 +2000,18 @@ hipError_t dl_launch_survivor_members(const QueryArgs& a, hipStream_t st) {
 }
 
 hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
+    hipError_t e = hipErrorInvalidValue;
     switch (a.L) {
-        case 1: return launch_select_l<1>(a, st);
-        case 2: return launch_select_l<2>(a, st);
-        case 4: return launch_select_l<4>(a, st);
-        case 8: return launch_select_l<8>(a, st);
-        default: return hipErrorInvalidValue;
+        case 1: e = launch_select_l<1>(a, st); break;
+        case 2: e = launch_select_l<2>(a, st); break;
+        case 4: e = launch_select_l<4>(a, st); break;
+        case 8: e = launch_select_l<8>(a, st); break;
+        default: break;
     }
+    if (e != hipSuccess) return e;
+    // an implicit S with L >= 3 may leave stop trees below L-1 to the exact pass
+    if (!a.fixed && !a.leaf && !a.compact_s && a.L >= 3) return launch_stop_exact(a, st);
+    return hipSuccess;
 }
 
 template <bool AL>

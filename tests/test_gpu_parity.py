@@ -269,6 +269,39 @@ def test_argument_errors(dl):
 # masked dense MFMA verification and the BF16 + rerank form
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("verify", ["dense", "dense_bf16"])
+def test_small_stop_tree_on_the_implicit_dense_path(dl, verify):
+    """8,001 identical points (more than N_S = 7,010) and queries on them: the
+    first tree alone admits the whole cluster at threshold 0, so the stop tree
+    is 1, below the L-1 that the dense path's selection settles from the
+    stored prefix minimum; its exact pass decides it.  The dense path (S kept
+    implicit) returns the gathered path's ids and distances bit for bit, the
+    stop trees equal the oracle's, and the results are the oracle's."""
+    say(f"small stop tree on the dense path n=70000 d=64 cluster=8001 verify={verify}")
+    c = U.case(n=70_000, d=64, N_r=256, frac=0.01, kind="mixture", nq=40, seed=41)
+    X, Q = c["X"].copy(), c["Q"].copy()
+    X[1000:9000] = X[500]
+    Q[0] = X[500]
+    Q[7] = X[500]
+    Q[13] = X[500]
+    k, beta = 10, 0.1
+    idx = dl.build_index(X, 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=verify == "dense_bf16")
+    Qt = t(Q)
+    g_ids, g_d = idx.query(Qt, k, 1.5, beta, verify="gather")
+    d_ids, d_d = idx.query(Qt, k, 1.5, beta, verify=verify)
+    assert np.array_equal(g_ids.cpu().numpy(), d_ids.cpu().numpy())
+    assert np.array_equal(g_d.cpu().numpy(), d_d.cpu().numpy())
+    ex = idx.export()
+    Qp = idx.project(Qt).cpu().numpy()
+    r = idx.query_debug(Qt, k, 1.5, beta, Qp=t(Qp), verify="dense")
+    for qi in (0, 7, 13, 1, 2):
+        ref = U.oracle_query(X, Q[qi], Qp[qi], ex["codes"], ex["B"], 4, 16, k, beta)
+        if qi in (0, 7, 13):
+            assert ref.stop_tree == 1
+        assert int(r["stop_tree"][qi]) == ref.stop_tree
+        U.compare_result(ref.ids, ref.dists, X, Q[qi], d_ids[qi].cpu().numpy(), d_d[qi].cpu().numpy(), ref.S, k)
+
+
 @pytest.mark.parametrize("n,d,kind,k,nq", [(70_001, 128, "integer", 10, 150), (66_000, 37, "mixture", 20, 130),
                                            (80_000, 96, "mixture", 100, 64), (65_600, 200, "mixture", 1, 257),
                                            (65_857, 300, "mixture", 10, 140), (65_536, 962, "integer", 5, 70)])
