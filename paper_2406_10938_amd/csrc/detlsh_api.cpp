@@ -992,12 +992,12 @@ struct Debug {
 int64_t round4(int64_t v) { return (v + 3) & ~(int64_t)3; }
 
 // The dense point path leaves S implicit in the candidate list (unless the
-// caller asked for the candidate dumps); its candidates then carry one bound
-// (the minimum over trees 1..L-1) instead of L.
+// caller asked for the candidate dumps); its candidates then carry running
+// minima of the bounds (dl_prefix_mins) instead of the L bounds.
 bool implicit_s(const QueryPlan& p, bool dumps) { return p.dense && !p.leaf && !p.fixed && !dumps; }
 
 size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d, bool dumps = false) {
-    const size_t nb = implicit_s(p, dumps) ? 1 : (size_t)L;
+    const size_t nb = (size_t)(implicit_s(p, dumps) ? dl_prefix_mins(L) : L);
     size_t b = (size_t)cap * (4 + 4 + 4 + 4 * nb + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
@@ -1083,7 +1083,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.cand_m = reinterpret_cast<float*>(take((size_t)nqc * cap * 4));
     a.cand_ft = reinterpret_cast<int32_t*>(take((size_t)nqc * cap * 4));
     a.cand_f8 = reinterpret_cast<uint8_t*>(take((size_t)nqc * cap));
-    a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * (a.compact_s ? ix->L : 1)));
+    a.cand_lb = reinterpret_cast<float*>(take((size_t)nqc * cap * 4 * (a.compact_s ? ix->L : dl_prefix_mins(ix->L))));
     a.ws = reinterpret_cast<uint64_t*>(take((size_t)nqc * cap * 8));
     if (plan.dense) {
         a.W = (ix->n + 63) / 64;

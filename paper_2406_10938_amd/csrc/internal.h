@@ -65,6 +65,10 @@ struct LeafTabs {
     const uint8_t* hi[8] = {};
 };
 
+// Running minima stored per candidate when S stays implicit: the minimum of
+// the per-tree bounds over trees 1..L-2 (when L >= 3) and over trees 1..L-1.
+constexpr int dl_prefix_mins(int L) { return L >= 3 ? 2 : 1; }
+
 struct QueryArgs {
     int L = 0, K = 0, N_r = 0, d = 0;
     int64_t n = 0;
@@ -94,7 +98,7 @@ struct QueryArgs {
     float* cand_m = nullptr;         // m^2 = min over trees of the bounds
     int32_t* cand_ft = nullptr;      // first admitting tree of each member of S
     uint8_t* cand_f8 = nullptr;      // first admitting tree of each candidate (implicit S)
-    float* cand_lb = nullptr;        // L bounds per candidate; with an implicit S one: min over trees 1..L-1
+    float* cand_lb = nullptr;        // L bounds per candidate; with an implicit S dl_prefix_mins(L) running minima
     int32_t* status = nullptr;
     uint32_t* s_count = nullptr;
     float* thr = nullptr;

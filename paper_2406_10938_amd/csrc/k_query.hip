@@ -464,13 +464,23 @@ __global__ __launch_bounds__(256) void guess_select_kernel(const float* __restri
 }
 
 // Candidates are written as id, key and either the L per-tree bounds (AoS, L
-// floats per slot) or, when S stays implicit (PREFIX), one float per slot:
-// the minimum over trees 1..L-1, which with the key decides the stop trees
-// L-1 and L (a smaller stop tree is settled by stop_exact_kernel).  Inside a group of kGroup queries each wave appends its hits to its
+// floats per slot) or, when S stays implicit (PREFIX), the running minima of
+// the bounds over trees 1..L-2 and 1..L-1 (dl_prefix_mins(L) floats per slot),
+// which with the key decide the stop trees L-2..L (a smaller stop tree is
+// settled by stop_exact_kernel).  Inside a group of kGroup queries each wave appends its hits to its
 // own LDS list (offsets from ballot and popcount, no atomics); at the end of
 // the group one atomic per query reserves the block's slots and the lists are
 // copied out contiguously.
 constexpr int kGroup = 8;
+
+// min over trees 1..J of the per-tree bounds (J >= 1)
+template <int J, int L>
+__device__ __forceinline__ float prefix_min(const float (&lb)[L]) {
+    float r = lb[0];
+#pragma unroll
+    for (int i = 1; i < J; ++i) r = fminf(r, lb[i]);
+    return r;
+}
 
 template <int L>
 __device__ __forceinline__ void store_lbs(float* __restrict__ dst, const float (&lb)[L]) {
@@ -525,7 +535,7 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
                                                      int64_t W, const float* __restrict__ rad2, int T, LeafTabs lt)
 {
     constexpr int LK = L * K;
-    constexpr int NB = PREFIX ? 1 : L;
+    constexpr int NB = PREFIX ? dl_prefix_mins(L) : L;
     __shared__ FilterShared<NB> sh;
     __shared__ float srad[64];
     if (FIXED) {
@@ -549,24 +559,43 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
     for (int e = 0; e < LK; ++e) asm volatile("" ::"v"(lo[e]), "v"(hi[e]));
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
+    // the ballot of a bare compare is the compare's own lane mask; the lanes
+    // past n are masked once, outside the query loop
+    const uint64_t vmask = dl_ballot(valid);
     for (int tg = ta; tg < tb; tg += kGroup) {
         const int ng = __builtin_amdgcn_readfirstlane((tb - tg < kGroup) ? tb - tg : kGroup);
 #pragma unroll 1
         for (int g = 0; g < ng; ++g) {
             const int t = tg + g;
             const float* qp = Qp + (q0 + t) * LK;
-            float lb[L], pm;
-            float m = cell_lbs<L, K>(qp, lo, hi, lb, pm);
+            float lb[L];
+            float m = cell_lbs<L, K>(qp, lo, hi, lb);
+            float p2 = 0.f, p1 = 0.f;
+            if constexpr (PREFIX && L >= 3) {
+                // the same minimum as a running chain over the trees, whose
+                // first links are the stored minima
+                p2 = prefix_min<L - 2>(lb);
+                p1 = fminf(p2, lb[L - 2]);
+                m = fminf(p1, lb[L - 1]);
+            }
             if (FIXED) m = entry_step<L>(lb, srad, T);   // the key is the entry step
             const float gt = gthr[t];
-            const bool hit = valid & (m <= gt);
-            const uint64_t mask = dl_ballot(hit);
+            const bool below = m <= gt;
+            const bool hit = valid & below;
+            const uint64_t mask = dl_ballot(below) & vmask;
             if (hit) {
                 const int pos = dl_rank_below(mask);
                 sh.ids[wave][g][pos] = (int32_t)o;
                 sh.key[wave][g][pos] = m;
                 if (PREFIX) {
-                    sh.lbs[wave][g][pos][0] = pm;
+                    if constexpr (L >= 3) {
+                        sh.lbs[wave][g][pos][0] = p2;
+                        sh.lbs[wave][g][pos][1] = p1;
+                    } else if constexpr (L == 2) {
+                        sh.lbs[wave][g][pos][0] = lb[0];
+                    } else {
+                        sh.lbs[wave][g][pos][0] = INFINITY;   // no tree before the last
+                    }
                 } else {
 #pragma unroll
                     for (int i = 0; i < NB; ++i) sh.lbs[wave][g][pos][i] = lb[i];
@@ -610,7 +639,11 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
                     cand_id[at] = sh.ids[w][g][pos];
                     cand_m[at] = sh.key[w][g][pos];
                     if (PREFIX) {
-                        cand_lb[at] = sh.lbs[w][g][pos][0];
+                        if constexpr (L >= 3)
+                            reinterpret_cast<float2*>(cand_lb)[at] =
+                                make_float2(sh.lbs[w][g][pos][0], sh.lbs[w][g][pos][1]);
+                        else
+                            cand_lb[at] = sh.lbs[w][g][pos][0];
                     } else {
                         float lb[L];
 #pragma unroll
@@ -745,36 +778,51 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     if (!LEAF && !compact) {
         // S stays implicit: the candidates with 1 <= f(o) <= istop (consumers
         // filter the list; s_count is the list's length).  Entry s holds m^2
-        // and pm = min over trees 1..L-1, so f(o) <= L-1 iff pm <= thr and
-        // f(o) <= L iff m^2 <= thr: the byte kept per entry is 0, L-1 or L,
-        // which decides membership for the stop trees L-1 and L.  When
-        // |U_{L-1}| >= N_S and L >= 3 a smaller stop tree is possible: the
+        // and the running minima p2 (trees 1..L-2, when L >= 3) and p1 (trees
+        // 1..L-1), so f(o) <= L-2 iff p2 <= thr, f(o) <= L-1 iff p1 <= thr and
+        // f(o) <= L iff m^2 <= thr: the byte kept per entry is 0, L-2, L-1 or
+        // L, which decides membership for the stop trees L-2..L.  When
+        // |U_{L-2}| >= N_S and L >= 4 a smaller stop tree is possible: the
         // stop is left at -1 for stop_exact_kernel.
-        const float* pmt = cand_lb + (int64_t)t * cap;
+        constexpr int NP = dl_prefix_mins(L);
+        const float* pmt = cand_lb + (int64_t)t * cap * NP;
         uint8_t* ft8 = cand_f8 + (int64_t)t * cap;
-        uint32_t u = 0;   // |U_{L-1}|
+        uint32_t u1 = 0, u2 = 0;   // |U_{L-1}|, |U_{L-2}|
         for (int64_t s0 = 4 * (int64_t)threadIdx.x; s0 < (int64_t)cnt; s0 += 1024) {
             const bool whole = s0 + 3 < (int64_t)cnt;
-            float mv[4], pv[4];
+            float mv[4], p1[4], p2[4];
             if (whole) {   // rows start 16-byte aligned
                 const float4 a4 = *reinterpret_cast<const float4*>(mt + s0);
-                const float4 b4 = *reinterpret_cast<const float4*>(pmt + s0);
                 mv[0] = a4.x; mv[1] = a4.y; mv[2] = a4.z; mv[3] = a4.w;
-                pv[0] = b4.x; pv[1] = b4.y; pv[2] = b4.z; pv[3] = b4.w;
+                if constexpr (NP == 2) {
+                    const float4 b0 = *reinterpret_cast<const float4*>(pmt + 2 * s0);
+                    const float4 b1 = *reinterpret_cast<const float4*>(pmt + 2 * s0 + 4);
+                    p2[0] = b0.x; p1[0] = b0.y; p2[1] = b0.z; p1[1] = b0.w;
+                    p2[2] = b1.x; p1[2] = b1.y; p2[3] = b1.z; p1[3] = b1.w;
+                } else {
+                    const float4 b0 = *reinterpret_cast<const float4*>(pmt + s0);
+                    p1[0] = b0.x; p1[1] = b0.y; p1[2] = b0.z; p1[3] = b0.w;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) p2[j] = INFINITY;
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const bool in = s0 + j < (int64_t)cnt;
                     mv[j] = in ? mt[s0 + j] : INFINITY;
-                    pv[j] = in ? pmt[s0 + j] : INFINITY;
+                    p1[j] = in ? pmt[NP * (s0 + j) + NP - 1] : INFINITY;
+                    p2[j] = (in && NP == 2) ? pmt[NP * (s0 + j)] : INFINITY;
                 }
             }
             uint32_t packed = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const bool early = L > 1 && pv[j] <= thr;
-                u += early ? 1u : 0u;
-                const uint32_t f = mv[j] <= thr ? (early ? (uint32_t)(L - 1) : (uint32_t)L) : 0u;
+                const bool in1 = L >= 2 && p1[j] <= thr;
+                const bool in2 = L >= 3 && p2[j] <= thr;
+                u1 += in1 ? 1u : 0u;
+                u2 += in2 ? 1u : 0u;
+                const uint32_t f = mv[j] <= thr ? (in2 ? (uint32_t)(L - 2) : in1 ? (uint32_t)(L - 1) : (uint32_t)L)
+                                                : 0u;
                 packed |= f << (8 * j);
             }
             if (whole) {
@@ -785,14 +833,21 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                     if (s0 + j < (int64_t)cnt) ft8[s0 + j] = (uint8_t)(packed >> (8 * j));
             }
         }
-        u = dl_wave_sum(u);
-        if (threadIdx.x == 0) tc[0] = 0;
+        u1 = dl_wave_sum(u1);
+        u2 = dl_wave_sum(u2);
+        if (threadIdx.x < 2) tc[threadIdx.x] = 0;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0) atomicAdd(&tc[0], u);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&tc[0], u1);
+            atomicAdd(&tc[1], u2);
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             int istop = L;
-            if (L > 1 && (uint64_t)tc[0] >= N_S) istop = (L == 2) ? 1 : -1;
+            if (L >= 2 && (uint64_t)tc[0] >= N_S) {
+                istop = L - 1;
+                if (L >= 3 && (uint64_t)tc[1] >= N_S) istop = (L == 3) ? 1 : -1;
+            }
             status[t] = 0;
             s_count[t] = (uint32_t)cnt;
             thr_out[t] = thr;
@@ -933,7 +988,7 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
     }
 }
 
-// The stop tree of a query whose first L-1 trees already admit N_S entries
+// The stop tree of a query whose first L-2 trees already admit N_S entries
 // at thr (stop left at -1 by the selection): the L bounds of each entry are
 // recomputed by the filter's own code from its codes and the query's
 // projection (so bit for bit the values the filter had), f(o) is written
@@ -2009,8 +2064,8 @@ hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
         default: break;
     }
     if (e != hipSuccess) return e;
-    // an implicit S with L >= 3 may leave stop trees below L-1 to the exact pass
-    if (!a.fixed && !a.leaf && !a.compact_s && a.L >= 3) return launch_stop_exact(a, st);
+    // an implicit S with L >= 4 may leave stop trees below L-2 to the exact pass
+    if (!a.fixed && !a.leaf && !a.compact_s && a.L >= 4) return launch_stop_exact(a, st);
     return hipSuccess;
 }
 
