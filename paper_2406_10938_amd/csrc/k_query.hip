@@ -2112,9 +2112,10 @@ hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t 
 hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     const int64_t ntiles = (a.n + kDP - 1) / kDP;
     const int gx = (a.nqc + kDQ - 1) / kDQ;
-    // about 8 workgroups per CU in total; the split count is a multiple of 8 (one per XCD)
-    int64_t gy = (2048 + gx - 1) / gx;
-    gy = ((gy + 7) / 8) * 8;
+    // at most 8 workgroups per CU in total (four rounds of two per CU, no
+    // partial fifth round); the split count is a multiple of 8 (one per XCD)
+    int64_t gy = 2048 / gx;
+    gy = gy < 8 ? 8 : (gy / 8) * 8;
     if (gy > ((ntiles + 7) / 8) * 8) gy = ((ntiles + 7) / 8) * 8;
     const int64_t tps = (ntiles + gy - 1) / gy;
     const int64_t blocks = 8 * ((gy + 7) / 8) * gx;
