@@ -289,6 +289,7 @@ struct detlsh_index_s {
     std::vector<int64_t> sample_ids;
     std::vector<float> A_host;
     int64_t n_leaves[8] = {};
+    DevBuf leaf_mem[8];           // tree i's leaf table: start, lo, hi (pointers below)
     int32_t* leaf_start[8] = {};
     uint8_t* leaf_lo[8] = {};
     uint8_t* leaf_hi[8] = {};
@@ -302,12 +303,8 @@ struct detlsh_index_s {
         for (DevBuf* b : {&X, &Xbf, &A, &Abf, &B, &E, &codes, &perm, &scodes, &xn, &xn_bf, &gcodes, &leaf_of,
                           &gleaf})
             pool_give(*b, device);
+        for (DevBuf& b : leaf_mem) pool_give(b, device);
         if (have) (void)hipSetDevice(cur);
-        for (int i = 0; i < 8; ++i) {
-            if (leaf_start[i]) (void)hipFree(leaf_start[i]);
-            if (leaf_lo[i]) (void)hipFree(leaf_lo[i]);
-            if (leaf_hi[i]) (void)hipFree(leaf_hi[i]);
-        }
     }
     size_t bytes() const {
         size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
@@ -330,16 +327,18 @@ detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_
     return DETLSH_OK;
 }
 
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 // Shared tail of build and import: row norms, trees.
 detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     HCHECK(pool_alloc(ix->xn, (size_t)ix->n * 4, ix->device));
     if (keep_bf16) HCHECK(pool_alloc(ix->xn_bf, (size_t)ix->n * 4, ix->device));
     ix->emax = 0.f;
+    DevBuf xe, mx;   // cached buffers, handed back once the stream is drained
     if (keep_bf16) {
         // the largest BF16 rounding error ||o - bf16(o)|| of the rows (for the BF16 screen)
-        DevBuf xe, mx;
-        HCHECK(xe.alloc((size_t)ix->n * 4));
-        HCHECK(mx.alloc(4));
+        HCHECK(pool_alloc(xe, (size_t)ix->n * 4, ix->device));
+        HCHECK(pool_alloc(mx, 4, ix->device));
         HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), ix->xn_bf.as<float>(),
                                    xe.as<float>(), st));
         HCHECK(dl_launch_max_f32(xe.as<float>(), ix->n, mx.as<uint32_t>(), st));
@@ -358,15 +357,43 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     ix->G = (int32_t)std::min<int64_t>(ix->n, kGuessMax);
     HCHECK(pool_alloc(ix->gcodes, (size_t)ix->G * ix->LK, ix->device));
     HCHECK(dl_launch_pack_sample(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->G, ix->gcodes.as<uint8_t>(), st));
-    DevBuf tmp;   // reused by the trees in turn (each build ends with a synchronisation)
-    HCHECK(tmp.alloc(dl_tree_tmp_bytes(ix->n, ix->K)));
-    for (int i = 0; i < ix->L; ++i) {
+    // the L trees, phase by phase: two host waits in all (for the run and
+    // leaf counts that size the next phase's launches), each tree with a tmp
+    // of its own
+    const int L = ix->L;
+    const size_t tb = align256(dl_tree_tmp_bytes(ix->n, ix->K));
+    DevBuf tmp, tot;
+    HCHECK(pool_alloc(tmp, tb * (size_t)L, ix->device));
+    HCHECK(pool_alloc(tot, (size_t)8 * L, ix->device));
+    uint32_t* dtot = tot.as<uint32_t>();
+    uint32_t htot[16] = {};
+    auto tmp_of = [&](int i) { return static_cast<void*>(tmp.as<char>() + tb * (size_t)i); };
+    auto codes_of = [&](int i) { return ix->codes.as<uint8_t>() + (int64_t)i * ix->n * ix->K; };
+    auto perm_of = [&](int i) { return ix->perm.as<int32_t>() + (int64_t)i * ix->n; };
+    auto scodes_of = [&](int i) { return ix->scodes.as<uint8_t>() + (int64_t)i * ix->n * ix->K; };
+    {
         DlTimer tm(T_TREE, st);
-        HCHECK(dl_build_tree(ix->codes.as<uint8_t>() + (int64_t)i * ix->n * ix->K, ix->n, ix->K, ix->N_r,
-                             ix->max_leaf, ix->perm.as<int32_t>() + (int64_t)i * ix->n,
-                             ix->scodes.as<uint8_t>() + (int64_t)i * ix->n * ix->K, tmp.p, st, &ix->n_leaves[i],
-                             &ix->leaf_start[i], &ix->leaf_lo[i], &ix->leaf_hi[i]));
+        for (int i = 0; i < L; ++i)
+            HCHECK(dl_tree_runs(codes_of(i), ix->n, ix->K, ix->N_r, perm_of(i), scodes_of(i), tmp_of(i),
+                                dtot + 2 * i, st));
+        HCHECK(hipMemcpyAsync(htot, dtot, (size_t)8 * L, hipMemcpyDeviceToHost, st));
         HCHECK(hipStreamSynchronize(st));
+        for (int i = 0; i < L; ++i)
+            HCHECK(dl_tree_split(ix->n, ix->K, ix->N_r, ix->max_leaf, perm_of(i), scodes_of(i), tmp_of(i),
+                                 htot[2 * i], dtot + 2 * i, st));
+        HCHECK(hipMemcpyAsync(htot, dtot, (size_t)8 * L, hipMemcpyDeviceToHost, st));
+        HCHECK(hipStreamSynchronize(st));
+        for (int i = 0; i < L; ++i) {
+            const uint32_t nruns = htot[2 * i], nl = htot[2 * i + 1];
+            ix->n_leaves[i] = nl;
+            const size_t sb = align256((size_t)(nl + 1) * 4), kb = align256((size_t)nl * ix->K + 4);
+            HCHECK(pool_alloc(ix->leaf_mem[i], sb + 2 * kb, ix->device));
+            ix->leaf_start[i] = ix->leaf_mem[i].as<int32_t>();
+            ix->leaf_lo[i] = ix->leaf_mem[i].as<uint8_t>() + sb;
+            ix->leaf_hi[i] = ix->leaf_mem[i].as<uint8_t>() + sb + kb;
+            HCHECK(dl_tree_leaves(ix->n, ix->K, ix->N_r, scodes_of(i), tmp_of(i), nruns, nl, ix->leaf_start[i],
+                                  ix->leaf_lo[i], ix->leaf_hi[i], st));
+        }
     }
     // point -> leaf of every tree, and the leaves of the guess subset
     HCHECK(pool_alloc(ix->leaf_of, (size_t)ix->n * ix->L * 4, ix->device));
@@ -376,6 +403,7 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
                                  ix->n, ix->leaf_of.as<int32_t>() + (int64_t)i * ix->n, st));
     HCHECK(dl_launch_pack_sample_leaves(ix->leaf_of.as<int32_t>(), ix->n, ix->L, ix->G, ix->gleaf.as<int32_t>(), st));
     HCHECK(hipStreamSynchronize(st));
+    for (DevBuf* b : {&xe, &mx, &tmp, &tot}) pool_give(*b, ix->device);
     return DETLSH_OK;
 }
 
@@ -484,9 +512,9 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
     {
         DevBuf rows, Ps, tmp;
         std::vector<int32_t> r32(ix->sample_ids.begin(), ix->sample_ids.end());
-        HCHECK(rows.alloc((size_t)n_s * 4));
+        HCHECK(pool_alloc(rows, (size_t)n_s * 4, ix->device));
         HCHECK(hipMemcpyAsync(rows.p, r32.data(), (size_t)n_s * 4, hipMemcpyHostToDevice, st));
-        HCHECK(Ps.alloc((size_t)n_s * ix->LK * 4));
+        HCHECK(pool_alloc(Ps, (size_t)n_s * ix->LK * 4, ix->device));
         ProjectArgs pa;
         pa.X = ix->X.as<float>(); pa.Xbf = ix->Xbf.as<uint16_t>(); pa.rows = rows.as<int32_t>();
         pa.M = n_s; pa.d = d; pa.A = ix->A.as<float>(); pa.Abf = ix->Abf.as<uint16_t>(); pa.N = ix->LK;
@@ -495,12 +523,13 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
             DlTimer tm(T_PROJECT_SAMPLE, st);
             HCHECK(dl_launch_project(pa, PROJ_COLMAJOR, st));
         }
-        HCHECK(tmp.alloc(dl_breakpoint_tmp_bytes(n_s, ix->LK)));
+        HCHECK(pool_alloc(tmp, dl_breakpoint_tmp_bytes(n_s, ix->LK), ix->device));
         {
             DlTimer tm(T_BREAKPOINTS, st);
             HCHECK(dl_breakpoints(Ps.as<float>(), n_s, ix->LK, N_r, ix->B.as<float>(), ix->E.as<float>(), tmp.p, st));
         }
         HCHECK(hipStreamSynchronize(st));
+        for (DevBuf* b : {&rows, &Ps, &tmp}) pool_give(*b, ix->device);   // idle: the stream is drained
     }
     // encode every point
     {
@@ -700,10 +729,8 @@ detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void
     std::swap(ix->codes.p, codes.p); std::swap(ix->codes.bytes, codes.bytes);
     if (keep_bf16) { std::swap(ix->Xbf.p, Xbf.p); std::swap(ix->Xbf.bytes, Xbf.bytes); }
     ix->n = n1;
-    for (int i = 0; i < 8; ++i) {
-        if (ix->leaf_start[i]) (void)hipFree(ix->leaf_start[i]);
-        if (ix->leaf_lo[i]) (void)hipFree(ix->leaf_lo[i]);
-        if (ix->leaf_hi[i]) (void)hipFree(ix->leaf_hi[i]);
+    for (int i = 0; i < 8; ++i) {   // the stream is drained: the old leaf tables are idle
+        pool_give(ix->leaf_mem[i], ix->device);
         ix->leaf_start[i] = nullptr; ix->leaf_lo[i] = nullptr; ix->leaf_hi[i] = nullptr;
         ix->n_leaves[i] = 0;
     }
@@ -1021,7 +1048,6 @@ struct Arena {
     }
 };
 
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 constexpr int64_t kQueryTile = 128;   // queries per workgroup tile of the dense verification
 
@@ -1350,7 +1376,7 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
             qp = reinterpret_cast<float*>(arena.take((size_t)nq * ix->LK * 4));
             if (!qp) return fail(DETLSH_ENOMEM, "workspace too small for %lld query projections", (long long)nq);
         } else {
-            HCHECK(qpbuf.alloc((size_t)nq * ix->LK * 4));
+            HCHECK(pool_alloc(qpbuf, (size_t)nq * ix->LK * 4, ix->device));
             qp = qpbuf.as<float>();
         }
         ProjectArgs pa;
@@ -1365,7 +1391,7 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
             lad = reinterpret_cast<float*>(arena.take(s.ladder.size() * 4));
             if (!lad) return fail(DETLSH_ENOMEM, "workspace too small for the radius ladder");
         } else {
-            HCHECK(ladder.alloc(s.ladder.size() * 4));
+            HCHECK(pool_alloc(ladder, s.ladder.size() * 4, ix->device));
             lad = ladder.as<float>();
         }
         HCHECK(hipMemcpyAsync(lad, s.ladder.data(), s.ladder.size() * 4, hipMemcpyHostToDevice, st));
@@ -1400,6 +1426,9 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
         if (e) { prof_resolve(); return e; }
         if (st1[0] == 1) { prof_resolve(); return fail(DETLSH_EINTERNAL, "query %lld: fallback failed", (long long)q); }
     }
+    // every pass ended with its stream drained: the temporaries are idle
+    pool_give(qpbuf, ix->device);
+    pool_give(ladder, ix->device);
     prof_resolve();
     return DETLSH_OK;
 }

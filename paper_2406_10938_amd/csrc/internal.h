@@ -48,10 +48,18 @@ hipError_t dl_breakpoints(const float* Ps, int64_t n_s, int N, int N_r, float* B
 hipError_t dl_edges_from_breakpoints(const float* B, float* E, int N, int N_r, hipStream_t st);
 
 // ---- trees (k_tree.hip) ----
+// A tree is built in three phases, so that the L trees of an index can run
+// interleaved with one host wait per phase boundary (the next phase's launch
+// shape is a count the previous one leaves on the device): runs (totals[0]
+// runs), split (totals[1] leaves), leaves (the leaf table).  Each tree keeps
+// its own tmp of dl_tree_tmp_bytes(n, K) bytes through all three.
 size_t dl_tree_tmp_bytes(int64_t n, int K);
-hipError_t dl_build_tree(const uint8_t* codes_i, int64_t n, int K, int N_r, int max_leaf, int32_t* perm,
-                         uint8_t* scodes, void* tmp, hipStream_t st, int64_t* n_leaves, int32_t** leaf_start,
-                         uint8_t** leaf_lo, uint8_t** leaf_hi);
+hipError_t dl_tree_runs(const uint8_t* codes_i, int64_t n, int K, int N_r, int32_t* perm, uint8_t* scodes,
+                        void* tmp, uint32_t* totals, hipStream_t st);
+hipError_t dl_tree_split(int64_t n, int K, int N_r, int max_leaf, int32_t* perm, uint8_t* scodes, void* tmp,
+                         uint32_t nruns, uint32_t* totals, hipStream_t st);
+hipError_t dl_tree_leaves(int64_t n, int K, int N_r, const uint8_t* scodes, void* tmp, uint32_t nruns, uint32_t nl,
+                          int32_t* leaf_start, uint8_t* leaf_lo, uint8_t* leaf_hi, hipStream_t st);
 
 // ---- query (k_query.hip) ----
 // Leaf tables of the L DE-Trees: leaf_of[i*n + o] is the leaf of point o in

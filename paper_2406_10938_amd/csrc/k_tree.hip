@@ -243,60 +243,77 @@ size_t dl_tree_tmp_bytes(int64_t n, int K) {
     return (size_t)n * (4 * 9 + 2 * K) + dl_radix_tmp_bytes(n) + dl_scan_tmp_bytes(n) + 4096;
 }
 
-// Builds one tree.  Device outputs: perm[n], scodes[n*K]; the leaf table is
-// allocated here (cudaMalloc-style) and returned through *leaf_*.
-hipError_t dl_build_tree(const uint8_t* codes_i, int64_t n, int K, int N_r, int max_leaf, int32_t* perm,
-                         uint8_t* scodes, void* tmp, hipStream_t st, int64_t* n_leaves,
-                         int32_t** leaf_start, uint8_t** leaf_lo, uint8_t** leaf_hi) {
+namespace {
+
+// The arrays one tree's build keeps in its tmp across the three phases.
+struct TreeTmp {
+    uint32_t *key, *val, *flag, *idx, *nleaf, *loff;
+    int32_t* tperm;
+    uint8_t* tcodes;
+    int32_t* rec_start;
+    uint8_t* rec_plen;
+    int32_t* run_start;
+    void* scratch;
+    TreeTmp(void* tmp, int64_t n, int K) {
+        char* p = static_cast<char*>(tmp);
+        auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) & ~(size_t)255; return r; };
+        key = reinterpret_cast<uint32_t*>(take(n * 4));
+        val = reinterpret_cast<uint32_t*>(take(n * 4));
+        flag = reinterpret_cast<uint32_t*>(take(n * 4));
+        idx = reinterpret_cast<uint32_t*>(take(n * 4));
+        nleaf = reinterpret_cast<uint32_t*>(take(n * 4 + 4));
+        loff = reinterpret_cast<uint32_t*>(take(n * 4 + 4));
+        tperm = reinterpret_cast<int32_t*>(take(n * 4));
+        tcodes = reinterpret_cast<uint8_t*>(take(n * K));
+        rec_start = reinterpret_cast<int32_t*>(take(n * 4));
+        rec_plen = reinterpret_cast<uint8_t*>(take(n * K));
+        run_start = reinterpret_cast<int32_t*>(take((n + 1) * 4));
+        scratch = take(dl_radix_tmp_bytes(n) + dl_scan_tmp_bytes(n));
+    }
+};
+
+int root_bits(int N_r) {
     int bits = 0;
     while ((1 << bits) < N_r) ++bits;
-    char* p = static_cast<char*>(tmp);
-    auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) & ~(size_t)255; return r; };
-    uint32_t* key = reinterpret_cast<uint32_t*>(take(n * 4));
-    uint32_t* val = reinterpret_cast<uint32_t*>(take(n * 4));
-    uint32_t* flag = reinterpret_cast<uint32_t*>(take(n * 4));
-    uint32_t* idx = reinterpret_cast<uint32_t*>(take(n * 4));
-    uint32_t* nleaf = reinterpret_cast<uint32_t*>(take(n * 4 + 4));
-    uint32_t* loff = reinterpret_cast<uint32_t*>(take(n * 4 + 4));
-    int32_t* tperm = reinterpret_cast<int32_t*>(take(n * 4));
-    uint8_t* tcodes = reinterpret_cast<uint8_t*>(take(n * K));
-    int32_t* rec_start = reinterpret_cast<int32_t*>(take(n * 4));
-    uint8_t* rec_plen = reinterpret_cast<uint8_t*>(take(n * K));
-    int32_t* run_start = reinterpret_cast<int32_t*>(take((n + 1) * 4));
-    uint32_t* totals = reinterpret_cast<uint32_t*>(take(64));
-    void* scratch = take(dl_radix_tmp_bytes(n) + dl_scan_tmp_bytes(n));
+    return bits;
+}
 
+}  // namespace
+
+// Phase 1 of one tree: points sorted by their root key into runs (perm and
+// sorted code words); the number of runs goes to totals[0] on the device.
+hipError_t dl_tree_runs(const uint8_t* codes_i, int64_t n, int K, int N_r, int32_t* perm, uint8_t* scodes,
+                        void* tmp, uint32_t* totals, hipStream_t st) {
+    const int bits = root_bits(N_r);
     if (bits < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(root_key_kernel, dim3(grid_for(n)), dim3(256), 0, st, codes_i, n, K, bits, key, val);
-    hipError_t e = dl_radix_sort_pairs(key, val, n, 0, ((K + 7) / 8) * 8, scratch, st);
+    TreeTmp t(tmp, n, K);
+    hipLaunchKernelGGL(root_key_kernel, dim3(grid_for(n)), dim3(256), 0, st, codes_i, n, K, bits, t.key, t.val);
+    hipError_t e = dl_radix_sort_pairs(t.key, t.val, n, 0, ((K + 7) / 8) * 8, t.scratch, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gather_runs_kernel, dim3(grid_for(n)), dim3(256), 0, st, codes_i, key, val, n, K, perm,
-                       scodes, flag);
-    e = dl_exclusive_scan(flag, idx, n, reinterpret_cast<uint32_t*>(scratch), totals, st);
-    if (e != hipSuccess) return e;
-    uint32_t nruns = 0;
-    e = hipMemcpyAsync(&nruns, totals, 4, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(run_starts_kernel, dim3(grid_for(n)), dim3(256), 0, st, flag, idx, n, run_start, nruns);
-    hipLaunchKernelGGL(split_runs_kernel, dim3(nruns), dim3(256), 0, st, run_start, perm, scodes, tperm, tcodes,
-                       K, bits, max_leaf, rec_start, rec_plen, nleaf);
-    e = dl_exclusive_scan(nleaf, loff, nruns, reinterpret_cast<uint32_t*>(scratch), totals + 1, st);
-    if (e != hipSuccess) return e;
-    uint32_t nl = 0;
-    e = hipMemcpyAsync(&nl, totals + 1, 4, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    *n_leaves = nl;
-    e = hipMalloc(leaf_start, (size_t)(nl + 1) * 4);
-    if (e != hipSuccess) return e;
-    e = hipMalloc(leaf_lo, (size_t)nl * K + 4);
-    if (e != hipSuccess) return e;
-    e = hipMalloc(leaf_hi, (size_t)nl * K + 4);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(leaf_table_kernel, dim3(grid_for(nruns)), dim3(256), 0, st, run_start, nleaf, loff, nruns,
-                       rec_start, rec_plen, scodes, K, bits, n, *leaf_start, *leaf_lo, *leaf_hi, nl);
+    hipLaunchKernelGGL(gather_runs_kernel, dim3(grid_for(n)), dim3(256), 0, st, codes_i, t.key, t.val, n, K, perm,
+                       scodes, t.flag);
+    return dl_exclusive_scan(t.flag, t.idx, n, reinterpret_cast<uint32_t*>(t.scratch), totals, st);
+}
+
+// Phase 2: each of the nruns runs split into leaves in place; the number of
+// leaves goes to totals[1].
+hipError_t dl_tree_split(int64_t n, int K, int N_r, int max_leaf, int32_t* perm, uint8_t* scodes, void* tmp,
+                         uint32_t nruns, uint32_t* totals, hipStream_t st) {
+    const int bits = root_bits(N_r);
+    TreeTmp t(tmp, n, K);
+    hipLaunchKernelGGL(run_starts_kernel, dim3(grid_for(n)), dim3(256), 0, st, t.flag, t.idx, n, t.run_start, nruns);
+    hipLaunchKernelGGL(split_runs_kernel, dim3(nruns), dim3(256), 0, st, t.run_start, perm, scodes, t.tperm, t.tcodes,
+                       K, bits, max_leaf, t.rec_start, t.rec_plen, t.nleaf);
+    return dl_exclusive_scan(t.nleaf, t.loff, nruns, reinterpret_cast<uint32_t*>(t.scratch), totals + 1, st);
+}
+
+// Phase 3: the leaf table of the nl leaves (offsets into perm, and the K-byte
+// box corners of each leaf).
+hipError_t dl_tree_leaves(int64_t n, int K, int N_r, const uint8_t* scodes, void* tmp, uint32_t nruns, uint32_t nl,
+                          int32_t* leaf_start, uint8_t* leaf_lo, uint8_t* leaf_hi, hipStream_t st) {
+    const int bits = root_bits(N_r);
+    TreeTmp t(tmp, n, K);
+    hipLaunchKernelGGL(leaf_table_kernel, dim3(grid_for(nruns)), dim3(256), 0, st, t.run_start, t.nleaf, t.loff,
+                       nruns, t.rec_start, t.rec_plen, scodes, K, bits, n, leaf_start, leaf_lo, leaf_hi, nl);
     return hipGetLastError();
 }
