@@ -105,7 +105,7 @@ struct QueryArgs {
     int32_t* cand_id = nullptr;
     float* cand_m = nullptr;         // m^2 = min over trees of the bounds
     int32_t* cand_ft = nullptr;      // first admitting tree of each member of S
-    uint8_t* cand_f8 = nullptr;      // first admitting tree of each candidate (implicit S)
+    uint8_t* cand_f8 = nullptr;      // first admitting tree per candidate where the exact stop pass ran
     float* cand_lb = nullptr;        // L bounds per candidate; with an implicit S dl_prefix_mins(L) running minima
     int32_t* status = nullptr;
     uint32_t* s_count = nullptr;

@@ -722,8 +722,7 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                                                      int32_t* __restrict__ status, uint32_t* __restrict__ s_count,
                                                      float* __restrict__ thr_out, int32_t* __restrict__ stop_out,
                                                      uint64_t* __restrict__ bm, int64_t W, LeafTabs lt, int64_t n,
-                                                     const float* __restrict__ gthr, int compact,
-                                                     uint8_t* __restrict__ cand_f8)
+                                                     const float* __restrict__ gthr, int compact)
 {
     __shared__ SelectShared sh;
     __shared__ uint32_t tc[8];
@@ -777,60 +776,35 @@ __global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict_
                                                              N_S, __float_as_uint(gthr[t]), sh));
     if (!LEAF && !compact) {
         // S stays implicit: the candidates with 1 <= f(o) <= istop (consumers
-        // filter the list; s_count is the list's length).  Entry s holds m^2
-        // and the running minima p2 (trees 1..L-2, when L >= 3) and p1 (trees
-        // 1..L-1), so f(o) <= L-2 iff p2 <= thr, f(o) <= L-1 iff p1 <= thr and
-        // f(o) <= L iff m^2 <= thr: the byte kept per entry is 0, L-2, L-1 or
-        // L, which decides membership for the stop trees L-2..L.  When
-        // |U_{L-2}| >= N_S and L >= 4 a smaller stop tree is possible: the
-        // stop is left at -1 for stop_exact_kernel.
+        // test membership themselves; s_count is the list's length).  Entry s
+        // holds m^2 and the running minima p2 (trees 1..L-2, when L >= 3) and
+        // p1 (trees 1..L-1), so |U_{L-1}| = #{p1 <= thr} and |U_{L-2}| =
+        // #{p2 <= thr} settle the stop trees L-2..L.  When |U_{L-2}| >= N_S
+        // and L >= 4 a smaller stop tree is possible: the stop is left at -1
+        // for stop_exact_kernel.
         constexpr int NP = dl_prefix_mins(L);
         const float* pmt = cand_lb + (int64_t)t * cap * NP;
-        uint8_t* ft8 = cand_f8 + (int64_t)t * cap;
         uint32_t u1 = 0, u2 = 0;   // |U_{L-1}|, |U_{L-2}|
-        for (int64_t s0 = 4 * (int64_t)threadIdx.x; s0 < (int64_t)cnt; s0 += 1024) {
-            const bool whole = s0 + 3 < (int64_t)cnt;
-            float mv[4], p1[4], p2[4];
-            if (whole) {   // rows start 16-byte aligned
-                const float4 a4 = *reinterpret_cast<const float4*>(mt + s0);
-                mv[0] = a4.x; mv[1] = a4.y; mv[2] = a4.z; mv[3] = a4.w;
-                if constexpr (NP == 2) {
-                    const float4 b0 = *reinterpret_cast<const float4*>(pmt + 2 * s0);
-                    const float4 b1 = *reinterpret_cast<const float4*>(pmt + 2 * s0 + 4);
-                    p2[0] = b0.x; p1[0] = b0.y; p2[1] = b0.z; p1[1] = b0.w;
-                    p2[2] = b1.x; p1[2] = b1.y; p2[3] = b1.z; p1[3] = b1.w;
+        if (L >= 2) {
+            // NP floats per entry, rows start 16-byte aligned: 16-byte loads
+            const int64_t nf = (int64_t)cnt * NP;
+            for (int64_t f0 = 4 * (int64_t)threadIdx.x; f0 < nf; f0 += 1024) {
+                float v[4];
+                if (f0 + 3 < nf) {
+                    const float4 a4 = *reinterpret_cast<const float4*>(pmt + f0);
+                    v[0] = a4.x; v[1] = a4.y; v[2] = a4.z; v[3] = a4.w;
                 } else {
-                    const float4 b0 = *reinterpret_cast<const float4*>(pmt + s0);
-                    p1[0] = b0.x; p1[1] = b0.y; p1[2] = b0.z; p1[3] = b0.w;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) p2[j] = INFINITY;
+                    for (int j = 0; j < 4; ++j) v[j] = f0 + j < nf ? pmt[f0 + j] : INFINITY;
                 }
-            } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const bool in = s0 + j < (int64_t)cnt;
-                    mv[j] = in ? mt[s0 + j] : INFINITY;
-                    p1[j] = in ? pmt[NP * (s0 + j) + NP - 1] : INFINITY;
-                    p2[j] = (in && NP == 2) ? pmt[NP * (s0 + j)] : INFINITY;
+                    // with NP = 2 even slots are p2 and odd slots p1
+                    const bool is_p1 = NP == 1 || (j & 1);
+                    const bool in = v[j] <= thr;
+                    u1 += (in && is_p1) ? 1u : 0u;
+                    u2 += (in && !is_p1) ? 1u : 0u;
                 }
-            }
-            uint32_t packed = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bool in1 = L >= 2 && p1[j] <= thr;
-                const bool in2 = L >= 3 && p2[j] <= thr;
-                u1 += in1 ? 1u : 0u;
-                u2 += in2 ? 1u : 0u;
-                const uint32_t f = mv[j] <= thr ? (in2 ? (uint32_t)(L - 2) : in1 ? (uint32_t)(L - 1) : (uint32_t)L)
-                                                : 0u;
-                packed |= f << (8 * j);
-            }
-            if (whole) {
-                *reinterpret_cast<uint32_t*>(ft8 + s0) = packed;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (s0 + j < (int64_t)cnt) ft8[s0 + j] = (uint8_t)(packed >> (8 * j));
             }
         }
         u1 = dl_wave_sum(u1);
@@ -1043,16 +1017,34 @@ __global__ __launch_bounds__(256) void stop_exact_kernel(const float* __restrict
     }
 }
 
+// Membership in an implicit S of one query's candidate list: entry s belongs
+// to S iff f(o) <= istop, read off the key (stop tree L), the running minima
+// (stop trees L-1 and L-2) or, for a stop tree the exact pass settled, its
+// first-tree bytes.
+struct ImplicitS {
+    const float* key = nullptr;     // m^2 per entry
+    const float* mins = nullptr;    // np running minima per entry: trees 1..L-2 (np = 2), trees 1..L-1
+    const uint8_t* f8 = nullptr;    // f(o) per entry (written by stop_exact_kernel only)
+    int np = 1, L = 1, istop = 0;
+    float thr = 0.f;
+    __device__ bool member(int64_t s) const {
+        if (istop == L) return key[s] <= thr;
+        if (istop == L - 1) return mins[s * np + np - 1] <= thr;
+        if (istop == L - 2 && np == 2) return mins[s * np] <= thr;
+        const int f = f8[s];
+        return f >= 1 && f <= istop;
+    }
+};
+
 // Exact FP32 squared distances (direct differences, half a wave per row, R
 // rows in flight) of the rows listed for one query, written as 64-bit keys
 // (distance bits, id) to buf.
-// With `ft` (one byte per entry), entry s is a member only if 1 <= ft[s] <=
-// istop (an uncompacted candidate list); other entries get the key (+inf, id)
-// without a gather.
+// With an implicit S (use_ims), non-members get the key (+inf, id) without
+// a gather.
 template <bool ALIGNED>
-__device__ void gather_keys(const float* __restrict__ X, int d, const float* sq, const int32_t* __restrict__ ids,
-                            int64_t m, uint64_t* __restrict__ buf, const uint8_t* __restrict__ ft = nullptr,
-                            int istop = 0) {
+__device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
+                                            const int32_t* __restrict__ ids, int64_t m, uint64_t* __restrict__ buf,
+                                            bool use_ims = false, ImplicitS ims = ImplicitS()) {
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
     constexpr int R = 4;
@@ -1065,9 +1057,8 @@ __device__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
             const int64_t s = s0 + r;
             id[r] = (s < m) ? (ids ? (int64_t)ids[s] : s) : -1;
             skip[r] = false;
-            if (ft && id[r] >= 0) {
-                const int f = ft[s];
-                if (f < 1 || f > istop) {
+            if (use_ims && id[r] >= 0) {
+                if (!ims.member(s)) {
                     skip[r] = true;
                     if (hl == 0) buf[s] = (0x7f800000ull << 32) | (uint64_t)(uint32_t)id[r];
                     id[r] = -1;
@@ -1127,7 +1118,8 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     int64_t all_n, int32_t* __restrict__ status, int want, int sv_check, int64_t sv_cap,
     uint64_t* __restrict__ ws, int64_t ld_ws, int k,
     int64_t* __restrict__ out_ids, float* __restrict__ out_d, float* __restrict__ tau, int keys_only,
-    const uint8_t* __restrict__ ftl, const int32_t* __restrict__ stops)
+    int implicit_s, const float* __restrict__ cand_m, const float* __restrict__ cand_mins, int L,
+    const uint8_t* __restrict__ cand_f8, const float* __restrict__ thrs, const int32_t* __restrict__ stops)
 {
     extern __shared__ unsigned char smem[];
     TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
@@ -1147,8 +1139,17 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
     __syncthreads();
     uint64_t* buf = ws + (int64_t)t * ld_ws;
-    gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf,
-                         ftl ? ftl + (int64_t)t * ld_list : nullptr, stops ? stops[t] : 0);
+    ImplicitS ims;
+    if (implicit_s) {
+        ims.np = dl_prefix_mins(L);
+        ims.L = L;
+        ims.key = cand_m + (int64_t)t * ld_list;
+        ims.mins = cand_mins + (int64_t)t * ld_list * ims.np;
+        ims.f8 = cand_f8 + (int64_t)t * ld_list;
+        ims.istop = stops[t];
+        ims.thr = thrs[t];
+    }
+    gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf, implicit_s != 0, ims);
     if (keys_only) return;
     topk_u64(buf, m, k, sh);
     if (tau) {
@@ -1951,18 +1952,18 @@ hipError_t launch_select_l(const QueryArgs& a, hipStream_t st) {
     if (a.fixed) {
         hipLaunchKernelGGL((select_kernel<L, true, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n, a.gthr, a.compact_s, a.cand_f8);
+                           a.lt, a.n, a.gthr, a.compact_s);
         return hipGetLastError();
     }
     if (a.leaf) {
         hipLaunchKernelGGL((select_kernel<L, false, true>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                            a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W,
-                           a.lt, a.n, a.gthr, a.compact_s, a.cand_f8);
+                           a.lt, a.n, a.gthr, a.compact_s);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((select_kernel<L, false, false>), dim3(a.nqc), dim3(256), 0, st, a.counts, a.cap, a.N_S,
                        a.cand_id, a.cand_m, a.cand_ft, a.cand_lb, a.status, a.s_count, a.thr, a.stop, a.bm, a.W, a.lt,
-                       a.n, a.gthr, a.compact_s, a.cand_f8);
+                       a.n, a.gthr, a.compact_s);
     return hipGetLastError();
 }
 
@@ -2076,8 +2077,8 @@ hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_
     const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
     hipLaunchKernelGGL((gather_topk_kernel<AL>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
                        counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
-                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only,
-                       members ? a.cand_f8 : nullptr, members ? a.stop : nullptr);
+                       tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only, members ? 1 : 0,
+                       a.cand_m, a.cand_lb, a.L, a.cand_f8, a.thr, a.stop);
     return hipGetLastError();
 }
 
