@@ -1047,7 +1047,7 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
                                             bool use_ims = false, ImplicitS ims = ImplicitS()) {
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
-    constexpr int R = 4;
+    constexpr int R = 8;
     for (int64_t s0 = (int64_t)hw * R; s0 < m; s0 += 8 * R) {
         int64_t id[R];
         float acc[R];

@@ -269,6 +269,23 @@ def test_argument_errors(dl):
 # masked dense MFMA verification and the BF16 + rerank form
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("kind,d", [("integer", 128), ("integer", 62), ("mixture", 96)])
+def test_bf16_copy_changes_no_answer(dl, kind, d):
+    """An index with the BF16 copy (integer data, which BF16 holds exactly, and
+    float data, which it rounds) answers bit-identically to one without it,
+    for the gathered, dense and BF16-screen paths."""
+    say(f"BF16 copy changes no answer kind={kind} d={d}")
+    c = U.case(n=70_000, d=d, N_r=256, frac=0.01, kind=kind, nq=100, seed=53)
+    plain = dl.build_index(c["X"], 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"])
+    with_bf = dl.build_index(c["X"], 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=True)
+    Q = t(c["Q"])
+    ref_ids, ref_d = (x.cpu().numpy() for x in plain.query(Q, 10, 1.5, 0.1, verify="gather"))
+    for idx, verify in ((plain, "dense"), (with_bf, "gather"), (with_bf, "dense"), (with_bf, "dense_bf16")):
+        ids, dists = (x.cpu().numpy() for x in idx.query(Q, 10, 1.5, 0.1, verify=verify))
+        assert np.array_equal(ids, ref_ids), verify
+        assert np.array_equal(dists.view(np.uint32), ref_d.view(np.uint32)), verify
+
+
 @pytest.mark.parametrize("verify", ["dense", "dense_bf16"])
 def test_small_stop_tree_on_the_implicit_dense_path(dl, verify):
     """8,001 identical points (more than N_S = 7,010) and queries on them: the
