@@ -1600,7 +1600,10 @@ __device__ __forceinline__ uint4 load_vec16(const float* __restrict__ X, const u
     return make_uint4(__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]), __float_as_uint(a[3]));
 }
 
-template <bool BF16, bool ALIGNED>
+// A8 (BF16 rows with d a multiple of 8): every staged 8-element vector is a
+// 16-byte load that lies wholly inside its row or wholly beyond it, at a
+// 32-bit offset from the tile's (wave-uniform) first row.
+template <bool BF16, bool ALIGNED, bool A8 = false>
 __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
     const float* __restrict__ Q, const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int64_t q0,
@@ -1650,6 +1653,33 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     // only the point rows are staged per tile
     const bool q_resident = nchunk == 1;
     auto stage_load = [&](int64_t tile, int c, bool with_q) {
+        if constexpr (BF16 && A8) {
+            const int k = c * S::DC + (int)(threadIdx.x % S::VPR) * S::VE;
+            const bool in = k < d;
+            const int kk = in ? k : 0;
+            const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+            if (with_q) {
+                const uint16_t* qb = Qbf + (int64_t)qt0 * d;
+                const int qlim = min(kDQ - 1, nqc - 1 - qt0);
+#pragma unroll
+                for (int i = 0; i < S::SQ; ++i) {
+                    const int row = min((int)(threadIdx.x / S::VPR) + (256 / S::VPR) * i, qlim);
+                    const uint2* src = reinterpret_cast<const uint2*>(qb + row * d + kk);
+                    const uint2 lo = src[0], hi = src[1];
+                    sgq[i] = in ? make_uint4(lo.x, lo.y, hi.x, hi.y) : zero;
+                }
+            }
+            const uint16_t* xb = Xbf + tile * (int64_t)kDP * d;
+            const int xlim = (int)min((int64_t)(kDP - 1), n - 1 - tile * kDP);
+#pragma unroll
+            for (int i = 0; i < S::SX; ++i) {
+                const int row = min((int)(threadIdx.x / S::VPR) + (256 / S::VPR) * i, xlim);
+                const uint2* src = reinterpret_cast<const uint2*>(xb + row * d + kk);
+                const uint2 lo = src[0], hi = src[1];
+                sgx[i] = in ? make_uint4(lo.x, lo.y, hi.x, hi.y) : zero;
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < S::SQ; ++i) {
             if (!with_q) break;
@@ -2139,16 +2169,18 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
         else if (ks <= 6) DL_DENSE(false, true, true, 6);
         else DL_DENSE(false, true, true, 8);
     } else {
-#define DL_DENSE_KC(BF, AL)                                                                                    \
-    hipLaunchKernelGGL((dense_verify_kc_kernel<BF, AL>), dim3((unsigned)blocks), dim3(256), 0, st, a.X, a.Xbf, xn,  \
+#define DL_DENSE_KC(BF, AL, A8)                                                                                \
+    hipLaunchKernelGGL((dense_verify_kc_kernel<BF, AL, A8>), dim3((unsigned)blocks), dim3(256), 0, st, a.X, a.Xbf, \
+                       xn,                                                                                        \
                        a.n, a.d, a.Q, a.Qbf, a.qn, a.q0, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv,  \
                        a.cap_sv, gx, gy, ntiles, tps)
         if (a.dense_bf16) {
-            if (al) DL_DENSE_KC(true, true);
-            else DL_DENSE_KC(true, false);
+            if (a.d % 8 == 0) DL_DENSE_KC(true, true, true);
+            else if (al) DL_DENSE_KC(true, true, false);
+            else DL_DENSE_KC(true, false, false);
         } else {
-            if (al) DL_DENSE_KC(false, true);
-            else DL_DENSE_KC(false, false);
+            if (al) DL_DENSE_KC(false, true, false);
+            else DL_DENSE_KC(false, false, false);
         }
 #undef DL_DENSE_KC
     }
