@@ -286,23 +286,25 @@ def test_bf16_copy_changes_no_answer(dl, kind, d):
         assert np.array_equal(dists.view(np.uint32), ref_d.view(np.uint32)), verify
 
 
+@pytest.mark.parametrize("L,K", [(4, 16), (8, 8), (2, 16), (1, 16)])
 @pytest.mark.parametrize("verify", ["dense", "dense_bf16"])
-def test_small_stop_tree_on_the_implicit_dense_path(dl, verify):
+def test_small_stop_tree_on_the_implicit_dense_path(dl, verify, L, K):
     """8,001 identical points (more than N_S = 7,010) and queries on them: the
     first tree alone admits the whole cluster at threshold 0, so the stop tree
-    is 1, below the L-1 that the dense path's selection settles from the
-    stored prefix minimum; its exact pass decides it.  The dense path (S kept
+    is 1.  For L >= 4 that is below the L-2 that the dense path's selection
+    settles from the stored running minima, and its exact pass decides it;
+    for L <= 3 the minima (or the key) settle it.  The dense path (S kept
     implicit) returns the gathered path's ids and distances bit for bit, the
     stop trees equal the oracle's, and the results are the oracle's."""
-    say(f"small stop tree on the dense path n=70000 d=64 cluster=8001 verify={verify}")
-    c = U.case(n=70_000, d=64, N_r=256, frac=0.01, kind="mixture", nq=40, seed=41)
+    say(f"small stop tree on the dense path n=70000 d=64 cluster=8001 L={L} K={K} verify={verify}")
+    c = U.case(n=70_000, d=64, L=L, K=K, N_r=256, frac=0.01, kind="mixture", nq=40, seed=41)
     X, Q = c["X"].copy(), c["Q"].copy()
     X[1000:9000] = X[500]
     Q[0] = X[500]
     Q[7] = X[500]
     Q[13] = X[500]
     k, beta = 10, 0.1
-    idx = dl.build_index(X, 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=verify == "dense_bf16")
+    idx = dl.build_index(X, L, K, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=verify == "dense_bf16")
     Qt = t(Q)
     g_ids, g_d = idx.query(Qt, k, 1.5, beta, verify="gather")
     d_ids, d_d = idx.query(Qt, k, 1.5, beta, verify=verify)
@@ -312,7 +314,7 @@ def test_small_stop_tree_on_the_implicit_dense_path(dl, verify):
     Qp = idx.project(Qt).cpu().numpy()
     r = idx.query_debug(Qt, k, 1.5, beta, Qp=t(Qp), verify="dense")
     for qi in (0, 7, 13, 1, 2):
-        ref = U.oracle_query(X, Q[qi], Qp[qi], ex["codes"], ex["B"], 4, 16, k, beta)
+        ref = U.oracle_query(X, Q[qi], Qp[qi], ex["codes"], ex["B"], L, K, k, beta)
         if qi in (0, 7, 13):
             assert ref.stop_tree == 1
         assert int(r["stop_tree"][qi]) == ref.stop_tree
