@@ -1600,9 +1600,10 @@ __device__ __forceinline__ uint4 load_vec16(const float* __restrict__ X, const u
     return make_uint4(__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]), __float_as_uint(a[3]));
 }
 
-// A8 (BF16 rows with d a multiple of 8): every staged 8-element vector is a
-// 16-byte load that lies wholly inside its row or wholly beyond it, at a
-// 32-bit offset from the tile's (wave-uniform) first row.
+// A8 (BF16 rows with d a multiple of 8): every staged 8-element vector lies
+// wholly inside its row or wholly beyond it and is read as two 8-byte halves
+// at a 32-bit offset from the tile's (wave-uniform) first row (one 16-byte
+// load made the compiler wait for the staging loads before the tile's MFMA).
 template <bool BF16, bool ALIGNED, bool A8 = false>
 __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     const float* __restrict__ X, const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
