@@ -29,7 +29,6 @@ __global__ __launch_bounds__(256) void project_kernel(
     const int wave = threadIdx.x >> 6;
     const int m = lane & 15;
     const int kq = lane >> 4;
-    const int64_t R0 = (int64_t)blockIdx.x * kRowsPerBlock;
 
     float* sE = reinterpret_cast<float*>(smem);
     uint8_t* sC = smem + (size_t)N * (N_r + 1) * sizeof(float);
@@ -37,123 +36,133 @@ __global__ __launch_bounds__(256) void project_kernel(
         const int tot = N * (N_r + 1);
         for (int t = threadIdx.x; t < tot; t += blockDim.x) sE[t] = E[t];
     }
+    // the encode grid is persistent (the breakpoint table is loaded once per
+    // workgroup): workgroup b takes the row tiles b, b + gridDim.x, ...
+    const int64_t ntile = (M + kRowsPerBlock - 1) / kRowsPerBlock;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += (EPI == EPI_ENCODE ? gridDim.x : ntile)) {
+        const int64_t R0 = tile * kRowsPerBlock;
 
-    int64_t src[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-        int64_t r = R0 + wave * kRowsPerWave + rb * 16 + m;
-        if (r >= M) r = M - 1;
-        src[rb] = rows ? (int64_t)rows[r] : r;
-    }
-
-    floatx4 acc[2][NT];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) acc[rb][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    if (!BF16) {
-        const float* xr0 = X + src[0] * (int64_t)d;
-        const float* xr1 = X + src[1] * (int64_t)d;
-        for (int k0 = 0; k0 < d; k0 += 16) {
-            const int kk = k0 + 4 * kq;
-            floatx4 xv0 = load4<ALIGNED>(xr0, kk, d);
-            floatx4 xv1 = load4<ALIGNED>(xr1, kk, d);
-            floatx4 av[NT];
-#pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const int c = ct * 16 + m;
-                if (c < N) av[ct] = load4<ALIGNED>(A + (int64_t)c * d, kk, d);
-                else av[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-#pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv0[s], av[ct][s], acc[0][ct], 0, 0, 0);
-                    acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv1[s], av[ct][s], acc[1][ct], 0, 0, 0);
-                }
-            }
+        int64_t src[2];
+    #pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            int64_t r = R0 + wave * kRowsPerWave + rb * 16 + m;
+            if (r >= M) r = M - 1;
+            src[rb] = rows ? (int64_t)rows[r] : r;
         }
-    } else {
-        // v_mfma_f32_16x16x16bf16_1k: lane l supplies 4 consecutive reduction
-        // elements k0 + 4*(l/16) .. +3 of its row (A operand) / column (B operand).
-        const uint16_t* xr0 = Xbf + src[0] * (int64_t)d;
-        const uint16_t* xr1 = Xbf + src[1] * (int64_t)d;
-        for (int k0 = 0; k0 < d; k0 += 16) {
-            const int kk = k0 + 4 * kq;
-            shortx4 xv0 = load4bf<ALIGNED>(xr0, kk, d);
-            shortx4 xv1 = load4bf<ALIGNED>(xr1, kk, d);
-#pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                const int c = ct * 16 + m;
-                shortx4 av = (c < N) ? load4bf<ALIGNED>(Abf + (int64_t)c * d, kk, d)
-                                     : shortx4{0, 0, 0, 0};
-                acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv0, av, acc[0][ct], 0, 0, 0);
-                acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv1, av, acc[1][ct], 0, 0, 0);
-            }
-        }
-    }
 
-    if (EPI == EPI_COLMAJOR || EPI == EPI_ROWMAJOR) {
-#pragma unroll
+        floatx4 acc[2][NT];
+    #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t r = R0 + wave * kRowsPerWave + rb * 16 + 4 * kq + v;
-                    const int e = ct * 16 + m;
-                    if (r < M && e < N) {
-                        if (EPI == EPI_COLMAJOR) Pout[(int64_t)e * ldp + r] = acc[rb][ct][v];
-                        else Pout[r * N + e] = acc[rb][ct][v];
+    #pragma unroll
+            for (int ct = 0; ct < NT; ++ct) acc[rb][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+        if (!BF16) {
+            const float* xr0 = X + src[0] * (int64_t)d;
+            const float* xr1 = X + src[1] * (int64_t)d;
+            for (int k0 = 0; k0 < d; k0 += 16) {
+                const int kk = k0 + 4 * kq;
+                floatx4 xv0 = load4<ALIGNED>(xr0, kk, d);
+                floatx4 xv1 = load4<ALIGNED>(xr1, kk, d);
+                floatx4 av[NT];
+    #pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int c = ct * 16 + m;
+                    if (c < N) av[ct] = load4<ALIGNED>(A + (int64_t)c * d, kk, d);
+                    else av[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+    #pragma unroll
+                for (int s = 0; s < 4; ++s) {
+    #pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) {
+                        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv0[s], av[ct][s], acc[0][ct], 0, 0, 0);
+                        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv1[s], av[ct][s], acc[1][ct], 0, 0, 0);
                     }
                 }
-        return;
-    }
-
-    // EPI_ENCODE: code = max b in [0, N_r-1] with E[e][b] <= h, where
-    // E[e][0] = -inf and E[e][b] = B_e(b+1): the number of interior
-    // breakpoints B(2..N_r) that are <= h (a tie goes to the upper region).
-    __syncthreads();
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rl = wave * kRowsPerWave + rb * 16 + 4 * kq + v;
-                const int e = ct * 16 + m;
-                if (e < N) {
-                    const float h = acc[rb][ct][v];
-                    const float* Ee = sE + e * (N_r + 1);
-                    int pos = 0;
-                    for (int s = N_r >> 1; s > 0; s >>= 1)
-                        if (Ee[pos + s] <= h) pos += s;
-                    sC[rl * 64 + e] = (uint8_t)pos;
+            }
+        } else {
+            // v_mfma_f32_16x16x16bf16_1k: lane l supplies 4 consecutive reduction
+            // elements k0 + 4*(l/16) .. +3 of its row (A operand) / column (B operand).
+            const uint16_t* xr0 = Xbf + src[0] * (int64_t)d;
+            const uint16_t* xr1 = Xbf + src[1] * (int64_t)d;
+            for (int k0 = 0; k0 < d; k0 += 16) {
+                const int kk = k0 + 4 * kq;
+                shortx4 xv0 = load4bf<ALIGNED>(xr0, kk, d);
+                shortx4 xv1 = load4bf<ALIGNED>(xr1, kk, d);
+    #pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int c = ct * 16 + m;
+                    shortx4 av = (c < N) ? load4bf<ALIGNED>(Abf + (int64_t)c * d, kk, d)
+                                         : shortx4{0, 0, 0, 0};
+                    acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv0, av, acc[0][ct], 0, 0, 0);
+                    acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv1, av, acc[1][ct], 0, 0, 0);
                 }
             }
-    __syncthreads();
-    // codes layout [L][n][K]: the tile of tree i is rows R0.. contiguous K-byte words
-    const int L = N / K;
-    const int64_t rows_here = (M - R0 < kRowsPerBlock) ? (M - R0) : kRowsPerBlock;
-    const int words_per_tree = (int)(rows_here * K / 4);
-    for (int i = 0; i < L; ++i) {
-        uint32_t* dst = reinterpret_cast<uint32_t*>(codes + ((int64_t)i * n_codes + R0) * K);
-        for (int w = threadIdx.x; w < words_per_tree; w += blockDim.x) {
-            const int byte = w * 4;
-            const int rl = byte / K;
-            const int j = byte % K;
-            const uint8_t* sp = sC + rl * 64 + i * K + j;
-            dst[w] = (uint32_t)sp[0] | ((uint32_t)sp[1] << 8) | ((uint32_t)sp[2] << 16) |
-                     ((uint32_t)sp[3] << 24);
         }
+
+        if (EPI == EPI_COLMAJOR || EPI == EPI_ROWMAJOR) {
+    #pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+    #pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t r = R0 + wave * kRowsPerWave + rb * 16 + 4 * kq + v;
+                        const int e = ct * 16 + m;
+                        if (r < M && e < N) {
+                            if (EPI == EPI_COLMAJOR) Pout[(int64_t)e * ldp + r] = acc[rb][ct][v];
+                            else Pout[r * N + e] = acc[rb][ct][v];
+                        }
+                    }
+            continue;
+        }
+
+        // EPI_ENCODE: code = max b in [0, N_r-1] with E[e][b] <= h, where
+        // E[e][0] = -inf and E[e][b] = B_e(b+1): the number of interior
+        // breakpoints B(2..N_r) that are <= h (a tie goes to the upper region).
+        __syncthreads();
+    #pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+    #pragma unroll
+            for (int ct = 0; ct < NT; ++ct)
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rl = wave * kRowsPerWave + rb * 16 + 4 * kq + v;
+                    const int e = ct * 16 + m;
+                    if (e < N) {
+                        const float h = acc[rb][ct][v];
+                        const float* Ee = sE + e * (N_r + 1);
+                        int pos = 0;
+                        for (int s = N_r >> 1; s > 0; s >>= 1)
+                            if (Ee[pos + s] <= h) pos += s;
+                        sC[rl * 64 + e] = (uint8_t)pos;
+                    }
+                }
+        __syncthreads();
+        // codes layout [L][n][K]: the tile of tree i is rows R0.. contiguous K-byte words
+        const int L = N / K;
+        const int64_t rows_here = (M - R0 < kRowsPerBlock) ? (M - R0) : kRowsPerBlock;
+        const int words_per_tree = (int)(rows_here * K / 4);
+        for (int i = 0; i < L; ++i) {
+            uint32_t* dst = reinterpret_cast<uint32_t*>(codes + ((int64_t)i * n_codes + R0) * K);
+            for (int w = threadIdx.x; w < words_per_tree; w += blockDim.x) {
+                const int byte = w * 4;
+                const int rl = byte / K;
+                const int j = byte % K;
+                const uint8_t* sp = sC + rl * 64 + i * K + j;
+                dst[w] = (uint32_t)sp[0] | ((uint32_t)sp[1] << 8) | ((uint32_t)sp[2] << 16) |
+                         ((uint32_t)sp[3] << 24);
+            }
+        }
+        __syncthreads();   // this tile's codes are read out before the next tile writes sC
     }
 }
 
 template <int NT, int EPI>
 hipError_t launch_nt(const ProjectArgs& a, hipStream_t st) {
-    const int64_t blocks = (a.M + kRowsPerBlock - 1) / kRowsPerBlock;
+    int64_t blocks = (a.M + kRowsPerBlock - 1) / kRowsPerBlock;
+    // encode: two resident workgroups per CU (the breakpoint table fills most of
+    // the LDS), each looping over row tiles
+    if (EPI == EPI_ENCODE && blocks > 512) blocks = 512;
     size_t shm = 0;
     if (EPI == EPI_ENCODE) shm = (size_t)a.N * (a.N_r + 1) * sizeof(float) + kRowsPerBlock * 64;
     const bool aligned = (a.d % 4) == 0;
