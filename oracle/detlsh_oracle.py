@@ -261,6 +261,19 @@ class Leaf:
     plen: np.ndarray      # per-dimension prefix length in bits
 
 
+def most_even_dimension(open_dims, ones, size: int) -> int:
+    """The split dimension of an overfull node (Sec. 4.2): among the dimensions
+    whose prefix is not yet complete, the one whose next bit divides the
+    node's ``size`` points most evenly, i.e. with the smallest |#ones - #zeros|
+    = |2 ones - size|; ties go to the lowest dimension (reading R15)."""
+    best, best_gap = None, None
+    for j, c in zip(open_dims, ones):
+        gap = abs(2 * c - size)
+        if best is None or gap < best_gap:
+            best, best_gap = j, gap
+    return best
+
+
 def build_tree(codes_i, N_r: int, max_leaf: int) -> list[Leaf]:
     """One DE-Tree over the K-dimensional codes of one projected space.
 
@@ -286,12 +299,8 @@ def build_tree(codes_i, N_r: int, max_leaf: int) -> list[Leaf]:
             hi = lo + (1 << (bits - plen)) - 1
             leaves.append(Leaf(np.sort(ids), lo, hi, plen.copy()))
             return
-        best, best_gap = None, None
-        for j in open_dims:
-            ones = int(((codes_i[ids, j] >> (bits - 1 - plen[j])) & 1).sum())
-            gap = abs(2 * ones - size)
-            if best is None or gap < best_gap:
-                best, best_gap = j, gap
+        ones = [int(((codes_i[ids, j] >> (bits - 1 - plen[j])) & 1).sum()) for j in open_dims]
+        best = most_even_dimension(open_dims, ones, size)
         bit = (codes_i[ids, best] >> (bits - 1 - plen[best])) & 1
         child = plen.copy()
         child[best] += 1

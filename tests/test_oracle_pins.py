@@ -299,6 +299,60 @@ def test_p9_tree_partition_and_boxes():
             assert np.all(lf.plen >= 1)
 
 
+# A hand-worked DE-Tree (Sec. 4.2, Alg. 3): N_r = 4 (two bits per code), K = 3,
+# max_leaf = 3.  Points 0..11 share the root child whose first-bit vector is
+# 000 (codes 0 or 1); point 12 (codes 2, 3, 2) is alone in root child 111.
+# Worked by hand with "the dimension whose next bit divides the node most
+# evenly, ties to the lowest dimension":
+#   root child 000, 12 points: next-bit ones 6, 6, 4 -> |2*ones - 12| = 0, 0, 4
+#     -> dimension 0 (tie with dimension 1 goes to the lower one)
+#   c0 = 0 {0..5}: ones in dimensions 1, 2 = 1, 3 -> gaps 4, 0 -> dimension 2
+#     -> {0,1,2} and {3,4,5}, both within max_leaf
+#   c0 = 1 {6..11}: ones 5, 1 -> gaps 4, 4 -> tie -> dimension 1
+#     -> {11}, and {6..10} (5 points) whose only open dimension is 2
+#        -> {7,8,9,10} (every prefix complete: a leaf despite its size), {6}
+# Leaves come root child by root child, depth first, 0-branch first.
+HAND_CODES = np.array([
+    [0, 0, 0], [0, 0, 0], [0, 0, 0], [0, 0, 1], [0, 0, 1], [0, 1, 1],
+    [1, 1, 1], [1, 1, 0], [1, 1, 0], [1, 1, 0], [1, 1, 0], [1, 0, 0],
+    [2, 3, 2]], dtype=np.uint8)
+HAND_LEAVES = [   # (ids, lo codes, hi codes)
+    ([0, 1, 2], [0, 0, 0], [0, 1, 0]),
+    ([3, 4, 5], [0, 0, 1], [0, 1, 1]),
+    ([11], [1, 0, 0], [1, 0, 1]),
+    ([7, 8, 9, 10], [1, 1, 0], [1, 1, 0]),
+    ([6], [1, 1, 1], [1, 1, 1]),
+    ([12], [2, 2, 2], [3, 3, 3]),
+]
+
+
+def hand_tree_matches():
+    leaves = O.build_tree(HAND_CODES, N_r=4, max_leaf=3)
+    got = [(lf.ids.tolist(), lf.lo.tolist(), lf.hi.tolist()) for lf in leaves]
+    return got == HAND_LEAVES
+
+
+def test_p9_split_on_the_most_even_dimension_hand_worked():
+    assert hand_tree_matches()
+
+
+def test_planted_split_on_least_even_dimension_is_caught(monkeypatch):
+    def least_even(open_dims, ones, size):
+        gaps = [abs(2 * c - size) for c in ones]
+        return open_dims[int(np.argmax(gaps))]
+    monkeypatch.setattr(O, "most_even_dimension", least_even)
+    assert not hand_tree_matches()
+
+
+def test_planted_split_tie_to_highest_dimension_is_caught(monkeypatch):
+    def highest_on_tie(open_dims, ones, size):
+        gaps = [abs(2 * c - size) for c in ones]
+        g = min(gaps)
+        return [j for j, x in zip(open_dims, gaps) if x == g][-1]
+    monkeypatch.setattr(O, "most_even_dimension", highest_on_tie)
+    assert not hand_tree_matches()
+
+
 def test_p9_candidate_sets_grow_with_radius():
     X, idx, _ = make_problem(n=1500, seed=9)
     qp = O.project((X[5] + 0.3)[None, :], idx.A)[0]
