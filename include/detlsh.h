@@ -257,6 +257,38 @@ detlsh_status detlsh_query_rc(detlsh_index idx, const float* Q, int64_t nq, doub
                               float* out_dists, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* query without device allocation                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Size of the fixed device array that detlsh_query_noalloc works in. */
+#define DETLSH_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the query of
+ * detlsh_query (magic radius; same arguments, same kernels, bit-identical
+ * results) run entirely inside one fixed array of DETLSH_NOALLOC_SCRATCH_BYTES
+ * bytes that the library's code object places on every device it runs on and
+ * that stays there until the process ends.  No device memory is allocated or
+ * freed.  Q, out_ids and out_dists are the caller's device buffers, as for
+ * detlsh_query.  The array keeps the last call's contents; the query path
+ * writes or clears everything it reads.  Overlapping calls on one device would
+ * race on the array, so the library serialises them (a per-process lock) and
+ * each call returns only after its work on `stream` is complete.
+ * Limits: those of detlsh_query, DETLSH_RMIN_MAGIC only (FIXED: DETLSH_EINVAL),
+ * and the array must hold one query with its fallback over all n points (about
+ * 40 bytes per point) plus nq*L*K*4 bytes of query projections, else
+ * DETLSH_ENOMEM with the sizes in the message.  Queries are run in as many
+ * passes as the array requires.
+ */
+detlsh_status detlsh_query_noalloc(detlsh_index idx, const float* Q, int64_t nq, int32_t k,
+                                   double c, double beta, const detlsh_query_opts* opts,
+                                   int64_t* out_ids, float* out_dists, void* stream);
+
+/* DETLSH_NOALLOC_SCRATCH_BYTES as compiled into the library. */
+size_t detlsh_noalloc_scratch_bytes(void);
+
+/* ------------------------------------------------------------------------ */
 /* incremental insertion                                                    */
 /* ------------------------------------------------------------------------ */
 

@@ -121,6 +121,20 @@ class Index:
                                  _ptr(dists), _stream_ptr()))
         return ids, dists
 
+    def query_noalloc(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, verify="auto",
+                      granularity="point"):
+        """detlsh_query inside the library's fixed device array: the call
+        allocates no device memory (the outputs here are the caller's)."""
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        nq = Q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        o = _query_opts(precision, rerank_mult, RMIN_MAGIC, 0.0, 0, 0, verify, granularity)
+        check(lib().detlsh_query_noalloc(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o),
+                                         _ptr(ids), _ptr(dists), _stream_ptr()))
+        return ids, dists
+
     def query_rc(self, Q, r, c=1.5, beta=0.1):
         """(r, c)-ANN query (Alg. 6): per query the nearest point of S, or id -1
         and distance +inf when the algorithm returns nothing."""

@@ -81,6 +81,9 @@ SIGNATURES = {
                                P]),
     "detlsh_query_debug": (C.c_int, [P, P, P, C.c_int64, C.c_int32, C.c_double, C.c_double,
                                      C.POINTER(QueryOpts), P, C.c_int64, P, P, P, P, P, P, P, P]),
+    "detlsh_query_noalloc": (C.c_int, [P, P, C.c_int64, C.c_int32, C.c_double, C.c_double, C.POINTER(QueryOpts),
+                                       P, P, P]),
+    "detlsh_noalloc_scratch_bytes": (C.c_size_t, []),
     "detlsh_query_rc": (C.c_int, [P, P, C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(QueryOpts), P,
                                   P, P]),
     "detlsh_insert": (C.c_int, [P, P, C.c_int64, P]),

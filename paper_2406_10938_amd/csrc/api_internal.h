@@ -12,6 +12,8 @@ detlsh_status dl_error(detlsh_status s, const char* msg);
 bool dl_is_device_ptr(const void* p);
 int dl_index_device(detlsh_index ix);
 int32_t dl_index_dim(detlsh_index ix);
+int32_t dl_index_lk(detlsh_index ix);    // L*K
+int64_t dl_index_n(detlsh_index ix);
 
 // Checks the scalar arguments of a query of nq rows exactly as detlsh_query
 // does; *bytes_one_pass (optional) receives the arena size that runs all nq

@@ -1447,6 +1447,10 @@ int dl_index_device(detlsh_index ix) { return ix->device; }
 
 int32_t dl_index_dim(detlsh_index ix) { return ix->d; }
 
+int32_t dl_index_lk(detlsh_index ix) { return ix->LK; }
+
+int64_t dl_index_n(detlsh_index ix) { return ix->n; }
+
 detlsh_status dl_query_check(detlsh_index ix, int64_t nq, int32_t k, double c, double beta,
                              const detlsh_query_opts* opts, size_t* bytes_one_pass) {
     QuerySetup s;
