@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the DET-LSH hot path on one MI355X.
 
-One step = the whole hot path over one batch: build the index over the
-SIFT-shaped set (n = 1,000,000, d = 128, integers in [0, 255]; L = 4, K = 16,
-N_r = 256, 1% breakpoint sample) and answer 10,000 queries from the same
-generator (k = 10, c = 1.5, beta = 0.1) with plain FP32 verification.  Inputs
-are resident in HBM before the timed region.  `value` is the whole-step
-throughput in queries/s (build included); the query-only rate and the build
-rate are reported beside it.
+Headline: one step = the whole hot path over one batch on the largest
+single-GPU workload: build the index over the n = 10^7, d = 96 normalised
+Gaussian mixture (unit vectors; L = 4, K = 16, N_r = 256, 1% breakpoint
+sample) and answer 10,000 queries from the same generator (k = 10, c = 1.5,
+beta the smallest grid value with recall@10 >= 0.9).  Inputs are resident in
+HBM before the timed region.  Three forms are timed: plain FP32 (the `value`),
+exact FP32 results through a BF16-product screen, and BF16 + rerank (BF16
+projection and products, top 4k reranked in FP32).  Each carries recall@10
+and the overall ratio (Sec. 6.1) against exact k-NN over all queries and
+against the FP64 oracle's answers on a fixed subset.  Extra keys: the
+SIFT-shaped n = 10^6 workload, the serving form (p50/p99 under Poisson load)
+and the oracle timed on the host cores.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build uses one GPU.
 """
@@ -77,27 +82,60 @@ def counted_traffic(kernel):
     return None
 
 
-def cpu_baseline(X_host, Q_host, A, sample, cfg, k, beta, nq_total, n_queries):
-    """The FP64 oracle on the host cores (one BLAS thread): full-n build, then
-    `n_queries` queries; scaled to whole-job queries/s."""
-    from threadpoolctl import threadpool_limits
+# ---------------------------------------------------------------------------
+# the three forms of the headline
+# ---------------------------------------------------------------------------
 
-    from oracle import detlsh_oracle as O
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        idx = O.build_index(X_host, A, sample, cfg.L, cfg.K, cfg.N_r)
-        t_build = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        for qi in range(n_queries):
-            qp = O.project(Q_host[qi:qi + 1], A)[0]
-            O.query_magic(X_host, Q_host[qi], qp, idx.codes, idx.B, cfg.L, cfg.K, k, beta)
-        t_q = (time.perf_counter() - t0) / n_queries
-    total = t_build + nq_total * t_q
-    return {"value": nq_total / total, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle, 1 thread: full build over n={X_host.shape[0]} "
-                       f"({t_build:.2f} s) + {n_queries} of the {nq_total} queries "
-                       f"({t_q * 1e3:.1f} ms each), scaled to the whole step"),
-            "build_s": t_build, "query_ms": t_q * 1e3}
+FORMS = {
+    # FP32 projection, FP32-product dense verification, exact FP32 ranking
+    "fp32": {"build": {"keep_bf16": False}, "query": {"verify": "dense"},
+             "dtype": "f32", "what": "plain FP32: FP32 projection, FP32-product verification, FP32 ranking"},
+    # the same results bit for bit: a BF16-product screen with a bound widened by
+    # the BF16 rounding decides which members of S reach the FP32 ranking
+    "fp32_bf16screen": {"build": {"keep_bf16": True}, "query": {},
+                        "dtype": "f32", "what": "exact FP32 results through a BF16-product screen (identical "
+                                                "answers to plain FP32)"},
+    # BF16 projection and products, top-4k reranked with exact FP32 distances
+    "bf16_rerank": {"build": {"keep_bf16": True, "proj_bf16": True}, "query": {"rerank_mult": 4},
+                    "dtype": "bf16", "what": "BF16 projection and verification products (FP32 accumulate), "
+                                             "top 4k reranked by exact FP32 distances"},
+}
+
+
+def knn_dists(X, Q, k, chunk):
+    """Exact k-NN distances per query (ascending), the reference R* of the
+    quality measures: FP32 products preselect k + 32 candidates, which are
+    re-measured in float64 by direct differences."""
+    import torch
+    xn = (X.double() ** 2).sum(1).float()
+    out = torch.empty((Q.shape[0], k), dtype=torch.float64, device=Q.device)
+    for s in range(0, Q.shape[0], chunk):
+        q = Q[s:s + chunk]
+        d2 = xn[None, :] - 2.0 * (q @ X.T) + (q.double() ** 2).sum(1).float()[:, None]
+        cand = torch.topk(d2, k + 32, dim=1, largest=False).indices
+        exact = ((X[cand].double() - q[:, None, :].double()) ** 2).sum(-1)
+        out[s:s + chunk] = torch.sort(exact, dim=1).values[:, :k].sqrt()
+    return out
+
+
+def quality(ret_d, ref_d):
+    """Mean recall and overall ratio (Sec. 6.1) of answers given by their
+    distances (nq x k, ascending) against reference distances: a returned point
+    counts for recall when its distance is at most the k-th reference distance
+    (ties, capped at k); a 0/0 ratio term counts as 1."""
+    import torch
+    ret = torch.as_tensor(ret_d, dtype=torch.float64)
+    ref = torch.as_tensor(ref_d, dtype=torch.float64).to(ret.device)
+    k = ref.shape[1]
+    hit = (ret <= ref[:, -1:] * (1 + 1e-12)).sum(1).clamp(max=k)
+    pos = ref > 0
+    terms = torch.where(pos, ret / torch.where(pos, ref, torch.ones_like(ref)),
+                        torch.where(ret > 0, torch.full_like(ret, float("inf")), torch.ones_like(ret)))
+    return float(hit.double().mean() / k), float(terms.mean())
+
+
+def exact_dists(X, Q, ids):
+    return ((X[ids].double() - Q[:, None, :].double()) ** 2).sum(-1).sqrt()
 
 
 def serve_load(dl, torch, idx, Qpool, reqs, rate, form, workspace, slots, max_batch):
@@ -228,10 +266,11 @@ def beta_grid_run(run, beta0):
 
 
 def precision_bench(dl, torch, name, steps, warmup, ks):
-    """A precision-form workload (d = 960 Beta-copula set, or the n = 10^7
-    normalised mixture): the index is built once (timed), then for each k and
-    form the query set is answered `steps` times per beta of the grid, with
-    recall@k against exact ground truth."""
+    """A workload's beta grid for the three forms of the headline (d = 960
+    Beta-copula set, the n = 10^7 normalised mixture or the SIFT-shaped set):
+    each form's index is built once (timed), then for each k the query set is
+    answered `steps` times per beta of the grid, with recall@k and the overall
+    ratio against exact k-NN."""
     import synth
     cfg = synth.config(name)
     dev = torch.device("cuda:0")
@@ -240,34 +279,31 @@ def precision_bench(dl, torch, name, steps, warmup, ks):
     Q = synth.make_queries(cfg, device=dev)
     A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
     sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
-    torch.cuda.synchronize()
-    idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
-    idx.free()
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
-    build_s = time.perf_counter() - tb
     out = {"workload": name, "n": cfg.n, "d": cfg.d, "nq": cfg.nq, "beta0": cfg.beta, "L": cfg.L, "K": cfg.K,
-           "N_r": cfg.N_r, "build_s": build_s, "build_mpts_s": cfg.n / build_s / 1e6,
-           "build_note": "build includes a BF16 copy of X", "results": []}
+           "N_r": cfg.N_r, "results": [], "builds": {}}
     chunk = max(1, int(2e9 // (cfg.n * 4)))
-    for k in ks:
-        log(f"[{name}] ground truth k={k}")
-        kth = ground_truth_kth(X, Q, k, chunk=chunk)
-        for form in ("fp32", "bf16"):
-            prec = dl.BF16_RERANK if form == "bf16" else dl.FP32
-
+    refs = {k: knn_dists(X, Q, k, chunk) for k in ks}
+    for form, f in FORMS.items():
+        prec = dl.BF16_RERANK if form == "bf16_rerank" else dl.FP32
+        dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, **f["build"]).free()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, **f["build"])
+        build_s = time.perf_counter() - tb
+        out["builds"][form] = {"build_s": build_s, "build_mpts_s": cfg.n / build_s / 1e6}
+        for k in ks:
             def run(beta):
                 for _ in range(warmup):
-                    idx.query(Q, k, cfg.c, beta, precision=prec)
+                    idx.query(Q, k, cfg.c, beta, precision=prec, **f["query"])
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for _ in range(steps):
-                    ids, _ = idx.query(Q, k, cfg.c, beta, precision=prec)
+                    ids, _ = idx.query(Q, k, cfg.c, beta, precision=prec, **f["query"])
                 torch.cuda.synchronize()
                 dt = (time.perf_counter() - t0) / steps
-                rec = recall_at_k(X, Q, ids, k, kth)
-                log(f"[{name}] k={k} {form} beta={beta}: {cfg.nq / dt:.0f} q/s, recall@{k} {rec:.4f}")
+                rec, rat = quality(exact_dists(X, Q, ids), refs[k])
+                log(f"[{name}] k={k} {form} beta={beta}: {cfg.nq / dt:.0f} q/s, recall@{k} {rec:.4f}, "
+                    f"ratio {rat:.6f}")
                 return cfg.nq / dt, rec
 
             r = beta_grid_run(run, cfg.beta)
@@ -275,15 +311,15 @@ def precision_bench(dl, torch, name, steps, warmup, ks):
             best = r["at_recall_0.9"]
             if best is not None:
                 dl.profile_enable(True, reset=True)
-                idx.query(Q, k, cfg.c, best["beta"], precision=prec)
+                idx.query(Q, k, cfg.c, best["beta"], precision=prec, **f["query"])
                 torch.cuda.synchronize()
                 dl.profile_enable(False, reset=False)
-                r["kernels_at_best"] = {name: {"launches": v["launches"], "total_ms": v["ms"]}
-                                        for name, v in dl.profile_read().items() if v["launches"]}
+                r["kernels_at_best"] = {kn: {"launches": v["launches"], "total_ms": v["ms"]}
+                                        for kn, v in dl.profile_read().items() if v["launches"]}
                 log(f"[{name}] k={k} {form} kernels at beta={best['beta']}: " +
                     ", ".join(f"{kn} {kv['total_ms']:.1f} ms" for kn, kv in r["kernels_at_best"].items()))
             out["results"].append(r)
-    idx.free()
+        idx.free()
     del X, Q
     torch.cuda.empty_cache()
     return out
@@ -390,25 +426,178 @@ def next_rows_bench(dl, torch, steps, warmup):
     return out
 
 
+def timed_steps(dl, torch, X, Q, cfg, k, beta, A, sample, form, steps, stream):
+    """`steps` whole steps (build the index, answer the query batch) between
+    two events on the launch stream; returns ms, summed build seconds, the
+    last answers and the kernel totals of these steps."""
+    f = FORMS[form]
+    prec = dl.BF16_RERANK if form == "bf16_rerank" else dl.FP32
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    dl.profile_enable(True, reset=True)
+    e0.record(stream)
+    bsum = 0.0
+    last = None
+    for _ in range(steps):
+        tb = time.perf_counter()
+        ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, **f["build"])
+        bsum += time.perf_counter() - tb
+        last = ix.query(Q, k, cfg.c, beta, precision=prec, **f["query"])
+        ix.free()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dl.profile_enable(False, reset=False)
+    prof = {name: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "total_ms": v["ms"]}
+            for name, v in dl.profile_read().items() if v["launches"]}
+    return e0.elapsed_time(e1), bsum, last, prof
+
+
+def roofline(kernels, steps, cfg, nq, k, beta, n, d, probe_rate):
+    """Roofline of the kernel with the largest total time (achieved =
+    algorithmic work of one average launch / its average duration)."""
+    LK, L = cfg.L * cfg.K, cfg.L
+    dom = max(kernels, key=lambda s: kernels[s]["total_ms"])
+    avg_s = kernels[dom]["avg_ms"] / 1e3
+    per_launch_q = nq / (kernels[dom]["launches"] / steps)
+    if dom == "range_filter":
+        # per (query, point): L*K bound terms, each 3 lane operations (clamp,
+        # difference, fused square-add), and one minimum per tree
+        ops = (3 * LK + L) * n * per_launch_q
+        r = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+             "work": f"{3 * LK + L} lane-ops per (query, point) = {LK} bound terms x 3 + {L} tree minima; "
+                     f"{n} points x {per_launch_q:.0f} queries per launch",
+             "peak_note": "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU op per 4 clocks; packed "
+                          "FP32 not used)"}
+        if probe_rate:
+            r["peak_measured"] = probe_rate / 1e12
+            r["frac_measured"] = r["achieved"] / r["peak_measured"]
+            r["peak_measured_note"] = ("detlsh_probe_valu: the filter's own bound arithmetic (clamp, difference, "
+                                       "fused square-add, tree minima) with nothing else, on this GPU in this run")
+    elif dom == "dense_verify":
+        fl = 2.0 * n * d * per_launch_q
+        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s",
+             "work": "2 n d flops per query (dense-equivalent)"}
+    elif dom == "project_encode":
+        fl = 2.0 * n * LK * d
+        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s",
+             "work": "2 L K d flops per point"}
+    else:
+        r = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    r["frac"] = (r["achieved"] / r["peak"]) if r["achieved"] else None
+    r["traffic"] = counted_traffic(dom)
+    r["kernel"] = dom
+    return r
+
+
+# ---------------------------------------------------------------------------
+# the oracle on the host cores
+# ---------------------------------------------------------------------------
+
+_ORC = {}
+
+
+def _oracle_one(qi):
+    from oracle import detlsh_oracle as O
+    w = _ORC
+    qp = O.project(w["Q"][qi:qi + 1], w["A"])[0]
+    r = O.query_magic(w["X"], w["Q"][qi], qp, w["codes"], w["B"], w["L"], w["K"], w["k"], w["beta"])
+    return qi, r.ids, r.dists
+
+
+def cpu_baseline(X, Q, A, sample, cfg, k, beta, idx, build_rows, one_core_q, all_core_q, workers):
+    """The FP64 oracle on the host cores, on bounded samples of the headline
+    workload: its index build over the first `build_rows` points (one thread),
+    scaled linearly to n; its queries on the GPU index's own encoding (the
+    exported codes and breakpoints), `one_core_q` of them on one thread and
+    `all_core_q` (a fixed subset: the first ones) over `workers` processes of
+    one thread each.  Returns the baseline (queries/s of the whole step) and
+    the oracle's answers to the subset."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import detlsh_oracle as O
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.build_index(X[:build_rows], A, sample[sample < build_rows], cfg.L, cfg.K, cfg.N_r)
+        t_build = (time.perf_counter() - t0) * (X.shape[0] / build_rows)
+    ex = idx.export()
+    _ORC.update(X=np.asarray(X, np.float64), Q=np.asarray(Q, np.float64), A=A, codes=ex["codes"],
+                B=ex["B"].astype(np.float64), L=cfg.L, K=cfg.K, k=k, beta=beta)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for qi in range(one_core_q):
+            _oracle_one(qi)
+        t_q1 = (time.perf_counter() - t0) / one_core_q
+    answers = {}
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        with mp.get_context("fork").Pool(workers) as pool:
+            for qi, ids, dists in pool.imap_unordered(_oracle_one, range(all_core_q)):
+                answers[qi] = (ids, dists)
+    t_qall = (time.perf_counter() - t0) / all_core_q
+    _ORC.clear()
+    nq = Q.shape[0]
+    one = nq / (t_build + nq * t_q1)
+    allc = nq / (t_build / 1.0 + nq * t_qall)
+    return {"value": allc, "unit": "queries/s", "cores": workers, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle on the same workload: build over the first {build_rows} of "
+                       f"{X.shape[0]} points on one thread ({t_build * build_rows / X.shape[0]:.2f} s, scaled "
+                       f"linearly to n: {t_build:.1f} s); queries on the GPU index's encoding, the first "
+                       f"{all_core_q} of the {nq} over {workers} one-thread processes "
+                       f"({t_qall * 1e3:.0f} ms per query of wall time) and {one_core_q} on one thread "
+                       f"({t_q1 * 1e3:.0f} ms each); whole step = build + {nq} queries"),
+            "one_core": {"value": one, "cores": 1, "query_ms": t_q1 * 1e3},
+            "build_s_scaled": t_build, "query_ms_wall_all_cores": t_qall * 1e3,
+            "os_cpu_count": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "blas_threads": 1}, answers
+
+
+def c2_block(dl, torch, steps, warmup, stream):
+    """The SIFT-shaped workload (n = 10^6, d = 128, 10,000 queries, k = 10,
+    beta = 0.1): whole steps of the three forms, as an extra key."""
+    import synth
+    cfg = synth.config("C2")
+    log("[c2] generating the SIFT-shaped set")
+    X = torch.from_numpy(synth.make_data(cfg)).cuda()
+    Q = torch.from_numpy(synth.make_queries(cfg)).cuda()
+    A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
+    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
+    ref = knn_dists(X, Q, 10, 1000)
+    out = {"workload": "SIFT-shaped n=1,000,000 d=128, 10,000 queries, k=10 c=1.5 beta=0.1", "forms": {}}
+    for form in FORMS:
+        for _ in range(warmup):
+            timed_steps(dl, torch, X, Q, cfg, 10, cfg.beta, A, sample, form, 1, stream)
+        ms, bs, (ids, d), prof = timed_steps(dl, torch, X, Q, cfg, 10, cfg.beta, A, sample, form, steps, stream)
+        rec, rat = quality(exact_dists(X, Q, ids), ref)
+        out["forms"][form] = {"value": cfg.nq * steps / (ms / 1e3), "ms_per_step": ms / steps,
+                              "build_ms": bs * 1e3 / steps, "recall_at_10": rec, "overall_ratio": rat,
+                              "filter_avg_ms": prof.get("range_filter", {}).get("avg_ms")}
+        log(f"[c2] {form}: {out['forms'][form]['value']:.0f} q/s whole step, recall {rec:.4f}, ratio {rat:.5f}")
+    del X, Q
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--beta", type=float, default=None)
-    ap.add_argument("--cpu-queries", type=int, default=6)
+    ap.add_argument("--beta", type=float, default=None, help="fix beta instead of taking it from the grid")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-recall", action="store_true")
-    ap.add_argument("--no-bf16", action="store_true", help="skip timing the BF16+rerank form")
+    ap.add_argument("--no-c2", action="store_true", help="skip the SIFT-shaped extra block")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-form block")
+    ap.add_argument("--forms", default=",".join(FORMS), help="comma-separated subset of " + ",".join(FORMS))
     ap.add_argument("--serve-requests", type=int, default=1500)
     ap.add_argument("--serve-only", action="store_true", help="print only the serving-form block")
-    ap.add_argument("--beta-sweep", action="store_true",
-                    help="also run the beta grid for QPS at recall@10 >= 0.9 (query only, both forms)")
+    ap.add_argument("--cpu-one", type=int, default=2, help="oracle queries timed on one thread")
+    ap.add_argument("--cpu-all", type=int, default=32, help="oracle queries over the worker processes")
+    ap.add_argument("--cpu-build-rows", type=int, default=500_000)
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "next"], default=None,
-                    help="print only the named workload's beta grid for both forms (c2: SIFT-shaped, k = 10 "
+                    help="print only the named workload's beta grid for two forms (c2: SIFT-shaped, k = 10 "
                          "and 50; c3: d=960 copula; c4: n=10^7 mixture, k = 10 and 100; next: the extra rows)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (counter calibration)")
@@ -435,19 +624,8 @@ def main():
         print(json.dumps(precision_bench(dl, torch, name, args.steps, args.warmup, ks)), flush=True)
         return
 
-    cfg = synth.config("C2")
-    nq = args.nq or cfg.nq
-    k = args.k
-    beta = cfg.beta if args.beta is None else args.beta
-    log(f"[bench] generating C2: n={cfg.n} d={cfg.d} nq={nq}")
-    X_host = synth.make_data(cfg)
-    Q_host = synth.make_queries(cfg, nq=nq)
-    A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
-    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    X = torch.from_numpy(X_host).to(dev)
-    Q = torch.from_numpy(Q_host).to(dev)
     stream = torch.cuda.current_stream()
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -458,167 +636,139 @@ def main():
         log("[bench] calibration copy: 1 GiB read + 1 GiB written")
         del src, dst
 
-    # both forms build the BF16 copy of X: the FP32 form screens with BF16
-    # products against a bound widened by their rounding (exact FP32 results)
-    def step(bf16=False):
-        idx = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
-        ids, dists = idx.query(Q, k, cfg.c, beta, precision=dl.BF16_RERANK if bf16 else dl.FP32)
-        return idx, ids, dists
+    # headline: the n = 10^7 normalised mixture (the largest single-GPU workload)
+    cfg = synth.config("C4")
+    k = args.k
+    forms = [f for f in args.forms.split(",") if f]
+    log(f"[bench] generating the normalised mixture on the GPU: n={cfg.n} d={cfg.d} nq={cfg.nq}")
+    X = synth.make_data(cfg, device=dev)
+    Q = synth.make_queries(cfg, device=dev)
+    A = synth.projection_matrix(cfg.L, cfg.K, cfg.d, cfg.index_seed)
+    sample = synth.sample_ids(cfg.n, cfg.n_s, cfg.index_seed)
+    n, d, nq = cfg.n, cfg.d, cfg.nq
+    log("[bench] exact k-NN distances for recall and overall ratio")
+    ref = knn_dists(X, Q, k, 200)
 
-    def timed(bf16, steps):
-        """`steps` whole steps between two events on the launch stream."""
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        bsum = 0.0
-        last = None
-        for _ in range(steps):
-            tb = time.perf_counter()
-            ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
-            bsum += time.perf_counter() - tb
-            last = ix.query(Q, k, cfg.c, beta, precision=dl.BF16_RERANK if bf16 else dl.FP32)
-            ix.free()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1), bsum, last
+    # beta from the grid, with the headline form (plain FP32)
+    grid = None
+    if args.beta is None:
+        ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample,
+                            **FORMS["fp32"]["build"])
 
-    log(f"[bench] warmup x{args.warmup}")
-    idx = ids = dists = None
-    for _ in range(args.warmup):
-        if idx is not None:
-            idx.free()
-        idx, ids, dists = step()
-    torch.cuda.synchronize()
-    recall = None
-    if not args.no_recall:
-        log("[bench] ground truth for recall@k")
-        if ids is None:
-            idx, ids, dists = step()
-        kth = ground_truth_kth(X, Q, k)
-        recall = recall_at_k(X, Q, ids, k, kth)
-        log(f"[bench] recall@{k} = {recall:.4f}")
-    if idx is not None:
-        idx.free()
+        def run(b):
+            ix.query(Q[:512], k, cfg.c, b, **FORMS["fp32"]["query"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids_b, _ = ix.query(Q, k, cfg.c, b, **FORMS["fp32"]["query"])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec_b, _ = quality(exact_dists(X, Q, ids_b), ref)
+            log(f"[bench] grid beta={b}: {nq / dt:.0f} q/s (query only), recall@{k} {rec_b:.4f}")
+            return nq / dt, rec_b
 
-    dl.profile_enable(True, reset=True)
-    log(f"[bench] timed x{args.steps}")
-    t0 = time.perf_counter()
-    ms_total, build_s, _ = timed(False, args.steps)
-    wall = time.perf_counter() - t0
-    dl.profile_enable(False, reset=False)
-    prof = dl.profile_read()
-    ms_per_step = ms_total / args.steps
-    value = nq * args.steps / (ms_total / 1e3)
-    build_ms = build_s * 1e3 / args.steps
-    query_ms = ms_per_step - build_ms
-
-    # roofline of the dominant kernel (largest total time in the timed region)
-    n, LK, L, K, d = cfg.n, cfg.L * cfg.K, cfg.L, cfg.K, cfg.d
-    N_S = k + math.ceil(beta * n)
-    kernels = {}
-    for name, v in prof.items():
-        if v["launches"]:
-            kernels[name] = {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "total_ms": v["ms"]}
-    dom = max(kernels, key=lambda s: kernels[s]["total_ms"])
-    avg_s = kernels[dom]["avg_ms"] / 1e3
-    launches_per_step = kernels[dom]["launches"] / args.steps
-    if dom == "range_filter":
-        # VALU lane-ops per (query, point): 3 per (tree, dim) + 1 per tree
-        ops = (3 * LK + L) * n * (nq / launches_per_step)
-        roof = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": VALU_PEAK_TOPS, "unit": "Tops/s"}
-    elif dom == "verify_topk":
-        byts = N_S * d * 4 * (nq / launches_per_step)
-        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    elif dom == "dense_verify":
-        fl = 2.0 * n * d * (nq / launches_per_step)
-        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s"}
-    elif dom == "project_encode":
-        fl = 2.0 * n * LK * d
-        roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s"}
+        grid = beta_grid_run(run, cfg.beta)
+        ix.free()
+        beta = grid["at_recall_0.9"]["beta"] if grid["at_recall_0.9"] else 0.5
     else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["frac"] = (roof["achieved"] / roof["peak"]) if roof["achieved"] else None
-    roof["traffic"] = counted_traffic(dom)
-    roof["kernel"] = dom
+        beta = args.beta
 
-    bf = None
-    if not args.no_bf16:
-        log(f"[bench] BF16+rerank form: warmup x{args.warmup}, timed x{args.steps}")
+    probe = None
+    try:
+        probe, probe_ms = dl.probe_valu()
+        log(f"[bench] measured VALU issue rate of the bound arithmetic: {probe / 1e12:.2f} T lane-ops/s "
+            f"({probe_ms:.2f} ms)")
+    except Exception as exc:   # the probe is context for the roofline, not the measurement
+        log(f"[bench] VALU probe failed: {exc}")
+
+    results = {}
+    answers = {}
+    for form in forms:
+        log(f"[bench] {form}: warmup x{args.warmup}, timed x{args.steps} (beta={beta})")
         for _ in range(args.warmup):
-            ixb, ids_b, _ = step(True)
-            ixb.free()
-        ms_b, bs_b, (ids_b, _) = timed(True, args.steps)
-        rec_b = recall_at_k(X, Q, ids_b, k, kth) if recall is not None else None
-        bf = {"value": nq * args.steps / (ms_b / 1e3), "unit": "queries/s", "ms_per_step": ms_b / args.steps,
-              "build_ms": bs_b * 1e3 / args.steps, "recall_at_k": rec_b, "rerank_mult": 4,
-              "dtype": "bf16 products, fp32 accumulate and rerank"}
-        log(f"[bench] BF16+rerank: {bf['value']:.0f} q/s, recall {rec_b}")
-
-    sweep = None
-    if args.beta_sweep and recall is not None:
-        ixs = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample, keep_bf16=True)
-        sweep = {}
-        for form in ("fp32", "bf16"):
-            prec = dl.BF16_RERANK if form == "bf16" else dl.FP32
-
-            def run(b):
-                ixs.query(Q, k, cfg.c, b, precision=prec)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                ids_s, _ = ixs.query(Q, k, cfg.c, b, precision=prec)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                rec = recall_at_k(X, Q, ids_s, k, kth)
-                log(f"[bench] sweep {form} beta={b}: {nq / dt:.0f} q/s, recall {rec:.4f}")
-                return nq / dt, rec
-
-            sweep[form] = beta_grid_run(run, beta)
-        ixs.free()
-
-    serving = None
-    if not args.no_serve:
-        del X, Q
-        torch.cuda.empty_cache()
-        serving = serve_bench(dl, torch, args.serve_requests)
+            timed_steps(dl, torch, X, Q, cfg, k, beta, A, sample, form, 1, stream)
+        t0 = time.perf_counter()
+        ms, bs, (ids, dists), prof = timed_steps(dl, torch, X, Q, cfg, k, beta, A, sample, form, args.steps, stream)
+        wall = time.perf_counter() - t0
+        ms_step = ms / args.steps
+        build_ms = bs * 1e3 / args.steps
+        rec, rat = quality(exact_dists(X, Q, ids), ref)
+        answers[form] = (ids, dists)
+        results[form] = {"value": nq / (ms_step / 1e3), "ms_per_step": ms_step, "build_ms": build_ms,
+                         "build_mpts_s": n / (build_ms / 1e3) / 1e6,
+                         "query_qps": nq / ((ms_step - build_ms) / 1e3) if ms_step > build_ms else None,
+                         "recall_at_k": rec, "overall_ratio": rat, "wall_s": wall, "kernels": prof,
+                         "dtype": FORMS[form]["dtype"], "what": FORMS[form]["what"]}
+        log(f"[bench] {form}: {results[form]['value']:.0f} q/s whole step ({ms_step:.1f} ms; build "
+            f"{build_ms:.1f} ms), recall@{k} {rec:.4f}, overall ratio {rat:.6f}")
+    head = "fp32" if "fp32" in results else forms[0]
+    hr = results[head]
+    roof = roofline(hr["kernels"], args.steps, cfg, nq, k, beta, n, d, probe)
 
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] oracle on host cores ({args.cpu_queries} queries)")
-        cpu = cpu_baseline(X_host, Q_host, A, sample, cfg, k, beta, nq, args.cpu_queries)
+        log("[bench] the oracle on the host cores")
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+        ix = dl.build_index(X, cfg.L, cfg.K, cfg.N_r, cfg.sample_frac, A=A, sample_ids=sample,
+                            **FORMS["fp32"]["build"])
+        Xh = X.cpu().numpy()
+        Qh = Q.cpu().numpy()
+        cpu, orc = cpu_baseline(Xh, Qh, A, sample, cfg, k, beta, ix, min(args.cpu_build_rows, n), args.cpu_one,
+                                args.cpu_all, workers)
+        ix.free()
+        del Xh
+        # each form's error against the FP64 oracle on the subset
+        sub = sorted(orc)
+        ref_o = torch.tensor(np.stack([orc[q][1] for q in sub]), dtype=torch.float64, device=dev)
+        for form, (ids, dists) in answers.items():
+            got = exact_dists(X[:], Q[sub], ids[sub])
+            r_o, q_o = quality(got, ref_o)
+            same = float(np.mean([np.array_equal(ids[q].cpu().numpy(), orc[q][0]) for q in sub]))
+            results[form]["against_oracle"] = {"queries": len(sub), "recall_at_k": r_o, "overall_ratio": q_o,
+                                               "identical_id_lists": same}
+            log(f"[bench] {form} against the oracle on {len(sub)} queries: recall {r_o:.4f}, ratio {q_o:.6f}, "
+                f"identical lists {same:.3f}")
+
+    c2 = None
+    if not args.no_c2:
+        del X, Q
+        torch.cuda.empty_cache()
+        c2 = c2_block(dl, torch, max(2, args.steps // 4), 1, stream)
+
+    serving = None
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        serving = serve_bench(dl, torch, args.serve_requests)
 
     out = {
         "metric": "QPS @ recall@10>=0.9 (plain FP32 vs BF16+rerank); build Mpts/s; p50/p99 latency",
-        "value": value,
+        "value": hr["value"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": hr["dtype"],
         "data": "synthetic",
-        "config": {"workload": "SIFT-shaped n=1,000,000 d=128, 10,000 queries, k=10 c=1.5 beta=0.1, "
-                               "L=4 K=16 N_r=256, 1% sample; step = build + query batch",
-                   "n": n, "d": d, "nq": nq, "k": k, "beta": beta, "L": L, "K": K, "N_r": cfg.N_r,
-                   "precision": "fp32",
-                   "verification": "FP32 direct distances rank the members of S that survive a BF16-product "
-                                   "screen whose bound is widened by the BF16 rounding (results identical to "
-                                   "an all-FP32 pass)"},
-        "recall_at_k": recall,
-        "query_qps": nq / (query_ms / 1e3) if query_ms > 0 else None,
-        "build_mpts_s": n / (build_ms / 1e3) / 1e6,
-        "build_ms": build_ms,
-        "query_ms": query_ms,
-        "wall_s": wall,
-        "kernels": kernels,
+        "config": {"workload": (f"normalised 1,024-component Gaussian mixture n=10,000,000 d=96 (unit vectors), "
+                                f"10,000 queries, k={k} c=1.5 beta={beta} (smallest grid beta with recall@10 >= "
+                                f"0.9), L=4 K=16 N_r=256, 1% sample; step = build + query batch; form {head}"),
+                   "n": n, "d": d, "nq": nq, "k": k, "beta": beta, "L": cfg.L, "K": cfg.K, "N_r": cfg.N_r,
+                   "form": head},
+        "recall_at_k": hr["recall_at_k"],
+        "overall_ratio": hr["overall_ratio"],
+        "query_qps": hr["query_qps"],
+        "build_mpts_s": hr["build_mpts_s"],
+        "build_ms": hr["build_ms"],
         "roofline": roof,
         "cpu_baseline": cpu,
-        "bf16_rerank": bf,
+        "forms": {f: {kk: v for kk, v in r.items() if kk != "kernels"} for f, r in results.items()},
+        "kernels": {f: r["kernels"] for f, r in results.items()},
+        "beta_grid": grid,
+        "c2": c2,
         "serving": serving,
-        "beta_sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 

@@ -438,6 +438,20 @@ detlsh_status detlsh_profile_enable(int32_t on, int32_t reset);
 detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double* total_ms,
                                   int32_t max, int32_t* count);
 
+/*
+ * Measured issue rate of the range filter's bound arithmetic on the current
+ * device: `lanes` synthetic cells (a multiple of 256), each against `nq`
+ * projected queries with the filter's own per-(tree, dimension) sequence
+ * (median-of-three clamp, subtraction, fused multiply-add: 3 operations) and
+ * one minimum per tree, at L = 4, K = 16 (196 lane operations per cell and
+ * query; the lower bounds of Sec. 4.3, readings R5 and R6).  Three launches
+ * on the null stream; the fastest of the last two is reported as lane
+ * operations per second in *lane_ops_per_s and its duration in *ms (may be
+ * NULL).  Synchronous; allocates from the device cache.  EINVAL on bad
+ * arguments, EDEVICE on a HIP error.
+ */
+detlsh_status detlsh_probe_valu(int32_t nq, int64_t lanes, double* lane_ops_per_s, double* ms);
+
 void detlsh_free(detlsh_index idx);
 
 /*

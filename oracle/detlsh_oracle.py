@@ -33,6 +33,7 @@ Everything is float64 NumPy.  Every function follows one passage of the paper:
                           projection that replaces the Gaussian hashes
   epsilon, beta_theory    Lemma 3 / Eq. 2
   brute_force_knn         Def. 2 with o_i* exact; ties broken by id (R13)
+  recall, overall_ratio   the two quality measures of Sec. 6.1 (ties: R16)
 
 Parity pins for every function live in ``tests/test_oracle_*.py``.
 """
@@ -376,6 +377,30 @@ def brute_force_knn(X, q, k):
     """Exact k nearest neighbours of q (Def. 2 with c = 1), ties by id."""
     d2 = sq_dists(X, q)
     return top_k(np.arange(len(d2)), d2, k)
+
+
+def recall(ret_d, ref_d) -> float:
+    """Recall of one answer (Sec. 6.1, Evaluation Measures): |R cap R*| / k,
+    with R* the reference answer (exact k-NN, or another method's answer)
+    given by its k distances.  Reading R16: distances may tie, so a returned
+    point counts as in R* when its distance is at most the k-th reference
+    distance; the count is capped at k."""
+    ret_d = np.asarray(ret_d, np.float64)
+    ref_d = np.asarray(ref_d, np.float64)
+    k = len(ref_d)
+    hit = int(np.sum(ret_d <= ref_d[-1]))
+    return min(hit, k) / k
+
+
+def overall_ratio(ret_d, ref_d) -> float:
+    """Overall ratio of one answer (Sec. 6.1): the mean over ranks i of
+    ||q, o_i|| / ||q, o_i*||, both lists ascending; a 0/0 term counts as 1
+    (reading R16)."""
+    ret_d = np.asarray(ret_d, np.float64)
+    ref_d = np.asarray(ref_d, np.float64)
+    terms = np.where(ref_d > 0, ret_d / np.where(ref_d > 0, ref_d, 1.0),
+                     np.where(ret_d > 0, np.inf, 1.0))
+    return float(np.mean(terms))
 
 
 @dataclass

@@ -320,6 +320,16 @@ def profile_enable(on=True, reset=True):
     check(lib().detlsh_profile_enable(int(on), int(reset)))
 
 
+def probe_valu(nq=2048, lanes=256 * 1024 * 3):
+    """Measured lane operations per second of the range filter's bound
+    arithmetic (3 per tree and dimension plus 1 per tree, L = 4, K = 16) on the
+    current device, and the probe launch's duration in ms."""
+    rate = C.c_double()
+    ms = C.c_double()
+    check(lib().detlsh_probe_valu(int(nq), int(lanes), C.byref(rate), C.byref(ms)))
+    return rate.value, ms.value
+
+
 def profile_read() -> dict:
     names = (C.c_char_p * 32)()
     launches = (C.c_int64 * 32)()

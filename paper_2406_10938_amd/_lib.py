@@ -98,6 +98,7 @@ SIGNATURES = {
     "detlsh_server_wait": (C.c_int, [P, C.c_uint64, C.c_int64, C.POINTER(RequestInfo)]),
     "detlsh_server_cancel": (C.c_int, [P, C.c_uint64]),
     "detlsh_server_destroy": (None, [P]),
+    "detlsh_probe_valu": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "detlsh_free": (None, [P]),
     "detlsh_trim": (None, []),
     "detlsh_last_error": (C.c_char_p, []),

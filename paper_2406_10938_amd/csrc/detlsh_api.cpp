@@ -931,6 +931,43 @@ detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double*
     return DETLSH_OK;
 }
 
+detlsh_status detlsh_probe_valu(int32_t nq, int64_t lanes, double* lane_ops_per_s, double* ms) {
+    g_err.clear();
+    if (nq < 1 || lanes < 256 || lanes % 256 || !lane_ops_per_s)
+        return fail(DETLSH_EINVAL, "probe needs nq >= 1, lanes a positive multiple of 256 and an output");
+    int dev = 0;
+    HCHECK(hipGetDevice(&dev));
+    DevBuf qp, out;
+    HCHECK(pool_alloc(qp, (size_t)nq * 64 * 4, dev));
+    HCHECK(pool_alloc(out, (size_t)lanes * 4, dev));
+    std::vector<float> qh((size_t)nq * 64);
+    for (size_t i = 0; i < qh.size(); ++i) qh[i] = (float)((i * 2654435761u) % 65536u) * (1.0f / 16384.0f) - 2.0f;
+    HCHECK(hipMemcpy(qp.p, qh.data(), qh.size() * 4, hipMemcpyHostToDevice));
+    hipEvent_t e0, e1;
+    HCHECK(hipEventCreate(&e0));
+    HCHECK(hipEventCreate(&e1));
+    float best = 0.f;
+    hipError_t he = hipSuccess;
+    for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {   // first run warms up; the fastest counts
+        he = hipEventRecord(e0, nullptr);
+        if (he == hipSuccess) he = dl_launch_valu_probe(qp.as<float>(), nq, out.as<float>(), lanes, nullptr);
+        if (he == hipSuccess) he = hipEventRecord(e1, nullptr);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+        if (he == hipSuccess && rep > 0 && (best == 0.f || t < best)) best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    pool_give(qp, dev);
+    pool_give(out, dev);
+    HCHECK(he);
+    const double ops = (3.0 * 64 + 4) * (double)lanes * nq;
+    *lane_ops_per_s = ops / (best * 1e-3);
+    if (ms) *ms = best;
+    return DETLSH_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

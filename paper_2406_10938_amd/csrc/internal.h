@@ -144,6 +144,9 @@ struct QueryArgs {
 };
 
 bool dl_supported_lk(int L, int K);
+// Issue-rate probe of the range filter's bound arithmetic (L = 4, K = 16):
+// `lanes` (a multiple of 256) synthetic cells against nq projected queries.
+hipError_t dl_launch_valu_probe(const float* qp, int nq, float* out, int64_t lanes, hipStream_t st);
 size_t dl_verify_smem(int d);
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
 // leaf_of of one tree: out[perm[p]] = the leaf whose run holds position p.

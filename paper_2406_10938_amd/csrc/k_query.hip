@@ -1036,12 +1036,45 @@ struct ImplicitS {
     }
 };
 
+// Dimension from which the exact distances use compensated sums.
+constexpr int kCompensateD = 512;
+
+// One term (x - q)^2 added to a compensated sum (acc, cmp) (Neumaier's
+// variant of Kahan summation): the rounding error of the difference (TwoSum),
+// of the square (an FMA gives it exactly) and of the addition (Fast2Sum on the
+// larger operand) all go to cmp, so acc + cmp carries the FP32 sum of squared
+// differences to about one rounding of the exact value instead of d of them.
+// Contraction is off: every rounding step below is meant as written.
+__device__ __forceinline__ void comp_sq_add(float x, float q, float& acc, float& cmp) {
+#pragma clang fp contract(off)
+    const float s = x - q;
+    const float bb = s - x;
+    const float de = (x - (s - bb)) + (-q - bb);   // s + de == x - q exactly
+    const float p = s * s;
+    const float pe = fmaf(s, s, -p);               // s * s == p + pe exactly
+    const float t = acc + p;
+    const float e = (fabsf(acc) >= fabsf(p)) ? (acc - t) + p : (p - t) + acc;   // acc + p == t + e
+    acc = t;
+    cmp += e + fmaf(2.0f * s, de, pe);             // (s + de)^2 - p up to de^2
+}
+
+// (a, ca) += (b, cb) for the lane reduction of compensated sums.
+__device__ __forceinline__ void comp_merge(float& a, float& ca, float b, float cb) {
+#pragma clang fp contract(off)
+    const float t = a + b;
+    const float bb = t - a;
+    const float e = (a - (t - bb)) + (b - bb);     // a + b == t + e exactly
+    a = t;
+    ca = (ca + cb) + e;
+}
+
 // Exact FP32 squared distances (direct differences, half a wave per row, R
 // rows in flight) of the rows listed for one query, written as 64-bit keys
-// (distance bits, id) to buf.
+// (distance bits, id) to buf.  For d >= kCompensateD (COMP) every sum is
+// compensated (comp_sq_add, comp_merge) before its one final rounding.
 // With an implicit S (use_ims), non-members get the key (+inf, id) without
 // a gather.
-template <bool ALIGNED>
+template <bool ALIGNED, bool COMP>
 __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
                                             const int32_t* __restrict__ ids, int64_t m, uint64_t* __restrict__ buf,
                                             bool use_ims = false, ImplicitS ims = ImplicitS()) {
@@ -1050,7 +1083,7 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
     constexpr int R = 8;
     for (int64_t s0 = (int64_t)hw * R; s0 < m; s0 += 8 * R) {
         int64_t id[R];
-        float acc[R];
+        float acc[R], cmp[R];
         bool skip[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1065,6 +1098,7 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
                 }
             }
             acc[r] = 0.0f;
+            cmp[r] = 0.0f;
         }
         for (int c = 4 * hl; c < d; c += 128) {
             if (ALIGNED && c + 4 <= d) {
@@ -1076,26 +1110,50 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
                 const float q0v = sq[c], q1v = sq[c + 1], q2v = sq[c + 2], q3v = sq[c + 3];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    float df = v[r].x - q0v; acc[r] = fmaf(df, df, acc[r]);
-                    df = v[r].y - q1v;       acc[r] = fmaf(df, df, acc[r]);
-                    df = v[r].z - q2v;       acc[r] = fmaf(df, df, acc[r]);
-                    df = v[r].w - q3v;       acc[r] = fmaf(df, df, acc[r]);
+                    if constexpr (COMP) {
+                        comp_sq_add(v[r].x, q0v, acc[r], cmp[r]);
+                        comp_sq_add(v[r].y, q1v, acc[r], cmp[r]);
+                        comp_sq_add(v[r].z, q2v, acc[r], cmp[r]);
+                        comp_sq_add(v[r].w, q3v, acc[r], cmp[r]);
+                    } else {
+                        float df = v[r].x - q0v; acc[r] = fmaf(df, df, acc[r]);
+                        df = v[r].y - q1v;       acc[r] = fmaf(df, df, acc[r]);
+                        df = v[r].z - q2v;       acc[r] = fmaf(df, df, acc[r]);
+                        df = v[r].w - q3v;       acc[r] = fmaf(df, df, acc[r]);
+                    }
                 }
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (id[r] < 0) continue;
                     const float* x = X + id[r] * d;
-                    for (int u = 0; u < 4; ++u)
-                        if (c + u < d) { const float df = x[c + u] - sq[c + u]; acc[r] = fmaf(df, df, acc[r]); }
+                    for (int u = 0; u < 4; ++u) {
+                        if (c + u >= d) continue;
+                        if constexpr (COMP) {
+                            comp_sq_add(x[c + u], sq[c + u], acc[r], cmp[r]);
+                        } else {
+                            const float df = x[c + u] - sq[c + u];
+                            acc[r] = fmaf(df, df, acc[r]);
+                        }
+                    }
                 }
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float a2 = acc[r];
+            if constexpr (COMP) {
+                float c2 = cmp[r];
 #pragma unroll
-            for (int o2 = 16; o2 > 0; o2 >>= 1) a2 += __shfl_xor(a2, o2, 32);
+                for (int o2 = 16; o2 > 0; o2 >>= 1) {
+                    const float b2 = __shfl_xor(a2, o2, 32), cb2 = __shfl_xor(c2, o2, 32);
+                    comp_merge(a2, c2, b2, cb2);
+                }
+                a2 = a2 + c2;
+            } else {
+#pragma unroll
+                for (int o2 = 16; o2 > 0; o2 >>= 1) a2 += __shfl_xor(a2, o2, 32);
+            }
             if (hl == 0 && id[r] >= 0 && !skip[r])
                 buf[s0 + r] = ((uint64_t)__float_as_uint(a2) << 32) | (uint64_t)(uint32_t)id[r];
         }
@@ -1111,7 +1169,7 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
 //   tau != null     : write tau[t] = squared distance of the k-th smallest
 // Queries are processed when status[t] == want.  When `sv_check`, a list with
 // more than `sv_cap` or fewer than k entries marks the query status 2 instead.
-template <bool ALIGNED>
+template <bool ALIGNED, bool COMP>
 __global__ __launch_bounds__(256) void gather_topk_kernel(
     const float* __restrict__ X, int d, const float* __restrict__ Q, int64_t q0,
     const int32_t* __restrict__ list, int64_t ld_list, const uint32_t* __restrict__ counts, int64_t use_max,
@@ -1149,7 +1207,7 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
         ims.istop = stops[t];
         ims.thr = thrs[t];
     }
-    gather_keys<ALIGNED>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf, implicit_s != 0, ims);
+    gather_keys<ALIGNED, COMP>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf, implicit_s != 0, ims);
     if (keys_only) return;
     topk_u64(buf, m, k, sh);
     if (tau) {
@@ -2062,6 +2120,45 @@ hipError_t dl_launch_pack_sample(const uint8_t* codes, int64_t n, int L, int K, 
     return hipGetLastError();
 }
 
+namespace {
+
+// Issue-rate probe of the range filter's arithmetic: one lane per synthetic
+// cell (lo <= hi per dimension, from a hash of the lane and dimension), every
+// query of `qp` (nq x 64, read as scalars like the filter's) through the same
+// cell_lbs<4, 16> the filter uses: 3 VALU operations per (tree, dimension) and
+// one per tree.  The per-lane minimum over queries is written so that nothing
+// is dead.
+__global__ __launch_bounds__(256, 3) void valu_probe_kernel(const float* __restrict__ qp, int nq,
+                                                            float* __restrict__ out)
+{
+    float lo[64], hi[64];
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < 64; ++e) {
+        const uint32_t h = (g * 2654435761u) ^ (uint32_t)(e * 40503u);
+        const float a = (float)(h & 0xffffu) * (1.0f / 16384.0f) - 2.0f;
+        lo[e] = a;
+        hi[e] = a + (float)((h >> 16) & 0xffu) * (1.0f / 1024.0f);
+    }
+#pragma unroll
+    for (int e = 0; e < 64; ++e) asm volatile("" ::"v"(lo[e]), "v"(hi[e]));
+    float best = INFINITY;
+#pragma unroll 1
+    for (int t = 0; t < nq; ++t) {
+        float lb[4];
+        best = fminf(best, cell_lbs<4, 16>(qp + (int64_t)t * 64, lo, hi, lb));
+    }
+    out[g] = best;
+}
+
+}  // namespace
+
+hipError_t dl_launch_valu_probe(const float* qp, int nq, float* out, int64_t lanes, hipStream_t st) {
+    if (lanes % 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(valu_probe_kernel, dim3((unsigned)(lanes / 256)), dim3(256), 0, st, qp, nq, out);
+    return hipGetLastError();
+}
+
 bool dl_supported_lk(int L, int K) {
     switch (L * 100 + K) {
         case 104: case 204: case 404: case 804: case 108: case 208: case 408: case 808:
@@ -2101,12 +2198,12 @@ hipError_t dl_launch_select(const QueryArgs& a, hipStream_t st) {
     return hipSuccess;
 }
 
-template <bool AL>
+template <bool AL, bool COMP>
 hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
                             int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
                             int keys_only, bool members) {
     const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
-    hipLaunchKernelGGL((gather_topk_kernel<AL>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
+    hipLaunchKernelGGL((gather_topk_kernel<AL, COMP>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
                        counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
                        tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only, members ? 1 : 0,
                        a.cand_m, a.cand_lb, a.L, a.cand_f8, a.thr, a.stop);
@@ -2118,11 +2215,19 @@ hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_
 hipError_t launch_gather(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
                          int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
                          int keys_only = 0, bool members = false) {
-    if (a.d % 4 == 0)
-        return launch_gather_al<true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only,
-                                      members);
-    return launch_gather_al<false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st, keys_only,
-                                   members);
+    const bool comp = a.d >= kCompensateD;
+    if (a.d % 4 == 0) {
+        if (comp)
+            return launch_gather_al<true, true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st,
+                                                keys_only, members);
+        return launch_gather_al<true, false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st,
+                                             keys_only, members);
+    }
+    if (comp)
+        return launch_gather_al<false, true>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st,
+                                             keys_only, members);
+    return launch_gather_al<false, false>(a, list, ld_list, counts, use_max, want, sv_check, k, tau, st,
+                                          keys_only, members);
 }
 
 // Gathered verification of the whole of S (or D) for queries with status `want`.

@@ -181,6 +181,28 @@ def test_save_load_roundtrip(dl, tmp_path):
     assert not os.path.exists(str(path) + ".tmp")
 
 
+def test_insert_codes_across_persistent_tiles(dl):
+    """Inserted points are encoded by the persistent encode at an offset into
+    the code array: with both the built set and the insertion above 65,536
+    rows (several tiles per workgroup), every code of both parts is compared
+    with the oracle's encoding against the frozen breakpoints."""
+    n0, m = 70_000, 80_000
+    say(f"insert codes across tiles n0={n0} m={m}")
+    cc = U.case(n=n0 + m, d=16, N_r=256, frac=0.01, kind="mixture", nq=4, seed=77)
+    X1, X2 = cc["X"][:n0], cc["X"][n0:]
+    sample = cc["sample"][cc["sample"] < n0][:700]
+    idx = dl.build_index(X1, 4, 16, 256, len(sample) / n0, A=cc["A"], sample_ids=sample)
+    idx.insert(X2)
+    ex = idx.export()
+    B64 = ex["B"].astype(np.float64)
+    for part, Xp, codes in (("built", X1, ex["codes"][:n0]), ("inserted", X2, ex["codes"][n0:])):
+        P = O.project(Xp, cc["A"])
+        ref = O.encode(P, B64)
+        nbad, hard = U.code_mismatches(P, U.proj_scale(Xp, cc["A"]), B64, B64, ref, codes)
+        say(f"  {part}: codes differing {nbad} of {ref.size} (non-borderline {hard})")
+        assert hard == 0
+
+
 @pytest.mark.parametrize("keep_bf16", [False, True])
 def test_insert_equals_import_of_the_union(dl, keep_bf16):
     """Points inserted after the build are encoded against the frozen

@@ -88,6 +88,23 @@ def test_breakpoints_and_codes(dl, n, d, N_r, frac, L, K):
     assert hard == 0
 
 
+def test_codes_across_persistent_tiles(dl):
+    """The encode runs a persistent grid whose workgroups each take several
+    512-row tiles once n exceeds 512 x 128 rows; codes past the first tile of
+    every workgroup are compared with the oracle's too (n = 200,000)."""
+    n, d, L, K, N_r = 200_000, 16, 4, 16, 256
+    say(f"codes across persistent tiles n={n}")
+    c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=0.01, seed=5)
+    idx = dl.build_index(c["X"], L, K, N_r, 0.01, A=c["A"], sample_ids=c["sample"])
+    ex = idx.export()
+    P = O.project(c["X"], c["A"])
+    ref = O.encode(P, ex["B"].astype(np.float64))
+    B64 = ex["B"].astype(np.float64)
+    nbad, hard = U.code_mismatches(P, U.proj_scale(c["X"], c["A"]), B64, B64, ref, ex["codes"])
+    say(f"  codes differing: {nbad} of {ref.size} (non-borderline {hard})")
+    assert hard == 0
+
+
 # --------------------------------------------------------------------------
 # step a4: DE-Trees as leaf runs
 # --------------------------------------------------------------------------
@@ -393,6 +410,44 @@ def test_bf16_rerank_form(dl, n, d, k):
         assert np.all(np.diff(b_d[qi]) >= 0)
     with pytest.raises(dl.DetlshError, match="keep_bf16"):
         dl.build_index(c["X"][:5000], 4, 16, 256, 0.1).query(Q[:2], k, 1.5, 0.1, precision=dl.BF16_RERANK)
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_compensated_distances_d960(dl, form):
+    """At d = 960 the exact distances of the final ranking are compensated
+    sums: every returned distance is within 4e-7 relative of the FP64 distance
+    of the returned id (an uncompensated FP32 sum of 960 squares may be off by
+    up to about 1e-4), and the FP32 form's answers equal the oracle's on the
+    GPU's own encoding (ids up to near-ties, distances within 1e-5)."""
+    import synth
+    n, d, k = 65_600, 960, 10
+    say(f"compensated distances n={n} d={d} form={form}")
+    X = synth.beta_copula(n, d, 91)
+    Qh = synth.beta_copula(12, d, 92)
+    A = synth.projection_matrix(4, 16, d, 93)
+    sample = synth.sample_ids(n, 656, 94)
+    idx = dl.build_index(X, 4, 16, 256, 0.01, A=A, sample_ids=sample, keep_bf16=(form == "bf16"))
+    Q = t(Qh)
+    kw = {"precision": dl.BF16_RERANK} if form == "bf16" else {}
+    ids, dists = (v.cpu().numpy() for v in idx.query(Q, k, 1.5, 0.1, **kw))
+    worst = 0.0
+    for qi in range(len(Qh)):
+        exact = np.sqrt(O.sq_dists(X[ids[qi]], Qh[qi]))
+        worst = max(worst, float(np.max(np.abs(dists[qi] - exact) / exact)))
+    say(f"  largest relative distance error {worst:.3g}")
+    assert worst <= 4e-7
+    if form == "fp32":
+        ex = idx.export()
+        Qp = idx.project(Q).cpu().numpy()
+        r = idx.query_debug(Q, k, 1.5, 0.1, Qp=t(Qp))
+        g_ids, g_d = r["ids"].cpu().numpy(), r["dists"].cpu().numpy()
+        for qi in range(len(Qh)):
+            ref = U.oracle_query(X, Qh[qi], Qp[qi], ex["codes"], ex["B"], 4, 16, k, 0.1)
+            S_gpu = set(r["cand"][qi, :int(r["counts"][qi])].cpu().numpy().tolist())
+            sym = S_gpu ^ set(ref.S.tolist())
+            assert sym <= U.borderline_points(Qp[qi], ex["codes"], ex["B"], 4, 16, ref.thr)
+            if not sym:
+                U.compare_result(ref.ids, ref.dists, X, Qh[qi], g_ids[qi], g_d[qi], ref.S, k)
 
 
 # --------------------------------------------------------------------------

@@ -447,6 +447,66 @@ def test_fixed_stops_on_condition_two_for_tight_clusters():
 # planted mistakes: each must be caught by one of the pins above
 # --------------------------------------------------------------------------
 
+# --------------------------------------------------------------------------
+# the quality measures of Sec. 6.1 (recall, overall ratio)
+# --------------------------------------------------------------------------
+
+def test_measures_hand_worked():
+    """recall = |R cap R*| / k and overall ratio = mean of ||q,o_i|| / ||q,o_i*||,
+    worked by hand: R* at distances 1, 2, 3; R at 1, 2, 4 shares two points
+    (recall 2/3) and has ratios 1, 1, 4/3 (mean 10/9)."""
+    assert O.recall([1.0, 2.0, 4.0], [1.0, 2.0, 3.0]) == pytest.approx(2 / 3)
+    assert O.overall_ratio([1.0, 2.0, 4.0], [1.0, 2.0, 3.0]) == pytest.approx(10 / 9)
+    # an exact answer
+    assert O.recall([0.5, 0.7], [0.5, 0.7]) == 1.0
+    assert O.overall_ratio([0.5, 0.7], [0.5, 0.7]) == 1.0
+    # ties at the k-th distance (R16): another point at the k-th distance counts
+    assert O.recall([1.0, 2.0, 2.0], [1.0, 2.0, 2.0]) == 1.0
+    assert O.recall([1.0, 2.0, 2.0, 2.0], [1.0, 1.5, 2.0, 2.0]) == 1.0
+    # a duplicate of the query: 0/0 counts as 1, x/0 as infinity
+    assert O.overall_ratio([0.0, 1.0], [0.0, 1.0]) == 1.0
+    assert math.isinf(O.overall_ratio([0.1, 1.0], [0.0, 1.0]))
+    # a farther answer never has a ratio below 1 or a recall above 1
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        ref = np.sort(rng.random(10))
+        ret = np.sort(ref + rng.random(10) * rng.integers(0, 2, 10))
+        assert O.overall_ratio(ret, ref) >= 1.0 and O.recall(ret, ref) <= 1.0
+
+
+def test_measures_of_the_oracle_answer_against_brute_force():
+    """With beta = 1 the oracle's answer is the exact k-NN: recall 1 and ratio 1
+    against brute force; at a small beta both stay within their ranges and the
+    answer of a worse method (every other point of the exact 2k-NN) is
+    measured worse."""
+    X, idx, _ = make_problem(n=1200, d=16, seed=11)
+    q = X[5] + 0.1
+    qp = O.project(q[None, :], idx.A)[0]
+    k = 10
+    ref_ids, ref_d2 = O.brute_force_knn(X, q, k)
+    full = O.query_magic(X, q, qp, idx.codes, idx.B, 4, 8, k, 1.0)
+    assert O.recall(full.dists, np.sqrt(ref_d2)) == 1.0
+    assert O.overall_ratio(full.dists, np.sqrt(ref_d2)) == pytest.approx(1.0)
+    ids2k, d2k = O.brute_force_knn(X, q, 2 * k)
+    worse = np.sqrt(d2k[1::2])
+    assert O.recall(worse, np.sqrt(ref_d2)) == pytest.approx(0.5)
+    assert O.overall_ratio(worse, np.sqrt(ref_d2)) > 1.0
+
+
+def test_planted_inverted_ratio_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "overall_ratio", lambda a, b: float(np.mean(np.asarray(b) / np.asarray(a))))
+    with pytest.raises(AssertionError):
+        test_measures_hand_worked()
+
+
+def test_planted_recall_by_rank_is_caught(monkeypatch):
+    """Counting hits rank by rank (ret_i <= ref_i) instead of against the k-th
+    reference distance misses returned points that are in R* out of order."""
+    monkeypatch.setattr(O, "recall", lambda a, b: float(np.mean(np.asarray(a) <= np.asarray(b))))
+    with pytest.raises(AssertionError):
+        test_measures_hand_worked()
+
+
 def test_planted_encode_tie_side_is_caught(monkeypatch):
     rng = np.random.default_rng(1)
     Ps = rng.standard_normal((1000, 2))
