@@ -190,6 +190,14 @@ typedef struct {
     int32_t granularity;        /* DETLSH_POINT (0): a point enters by its cell's
                                    bound; DETLSH_LEAF (1): by its DE-Tree leaf's box
                                    (the query-phase optimisation; MAGIC only)       */
+    int32_t filter;             /* range filter of the magic radius, point
+                                   granularity (same candidates either way):
+                                   0 automatic (the screen when N_S <= 0.03 n),
+                                   1 every bound of every pair evaluated,
+                                   2 an MFMA screen by the ball around each cell
+                                   (clamped to the interior breakpoint range),
+                                   then the exact bounds of the pairs it keeps
+                                   (L <= 4; other shapes use 1)                   */
 } detlsh_query_opts;
 
 /* Candidate granularity of the range query. */

@@ -66,8 +66,9 @@ def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, proje
 
 
 def _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify=0,
-                granularity="point"):
+                granularity="point", filter="auto"):
     o = _lib.QueryOpts()
+    o.filter = {"auto": 0, "plain": 1, "screen": 2}.get(filter, filter)
     o.granularity = {"point": 0, "leaf": 1}.get(granularity, granularity)
     o.verify = {"auto": 0, "gather": 1, "dense": 2, "dense_bf16": 3}.get(verify, verify)
     o.precision = int(precision)
@@ -90,7 +91,10 @@ class Index:
 
     def free(self):
         if getattr(self, "_h", None):
-            lib().detlsh_free(self._h)
+            try:
+                lib().detlsh_free(self._h)
+            except TypeError:   # interpreter shutdown: the module is already torn down
+                pass
             self._h = None
 
     @property
@@ -110,13 +114,14 @@ class Index:
         return out
 
     def query(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC,
-              r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto", granularity="point"):
+              r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto", granularity="point", filter="auto"):
         torch = _torch()
         Q = _dev_f32(Q, "Q")
         nq = Q.shape[0]
         ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
         dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity,
+                        filter)
         check(lib().detlsh_query(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
                                  _ptr(dists), _stream_ptr()))
         return ids, dists
@@ -158,7 +163,7 @@ class Index:
 
     def query_debug(self, Q, k, c=1.5, beta=0.1, Qp=None, cand_cap=None, precision=FP32, rerank_mult=4,
                     rmin_policy=RMIN_MAGIC, r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto",
-                    granularity="point"):
+                    granularity="point", filter="auto"):
         """Query that also returns S, first trees, thr, stop tree and rounds."""
         torch = _torch()
         Q = _dev_f32(Q, "Q")
@@ -178,7 +183,8 @@ class Index:
         if Qp is not None:
             Qp = _dev_f32(Qp, "Qp")
             qp_ptr = _ptr(Qp)
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity,
+                        filter)
         check(lib().detlsh_query_debug(self._h, qp_ptr, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o),
                                        _ptr(cand), cap, _ptr(counts), _ptr(first), _ptr(thr), _ptr(stop),
                                        _ptr(rounds), _ptr(ids), _ptr(dists), _stream_ptr()))

@@ -40,6 +40,7 @@ class QueryOpts(C.Structure):
         ("workspace_bytes", C.c_size_t),
         ("verify", C.c_int32),
         ("granularity", C.c_int32),
+        ("filter", C.c_int32),
     ]
 
 

@@ -284,6 +284,8 @@ struct detlsh_index_s {
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
     DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
+    DevBuf ball;                  // point vectors of the filter's MFMA screen, [L][n][KA]
+    DevBuf codes_pm;              // codes point-major, [n][L*K] (the screen's exact pass)
     int32_t G = 0;                // guess subset size, min(n, kGuessMax)
     float emax = 0.f;             // bound on the largest ||o - bf16(o)|| (slightly above it)
     std::vector<int64_t> sample_ids;
@@ -301,14 +303,14 @@ struct detlsh_index_s {
         const bool have = hipGetDevice(&cur) == hipSuccess;
         if (hipSetDevice(device) == hipSuccess) (void)hipDeviceSynchronize();
         for (DevBuf* b : {&X, &Xbf, &A, &Abf, &B, &E, &codes, &perm, &scodes, &xn, &xn_bf, &gcodes, &leaf_of,
-                          &gleaf})
+                          &gleaf, &ball, &codes_pm})
             pool_give(*b, device);
         for (DevBuf& b : leaf_mem) pool_give(b, device);
         if (have) (void)hipSetDevice(cur);
     }
     size_t bytes() const {
         size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
-                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes + leaf_of.bytes + gleaf.bytes;
+                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes + leaf_of.bytes + gleaf.bytes + ball.bytes + codes_pm.bytes;
         for (int i = 0; i < L; ++i) b += (size_t)(n_leaves[i] + 1) * 4 + 2 * (size_t)n_leaves[i] * K;
         return b;
     }
@@ -353,6 +355,14 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
                            (1.0 + std::ldexp(1.0, -20)));
     } else {
         HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), nullptr, nullptr, st));
+    }
+    if (dl_ball_supported(ix->L, ix->K)) {
+        HCHECK(pool_alloc(ix->ball, (size_t)ix->n * ix->L * dl_ball_width(ix->K) * 4, ix->device));
+        HCHECK(dl_launch_ball_table(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->E.as<float>(), ix->N_r,
+                                    ix->ball.as<float>(), st));
+        HCHECK(pool_alloc(ix->codes_pm, (size_t)ix->n * ix->LK, ix->device));
+        HCHECK(dl_launch_codes_point_major(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->codes_pm.as<uint8_t>(),
+                                           st));
     }
     ix->G = (int32_t)std::min<int64_t>(ix->n, kGuessMax);
     HCHECK(pool_alloc(ix->gcodes, (size_t)ix->G * ix->LK, ix->device));
@@ -990,6 +1000,7 @@ struct QueryPlan {
     int64_t cap_sv = 0;     // survivor slots per query
     bool fixed = false;     // printed radius ladder from r_min
     bool leaf = false;      // leaf-granularity candidates
+    bool ball = false;      // range filter as an MFMA screen plus exact bounds of its survivors
     int rounds = 0;         // radius rounds before S = D
     const float* rad2 = nullptr;
     const float* c2 = nullptr;
@@ -1060,9 +1071,11 @@ int64_t round4(int64_t v) { return (v + 3) & ~(int64_t)3; }
 // minima of the bounds (dl_prefix_mins) instead of the L bounds.
 bool implicit_s(const QueryPlan& p, bool dumps) { return p.dense && !p.leaf && !p.fixed && !dumps; }
 
-size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d, bool dumps = false) {
+size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d, bool dumps = false, int K = 16) {
     const size_t nb = (size_t)(implicit_s(p, dumps) ? dl_prefix_mins(L) : L);
     size_t b = (size_t)cap * (4 + 4 + 4 + 4 * nb + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
+    if (p.ball) b += (size_t)L * dl_ball_width(K) * 4;
+    if (p.ball && !p.dense) b += (size_t)((n + 63) / 64) * 8;   // the screen's survivor words
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
 }
@@ -1094,7 +1107,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     // candidate rows start 16-byte aligned (vector loads in the selection)
     const int64_t cap = round4((force_all_candidates || plan.fixed) ? ix->n : plan.cap);
     const bool dumps = dbg.cand_ids || dbg.cand_counts || dbg.first_tree;
-    const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d, dumps);
+    const size_t pq = per_query_bytes(cap, ix->L, plan, ix->n, ix->d, dumps, ix->K);
     int64_t nqc = (int64_t)(arena.bytes / pq);
     if (nqc < 1) {
         if (arena.p)
@@ -1172,6 +1185,16 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         a.tau_rel = (float)((ix->d + 4.0) * std::ldexp(1.0, -24));
         a.emax = ix->emax;
     }
+    const bool ball = plan.ball && !force_all_candidates;
+    if (ball) {
+        if (!a.bm) {   // the screen writes its survivor words where the dense pass reads the hits
+            a.W = (ix->n + 63) / 64;
+            a.bm = reinterpret_cast<uint64_t*>(take((size_t)nqc * a.W * 8));
+        }
+        a.ball = ix->ball.as<float>();
+        a.codes_pm = ix->codes_pm.as<uint8_t>();
+        a.uq = reinterpret_cast<float*>(take((size_t)nqc * ix->L * dl_ball_width(ix->K) * 4));
+    }
     a.out_ids = out_ids; a.out_d = out_d;
     std::vector<float> inf_host;
     std::vector<uint32_t> sc_host;
@@ -1206,7 +1229,12 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
             }
             {
                 DlTimer tm(T_FILTER, st);
-                HCHECK(dl_launch_filter(a, st));
+                if (ball) {
+                    HCHECK(dl_launch_ball_query(a, st));
+                    HCHECK(dl_launch_ball_filter(a, st));
+                } else {
+                    HCHECK(dl_launch_filter(a, st));
+                }
             }
             {
                 DlTimer tm(T_SELECT, st);
@@ -1342,6 +1370,12 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
         plan.rounds = s.rounds;
         plan.cap = ix->n;
     }
+    const int filter = opts ? opts->filter : 0;
+    if (filter < 0 || filter > 2) return fail(DETLSH_EINVAL, "filter %d is not defined", filter);
+    // the MFMA screen pays while few pairs survive it (measured: 2x faster at
+    // N_S = 1% of n, slower at 10%)
+    plan.ball = !plan.all && !plan.fixed && !plan.leaf && ix->ball.p != nullptr && filter != 1 &&
+                (filter == 2 || (double)plan.N_S <= 0.03 * (double)ix->n);
     const bool bf16 = s.precision == DETLSH_BF16_RERANK;
     plan.dense = !plan.all && !plan.fixed &&
                  (s.verify == 2 || s.verify == 3 || (s.verify == 0 && (ix->n >= 65536 || bf16)));
@@ -1372,9 +1406,10 @@ QueryPlan all_points_plan(const QueryPlan& plan, int64_t n) {
 size_t query_arena_bytes(const detlsh_index_s* ix, const QuerySetup& s, int64_t nq, bool with_qp) {
     const QueryPlan& plan = s.plan;
     const int64_t cap = round4(plan.fixed ? ix->n : plan.cap);
-    size_t run = per_query_bytes(cap, ix->L, plan, ix->n, ix->d) * (size_t)nq;
-    const size_t fb = std::max(per_query_bytes(round4(ix->n), ix->L, plan, ix->n, ix->d),
-                               per_query_bytes(round4(ix->n), ix->L, all_points_plan(plan, ix->n), ix->n, ix->d));
+    size_t run = per_query_bytes(cap, ix->L, plan, ix->n, ix->d, false, ix->K) * (size_t)nq;
+    const size_t fb = std::max(per_query_bytes(round4(ix->n), ix->L, plan, ix->n, ix->d, false, ix->K),
+                               per_query_bytes(round4(ix->n), ix->L, all_points_plan(plan, ix->n), ix->n, ix->d,
+                                               false, ix->K));
     size_t b = std::max(run, fb);
     if (with_qp) b += align256((size_t)nq * ix->LK * 4);
     if (!s.ladder.empty()) b += align256(s.ladder.size() * 4);

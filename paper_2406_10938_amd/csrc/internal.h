@@ -138,12 +138,28 @@ struct QueryArgs {
     const float* rad2 = nullptr;     // (eps r_min c^t)^2, t < T
     const float* c2 = nullptr;       // (c r_min c^t)^2, t < T
     int T = 0;
+    // MFMA screen of the range filter: point vectors [L][n][KA] of the index and
+    // the chunk's query vectors [L][nqc][KA]
+    const float* ball = nullptr;
+    float* uq = nullptr;
+    const uint8_t* codes_pm = nullptr;   // codes point-major, [n][L*K] (exact pass of the screen)
     // outputs (all queries)
     int64_t* out_ids = nullptr;
     float* out_d = nullptr;
 };
 
 bool dl_supported_lk(int L, int K);
+// Range filter as an MFMA screen (a ball around each clamped cell) followed by
+// the exact bound of the pairs it keeps (k_ball.hip); same output as
+// dl_launch_filter for the magic radius at point granularity.
+bool dl_ball_supported(int L, int K);
+int dl_ball_width(int K);   // KA: floats per point vector and tree
+// codes [L][n][K] -> point-major [n][L*K]
+hipError_t dl_launch_codes_point_major(const uint8_t* codes, int64_t n, int L, int K, uint8_t* out, hipStream_t st);
+hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, const float* E, int N_r, float* out,
+                                hipStream_t st);
+hipError_t dl_launch_ball_query(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_ball_filter(const QueryArgs& a, hipStream_t st);
 // Issue-rate probe of the range filter's bound arithmetic (L = 4, K = 16):
 // `lanes` (a multiple of 256) synthetic cells against nq projected queries.
 hipError_t dl_launch_valu_probe(const float* qp, int nq, float* out, int64_t lanes, hipStream_t st);

@@ -657,46 +657,6 @@ __global__ __launch_bounds__(256, 3) void filter_kernel(const float* __restrict_
     }
 }
 
-// Block-wide exclusive prefix of a 0/1 flag over 256 threads; returns the
-// prefix and writes the block total to *tot.
-__device__ __forceinline__ uint32_t block_flag_prefix(bool f, uint32_t* wtot, uint32_t* tot) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t msk = dl_ballot(f);
-    const uint32_t r = (uint32_t)dl_rank_below(msk);
-    if (lane == 0) wtot[wave] = (uint32_t)__popcll(msk);
-    __syncthreads();
-    uint32_t pre = 0, all = 0;
-    for (int w = 0; w < 4; ++w) {
-        if (w < wave) pre += wtot[w];
-        all += wtot[w];
-    }
-    *tot = all;
-    __syncthreads();
-    return pre + r;
-}
-
-// Block-wide exclusive prefix of per-thread counts over 256 threads (all
-// lanes active); returns the prefix and writes the block total to *tot.
-__device__ __forceinline__ uint32_t block_count_prefix(uint32_t c, uint32_t* wtot, uint32_t* tot) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = dl_shfl_u32(incl, lane >= o ? lane - o : lane);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) wtot[wave] = incl;
-    __syncthreads();
-    uint32_t pre = 0, all = 0;
-    for (int w = 0; w < 4; ++w) {
-        if (w < wave) pre += wtot[w];
-        all += wtot[w];
-    }
-    *tot = all;
-    __syncthreads();
-    return pre + incl - c;
-}
-
 template <int L>
 __device__ __forceinline__ void load_lbs(const float* __restrict__ src, float (&lb)[L]) {
     if constexpr (L % 4 == 0) {

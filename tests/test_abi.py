@@ -38,12 +38,30 @@ def test_binding_matches_header():
     assert sorted(_lib.SIGNATURES) == declared_functions()
 
 
-def test_struct_layouts():
+def test_struct_layouts(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals the C
+    compiler's for the header's structs."""
+    import subprocess
+
     from paper_2406_10938_amd import _lib
-    assert ctypes.sizeof(_lib.BuildOpts) == 8 + 4 * 4 + 8 + 8
-    assert ctypes.sizeof(_lib.QueryOpts) == 4 * 4 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(_lib.Info) == 8 + 4 * 4 + 8 + 4 + 4 + 8 * 8 + 8
-    assert ctypes.sizeof(_lib.RequestInfo) == 3 * 8 + 4 + 4 + 8
+    structs = {"detlsh_build_opts": _lib.BuildOpts, "detlsh_query_opts": _lib.QueryOpts,
+               "detlsh_info": _lib.Info, "detlsh_request_info": _lib.RequestInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "detlsh.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
 
 
 def test_server_rejects_null_handles_without_a_device():

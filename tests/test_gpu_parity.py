@@ -412,6 +412,58 @@ def test_bf16_rerank_form(dl, n, d, k):
         dl.build_index(c["X"][:5000], 4, 16, 256, 0.1).query(Q[:2], k, 1.5, 0.1, precision=dl.BF16_RERANK)
 
 
+@pytest.mark.parametrize("n,d,L,K,N_r,beta,k,kind,nq", [
+    (70_001, 96, 4, 16, 256, 0.01, 10, "mixture", 37),
+    (65_600, 128, 4, 16, 256, 0.1, 10, "integer", 40),
+    (9_000, 64, 4, 16, 64, 0.05, 5, "mixture", 21),
+    (20_000, 48, 2, 8, 256, 0.2, 25, "mixture", 33),
+    (12_345, 32, 1, 32, 128, 0.02, 7, "mixture", 17),
+    (8_200, 40, 4, 4, 16, 0.1, 10, "smallint", 19),
+    (30_000, 64, 2, 32, 256, 0.3, 3, "integer", 16),
+])
+def test_screen_filter_equals_plain_filter(dl, n, d, L, K, N_r, beta, k, kind, nq):
+    """The MFMA screen (ball around each clamped cell) plus exact bounds of its
+    survivors keeps exactly the plain filter's candidates with bit-identical
+    keys: the same S, threshold, stop tree and first trees, and bit-identical
+    answers on the dumps path and on the implicit-S dense path; and both
+    equal the oracle on its own encoding up to points on the threshold."""
+    say(f"screen vs plain filter n={n} d={d} L={L} K={K} N_r={N_r} beta={beta} k={k} kind={kind} nq={nq}")
+    c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=0.05, kind=kind, nq=nq, seed=n % 101)
+    idx = dl.build_index(c["X"], L, K, N_r, 0.05, A=c["A"], sample_ids=c["sample"], keep_bf16=True)
+    Qh = c["Q"].copy()
+    Qh[: min(3, nq)] = c["X"][[0, n // 2, n - 1][: min(3, nq)]]   # queries on data points (bounds of 0)
+    Q = t(Qh)
+    dbg = {}
+    for f in ("plain", "screen"):
+        dbg[f] = idx.query_debug(Q, k, 1.5, beta, filter=f)
+    a, b = dbg["plain"], dbg["screen"]
+    for key in ("counts", "thr", "stop_tree", "ids", "dists"):
+        assert torch_equal(a[key], b[key]), key
+    ca, cb = a["cand"].cpu().numpy(), b["cand"].cpu().numpy()
+    fa, fb = a["first_tree"].cpu().numpy(), b["first_tree"].cpu().numpy()
+    counts = a["counts"].cpu().numpy()
+    for qi in range(nq):
+        m = int(counts[qi])
+        oa, ob = np.argsort(ca[qi, :m]), np.argsort(cb[qi, :m])
+        assert np.array_equal(ca[qi, :m][oa], cb[qi, :m][ob])
+        assert np.array_equal(fa[qi, :m][oa], fb[qi, :m][ob])
+    pa = idx.query(Q, k, 1.5, beta, filter="plain")
+    pb = idx.query(Q, k, 1.5, beta, filter="screen")
+    assert torch_equal(pa[0], pb[0]) and torch_equal(pa[1], pb[1])
+    ex = idx.export()
+    Qp = idx.project(Q).cpu().numpy()
+    r = idx.query_debug(Q, k, 1.5, beta, Qp=t(Qp), filter="screen")
+    for qi in range(0, nq, 4):
+        ref = U.oracle_query(c["X"], Qh[qi], Qp[qi], ex["codes"], ex["B"], L, K, k, beta)
+        S_gpu = set(r["cand"][qi, :int(r["counts"][qi])].cpu().numpy().tolist())
+        assert S_gpu ^ set(ref.S.tolist()) <= U.borderline_points(Qp[qi], ex["codes"], ex["B"], L, K, ref.thr)
+
+
+def torch_equal(x, y):
+    import torch
+    return bool(torch.equal(x, y))
+
+
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
 def test_compensated_distances_d960(dl, form):
     """At d = 960 the exact distances of the final ranking are compensated
