@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-ops/s without packed FP32: 39.32 T
 FP32_MFMA_PEAK = 157.3           # TFLOP/s dense
+BF16_MFMA_PEAK = 2500.0          # TFLOP/s dense
 
 
 def log(*a):
@@ -453,14 +454,13 @@ def timed_steps(dl, torch, X, Q, cfg, k, beta, A, sample, form, steps, stream):
     return e0.elapsed_time(e1), bsum, last, prof
 
 
-def roofline(kernels, steps, cfg, nq, k, beta, n, d, probe_rate):
-    """Roofline of the kernel with the largest total time (achieved =
-    algorithmic work of one average launch / its average duration)."""
-    LK, L = cfg.L * cfg.K, cfg.L
-    dom = max(kernels, key=lambda s: kernels[s]["total_ms"])
-    avg_s = kernels[dom]["avg_ms"] / 1e3
-    per_launch_q = nq / (kernels[dom]["launches"] / steps)
-    if dom == "range_filter":
+def kernel_roof(name, kern, steps, cfg, nq, n, d, probe_rate, bf16_products=False):
+    """Roofline entry of one kernel: algorithmic work of its average launch
+    divided by the average launch duration, against the peak that bounds it."""
+    LK, L, K = cfg.L * cfg.K, cfg.L, cfg.K
+    avg_s = kern["avg_ms"] / 1e3
+    per_launch_q = nq / (kern["launches"] / steps)
+    if name == "range_filter":
         # per (query, point): L*K bound terms, each 3 lane operations (clamp,
         # difference, fused square-add), and one minimum per tree
         ops = (3 * LK + L) * n * per_launch_q
@@ -474,19 +474,43 @@ def roofline(kernels, steps, cfg, nq, k, beta, n, d, probe_rate):
             r["frac_measured"] = r["achieved"] / r["peak_measured"]
             r["peak_measured_note"] = ("detlsh_probe_valu: the filter's own bound arithmetic (clamp, difference, "
                                        "fused square-add, tree minima) with nothing else, on this GPU in this run")
-    elif dom == "dense_verify":
+    elif name == "range_screen":
+        # per (query, point, tree): one dot product of K + 3 terms, taken in
+        # three BF16 terms (hi.hi + hi.lo + lo.hi) on MFMA
+        fl = 2.0 * L * 3 * (K + 3) * n * per_launch_q
+        kb = 32 * ((3 * (K + 3) + 31) // 32)
+        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": BF16_MFMA_PEAK, "unit": "TFLOP/s",
+             "work": f"2 L 3 (K + 3) = {2 * L * 3 * (K + 3)} flops per (query, point): the ball-screen dot "
+                     f"products in three BF16 terms (issued padded to {kb} terms per tree, "
+                     f"{2 * L * kb} flops); {n} points x {per_launch_q:.0f} queries per launch"}
+    elif name == "dense_verify":
         fl = 2.0 * n * d * per_launch_q
-        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s",
-             "work": "2 n d flops per query (dense-equivalent)"}
-    elif dom == "project_encode":
+        peak = BF16_MFMA_PEAK if bf16_products else FP32_MFMA_PEAK
+        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+             "work": f"2 n d flops per query (dense-equivalent, {'BF16' if bf16_products else 'FP32'} products); "
+                     f"{per_launch_q:.0f} queries per launch"}
+    elif name == "project_encode":
         fl = 2.0 * n * LK * d
         r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s",
              "work": "2 L K d flops per point"}
     else:
-        r = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        r = {"bound": None, "achieved": None, "peak": None, "unit": None}
     r["frac"] = (r["achieved"] / r["peak"]) if r["achieved"] else None
-    r["traffic"] = counted_traffic(dom)
-    r["kernel"] = dom
+    r["traffic"] = counted_traffic(name)
+    r["kernel"] = name
+    r["avg_ms"] = kern["avg_ms"]
+    return r
+
+
+def roofline(kernels, steps, cfg, nq, k, beta, n, d, probe_rate, bf16_products=False):
+    """Roofline of the kernel with the largest total time in the timed steps,
+    and of every kernel above 5% of the step."""
+    tot = sum(v["total_ms"] for v in kernels.values())
+    dom = max(kernels, key=lambda s: kernels[s]["total_ms"])
+    r = kernel_roof(dom, kernels[dom], steps, cfg, nq, n, d, probe_rate, bf16_products)
+    r["others"] = [kernel_roof(nm, kv, steps, cfg, nq, n, d, probe_rate, bf16_products)
+                   for nm, kv in sorted(kernels.items(), key=lambda x: -x[1]["total_ms"])
+                   if nm != dom and kv["total_ms"] > 0.05 * tot]
     return r
 
 

@@ -197,7 +197,7 @@ struct WsLease {
 const char* kTimerNames[T_COUNT] = {"project_sample", "breakpoints", "project_encode", "tree_build",
                                     "project_queries", "guess",      "range_filter",   "select",
                                     "verify_topk",     "to_bf16",     "tau",            "dense_verify",
-                                    "rerank_topk"};
+                                    "rerank_topk",     "range_screen",   "range_exact"};
 
 struct Profiler {
     std::mutex mu;
@@ -284,7 +284,7 @@ struct detlsh_index_s {
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
     DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
-    DevBuf ball;                  // point vectors of the filter's MFMA screen, [L][n][KA]
+    DevBuf ballb;                 // point vectors of the filter's MFMA screen, three-term BF16 form, [L][n][KB]
     DevBuf codes_pm;              // codes point-major, [n][L*K] (the screen's exact pass)
     int32_t G = 0;                // guess subset size, min(n, kGuessMax)
     float emax = 0.f;             // bound on the largest ||o - bf16(o)|| (slightly above it)
@@ -303,14 +303,14 @@ struct detlsh_index_s {
         const bool have = hipGetDevice(&cur) == hipSuccess;
         if (hipSetDevice(device) == hipSuccess) (void)hipDeviceSynchronize();
         for (DevBuf* b : {&X, &Xbf, &A, &Abf, &B, &E, &codes, &perm, &scodes, &xn, &xn_bf, &gcodes, &leaf_of,
-                          &gleaf, &ball, &codes_pm})
+                          &gleaf, &ballb, &codes_pm})
             pool_give(*b, device);
         for (DevBuf& b : leaf_mem) pool_give(b, device);
         if (have) (void)hipSetDevice(cur);
     }
     size_t bytes() const {
         size_t b = X.bytes + Xbf.bytes + A.bytes + Abf.bytes + B.bytes + E.bytes + codes.bytes + perm.bytes +
-                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes + leaf_of.bytes + gleaf.bytes + ball.bytes + codes_pm.bytes;
+                   scodes.bytes + xn.bytes + xn_bf.bytes + gcodes.bytes + leaf_of.bytes + gleaf.bytes + ballb.bytes + codes_pm.bytes;
         for (int i = 0; i < L; ++i) b += (size_t)(n_leaves[i] + 1) * 4 + 2 * (size_t)n_leaves[i] * K;
         return b;
     }
@@ -357,9 +357,9 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
         HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), nullptr, nullptr, st));
     }
     if (dl_ball_supported(ix->L, ix->K)) {
-        HCHECK(pool_alloc(ix->ball, (size_t)ix->n * ix->L * dl_ball_width(ix->K) * 4, ix->device));
+        HCHECK(pool_alloc(ix->ballb, (size_t)ix->n * ix->L * dl_ball_width_bf16(ix->K) * 2, ix->device));
         HCHECK(dl_launch_ball_table(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->E.as<float>(), ix->N_r,
-                                    ix->ball.as<float>(), st));
+                                    ix->ballb.as<uint16_t>(), st));
         HCHECK(pool_alloc(ix->codes_pm, (size_t)ix->n * ix->LK, ix->device));
         HCHECK(dl_launch_codes_point_major(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->codes_pm.as<uint8_t>(),
                                            st));
@@ -1074,7 +1074,7 @@ bool implicit_s(const QueryPlan& p, bool dumps) { return p.dense && !p.leaf && !
 size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d, bool dumps = false, int K = 16) {
     const size_t nb = (size_t)(implicit_s(p, dumps) ? dl_prefix_mins(L) : L);
     size_t b = (size_t)cap * (4 + 4 + 4 + 4 * nb + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
-    if (p.ball) b += (size_t)L * dl_ball_width(K) * 4;
+    if (p.ball) b += (size_t)L * dl_ball_width_bf16(K) * 2 + 512;
     if (p.ball && !p.dense) b += (size_t)((n + 63) / 64) * 8;   // the screen's survivor words
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
@@ -1191,9 +1191,9 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
             a.W = (ix->n + 63) / 64;
             a.bm = reinterpret_cast<uint64_t*>(take((size_t)nqc * a.W * 8));
         }
-        a.ball = ix->ball.as<float>();
+        a.ballb = ix->ballb.as<uint16_t>();
         a.codes_pm = ix->codes_pm.as<uint8_t>();
-        a.uq = reinterpret_cast<float*>(take((size_t)nqc * ix->L * dl_ball_width(ix->K) * 4));
+        a.uqb = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->L * dl_ball_width_bf16(ix->K) * 2));
     }
     a.out_ids = out_ids; a.out_d = out_d;
     std::vector<float> inf_host;
@@ -1227,14 +1227,17 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
                 DlTimer tm(T_GUESS, st);
                 HCHECK(dl_launch_guess(a, st));
             }
-            {
-                DlTimer tm(T_FILTER, st);
-                if (ball) {
+            if (ball) {
+                {
+                    DlTimer tm(T_SCREEN, st);
                     HCHECK(dl_launch_ball_query(a, st));
-                    HCHECK(dl_launch_ball_filter(a, st));
-                } else {
-                    HCHECK(dl_launch_filter(a, st));
+                    HCHECK(dl_launch_ball_screen(a, st));
                 }
+                DlTimer tm(T_EXACT, st);
+                HCHECK(dl_launch_ball_exact(a, st));
+            } else {
+                DlTimer tm(T_FILTER, st);
+                HCHECK(dl_launch_filter(a, st));
             }
             {
                 DlTimer tm(T_SELECT, st);
@@ -1374,7 +1377,7 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
     if (filter < 0 || filter > 2) return fail(DETLSH_EINVAL, "filter %d is not defined", filter);
     // the MFMA screen pays while few pairs survive it (measured: 2x faster at
     // N_S = 1% of n, slower at 10%)
-    plan.ball = !plan.all && !plan.fixed && !plan.leaf && ix->ball.p != nullptr && filter != 1 &&
+    plan.ball = !plan.all && !plan.fixed && !plan.leaf && ix->ballb.p != nullptr && filter != 1 &&
                 (filter == 2 || (double)plan.N_S <= 0.03 * (double)ix->n);
     const bool bf16 = s.precision == DETLSH_BF16_RERANK;
     plan.dense = !plan.all && !plan.fixed &&

@@ -138,10 +138,9 @@ struct QueryArgs {
     const float* rad2 = nullptr;     // (eps r_min c^t)^2, t < T
     const float* c2 = nullptr;       // (c r_min c^t)^2, t < T
     int T = 0;
-    // MFMA screen of the range filter: point vectors [L][n][KA] of the index and
-    // the chunk's query vectors [L][nqc][KA]
-    const float* ball = nullptr;
-    float* uq = nullptr;
+    // MFMA screen of the range filter and its exact pass
+    const uint16_t* ballb = nullptr;  // point vectors, three-term BF16 form [L][n][KB]
+    uint16_t* uqb = nullptr;          // the chunk's query vectors, the same form [L][nqc][KB]
     const uint8_t* codes_pm = nullptr;   // codes point-major, [n][L*K] (exact pass of the screen)
     // outputs (all queries)
     int64_t* out_ids = nullptr;
@@ -153,13 +152,16 @@ bool dl_supported_lk(int L, int K);
 // the exact bound of the pairs it keeps (k_ball.hip); same output as
 // dl_launch_filter for the magic radius at point granularity.
 bool dl_ball_supported(int L, int K);
-int dl_ball_width(int K);   // KA: floats per point vector and tree
+int dl_ball_width_bf16(int K);   // KB: BF16 values per vector and tree (three-term form)
 // codes [L][n][K] -> point-major [n][L*K]
 hipError_t dl_launch_codes_point_major(const uint8_t* codes, int64_t n, int L, int K, uint8_t* out, hipStream_t st);
-hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, const float* E, int N_r, float* out,
-                                hipStream_t st);
+// point vectors of the screen, three-term BF16 form [L][n][KB]
+hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, const float* E, int N_r,
+                                uint16_t* outb, hipStream_t st);
 hipError_t dl_launch_ball_query(const QueryArgs& a, hipStream_t st);
-hipError_t dl_launch_ball_filter(const QueryArgs& a, hipStream_t st);
+// the screen (survivor words into a.bm) and the exact pass over them
+hipError_t dl_launch_ball_screen(const QueryArgs& a, hipStream_t st);
+hipError_t dl_launch_ball_exact(const QueryArgs& a, hipStream_t st);
 // Issue-rate probe of the range filter's bound arithmetic (L = 4, K = 16):
 // `lanes` (a multiple of 256) synthetic cells against nq projected queries.
 hipError_t dl_launch_valu_probe(const float* qp, int nq, float* out, int64_t lanes, hipStream_t st);
@@ -195,5 +197,5 @@ struct DlTimer {
 };
 enum {
     T_PROJECT_SAMPLE = 0, T_BREAKPOINTS, T_ENCODE, T_TREE, T_QPROJECT, T_GUESS, T_FILTER, T_SELECT,
-    T_VERIFY, T_BF16, T_TAU, T_DENSE, T_FINAL, T_COUNT
+    T_VERIFY, T_BF16, T_TAU, T_DENSE, T_FINAL, T_SCREEN, T_EXACT, T_COUNT
 };

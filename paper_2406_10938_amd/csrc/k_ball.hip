@@ -1,6 +1,6 @@
 // Range filter of the magic-radius query (Alg. 4/5 with the point-level
 // predicate LB_i(q,o)^2 <= thr, the Alg. 7 stop of Sec. 5.2) as a screen on
-// MFMA followed by the exact bound of the pairs the screen keeps.
+// MFMA followed by the exact bounds of the pairs the screen keeps.
 //
 // Screen.  Clamp every coordinate (query and cell edges) to the interior
 // breakpoint range [B(2), B(N_r)] of its dimension; the outer regions become
@@ -14,64 +14,58 @@
 //     (|q~ - c| - W)_+^2  <=  LB_i(q,o)^2 .
 // A pair can pass the filter's test LB_i^2 <= thr only if
 //     V_i = |q~|^2 - 2 q~.c + |c|^2 - (sqrt(thr') + W)^2  <=  0
-// (thr' = thr (1 + 2^-16) covers the rounding of the FP32 bound the filter
+// (thr' = thr (1 + d) covers the rounding of the FP32 bound the filter
 // compares).  V_i is one dot product of a query vector
 //     u = [-2 q~, (1-d)|q~|^2 - (1+d) thr', 1, -2 sqrt(thr')]
 // and a point vector
 //     p = [c, 1, (1-d)|c|^2 - (1+d) W^2, W],
-// where the d = 2^-16 terms subtract d (|q~|^2 + thr' + |c|^2 + W^2), more
-// than the rounding error of the FP32 dot product and of its entries (at most
-// (KA + 4) 2^-24 times twice that sum).  So the screen is an FP32 GEMM of the
-// chunk's query vectors against every point's L vectors
-// (v_mfma_f32_16x16x4f32), and a pair is dropped when min_i V_i > 0.
+// where the d = 2^-12 terms subtract d (|q~|^2 + thr' + |c|^2 + W^2) >=
+// d/2.01 sum_k |u_k p_k|.  The GPU takes the dot product on BF16 MFMA in three
+// terms (every FP32 entry split as hi + lo), whose error is below 2.5 times
+// less than that slack; a pair is dropped when min_i V_i > 0.  The screen
+// writes its survivors as the query's hit words (64 points per word).
 //
-// Exact bound.  The pairs left are evaluated exactly as the plain filter does
-// (same edges, same FP32 operations in the same order, so bit-identical keys):
-// lanes take survivors from a per-wave queue in LDS, read the point's codes,
-// the query's projection and the edge table from LDS, and keep candidates
-// with m^2 <= thr.  Candidates go to per-wave hit lists in LDS; per group of
-// 16 queries one global atomic per query reserves the workgroup's slots, the
-// lists are copied out and the membership bitmap words are written, exactly
-// the output of the plain filter.
+// Exact pass.  The survivors are evaluated exactly as the plain filter does
+// (same edges, same FP32 operations in the same order, so bit-identical keys),
+// candidates with m^2 <= thr are appended to the query's list and the hit
+// words are rewritten with the candidates only: the output of the plain
+// filter.
 #include "common.h"
 #include "internal.h"
 
 namespace {
 
-constexpr int kBallWaves = 8;                   // waves per workgroup, 64 points each
-constexpr int kBallPoints = 64 * kBallWaves;    // points per workgroup tile
-constexpr int kBallG = 16;                      // queries per group (one 16-row MFMA block)
-constexpr int kBallHitCap = 96;                 // LDS hit slots per query and group
-constexpr double kBallDelta = 1.0 / 65536.0;
+constexpr double kBallDelta = 1.0 / 4096.0;
+
+__host__ __device__ inline size_t ball_align(size_t b) { return (b + 15) & ~(size_t)15; }
 
 template <int K>
 struct BallDims {
-    static constexpr int KA = ((K + 3 + 3) / 4) * 4;   // K centre terms + 3, padded to MFMA steps of 4
-    static constexpr int S = KA / 4;                    // MFMA steps per tree
+    static constexpr int NCH = (3 * (K + 3) + 31) / 32; // 32-element BF16 MFMA steps of the three-term form
+    static constexpr int KB = 32 * NCH;                 // K centre terms + 3, three times, padded
 };
 
-// Element k = 4 s + kq of a vector is stored at kq * S + s, so that the lane
-// that feeds reduction index kq of every step reads S consecutive values.
-template <int K>
-__device__ __forceinline__ int ball_slot(int k) {
-    return (k & 3) * BallDims<K>::S + (k >> 2);
+// x - bf16(x) rounded to BF16 (the difference is exact in FP32).
+__device__ __forceinline__ uint16_t bf16_lo(float x) {
+    return dl_f32_to_bf16(x - dl_bf16_to_f32(dl_f32_to_bf16(x)));
 }
 
 __device__ __forceinline__ float clampf(float x, float a, float b) { return fminf(fmaxf(x, a), b); }
 
-// Point vectors p of every (tree, point), [L][n][KA].
+// Point vectors p of every (tree, point) in the three-term BF16 form,
+// [L][n][KB]: hi(p), lo(p), hi(p), zeros.
 template <int K>
 __global__ __launch_bounds__(256) void ball_table_kernel(const uint8_t* __restrict__ codes, int64_t n, int L,
                                                          const float* __restrict__ E, int N_r,
-                                                         float* __restrict__ out)
+                                                         uint16_t* __restrict__ outb)
 {
-    constexpr int KA = BallDims<K>::KA;
+    constexpr int P = K + 3;
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= (int64_t)L * n) return;
     const int i = (int)(g / n);
     const int ldE = N_r + 1;
     const uint8_t* c = codes + g * K;   // [L][n][K]: row g = i*n + o
-    float v[KA];
+    float v[P];
     double cc = 0.0, ww = 0.0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -92,22 +86,26 @@ __global__ __launch_bounds__(256) void ball_table_kernel(const uint8_t* __restri
     v[K] = 1.0f;
     v[K + 1] = (float)((1.0 - kBallDelta) * cc - (1.0 + kBallDelta) * Wd * Wd);
     v[K + 2] = W;
+    uint16_t* db = outb + g * BallDims<K>::KB;
 #pragma unroll
-    for (int k = K + 3; k < KA; ++k) v[k] = 0.0f;
-    float* dst = out + g * KA;
-#pragma unroll
-    for (int k = 0; k < KA; ++k) dst[ball_slot<K>(k)] = v[k];
+    for (int k = 0; k < BallDims<K>::KB; ++k) {
+        uint16_t h = 0;
+        if (k < P || (k >= 2 * P && k < 3 * P)) h = dl_f32_to_bf16(v[k < P ? k : k - 2 * P]);
+        else if (k < 2 * P) h = bf16_lo(v[k - P]);
+        db[k] = h;
+    }
 }
 
-// Query vectors u of the chunk, [L][nqc][KA].  A threshold that is not finite
-// (or the row past the chunk) gives u = [0, .., -1, 0, ..]: V = -1, every pair
-// passes to the exact test.
+// Query vectors u of the chunk in the three-term BF16 form, [L][nqc][KB]:
+// hi(u), hi(u), lo(u), zeros.  A threshold that is not finite gives
+// u = [0, .., -1, 0, ..]: V = -1, every pair passes to the exact test.
 template <int K>
 __global__ __launch_bounds__(256) void ball_query_kernel(const float* __restrict__ Qp, int64_t q0, int nqc, int L,
                                                          const float* __restrict__ E, int N_r,
-                                                         const float* __restrict__ gthr, float* __restrict__ out)
+                                                         const float* __restrict__ gthr,
+                                                         uint16_t* __restrict__ outb)
 {
-    constexpr int KA = BallDims<K>::KA;
+    constexpr int P = K + 3;
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= (int64_t)L * nqc) return;
     const int i = (int)(g / nqc);
@@ -115,9 +113,9 @@ __global__ __launch_bounds__(256) void ball_query_kernel(const float* __restrict
     const int ldE = N_r + 1;
     const float* q = Qp + (q0 + t) * (int64_t)(L * K) + i * K;
     const float th = gthr[t];
-    float v[KA];
+    float v[P];
 #pragma unroll
-    for (int k = 0; k < KA; ++k) v[k] = 0.0f;
+    for (int k = 0; k < P; ++k) v[k] = 0.0f;
     if (!(th < INFINITY)) {
         v[K] = -1.0f;
     } else {
@@ -134,9 +132,14 @@ __global__ __launch_bounds__(256) void ball_query_kernel(const float* __restrict
         v[K + 1] = 1.0f;
         v[K + 2] = (float)(-2.0 * sqrt(tp));
     }
-    float* dst = out + g * KA;
+    uint16_t* db = outb + g * BallDims<K>::KB;
 #pragma unroll
-    for (int k = 0; k < KA; ++k) dst[ball_slot<K>(k)] = v[k];
+    for (int k = 0; k < BallDims<K>::KB; ++k) {
+        uint16_t h = 0;
+        if (k < 2 * P) h = dl_f32_to_bf16(v[k < P ? k : k - P]);
+        else if (k < 3 * P) h = bf16_lo(v[k - 2 * P]);
+        db[k] = h;
+    }
 }
 
 template <int J, int L>
@@ -147,37 +150,39 @@ __device__ __forceinline__ float ball_prefix_min(const float (&lb)[L]) {
     return r;
 }
 
-// Screen: one wave per 64 points (their L point vectors in registers), every
-// query of the block's slice, 16 at a time.  The 16 x 16 MFMA blocks take the
-// points as rows and the queries as columns, so lane (kq, m) holds points
-// 16 b + 4 kq + v of query m; its 16 survivor bits are ORed with those of the
-// other three lanes of query m and one lane writes the query's 64-bit word.
-// The word is the filter's hit word with the screen's survivors (a superset);
-// the exact pass below rewrites it.
+// Screen with BF16 MFMA (v_mfma_f32_16x16x32_bf16): every FP32 entry x of
+// the two vectors is split as hi = bf16(x), lo = bf16(x - hi), and the dot
+// product is taken as hi(u).hi(p) + hi(u).lo(p) + lo(u).hi(p), in NCH steps
+// of 32 elements.  Its error is below (3.01 2^-16 + 64 2^-24) sum |u_k p_k|,
+// under 2.5 times less than the 2^-12 slack folded into the vectors.  Point
+// operands are rebuilt from the FP32 point vectors once per wave; the
+// queries' BF16 vectors of a 16-query block are staged in LDS (double
+// buffered, one barrier per block) for the workgroup's four waves.
 template <int L, int K>
-__global__ __launch_bounds__(256) void ball_screen_kernel(const float* __restrict__ ball,
-                                                          const float* __restrict__ uq, int64_t n, int nqc,
-                                                          int q_per_block, uint64_t* __restrict__ bm, int64_t W)
+__global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t* __restrict__ ballb,
+                                                                  const uint16_t* __restrict__ uqb, int64_t n,
+                                                                  int nqc, int q_per_block,
+                                                                  uint64_t* __restrict__ bm, int64_t W)
 {
-    constexpr int KA = BallDims<K>::KA;
-    constexpr int S = BallDims<K>::S;
+    constexpr int NCH = BallDims<K>::NCH;
+    constexpr int KB = BallDims<K>::KB;
+    __shared__ __attribute__((aligned(16))) uint16_t sU[2][L][16][KB];
     const int lane = threadIdx.x & 63;
     const int m = lane & 15;
     const int kq = lane >> 4;
     const int64_t wbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
-    if (wbase >= n) return;   // the whole wave is past the last point
-    float Bv[L][4][S];
-    uint32_t vbits = 0;       // bit 4b+v: point 16b + 4kq + v exists
+    const bool live = wbase < n;   // a wave past the last point still takes part in the staging
+    bf16x8 Bv[L][4][NCH];
+    uint32_t vbits = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int64_t o_raw = wbase + 16 * b + m;
         const int64_t o = o_raw < n ? o_raw : n - 1;
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const float* src = ball + ((int64_t)i * n + o) * KA + kq * S;
+        for (int i = 0; i < L; ++i)
 #pragma unroll
-            for (int s = 0; s < S; ++s) Bv[i][b][s] = src[s];
-        }
+            for (int ch = 0; ch < NCH; ++ch)
+                Bv[i][b][ch] = *reinterpret_cast<const bf16x8*>(ballb + ((int64_t)i * n + o) * KB + 32 * ch + 8 * kq);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             if (wbase + 16 * b + 4 * kq + v < n) vbits |= 1u << (4 * b + v);
@@ -185,69 +190,134 @@ __global__ __launch_bounds__(256) void ball_screen_kernel(const float* __restric
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
     const int64_t word = wbase / 64;
-    float Un[L][S];
-    auto load_u = [&](int t0, float (&U)[L][S]) {
-        const int tq = (t0 + m < tb) ? t0 + m : tb - 1;
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const float* src = uq + ((int64_t)i * nqc + tq) * KA + kq * S;
-#pragma unroll
-            for (int s = 0; s < S; ++s) U[i][s] = src[s];
+    // staging: the block's L x 16 x KB BF16 values, 16 bytes per thread and step
+    constexpr int NV = L * 16 * KB / 8;
+    auto stage = [&](int t0, int buf) {
+        for (int x = threadIdx.x; x < NV; x += 256) {
+            const int i = x / (16 * KB / 8), rem = x - i * (16 * KB / 8);
+            const int r = rem / (KB / 8), c8 = rem - r * (KB / 8);
+            const int tq = (t0 + r < tb) ? t0 + r : tb - 1;
+            *reinterpret_cast<uint4*>(&sU[buf][i][r][8 * c8]) =
+                *reinterpret_cast<const uint4*>(uqb + ((int64_t)i * nqc + tq) * KB + 8 * c8);
         }
     };
-    load_u(ta, Un);
+    stage(ta, 0);
+    __syncthreads();
+    int buf = 0;
     for (int t0 = ta; t0 < tb; t0 += 16) {
-        float U[L][S];
+        if (t0 + 16 < tb) stage(t0 + 16, buf ^ 1);
+        if (live) {
+            // tree by tree, the minimum over trees kept as it goes
+            floatx4 mn[4];
 #pragma unroll
-        for (int i = 0; i < L; ++i)
+            for (int i = 0; i < L; ++i) {
+                floatx4 acc[4];
 #pragma unroll
-            for (int s = 0; s < S; ++s) U[i][s] = Un[i][s];
-        if (t0 + 16 < tb) load_u(t0 + 16, Un);   // the next block's operands, in flight during this one
-        floatx4 acc[4][L];
+                for (int b = 0; b < 4; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const bf16x8 qv = *reinterpret_cast<const bf16x8*>(&sU[buf][i][m][32 * ch + 8 * kq]);
 #pragma unroll
-            for (int i = 0; i < L; ++i) acc[b][i] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-#pragma unroll
-            for (int s = 0; s < S; ++s)
+                    for (int b = 0; b < 4; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bv[i][b][ch], qv, acc[b], 0, 0, 0);
+                }
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(Bv[i][b][s], U[i][s], acc[b][i], 0, 0, 0);
-        uint32_t lo = 0, hi = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float mv = acc[b][0][v];
-#pragma unroll
-                for (int i = 1; i < L; ++i) mv = fminf(mv, acc[b][i][v]);
-                const uint32_t bit = (mv <= 0.0f && ((vbits >> (4 * b + v)) & 1u)) ? 1u : 0u;
-                if (b < 2) lo |= bit << (16 * b + 4 * kq + v);
-                else hi |= bit << (16 * (b - 2) + 4 * kq + v);
+                    for (int v = 0; v < 4; ++v) mn[b][v] = (i == 0) ? acc[b][v] : fminf(mn[b][v], acc[b][v]);
             }
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t bit = (mn[b][v] <= 0.0f && ((vbits >> (4 * b + v)) & 1u)) ? 1u : 0u;
+                    if (b < 2) lo |= bit << (16 * b + 4 * kq + v);
+                    else hi |= bit << (16 * (b - 2) + 4 * kq + v);
+                }
+            }
+            lo |= (uint32_t)__shfl_xor((int)lo, 16);
+            hi |= (uint32_t)__shfl_xor((int)hi, 16);
+            lo |= (uint32_t)__shfl_xor((int)lo, 32);
+            hi |= (uint32_t)__shfl_xor((int)hi, 32);
+            if (kq == 0 && t0 + m < tb && word < W)
+                bm[(int64_t)(t0 + m) * W + word] = (uint64_t)lo | ((uint64_t)hi << 32);
         }
-        lo |= (uint32_t)__shfl_xor((int)lo, 16);
-        hi |= (uint32_t)__shfl_xor((int)hi, 16);
-        lo |= (uint32_t)__shfl_xor((int)lo, 32);
-        hi |= (uint32_t)__shfl_xor((int)hi, 32);
-        if (kq == 0 && t0 + m < tb && word < W) bm[(int64_t)(t0 + m) * W + word] = (uint64_t)lo | ((uint64_t)hi << 32);
+        __syncthreads();   // the next block's staging is complete; this one's reads are done
+        buf ^= 1;
     }
 }
 
-constexpr int kExactWords = 256;   // survivor words per chunk of the exact pass (one per thread)
+constexpr int kExactThreads = 512;   // threads of an exact-pass workgroup; one survivor word each per chunk
+constexpr int kExactList = 2048;     // survivor ids expanded into LDS per pass over a chunk
 
-// Exact pass: one workgroup per (query, slice of words).  Per chunk of 256
-// words the screen's survivors are ranked by a block prefix of popcounts;
-// batches of 256 survivors (one per thread, found by a binary search over the
-// prefix and a select of the bit) are evaluated exactly as the plain filter
-// does (edges from LDS, the query's projection from scalar loads, the same
-// FP32 operations in the same order), candidates (m^2 <= thr) are appended to
-// the query's list with one atomic per batch, and the chunk's words are
-// rewritten with the candidates only.
+// Exclusive prefix of per-thread counts over a workgroup of NW waves (every
+// thread takes part); the total goes to *tot.  wtot: NW words of LDS.
+template <int NW>
+__device__ __forceinline__ uint32_t wg_count_prefix(uint32_t c, uint32_t* wtot, uint32_t* tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = dl_shfl_u32(incl, lane >= o ? lane - o : lane);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wave) pre += wtot[w];
+        all += wtot[w];
+    }
+    *tot = all;
+    __syncthreads();
+    return pre + incl - c;
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t wg_flag_prefix(bool f, uint32_t* wtot, uint32_t* tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t msk = dl_ballot(f);
+    if (lane == 0) wtot[wave] = (uint32_t)__popcll(msk);
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wave) pre += wtot[w];
+        all += wtot[w];
+    }
+    *tot = all;
+    __syncthreads();
+    return pre + (uint32_t)dl_rank_below(msk);
+}
+
+struct ExactLds {
+    size_t sE, list, spre, sbits, wtot, total;
+};
+
+__host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
+    ExactLds s;
+    size_t o = 0;
+    s.sE = o;    o += ball_align((size_t)LK * (N_r + 1) * 4);
+    s.list = o;  o += ball_align((size_t)kExactList * 4);
+    s.spre = o;  o += ball_align((size_t)kExactThreads * 4);
+    s.sbits = o; o += ball_align((size_t)kExactThreads * 2 * 4);
+    s.wtot = o;  o += ball_align(16 * 4 + 4);
+    s.total = o;
+    return s;
+}
+
+// Exact pass: one workgroup per (query, slice of words).  Per chunk of 512
+// words the screen's survivors are ranked by a workgroup prefix of popcounts
+// and expanded into an LDS list of point ids (2,048 per pass; more passes
+// when a chunk holds more); batches of 512 survivors (one per thread) are
+// evaluated exactly as the plain filter does (edges from LDS, the query's
+// projection from scalar loads, the same FP32 operations in the same order),
+// candidates (m^2 <= thr) are appended to the query's list with one atomic
+// per batch, and the chunk's words are rewritten with the candidates only.
 template <int L, int K, bool PREFIX>
-__global__ __launch_bounds__(256) void ball_exact_kernel(
+__global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     const float* __restrict__ E, int N_r, const uint8_t* __restrict__ codes_pm, int64_t n,
     const float* __restrict__ Qp, int64_t q0, const float* __restrict__ gthr, int64_t words_per_slice,
     uint32_t* __restrict__ counts, int64_t cap, int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
@@ -255,147 +325,157 @@ __global__ __launch_bounds__(256) void ball_exact_kernel(
 {
     constexpr int LK = L * K;
     constexpr int NB = PREFIX ? dl_prefix_mins(L) : L;
+    constexpr int NW = kExactThreads / 64;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    float* sE = reinterpret_cast<float*>(smem);
+    const ExactLds lay = exact_lds(LK, N_r);
+    float* sE = reinterpret_cast<float*>(smem + lay.sE);
+    int32_t* list = reinterpret_cast<int32_t*>(smem + lay.list);
+    uint32_t* spre = reinterpret_cast<uint32_t*>(smem + lay.spre);
+    uint32_t* sbits = reinterpret_cast<uint32_t*>(smem + lay.sbits);
+    uint32_t* wtot = reinterpret_cast<uint32_t*>(smem + lay.wtot);
+    uint32_t* sbase = wtot + 16;
     const int ldE = N_r + 1;
-    uint32_t* spre = reinterpret_cast<uint32_t*>(smem + (((size_t)LK * ldE * 4 + 15) & ~(size_t)15));
-    uint32_t* sbits = spre + kExactWords + 1;       // [256][2] rewritten words
-    uint32_t* wtot = sbits + 2 * kExactWords;      // scan scratch
-    __shared__ uint32_t sbase;
     const int t = blockIdx.x;
     const float th = gthr[t];
     const float* qp = Qp + (q0 + t) * (int64_t)LK;
-    for (int x = threadIdx.x; x < LK * ldE; x += 256) sE[x] = E[x];
+    for (int x = threadIdx.x; x < LK * ldE; x += kExactThreads) sE[x] = E[x];
     const int64_t w_lo = (int64_t)blockIdx.y * words_per_slice;
     const int64_t w_hi = (w_lo + words_per_slice < W) ? w_lo + words_per_slice : W;
     uint64_t* row = bm + (int64_t)t * W;
     __syncthreads();
-    for (int64_t c0 = w_lo; c0 < w_hi; c0 += kExactWords) {
+    for (int64_t c0 = w_lo; c0 < w_hi; c0 += kExactThreads) {
         const int64_t wi = c0 + threadIdx.x;
         const uint64_t word = (wi < w_hi) ? row[wi] : 0ull;
         uint32_t tot;
-        const uint32_t pre = block_count_prefix((uint32_t)__popcll(word), wtot, &tot);
-        spre[threadIdx.x] = pre;
-        if (threadIdx.x == 0) spre[kExactWords] = tot;
+        const uint32_t pre = wg_count_prefix<NW>((uint32_t)__popcll(word), wtot, &tot);
         sbits[2 * threadIdx.x] = 0u;
         sbits[2 * threadIdx.x + 1] = 0u;
-        __syncthreads();
-        for (uint32_t r0 = 0; r0 < tot; r0 += 256) {
-            const uint32_t r = r0 + threadIdx.x;
-            bool cand = false;
-            int64_t o = 0;
-            int wl = 0, bit = 0;
-            float key = 0.f, mins[NB];
-            if (r < tot) {
-                // the word holding rank r: the last with prefix <= r
-                int lo = 0, hi = kExactWords - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (spre[mid] <= r) lo = mid; else hi = mid - 1;
-                }
-                wl = lo;
-                uint64_t w = row[c0 + wl];
-                uint32_t k = r - spre[wl];   // the k-th set bit of w
-                for (; k > 0; --k) w &= w - 1;
-                bit = __ffsll((unsigned long long)w) - 1;
-                o = (c0 + wl) * 64 + bit;
-                const uint32_t* cw = reinterpret_cast<const uint32_t*>(codes_pm + o * LK);
-                uint32_t words[LK / 4];
-#pragma unroll
-                for (int j = 0; j < LK / 4; ++j) words[j] = cw[j];
-                float lb[L];
-#pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    float lo_e[K], hi_e[K];
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const int e = i * K + j;
-                        const uint32_t code = (words[e >> 2] >> (8 * (e & 3))) & 0xffu;
-                        lo_e[j] = sE[e * ldE + code];
-                        hi_e[j] = sE[e * ldE + code + 1];
-                    }
-                    float a = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const float q = qp[i * K + j];
-                        const float p = __builtin_amdgcn_fmed3f(q, lo_e[j], hi_e[j]);
-                        const float dd = q - p;
-                        a = fmaf(dd, dd, a);
-                    }
-                    lb[i] = a;
-                }
-                float m1 = INFINITY, m2 = INFINITY;
-                if constexpr (PREFIX && L >= 3) {
-                    m2 = ball_prefix_min<L - 2, L>(lb);
-                    m1 = fminf(m2, lb[L - 2]);
-                    key = fminf(m1, lb[L - 1]);
-                } else {
-                    float run = lb[0];
-#pragma unroll
-                    for (int i = 1; i < L - 1; ++i) run = fminf(run, lb[i]);
-                    key = L > 1 ? fminf(run, lb[L - 1]) : lb[0];
-                }
-                if constexpr (PREFIX) {
-                    if constexpr (L >= 3) { mins[0] = m2; mins[1] = m1; }
-                    else if constexpr (L == 2) mins[0] = lb[0];
-                    else mins[0] = INFINITY;   // no tree before the last
-                } else {
-#pragma unroll
-                    for (int i = 0; i < NB; ++i) mins[i] = lb[i];
-                }
-                cand = key <= th;
-                if (cand) atomicOr(&sbits[2 * wl + (bit >> 5)], 1u << (bit & 31));
+        for (uint32_t p0 = 0; p0 < tot; p0 += kExactList) {
+            // this thread's survivors with ranks in [p0, p0 + kExactList) into the list
+            uint64_t w = word;
+            uint32_t r = pre;
+            while (w) {
+                const int bit = __ffsll((unsigned long long)w) - 1;
+                w &= w - 1;
+                if (r >= p0 && r < p0 + kExactList) list[r - p0] = (int32_t)(wi * 64 + bit);
+                ++r;
             }
-            uint32_t ctot;
-            const uint32_t cpre = block_flag_prefix(cand, wtot, &ctot);
-            if (threadIdx.x == 0) sbase = ctot ? atomicAdd(&counts[t], ctot) : 0u;
             __syncthreads();
-            if (cand) {
-                const int64_t idx = (int64_t)sbase + cpre;
-                if (idx < cap) {
-                    const int64_t at = (int64_t)t * cap + idx;
-                    cand_id[at] = (int32_t)o;
-                    cand_m[at] = key;
-                    if constexpr (NB == 2) {
-                        reinterpret_cast<float2*>(cand_lb)[at] = make_float2(mins[0], mins[1]);
+            const uint32_t np = (tot - p0 < (uint32_t)kExactList) ? tot - p0 : (uint32_t)kExactList;
+            for (uint32_t b0 = 0; b0 < np; b0 += kExactThreads) {
+                const uint32_t j = b0 + threadIdx.x;
+                bool cand = false;
+                int64_t o = 0;
+                float key = 0.f, mins[NB];
+                if (j < np) {
+                    o = list[j];
+                    const uint4* cw = reinterpret_cast<const uint4*>(codes_pm + o * LK);
+                    uint32_t words[LK / 4];
+#pragma unroll
+                    for (int c = 0; c < LK / 16; ++c) {
+                        const uint4 v = cw[c];
+                        words[4 * c] = v.x; words[4 * c + 1] = v.y; words[4 * c + 2] = v.z; words[4 * c + 3] = v.w;
+                    }
+                    float lb[L];
+#pragma unroll
+                    for (int i = 0; i < L; ++i) {
+                        float lo_e[K], hi_e[K];
+#pragma unroll
+                        for (int jj = 0; jj < K; ++jj) {
+                            const int e = i * K + jj;
+                            const uint32_t code = (words[e >> 2] >> (8 * (e & 3))) & 0xffu;
+                            lo_e[jj] = sE[e * ldE + code];
+                            hi_e[jj] = sE[e * ldE + code + 1];
+                        }
+                        float a = 0.0f;
+#pragma unroll
+                        for (int jj = 0; jj < K; ++jj) {
+                            const float q = qp[i * K + jj];
+                            const float pp = __builtin_amdgcn_fmed3f(q, lo_e[jj], hi_e[jj]);
+                            const float dd = q - pp;
+                            a = fmaf(dd, dd, a);
+                        }
+                        lb[i] = a;
+                    }
+                    float m1 = INFINITY, m2 = INFINITY;
+                    if constexpr (PREFIX && L >= 3) {
+                        m2 = ball_prefix_min<L - 2, L>(lb);
+                        m1 = fminf(m2, lb[L - 2]);
+                        key = fminf(m1, lb[L - 1]);
+                    } else {
+                        float run = lb[0];
+#pragma unroll
+                        for (int i = 1; i < L - 1; ++i) run = fminf(run, lb[i]);
+                        key = L > 1 ? fminf(run, lb[L - 1]) : lb[0];
+                    }
+                    if constexpr (PREFIX) {
+                        if constexpr (L >= 3) { mins[0] = m2; mins[1] = m1; }
+                        else if constexpr (L == 2) mins[0] = lb[0];
+                        else mins[0] = INFINITY;   // no tree before the last
                     } else {
 #pragma unroll
-                        for (int i = 0; i < NB; ++i) cand_lb[at * NB + i] = mins[i];
+                        for (int i = 0; i < NB; ++i) mins[i] = lb[i];
+                    }
+                    cand = key <= th;
+                    if (cand) {
+                        const int wl = (int)(o / 64 - c0), bit = (int)(o & 63);
+                        atomicOr(&sbits[2 * wl + (bit >> 5)], 1u << (bit & 31));
                     }
                 }
+                uint32_t ctot;
+                const uint32_t cpre = wg_flag_prefix<NW>(cand, wtot, &ctot);
+                if (threadIdx.x == 0) *sbase = ctot ? atomicAdd(&counts[t], ctot) : 0u;
+                __syncthreads();
+                if (cand) {
+                    const int64_t idx = (int64_t)*sbase + cpre;
+                    if (idx < cap) {
+                        const int64_t at = (int64_t)t * cap + idx;
+                        cand_id[at] = (int32_t)o;
+                        cand_m[at] = key;
+                        if constexpr (NB == 2) {
+                            reinterpret_cast<float2*>(cand_lb)[at] = make_float2(mins[0], mins[1]);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < NB; ++i) cand_lb[at * NB + i] = mins[i];
+                        }
+                    }
+                }
+                __syncthreads();   // sbase and the scan scratch are reused
             }
-            __syncthreads();   // sbase and the scan scratch are reused
         }
         if (wi < w_hi) row[wi] = (uint64_t)sbits[2 * threadIdx.x] | ((uint64_t)sbits[2 * threadIdx.x + 1] << 32);
-        __syncthreads();   // spre and sbits are reused by the next chunk
+        __syncthreads();   // the list and sbits are reused by the next chunk
     }
 }
 
 template <int L, int K>
-hipError_t launch_ball_filter_lk(const QueryArgs& a, hipStream_t st) {
-    // screen: 4 waves of 64 points per workgroup; split the chunk's queries
-    // when the points alone give too few workgroups
+hipError_t launch_ball_screen_lk(const QueryArgs& a, hipStream_t st) {
+    // 4 waves of 64 points per workgroup; the chunk's queries are split when
+    // the points alone give too few workgroups
     const int64_t nblk = (a.n + 255) / 256;
     int ysplit = 1;
     while (nblk * ysplit < 2048 && a.nqc / (ysplit * 2) >= 64) ysplit *= 2;
     const int qpb = (int)(((a.nqc + ysplit - 1) / ysplit + 15) / 16 * 16);
     const int gy = (a.nqc + qpb - 1) / qpb;
-    hipLaunchKernelGGL((ball_screen_kernel<L, K>), dim3((unsigned)nblk, (unsigned)gy), dim3(256), 0, st, a.ball,
-                       a.uq, a.n, a.nqc, qpb, a.bm, a.W);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // exact pass: (query, slice of words) workgroups
+    hipLaunchKernelGGL((ball_screen_bf16_kernel<L, K>), dim3((unsigned)nblk, (unsigned)gy), dim3(256), 0, st,
+                       a.ballb, a.uqb, a.n, a.nqc, qpb, a.bm, a.W);
+    return hipGetLastError();
+}
+
+template <int L, int K>
+hipError_t launch_ball_exact_lk(const QueryArgs& a, hipStream_t st) {
+    // (query, slice of 8,192 words) workgroups
     const int64_t wps = 8192;
     const int64_t nsl = (a.W + wps - 1) / wps;
-    const size_t shm = (((size_t)L * K * (a.N_r + 1) * 4 + 15) & ~(size_t)15) + (kExactWords + 1 + 2 * kExactWords + 8) * 4;
+    const size_t shm = exact_lds(L * K, a.N_r).total;
     if (a.compact_s)
-        hipLaunchKernelGGL((ball_exact_kernel<L, K, false>), dim3((unsigned)a.nqc, (unsigned)nsl), dim3(256), shm, st,
-                           a.E, a.N_r, a.codes_pm, a.n, a.Qp, a.q0, a.gthr, wps, a.counts, a.cap, a.cand_id, a.cand_m,
-                           a.cand_lb, a.bm, a.W);
+        hipLaunchKernelGGL((ball_exact_kernel<L, K, false>), dim3((unsigned)a.nqc, (unsigned)nsl), dim3(kExactThreads),
+                           shm, st, a.E, a.N_r, a.codes_pm, a.n, a.Qp, a.q0, a.gthr, wps, a.counts, a.cap, a.cand_id,
+                           a.cand_m, a.cand_lb, a.bm, a.W);
     else
-        hipLaunchKernelGGL((ball_exact_kernel<L, K, true>), dim3((unsigned)a.nqc, (unsigned)nsl), dim3(256), shm, st,
-                           a.E, a.N_r, a.codes_pm, a.n, a.Qp, a.q0, a.gthr, wps, a.counts, a.cap, a.cand_id, a.cand_m,
-                           a.cand_lb, a.bm, a.W);
+        hipLaunchKernelGGL((ball_exact_kernel<L, K, true>), dim3((unsigned)a.nqc, (unsigned)nsl), dim3(kExactThreads),
+                           shm, st, a.E, a.N_r, a.codes_pm, a.n, a.Qp, a.q0, a.gthr, wps, a.counts, a.cap, a.cand_id,
+                           a.cand_m, a.cand_lb, a.bm, a.W);
     return hipGetLastError();
 }
 
@@ -403,16 +483,16 @@ template <int L, int K>
 hipError_t launch_ball_query_lk(const QueryArgs& a, hipStream_t st) {
     const int64_t tot = (int64_t)L * a.nqc;
     hipLaunchKernelGGL((ball_query_kernel<K>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a.Qp, a.q0,
-                       a.nqc, L, a.E, a.N_r, a.gthr, a.uq);
+                       a.nqc, L, a.E, a.N_r, a.gthr, a.uqb);
     return hipGetLastError();
 }
 
 template <int K>
-hipError_t launch_ball_table_k(const uint8_t* codes, int64_t n, int L, const float* E, int N_r, float* out,
+hipError_t launch_ball_table_k(const uint8_t* codes, int64_t n, int L, const float* E, int N_r, uint16_t* outb,
                                hipStream_t st) {
     const int64_t tot = (int64_t)L * n;
     hipLaunchKernelGGL((ball_table_kernel<K>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, codes, n, L,
-                       E, N_r, out);
+                       E, N_r, outb);
     return hipGetLastError();
 }
 
@@ -442,23 +522,23 @@ bool dl_ball_supported(int L, int K) {
     }
 }
 
-int dl_ball_width(int K) {
+int dl_ball_width_bf16(int K) {
     switch (K) {
-        case 4: return BallDims<4>::KA;
-        case 8: return BallDims<8>::KA;
-        case 16: return BallDims<16>::KA;
-        default: return BallDims<32>::KA;
+        case 4: return BallDims<4>::KB;
+        case 8: return BallDims<8>::KB;
+        case 16: return BallDims<16>::KB;
+        default: return BallDims<32>::KB;
     }
 }
 
-hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, const float* E, int N_r, float* out,
-                                hipStream_t st) {
+hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, const float* E, int N_r,
+                                uint16_t* outb, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     switch (K) {
-        case 4: return launch_ball_table_k<4>(codes, n, L, E, N_r, out, st);
-        case 8: return launch_ball_table_k<8>(codes, n, L, E, N_r, out, st);
-        case 16: return launch_ball_table_k<16>(codes, n, L, E, N_r, out, st);
-        case 32: return launch_ball_table_k<32>(codes, n, L, E, N_r, out, st);
+        case 4: return launch_ball_table_k<4>(codes, n, L, E, N_r, outb, st);
+        case 8: return launch_ball_table_k<8>(codes, n, L, E, N_r, outb, st);
+        case 16: return launch_ball_table_k<16>(codes, n, L, E, N_r, outb, st);
+        case 32: return launch_ball_table_k<32>(codes, n, L, E, N_r, outb, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -487,4 +567,6 @@ hipError_t dl_launch_codes_point_major(const uint8_t* codes, int64_t n, int L, i
     return hipGetLastError();
 }
 
-hipError_t dl_launch_ball_filter(const QueryArgs& a, hipStream_t st) { DL_BALL_DISPATCH(launch_ball_filter_lk) }
+hipError_t dl_launch_ball_screen(const QueryArgs& a, hipStream_t st) { DL_BALL_DISPATCH(launch_ball_screen_lk) }
+
+hipError_t dl_launch_ball_exact(const QueryArgs& a, hipStream_t st) { DL_BALL_DISPATCH(launch_ball_exact_lk) }
