@@ -192,7 +192,7 @@ typedef struct {
                                    (the query-phase optimisation; MAGIC only)       */
     int32_t filter;             /* range filter of the magic radius, point
                                    granularity (same candidates either way):
-                                   0 automatic (the screen when N_S <= 0.03 n),
+                                   0 automatic (the screen when N_S <= 0.12 n),
                                    1 every bound of every pair evaluated,
                                    2 an MFMA screen by the ball around each cell
                                    (clamped to the interior breakpoint range),

@@ -166,7 +166,10 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
 {
     constexpr int NCH = BallDims<K>::NCH;
     constexpr int KB = BallDims<K>::KB;
-    __shared__ __attribute__((aligned(16))) uint16_t sU[2][L][16][KB];
+    // rows padded by 16 bytes: with a 128-byte stride the 16 query rows one
+    // MFMA operand reads would all start in the same LDS bank
+    constexpr int LDU = KB + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t sU[2][L][16][LDU];
     const int lane = threadIdx.x & 63;
     const int m = lane & 15;
     const int kq = lane >> 4;
@@ -299,7 +302,7 @@ struct ExactLds {
 __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
     ExactLds s;
     size_t o = 0;
-    s.sE = o;    o += ball_align((size_t)LK * (N_r + 1) * 4);
+    s.sE = o;    o += ball_align((size_t)LK * N_r * 4);
     s.list = o;  o += ball_align((size_t)kExactList * 4);
     s.spre = o;  o += ball_align((size_t)kExactThreads * 4);
     s.sbits = o; o += ball_align((size_t)kExactThreads * 2 * 4);
@@ -308,14 +311,17 @@ __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
     return s;
 }
 
-// Exact pass: one workgroup per (query, slice of words).  Per chunk of 512
-// words the screen's survivors are ranked by a workgroup prefix of popcounts
-// and expanded into an LDS list of point ids (2,048 per pass; more passes
-// when a chunk holds more); batches of 512 survivors (one per thread) are
-// evaluated exactly as the plain filter does (edges from LDS, the query's
-// projection from scalar loads, the same FP32 operations in the same order),
-// candidates (m^2 <= thr) are appended to the query's list with one atomic
-// per batch, and the chunk's words are rewritten with the candidates only.
+// Exact pass: one workgroup per (query, slice of words).  The workgroup first
+// tabulates, for its query, d = q - med3(q, lo, hi) of every (dimension,
+// region) in LDS (the plain filter's first two operations on the same
+// values).  Per chunk of 512 words the screen's survivors are ranked by a
+// workgroup prefix of popcounts and expanded into an LDS list of point ids
+// (2,048 per pass; more passes when a chunk holds more); batches of 512
+// survivors (one per thread) sum fma(d, d, a) over the tabulated d of their
+// regions in the plain filter's order (so the bounds are bit-identical to it,
+// at one LDS read and one fma per term), candidates (m^2 <= thr) are appended
+// to the query's list with one atomic per batch, and the chunk's words are
+// rewritten with the candidates only.
 template <int L, int K, bool PREFIX>
 __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     const float* __restrict__ E, int N_r, const uint8_t* __restrict__ codes_pm, int64_t n,
@@ -338,7 +344,11 @@ __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     const int t = blockIdx.x;
     const float th = gthr[t];
     const float* qp = Qp + (q0 + t) * (int64_t)LK;
-    for (int x = threadIdx.x; x < LK * ldE; x += kExactThreads) sE[x] = E[x];
+    for (int x = threadIdx.x; x < LK * N_r; x += kExactThreads) {
+        const int e = x / N_r, code = x - e * N_r;
+        const float q = qp[e];
+        sE[x] = q - __builtin_amdgcn_fmed3f(q, E[e * ldE + code], E[e * ldE + code + 1]);
+    }
     const int64_t w_lo = (int64_t)blockIdx.y * words_per_slice;
     const int64_t w_hi = (w_lo + words_per_slice < W) ? w_lo + words_per_slice : W;
     uint64_t* row = bm + (int64_t)t * W;
@@ -379,22 +389,16 @@ __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
                     float lb[L];
 #pragma unroll
                     for (int i = 0; i < L; ++i) {
-                        float lo_e[K], hi_e[K];
+                        float dd[K];
 #pragma unroll
                         for (int jj = 0; jj < K; ++jj) {
                             const int e = i * K + jj;
                             const uint32_t code = (words[e >> 2] >> (8 * (e & 3))) & 0xffu;
-                            lo_e[jj] = sE[e * ldE + code];
-                            hi_e[jj] = sE[e * ldE + code + 1];
+                            dd[jj] = sE[e * N_r + code];
                         }
                         float a = 0.0f;
 #pragma unroll
-                        for (int jj = 0; jj < K; ++jj) {
-                            const float q = qp[i * K + jj];
-                            const float pp = __builtin_amdgcn_fmed3f(q, lo_e[jj], hi_e[jj]);
-                            const float dd = q - pp;
-                            a = fmaf(dd, dd, a);
-                        }
+                        for (int jj = 0; jj < K; ++jj) a = fmaf(dd[jj], dd[jj], a);
                         lb[i] = a;
                     }
                     float m1 = INFINITY, m2 = INFINITY;

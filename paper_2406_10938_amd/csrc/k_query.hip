@@ -1324,6 +1324,27 @@ __device__ __forceinline__ float dense_xb(float xn, float margin_c) { return 0.5
 // Screen of one tile's shifted products: a member of S with acc >= a(q)
 // joins its survivor list (LDS, epoch buffer ep; straight to HBM when the
 // list is full).
+// Appends the survivors marked in hits (bit 8 qb + 2 v + pb: query
+// 64 qh + 16 qb + 4 kq + v, point pi0 + 16 pb of the tile at p0).
+__device__ __forceinline__ void dense_append(uint32_t hits, DenseShared& sh, int ep, int qh, int pi0, int kq,
+                                             int64_t p0, int qt0, uint32_t* __restrict__ svc,
+                                             int32_t* __restrict__ sv, int64_t cap_sv) {
+    while (hits) {
+        const int b = __builtin_ctz(hits);
+        hits &= hits - 1u;
+        const int qi = 64 * qh + 16 * (b >> 3) + 4 * kq + ((b >> 1) & 3);
+        const int pi = pi0 + 16 * (b & 1);
+        const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
+        if (s < (uint32_t)kSvl) {
+            sh.list[ep][qi][s] = (int32_t)(p0 + pi);
+        } else {
+            const int t = qt0 + qi;
+            const uint32_t slot = atomicAdd(&svc[t], 1u);
+            if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
+        }
+    }
+}
+
 __device__ __forceinline__ void dense_screen(const floatx4 (&acc)[4][2], DenseShared& sh, int cur, int ep, int qh,
                                              int ph, int m, int kq, int64_t p0, int qt0,
                                              uint32_t* __restrict__ svc, int32_t* __restrict__ sv, int64_t cap_sv) {
@@ -1346,20 +1367,7 @@ __device__ __forceinline__ void dense_screen(const floatx4 (&acc)[4][2], DenseSh
             }
         }
     if (dl_ballot(hits != 0u) == 0ull) return;
-    while (hits) {
-        const int b = __builtin_ctz(hits);
-        hits &= hits - 1u;
-        const int qi = 64 * qh + 16 * (b >> 3) + 4 * kq + ((b >> 1) & 3);
-        const int pi = pi0 + 16 * (b & 1);
-        const uint32_t s = atomicAdd(&sh.cnt[ep][qi], 1u);
-        if (s < (uint32_t)kSvl) {
-            sh.list[ep][qi][s] = (int32_t)(p0 + pi);
-        } else {
-            const int t = qt0 + qi;
-            const uint32_t slot = atomicAdd(&svc[t], 1u);
-            if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(p0 + pi);
-        }
-    }
+    dense_append(hits, sh, ep, qh, pi0, kq, p0, qt0, svc, sv, cap_sv);
 }
 
 // After a barrier that follows an epoch's last screen: one global atomic per
@@ -1825,6 +1833,233 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
     }
 }
 
+
+// BF16 products with d <= 32 NK (NK <= 4) and d a multiple of 8.  The wave's
+// 64 query rows stay in registers, already in the operand layout of
+// v_mfma_f32_16x16x32_bf16, for the whole point range; the point tiles go
+// through a double-buffered LDS tile (one barrier per tile), fetched into
+// registers two tiles ahead so that a load has two tiles' products to arrive.
+// Products that pass the shifted screen are rare (pairs within the query's
+// distance bound), so each product first takes one compare against the
+// register-held a(q); only a wave with a passing product reads the tile's
+// membership words (staged in LDS with the tile) and appends.  Reduction
+// order, screen and survivor lists are those of dense_verify_kc_kernel.
+constexpr int kBqList = 64;   // survivors per query and workgroup kept in LDS
+
+struct BqShared {
+    float aq[kDQ];              // a(q) per query (+inf: skip the query)
+    uint64_t bits[2][kDQ];      // membership words of the current / next tile
+    float xb[2][kDP];           // b(o) of the current / next tile's points
+    uint32_t cnt[kDQ];
+    int32_t list[kDQ][kBqList];
+};
+
+// Appends the survivors marked in hits (layout of dense_append) to the LDS
+// lists.  A list keeps counting past its capacity; the flush then marks the
+// query's survivor count as overflowed.  No global memory operation happens
+// here: one under this branch (a returning atomic, or any store, which the
+// hardware counts with the loads) made the compiler wait for every staging
+// load in flight after it.
+__device__ __forceinline__ void bq_append(uint32_t hits, BqShared& sh, int qh, int pi0, int kq, int64_t p0) {
+    while (hits) {
+        const int b = __builtin_ctz(hits);
+        hits &= hits - 1u;
+        const int qi = 64 * qh + 16 * (b >> 3) + 4 * kq + ((b >> 1) & 3);
+        const int pi = pi0 + 16 * (b & 1);
+        const uint32_t s = atomicAdd(&sh.cnt[qi], 1u);
+        if (s < (uint32_t)kBqList) sh.list[qi][s] = (int32_t)(p0 + pi);
+    }
+}
+
+template <int NK>
+struct BqStage {
+    static constexpr int VPR = 4 * NK;          // 16-byte vectors per staged row
+    static constexpr int SV = kDP * VPR / 256;  // staged vectors per thread
+    uint4 v[SV];
+    float xn;       // thread < kDP: |o|^2 of point t of the tile
+    uint64_t bits;  // thread < kDQ: membership word of query t
+    bool pin;       // the point is inside the set
+};
+
+template <int NK>
+__global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
+    const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
+    const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int nqc, const uint64_t* __restrict__ bm,
+    int64_t W, const float* __restrict__ tau, const int32_t* __restrict__ status, float margin_c,
+    uint32_t* __restrict__ svc, int32_t* __restrict__ sv, int64_t cap_sv, int gx, int64_t gy, int64_t ntiles,
+    int64_t tiles_per_split)
+{
+    using St = BqStage<NK>;
+    constexpr int LD = 32 * NK + 8;     // LDS row stride in elements (+16 bytes against bank conflicts)
+    constexpr int VPR = St::VPR;
+    constexpr int SV = St::SV;
+    static_assert(kDP * VPR % 256 == 0, "staging covers the tile exactly");
+    __shared__ BqShared sh;
+    __shared__ __attribute__((aligned(16))) uint16_t sx[2][kDP * LD];
+    const int64_t lid = blockIdx.x;
+    const int xcd = (int)(lid & 7);
+    const int64_t r = lid >> 3;
+    const int qtile = (int)(r % gx);
+    const int64_t split = xcd + 8 * (r / gx);
+    if (split >= gy) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int qh = wave & 1, ph = wave >> 1;
+    const int qt0 = qtile * kDQ;
+    const int64_t tb = split * tiles_per_split;
+    const int64_t te = (tb + tiles_per_split < ntiles) ? tb + tiles_per_split : ntiles;
+    if (tb >= te) return;
+    // this thread's query row of the membership words (clamped: rows past the
+    // chunk are never read, their a(q) is +inf)
+    const int tqm = min(qt0 + (int)(threadIdx.x & (kDQ - 1)), nqc - 1);
+    if (threadIdx.x < kDQ) {
+        const int tq = qt0 + (int)threadIdx.x;
+        const bool qok = tq < nqc && status[tq] == 0;
+        sh.aq[threadIdx.x] = qok ? dense_aq(qn[tq], tau[tq], margin_c) : INFINITY;
+        sh.cnt[threadIdx.x] = 0;
+    }
+    // the wave's query fragments: row 64 qh + 16 qb + m, elements 32 ks + 8 kq .. + 7
+    bf16x8 qv[4][NK];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+        const int t = qt0 + 64 * qh + 16 * qb + m;
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) {
+            const int k = 32 * ks + 8 * kq;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (t < nqc && k < d) {
+                const uint2* src = reinterpret_cast<const uint2*>(Qbf + (int64_t)t * d + k);
+                const uint2 lo = src[0], hi = src[1];
+                v = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            }
+            qv[qb][ks] = __builtin_bit_cast(bf16x8, v);
+        }
+    }
+    // Thread t stages vectors t + 256 i of a tile (row x / VPR, vector x %
+    // VPR).  Every load is issued by every thread from a clamped, in-bounds
+    // address (tiles past the split reload its last one), and what lies beyond
+    // d or n is masked only when the vectors are stored: loads under a branch,
+    // or masked at once, make the products wait for them.
+    auto stage_load = [&](int64_t tile, St& g) {
+        tile = tile < te ? tile : te - 1;
+        const uint16_t* xb = Xbf + tile * (int64_t)kDP * d;
+        const int xlim = (int)min((int64_t)(kDP - 1), n - 1 - tile * kDP);
+#pragma unroll
+        for (int i = 0; i < SV; ++i) {
+            const int x = (int)threadIdx.x + 256 * i;
+            const int row = min(x / VPR, xlim);
+            const int k = 8 * (x % VPR);
+            const uint2* src = reinterpret_cast<const uint2*>(xb + row * d + min(k, d - 8));
+            const uint2 lo = src[0], hi = src[1];
+            g.v[i] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+        }
+        const int64_t p = tile * kDP + (threadIdx.x & (kDP - 1));
+        g.pin = p < n;
+        g.xn = xn[g.pin ? p : n - 1];
+        g.bits = bm[(int64_t)tqm * W + tile];
+    };
+    auto stage_store = [&](const St& g, int buf) {
+#pragma unroll
+        for (int i = 0; i < SV; ++i) {
+            const int x = (int)threadIdx.x + 256 * i;
+            const uint32_t keep = 8 * (x % VPR) < d ? 0xffffffffu : 0u;
+            const uint4 v = make_uint4(g.v[i].x & keep, g.v[i].y & keep, g.v[i].z & keep, g.v[i].w & keep);
+            *reinterpret_cast<uint4*>(&sx[buf][(x / VPR) * LD + 8 * (x % VPR)]) = v;
+        }
+        // every thread stores (threads with the same point or query store the
+        // same value): a store under a branch made the compiler wait for all
+        // loads in flight, the other register set's included
+        sh.xb[buf][threadIdx.x & (kDP - 1)] = dense_xb(g.pin ? g.xn : 0.f, margin_c);
+        sh.bits[buf][threadIdx.x & (kDQ - 1)] = g.bits;
+    };
+    St g0, g1;
+    stage_load(tb, g0);
+    stage_store(g0, 0);
+    stage_load(tb + 1, g1);
+    stage_load(tb + 2, g0);
+    __syncthreads();
+    // a(q) of the lane's 16 accumulator rows
+    float areg[4][4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) areg[qb][v] = sh.aq[64 * qh + 16 * qb + 4 * kq + v];
+    const int pi0 = 32 * ph + m;
+    // one tile: products from LDS buffer cur, then the registers g (the next
+    // tile, fetched two tiles ago) go to the other buffer and take the tile
+    // after the next
+    auto tile_step = [&](int64_t tile, St& g) {
+        const int cur = (int)((tile - tb) & 1);
+        const int64_t p0 = tile * kDP;
+        floatx4 acc[4][2];
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+            const float b = -sh.xb[cur][pi0 + 16 * pb];   // accumulator column m is point m
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) acc[qb][pb] = floatx4{b, b, b, b};
+        }
+#pragma unroll
+        for (int ks = 0; ks < NK; ++ks) {
+            bf16x8 xv[2];
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb)
+                xv[pb] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4*>(&sx[cur][(pi0 + 16 * pb) * LD + 32 * ks + 8 * kq]));
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb)
+                    acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[qb][ks], xv[pb], acc[qb][pb], 0, 0, 0);
+        }
+        bool any = false;
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) any |= (acc[qb][0][v] >= areg[qb][v]) | (acc[qb][1][v] >= areg[qb][v]);
+        if (dl_ballot(any) != 0ull) {
+            uint32_t hits = 0;
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t w = (uint32_t)(sh.bits[cur][64 * qh + 16 * qb + 4 * kq + v] >> pi0);
+                    const bool h0 = acc[qb][0][v] >= areg[qb][v] && (w & 1u);
+                    const bool h1 = acc[qb][1][v] >= areg[qb][v] && ((w >> 16) & 1u);
+                    hits |= (h0 ? 1u : 0u) << (8 * qb + 2 * v);
+                    hits |= (h1 ? 1u : 0u) << (8 * qb + 2 * v + 1);
+                }
+            bq_append(hits, sh, qh, pi0, kq, p0);
+        }
+        stage_store(g, cur ^ 1);
+        stage_load(tile + 3, g);
+        __syncthreads();   // next tile staged
+    };
+    // (every path back to the top passes both steps, so the compiler keeps
+    // the order of the two register sets' loads and waits only for the older)
+    for (int64_t tile = tb;; tile += 2) {
+        tile_step(tile, g1);
+        if (tile + 1 >= te) break;
+        tile_step(tile + 1, g0);
+        if (tile + 2 >= te) break;
+    }
+    // The lists are flushed once, after the last tile: one global atomic per
+    // query with survivors reserves their slots (a query has a few survivors
+    // per split).  A list that overflowed sets bit 31 of the query's count,
+    // which is then above any list capacity: the query is verified by the
+    // gathered pass over S instead.
+    if (threadIdx.x < kDQ) {
+        const uint32_t n_all = sh.cnt[threadIdx.x];
+        const uint32_t c = min(n_all, (uint32_t)kBqList);
+        const int tq = qt0 + (int)threadIdx.x;
+        if (n_all > (uint32_t)kBqList) atomicOr(&svc[tq], 0x80000000u);
+        if (c > 0) {
+            const uint32_t base = atomicAdd(&svc[tq], c);
+            for (uint32_t i = 0; i < c; ++i)
+                if ((int64_t)(base + i) < cap_sv) sv[(int64_t)tq * cap_sv + base + i] = sh.list[threadIdx.x][i];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // end of the printed radius ladder (FIXED r_min)
 // ---------------------------------------------------------------------------
@@ -2230,7 +2465,18 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     const bool qlds = al && qbytes <= 80 * 1024;
     const size_t shm = qlds ? qbytes : 0;
     const int ks = (a.d + 15) / 16;
-    if (!a.dense_bf16 && qlds && ks <= 8) {
+    if (a.dense_bf16 && a.d % 8 == 0 && a.d <= 128) {
+#define DL_DENSE_BQ(NK)                                                                                         \
+    hipLaunchKernelGGL((dense_verify_bq_kernel<NK>), dim3((unsigned)blocks), dim3(256), 0, st, a.Xbf, xn, a.n, a.d, \
+                       a.Qbf, a.qn, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv, a.cap_sv, gx, gy,   \
+                       ntiles, tps)
+        const int nk = (a.d + 31) / 32;
+        if (nk <= 1) DL_DENSE_BQ(1);
+        else if (nk == 2) DL_DENSE_BQ(2);
+        else if (nk == 3) DL_DENSE_BQ(3);
+        else DL_DENSE_BQ(4);
+#undef DL_DENSE_BQ
+    } else if (!a.dense_bf16 && qlds && ks <= 8) {
         if (ks <= 4) DL_DENSE(false, true, true, 4);
         else if (ks <= 6) DL_DENSE(false, true, true, 6);
         else DL_DENSE(false, true, true, 8);
