@@ -41,8 +41,9 @@ __host__ __device__ inline size_t ball_align(size_t b) { return (b + 15) & ~(siz
 
 template <int K>
 struct BallDims {
-    static constexpr int NCH = (3 * (K + 3) + 31) / 32; // 32-element BF16 MFMA steps of the three-term form
-    static constexpr int KB = 32 * NCH;                 // K centre terms + 3, three times, padded
+    static constexpr int NCH = (3 * (K + 3) + 1 + 31) / 32; // 32-element BF16 MFMA steps of the three-term form
+    static constexpr int KB = 32 * NCH;   // K centre terms + 3, three times, the sign term, padded
+    static constexpr int KS = 3 * (K + 3);                  // the sign term: point 1, query -2^-100
 };
 
 // x - bf16(x) rounded to BF16 (the difference is exact in FP32).
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(256) void ball_table_kernel(const uint8_t* __restri
         uint16_t h = 0;
         if (k < P || (k >= 2 * P && k < 3 * P)) h = dl_f32_to_bf16(v[k < P ? k : k - 2 * P]);
         else if (k < 2 * P) h = bf16_lo(v[k - P]);
+        else if (k == BallDims<K>::KS) h = dl_f32_to_bf16(1.0f);
         db[k] = h;
     }
 }
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(256) void ball_query_kernel(const float* __restrict
         uint16_t h = 0;
         if (k < 2 * P) h = dl_f32_to_bf16(v[k < P ? k : k - P]);
         else if (k < 3 * P) h = bf16_lo(v[k - 2 * P]);
+        else if (k == BallDims<K>::KS) h = dl_f32_to_bf16(-0x1p-100f);
         db[k] = h;
     }
 }
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
     const int64_t wbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
     const bool live = wbase < n;   // a wave past the last point still takes part in the staging
     bf16x8 Bv[L][4][NCH];
-    uint32_t vbits = 0;
+    uint64_t vmask = 0;   // points of the wave's word inside the set
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int64_t o_raw = wbase + 16 * b + m;
@@ -186,32 +189,62 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
                 Bv[i][b][ch] = *reinterpret_cast<const bf16x8*>(ballb + ((int64_t)i * n + o) * KB + 32 * ch + 8 * kq);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (wbase + 16 * b + 4 * kq + v < n) vbits |= 1u << (4 * b + v);
+    }
+    {
+        const int64_t left = n - wbase;
+        vmask = left >= 64 ? ~0ull : (left > 0 ? (1ull << left) - 1ull : 0ull);
     }
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
     const int64_t word = wbase / 64;
-    // staging: the block's L x 16 x KB BF16 values, 16 bytes per thread and step
+    // staging: the block's L x 16 x KB BF16 values, 16 bytes per thread and
+    // vector, fetched into registers one 16-query block ahead and stored into
+    // the idle LDS buffer after the products (a load stored at once would
+    // make every block wait for L2)
     constexpr int NV = L * 16 * KB / 8;
-    auto stage = [&](int t0, int buf) {
-        for (int x = threadIdx.x; x < NV; x += 256) {
-            const int i = x / (16 * KB / 8), rem = x - i * (16 * KB / 8);
-            const int r = rem / (KB / 8), c8 = rem - r * (KB / 8);
-            const int tq = (t0 + r < tb) ? t0 + r : tb - 1;
-            *reinterpret_cast<uint4*>(&sU[buf][i][r][8 * c8]) =
-                *reinterpret_cast<const uint4*>(uqb + ((int64_t)i * nqc + tq) * KB + 8 * c8);
+    static_assert(NV <= 512, "two staged vectors per thread at most");
+    // vector g of this thread: index min(tid + 256 g, NV - 1) (threads past NV
+    // repeat the last one: same value, same place)
+    auto vec_at = [&](int g, int& i, int& r, int& c8) __attribute__((always_inline)) {
+        const int x = min((int)threadIdx.x + 256 * g, NV - 1);
+        i = x / (16 * KB / 8);
+        const int rem = x - i * (16 * KB / 8);
+        r = rem / (KB / 8);
+        c8 = rem - r * (KB / 8);
+    };
+    uint4 stg0 = make_uint4(0u, 0u, 0u, 0u), stg1 = make_uint4(0u, 0u, 0u, 0u);
+    auto stage_load = [&](int t0) __attribute__((always_inline)) {
+        int i, r, c8;
+        vec_at(0, i, r, c8);
+        stg0 = *reinterpret_cast<const uint4*>(uqb + ((int64_t)i * nqc + min(t0 + r, tb - 1)) * KB + 8 * c8);
+        if constexpr (NV > 256) {
+            vec_at(1, i, r, c8);
+            stg1 = *reinterpret_cast<const uint4*>(uqb + ((int64_t)i * nqc + min(t0 + r, tb - 1)) * KB + 8 * c8);
         }
     };
-    stage(ta, 0);
+    auto stage_store = [&](int buf) __attribute__((always_inline)) {
+        int i, r, c8;
+        vec_at(0, i, r, c8);
+        *reinterpret_cast<uint4*>(&sU[buf][i][r][8 * c8]) = stg0;
+        if constexpr (NV > 256) {
+            vec_at(1, i, r, c8);
+            *reinterpret_cast<uint4*>(&sU[buf][i][r][8 * c8]) = stg1;
+        }
+    };
+    stage_load(ta);
+    stage_store(0);
     __syncthreads();
     int buf = 0;
     for (int t0 = ta; t0 < tb; t0 += 16) {
-        if (t0 + 16 < tb) stage(t0 + 16, buf ^ 1);
+        const bool more = t0 + 16 < tb;
+        stage_load(more ? t0 + 16 : t0);   // the last block reloads itself into the idle buffer
         if (live) {
-            // tree by tree, the minimum over trees kept as it goes
-            floatx4 mn[4];
+            // A pair passes when V_i <= 0 for some tree i.  The sign term makes
+            // every computed V of a pair that can pass strictly negative (with
+            // any nonzero term the margin already does; with none, V is the
+            // sign term alone), so the test is the sign bit of the OR of the
+            // trees' V bit patterns.
+            uint32_t sg[4][4];
 #pragma unroll
             for (int i = 0; i < L; ++i) {
                 floatx4 acc[4];
@@ -227,25 +260,29 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) mn[b][v] = (i == 0) ? acc[b][v] : fminf(mn[b][v], acc[b][v]);
+                    for (int v = 0; v < 4; ++v)
+                        sg[b][v] = (i == 0) ? __float_as_uint(acc[b][v]) : (sg[b][v] | __float_as_uint(acc[b][v]));
             }
-            uint32_t lo = 0, hi = 0;
+            // lane (m, kq) holds query m, points 16 b + 4 kq + v: the sign bits
+            // are shifted in as bit 4 (b & 1) + v of word b >> 1, then each
+            // nibble is moved to bit 16 (b & 1) + 4 kq
+            uint32_t x[2] = {0u, 0u};
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const uint32_t bit = (mn[b][v] <= 0.0f && ((vbits >> (4 * b + v)) & 1u)) ? 1u : 0u;
-                    if (b < 2) lo |= bit << (16 * b + 4 * kq + v);
-                    else hi |= bit << (16 * (b - 2) + 4 * kq + v);
-                }
-            }
+                for (int b = 2 * h + 1; b >= 2 * h; --b)
+#pragma unroll
+                    for (int v = 3; v >= 0; --v) x[h] = __builtin_amdgcn_alignbit(x[h], sg[b][v], 31);
+            uint32_t lo = ((x[0] & 0xfu) | ((x[0] & 0xf0u) << 12)) << (4 * kq);
+            uint32_t hi = ((x[1] & 0xfu) | ((x[1] & 0xf0u) << 12)) << (4 * kq);
             lo |= (uint32_t)__shfl_xor((int)lo, 16);
             hi |= (uint32_t)__shfl_xor((int)hi, 16);
             lo |= (uint32_t)__shfl_xor((int)lo, 32);
             hi |= (uint32_t)__shfl_xor((int)hi, 32);
             if (kq == 0 && t0 + m < tb && word < W)
-                bm[(int64_t)(t0 + m) * W + word] = (uint64_t)lo | ((uint64_t)hi << 32);
+                bm[(int64_t)(t0 + m) * W + word] = ((uint64_t)lo | ((uint64_t)hi << 32)) & vmask;
         }
+        stage_store(buf ^ 1);
         __syncthreads();   // the next block's staging is complete; this one's reads are done
         buf ^= 1;
     }
