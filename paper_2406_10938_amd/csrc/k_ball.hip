@@ -288,8 +288,8 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
     }
 }
 
-constexpr int kExactThreads = 512;   // threads of an exact-pass workgroup; one survivor word each per chunk
-constexpr int kExactList = 2048;     // survivor ids expanded into LDS per pass over a chunk
+constexpr int kExactThreads = 512;   // threads of an exact-pass workgroup: one survivor each per batch
+constexpr int kExactList = 2048;     // ring of survivor ids in LDS (a multiple of kExactThreads)
 
 // Exclusive prefix of per-thread counts over a workgroup of NW waves (every
 // thread takes part); the total goes to *tot.  wtot: NW words of LDS.
@@ -333,7 +333,7 @@ __device__ __forceinline__ uint32_t wg_flag_prefix(bool f, uint32_t* wtot, uint3
 }
 
 struct ExactLds {
-    size_t sE, list, spre, sbits, wtot, total;
+    size_t sE, list, wtot, total;
 };
 
 __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
@@ -341,8 +341,6 @@ __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
     size_t o = 0;
     s.sE = o;    o += ball_align((size_t)LK * N_r * 4);
     s.list = o;  o += ball_align((size_t)kExactList * 4);
-    s.spre = o;  o += ball_align((size_t)kExactThreads * 4);
-    s.sbits = o; o += ball_align((size_t)kExactThreads * 2 * 4);
     s.wtot = o;  o += ball_align(16 * 4 + 4);
     s.total = o;
     return s;
@@ -351,20 +349,21 @@ __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
 // Exact pass: one workgroup per (query, slice of words).  The workgroup first
 // tabulates, for its query, d = q - med3(q, lo, hi) of every (dimension,
 // region) in LDS (the plain filter's first two operations on the same
-// values).  Per chunk of 512 words the screen's survivors are ranked by a
-// workgroup prefix of popcounts and expanded into an LDS list of point ids
-// (2,048 per pass; more passes when a chunk holds more); batches of 512
-// survivors (one per thread) sum fma(d, d, a) over the tabulated d of their
-// regions in the plain filter's order (so the bounds are bit-identical to it,
-// at one LDS read and one fma per term), candidates (m^2 <= thr) are appended
-// to the query's list with one atomic per batch, and the chunk's words are
-// rewritten with the candidates only.
+// values).  The screen's survivors are ranked chunk by chunk (512 words, a
+// workgroup prefix of popcounts) into a ring of point ids in LDS; every full
+// batch of 512 (and the rest at the end) is evaluated one survivor per
+// thread: fma(d, d, a) over the tabulated d of its regions in the plain
+// filter's order, so the bounds are bit-identical to it at one LDS read and
+// one fma per term.  Candidates (m^2 <= thr) are appended to the query's list
+// with one atomic per batch.  The hit words stay the screen's: a superset of
+// the candidates, which is all the verification needs (it re-checks the
+// membership of what it keeps).
 template <int L, int K, bool PREFIX>
 __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     const float* __restrict__ E, int N_r, const uint8_t* __restrict__ codes_pm, int64_t n,
     const float* __restrict__ Qp, int64_t q0, const float* __restrict__ gthr, int64_t words_per_slice,
     uint32_t* __restrict__ counts, int64_t cap, int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
-    float* __restrict__ cand_lb, uint64_t* __restrict__ bm, int64_t W)
+    float* __restrict__ cand_lb, const uint64_t* __restrict__ bm, int64_t W)
 {
     constexpr int LK = L * K;
     constexpr int NB = PREFIX ? dl_prefix_mins(L) : L;
@@ -373,8 +372,6 @@ __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     const ExactLds lay = exact_lds(LK, N_r);
     float* sE = reinterpret_cast<float*>(smem + lay.sE);
     int32_t* list = reinterpret_cast<int32_t*>(smem + lay.list);
-    uint32_t* spre = reinterpret_cast<uint32_t*>(smem + lay.spre);
-    uint32_t* sbits = reinterpret_cast<uint32_t*>(smem + lay.sbits);
     uint32_t* wtot = reinterpret_cast<uint32_t*>(smem + lay.wtot);
     uint32_t* sbase = wtot + 16;
     const int ldE = N_r + 1;
@@ -388,105 +385,107 @@ __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     }
     const int64_t w_lo = (int64_t)blockIdx.y * words_per_slice;
     const int64_t w_hi = (w_lo + words_per_slice < W) ? w_lo + words_per_slice : W;
-    uint64_t* row = bm + (int64_t)t * W;
+    const uint64_t* row = bm + (int64_t)t * W;
     __syncthreads();
+    // evaluates ring entries [head, head + cnt), cnt <= kExactThreads, head a
+    // multiple of kExactThreads
+    auto batch = [&](uint32_t head, uint32_t cnt) {
+        const uint32_t j = threadIdx.x;
+        bool cand = false;
+        int64_t o = 0;
+        float key = 0.f, mins[NB];
+        if (j < cnt) {
+            o = list[(head + j) % kExactList];
+            const uint4* cw = reinterpret_cast<const uint4*>(codes_pm + o * LK);
+            uint32_t words[LK / 4];
+#pragma unroll
+            for (int c = 0; c < LK / 16; ++c) {
+                const uint4 v = cw[c];
+                words[4 * c] = v.x; words[4 * c + 1] = v.y; words[4 * c + 2] = v.z; words[4 * c + 3] = v.w;
+            }
+            float lb[L];
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                float dd[K];
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) {
+                    const int e = i * K + jj;
+                    const uint32_t code = (words[e >> 2] >> (8 * (e & 3))) & 0xffu;
+                    dd[jj] = sE[e * N_r + code];
+                }
+                float acc = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) acc = fmaf(dd[jj], dd[jj], acc);
+                lb[i] = acc;
+            }
+            float m1 = INFINITY, m2 = INFINITY;
+            if constexpr (PREFIX && L >= 3) {
+                m2 = ball_prefix_min<L - 2, L>(lb);
+                m1 = fminf(m2, lb[L - 2]);
+                key = fminf(m1, lb[L - 1]);
+            } else {
+                float run = lb[0];
+#pragma unroll
+                for (int i = 1; i < L - 1; ++i) run = fminf(run, lb[i]);
+                key = L > 1 ? fminf(run, lb[L - 1]) : lb[0];
+            }
+            if constexpr (PREFIX) {
+                if constexpr (L >= 3) { mins[0] = m2; mins[1] = m1; }
+                else if constexpr (L == 2) mins[0] = lb[0];
+                else mins[0] = INFINITY;   // no tree before the last
+            } else {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) mins[i] = lb[i];
+            }
+            cand = key <= th;
+        }
+        uint32_t ctot;
+        const uint32_t cpre = wg_flag_prefix<NW>(cand, wtot, &ctot);
+        if (threadIdx.x == 0) *sbase = ctot ? atomicAdd(&counts[t], ctot) : 0u;
+        __syncthreads();
+        if (cand) {
+            const int64_t idx = (int64_t)*sbase + cpre;
+            if (idx < cap) {
+                const int64_t at = (int64_t)t * cap + idx;
+                cand_id[at] = (int32_t)o;
+                cand_m[at] = key;
+                if constexpr (NB == 2) {
+                    reinterpret_cast<float2*>(cand_lb)[at] = make_float2(mins[0], mins[1]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NB; ++i) cand_lb[at * NB + i] = mins[i];
+                }
+            }
+        }
+        __syncthreads();   // sbase, the scan scratch and the batch's ring entries are reused
+    };
+    uint32_t head = 0, tail = 0;   // ring positions (every thread holds the same values)
     for (int64_t c0 = w_lo; c0 < w_hi; c0 += kExactThreads) {
         const int64_t wi = c0 + threadIdx.x;
         const uint64_t word = (wi < w_hi) ? row[wi] : 0ull;
         uint32_t tot;
         const uint32_t pre = wg_count_prefix<NW>((uint32_t)__popcll(word), wtot, &tot);
-        sbits[2 * threadIdx.x] = 0u;
-        sbits[2 * threadIdx.x + 1] = 0u;
-        for (uint32_t p0 = 0; p0 < tot; p0 += kExactList) {
-            // this thread's survivors with ranks in [p0, p0 + kExactList) into the list
+        for (uint32_t p0 = 0; p0 < tot;) {
+            // ranks [p0, p0 + take) of this chunk go to ring positions tail + (r - p0)
+            const uint32_t take = min(tot - p0, (uint32_t)kExactList - (tail - head));
             uint64_t w = word;
             uint32_t r = pre;
             while (w) {
                 const int bit = __ffsll((unsigned long long)w) - 1;
                 w &= w - 1;
-                if (r >= p0 && r < p0 + kExactList) list[r - p0] = (int32_t)(wi * 64 + bit);
+                if (r >= p0 && r < p0 + take) list[(tail + r - p0) % kExactList] = (int32_t)(wi * 64 + bit);
                 ++r;
             }
             __syncthreads();
-            const uint32_t np = (tot - p0 < (uint32_t)kExactList) ? tot - p0 : (uint32_t)kExactList;
-            for (uint32_t b0 = 0; b0 < np; b0 += kExactThreads) {
-                const uint32_t j = b0 + threadIdx.x;
-                bool cand = false;
-                int64_t o = 0;
-                float key = 0.f, mins[NB];
-                if (j < np) {
-                    o = list[j];
-                    const uint4* cw = reinterpret_cast<const uint4*>(codes_pm + o * LK);
-                    uint32_t words[LK / 4];
-#pragma unroll
-                    for (int c = 0; c < LK / 16; ++c) {
-                        const uint4 v = cw[c];
-                        words[4 * c] = v.x; words[4 * c + 1] = v.y; words[4 * c + 2] = v.z; words[4 * c + 3] = v.w;
-                    }
-                    float lb[L];
-#pragma unroll
-                    for (int i = 0; i < L; ++i) {
-                        float dd[K];
-#pragma unroll
-                        for (int jj = 0; jj < K; ++jj) {
-                            const int e = i * K + jj;
-                            const uint32_t code = (words[e >> 2] >> (8 * (e & 3))) & 0xffu;
-                            dd[jj] = sE[e * N_r + code];
-                        }
-                        float a = 0.0f;
-#pragma unroll
-                        for (int jj = 0; jj < K; ++jj) a = fmaf(dd[jj], dd[jj], a);
-                        lb[i] = a;
-                    }
-                    float m1 = INFINITY, m2 = INFINITY;
-                    if constexpr (PREFIX && L >= 3) {
-                        m2 = ball_prefix_min<L - 2, L>(lb);
-                        m1 = fminf(m2, lb[L - 2]);
-                        key = fminf(m1, lb[L - 1]);
-                    } else {
-                        float run = lb[0];
-#pragma unroll
-                        for (int i = 1; i < L - 1; ++i) run = fminf(run, lb[i]);
-                        key = L > 1 ? fminf(run, lb[L - 1]) : lb[0];
-                    }
-                    if constexpr (PREFIX) {
-                        if constexpr (L >= 3) { mins[0] = m2; mins[1] = m1; }
-                        else if constexpr (L == 2) mins[0] = lb[0];
-                        else mins[0] = INFINITY;   // no tree before the last
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < NB; ++i) mins[i] = lb[i];
-                    }
-                    cand = key <= th;
-                    if (cand) {
-                        const int wl = (int)(o / 64 - c0), bit = (int)(o & 63);
-                        atomicOr(&sbits[2 * wl + (bit >> 5)], 1u << (bit & 31));
-                    }
-                }
-                uint32_t ctot;
-                const uint32_t cpre = wg_flag_prefix<NW>(cand, wtot, &ctot);
-                if (threadIdx.x == 0) *sbase = ctot ? atomicAdd(&counts[t], ctot) : 0u;
-                __syncthreads();
-                if (cand) {
-                    const int64_t idx = (int64_t)*sbase + cpre;
-                    if (idx < cap) {
-                        const int64_t at = (int64_t)t * cap + idx;
-                        cand_id[at] = (int32_t)o;
-                        cand_m[at] = key;
-                        if constexpr (NB == 2) {
-                            reinterpret_cast<float2*>(cand_lb)[at] = make_float2(mins[0], mins[1]);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < NB; ++i) cand_lb[at * NB + i] = mins[i];
-                        }
-                    }
-                }
-                __syncthreads();   // sbase and the scan scratch are reused
+            tail += take;
+            p0 += take;
+            while (tail - head >= (uint32_t)kExactThreads) {
+                batch(head, kExactThreads);
+                head += kExactThreads;
             }
         }
-        if (wi < w_hi) row[wi] = (uint64_t)sbits[2 * threadIdx.x] | ((uint64_t)sbits[2 * threadIdx.x + 1] << 32);
-        __syncthreads();   // the list and sbits are reused by the next chunk
     }
+    if (tail > head) batch(head, tail - head);
 }
 
 template <int L, int K>
@@ -505,8 +504,11 @@ hipError_t launch_ball_screen_lk(const QueryArgs& a, hipStream_t st) {
 
 template <int L, int K>
 hipError_t launch_ball_exact_lk(const QueryArgs& a, hipStream_t st) {
-    // (query, slice of 8,192 words) workgroups
-    const int64_t wps = 8192;
+    // (query, slice of words) workgroups: slices of up to 16,384 words (the
+    // per-query table is built once per slice), halved while the launch would
+    // have fewer than 4,096 workgroups (eight rounds of two per CU)
+    int64_t wps = 16384;
+    while (wps > 1024 && (int64_t)a.nqc * ((a.W + wps - 1) / wps) < 4096) wps /= 2;
     const int64_t nsl = (a.W + wps - 1) / wps;
     const size_t shm = exact_lds(L * K, a.N_r).total;
     if (a.compact_s)
