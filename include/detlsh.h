@@ -23,7 +23,8 @@
  *  - `stream` is a hipStream_t (NULL = the null stream).  Every call that
  *    takes a stream returns only after its results are complete (it
  *    synchronises `stream`), so inputs may be freed and outputs read as soon
- *    as it returns.
+ *    as it returns; detlsh_query_async is the exception (stream-ordered: it
+ *    returns once its work is enqueued).
  *  - Matrices are row-major and densely packed unless stated otherwise.
  *  - An index is read-only after it is built: any number of threads may call
  *    detlsh_query on it concurrently, each with its own stream; every call
@@ -246,6 +247,27 @@ enum {
 detlsh_status detlsh_query(detlsh_index idx, const float* Q, int64_t nq, int32_t k,
                            double c, double beta, const detlsh_query_opts* opts,
                            int64_t* out_ids, float* out_dists, void* stream);
+
+/*
+ * detlsh_query in stream order: every step is enqueued on `stream` after the
+ * work already there, and the call returns without waiting for the device
+ * (no host synchronisation anywhere on its path).  Q must stay valid, and the
+ * outputs unread, until the stream has run past the call (for example: an
+ * event recorded after it has completed, or a later synchronisation); its
+ * workspace is reused by later calls only after that point.  Arguments,
+ * limits and results are those of detlsh_query, plus out_status (device, nq
+ * int32), written on the stream: 0 for a query answered as detlsh_query
+ * answers it, 1 (MAGIC) when its candidate count left the planned range
+ * [N_S, cap] of the sampled magic radius, 3 (FIXED) when the radius ladder
+ * ended without a stop.  For a nonzero status the query's outputs are
+ * unspecified: detlsh_query answers it (it runs those fallbacks itself; the
+ * first is a probability below 1e-6 per query by the planned margins).
+ * Calls on different streams run concurrently on the device.
+ */
+detlsh_status detlsh_query_async(detlsh_index idx, const float* Q, int64_t nq, int32_t k,
+                                 double c, double beta, const detlsh_query_opts* opts,
+                                 int64_t* out_ids, float* out_dists, int32_t* out_status,
+                                 void* stream);
 
 /*
  * (r, c)-ANN query (Alg. 6) for nq rows of Q (device, nq x d FP32) with one

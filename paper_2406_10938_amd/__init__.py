@@ -126,6 +126,26 @@ class Index:
                                  _ptr(dists), _stream_ptr()))
         return ids, dists
 
+    def query_async(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC,
+                    r_min=0.0, max_rounds=0, workspace_bytes=0, verify="auto", granularity="point",
+                    filter="auto"):
+        """detlsh_query_async on torch's current stream: returns (ids, dists,
+        status) as soon as the work is enqueued.  The outputs are allocated on
+        that stream and are complete once the stream has run past the call;
+        Q must not be freed or overwritten before then.  status[q] != 0 marks
+        a query that needs one of detlsh_query's fallbacks."""
+        torch = _torch()
+        Q = _dev_f32(Q, "Q")
+        nq = Q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        status = torch.empty(nq, dtype=torch.int32, device=Q.device)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, workspace_bytes, verify, granularity,
+                        filter)
+        check(lib().detlsh_query_async(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
+                                       _ptr(dists), _ptr(status), _stream_ptr()))
+        return ids, dists, status
+
     def query_noalloc(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, verify="auto",
                       granularity="point"):
         """detlsh_query inside the library's fixed device array: the call

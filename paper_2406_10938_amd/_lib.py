@@ -80,6 +80,8 @@ SIGNATURES = {
     "detlsh_project": (C.c_int, [P, P, C.c_int64, P, P]),
     "detlsh_query": (C.c_int, [P, P, C.c_int64, C.c_int32, C.c_double, C.c_double, C.POINTER(QueryOpts), P, P,
                                P]),
+    "detlsh_query_async": (C.c_int, [P, P, C.c_int64, C.c_int32, C.c_double, C.c_double, C.POINTER(QueryOpts),
+                                     P, P, P, P]),
     "detlsh_query_debug": (C.c_int, [P, P, P, C.c_int64, C.c_int32, C.c_double, C.c_double,
                                      C.POINTER(QueryOpts), P, C.c_int64, P, P, P, P, P, P, P, P]),
     "detlsh_query_noalloc": (C.c_int, [P, P, C.c_int64, C.c_int32, C.c_double, C.c_double, C.POINTER(QueryOpts),

@@ -86,10 +86,26 @@ struct DevBuf {
 // may be gone); the driver reclaims the memory at process exit.
 constexpr size_t kWsIdle = 32;
 
+// A buffer handed back by a stream-ordered call carries an event recorded
+// after its last use: it is idle once the event has completed.
+struct WsEntry {
+    int dev;
+    DevBuf* b;
+    hipEvent_t ev;   // nullptr: idle now
+};
+
 struct WsCache {
     std::mutex mu;
-    std::vector<std::pair<int, DevBuf*>> idle;   // (device, buffer)
+    std::vector<WsEntry> idle;
 };
+
+bool ws_ready(const WsEntry& e) {
+    if (!e.ev) return true;
+    const hipError_t r = hipEventQuery(e.ev);
+    if (r == hipErrorNotReady) return false;
+    (void)hipGetLastError();
+    return true;
+}
 WsCache& ws_cache() {
     static WsCache* c = new WsCache;
     return *c;
@@ -101,11 +117,12 @@ DevBuf* ws_cached(int dev, size_t bytes, size_t max_bytes) {
     std::lock_guard<std::mutex> lk(c.mu);
     size_t best = c.idle.size();
     for (size_t i = 0; i < c.idle.size(); ++i)
-        if (c.idle[i].first == dev && c.idle[i].second->bytes >= bytes && c.idle[i].second->bytes <= max_bytes &&
-            (best == c.idle.size() || c.idle[i].second->bytes < c.idle[best].second->bytes))
+        if (c.idle[i].dev == dev && c.idle[i].b->bytes >= bytes && c.idle[i].b->bytes <= max_bytes &&
+            (best == c.idle.size() || c.idle[i].b->bytes < c.idle[best].b->bytes) && ws_ready(c.idle[i]))
             best = i;
     if (best == c.idle.size()) return nullptr;
-    DevBuf* b = c.idle[best].second;
+    DevBuf* b = c.idle[best].b;
+    if (c.idle[best].ev) (void)hipEventDestroy(c.idle[best].ev);
     c.idle.erase(c.idle.begin() + (std::ptrdiff_t)best);
     return b;
 }
@@ -124,25 +141,42 @@ DevBuf* ws_take(int dev, size_t bytes) {
     return b.release();
 }
 
-void ws_give(int dev, DevBuf* b) {
+// Hands b to the cache; with `after`, once the work enqueued on that stream
+// so far has completed (an event marks the point; the caller does not wait).
+// Dropping a buffer beyond the cache's limit frees it, which waits for the
+// device.
+void ws_give(int dev, DevBuf* b, hipStream_t after = nullptr, bool ordered = false) {
+    hipEvent_t ev = nullptr;
+    if (ordered) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev, after) != hipSuccess) {
+            (void)hipGetLastError();
+            if (ev) (void)hipEventDestroy(ev);
+            (void)hipStreamSynchronize(after);   // the event failed: wait here instead
+            (void)hipGetLastError();
+            ev = nullptr;
+        }
+    }
     WsCache& c = ws_cache();
     DevBuf* drop = nullptr;
+    hipEvent_t drop_ev = nullptr;
     {
         std::lock_guard<std::mutex> lk(c.mu);
-        c.idle.emplace_back(dev, b);
+        c.idle.push_back({dev, b, ev});
         size_t on_dev = 0, smallest = c.idle.size();
         for (size_t i = 0; i < c.idle.size(); ++i)
-            if (c.idle[i].first == dev) {
+            if (c.idle[i].dev == dev) {
                 ++on_dev;
-                if (smallest == c.idle.size() || c.idle[i].second->bytes < c.idle[smallest].second->bytes)
-                    smallest = i;
+                if (smallest == c.idle.size() || c.idle[i].b->bytes < c.idle[smallest].b->bytes) smallest = i;
             }
         if (on_dev > kWsIdle) {
-            drop = c.idle[smallest].second;
+            drop = c.idle[smallest].b;
+            drop_ev = c.idle[smallest].ev;
             c.idle.erase(c.idle.begin() + (std::ptrdiff_t)smallest);
         }
     }
     delete drop;
+    if (drop_ev) (void)hipEventDestroy(drop_ev);
 }
 
 // Allocation of an index array (current device `dev`): an idle cached buffer
@@ -165,15 +199,16 @@ hipError_t pool_alloc(DevBuf& dst, size_t bytes, int dev) {
     return dst.alloc(bytes);
 }
 
-// Hands an idle index array to the cache.
-void pool_give(DevBuf& src, int dev) {
+// Hands an idle index array to the cache (ordered: once the work enqueued on
+// `after` so far has completed).
+void pool_give(DevBuf& src, int dev, hipStream_t after = nullptr, bool ordered = false) {
     if (!src.p) return;
     DevBuf* b = new DevBuf;
     b->p = src.p;
     b->bytes = src.bytes;
     src.p = nullptr;
     src.bytes = 0;
-    ws_give(dev, b);
+    ws_give(dev, b, after, ordered);
 }
 
 // A workspace held by one call: returned to the cache when the call marks it
@@ -183,9 +218,12 @@ struct WsLease {
     int dev = 0;
     DevBuf* b = nullptr;
     bool idle = false;
+    bool ordered = false;          // idle once `after` has run the work enqueued so far
+    hipStream_t after = nullptr;
     ~WsLease() {
         if (!b) return;
         if (idle) ws_give(dev, b);
+        else if (ordered) ws_give(dev, b, after, true);
         else delete b;
     }
 };
@@ -913,7 +951,10 @@ void detlsh_trim(void) {
     {
         WsCache& c = ws_cache();
         std::lock_guard<std::mutex> lk(c.mu);
-        for (auto& e : c.idle) drop.push_back(e.second);
+        for (auto& e : c.idle) {
+            drop.push_back(e.b);
+            if (e.ev) (void)hipEventDestroy(e.ev);   // hipFree below waits for the device
+        }
         c.idle.clear();
     }
     for (DevBuf* b : drop) delete b;
@@ -930,6 +971,7 @@ detlsh_status detlsh_profile_enable(int32_t on, int32_t reset) {
 
 detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double* total_ms, int32_t max,
                                   int32_t* count) {
+    prof_resolve();   // timings of stream-ordered calls still in flight (waits for them)
     std::lock_guard<std::mutex> lk(g_prof.mu);
     int c = 0;
     for (int i = 0; i < T_COUNT && c < max; ++i, ++c) {
@@ -1101,9 +1143,14 @@ struct Arena {
 
 constexpr int64_t kQueryTile = 128;   // queries per workgroup tile of the dense verification
 
+// status_dev == nullptr: the per-query status goes to status_host and the
+// call returns with its stream drained.  Otherwise (stream-ordered) it goes to
+// status_dev on the stream, nothing waits, and the workspace returns to the
+// cache once the stream has run past the last launch.
 detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, int64_t q0, int64_t nq, int k,
                           const QueryPlan& plan, bool force_all_candidates, const Arena& arena, int64_t* out_ids,
-                          float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st) {
+                          float* out_d, const Debug& dbg, std::vector<int32_t>& status_host, hipStream_t st,
+                          int32_t* status_dev = nullptr) {
     // candidate rows start 16-byte aligned (vector loads in the selection)
     const int64_t cap = round4((force_all_candidates || plan.fixed) ? ix->n : plan.cap);
     const bool dumps = dbg.cand_ids || dbg.cand_counts || dbg.first_tree;
@@ -1125,6 +1172,8 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         own.dev = ix->device;
         own.b = ws_take(ix->device, pq * (size_t)nqc);
         if (!own.b) return fail(DETLSH_ENOMEM, "query workspace of %zu bytes", pq * (size_t)nqc);
+        own.ordered = status_dev != nullptr;
+        own.after = st;
         p = own.b->as<char>();
     }
     auto take = [&](size_t b) { char* r = p; p += (b + 255) & ~(size_t)255; return r; };
@@ -1196,7 +1245,6 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         a.uqb = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->L * dl_ball_width_bf16(ix->K) * 2));
     }
     a.out_ids = out_ids; a.out_d = out_d;
-    std::vector<float> inf_host;
     std::vector<uint32_t> sc_host;
     for (int64_t c0 = 0; c0 < nq; c0 += nqc) {
         const int cnt = (int)std::min<int64_t>(nqc, nq - c0);
@@ -1204,8 +1252,8 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         a.nqc = cnt;
         if (plan.fixed) {
             HCHECK(hipMemsetAsync(a.counts, 0, (size_t)cnt * 4, st));
-            inf_host.assign(cnt, (float)((double)plan.rounds * ix->L));   // every point that ever enters
-            HCHECK(hipMemcpyAsync(a.gthr, inf_host.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, st));
+            // every point that ever enters
+            HCHECK(dl_launch_fill_f32(a.gthr, (float)((double)plan.rounds * ix->L), cnt, st));
             {
                 DlTimer tm(T_FILTER, st);
                 HCHECK(dl_launch_filter(a, st));
@@ -1221,8 +1269,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         } else if (!plan.all) {
             HCHECK(hipMemsetAsync(a.counts, 0, (size_t)cnt * 4, st));
             if (force_all_candidates) {
-                inf_host.assign(cnt, INFINITY);
-                HCHECK(hipMemcpyAsync(a.gthr, inf_host.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, st));
+                HCHECK(dl_launch_fill_f32(a.gthr, INFINITY, cnt, st));
             } else {
                 DlTimer tm(T_GUESS, st);
                 HCHECK(dl_launch_guess(a, st));
@@ -1271,7 +1318,10 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
             DlTimer tm(T_VERIFY, st);
             HCHECK(dl_launch_verify(a, 0, st));
         }
-        HCHECK(hipMemcpyAsync(status_host.data() + c0, a.status, (size_t)cnt * 4, hipMemcpyDeviceToHost, st));
+        if (status_dev)
+            HCHECK(hipMemcpyAsync(status_dev + c0, a.status, (size_t)cnt * 4, hipMemcpyDeviceToDevice, st));
+        else
+            HCHECK(hipMemcpyAsync(status_host.data() + c0, a.status, (size_t)cnt * 4, hipMemcpyDeviceToHost, st));
         if (dbg.cand_ids || dbg.cand_counts || dbg.first_tree || dbg.thr || dbg.stop_tree || dbg.rounds) {
             HCHECK(hipStreamSynchronize(st));
             sc_host.resize(cnt);
@@ -1302,6 +1352,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
             }
         }
     }
+    if (status_dev) return DETLSH_OK;   // the lease goes back to the cache ordered after the stream
     HCHECK(hipStreamSynchronize(st));
     own.idle = true;
     return DETLSH_OK;
@@ -1315,7 +1366,8 @@ struct QuerySetup {
     int rmult = 4;
     int rounds = 64;
     QueryPlan plan;
-    std::vector<float> ladder;   // FIXED: (eps r_t)^2 then (c r_t)^2, t < rounds
+    std::vector<float> ladder;   // FIXED: room for (eps r_t)^2 then (c r_t)^2, t < rounds
+    double eps = 0.0, r_min = 0.0, c = 0.0;   // FIXED: what the ladder is formed from
 };
 
 detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, double c, double beta,
@@ -1361,13 +1413,10 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
         // radii r_t = r_min c^t (formed by repeated multiplication), squared
         // projected radius (eps r_t)^2 and squared verification radius (c r_t)^2
         const double eps = std::sqrt(chi2_upper_quantile_even(std::exp(-1.0 / ix->L), ix->K));
-        s.ladder.assign(2 * (size_t)s.rounds, 0.f);
-        double r = opts->r_min;
-        for (int t = 0; t < s.rounds; ++t) {
-            s.ladder[t] = (float)((eps * r) * (eps * r));
-            s.ladder[s.rounds + t] = (float)((c * r) * (c * r));
-            r *= c;
-        }
+        s.eps = eps;
+        s.r_min = opts->r_min;
+        s.c = c;
+        s.ladder.assign(2 * (size_t)s.rounds, 0.f);   // sized here, formed on the device (dl_launch_ladder)
         plan.fixed = true;
         plan.all = false;
         plan.rounds = s.rounds;
@@ -1470,8 +1519,7 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
             HCHECK(pool_alloc(ladder, s.ladder.size() * 4, ix->device));
             lad = ladder.as<float>();
         }
-        HCHECK(hipMemcpyAsync(lad, s.ladder.data(), s.ladder.size() * 4, hipMemcpyHostToDevice, st));
-        HCHECK(hipStreamSynchronize(st));
+        HCHECK(dl_launch_ladder(lad, s.rounds, s.eps, s.r_min, s.c, st));
         plan.rad2 = lad;
         plan.c2 = lad + s.rounds;
     }
@@ -1507,6 +1555,48 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     pool_give(ladder, ix->device);
     prof_resolve();
     return DETLSH_OK;
+}
+
+// Stream-ordered form: every launch goes on `st` and nothing waits; the
+// temporaries and the workspace return to the cache ordered after the stream.
+// A query that needs one of the fallbacks keeps its status (1 or 3) in
+// out_status instead of being re-run.
+detlsh_status query_async_impl(detlsh_index ix, const float* Q, int64_t nq, int32_t k, double c, double beta,
+                               const detlsh_query_opts* opts, int64_t* out_ids, float* out_d, int32_t* out_status,
+                               hipStream_t st) {
+    g_err.clear();
+    QuerySetup s;
+    if (detlsh_status e = setup_query(ix, nq, k, c, beta, opts, s)) return e;
+    if (nq == 0) return DETLSH_OK;
+    if (!is_device_ptr(Q)) return fail(DETLSH_EINVAL, "Q must be a device pointer");
+    if (!is_device_ptr(out_ids) || !is_device_ptr(out_d) || !is_device_ptr(out_status))
+        return fail(DETLSH_EINVAL, "outputs must be device pointers");
+    HCHECK(hipSetDevice(ix->device));
+    QueryPlan& plan = s.plan;
+    Arena arena;
+    arena.bytes = (opts && opts->workspace_bytes) ? opts->workspace_bytes : ((size_t)8 << 30);
+    DevBuf qpbuf, ladder;
+    struct Ordered {   // the temporaries go back once the stream is past this call's work
+        DevBuf& a; DevBuf& b; int dev; hipStream_t st;
+        ~Ordered() { pool_give(a, dev, st, true); pool_give(b, dev, st, true); }
+    } ordered{qpbuf, ladder, ix->device, st};
+    HCHECK(pool_alloc(qpbuf, (size_t)nq * ix->LK * 4, ix->device));
+    {
+        ProjectArgs pa;
+        pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK; pa.Pout = qpbuf.as<float>();
+        DlTimer tm(T_QPROJECT, st);
+        HCHECK(dl_launch_project(pa, PROJ_ROWMAJOR, st));
+    }
+    if (plan.fixed) {
+        HCHECK(pool_alloc(ladder, s.ladder.size() * 4, ix->device));
+        HCHECK(dl_launch_ladder(ladder.as<float>(), s.rounds, s.eps, s.r_min, s.c, st));
+        plan.rad2 = ladder.as<float>();
+        plan.c2 = plan.rad2 + s.rounds;
+    }
+    std::vector<int32_t> unused;
+    Debug dbg;
+    return run_queries(ix, Q, qpbuf.as<float>(), 0, nq, k, plan, false, arena, out_ids, out_d, dbg, unused, st,
+                       out_status);
 }
 
 }  // namespace
@@ -1557,6 +1647,13 @@ detlsh_status detlsh_query(detlsh_index ix, const float* Q, int64_t nq, int32_t 
     Debug dbg;
     return query_impl(ix, nullptr, Q, nq, k, c, beta, opts, out_ids, out_dists, dbg, nullptr,
                       static_cast<hipStream_t>(stream));
+}
+
+detlsh_status detlsh_query_async(detlsh_index ix, const float* Q, int64_t nq, int32_t k, double c, double beta,
+                                 const detlsh_query_opts* opts, int64_t* out_ids, float* out_dists,
+                                 int32_t* out_status, void* stream) {
+    return query_async_impl(ix, Q, nq, k, c, beta, opts, out_ids, out_dists, out_status,
+                            static_cast<hipStream_t>(stream));
 }
 
 detlsh_status detlsh_query_rc(detlsh_index ix, const float* Q, int64_t nq, double r, double c, double beta,

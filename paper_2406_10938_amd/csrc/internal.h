@@ -165,6 +165,10 @@ hipError_t dl_launch_ball_exact(const QueryArgs& a, hipStream_t st);
 // Issue-rate probe of the range filter's bound arithmetic (L = 4, K = 16):
 // `lanes` (a multiple of 256) synthetic cells against nq projected queries.
 hipError_t dl_launch_valu_probe(const float* qp, int nq, float* out, int64_t lanes, hipStream_t st);
+// p[0..n) = v, on the stream
+hipError_t dl_launch_fill_f32(float* p, float v, int64_t n, hipStream_t st);
+// the FIXED radius ladder (eps r_t)^2, then (c r_t)^2, r_t = r_min c^t, t < rounds
+hipError_t dl_launch_ladder(float* out, int rounds, double eps, double r_min, double c, hipStream_t st);
 size_t dl_verify_smem(int d);
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
 // leaf_of of one tree: out[perm[p]] = the leaf whose run holds position p.

@@ -2517,3 +2517,41 @@ hipError_t dl_launch_fixed_finish(const QueryArgs& a, int32_t* rounds, hipStream
 }
 
 size_t dl_verify_smem(int d) { return sizeof(TopkShared) + (size_t)d * 4 + 64; }
+
+// ---------------------------------------------------------------------------
+// small stream-ordered fills (no host buffer to keep alive)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void fill_f32_kernel(float* __restrict__ p, float v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// The radius ladder of Alg. 7 from r_min: r_t = r_min c^t formed by repeated
+// multiplication in FP64, out[t] = (eps r_t)^2 and out[rounds + t] = (c r_t)^2
+// rounded to FP32 (the same operations, in the same order, as on the host).
+__global__ void ladder_kernel(float* __restrict__ out, int rounds, double eps, double r_min, double c) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double r = r_min;
+    for (int t = 0; t < rounds; ++t) {
+        const double er = eps * r, cr = c * r;
+        out[t] = (float)(er * er);
+        out[rounds + t] = (float)(cr * cr);
+        r *= c;
+    }
+}
+
+}  // namespace
+
+hipError_t dl_launch_fill_f32(float* p, float v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t dl_launch_ladder(float* out, int rounds, double eps, double r_min, double c, hipStream_t st) {
+    hipLaunchKernelGGL(ladder_kernel, dim3(1), dim3(64), 0, st, out, rounds, eps, r_min, c);
+    return hipGetLastError();
+}
