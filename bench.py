@@ -88,14 +88,18 @@ def counted_traffic(kernel):
 # ---------------------------------------------------------------------------
 
 FORMS = {
-    # FP32 projection, FP32-product dense verification, exact FP32 ranking
-    "fp32": {"build": {"keep_bf16": False}, "query": {"verify": "dense"},
-             "dtype": "f32", "what": "plain FP32: FP32 projection, FP32-product verification, FP32 ranking"},
-    # the same results bit for bit: a BF16-product screen with a bound widened by
-    # the BF16 rounding decides which members of S reach the FP32 ranking
+    # FP32 arithmetic throughout: FP32 projection, the plain VALU range filter,
+    # FP32-product dense verification, exact FP32 ranking
+    "fp32": {"build": {"keep_bf16": False}, "query": {"verify": "dense", "filter": "plain"},
+             "dtype": "f32", "what": "plain FP32: FP32 projection, FP32 range filter, FP32-product verification, "
+                                     "FP32 ranking"},
+    # the same results bit for bit: BF16-product screens with proven margins
+    # (the range filter's ball screen, and the verification's screen with a
+    # bound widened by the BF16 rounding) decide which pairs reach the exact
+    # FP32 bounds and distances
     "fp32_bf16screen": {"build": {"keep_bf16": True}, "query": {},
-                        "dtype": "f32", "what": "exact FP32 results through a BF16-product screen (identical "
-                                                "answers to plain FP32)"},
+                        "dtype": "f32", "what": "exact FP32 results through BF16-product screens of the range filter "
+                                                "and the verification (identical answers to plain FP32)"},
     # BF16 projection and products, top-4k reranked with exact FP32 distances
     "bf16_rerank": {"build": {"keep_bf16": True, "proj_bf16": True}, "query": {"rerank_mult": 4},
                     "dtype": "bf16", "what": "BF16 projection and verification products (FP32 accumulate), "
@@ -724,9 +728,12 @@ def main():
                          "dtype": FORMS[form]["dtype"], "what": FORMS[form]["what"]}
         log(f"[bench] {form}: {results[form]['value']:.0f} q/s whole step ({ms_step:.1f} ms; build "
             f"{build_ms:.1f} ms), recall@{k} {rec:.4f}, overall ratio {rat:.6f}")
-    head = "fp32" if "fp32" in results else forms[0]
+    # the headline is the fastest form at recall@k >= 0.9 (every form is in
+    # "forms", the plain FP32 one included)
+    ok = [f for f in results if results[f]["recall_at_k"] >= 0.9] or list(results)
+    head = max(ok, key=lambda f: results[f]["value"])
     hr = results[head]
-    roof = roofline(hr["kernels"], args.steps, cfg, nq, k, beta, n, d, probe)
+    roof = roofline(hr["kernels"], args.steps, cfg, nq, k, beta, n, d, probe, bf16_products=head != "fp32")
 
     cpu = None
     if not args.no_cpu:
@@ -778,7 +785,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"normalised 1,024-component Gaussian mixture n=10,000,000 d=96 (unit vectors), "
                                 f"10,000 queries, k={k} c=1.5 beta={beta} (smallest grid beta with recall@10 >= "
-                                f"0.9), L=4 K=16 N_r=256, 1% sample; step = build + query batch; form {head}"),
+                                f"0.9), L=4 K=16 N_r=256, 1% sample; step = build + query batch; form {head}: "
+                                f"{FORMS[head]['what']} (the fastest form at recall@{k} >= 0.9; all forms under "
+                                f"'forms')"),
                    "n": n, "d": d, "nq": nq, "k": k, "beta": beta, "L": cfg.L, "K": cfg.K, "N_r": cfg.N_r,
                    "form": head},
         "recall_at_k": hr["recall_at_k"],
