@@ -172,7 +172,9 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
     // rows padded by 16 bytes: with a 128-byte stride the 16 query rows one
     // MFMA operand reads would all start in the same LDS bank
     constexpr int LDU = KB + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t sU[2][L][16][LDU];
+    constexpr int QS = 2;          // 16-query sets per staged block (fewer barriers per product)
+    constexpr int QB = 16 * QS;    // queries per staged block
+    __shared__ __attribute__((aligned(16))) uint16_t sU[2][L][QB][LDU];
     const int lane = threadIdx.x & 63;
     const int m = lane & 15;
     const int kq = lane >> 4;
@@ -197,90 +199,93 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
     const int64_t word = wbase / 64;
-    // staging: the block's L x 16 x KB BF16 values, 16 bytes per thread and
-    // vector, fetched into registers one 16-query block ahead and stored into
-    // the idle LDS buffer after the products (a load stored at once would
-    // make every block wait for L2)
-    constexpr int NV = L * 16 * KB / 8;
-    static_assert(NV <= 512, "two staged vectors per thread at most");
-    // vector g of this thread: index min(tid + 256 g, NV - 1) (threads past NV
-    // repeat the last one: same value, same place)
-    auto vec_at = [&](int g, int& i, int& r, int& c8) __attribute__((always_inline)) {
+    // staging: the block's L x QB x KB BF16 values, 16 bytes per thread and
+    // vector, fetched into registers one block ahead and stored into the idle
+    // LDS buffer after the products (a load stored at once would make every
+    // block wait for L2).  Vector g of this thread has index min(tid + 256 g,
+    // NV - 1) (threads past NV repeat the last one: same value, same place).
+    constexpr int NV = L * QB * KB / 8;
+    constexpr int NSTG = (NV + 255) / 256;
+    uint4 stg[NSTG];
+#pragma unroll
+    for (int g = 0; g < NSTG; ++g) stg[g] = make_uint4(0u, 0u, 0u, 0u);
+    int soff[NSTG];   // the vectors' LDS element offsets within a buffer, and their rows
+    int srow[NSTG];
+    int64_t sglb[NSTG];
+#pragma unroll
+    for (int g = 0; g < NSTG; ++g) {
         const int x = min((int)threadIdx.x + 256 * g, NV - 1);
-        i = x / (16 * KB / 8);
-        const int rem = x - i * (16 * KB / 8);
-        r = rem / (KB / 8);
-        c8 = rem - r * (KB / 8);
-    };
-    uint4 stg0 = make_uint4(0u, 0u, 0u, 0u), stg1 = make_uint4(0u, 0u, 0u, 0u);
+        const int i = x / (QB * KB / 8);
+        const int rem = x - i * (QB * KB / 8);
+        const int r = rem / (KB / 8), c8 = rem - r * (KB / 8);
+        soff[g] = (i * QB + r) * LDU + 8 * c8;
+        srow[g] = r;
+        sglb[g] = (int64_t)i * nqc * KB + 8 * c8;
+    }
     auto stage_load = [&](int t0) __attribute__((always_inline)) {
-        int i, r, c8;
-        vec_at(0, i, r, c8);
-        stg0 = *reinterpret_cast<const uint4*>(uqb + ((int64_t)i * nqc + min(t0 + r, tb - 1)) * KB + 8 * c8);
-        if constexpr (NV > 256) {
-            vec_at(1, i, r, c8);
-            stg1 = *reinterpret_cast<const uint4*>(uqb + ((int64_t)i * nqc + min(t0 + r, tb - 1)) * KB + 8 * c8);
-        }
+#pragma unroll
+        for (int g = 0; g < NSTG; ++g)
+            stg[g] = *reinterpret_cast<const uint4*>(uqb + sglb[g] + (int64_t)min(t0 + srow[g], tb - 1) * KB);
     };
     auto stage_store = [&](int buf) __attribute__((always_inline)) {
-        int i, r, c8;
-        vec_at(0, i, r, c8);
-        *reinterpret_cast<uint4*>(&sU[buf][i][r][8 * c8]) = stg0;
-        if constexpr (NV > 256) {
-            vec_at(1, i, r, c8);
-            *reinterpret_cast<uint4*>(&sU[buf][i][r][8 * c8]) = stg1;
-        }
+#pragma unroll
+        for (int g = 0; g < NSTG; ++g) *reinterpret_cast<uint4*>(&sU[buf][0][0][0] + soff[g]) = stg[g];
     };
     stage_load(ta);
     stage_store(0);
     __syncthreads();
     int buf = 0;
-    for (int t0 = ta; t0 < tb; t0 += 16) {
-        const bool more = t0 + 16 < tb;
-        stage_load(more ? t0 + 16 : t0);   // the last block reloads itself into the idle buffer
+    for (int t0 = ta; t0 < tb; t0 += QB) {
+        const bool more = t0 + QB < tb;
+        stage_load(more ? t0 + QB : t0);   // the last block reloads itself into the idle buffer
         if (live) {
-            // A pair passes when V_i <= 0 for some tree i.  The sign term makes
-            // every computed V of a pair that can pass strictly negative (with
-            // any nonzero term the margin already does; with none, V is the
-            // sign term alone), so the test is the sign bit of the OR of the
-            // trees' V bit patterns.
-            uint32_t sg[4][4];
 #pragma unroll
-            for (int i = 0; i < L; ++i) {
-                floatx4 acc[4];
+            for (int qs = 0; qs < QS; ++qs) {
+                // A pair passes when V_i <= 0 for some tree i.  The sign term
+                // makes every computed V of a pair that can pass strictly
+                // negative (with any nonzero term the margin already does; with
+                // none, V is the sign term alone), so the test is the sign bit
+                // of the OR of the trees' V bit patterns.
+                uint32_t sg[4][4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int i = 0; i < L; ++i) {
+                    floatx4 acc[4];
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const bf16x8 qv = *reinterpret_cast<const bf16x8*>(&sU[buf][i][m][32 * ch + 8 * kq]);
+                    for (int b = 0; b < 4; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        const bf16x8 qv =
+                            *reinterpret_cast<const bf16x8*>(&sU[buf][i][16 * qs + m][32 * ch + 8 * kq]);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bv[i][b][ch], qv, acc[b], 0, 0, 0);
+                    }
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bv[i][b][ch], qv, acc[b], 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            sg[b][v] = (i == 0) ? __float_as_uint(acc[b][v]) : (sg[b][v] | __float_as_uint(acc[b][v]));
                 }
+                // lane (m, kq) holds query m of the set, points 16 b + 4 kq + v:
+                // the sign bits are shifted in as bit 4 (b & 1) + v of word
+                // b >> 1, then each nibble is moved to bit 16 (b & 1) + 4 kq
+                uint32_t x[2] = {0u, 0u};
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        sg[b][v] = (i == 0) ? __float_as_uint(acc[b][v]) : (sg[b][v] | __float_as_uint(acc[b][v]));
+                    for (int b = 2 * h + 1; b >= 2 * h; --b)
+#pragma unroll
+                        for (int v = 3; v >= 0; --v) x[h] = __builtin_amdgcn_alignbit(x[h], sg[b][v], 31);
+                uint32_t lo = ((x[0] & 0xfu) | ((x[0] & 0xf0u) << 12)) << (4 * kq);
+                uint32_t hi = ((x[1] & 0xfu) | ((x[1] & 0xf0u) << 12)) << (4 * kq);
+                lo |= (uint32_t)__shfl_xor((int)lo, 16);
+                hi |= (uint32_t)__shfl_xor((int)hi, 16);
+                lo |= (uint32_t)__shfl_xor((int)lo, 32);
+                hi |= (uint32_t)__shfl_xor((int)hi, 32);
+                const int t = t0 + 16 * qs + m;
+                if (kq == 0 && t < tb && word < W)
+                    bm[(int64_t)t * W + word] = ((uint64_t)lo | ((uint64_t)hi << 32)) & vmask;
             }
-            // lane (m, kq) holds query m, points 16 b + 4 kq + v: the sign bits
-            // are shifted in as bit 4 (b & 1) + v of word b >> 1, then each
-            // nibble is moved to bit 16 (b & 1) + 4 kq
-            uint32_t x[2] = {0u, 0u};
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int b = 2 * h + 1; b >= 2 * h; --b)
-#pragma unroll
-                    for (int v = 3; v >= 0; --v) x[h] = __builtin_amdgcn_alignbit(x[h], sg[b][v], 31);
-            uint32_t lo = ((x[0] & 0xfu) | ((x[0] & 0xf0u) << 12)) << (4 * kq);
-            uint32_t hi = ((x[1] & 0xfu) | ((x[1] & 0xf0u) << 12)) << (4 * kq);
-            lo |= (uint32_t)__shfl_xor((int)lo, 16);
-            hi |= (uint32_t)__shfl_xor((int)hi, 16);
-            lo |= (uint32_t)__shfl_xor((int)lo, 32);
-            hi |= (uint32_t)__shfl_xor((int)hi, 32);
-            if (kq == 0 && t0 + m < tb && word < W)
-                bm[(int64_t)(t0 + m) * W + word] = ((uint64_t)lo | ((uint64_t)hi << 32)) & vmask;
         }
         stage_store(buf ^ 1);
         __syncthreads();   // the next block's staging is complete; this one's reads are done
@@ -495,7 +500,7 @@ hipError_t launch_ball_screen_lk(const QueryArgs& a, hipStream_t st) {
     const int64_t nblk = (a.n + 255) / 256;
     int ysplit = 1;
     while (nblk * ysplit < 2048 && a.nqc / (ysplit * 2) >= 64) ysplit *= 2;
-    const int qpb = (int)(((a.nqc + ysplit - 1) / ysplit + 15) / 16 * 16);
+    const int qpb = (int)(((a.nqc + ysplit - 1) / ysplit + 31) / 32 * 32);   // whole staged blocks of 32
     const int gy = (a.nqc + qpb - 1) / qpb;
     hipLaunchKernelGGL((ball_screen_bf16_kernel<L, K>), dim3((unsigned)nblk, (unsigned)gy), dim3(256), 0, st,
                        a.ballb, a.uqb, a.n, a.nqc, qpb, a.bm, a.W);
