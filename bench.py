@@ -143,6 +143,14 @@ def exact_dists(X, Q, ids):
     return ((X[ids].double() - Q[:, None, :].double()) ** 2).sum(-1).sqrt()
 
 
+# query options of the serving forms on the one resident index (built with its
+# BF16 copy): plain FP32 arithmetic, exact FP32 answers through the BF16
+# screens, and BF16 products with the exact FP32 re-rank of the best 4k
+SERVE_FORMS = {"fp32": {"precision": 0, "verify": "dense", "filter": "plain"},
+               "fp32_bf16screen": {"precision": 0},
+               "bf16": {"precision": 1}}
+
+
 def serve_load(dl, torch, idx, Qpool, reqs, rate, form, workspace, slots, max_batch):
     """Serve the request stream through a detlsh server.  rate = None submits
     every request at once (closed-loop backlog: saturation); otherwise Poisson
@@ -152,7 +160,7 @@ def serve_load(dl, torch, idx, Qpool, reqs, rate, form, workspace, slots, max_ba
     import threading
     srv = dl.Server(idx, workspace_bytes=workspace, slots=slots, max_batch=max_batch)
     nreq = len(reqs["nq"])
-    prec = dl.BF16_RERANK if form == "bf16" else dl.FP32
+    qkw = SERVE_FORMS[form]
     tickets = queue.Queue()
     results = [None] * nreq
 
@@ -173,7 +181,7 @@ def serve_load(dl, torch, idx, Qpool, reqs, rate, form, workspace, slots, max_ba
             if dt > 0:
                 time.sleep(dt)
         q0, nq = int(reqs["q0"][i]), int(reqs["nq"][i])
-        t = srv.submit(Qpool[q0:q0 + nq], int(reqs["k"][i]), float(reqs["c"][i]), 0.1, precision=prec, sync=False)
+        t = srv.submit(Qpool[q0:q0 + nq], int(reqs["k"][i]), float(reqs["c"][i]), 0.1, sync=False, **qkw)
         tickets.put((i, t, float(arrivals[i]) if rate else time.monotonic()))
     th.join()
     srv.close()
@@ -191,7 +199,8 @@ def serve_load(dl, torch, idx, Qpool, reqs, rate, form, workspace, slots, max_ba
 def serve_bench(dl, torch, nreq, loads=(0.5, 0.8, 1.1), slots=3, max_batch=512, pool=8192, log_prefix="[serve]"):
     """Serving form on the resident 256-d mixture index (n = 1,000,000):
     saturation by a closed-loop backlog, then Poisson arrivals at the given
-    fractions of it, for plain FP32 and BF16 + rerank."""
+    fractions of it, for the three forms (plain FP32, exact FP32 through the
+    BF16 screens, BF16 + rerank)."""
     import synth
     cfg = synth.config("C5")
     dev = torch.device("cuda:0")
@@ -210,7 +219,7 @@ def serve_bench(dl, torch, nreq, loads=(0.5, 0.8, 1.1), slots=3, max_batch=512, 
     out = {"workload": f"256-d Gaussian mixture n={cfg.n}, L=4 K=16 N_r=256, 1% sample, beta=0.1; "
                        f"{nreq} requests, nq log-uniform 1..256, k in {{1,10,100}}, c in {{1.5,2.0}}",
            "slots": slots, "max_batch": max_batch, "workspace_bytes": workspace, "build_s": build_s, "forms": {}}
-    for form in ("fp32", "bf16"):
+    for form in SERVE_FORMS:
         warm = {key: v[:min(64, nreq)] for key, v in reqs.items()}
         serve_load(dl, torch, idx, Qpool, warm, None, form, workspace, slots, max_batch)
         sat, res = serve_load(dl, torch, idx, Qpool, reqs, None, form, workspace, slots, max_batch)

@@ -262,7 +262,7 @@ class Server:
             self._live = {}
 
     def submit(self, Q, k, c=1.5, beta=0.1, precision=FP32, rerank_mult=4, rmin_policy=RMIN_MAGIC, r_min=0.0,
-               max_rounds=0, verify="auto", granularity="point", sync=True) -> int:
+               max_rounds=0, verify="auto", granularity="point", sync=True, filter="auto") -> int:
         """Queue Q (nq x d) for k-ANN; the server reads Q on its own streams, so
         with sync=True the current stream is synchronised first."""
         torch = _torch()
@@ -272,7 +272,7 @@ class Server:
         dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         if sync:
             torch.cuda.current_stream().synchronize()
-        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, 0, verify, granularity)
+        o = _query_opts(precision, rerank_mult, rmin_policy, r_min, max_rounds, 0, verify, granularity, filter)
         t = C.c_uint64()
         check(lib().detlsh_server_submit(self._h, _ptr(Q), nq, int(k), float(c), float(beta), C.byref(o), _ptr(ids),
                                          _ptr(dists), C.byref(t)))

@@ -60,7 +60,7 @@ struct Params {
         return k == p.k && c_ok && beta == p.beta && o.precision == p.o.precision &&
                o.rerank_mult == p.o.rerank_mult && o.rmin_policy == p.o.rmin_policy &&
                o.max_rounds == p.o.max_rounds && o.r_min == p.o.r_min && o.verify == p.o.verify &&
-               o.granularity == p.o.granularity;
+               o.granularity == p.o.granularity && o.filter == p.o.filter;
     }
 };
 
