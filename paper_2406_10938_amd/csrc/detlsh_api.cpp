@@ -426,9 +426,19 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
                                 dtot + 2 * i, st));
         HCHECK(hipMemcpyAsync(htot, dtot, (size_t)8 * L, hipMemcpyDeviceToHost, st));
         HCHECK(hipStreamSynchronize(st));
-        for (int i = 0; i < L; ++i)
-            HCHECK(dl_tree_split(ix->n, ix->K, ix->N_r, ix->max_leaf, perm_of(i), scodes_of(i), tmp_of(i),
-                                 htot[2 * i], dtot + 2 * i, st));
+        {
+            int32_t* perms[8];
+            uint8_t* scs[8];
+            void* tmps[8];
+            uint32_t nruns[8];
+            for (int i = 0; i < L; ++i) {
+                perms[i] = perm_of(i);
+                scs[i] = scodes_of(i);
+                tmps[i] = tmp_of(i);
+                nruns[i] = htot[2 * i];
+            }
+            HCHECK(dl_tree_split_all(L, ix->n, ix->K, ix->N_r, ix->max_leaf, perms, scs, tmps, nruns, dtot, st));
+        }
         HCHECK(hipMemcpyAsync(htot, dtot, (size_t)8 * L, hipMemcpyDeviceToHost, st));
         HCHECK(hipStreamSynchronize(st));
         for (int i = 0; i < L; ++i) {

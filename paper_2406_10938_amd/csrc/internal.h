@@ -56,8 +56,11 @@ hipError_t dl_edges_from_breakpoints(const float* B, float* E, int N, int N_r, h
 size_t dl_tree_tmp_bytes(int64_t n, int K);
 hipError_t dl_tree_runs(const uint8_t* codes_i, int64_t n, int K, int N_r, int32_t* perm, uint8_t* scodes,
                         void* tmp, uint32_t* totals, hipStream_t st);
-hipError_t dl_tree_split(int64_t n, int K, int N_r, int max_leaf, int32_t* perm, uint8_t* scodes, void* tmp,
-                         uint32_t nruns, uint32_t* totals, hipStream_t st);
+// phase 2 of the L trees together (L <= 8): nruns[i] from phase 1; the leaf
+// count of tree i goes to totals[2 i + 1]
+hipError_t dl_tree_split_all(int L, int64_t n, int K, int N_r, int max_leaf, int32_t* const* perm,
+                             uint8_t* const* scodes, void* const* tmp, const uint32_t* nruns, uint32_t* totals,
+                             hipStream_t st);
 hipError_t dl_tree_leaves(int64_t n, int K, int N_r, const uint8_t* scodes, void* tmp, uint32_t nruns, uint32_t nl,
                           int32_t* leaf_start, uint8_t* leaf_lo, uint8_t* leaf_hi, hipStream_t st);
 

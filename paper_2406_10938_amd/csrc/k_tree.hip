@@ -63,13 +63,37 @@ struct Node {
     uint8_t plen[kMaxK];
 };
 
-// One workgroup per root run.  Leaf records go to slots [s, s + nleaf) of the
-// run's own position range (a run of m points has at most m leaves).
-__global__ __launch_bounds__(256) void split_runs_kernel(
-    const int32_t* __restrict__ run_start, int32_t* __restrict__ perm, uint8_t* __restrict__ scodes,
-    int32_t* __restrict__ tperm, uint8_t* __restrict__ tcodes, int K, int bits, int max_leaf,
-    int32_t* __restrict__ rec_start, uint8_t* __restrict__ rec_plen, uint32_t* __restrict__ nleaf)
+// The arrays of the L trees whose runs one split launch serves: tree i owns
+// workgroups [first[i], first[i + 1]).
+struct SplitTrees {
+    const int32_t* run_start[8];
+    int32_t* perm[8];
+    uint8_t* scodes[8];
+    int32_t* tperm[8];
+    uint8_t* tcodes[8];
+    int32_t* rec_start[8];
+    uint8_t* rec_plen[8];
+    uint32_t* nleaf[8];
+    uint32_t first[9];
+    int L;
+};
+
+// One workgroup per root run, the runs of all L trees in one launch (a tree's
+// time is its largest run's: one launch overlaps the trees' tails).  Leaf
+// records go to slots [s, s + nleaf) of the run's own position range (a run
+// of m points has at most m leaves).
+__global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, int bits, int max_leaf)
 {
+    int tree = 0;
+    while (tree + 1 < T.L && blockIdx.x >= T.first[tree + 1]) ++tree;
+    const int32_t* __restrict__ run_start = T.run_start[tree];
+    int32_t* __restrict__ perm = T.perm[tree];
+    uint8_t* __restrict__ scodes = T.scodes[tree];
+    int32_t* __restrict__ tperm = T.tperm[tree];
+    uint8_t* __restrict__ tcodes = T.tcodes[tree];
+    int32_t* __restrict__ rec_start = T.rec_start[tree];
+    uint8_t* __restrict__ rec_plen = T.rec_plen[tree];
+    uint32_t* __restrict__ nleaf = T.nleaf[tree];
     __shared__ Node stack[kStack];
     __shared__ int sp;
     __shared__ uint32_t ones[kMaxK];
@@ -78,7 +102,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(
     __shared__ Node cur;
     __shared__ int best_j;
 
-    const int q = blockIdx.x;
+    const int q = (int)(blockIdx.x - T.first[tree]);
     const int32_t s = run_start[q];
     const int32_t t = run_start[q + 1];
     const int tid = threadIdx.x;
@@ -295,16 +319,42 @@ hipError_t dl_tree_runs(const uint8_t* codes_i, int64_t n, int K, int N_r, int32
     return dl_exclusive_scan(t.flag, t.idx, n, reinterpret_cast<uint32_t*>(t.scratch), totals, st);
 }
 
-// Phase 2: each of the nruns runs split into leaves in place; the number of
-// leaves goes to totals[1].
-hipError_t dl_tree_split(int64_t n, int K, int N_r, int max_leaf, int32_t* perm, uint8_t* scodes, void* tmp,
-                         uint32_t nruns, uint32_t* totals, hipStream_t st) {
+// Phase 2, the L trees together: each tree's nruns[i] runs split into leaves
+// in place (one launch for all trees); the number of leaves of tree i goes to
+// totals[2 i + 1].
+hipError_t dl_tree_split_all(int L, int64_t n, int K, int N_r, int max_leaf, int32_t* const* perm,
+                             uint8_t* const* scodes, void* const* tmp, const uint32_t* nruns, uint32_t* totals,
+                             hipStream_t st) {
+    if (L < 1 || L > 8) return hipErrorInvalidValue;
     const int bits = root_bits(N_r);
-    TreeTmp t(tmp, n, K);
-    hipLaunchKernelGGL(run_starts_kernel, dim3(grid_for(n)), dim3(256), 0, st, t.flag, t.idx, n, t.run_start, nruns);
-    hipLaunchKernelGGL(split_runs_kernel, dim3(nruns), dim3(256), 0, st, t.run_start, perm, scodes, t.tperm, t.tcodes,
-                       K, bits, max_leaf, t.rec_start, t.rec_plen, t.nleaf);
-    return dl_exclusive_scan(t.nleaf, t.loff, nruns, reinterpret_cast<uint32_t*>(t.scratch), totals + 1, st);
+    SplitTrees T{};
+    T.L = L;
+    T.first[0] = 0;
+    for (int i = 0; i < L; ++i) {
+        TreeTmp t(tmp[i], n, K);
+        hipLaunchKernelGGL(run_starts_kernel, dim3(grid_for(n)), dim3(256), 0, st, t.flag, t.idx, n, t.run_start,
+                           nruns[i]);
+        T.run_start[i] = t.run_start;
+        T.perm[i] = perm[i];
+        T.scodes[i] = scodes[i];
+        T.tperm[i] = t.tperm;
+        T.tcodes[i] = t.tcodes;
+        T.rec_start[i] = t.rec_start;
+        T.rec_plen[i] = t.rec_plen;
+        T.nleaf[i] = t.nleaf;
+        T.first[i + 1] = T.first[i] + nruns[i];
+    }
+    if (T.first[L] > 0)
+        hipLaunchKernelGGL(split_runs_kernel, dim3(T.first[L]), dim3(256), 0, st, T, K, bits, max_leaf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < L; ++i) {
+        TreeTmp t(tmp[i], n, K);
+        e = dl_exclusive_scan(t.nleaf, t.loff, nruns[i], reinterpret_cast<uint32_t*>(t.scratch), totals + 2 * i + 1,
+                              st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Phase 3: the leaf table of the nl leaves (offsets into perm, and the K-byte
