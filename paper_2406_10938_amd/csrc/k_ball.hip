@@ -87,15 +87,21 @@ __global__ __launch_bounds__(256) void ball_table_kernel(const uint8_t* __restri
     v[K] = 1.0f;
     v[K + 1] = (float)((1.0 - kBallDelta) * cc - (1.0 + kBallDelta) * Wd * Wd);
     v[K + 2] = W;
-    uint16_t* db = outb + g * BallDims<K>::KB;
+    // the row assembled in registers and written with 16-byte stores
+    constexpr int KB = BallDims<K>::KB;
+    uint32_t w[KB / 2];
 #pragma unroll
-    for (int k = 0; k < BallDims<K>::KB; ++k) {
-        uint16_t h = 0;
+    for (int k = 0; k < KB; ++k) {
+        uint32_t h = 0;
         if (k < P || (k >= 2 * P && k < 3 * P)) h = dl_f32_to_bf16(v[k < P ? k : k - 2 * P]);
         else if (k < 2 * P) h = bf16_lo(v[k - P]);
         else if (k == BallDims<K>::KS) h = dl_f32_to_bf16(1.0f);
-        db[k] = h;
+        if (k & 1) w[k >> 1] |= h << 16;
+        else w[k >> 1] = h;
     }
+    uint4* db = reinterpret_cast<uint4*>(outb + g * KB);
+#pragma unroll
+    for (int j = 0; j < KB / 8; ++j) db[j] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
 }
 
 // Query vectors u of the chunk in the three-term BF16 form, [L][nqc][KB]:
@@ -594,25 +600,58 @@ hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, c
 hipError_t dl_launch_ball_query(const QueryArgs& a, hipStream_t st) { DL_BALL_DISPATCH(launch_ball_query_lk) }
 
 namespace {
-__global__ __launch_bounds__(256) void codes_point_major_kernel(const uint8_t* __restrict__ codes, int64_t n, int L,
-                                                                int K, uint8_t* __restrict__ out)
+// out[o] = the L K-byte code words of point o, tree by tree: one thread per
+// point reads its L words (each a coalesced column read) and writes its
+// L K-byte row with 16-byte stores.
+template <int L, int K>
+__global__ __launch_bounds__(256) void codes_point_major_kernel(const uint8_t* __restrict__ codes, int64_t n,
+                                                                uint8_t* __restrict__ out)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;   // one (tree, point) word of K bytes
-    if (g >= (int64_t)L * n) return;
-    const int i = (int)(g / n);
-    const int64_t o = g - (int64_t)i * n;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(codes + g * K);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(out + o * (int64_t)(L * K) + i * K);
-    for (int j = 0; j < K / 4; ++j) dst[j] = src[j];
+    constexpr int WK = K / 4, W = L * WK;   // 32-bit words per tree and per point
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    uint32_t w[W];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(codes + ((int64_t)i * n + o) * K);
+#pragma unroll
+        for (int j = 0; j < WK; ++j) w[i * WK + j] = src[j];
+    }
+    uint32_t* dst = reinterpret_cast<uint32_t*>(out + o * (int64_t)(L * K));
+    if constexpr (W % 4 == 0) {
+#pragma unroll
+        for (int j = 0; j < W; j += 4)
+            *reinterpret_cast<uint4*>(dst + j) = make_uint4(w[j], w[j + 1], w[j + 2], w[j + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) dst[j] = w[j];
+    }
+}
+
+template <int L, int K>
+hipError_t launch_codes_pm_lk(const uint8_t* codes, int64_t n, uint8_t* out, hipStream_t st) {
+    hipLaunchKernelGGL((codes_point_major_kernel<L, K>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, codes,
+                       n, out);
+    return hipGetLastError();
 }
 }  // namespace
 
 hipError_t dl_launch_codes_point_major(const uint8_t* codes, int64_t n, int L, int K, uint8_t* out, hipStream_t st) {
-    const int64_t tot = (int64_t)L * n;
-    if (tot <= 0) return hipSuccess;
-    hipLaunchKernelGGL(codes_point_major_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, codes, n, L, K,
-                       out);
-    return hipGetLastError();
+    if (n <= 0) return hipSuccess;
+    switch (L * 100 + K) {
+        case 104: return launch_codes_pm_lk<1, 4>(codes, n, out, st);
+        case 204: return launch_codes_pm_lk<2, 4>(codes, n, out, st);
+        case 404: return launch_codes_pm_lk<4, 4>(codes, n, out, st);
+        case 108: return launch_codes_pm_lk<1, 8>(codes, n, out, st);
+        case 208: return launch_codes_pm_lk<2, 8>(codes, n, out, st);
+        case 408: return launch_codes_pm_lk<4, 8>(codes, n, out, st);
+        case 116: return launch_codes_pm_lk<1, 16>(codes, n, out, st);
+        case 216: return launch_codes_pm_lk<2, 16>(codes, n, out, st);
+        case 416: return launch_codes_pm_lk<4, 16>(codes, n, out, st);
+        case 132: return launch_codes_pm_lk<1, 32>(codes, n, out, st);
+        case 232: return launch_codes_pm_lk<2, 32>(codes, n, out, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t dl_launch_ball_screen(const QueryArgs& a, hipStream_t st) { DL_BALL_DISPATCH(launch_ball_screen_lk) }

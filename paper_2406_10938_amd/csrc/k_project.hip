@@ -244,10 +244,51 @@ __global__ void row_norms_kernel(const float* __restrict__ X, int64_t n, int d, 
     }
 }
 
+// d a multiple of 4: sixteen lanes per row (sixteen rows per workgroup),
+// four-element vector loads, reductions over the sixteen lanes.  The sums'
+// order differs from row_norms_kernel; every use of the norms allows any order.
+__global__ __launch_bounds__(256) void row_norms16_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                          float* __restrict__ xn, float* __restrict__ xn_bf,
+                                                          float* __restrict__ xe)
+{
+    const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int l = threadIdx.x & 15;
+    const bool live = row < n;
+    const float* x = X + (live ? row : n - 1) * d;
+    float a = 0.f, b = 0.f, e = 0.f;
+    for (int c = 4 * l; c < d; c += 64) {
+        const float4 v4 = *reinterpret_cast<const float4*>(x + c);
+        const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            a = fmaf(v[t], v[t], a);
+            const float w = dl_bf16_to_f32(dl_f32_to_bf16(v[t]));
+            b = fmaf(w, w, b);
+            const float r = v[t] - w;
+            e = fmaf(r, r, e);
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 16);
+        b += __shfl_xor(b, o, 16);
+        e += __shfl_xor(e, o, 16);
+    }
+    if (live && l == 0) {
+        xn[row] = a;
+        if (xn_bf) xn_bf[row] = b;
+        if (xe) xe[row] = e;
+    }
+}
+
 hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe,
                                hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, d, xn, xn_bf, xe);
+    if (d % 4 == 0)
+        hipLaunchKernelGGL(row_norms16_kernel, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, X, n, d, xn, xn_bf,
+                           xe);
+    else
+        hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, d, xn, xn_bf, xe);
     return hipGetLastError();
 }
 
@@ -274,10 +315,33 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict
     for (; i < cnt; i += stride) y[i] = dl_f32_to_bf16(x[i]);
 }
 
+// four elements per thread: one 16-byte load, one 8-byte store (x 16-byte and
+// y 8-byte aligned; the last cnt % 4 elements by the scalar kernel)
+__global__ void to_bf16_x4_kernel(const float4* __restrict__ x, uint2* __restrict__ y, int64_t cnt4) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < cnt4; i += stride) {
+        const float4 v = x[i];
+        y[i] = make_uint2((uint32_t)dl_f32_to_bf16(v.x) | ((uint32_t)dl_f32_to_bf16(v.y) << 16),
+                          (uint32_t)dl_f32_to_bf16(v.z) | ((uint32_t)dl_f32_to_bf16(v.w) << 16));
+    }
+}
+
 hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st) {
     if (cnt <= 0) return hipSuccess;
-    int64_t blocks = (cnt + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, y, cnt);
+    int64_t done = 0;
+    if (reinterpret_cast<uintptr_t>(x) % 16 == 0 && reinterpret_cast<uintptr_t>(y) % 8 == 0 && cnt >= 4) {
+        const int64_t cnt4 = cnt / 4;
+        int64_t blocks = (cnt4 + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(to_bf16_x4_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                           reinterpret_cast<const float4*>(x), reinterpret_cast<uint2*>(y), cnt4);
+        done = 4 * cnt4;
+    }
+    if (done < cnt) {
+        int64_t blocks = (cnt - done + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x + done, y + done, cnt - done);
+    }
     return hipGetLastError();
 }
