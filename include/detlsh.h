@@ -113,7 +113,10 @@ typedef struct {
  * Limits (else DETLSH_EINVAL): n >= 1, d >= 1, K in {4, 8, 16, 32} and
  * L in {1, 2, 4, 8} with L*K <= 64,
  * N_r a power of two in [2, 256], 0 < sample_frac <= 1 with
- * floor(sample_frac*n) >= N_r, n < 2^31.
+ * floor(sample_frac*n) >= N_r, n < 2^31.  The (L, K) limits are the kernels'
+ * register budget: the range query is compiled per (L, K), keeping a point's
+ * 2*L*K cell edges (or its L screen vectors) in registers, 128 of a wave's
+ * VGPRs at L*K = 64; other K and L are refused rather than padded.
  * X is copied: the caller may free it when the call returns.  On success
  * *out owns all of its device memory until detlsh_free.
  */
@@ -232,7 +235,8 @@ enum {
  * the k members of S nearest to each query, ascending by (distance, id);
  * N_S is computed in IEEE double from the double `beta` as k + ceil(beta*n);
  * distances are Euclidean (not squared).  Limits: 1 <= k <= min(n, 1024)
- * (BF16 form: rerank_mult*k <= 1024, needs an index built with keep_bf16),
+ * (the top-k keeps its k results and the candidates of its last radix digit
+ * in LDS; BF16 form: rerank_mult*k <= 1024, needs an index built with keep_bf16),
  * c > 1, 0 <= beta <= 1, nq >= 0 (0 is a no-op), FIXED needs r_min > 0.
  *
  * Verification (both forms give the top-k of S by FP32 distance computed by
