@@ -110,13 +110,17 @@ typedef struct {
  * one child per vector of first code bits and whose overfull nodes are split
  * on the dimension whose next bit divides them most evenly (Sec. 4.2).
  *
- * Limits (else DETLSH_EINVAL): n >= 1, d >= 1, K in {4, 8, 16, 32} and
- * L in {1, 2, 4, 8} with L*K <= 64,
- * N_r a power of two in [2, 256], 0 < sample_frac <= 1 with
- * floor(sample_frac*n) >= N_r, n < 2^31.  The (L, K) limits are the kernels'
- * register budget: the range query is compiled per (L, K), keeping a point's
- * 2*L*K cell edges (or its L screen vectors) in registers, 128 of a wave's
- * VGPRs at L*K = 64; other K and L are refused rather than padded.
+ * Limits (else DETLSH_EINVAL): n >= 1, d >= 1, 1 <= K <= 32 and
+ * L in {1, 2, 4, 8} with L*K' <= 64, where K' is the smallest of 4, 8, 16, 32
+ * that is >= K, N_r a power of two in [2, 256], 0 < sample_frac <= 1 with
+ * floor(sample_frac*n) >= N_r, n < 2^31.  The kernels run K' dimensions per
+ * tree: the K' - K extra ones have zero projection rows, so every point and
+ * query projects to 0 there (all their breakpoints 0, every code N_r - 1) and
+ * no bound, tree split or answer changes; every array this interface returns
+ * or takes (A, B, codes, leaf boxes, projections) has the caller's K.  The
+ * (L, K') limits are the kernels' register budget: the range query is compiled
+ * per (L, K'), keeping a point's 2*L*K' cell edges (or its L screen vectors) in
+ * registers, 128 of a wave's VGPRs at L*K' = 64.
  * X is copied: the caller may free it when the call returns.  On success
  * *out owns all of its device memory until detlsh_free.
  */

@@ -317,7 +317,8 @@ DlTimer::~DlTimer() {
 struct detlsh_index_s {
     int device = 0;
     int64_t n = 0;
-    int32_t d = 0, L = 0, K = 0, N_r = 0, LK = 0;
+    int32_t d = 0, L = 0, K = 0, N_r = 0, LK = 0;   // K, LK: the widths the kernels run (padded)
+    int32_t Ku = 0;                                 // K as the caller gave it (<= K)
     int64_t n_s = 0;
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
@@ -356,12 +357,39 @@ struct detlsh_index_s {
 
 namespace {
 
+// The caller's K (1..32) runs as the next instantiated width Kp in {4, 8, 16,
+// 32}: the extra dimensions get zero projection rows, so every point and query
+// projects to 0 there, their breakpoints are all 0 and every code is N_r - 1;
+// each of them adds 0 to every bound (a region of code N_r - 1 reaches up to
+// +inf from 0), is never the most even split while a real dimension is open
+// (a tie goes to the lower, real dimension), and so changes no answer.
+int padded_k(int K) { return K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 16 ? 16 : 32)); }
+
+// Per-dimension tables between the caller's layout (rows i*Ku + j) and the
+// kernels' (rows i*Kp + j); padding rows take `fill`.
+template <typename T>
+std::vector<T> pad_rows(const T* src, int L, int Ku, int Kp, size_t width, T fill) {
+    std::vector<T> out((size_t)L * Kp * width, fill);
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < Ku; ++j)
+            std::memcpy(&out[((size_t)i * Kp + j) * width], src + ((size_t)i * Ku + j) * width, width * sizeof(T));
+    return out;
+}
+template <typename T>
+void strip_rows(const T* src, int L, int Ku, int Kp, size_t width, T* dst) {
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < Ku; ++j)
+            std::memcpy(dst + ((size_t)i * Ku + j) * width, src + ((size_t)i * Kp + j) * width, width * sizeof(T));
+}
+
 detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_r) {
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(DETLSH_EINVAL, "n must be in [1, 2^31), got %lld", (long long)n);
     if (d < 1) return fail(DETLSH_EINVAL, "d must be >= 1, got %d", d);
-    if (!dl_supported_lk(L, K))
+    if (K < 1 || K > 32) return fail(DETLSH_EINVAL, "K must be in [1, 32], got %d", K);
+    if (!dl_supported_lk(L, padded_k(K)))
         return fail(DETLSH_EINVAL,
-                    "unsupported (L, K) = (%d, %d): K in {4,8,16,32}, L in {1,2,4,8}, L*K <= 64", L, K);
+                    "unsupported (L, K) = (%d, %d): L in {1,2,4,8} and L*K' <= 64, K' = %d (K run as the next of "
+                    "4, 8, 16, 32)", L, K, padded_k(K));
     if (N_r < 2 || N_r > 256 || (N_r & (N_r - 1)))
         return fail(DETLSH_EINVAL, "N_r must be a power of two in [2, 256], got %d", N_r);
     return DETLSH_OK;
@@ -518,7 +546,8 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
     if (!ix) return fail(DETLSH_ENOMEM, "host allocation failed");
     std::unique_ptr<detlsh_index_s> guard(ix);
     HCHECK(hipGetDevice(&ix->device));
-    ix->n = n; ix->d = d; ix->L = L; ix->K = K; ix->N_r = N_r; ix->LK = L * K; ix->n_s = n_s;
+    const int Kp = padded_k(K);
+    ix->n = n; ix->d = d; ix->L = L; ix->K = Kp; ix->Ku = K; ix->N_r = N_r; ix->LK = L * Kp; ix->n_s = n_s;
     ix->max_leaf = (opts && opts->max_leaf > 0) ? opts->max_leaf : 256;
     ix->proj_bf16 = (opts && opts->proj_bf16) ? 1 : 0;
     const uint64_t seed = opts ? opts->seed : 0;
@@ -528,19 +557,20 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
         return fail(DETLSH_EINVAL, "projection %d is not defined", projection);
     if (projection == DETLSH_PROJ_PAA && (L != 1 || d < K))
         return fail(DETLSH_EINVAL, "the PAA projection needs L = 1 and d >= K, got L = %d, d = %d, K = %d", L, d, K);
-    ix->A_host.resize((size_t)ix->LK * d);
+    std::vector<float> Au((size_t)L * K * d);   // the caller's L*K rows
     if (projection == DETLSH_PROJ_PAA) {
         // DET-ONLY: row j averages the j-th segment of floor(d/K) coordinates
         const int w = d / K;
-        std::fill(ix->A_host.begin(), ix->A_host.end(), 0.0f);
+        std::fill(Au.begin(), Au.end(), 0.0f);
         for (int j = 0; j < K; ++j)
-            for (int c = j * w; c < (j + 1) * w; ++c) ix->A_host[(size_t)j * d + c] = (float)(1.0 / w);
+            for (int c = j * w; c < (j + 1) * w; ++c) Au[(size_t)j * d + c] = (float)(1.0 / w);
     } else if (opts && opts->A) {
-        std::memcpy(ix->A_host.data(), opts->A, ix->A_host.size() * 4);
+        std::memcpy(Au.data(), opts->A, Au.size() * 4);
     } else {
         HostRng rng(seed);
-        for (auto& v : ix->A_host) v = (float)rng.normal();
+        for (auto& v : Au) v = (float)rng.normal();
     }
+    ix->A_host = pad_rows(Au.data(), L, K, Kp, (size_t)d, 0.0f);
     ix->sample_ids.resize((size_t)n_s);
     if (opts && opts->sample_ids) {
         std::memcpy(ix->sample_ids.data(), opts->sample_ids, (size_t)n_s * 8);
@@ -594,7 +624,7 @@ detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L
         ProjectArgs pa;
         pa.X = ix->X.as<float>(); pa.Xbf = ix->Xbf.as<uint16_t>(); pa.M = n; pa.d = d;
         pa.A = ix->A.as<float>(); pa.Abf = ix->Abf.as<uint16_t>(); pa.N = ix->LK; pa.bf16 = ix->proj_bf16;
-        pa.E = ix->E.as<float>(); pa.N_r = N_r; pa.K = K; pa.codes = ix->codes.as<uint8_t>(); pa.n_codes = n;
+        pa.E = ix->E.as<float>(); pa.N_r = N_r; pa.K = ix->K; pa.codes = ix->codes.as<uint8_t>(); pa.n_codes = n;
         DlTimer tm(T_ENCODE, st);
         HCHECK(dl_launch_project(pa, PROJ_ENCODE, st));
     }
@@ -624,26 +654,28 @@ detlsh_status detlsh_index_import(const float* X, int64_t n, int32_t d, int32_t 
     if (!ix) return fail(DETLSH_ENOMEM, "host allocation failed");
     std::unique_ptr<detlsh_index_s> guard(ix);
     HCHECK(hipGetDevice(&ix->device));
-    ix->n = n; ix->d = d; ix->L = L; ix->K = K; ix->N_r = N_r; ix->LK = L * K; ix->n_s = 0;
+    const int Kp = padded_k(K);
+    ix->n = n; ix->d = d; ix->L = L; ix->K = Kp; ix->Ku = K; ix->N_r = N_r; ix->LK = L * Kp; ix->n_s = 0;
     ix->max_leaf = (opts && opts->max_leaf > 0) ? opts->max_leaf : 256;
-    ix->A_host.assign(A, A + (size_t)ix->LK * d);
+    ix->A_host = pad_rows(A, L, K, Kp, (size_t)d, 0.0f);
     s = alloc_common(ix, X, opts, st);
     if (s) return s;
     const int N1 = N_r + 1;
-    for (int e = 0; e < ix->LK; ++e)
+    for (int e = 0; e < L * K; ++e)
         for (int z = 1; z < N1; ++z)
             if (!(B[(size_t)e * N1 + z] >= B[(size_t)e * N1 + z - 1]))
                 return fail(DETLSH_EINVAL, "B row %d is not non-decreasing at %d", e, z);
-    HCHECK(hipMemcpyAsync(ix->B.p, B, (size_t)ix->LK * N1 * 4, hipMemcpyHostToDevice, st));
+    const std::vector<float> Bp = pad_rows(B, L, K, Kp, (size_t)N1, 0.0f);
+    HCHECK(hipMemcpyAsync(ix->B.p, Bp.data(), Bp.size() * 4, hipMemcpyHostToDevice, st));
     HCHECK(dl_edges_from_breakpoints(ix->B.as<float>(), ix->E.as<float>(), ix->LK, N_r, st));
-    // codes: n x LK (column e = i*K + j) -> [L][n][K]
-    std::vector<uint8_t> t((size_t)n * ix->LK);
+    // codes: n x (L*K) (column i*K + j) -> [L][n][Kp], the padding dimensions N_r - 1
+    std::vector<uint8_t> t((size_t)n * ix->LK, (uint8_t)(N_r - 1));
     for (int64_t o = 0; o < n; ++o)
         for (int i = 0; i < L; ++i)
             for (int j = 0; j < K; ++j) {
-                const uint8_t c = codes[(size_t)o * ix->LK + i * K + j];
+                const uint8_t c = codes[(size_t)o * L * K + i * K + j];
                 if (c >= N_r) return fail(DETLSH_EINVAL, "code %d of point %lld >= N_r", (int)c, (long long)o);
-                t[((size_t)i * n + o) * K + j] = c;
+                t[((size_t)i * n + o) * Kp + j] = c;
             }
     HCHECK(hipMemcpyAsync(ix->codes.p, t.data(), t.size(), hipMemcpyHostToDevice, st));
     HCHECK(hipStreamSynchronize(st));
@@ -809,7 +841,7 @@ detlsh_status detlsh_index_save(detlsh_index ix, const char* path) {
     std::memcpy(h.magic, kMagic, 8);
     h.format = kFormat;
     h.header_bytes = sizeof(FileHeader);
-    h.n = ix->n; h.d = ix->d; h.L = ix->L; h.K = ix->K; h.N_r = ix->N_r; h.n_s = ix->n_s;
+    h.n = ix->n; h.d = ix->d; h.L = ix->L; h.K = ix->Ku; h.N_r = ix->N_r; h.n_s = ix->n_s;
     h.max_leaf = ix->max_leaf; h.keep_bf16 = ix->Xbf.p ? 1 : 0; h.proj_bf16 = ix->proj_bf16;
     const std::string tmp = std::string(path) + ".tmp";
     {
@@ -819,10 +851,23 @@ detlsh_status detlsh_index_save(detlsh_index ix, const char* path) {
         if (fwrite(&h, sizeof h, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "write failed");
         Checksum ck;
         detlsh_status s;
-        if ((s = put(fp, ck, ix->A_host.data(), ix->A_host.size() * 4, false))) return s;
-        if ((s = put(fp, ck, ix->B.p, (size_t)ix->LK * (ix->N_r + 1) * 4, true))) return s;
+        // the file holds the caller's K dimensions (padding dimensions are rebuilt at load)
+        const int L = ix->L, Ku = ix->Ku, Kp = ix->K, N1 = ix->N_r + 1;
+        std::vector<float> A((size_t)L * Ku * ix->d), B((size_t)L * Ku * N1), Bp((size_t)ix->LK * N1);
+        strip_rows(ix->A_host.data(), L, Ku, Kp, (size_t)ix->d, A.data());
+        HCHECK(hipMemcpy(Bp.data(), ix->B.p, Bp.size() * 4, hipMemcpyDeviceToHost));
+        strip_rows(Bp.data(), L, Ku, Kp, (size_t)N1, B.data());
+        if ((s = put(fp, ck, A.data(), A.size() * 4, false))) return s;
+        if ((s = put(fp, ck, B.data(), B.size() * 4, false))) return s;
         if ((s = put(fp, ck, ix->sample_ids.data(), ix->sample_ids.size() * 8, false))) return s;
-        if ((s = put(fp, ck, ix->codes.p, (size_t)ix->n * ix->LK, true))) return s;
+        if (Ku == Kp) {
+            if ((s = put(fp, ck, ix->codes.p, (size_t)ix->n * ix->LK, true))) return s;
+        } else {   // [L][n][Kp] -> [L][n][Ku]
+            std::vector<uint8_t> cp((size_t)ix->n * ix->LK), cu((size_t)ix->n * L * Ku);
+            HCHECK(hipMemcpy(cp.data(), ix->codes.p, cp.size(), hipMemcpyDeviceToHost));
+            for (size_t w = 0; w < (size_t)L * ix->n; ++w) std::memcpy(&cu[w * Ku], &cp[w * Kp], (size_t)Ku);
+            if ((s = put(fp, ck, cu.data(), cu.size(), false))) return s;
+        }
         if ((s = put(fp, ck, ix->X.p, (size_t)ix->n * ix->d * 4, true))) return s;
         const uint64_t sum = ck.done();
         if (fwrite(&sum, 8, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "write failed");
@@ -851,28 +896,39 @@ detlsh_status detlsh_index_load(const char* path, void* stream, detlsh_index* ou
     if (!ix) return fail(DETLSH_ENOMEM, "host allocation failed");
     std::unique_ptr<detlsh_index_s> guard(ix);
     HCHECK(hipGetDevice(&ix->device));
-    ix->n = h.n; ix->d = h.d; ix->L = h.L; ix->K = h.K; ix->N_r = h.N_r; ix->LK = h.L * h.K; ix->n_s = h.n_s;
+    const int Ku = h.K, Kp = padded_k(h.K);
+    ix->n = h.n; ix->d = h.d; ix->L = h.L; ix->K = Kp; ix->Ku = Ku; ix->N_r = h.N_r; ix->LK = h.L * Kp;
+    ix->n_s = h.n_s;
     ix->max_leaf = h.max_leaf;
     ix->proj_bf16 = h.proj_bf16 ? 1 : 0;
     Checksum ck;
-    ix->A_host.resize((size_t)ix->LK * ix->d);
-    if ((s = get(fp, ck, ix->A_host.data(), ix->A_host.size() * 4, false))) return s;
-    std::vector<float> B((size_t)ix->LK * (ix->N_r + 1));
-    if ((s = get(fp, ck, B.data(), B.size() * 4, false))) return s;
+    std::vector<float> Au((size_t)h.L * Ku * ix->d);
+    if ((s = get(fp, ck, Au.data(), Au.size() * 4, false))) return s;
+    ix->A_host = pad_rows(Au.data(), h.L, Ku, Kp, (size_t)ix->d, 0.0f);
+    std::vector<float> Bu((size_t)h.L * Ku * (ix->N_r + 1));
+    if ((s = get(fp, ck, Bu.data(), Bu.size() * 4, false))) return s;
     ix->sample_ids.resize((size_t)ix->n_s);
     if ((s = get(fp, ck, ix->sample_ids.data(), ix->sample_ids.size() * 8, false))) return s;
     if (ix->X.alloc((size_t)ix->n * ix->d * 4) != hipSuccess) return fail(DETLSH_ENOMEM, "X does not fit");
     if (ix->codes.alloc((size_t)ix->n * ix->LK) != hipSuccess) return fail(DETLSH_ENOMEM, "codes do not fit");
-    if ((s = get(fp, ck, ix->codes.p, (size_t)ix->n * ix->LK, true))) return s;
+    if (Ku == Kp) {
+        if ((s = get(fp, ck, ix->codes.p, (size_t)ix->n * ix->LK, true))) return s;
+    } else {   // [L][n][Ku] -> [L][n][Kp], the padding dimensions N_r - 1
+        std::vector<uint8_t> cu((size_t)ix->n * h.L * Ku), cp((size_t)ix->n * ix->LK, (uint8_t)(ix->N_r - 1));
+        if ((s = get(fp, ck, cu.data(), cu.size(), false))) return s;
+        for (size_t w = 0; w < (size_t)h.L * ix->n; ++w) std::memcpy(&cp[w * Kp], &cu[w * Ku], (size_t)Ku);
+        HCHECK(hipMemcpy(ix->codes.p, cp.data(), cp.size(), hipMemcpyHostToDevice));
+    }
     if ((s = get(fp, ck, ix->X.p, (size_t)ix->n * ix->d * 4, true))) return s;
     uint64_t sum = 0;
     if (fread(&sum, 8, 1, fp.f) != 1) return fail(DETLSH_EINVAL, "the file is truncated");
     if (sum != ck.done()) return fail(DETLSH_EINVAL, "checksum mismatch: %s is corrupt", path);
     const int N1 = ix->N_r + 1;
-    for (int e = 0; e < ix->LK; ++e)
+    for (int e = 0; e < h.L * Ku; ++e)
         for (int z = 1; z < N1; ++z)
-            if (!(B[(size_t)e * N1 + z] >= B[(size_t)e * N1 + z - 1]))
+            if (!(Bu[(size_t)e * N1 + z] >= Bu[(size_t)e * N1 + z - 1]))
                 return fail(DETLSH_EINVAL, "breakpoint row %d is not non-decreasing", e);
+    const std::vector<float> B = pad_rows(Bu.data(), h.L, Ku, Kp, (size_t)N1, 0.0f);
     detlsh_build_opts o{};
     o.keep_bf16 = h.keep_bf16;
     o.max_leaf = h.max_leaf;
@@ -893,7 +949,7 @@ detlsh_status detlsh_index_info(detlsh_index ix, detlsh_info* o) {
     g_err.clear();
     if (!ix || !o) return fail(DETLSH_EINVAL, "NULL argument");
     std::memset(o, 0, sizeof *o);
-    o->n = ix->n; o->d = ix->d; o->L = ix->L; o->K = ix->K; o->N_r = ix->N_r; o->n_s = ix->n_s;
+    o->n = ix->n; o->d = ix->d; o->L = ix->L; o->K = ix->Ku; o->N_r = ix->N_r; o->n_s = ix->n_s;
     o->max_leaf = ix->max_leaf;
     o->has_bf16 = ix->Xbf.p != nullptr;
     for (int i = 0; i < ix->L && i < 8; ++i) o->n_leaves[i] = ix->n_leaves[i];
@@ -905,15 +961,20 @@ detlsh_status detlsh_export(detlsh_index ix, float* A, float* B, uint8_t* codes,
     g_err.clear();
     if (!ix) return fail(DETLSH_EINVAL, "NULL index");
     HCHECK(hipSetDevice(ix->device));
-    if (A) std::memcpy(A, ix->A_host.data(), ix->A_host.size() * 4);
-    if (B) HCHECK(hipMemcpy(B, ix->B.p, (size_t)ix->LK * (ix->N_r + 1) * 4, hipMemcpyDeviceToHost));
-    if (codes) {
+    const int L = ix->L, Ku = ix->Ku, Kp = ix->K, N1 = ix->N_r + 1;
+    if (A) strip_rows(ix->A_host.data(), L, Ku, Kp, (size_t)ix->d, A);
+    if (B) {
+        std::vector<float> Bp((size_t)ix->LK * N1);
+        HCHECK(hipMemcpy(Bp.data(), ix->B.p, Bp.size() * 4, hipMemcpyDeviceToHost));
+        strip_rows(Bp.data(), L, Ku, Kp, (size_t)N1, B);
+    }
+    if (codes) {   // [L][n][Kp] -> n x (L*Ku)
         std::vector<uint8_t> t((size_t)ix->n * ix->LK);
         HCHECK(hipMemcpy(t.data(), ix->codes.p, t.size(), hipMemcpyDeviceToHost));
-        for (int i = 0; i < ix->L; ++i)
+        for (int i = 0; i < L; ++i)
             for (int64_t o = 0; o < ix->n; ++o)
-                for (int j = 0; j < ix->K; ++j)
-                    codes[(size_t)o * ix->LK + i * ix->K + j] = t[((size_t)i * ix->n + o) * ix->K + j];
+                for (int j = 0; j < Ku; ++j)
+                    codes[(size_t)o * L * Ku + i * Ku + j] = t[((size_t)i * ix->n + o) * Kp + j];
     }
     if (sample_ids && !ix->sample_ids.empty())
         std::memcpy(sample_ids, ix->sample_ids.data(), ix->sample_ids.size() * 8);
@@ -931,8 +992,13 @@ detlsh_status detlsh_export_tree(detlsh_index ix, int32_t tree, int32_t* perm, i
     HCHECK(hipSetDevice(ix->device));
     if (perm) HCHECK(hipMemcpy(perm, ix->perm.as<int32_t>() + (int64_t)tree * ix->n, (size_t)ix->n * 4, hipMemcpyDeviceToHost));
     if (leaf_start) HCHECK(hipMemcpy(leaf_start, ix->leaf_start[tree], (size_t)(nl + 1) * 4, hipMemcpyDeviceToHost));
-    if (leaf_lo) HCHECK(hipMemcpy(leaf_lo, ix->leaf_lo[tree], (size_t)nl * ix->K, hipMemcpyDeviceToHost));
-    if (leaf_hi) HCHECK(hipMemcpy(leaf_hi, ix->leaf_hi[tree], (size_t)nl * ix->K, hipMemcpyDeviceToHost));
+    for (int side = 0; side < 2; ++side) {   // leaf boxes: nl x Kp -> nl x Ku
+        uint8_t* dst = side ? leaf_hi : leaf_lo;
+        if (!dst) continue;
+        std::vector<uint8_t> t((size_t)nl * ix->K);
+        HCHECK(hipMemcpy(t.data(), side ? ix->leaf_hi[tree] : ix->leaf_lo[tree], t.size(), hipMemcpyDeviceToHost));
+        for (int64_t l = 0; l < nl; ++l) std::memcpy(dst + l * ix->Ku, &t[(size_t)l * ix->K], (size_t)ix->Ku);
+    }
     return DETLSH_OK;
 }
 
@@ -943,13 +1009,23 @@ detlsh_status detlsh_project(detlsh_index ix, const float* Q, int64_t nq, float*
     if (nq == 0) return DETLSH_OK;
     if (!is_device_ptr(Q) || !is_device_ptr(out)) return fail(DETLSH_EINVAL, "Q and out must be device pointers");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    HCHECK(hipSetDevice(ix->device));
+    DevBuf tmp;   // the kernels' width when K was padded; out gets the caller's L*K columns
+    if (ix->Ku != ix->K) HCHECK(pool_alloc(tmp, (size_t)nq * ix->LK * 4, ix->device));
     ProjectArgs pa;
-    pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK; pa.Pout = out;
+    pa.X = Q; pa.M = nq; pa.d = ix->d; pa.A = ix->A.as<float>(); pa.N = ix->LK;
+    pa.Pout = tmp.p ? tmp.as<float>() : out;
     {
         DlTimer tm(T_QPROJECT, st);
         HCHECK(dl_launch_project(pa, PROJ_ROWMAJOR, st));
     }
+    if (tmp.p)
+        for (int i = 0; i < ix->L; ++i)
+            HCHECK(hipMemcpy2DAsync(out + (size_t)i * ix->Ku, (size_t)ix->L * ix->Ku * 4,
+                                    tmp.as<float>() + (size_t)i * ix->K, (size_t)ix->LK * 4, (size_t)ix->Ku * 4,
+                                    (size_t)nq, hipMemcpyDeviceToDevice, st));
     HCHECK(hipStreamSynchronize(st));
+    pool_give(tmp, ix->device);
     prof_resolve();
     return DETLSH_OK;
 }
@@ -1060,12 +1136,25 @@ struct QueryPlan {
 
 // chi^2_alpha(K): Pr[Y > x] = alpha for Y ~ chi^2(K), K even, by bisection on the
 // closed form Pr[Y > x] = exp(-x/2) sum_{i<K/2} (x/2)^i / i!  (Lemma 2).
-double chi2_upper_quantile_even(double alpha, int K) {
+// x with P(chi^2_K > x) = alpha.  Survival function of chi^2_K at x (h = x/2):
+// even K: e^-h sum_{i < K/2} h^i / i!; odd K: erfc(sqrt h) plus
+// e^-h sum_{j = 1 .. (K-1)/2} h^(j - 1/2) / Gamma(j + 1/2).
+double chi2_upper_quantile(double alpha, int K) {
     auto sf = [K](double x) {
         const double h = 0.5 * x;
-        double term = 1.0, s = 1.0;
-        for (int i = 1; i < K / 2; ++i) { term *= h / i; s += term; }
-        return std::exp(-h) * s;
+        if (K % 2 == 0) {
+            double term = 1.0, s = 1.0;
+            for (int i = 1; i < K / 2; ++i) { term *= h / i; s += term; }
+            return std::exp(-h) * s;
+        }
+        double s = std::erfc(std::sqrt(h));
+        if (K > 1) {
+            double term = 2.0 * std::sqrt(h / 3.141592653589793);   // h^(1/2) / Gamma(3/2)
+            double acc = term;
+            for (int j = 2; j <= (K - 1) / 2; ++j) { term *= h / (j - 0.5); acc += term; }
+            s += std::exp(-h) * acc;
+        }
+        return s;
     };
     double lo = 0.0, hi = 1.0;
     while (sf(hi) > alpha) hi *= 2.0;
@@ -1422,7 +1511,7 @@ detlsh_status setup_query(const detlsh_index_s* ix, int64_t nq, int32_t k, doubl
     if (s.policy == DETLSH_RMIN_FIXED) {
         // radii r_t = r_min c^t (formed by repeated multiplication), squared
         // projected radius (eps r_t)^2 and squared verification radius (c r_t)^2
-        const double eps = std::sqrt(chi2_upper_quantile_even(std::exp(-1.0 / ix->L), ix->K));
+        const double eps = std::sqrt(chi2_upper_quantile(std::exp(-1.0 / ix->L), ix->Ku));
         s.eps = eps;
         s.r_min = opts->r_min;
         s.c = c;
@@ -1505,6 +1594,15 @@ detlsh_status query_impl(detlsh_index ix, const float* Qp_in, const float* Q, in
     }
     DevBuf qpbuf, ladder;
     const float* Qp = Qp_in;
+    if (Qp && ix->Ku != ix->K) {   // the caller's L*K columns into the kernels' width (zeros between)
+        HCHECK(pool_alloc(qpbuf, (size_t)nq * ix->LK * 4, ix->device));
+        HCHECK(hipMemsetAsync(qpbuf.p, 0, (size_t)nq * ix->LK * 4, st));
+        for (int i = 0; i < ix->L; ++i)
+            HCHECK(hipMemcpy2DAsync(qpbuf.as<float>() + (size_t)i * ix->K, (size_t)ix->LK * 4, Qp + (size_t)i * ix->Ku,
+                                    (size_t)ix->L * ix->Ku * 4, (size_t)ix->Ku * 4, (size_t)nq,
+                                    hipMemcpyDeviceToDevice, st));
+        Qp = qpbuf.as<float>();
+    }
     if (!Qp) {
         float* qp = nullptr;
         if (ext) {

@@ -139,6 +139,29 @@ def test_det_only_paa_matches_oracle(dl, d, kind):
         dl.build_index(cc["X"], 4, 16, 256, 0.1, projection="paa")
 
 
+def test_save_load_padded_k(dl, tmp_path):
+    """K = 12 runs as 16 internally; the file and every export hold 12."""
+    say("save / load, K = 12")
+    cc = U.case(n=7000, d=40, L=4, K=12, N_r=64, frac=0.05, kind="mixture", nq=12, seed=76)
+    idx = dl.build_index(cc["X"], 4, 12, 64, 0.05, A=cc["A"], sample_ids=cc["sample"])
+    path = tmp_path / "index12.detlsh"
+    idx.save(path)
+    back = dl.load_index(path)
+    assert back.info["K"] == 12
+    a, b = idx.export(), back.export()
+    assert a["codes"].shape == (7000, 48) and a["B"].shape == (48, 65)
+    for key in ("A", "B", "codes", "sample_ids"):
+        assert np.array_equal(a[key], b[key]), key
+    for i in range(4):
+        for x, y in zip(idx.tree(i), back.tree(i)):
+            assert np.array_equal(x, y)
+    Q = t(cc["Q"])
+    i1, d1 = idx.query(Q, 10, 1.5, 0.1)
+    i2, d2 = back.query(Q, 10, 1.5, 0.1)
+    assert np.array_equal(i1.cpu().numpy(), i2.cpu().numpy()) and np.array_equal(d1.cpu().numpy(), d2.cpu().numpy())
+    assert idx.project(Q).shape == (12, 48)
+
+
 def test_save_load_roundtrip(dl, tmp_path):
     say("save / load")
     cc = U.case(n=9000, d=40, N_r=128, frac=0.05, kind="mixture", nq=30, seed=75)

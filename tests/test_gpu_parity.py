@@ -40,7 +40,8 @@ def t(x):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,d,L,K", [(1000, 128, 4, 16), (777, 100, 4, 16), (513, 37, 2, 8),
-                                     (300, 960, 4, 16), (129, 96, 1, 32), (2000, 24, 8, 8)])
+                                     (300, 960, 4, 16), (129, 96, 1, 32), (2000, 24, 8, 8),
+                                     (700, 64, 4, 12), (300, 40, 2, 5)])
 def test_projection_parity(dl, n, d, L, K):
     say(f"projection n={n} d={d} L={L} K={K}")
     c = U.case(n=n, d=d, L=L, K=K, N_r=16, frac=0.2, nq=5, seed=n + d)
@@ -71,7 +72,8 @@ def test_bf16_projection_close(dl, n, d):
 
 @pytest.mark.parametrize("n,d,N_r,frac,L,K", [(10_000, 128, 256, 0.1, 4, 16), (4097, 64, 64, 0.25, 4, 16),
                                               (3000, 32, 16, 0.1, 2, 8), (2500, 48, 4, 0.05, 8, 4),
-                                              (20_000, 16, 256, 0.02, 1, 32)])
+                                              (20_000, 16, 256, 0.02, 1, 32), (3000, 48, 64, 0.1, 4, 12),
+                                              (2000, 20, 16, 0.1, 8, 3)])
 def test_breakpoints_and_codes(dl, n, d, N_r, frac, L, K):
     say(f"breakpoints/codes n={n} d={d} N_r={N_r} frac={frac} L={L} K={K}")
     c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=frac, seed=n % 97)
@@ -110,7 +112,8 @@ def test_codes_across_persistent_tiles(dl):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,K,N_r,max_leaf,kind", [(6000, 16, 64, 16, "mixture"), (20_000, 8, 16, 64, "mixture"),
-                                                   (5000, 4, 4, 8, "smallint"), (3000, 32, 256, 4, "mixture")])
+                                                   (5000, 4, 4, 8, "smallint"), (3000, 32, 256, 4, "mixture"),
+                                                   (6000, 12, 64, 16, "mixture"), (4000, 5, 16, 8, "smallint")])
 def test_tree_runs_match_oracle_tree(dl, n, K, N_r, max_leaf, kind):
     say(f"trees n={n} K={K} N_r={N_r} max_leaf={max_leaf} kind={kind}")
     L = 2
@@ -181,7 +184,8 @@ def test_candidates_and_results_fed_oracle_encoding(dl, n, d, N_r, k, beta, kind
     _fed_oracle_case(dl, c, k, beta)
 
 
-@pytest.mark.parametrize("L,K", [(1, 16), (2, 32), (8, 8), (4, 4), (1, 4), (2, 8)])
+@pytest.mark.parametrize("L,K", [(1, 16), (2, 32), (8, 8), (4, 4), (1, 4), (2, 8), (4, 12), (2, 5), (1, 1),
+                                 (8, 3)])
 def test_fed_oracle_other_tree_shapes(dl, L, K):
     say(f"fed-oracle query L={L} K={K}")
     c = U.case(n=5000, d=48, L=L, K=K, N_r=32, frac=0.1, nq=8, seed=L * 10 + K)
@@ -420,6 +424,7 @@ def test_bf16_rerank_form(dl, n, d, k):
     (12_345, 32, 1, 32, 128, 0.02, 7, "mixture", 17),
     (8_200, 40, 4, 4, 16, 0.1, 10, "smallint", 19),
     (30_000, 64, 2, 32, 256, 0.3, 3, "integer", 16),
+    (25_000, 48, 4, 12, 128, 0.02, 10, "mixture", 20),
 ])
 def test_screen_filter_equals_plain_filter(dl, n, d, L, K, N_r, beta, k, kind, nq):
     """The MFMA screen (ball around each clamped cell) plus exact bounds of its
@@ -518,27 +523,33 @@ def _ladder_borderline(lb, eps, r_min, c, rounds, rel=1e-5):
     return out
 
 
-@pytest.mark.parametrize("c,div,beta,k,kind", [(1.5, 40.0, 0.1, 10, "mixture"), (2.0, 40.0, 0.1, 10, "integer"),
-                                                (1.5, 5.0, 0.05, 25, "mixture"), (1.5, 40.0, 0.99, 5, "mixture")])
-def test_fixed_ladder_fed_oracle_encoding(dl, c, div, beta, k, kind):
-    say(f"fixed ladder c={c} r_min=r*/{div} beta={beta} k={k} kind={kind}")
-    cc = U.case(n=6000, d=48, N_r=64, frac=0.1, kind=kind, nq=10, seed=61)
+@pytest.mark.parametrize("c,div,beta,k,kind,L,K", [(1.5, 40.0, 0.1, 10, "mixture", 4, 16),
+                                                    (2.0, 40.0, 0.1, 10, "integer", 4, 16),
+                                                    (1.5, 5.0, 0.05, 25, "mixture", 4, 16),
+                                                    (1.5, 40.0, 0.99, 5, "mixture", 4, 16),
+                                                    (1.5, 40.0, 0.1, 10, "mixture", 2, 5),
+                                                    (2.0, 40.0, 0.1, 10, "mixture", 4, 7)])
+def test_fixed_ladder_fed_oracle_encoding(dl, c, div, beta, k, kind, L, K):
+    """The radius ladder fed the oracle's encoding; odd K checks the chi-square
+    quantile of eps (Lemma 3) for odd degrees of freedom."""
+    say(f"fixed ladder c={c} r_min=r*/{div} beta={beta} k={k} kind={kind} L={L} K={K}")
+    cc = U.case(n=6000, d=48, L=L, K=K, N_r=64, frac=0.1, kind=kind, nq=10, seed=61)
     P, B, codes = U.oracle_encoding(cc)
     B32 = B.astype(np.float32)
-    idx = dl.import_index(cc["X"], cc["A"], B32, codes, 4, 16, 64)
+    idx = dl.import_index(cc["X"], cc["A"], B32, codes, L, K, 64)
     Qp32 = O.project(cc["Q"], cc["A"]).astype(np.float32)
-    eps = O.epsilon(4, 16)
+    eps = O.epsilon(L, K)
     stops = {1: 0, 2: 0}
     for qi in range(len(cc["Q"])):
         qp = Qp32[qi].astype(np.float64)
-        mg = O.query_magic(cc["X"], cc["Q"][qi], qp, codes, B32.astype(np.float64), 4, 16, k, min(beta, 0.5))
+        mg = O.query_magic(cc["X"], cc["Q"][qi], qp, codes, B32.astype(np.float64), L, K, k, min(beta, 0.5))
         r_min = float(np.sqrt(max(mg.thr, 1e-12)) / eps / div)
-        ref = O.query_fixed(cc["X"], cc["Q"][qi], qp, codes, B32.astype(np.float64), 4, 16, k, beta, c, r_min, eps)
+        ref = O.query_fixed(cc["X"], cc["Q"][qi], qp, codes, B32.astype(np.float64), L, K, k, beta, c, r_min, eps)
         r = idx.query_debug(t(cc["Q"][qi:qi + 1]), k, c, beta, Qp=t(Qp32[qi:qi + 1]), rmin_policy=dl.RMIN_FIXED,
                             r_min=r_min, max_rounds=64)
         S = set(r["cand"][0, :int(r["counts"][0])].cpu().numpy().tolist())
         if S != set(ref.S.tolist()):
-            lb = O.lower_bounds(qp, codes, B32.astype(np.float64), 4, 16)
+            lb = O.lower_bounds(qp, codes, B32.astype(np.float64), L, K)
             assert S ^ set(ref.S.tolist()) <= _ladder_borderline(lb, eps, r_min, c, ref.rounds + 1)
             continue
         assert int(r["rounds"][0]) == ref.rounds and int(r["stop_tree"][0]) == ref.stop_tree
