@@ -1034,10 +1034,15 @@ __device__ __forceinline__ void comp_merge(float& a, float& ca, float b, float c
 // compensated (comp_sq_add, comp_merge) before its one final rounding.
 // With an implicit S (use_ims), non-members get the key (+inf, id) without
 // a gather.
+// m_full > m: the m keys are a sample of the whole list, spread over it in
+// blocks of 32 consecutive entries (entry s is list entry (s / 32) g + s % 32,
+// g = the block spacing): a prefix of a list in storage order can be one
+// cluster of points, and whole blocks keep the row gathers as local as a
+// prefix's.
 template <bool ALIGNED, bool COMP>
 __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, const float* sq,
                                             const int32_t* __restrict__ ids, int64_t m, uint64_t* __restrict__ buf,
-                                            bool use_ims = false, ImplicitS ims = ImplicitS()) {
+                                            bool use_ims = false, ImplicitS ims = ImplicitS(), int64_t m_full = 0) {
     const int hl = threadIdx.x & 31;
     const int hw = threadIdx.x >> 5;
     constexpr int R = 8;
@@ -1048,10 +1053,11 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t s = s0 + r;
-            id[r] = (s < m) ? (ids ? (int64_t)ids[s] : s) : -1;
+            const int64_t e = (m_full > m) ? (s >> 5) * ((m_full << 5) / m) + (s & 31) : s;   // the list entry
+            id[r] = (s < m) ? (ids ? (int64_t)ids[e] : e) : -1;
             skip[r] = false;
             if (use_ims && id[r] >= 0) {
-                if (!ims.member(s)) {
+                if (!ims.member(e)) {
                     skip[r] = true;
                     if (hl == 0) buf[s] = (0x7f800000ull << 32) | (uint64_t)(uint32_t)id[r];
                     id[r] = -1;
@@ -1151,7 +1157,11 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
             return;
         }
     }
-    if (use_max > 0 && m > use_max) m = use_max;
+    int64_t m_full = 0;   // a bounded sample (tau): spread over the whole list
+    if (use_max > 0 && m > use_max) {
+        m_full = m;
+        m = use_max;
+    }
     if (m < k && !keys_only) return;   // cannot happen for S (|S| >= N_S >= k)
     const int64_t q = q0 + t;
     for (int c = threadIdx.x; c < d; c += 256) sq[c] = Q[q * d + c];
@@ -1167,7 +1177,8 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
         ims.istop = stops[t];
         ims.thr = thrs[t];
     }
-    gather_keys<ALIGNED, COMP>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf, implicit_s != 0, ims);
+    gather_keys<ALIGNED, COMP>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf, implicit_s != 0, ims,
+                               m_full);
     if (keys_only) return;
     topk_u64(buf, m, k, sh);
     if (tau) {
@@ -1847,6 +1858,7 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
 constexpr int kBqList = 64;   // survivors per query and workgroup kept in LDS
 
 struct BqShared {
+    int ovf;                    // some query's list overflowed
     float aq[kDQ];              // a(q) per query (+inf: skip the query)
     uint64_t bits[2][kDQ];      // membership words of the current / next tile
     float xb[2][kDP];           // b(o) of the current / next tile's points
@@ -1985,13 +1997,8 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
 #pragma unroll
         for (int v = 0; v < 4; ++v) areg[qb][v] = sh.aq[64 * qh + 16 * qb + 4 * kq + v];
     const int pi0 = 32 * ph + m;
-    // one tile: products from LDS buffer cur, then the registers g (the next
-    // tile, fetched two tiles ago) go to the other buffer and take the tile
-    // after the next
-    auto tile_step = [&](int64_t tile, St& g) {
-        const int cur = (int)((tile - tb) & 1);
-        const int64_t p0 = tile * kDP;
-        floatx4 acc[4][2];
+    // the shifted products of the tile in LDS buffer cur
+    auto products = [&](int cur, floatx4 (&acc)[4][2]) __attribute__((always_inline)) {
 #pragma unroll
         for (int pb = 0; pb < 2; ++pb) {
             const float b = -sh.xb[cur][pi0 + 16 * pb];   // accumulator column m is point m
@@ -2011,6 +2018,15 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
                 for (int pb = 0; pb < 2; ++pb)
                     acc[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qv[qb][ks], xv[pb], acc[qb][pb], 0, 0, 0);
         }
+    };
+    // one tile: products from LDS buffer cur, then the registers g (the next
+    // tile, fetched two tiles ago) go to the other buffer and take the tile
+    // after the next
+    auto tile_step = [&](int64_t tile, St& g) {
+        const int cur = (int)((tile - tb) & 1);
+        const int64_t p0 = tile * kDP;
+        floatx4 acc[4][2];
+        products(cur, acc);
         bool any = false;
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
@@ -2042,17 +2058,55 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
         tile_step(tile + 1, g0);
         if (tile + 2 >= te) break;
     }
+    // A query whose list overflowed (its survivors crowd one split, as when the
+    // rows are stored in an order that groups near points) has this split's
+    // survivors found again here and appended straight to HBM, one global
+    // atomic each; its list is dropped.  Rare, and outside the main loop so
+    // that its global atomics cannot hold up the loop's staging loads.
+    if (threadIdx.x == 0) sh.ovf = 0;
+    __syncthreads();
+    if (threadIdx.x < kDQ && sh.cnt[threadIdx.x] > (uint32_t)kBqList) sh.ovf = 1;
+    __syncthreads();
+    if (sh.ovf) {
+        float aov[4][4];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int qi = 64 * qh + 16 * qb + 4 * kq + v;
+                aov[qb][v] = sh.cnt[qi] > (uint32_t)kBqList ? areg[qb][v] : INFINITY;
+            }
+        for (int64_t tile = tb; tile < te; ++tile) {
+            St g;
+            stage_load(tile, g);
+            stage_store(g, 0);
+            __syncthreads();
+            floatx4 acc[4][2];
+            products(0, acc);
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int qi = 64 * qh + 16 * qb + 4 * kq + v;
+                    const uint32_t w = (uint32_t)(sh.bits[0][qi] >> pi0);
+#pragma unroll
+                    for (int pb = 0; pb < 2; ++pb)
+                        if (acc[qb][pb][v] >= aov[qb][v] && ((w >> (16 * pb)) & 1u)) {
+                            const int t = qt0 + qi;
+                            const uint32_t slot = atomicAdd(&svc[t], 1u);
+                            if ((int64_t)slot < cap_sv) sv[(int64_t)t * cap_sv + slot] = (int32_t)(tile * kDP + pi0 + 16 * pb);
+                        }
+                }
+            __syncthreads();   // buffer 0 is restaged next
+        }
+    }
     // The lists are flushed once, after the last tile: one global atomic per
     // query with survivors reserves their slots (a query has a few survivors
-    // per split).  A list that overflowed sets bit 31 of the query's count,
-    // which is then above any list capacity: the query is verified by the
-    // gathered pass over S instead.
+    // per split).
     if (threadIdx.x < kDQ) {
-        const uint32_t n_all = sh.cnt[threadIdx.x];
-        const uint32_t c = min(n_all, (uint32_t)kBqList);
-        const int tq = qt0 + (int)threadIdx.x;
-        if (n_all > (uint32_t)kBqList) atomicOr(&svc[tq], 0x80000000u);
-        if (c > 0) {
+        const uint32_t c = sh.cnt[threadIdx.x];
+        if (c > 0 && c <= (uint32_t)kBqList) {
+            const int tq = qt0 + (int)threadIdx.x;
             const uint32_t base = atomicAdd(&svc[tq], c);
             for (uint32_t i = 0; i < c; ++i)
                 if ((int64_t)(base + i) < cap_sv) sv[(int64_t)tq * cap_sv + base + i] = sh.list[threadIdx.x][i];
@@ -2430,9 +2484,12 @@ hipError_t dl_launch_verify(const QueryArgs& a, int want, hipStream_t st) {
     return launch_gather(a, a.cand_id, a.cap, a.s_count, 0, want, 0, a.k, nullptr, st, 0, !a.compact_s);
 }
 
-// tau[t] = k'-th smallest exact distance over the members of S among the first
-// T entries of the list (all of them when S is compacted); +inf when fewer
-// than k' are members, which lets every member through the screen.
+// tau[t] = k'-th smallest exact distance over the members of S among T entries
+// spread over the list in blocks (all of them when the list is no longer); +inf
+// when fewer than k' are members, which lets every member through the screen.
+// Any subset of S gives a bound no smaller than S's own k'-th distance; an even
+// spread keeps it tight when the list follows a storage order that groups
+// near points (a prefix would then be one cluster).
 hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t st) {
     hipError_t e = launch_gather(a, a.cand_id, a.cap, a.s_count, T, 0, 0, kprime, a.tau, st, 0, !a.compact_s);
     if (e != hipSuccess) return e;
