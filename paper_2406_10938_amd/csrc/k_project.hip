@@ -8,44 +8,124 @@
 namespace {
 
 constexpr int kRowsPerWave = 32;                  // two 16-row MFMA blocks
-constexpr int kRowsPerBlock = 4 * kRowsPerWave;   // 4 waves
+constexpr int kCus = 256;                         // compute units of the MI355X
+constexpr size_t kLdsPerCu = 160 * 1024;          // LDS bytes per CU (gfx950)
 
 enum { EPI_COLMAJOR = 0, EPI_ROWMAJOR = 1, EPI_ENCODE = 2 };
 
+// Waves per workgroup: the breakpoint table of the encode fills most of the
+// LDS, so two encode workgroups fit on a CU and each brings eight waves; with
+// A in LDS as well (ALDS) one workgroup of sixteen waves takes the CU.
+template <int EPI, bool ALDS>
+constexpr int proj_waves() { return ALDS ? 16 : (EPI == EPI_ENCODE ? 8 : 4); }
+
+// ALIGNED: d a multiple of 16, so every 16-wide chunk lies inside the row and
+// the loads need no bounds (the general form zeroes the elements beyond d).
+__device__ __forceinline__ floatx4 ld4f(const float* __restrict__ p) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    return floatx4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ shortx4 ld4h(const uint16_t* __restrict__ p) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    return shortx4{(short)(v.x & 0xffff), (short)(v.x >> 16), (short)(v.y & 0xffff), (short)(v.y >> 16)};
+}
+// Row of A that lane m reads for column tile ct: hashes past N read row N - 1
+// (their products land in accumulator rows that are never used).
+__device__ __forceinline__ int a_row(int ct, int m, int N) {
+    const int c = ct * 16 + m;
+    return c < N ? c : N - 1;
+}
+
+// One 16-wide reduction chunk: v_mfma_f32_16x16x4f32 step s takes element s
+// of every lane's four values; v_mfma_f32_16x16x16bf16_1k takes all four.
+template <int NT>
+__device__ __forceinline__ void mma_f32(floatx4 (&acc)[2][NT], const floatx4 (&av)[NT], const floatx4& x0,
+                                        const floatx4& x1) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ct][s], x0[s], acc[0][ct], 0, 0, 0);
+            acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ct][s], x1[s], acc[1][ct], 0, 0, 0);
+        }
+}
+template <int NT>
+__device__ __forceinline__ void mma_bf16(floatx4 (&acc)[2][NT], const shortx4 (&av)[NT], const shortx4& x0,
+                                         const shortx4& x1) {
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[ct], x0, acc[0][ct], 0, 0, 0);
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[ct], x1, acc[1][ct], 0, 0, 0);
+    }
+}
+
 // Rows r of X (or rows[r] when `rows` is given) times A^T; A is N x d, N <= 16*NT.
-// Accumulator layout of v_mfma_f32_16x16x4f32: lane l holds P[4*(l/16)+v][l%16].
-// The reduction index of MFMA step s inside a 16-wide chunk at k0 is
-// k0 + 4*(l/16) + s for both operands, so each lane reads 4 consecutive values.
-template <int NT, int EPI, bool ALIGNED, bool BF16>
-__global__ __launch_bounds__(256) void project_kernel(
+// The hashes are the MFMA's first operand and the rows its second, so the
+// accumulator of v_mfma_f32_16x16x4f32 gives lane l the four consecutive
+// hashes 16 ct + 4 (l/16) + v (v = 0..3) of row 16 rb + l%16.  The reduction
+// index of MFMA step s inside a 16-wide chunk at k0 is k0 + 4*(l/16) + s for
+// both operands (all four in one BF16 step), so each lane reads 4 consecutive
+// values; a wave reads the next chunk of its rows before the products of the
+// current one.  ALDS (FP32, ALIGNED): A sits in LDS with rows padded to d + 4
+// floats (the b128 reads of eight consecutive lanes then fall on distinct
+// banks), so the rows' vector loads are the only ones the waits count.
+template <int NT, int EPI, bool ALIGNED, bool BF16, bool ALDS>
+__global__ __launch_bounds__(1024, 4) void project_kernel(
     const float* __restrict__ X, const uint16_t* __restrict__ Xbf,
     const int32_t* __restrict__ rows, int64_t M, int d,
     const float* __restrict__ A, const uint16_t* __restrict__ Abf, int N,
     float* __restrict__ Pout, int64_t ldp,
     const float* __restrict__ E, int N_r, int K, uint8_t* __restrict__ codes, int64_t n_codes)
 {
+    static_assert(!ALDS || (ALIGNED && !BF16), "A in LDS: FP32 rows, d a multiple of 16");
+    constexpr int kRowsPerBlock = proj_waves<EPI, ALDS>() * kRowsPerWave;
     extern __shared__ unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int m = lane & 15;
     const int kq = lane >> 4;
 
+    // Encode: the N_r - 1 interior breakpoints of hash e in the breadth-first
+    // order of their binary search tree (node i = 1 .. N_r - 1 at depth t holds
+    // E[e][(2 (i - 2^t) + 1) 2^(log N_r - 1 - t)]), one table of N_r + 2
+    // floats per hash.  The rows of a wave that reach depth t read nodes of
+    // one contiguous range, so they spread over the LDS banks instead of
+    // sharing the low bits of their positions; the stride of N_r + 2 puts the
+    // four tables read by one instruction (hashes 4 apart) on different banks.
     float* sE = reinterpret_cast<float*>(smem);
-    uint8_t* sC = smem + (size_t)N * (N_r + 1) * sizeof(float);
+    const int tstride = N_r + 2;
+    float* sA = sE + (EPI == EPI_ENCODE ? N * tstride : 0);   // 16-byte aligned: N % 4 == 0
+    const int lda = d + 4;
+    int logNr = 0;
+    while ((2 << logNr) <= N_r) ++logNr;   // N_r = 2^logNr
     if (EPI == EPI_ENCODE) {
-        const int tot = N * (N_r + 1);
-        for (int t = threadIdx.x; t < tot; t += blockDim.x) sE[t] = E[t];
+        const int tot = N * N_r;
+        for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+            const int e = t / N_r, i = t - e * N_r;
+            if (i == 0) continue;
+            const int dep = 31 - __clz(i);
+            const int pos = (2 * (i - (1 << dep)) + 1) << (logNr - 1 - dep);
+            sE[e * tstride + i] = E[e * (N_r + 1) + pos];
+        }
     }
+    if (ALDS) {
+        const int q4 = N * d / 4;
+        for (int t = threadIdx.x; t < q4; t += blockDim.x) {
+            const int row = (4 * t) / d, col = 4 * t - row * d;
+            *reinterpret_cast<floatx4*>(sA + row * lda + col) = ld4f(A + 4 * t);
+        }
+    }
+    if (EPI == EPI_ENCODE || ALDS) __syncthreads();
     // the encode grid is persistent (the breakpoint table is loaded once per
     // workgroup): workgroup b takes the row tiles b, b + gridDim.x, ...
     const int64_t ntile = (M + kRowsPerBlock - 1) / kRowsPerBlock;
     for (int64_t tile = blockIdx.x; tile < ntile; tile += (EPI == EPI_ENCODE ? gridDim.x : ntile)) {
-        const int64_t R0 = tile * kRowsPerBlock;
+        const int64_t R0 = tile * kRowsPerBlock + wave * kRowsPerWave;   // this wave's first row
 
         int64_t src[2];
     #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-            int64_t r = R0 + wave * kRowsPerWave + rb * 16 + m;
+            int64_t r = R0 + rb * 16 + m;
             if (r >= M) r = M - 1;
             src[rb] = rows ? (int64_t)rows[r] : r;
         }
@@ -59,42 +139,84 @@ __global__ __launch_bounds__(256) void project_kernel(
         if (!BF16) {
             const float* xr0 = X + src[0] * (int64_t)d;
             const float* xr1 = X + src[1] * (int64_t)d;
-            for (int k0 = 0; k0 < d; k0 += 16) {
-                const int kk = k0 + 4 * kq;
-                floatx4 xv0 = load4<ALIGNED>(xr0, kk, d);
-                floatx4 xv1 = load4<ALIGNED>(xr1, kk, d);
-                floatx4 av[NT];
-    #pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    const int c = ct * 16 + m;
-                    if (c < N) av[ct] = load4<ALIGNED>(A + (int64_t)c * d, kk, d);
-                    else av[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-                }
-    #pragma unroll
-                for (int s = 0; s < 4; ++s) {
+            if (ALIGNED) {
+                // two register sets for the rows: the loads of one chunk are in
+                // flight while the products of the other run (A is read from
+                // the cache at each chunk)
+                floatx4 xa0, xa1, xb0, xb1;
+                auto chunk = [&](int k0, const floatx4& x0, const floatx4& x1) {
+                    floatx4 av[NT];
     #pragma unroll
                     for (int ct = 0; ct < NT; ++ct) {
-                        acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv0[s], av[ct][s], acc[0][ct], 0, 0, 0);
-                        acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv1[s], av[ct][s], acc[1][ct], 0, 0, 0);
+                        if (ALDS)
+                            av[ct] = *reinterpret_cast<const floatx4*>(sA + a_row(ct, m, N) * lda + k0 + 4 * kq);
+                        else
+                            av[ct] = ld4f(A + (int64_t)a_row(ct, m, N) * d + k0 + 4 * kq);
                     }
+                    mma_f32<NT>(acc, av, x0, x1);
+                };
+                xa0 = ld4f(xr0 + 4 * kq);
+                xa1 = ld4f(xr1 + 4 * kq);
+                int k0 = 0;
+                for (; k0 + 16 < d; k0 += 32) {
+                    // (the scheduling barriers keep each load ahead of the
+                    // products it overlaps)
+                    xb0 = ld4f(xr0 + k0 + 16 + 4 * kq);
+                    xb1 = ld4f(xr1 + k0 + 16 + 4 * kq);
+                    __builtin_amdgcn_sched_barrier(0);
+                    chunk(k0, xa0, xa1);
+                    // chunk k0 + 32, or chunk k0 again past the end (not used)
+                    const int kn = (k0 + 32 < d ? k0 + 32 : k0) + 4 * kq;
+                    xa0 = ld4f(xr0 + kn);
+                    xa1 = ld4f(xr1 + kn);
+                    __builtin_amdgcn_sched_barrier(0);
+                    chunk(k0 + 16, xb0, xb1);
+                }
+                if (k0 < d) chunk(k0, xa0, xa1);   // an odd number of chunks
+            } else {
+                for (int k0 = 0; k0 < d; k0 += 16) {
+                    const int kk = k0 + 4 * kq;
+                    const floatx4 x0 = load4<false>(xr0, kk, d), x1 = load4<false>(xr1, kk, d);
+                    floatx4 av[NT];
+    #pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) av[ct] = load4<false>(A + (int64_t)a_row(ct, m, N) * d, kk, d);
+                    mma_f32<NT>(acc, av, x0, x1);
                 }
             }
         } else {
-            // v_mfma_f32_16x16x16bf16_1k: lane l supplies 4 consecutive reduction
-            // elements k0 + 4*(l/16) .. +3 of its row (A operand) / column (B operand).
             const uint16_t* xr0 = Xbf + src[0] * (int64_t)d;
             const uint16_t* xr1 = Xbf + src[1] * (int64_t)d;
-            for (int k0 = 0; k0 < d; k0 += 16) {
-                const int kk = k0 + 4 * kq;
-                shortx4 xv0 = load4bf<ALIGNED>(xr0, kk, d);
-                shortx4 xv1 = load4bf<ALIGNED>(xr1, kk, d);
+            if (ALIGNED) {
+                shortx4 xa0, xa1, xb0, xb1;
+                auto chunk = [&](int k0, const shortx4& x0, const shortx4& x1) {
+                    shortx4 av[NT];
     #pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    const int c = ct * 16 + m;
-                    shortx4 av = (c < N) ? load4bf<ALIGNED>(Abf + (int64_t)c * d, kk, d)
-                                         : shortx4{0, 0, 0, 0};
-                    acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv0, av, acc[0][ct], 0, 0, 0);
-                    acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xv1, av, acc[1][ct], 0, 0, 0);
+                    for (int ct = 0; ct < NT; ++ct) av[ct] = ld4h(Abf + (int64_t)a_row(ct, m, N) * d + k0 + 4 * kq);
+                    mma_bf16<NT>(acc, av, x0, x1);
+                };
+                xa0 = ld4h(xr0 + 4 * kq);
+                xa1 = ld4h(xr1 + 4 * kq);
+                int k0 = 0;
+                for (; k0 + 16 < d; k0 += 32) {
+                    xb0 = ld4h(xr0 + k0 + 16 + 4 * kq);
+                    xb1 = ld4h(xr1 + k0 + 16 + 4 * kq);
+                    __builtin_amdgcn_sched_barrier(0);
+                    chunk(k0, xa0, xa1);
+                    const int kn = (k0 + 32 < d ? k0 + 32 : k0) + 4 * kq;
+                    xa0 = ld4h(xr0 + kn);
+                    xa1 = ld4h(xr1 + kn);
+                    __builtin_amdgcn_sched_barrier(0);
+                    chunk(k0 + 16, xb0, xb1);
+                }
+                if (k0 < d) chunk(k0, xa0, xa1);
+            } else {
+                for (int k0 = 0; k0 < d; k0 += 16) {
+                    const int kk = k0 + 4 * kq;
+                    const shortx4 x0 = load4bf<false>(xr0, kk, d), x1 = load4bf<false>(xr1, kk, d);
+                    shortx4 av[NT];
+    #pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) av[ct] = load4bf<false>(Abf + (int64_t)a_row(ct, m, N) * d, kk, d);
+                    mma_bf16<NT>(acc, av, x0, x1);
                 }
             }
         }
@@ -106,8 +228,8 @@ __global__ __launch_bounds__(256) void project_kernel(
                 for (int ct = 0; ct < NT; ++ct)
     #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int64_t r = R0 + wave * kRowsPerWave + rb * 16 + 4 * kq + v;
-                        const int e = ct * 16 + m;
+                        const int64_t r = R0 + rb * 16 + m;
+                        const int e = ct * 16 + 4 * kq + v;
                         if (r < M && e < N) {
                             if (EPI == EPI_COLMAJOR) Pout[(int64_t)e * ldp + r] = acc[rb][ct][v];
                             else Pout[r * N + e] = acc[rb][ct][v];
@@ -119,74 +241,91 @@ __global__ __launch_bounds__(256) void project_kernel(
         // EPI_ENCODE: code = max b in [0, N_r-1] with E[e][b] <= h, where
         // E[e][0] = -inf and E[e][b] = B_e(b+1): the number of interior
         // breakpoints B(2..N_r) that are <= h (a tie goes to the upper region).
-        __syncthreads();
+        // Binary search over the breadth-first table: at depth t the node's
+        // key is E[p + 2^(log N_r - 1 - t)] for the code prefix p found so far,
+        // a key <= h sets the next bit, and after log N_r steps the node is
+        // N_r + code.  The searches of a lane's 4*NT values of one row block
+        // advance one step at a time together, so their table reads are
+        // independent.  N is a multiple of 4 (L*K with K a multiple of 4): a
+        // lane's four hashes are all below N or all beyond it (those read
+        // table 0 and store nothing).
+        int eq[NT];   // table of hash 16 ct + 4 kq
     #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int ct = 0; ct < NT; ++ct) {
+            const int e0 = ct * 16 + 4 * kq;
+            eq[ct] = (e0 < N ? e0 : 0) * tstride;
+        }
+    #pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            int node[NT][4];   // the search tree node, 1 at the root
     #pragma unroll
             for (int ct = 0; ct < NT; ++ct)
     #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int rl = wave * kRowsPerWave + rb * 16 + 4 * kq + v;
-                    const int e = ct * 16 + m;
-                    if (e < N) {
-                        const float h = acc[rb][ct][v];
-                        const float* Ee = sE + e * (N_r + 1);
-                        int pos = 0;
-                        for (int s = N_r >> 1; s > 0; s >>= 1)
-                            if (Ee[pos + s] <= h) pos += s;
-                        sC[rl * 64 + e] = (uint8_t)pos;
+                for (int v = 0; v < 4; ++v) node[ct][v] = 1;
+            for (int t = 0; t < logNr; ++t) {
+    #pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float b = sE[eq[ct] + v * tstride + node[ct][v]];
+                        node[ct][v] = 2 * node[ct][v] + ((b <= acc[rb][ct][v]) ? 1 : 0);
                     }
+            }
+            int pos[NT][4];   // the leaf's path bits are the code
+    #pragma unroll
+            for (int ct = 0; ct < NT; ++ct)
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) pos[ct][v] = node[ct][v] - N_r;
+            // codes layout [L][n][K]: the four codes of a lane are the bytes
+            // j..j+3 of row r in tree i, one aligned 4-byte word
+            const int64_t r = R0 + rb * 16 + m;
+    #pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                const int e0 = ct * 16 + 4 * kq;
+                if (r < M && e0 < N) {
+                    const int i = e0 / K, j = e0 - i * K;
+                    const uint32_t w = (uint32_t)pos[ct][0] | ((uint32_t)pos[ct][1] << 8) |
+                                       ((uint32_t)pos[ct][2] << 16) | ((uint32_t)pos[ct][3] << 24);
+                    *reinterpret_cast<uint32_t*>(codes + ((int64_t)i * n_codes + r) * K + j) = w;
                 }
-        __syncthreads();
-        // codes layout [L][n][K]: the tile of tree i is rows R0.. contiguous K-byte words
-        const int L = N / K;
-        const int64_t rows_here = (M - R0 < kRowsPerBlock) ? (M - R0) : kRowsPerBlock;
-        const int words_per_tree = (int)(rows_here * K / 4);
-        for (int i = 0; i < L; ++i) {
-            uint32_t* dst = reinterpret_cast<uint32_t*>(codes + ((int64_t)i * n_codes + R0) * K);
-            for (int w = threadIdx.x; w < words_per_tree; w += blockDim.x) {
-                const int byte = w * 4;
-                const int rl = byte / K;
-                const int j = byte % K;
-                const uint8_t* sp = sC + rl * 64 + i * K + j;
-                dst[w] = (uint32_t)sp[0] | ((uint32_t)sp[1] << 8) | ((uint32_t)sp[2] << 16) |
-                         ((uint32_t)sp[3] << 24);
             }
         }
-        __syncthreads();   // this tile's codes are read out before the next tile writes sC
     }
+}
+
+template <int NT, int EPI, bool ALIGNED, bool BF16, bool ALDS>
+hipError_t launch_one(const ProjectArgs& a, int64_t blocks, size_t shm, hipStream_t st) {
+    hipLaunchKernelGGL((project_kernel<NT, EPI, ALIGNED, BF16, ALDS>), dim3((unsigned)blocks),
+                       dim3(64 * proj_waves<EPI, ALDS>()), shm, st, a.X, a.Xbf, a.rows, a.M, a.d, a.A, a.Abf,
+                       a.N, a.Pout, a.ldp, a.E, a.N_r, a.K, a.codes, a.n_codes);
+    return hipGetLastError();
 }
 
 template <int NT, int EPI>
 hipError_t launch_nt(const ProjectArgs& a, hipStream_t st) {
-    int64_t blocks = (a.M + kRowsPerBlock - 1) / kRowsPerBlock;
+    const bool aligned = (a.d % 16) == 0;
+    size_t shm = 0;
+    if (EPI == EPI_ENCODE) {
+        if (a.N % 4 != 0 || a.K % 4 != 0) return hipErrorInvalidValue;   // word stores of four codes
+        shm = (size_t)a.N * (a.N_r + 2) * sizeof(float);
+        // A joins the table in LDS when both fit one workgroup's share of the CU
+        const size_t shm_a = shm + (size_t)a.N * (a.d + 4) * sizeof(float);
+        if constexpr (EPI == EPI_ENCODE) if (!a.bf16 && aligned && shm_a <= kLdsPerCu) {
+            constexpr int64_t rows_per_block = proj_waves<EPI, true>() * kRowsPerWave;
+            const int64_t blocks = std::min<int64_t>((a.M + rows_per_block - 1) / rows_per_block, kCus);
+            return launch_one<NT, EPI, true, false, true>(a, blocks, shm_a, st);
+        }
+    }
+    constexpr int64_t rows_per_block = proj_waves<EPI, false>() * kRowsPerWave;
+    int64_t blocks = (a.M + rows_per_block - 1) / rows_per_block;
     // encode: two resident workgroups per CU (the breakpoint table fills most of
     // the LDS), each looping over row tiles
-    if (EPI == EPI_ENCODE && blocks > 512) blocks = 512;
-    size_t shm = 0;
-    if (EPI == EPI_ENCODE) shm = (size_t)a.N * (a.N_r + 1) * sizeof(float) + kRowsPerBlock * 64;
-    const bool aligned = (a.d % 4) == 0;
-    dim3 grid((unsigned)blocks), block(256);
-    if (a.bf16) {
-        if (aligned)
-            hipLaunchKernelGGL((project_kernel<NT, EPI, true, true>), grid, block, shm, st, a.X, a.Xbf,
-                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
-                               a.codes, a.n_codes);
-        else
-            hipLaunchKernelGGL((project_kernel<NT, EPI, false, true>), grid, block, shm, st, a.X, a.Xbf,
-                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
-                               a.codes, a.n_codes);
-    } else {
-        if (aligned)
-            hipLaunchKernelGGL((project_kernel<NT, EPI, true, false>), grid, block, shm, st, a.X, a.Xbf,
-                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
-                               a.codes, a.n_codes);
-        else
-            hipLaunchKernelGGL((project_kernel<NT, EPI, false, false>), grid, block, shm, st, a.X, a.Xbf,
-                               a.rows, a.M, a.d, a.A, a.Abf, a.N, a.Pout, a.ldp, a.E, a.N_r, a.K,
-                               a.codes, a.n_codes);
-    }
-    return hipGetLastError();
+    if (EPI == EPI_ENCODE) blocks = std::min<int64_t>(blocks, 2 * kCus);
+    if (a.bf16)
+        return aligned ? launch_one<NT, EPI, true, true, false>(a, blocks, shm, st)
+                       : launch_one<NT, EPI, false, true, false>(a, blocks, shm, st);
+    return aligned ? launch_one<NT, EPI, true, false, false>(a, blocks, shm, st)
+                   : launch_one<NT, EPI, false, false, false>(a, blocks, shm, st);
 }
 
 template <int EPI>
