@@ -323,7 +323,7 @@ struct detlsh_index_s {
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
     DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
-    DevBuf ballb;                 // point vectors of the filter's MFMA screen, three-term BF16 form, [L][n][KB]
+    DevBuf ballb;                 // point vectors of the filter's MFMA screen, FP16, [L][n][KB]
     DevBuf codes_pm;              // codes point-major, [n][L*K] (the screen's exact pass)
     int32_t G = 0;                // guess subset size, min(n, kGuessMax)
     float emax = 0.f;             // bound on the largest ||o - bf16(o)|| (slightly above it)
@@ -423,7 +423,7 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
         HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), nullptr, nullptr, st));
     }
     if (dl_ball_supported(ix->L, ix->K)) {
-        HCHECK(pool_alloc(ix->ballb, (size_t)ix->n * ix->L * dl_ball_width_bf16(ix->K) * 2, ix->device));
+        HCHECK(pool_alloc(ix->ballb, (size_t)ix->n * ix->L * dl_ball_width(ix->K) * 2, ix->device));
         HCHECK(dl_launch_ball_table(ix->codes.as<uint8_t>(), ix->n, ix->L, ix->K, ix->E.as<float>(), ix->N_r,
                                     ix->ballb.as<uint16_t>(), st));
         HCHECK(pool_alloc(ix->codes_pm, (size_t)ix->n * ix->LK, ix->device));
@@ -1215,7 +1215,7 @@ bool implicit_s(const QueryPlan& p, bool dumps) { return p.dense && !p.leaf && !
 size_t per_query_bytes(int64_t cap, int L, const QueryPlan& p, int64_t n, int d, bool dumps = false, int K = 16) {
     const size_t nb = (size_t)(implicit_s(p, dumps) ? dl_prefix_mins(L) : L);
     size_t b = (size_t)cap * (4 + 4 + 4 + 4 * nb + 8 + 1) + 64 * 256 + 256 + (size_t)p.G * 4;
-    if (p.ball) b += (size_t)L * dl_ball_width_bf16(K) * 2 + 512;
+    if (p.ball) b += (size_t)(L + 32) * dl_ball_width(K) * 2 + 512;   // + the screen's 32 rows of padding
     if (p.ball && !p.dense) b += (size_t)((n + 63) / 64) * 8;   // the screen's survivor words
     if (p.dense) b += (size_t)((n + 63) / 64) * 8 + (size_t)p.cap_sv * 4 + (size_t)d * 2 + 64;
     return b;
@@ -1341,7 +1341,9 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
         }
         a.ballb = ix->ballb.as<uint16_t>();
         a.codes_pm = ix->codes_pm.as<uint8_t>();
-        a.uqb = reinterpret_cast<uint16_t*>(take((size_t)nqc * ix->L * dl_ball_width_bf16(ix->K) * 2));
+        // the query vectors and 32 rows of padding that the screen's last
+        // staged block may read
+        a.uqb = reinterpret_cast<uint16_t*>(take((size_t)(nqc * ix->L + 32) * dl_ball_width(ix->K) * 2));
     }
     a.out_ids = out_ids; a.out_d = out_d;
     std::vector<uint32_t> sc_host;

@@ -142,8 +142,8 @@ struct QueryArgs {
     const float* c2 = nullptr;       // (c r_min c^t)^2, t < T
     int T = 0;
     // MFMA screen of the range filter and its exact pass
-    const uint16_t* ballb = nullptr;  // point vectors, three-term BF16 form [L][n][KB]
-    uint16_t* uqb = nullptr;          // the chunk's query vectors, the same form [L][nqc][KB]
+    const uint16_t* ballb = nullptr;  // point vectors of the screen, FP16 [L][n][KB]
+    uint16_t* uqb = nullptr;          // the chunk's query vectors, FP16 [L][nqc][KB]
     const uint8_t* codes_pm = nullptr;   // codes point-major, [n][L*K] (exact pass of the screen)
     // outputs (all queries)
     int64_t* out_ids = nullptr;
@@ -155,10 +155,10 @@ bool dl_supported_lk(int L, int K);
 // the exact bound of the pairs it keeps (k_ball.hip); same output as
 // dl_launch_filter for the magic radius at point granularity.
 bool dl_ball_supported(int L, int K);
-int dl_ball_width_bf16(int K);   // KB: BF16 values per vector and tree (three-term form)
+int dl_ball_width(int K);   // KB: FP16 values per vector and tree
 // codes [L][n][K] -> point-major [n][L*K]
 hipError_t dl_launch_codes_point_major(const uint8_t* codes, int64_t n, int L, int K, uint8_t* out, hipStream_t st);
-// point vectors of the screen, three-term BF16 form [L][n][KB]
+// point vectors of the screen, FP16 [L][n][KB]
 hipError_t dl_launch_ball_table(const uint8_t* codes, int64_t n, int L, int K, const float* E, int N_r,
                                 uint16_t* outb, hipStream_t st);
 hipError_t dl_launch_ball_query(const QueryArgs& a, hipStream_t st);

@@ -7,22 +7,28 @@
 // points.  Per dimension the distance from the clamped query to the clamped
 // cell is at most the distance from the query to the cell (clamping moves the
 // query towards the range that holds both ends of every clamped cell), so
-// summed over the K dimensions of a tree it stays below LB_i(q,o)^2.  The
-// clamped cell lies inside the ball of centre c (a stored FP32 point of the
-// cell) and radius W (its half-diagonal, rounded up), so by the triangle
-// inequality
-//     (|q~ - c| - W)_+^2  <=  LB_i(q,o)^2 .
-// A pair can pass the filter's test LB_i^2 <= thr only if
-//     V_i = |q~|^2 - 2 q~.c + |c|^2 - (sqrt(thr') + W)^2  <=  0
-// (thr' = thr (1 + d) covers the rounding of the FP32 bound the filter
-// compares).  V_i is one dot product of a query vector
-//     u = [-2 q~, (1-d)|q~|^2 - (1+d) thr', 1, -2 sqrt(thr')]
+// summed over the K dimensions of a tree it stays below LB_i(q,o)^2.  Every
+// coordinate of tree i is scaled by s = 2^k with s max|B| in [4, 8) (exact,
+// and it keeps the test's sign).  A pair can pass the filter's test
+// LB_i^2 <= thr only if the scaled clamped query q~ lies within s sqrt(thr')
+// of the scaled clamped cell (thr' = thr (1 + d) covers the rounding of the
+// FP32 bound the filter compares).  With c^ the FP16 rounding of the cell's
+// centre, W^ >= the largest distance from c^ to a corner of the cell, q^ the
+// FP16 rounding of q~ and R^ >= s sqrt(thr') + |q~ - q^| (both rounded up to
+// FP16), the triangle inequality gives
+//     V_i = |q^|^2 - 2 q^.c^ + |c^|^2 - (R^ + W^)^2  <=  0 .
+// V_i is one dot product of a query vector
+//     u = [-2 q^, U_hi, U_lo, 1, 1, -2 R^, -2^-14],
+//     U = (1-d)|q^|^2 - (1+d) R^2 - 2^-12,
 // and a point vector
-//     p = [c, 1, (1-d)|c|^2 - (1+d) W^2, W],
-// where the d = 2^-12 terms subtract d (|q~|^2 + thr' + |c|^2 + W^2) >=
-// d/2.01 sum_k |u_k p_k|.  The GPU takes the dot product on BF16 MFMA in three
-// terms (every FP32 entry split as hi + lo), whose error is below 2.5 times
-// less than that slack; a pair is dropped when min_i V_i > 0.  The screen
+//     p = [c^, 1, 1, P_hi, P_lo, W^, 1],   P = (1-d)|c^|^2 - (1+d) W^2,
+// where the d = 2^-12 terms subtract d (|q^|^2 + R^2 + |c^|^2 + W^2) >=
+// d/2.01 sum_k |u_k p_k| and 2^-12 more.  Every entry is an FP16 number
+// (subnormals flushed to zero by the kernels themselves), so on FP16 MFMA
+// every product is exact; the FP32 sums, the hi + lo splits of U and P and
+// their flushed low parts err by far less than that slack, and the last term
+// (negative, below every other) makes the computed V of a pair that can pass
+// strictly negative.  A pair is dropped when min_i V_i > 0.  The screen
 // writes its survivors as the query's hit words (64 points per word).
 //
 // Exact pass.  The survivors are evaluated exactly as the plain filter does
@@ -41,79 +47,112 @@ __host__ __device__ inline size_t ball_align(size_t b) { return (b + 15) & ~(siz
 
 template <int K>
 struct BallDims {
-    static constexpr int NCH = (3 * (K + 3) + 1 + 31) / 32; // 32-element BF16 MFMA steps of the three-term form
-    static constexpr int KB = 32 * NCH;   // K centre terms + 3, three times, the sign term, padded
-    static constexpr int KS = 3 * (K + 3);                  // the sign term: point 1, query -2^-100
+    static constexpr int P = K + 6;                   // entries of u and p
+    static constexpr int NCH = (P + 31) / 32;         // 32-element FP16 MFMA steps
+    static constexpr int KB = 32 * NCH;               // FP16 values per vector, zero padded
 };
 
-// x - bf16(x) rounded to BF16 (the difference is exact in FP32).
-__device__ __forceinline__ uint16_t bf16_lo(float x) {
-    return dl_f32_to_bf16(x - dl_bf16_to_f32(dl_f32_to_bf16(x)));
+constexpr float kBallAbs = 0x1p-12f;    // absolute slack (scaled units)
+constexpr float kBallSign = -0x1p-14f;  // the last term of u: the smallest normal FP16, negated
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// FP16 rounding (to nearest even) as FP32, results below the smallest normal
+// FP16 flushed to zero.
+__device__ __forceinline__ float f16r(float x) {
+    const float r = (float)(_Float16)x;
+    return fabsf(r) < 0x1p-14f ? 0.0f : r;
+}
+
+// The smallest normal FP16 number >= x (x >= 0 finite; 0 for x = 0).
+__device__ __forceinline__ float f16_up(double x) {
+    if (!(x > 0.0)) return 0.0f;
+    _Float16 h = (_Float16)(float)x;
+    for (int it = 0; it < 2 && (double)(float)h < x; ++it)
+        h = __builtin_bit_cast(_Float16, (uint16_t)(__builtin_bit_cast(uint16_t, h) + 1));
+    const float r = (float)h;
+    return r < 0x1p-14f ? 0x1p-14f : r;
+}
+
+__device__ __forceinline__ uint16_t f16_bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+
+// s = 2^k with s M in [4, 8), M = the largest |interior breakpoint| of tree i
+// (1 when M is 0 or not finite).
+template <int K>
+__device__ __forceinline__ float ball_scale(const float* __restrict__ E, int N_r, int i) {
+    float M = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float* Ee = E + (int64_t)(i * K + j) * (N_r + 1);
+        M = fmaxf(M, fmaxf(fabsf(Ee[1]), fabsf(Ee[N_r - 1])));
+    }
+    if (!(M > 0.0f) || !(M < INFINITY)) return 1.0f;
+    int ex;
+    frexpf(M, &ex);   // M = m 2^ex, m in [0.5, 1)
+    return ldexpf(1.0f, 3 - ex);
 }
 
 __device__ __forceinline__ float clampf(float x, float a, float b) { return fminf(fmaxf(x, a), b); }
 
-// Point vectors p of every (tree, point) in the three-term BF16 form,
-// [L][n][KB]: hi(p), lo(p), hi(p), zeros.
+// Point vectors p of every (tree, point) in FP16, [L][n][KB] (zero padded).
 template <int K>
 __global__ __launch_bounds__(256) void ball_table_kernel(const uint8_t* __restrict__ codes, int64_t n, int L,
                                                          const float* __restrict__ E, int N_r,
                                                          uint16_t* __restrict__ outb)
 {
-    constexpr int P = K + 3;
+    constexpr int KB = BallDims<K>::KB;
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= (int64_t)L * n) return;
     const int i = (int)(g / n);
     const int ldE = N_r + 1;
+    const float sc = ball_scale<K>(E, N_r, i);
     const uint8_t* c = codes + g * K;   // [L][n][K]: row g = i*n + o
-    float v[P];
+    float v[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) v[k] = 0.0f;
     double cc = 0.0, ww = 0.0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const float* Ee = E + (int64_t)(i * K + j) * ldE;
         const float a = Ee[1], b = Ee[N_r - 1];
         const int code = c[j];
-        const float lo = clampf(Ee[code], a, b);        // region 0 starts at -inf
-        const float hi = clampf(Ee[code + 1], a, b);    // region N_r-1 ends at +inf
-        const float cj = (float)(0.5 * ((double)lo + (double)hi));
-        const double w = fmax((double)hi - (double)cj, (double)cj - (double)lo);
+        const double lo = (double)(clampf(Ee[code], a, b) * sc);       // region 0 starts at -inf
+        const double hi = (double)(clampf(Ee[code + 1], a, b) * sc);   // region N_r-1 ends at +inf
+        const float cj = f16r((float)(0.5 * (lo + hi)));
+        const double w = fmax(hi - (double)cj, (double)cj - lo);      // farthest edge from c^ (>= 0)
         v[j] = cj;
-        cc += (double)cj * (double)cj;
+        cc += (double)cj * (double)cj;   // exact: FP16 squares
         ww += w * w;
     }
-    // W >= the half-diagonal: the double root rounded to FP32, raised by 2^-20
-    const float W = (float)sqrt(ww) * (1.0f + 0x1p-20f);
-    const double Wd = (double)W;
+    const float W = f16_up(sqrt(ww) * (1.0 + 0x1p-40));
+    const float Pn = (float)((1.0 - kBallDelta) * cc - (1.0 + kBallDelta) * (double)W * (double)W);
+    const float Ph = f16r(Pn);
     v[K] = 1.0f;
-    v[K + 1] = (float)((1.0 - kBallDelta) * cc - (1.0 + kBallDelta) * Wd * Wd);
-    v[K + 2] = W;
+    v[K + 1] = 1.0f;
+    v[K + 2] = Ph;
+    v[K + 3] = f16r(Pn - Ph);   // the difference is exact in FP32
+    v[K + 4] = W;
+    v[K + 5] = 1.0f;
     // the row assembled in registers and written with 16-byte stores
-    constexpr int KB = BallDims<K>::KB;
     uint32_t w[KB / 2];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        uint32_t h = 0;
-        if (k < P || (k >= 2 * P && k < 3 * P)) h = dl_f32_to_bf16(v[k < P ? k : k - 2 * P]);
-        else if (k < 2 * P) h = bf16_lo(v[k - P]);
-        else if (k == BallDims<K>::KS) h = dl_f32_to_bf16(1.0f);
-        if (k & 1) w[k >> 1] |= h << 16;
-        else w[k >> 1] = h;
-    }
+    for (int k = 0; k < KB / 2; ++k) w[k] = (uint32_t)f16_bits(v[2 * k]) | ((uint32_t)f16_bits(v[2 * k + 1]) << 16);
     uint4* db = reinterpret_cast<uint4*>(outb + g * KB);
 #pragma unroll
     for (int j = 0; j < KB / 8; ++j) db[j] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
 }
 
-// Query vectors u of the chunk in the three-term BF16 form, [L][nqc][KB]:
-// hi(u), hi(u), lo(u), zeros.  A threshold that is not finite gives
-// u = [0, .., -1, 0, ..]: V = -1, every pair passes to the exact test.
+// Query vectors u of the chunk in FP16, [L][nqc][KB].  A threshold that is not
+// finite, or a radius beyond every scaled distance (R^ >= 128, while scaled
+// coordinates lie within 8), gives u = [0, .., -1, 0, ..]: V = -1, every pair
+// passes to the exact test.
 template <int K>
 __global__ __launch_bounds__(256) void ball_query_kernel(const float* __restrict__ Qp, int64_t q0, int nqc, int L,
                                                          const float* __restrict__ E, int N_r,
                                                          const float* __restrict__ gthr,
                                                          uint16_t* __restrict__ outb)
 {
-    constexpr int P = K + 3;
+    constexpr int KB = BallDims<K>::KB;
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= (int64_t)L * nqc) return;
     const int i = (int)(g / nqc);
@@ -121,34 +160,45 @@ __global__ __launch_bounds__(256) void ball_query_kernel(const float* __restrict
     const int ldE = N_r + 1;
     const float* q = Qp + (q0 + t) * (int64_t)(L * K) + i * K;
     const float th = gthr[t];
-    float v[P];
+    float v[KB];
 #pragma unroll
-    for (int k = 0; k < P; ++k) v[k] = 0.0f;
-    if (!(th < INFINITY)) {
-        v[K] = -1.0f;
-    } else {
-        double qq = 0.0;
+    for (int k = 0; k < KB; ++k) v[k] = 0.0f;
+    bool all = !(th < INFINITY);
+    if (!all) {
+        const float sc = ball_scale<K>(E, N_r, i);
+        double qq = 0.0, ee = 0.0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const float* Ee = E + (int64_t)(i * K + j) * ldE;
-            const float qt = clampf(q[j], Ee[1], Ee[N_r - 1]);
-            v[j] = -2.0f * qt;
-            qq += (double)qt * (double)qt;
+            const float qt = clampf(q[j], Ee[1], Ee[N_r - 1]) * sc;
+            const float qh = f16r(qt);
+            v[j] = -2.0f * qh;
+            qq += (double)qh * (double)qh;   // exact: FP16 squares
+            ee += ((double)qt - (double)qh) * ((double)qt - (double)qh);
         }
         const double tp = (double)th * (1.0 + kBallDelta);
-        v[K] = (float)((1.0 - kBallDelta) * qq - (1.0 + kBallDelta) * tp);
-        v[K + 1] = 1.0f;
-        v[K + 2] = (float)(-2.0 * sqrt(tp));
+        const float R = f16_up(((double)sc * sqrt(tp) + sqrt(ee)) * (1.0 + 0x1p-40));
+        if (R >= 128.0f) {
+            all = true;
+        } else {
+            const float Un = (float)((1.0 - kBallDelta) * qq - (1.0 + kBallDelta) * (double)R * (double)R -
+                                     (double)kBallAbs);
+            const float Uh = f16r(Un);
+            v[K] = Uh;
+            v[K + 1] = f16r(Un - Uh);   // the difference is exact in FP32
+            v[K + 2] = 1.0f;
+            v[K + 3] = 1.0f;
+            v[K + 4] = -2.0f * R;
+            v[K + 5] = kBallSign;
+        }
     }
-    uint16_t* db = outb + g * BallDims<K>::KB;
+    if (all) {
 #pragma unroll
-    for (int k = 0; k < BallDims<K>::KB; ++k) {
-        uint16_t h = 0;
-        if (k < 2 * P) h = dl_f32_to_bf16(v[k < P ? k : k - P]);
-        else if (k < 3 * P) h = bf16_lo(v[k - 2 * P]);
-        else if (k == BallDims<K>::KS) h = dl_f32_to_bf16(-0x1p-100f);
-        db[k] = h;
+        for (int k = 0; k < KB; ++k) v[k] = (k == K) ? -1.0f : 0.0f;
     }
+    uint16_t* db = outb + g * KB;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) db[k] = f16_bits(v[k]);
 }
 
 template <int J, int L>
@@ -159,16 +209,13 @@ __device__ __forceinline__ float ball_prefix_min(const float (&lb)[L]) {
     return r;
 }
 
-// Screen with BF16 MFMA (v_mfma_f32_16x16x32_bf16): every FP32 entry x of
-// the two vectors is split as hi = bf16(x), lo = bf16(x - hi), and the dot
-// product is taken as hi(u).hi(p) + hi(u).lo(p) + lo(u).hi(p), in NCH steps
-// of 32 elements.  Its error is below (3.01 2^-16 + 64 2^-24) sum |u_k p_k|,
-// under 2.5 times less than the 2^-12 slack folded into the vectors.  Point
-// operands are rebuilt from the FP32 point vectors once per wave; the
-// queries' BF16 vectors of a 16-query block are staged in LDS (double
-// buffered, one barrier per block) for the workgroup's four waves.
+// Screen with FP16 MFMA (v_mfma_f32_16x16x32_f16), the dot products of the
+// FP16 vectors in NCH steps of 32 elements.  The point operands of a wave's
+// 64 points stay in registers; the queries' vectors of a 32-query block are
+// staged in LDS (double buffered, one barrier per block) for the
+// workgroup's four waves.
 template <int L, int K>
-__global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t* __restrict__ ballb,
+__global__ __launch_bounds__(256, 3) void ball_screen_kernel(const uint16_t* __restrict__ ballb,
                                                                   const uint16_t* __restrict__ uqb, int64_t n,
                                                                   int nqc, int q_per_block,
                                                                   uint64_t* __restrict__ bm, int64_t W)
@@ -184,9 +231,11 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
     const int lane = threadIdx.x & 63;
     const int m = lane & 15;
     const int kq = lane >> 4;
-    const int64_t wbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    // (the wave's index is uniform: in scalar registers, so are its point range and word)
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t wbase = ((int64_t)blockIdx.x * 4 + wv) * 64;
     const bool live = wbase < n;   // a wave past the last point still takes part in the staging
-    bf16x8 Bv[L][4][NCH];
+    f16x8 Bv[L][4][NCH];
     uint64_t vmask = 0;   // points of the wave's word inside the set
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -196,7 +245,7 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
         for (int i = 0; i < L; ++i)
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
-                Bv[i][b][ch] = *reinterpret_cast<const bf16x8*>(ballb + ((int64_t)i * n + o) * KB + 32 * ch + 8 * kq);
+                Bv[i][b][ch] = *reinterpret_cast<const f16x8*>(ballb + ((int64_t)i * n + o) * KB + 32 * ch + 8 * kq);
     }
     {
         const int64_t left = n - wbase;
@@ -205,19 +254,26 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
     const int ta = blockIdx.y * q_per_block;
     const int tb = (ta + q_per_block < nqc) ? ta + q_per_block : nqc;
     const int64_t word = wbase / 64;
-    // staging: the block's L x QB x KB BF16 values, 16 bytes per thread and
+    // hit word of query ta + m at bmw[m W] (the lanes with kq = 0 store it; the
+    // offset fits 32 bits for n < 2^37), and the byte addresses of lanes l ^ 16
+    // and l ^ 32 for the word's assembly
+    uint64_t* const bmw = bm + (int64_t)ta * W + word;
+    const uint32_t mo = (uint32_t)m * (uint32_t)W;
+    const int x16 = (lane ^ 16) << 2, x32 = (lane ^ 32) << 2;
+    // staging: the block's L x QB x KB FP16 values, 16 bytes per thread and
     // vector, fetched into registers one block ahead and stored into the idle
     // LDS buffer after the products (a load stored at once would make every
     // block wait for L2).  Vector g of this thread has index min(tid + 256 g,
     // NV - 1) (threads past NV repeat the last one: same value, same place).
+    // Rows past the chunk's last query read the next tree's rows or the
+    // QB rows of padding after the array; their products are never stored.
     constexpr int NV = L * QB * KB / 8;
     constexpr int NSTG = (NV + 255) / 256;
     uint4 stg[NSTG];
 #pragma unroll
     for (int g = 0; g < NSTG; ++g) stg[g] = make_uint4(0u, 0u, 0u, 0u);
-    int soff[NSTG];   // the vectors' LDS element offsets within a buffer, and their rows
-    int srow[NSTG];
-    int64_t sglb[NSTG];
+    int soff[NSTG];        // the vectors' LDS element offsets within a buffer
+    uint32_t sgo[NSTG];    // their element offsets in uqb for the block at query 0
 #pragma unroll
     for (int g = 0; g < NSTG; ++g) {
         const int x = min((int)threadIdx.x + 256 * g, NV - 1);
@@ -225,13 +281,12 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
         const int rem = x - i * (QB * KB / 8);
         const int r = rem / (KB / 8), c8 = rem - r * (KB / 8);
         soff[g] = (i * QB + r) * LDU + 8 * c8;
-        srow[g] = r;
-        sglb[g] = (int64_t)i * nqc * KB + 8 * c8;
+        sgo[g] = (uint32_t)((i * nqc + r) * KB + 8 * c8);
     }
     auto stage_load = [&](int t0) __attribute__((always_inline)) {
+        const uint16_t* ub = uqb + (int64_t)t0 * KB;
 #pragma unroll
-        for (int g = 0; g < NSTG; ++g)
-            stg[g] = *reinterpret_cast<const uint4*>(uqb + sglb[g] + (int64_t)min(t0 + srow[g], tb - 1) * KB);
+        for (int g = 0; g < NSTG; ++g) stg[g] = *reinterpret_cast<const uint4*>(ub + sgo[g]);
     };
     auto stage_store = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
@@ -260,11 +315,11 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
                     for (int b = 0; b < 4; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int ch = 0; ch < NCH; ++ch) {
-                        const bf16x8 qv =
-                            *reinterpret_cast<const bf16x8*>(&sU[buf][i][16 * qs + m][32 * ch + 8 * kq]);
+                        const f16x8 qv =
+                            *reinterpret_cast<const f16x8*>(&sU[buf][i][16 * qs + m][32 * ch + 8 * kq]);
 #pragma unroll
                         for (int b = 0; b < 4; ++b)
-                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bv[i][b][ch], qv, acc[b], 0, 0, 0);
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Bv[i][b][ch], qv, acc[b], 0, 0, 0);
                     }
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
@@ -284,13 +339,13 @@ __global__ __launch_bounds__(256, 2) void ball_screen_bf16_kernel(const uint16_t
                         for (int v = 3; v >= 0; --v) x[h] = __builtin_amdgcn_alignbit(x[h], sg[b][v], 31);
                 uint32_t lo = ((x[0] & 0xfu) | ((x[0] & 0xf0u) << 12)) << (4 * kq);
                 uint32_t hi = ((x[1] & 0xfu) | ((x[1] & 0xf0u) << 12)) << (4 * kq);
-                lo |= (uint32_t)__shfl_xor((int)lo, 16);
-                hi |= (uint32_t)__shfl_xor((int)hi, 16);
-                lo |= (uint32_t)__shfl_xor((int)lo, 32);
-                hi |= (uint32_t)__shfl_xor((int)hi, 32);
-                const int t = t0 + 16 * qs + m;
-                if (kq == 0 && t < tb && word < W)
-                    bm[(int64_t)t * W + word] = ((uint64_t)lo | ((uint64_t)hi << 32)) & vmask;
+                lo |= (uint32_t)__builtin_amdgcn_ds_bpermute(x16, (int)lo);
+                hi |= (uint32_t)__builtin_amdgcn_ds_bpermute(x16, (int)hi);
+                lo |= (uint32_t)__builtin_amdgcn_ds_bpermute(x32, (int)lo);
+                hi |= (uint32_t)__builtin_amdgcn_ds_bpermute(x32, (int)hi);
+                const int tq = t0 - ta + 16 * qs;   // the set's first query, from the workgroup's
+                if (kq == 0 && m < tb - ta - tq)
+                    (bmw + (int64_t)tq * W)[mo] = ((uint64_t)lo | ((uint64_t)hi << 32)) & vmask;
             }
         }
         stage_store(buf ^ 1);
@@ -504,11 +559,12 @@ hipError_t launch_ball_screen_lk(const QueryArgs& a, hipStream_t st) {
     // 4 waves of 64 points per workgroup; the chunk's queries are split when
     // the points alone give too few workgroups
     const int64_t nblk = (a.n + 255) / 256;
+    if ((int64_t)L * (a.nqc + 32) * BallDims<K>::KB >= (int64_t)1 << 31) return hipErrorInvalidValue;
     int ysplit = 1;
     while (nblk * ysplit < 2048 && a.nqc / (ysplit * 2) >= 64) ysplit *= 2;
     const int qpb = (int)(((a.nqc + ysplit - 1) / ysplit + 31) / 32 * 32);   // whole staged blocks of 32
     const int gy = (a.nqc + qpb - 1) / qpb;
-    hipLaunchKernelGGL((ball_screen_bf16_kernel<L, K>), dim3((unsigned)nblk, (unsigned)gy), dim3(256), 0, st,
+    hipLaunchKernelGGL((ball_screen_kernel<L, K>), dim3((unsigned)nblk, (unsigned)gy), dim3(256), 0, st,
                        a.ballb, a.uqb, a.n, a.nqc, qpb, a.bm, a.W);
     return hipGetLastError();
 }
@@ -576,7 +632,7 @@ bool dl_ball_supported(int L, int K) {
     }
 }
 
-int dl_ball_width_bf16(int K) {
+int dl_ball_width(int K) {
     switch (K) {
         case 4: return BallDims<4>::KB;
         case 8: return BallDims<8>::KB;
