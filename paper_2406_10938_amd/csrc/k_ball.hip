@@ -354,8 +354,10 @@ __global__ __launch_bounds__(256, 3) void ball_screen_kernel(const uint16_t* __r
     }
 }
 
-constexpr int kExactThreads = 512;   // threads of an exact-pass workgroup: one survivor each per batch
-constexpr int kExactList = 2048;     // ring of survivor ids in LDS (a multiple of kExactThreads)
+// threads of an exact-pass workgroup (one survivor each per batch): two
+// workgroups per CU fit the LDS, 32 waves in all with at most 64 VGPRs each
+constexpr int kExactThreads = 1024;
+constexpr int kExactList = 3072;     // ring of survivor ids in LDS (a multiple of kExactThreads)
 
 // Exclusive prefix of per-thread counts over a workgroup of NW waves (every
 // thread takes part); the total goes to *tot.  wtot: NW words of LDS.
@@ -398,6 +400,10 @@ __device__ __forceinline__ uint32_t wg_flag_prefix(bool f, uint32_t* wtot, uint3
     return pre + (uint32_t)dl_rank_below(msk);
 }
 
+// Entries per dimension of the exact pass's table (N_r <= 256): a fixed
+// stride makes a dimension's offset a constant of the LDS read.
+constexpr int kExactStride = 256;
+
 struct ExactLds {
     size_t sE, list, wtot, total;
 };
@@ -405,7 +411,7 @@ struct ExactLds {
 __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
     ExactLds s;
     size_t o = 0;
-    s.sE = o;    o += ball_align((size_t)LK * N_r * 4);
+    s.sE = o;    o += ball_align((size_t)LK * kExactStride * 4);
     s.list = o;  o += ball_align((size_t)kExactList * 4);
     s.wtot = o;  o += ball_align(16 * 4 + 4);
     s.total = o;
@@ -415,9 +421,9 @@ __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
 // Exact pass: one workgroup per (query, slice of words).  The workgroup first
 // tabulates, for its query, d = q - med3(q, lo, hi) of every (dimension,
 // region) in LDS (the plain filter's first two operations on the same
-// values).  The screen's survivors are ranked chunk by chunk (512 words, a
+// values).  The screen's survivors are ranked chunk by chunk (1024 words, a
 // workgroup prefix of popcounts) into a ring of point ids in LDS; every full
-// batch of 512 (and the rest at the end) is evaluated one survivor per
+// batch of 1024 (and the rest at the end) is evaluated one survivor per
 // thread: fma(d, d, a) over the tabulated d of its regions in the plain
 // filter's order, so the bounds are bit-identical to it at one LDS read and
 // one fma per term.  Candidates (m^2 <= thr) are appended to the query's list
@@ -425,7 +431,7 @@ __host__ __device__ inline ExactLds exact_lds(int LK, int N_r) {
 // the candidates, which is all the verification needs (it re-checks the
 // membership of what it keeps).
 template <int L, int K, bool PREFIX>
-__global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
+__global__ __launch_bounds__(kExactThreads, 8) void ball_exact_kernel(
     const float* __restrict__ E, int N_r, const uint8_t* __restrict__ codes_pm, int64_t n,
     const float* __restrict__ Qp, int64_t q0, const float* __restrict__ gthr, int64_t words_per_slice,
     uint32_t* __restrict__ counts, int64_t cap, int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
     for (int x = threadIdx.x; x < LK * N_r; x += kExactThreads) {
         const int e = x / N_r, code = x - e * N_r;
         const float q = qp[e];
-        sE[x] = q - __builtin_amdgcn_fmed3f(q, E[e * ldE + code], E[e * ldE + code + 1]);
+        sE[e * kExactStride + code] = q - __builtin_amdgcn_fmed3f(q, E[e * ldE + code], E[e * ldE + code + 1]);
     }
     const int64_t w_lo = (int64_t)blockIdx.y * words_per_slice;
     const int64_t w_hi = (w_lo + words_per_slice < W) ? w_lo + words_per_slice : W;
@@ -477,7 +483,7 @@ __global__ __launch_bounds__(kExactThreads) void ball_exact_kernel(
                 for (int jj = 0; jj < K; ++jj) {
                     const int e = i * K + jj;
                     const uint32_t code = (words[e >> 2] >> (8 * (e & 3))) & 0xffu;
-                    dd[jj] = sE[e * N_r + code];
+                    dd[jj] = sE[e * kExactStride + code];
                 }
                 float acc = 0.0f;
 #pragma unroll
