@@ -397,6 +397,10 @@ detlsh_status check_shape(int64_t n, int32_t d, int32_t L, int32_t K, int32_t N_
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The BF16 copy of X and 64 rows of zeros after it: the dense verification's
+// last point tile reads whole tiles.
+size_t xbf_bytes(int64_t n, int d) { return ((size_t)n + 64) * (size_t)d * 2; }
+
 // Shared tail of build and import: row norms, trees.
 detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     HCHECK(pool_alloc(ix->xn, (size_t)ix->n * 4, ix->device));
@@ -502,7 +506,8 @@ detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_buil
     }
     const bool want_bf = opts && (opts->keep_bf16 || opts->proj_bf16);
     if (want_bf) {
-        HCHECK(pool_alloc(ix->Xbf, (size_t)nd * 2, ix->device));
+        HCHECK(pool_alloc(ix->Xbf, xbf_bytes(ix->n, ix->d), ix->device));
+        HCHECK(hipMemsetAsync(ix->Xbf.as<uint16_t>() + nd, 0, xbf_bytes(ix->n, ix->d) - (size_t)nd * 2, st));
         DlTimer tm(T_BF16, st);
         HCHECK(dl_launch_to_bf16(ix->X.as<float>(), ix->Xbf.as<uint16_t>(), nd, st));
     }
@@ -788,7 +793,7 @@ detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void
     // new arrays first: on failure the index is untouched
     DevBuf X, codes, Xbf, newbf;
     if (X.alloc((size_t)n1 * d * 4) != hipSuccess || codes.alloc((size_t)n1 * ix->LK) != hipSuccess ||
-        (keep_bf16 && Xbf.alloc((size_t)n1 * d * 2) != hipSuccess) ||
+        (keep_bf16 && Xbf.alloc(xbf_bytes(n1, d)) != hipSuccess) ||
         (ix->proj_bf16 && !keep_bf16 && newbf.alloc((size_t)m * d * 2) != hipSuccess))
         return fail(DETLSH_ENOMEM, "no room for %lld more points", (long long)m);
     HCHECK(hipMemcpyAsync(X.p, ix->X.p, (size_t)n0 * d * 4, hipMemcpyDeviceToDevice, st));
@@ -798,6 +803,7 @@ detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void
                             ix->L, hipMemcpyDeviceToDevice, st));
     const uint16_t* bf_new = nullptr;
     if (keep_bf16) {
+        HCHECK(hipMemsetAsync(Xbf.as<uint16_t>() + n1 * d, 0, xbf_bytes(n1, d) - (size_t)n1 * d * 2, st));
         HCHECK(hipMemcpyAsync(Xbf.p, ix->Xbf.p, (size_t)n0 * d * 2, hipMemcpyDeviceToDevice, st));
         HCHECK(dl_launch_to_bf16(X.as<float>() + n0 * d, Xbf.as<uint16_t>() + n0 * d, m * d, st));
         bf_new = Xbf.as<uint16_t>() + n0 * d;

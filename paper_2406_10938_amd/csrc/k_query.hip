@@ -1855,11 +1855,11 @@ __global__ __launch_bounds__(256, 2) void dense_verify_kc_kernel(
 // register-held a(q); only a wave with a passing product reads the tile's
 // membership words (staged in LDS with the tile) and appends.  Reduction
 // order, screen and survivor lists are those of dense_verify_kc_kernel.
-constexpr int kBqList = 64;   // survivors per query and workgroup kept in LDS
+constexpr int kBqList = 40;   // survivors per query and workgroup kept in LDS (three workgroups per CU)
 
 struct BqShared {
+    float aq[kDQ];              // a(q) per query (+inf: skip the query); 16-byte aligned
     int ovf;                    // some query's list overflowed
-    float aq[kDQ];              // a(q) per query (+inf: skip the query)
     uint64_t bits[2][kDQ];      // membership words of the current / next tile
     float xb[2][kDP];           // b(o) of the current / next tile's points
     uint32_t cnt[kDQ];
@@ -1894,7 +1894,7 @@ struct BqStage {
 };
 
 template <int NK>
-__global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
+__global__ __launch_bounds__(256, 3) void dense_verify_bq_kernel(
     const uint16_t* __restrict__ Xbf, const float* __restrict__ xn, int64_t n, int d,
     const uint16_t* __restrict__ Qbf, const float* __restrict__ qn, int nqc, const uint64_t* __restrict__ bm,
     int64_t W, const float* __restrict__ tau, const int32_t* __restrict__ status, float margin_c,
@@ -1906,7 +1906,7 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
     constexpr int VPR = St::VPR;
     constexpr int SV = St::SV;
     static_assert(kDP * VPR % 256 == 0, "staging covers the tile exactly");
-    __shared__ BqShared sh;
+    __shared__ __attribute__((aligned(16))) BqShared sh;
     __shared__ __attribute__((aligned(16))) uint16_t sx[2][kDP * LD];
     const int64_t lid = blockIdx.x;
     const int xcd = (int)(lid & 7);
@@ -1948,27 +1948,28 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
         }
     }
     // Thread t stages vectors t + 256 i of a tile (row x / VPR, vector x %
-    // VPR).  Every load is issued by every thread from a clamped, in-bounds
-    // address (tiles past the split reload its last one), and what lies beyond
-    // d or n is masked only when the vectors are stored: loads under a branch,
-    // or masked at once, make the products wait for them.
+    // VPR), at element offsets within the tile that every tile shares.  Every
+    // load is issued by every thread from an in-bounds address (tiles past the
+    // split reload its last one; the last tile's rows past n read the rows of
+    // padding after the BF16 array, whose points have no membership bits),
+    // and what lies beyond d is masked only when the vectors are stored: loads
+    // under a branch, or masked at once, make the products wait for them.
+    uint32_t soff[SV];
+#pragma unroll
+    for (int i = 0; i < SV; ++i) {
+        const int x = (int)threadIdx.x + 256 * i;
+        soff[i] = (uint32_t)((x / VPR) * d + min(8 * (x % VPR), d - 8));
+    }
+    const uint64_t* const bmq = bm + (int64_t)tqm * W;
     auto stage_load = [&](int64_t tile, St& g) {
         tile = tile < te ? tile : te - 1;
         const uint16_t* xb = Xbf + tile * (int64_t)kDP * d;
-        const int xlim = (int)min((int64_t)(kDP - 1), n - 1 - tile * kDP);
 #pragma unroll
-        for (int i = 0; i < SV; ++i) {
-            const int x = (int)threadIdx.x + 256 * i;
-            const int row = min(x / VPR, xlim);
-            const int k = 8 * (x % VPR);
-            const uint2* src = reinterpret_cast<const uint2*>(xb + row * d + min(k, d - 8));
-            const uint2 lo = src[0], hi = src[1];
-            g.v[i] = make_uint4(lo.x, lo.y, hi.x, hi.y);
-        }
+        for (int i = 0; i < SV; ++i) g.v[i] = *reinterpret_cast<const uint4*>(xb + soff[i]);   // 16-byte aligned: d % 8 == 0
         const int64_t p = tile * kDP + (threadIdx.x & (kDP - 1));
         g.pin = p < n;
         g.xn = xn[g.pin ? p : n - 1];
-        g.bits = bm[(int64_t)tqm * W + tile];
+        g.bits = bmq[tile];
     };
     auto stage_store = [&](const St& g, int buf) {
 #pragma unroll
@@ -1990,12 +1991,15 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
     stage_load(tb + 1, g1);
     stage_load(tb + 2, g0);
     __syncthreads();
-    // a(q) of the lane's 16 accumulator rows
-    float areg[4][4];
+    // a(q) of the lane's 16 accumulator rows, read from LDS where compared
+    // (four 16-byte reads; held in registers they would cost the occupancy)
+    auto aq_rows = [&](float (&ar)[4][4]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int qb = 0; qb < 4; ++qb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) areg[qb][v] = sh.aq[64 * qh + 16 * qb + 4 * kq + v];
+        for (int qb = 0; qb < 4; ++qb) {
+            const float4 a = *reinterpret_cast<const float4*>(&sh.aq[64 * qh + 16 * qb + 4 * kq]);
+            ar[qb][0] = a.x; ar[qb][1] = a.y; ar[qb][2] = a.z; ar[qb][3] = a.w;
+        }
+    };
     const int pi0 = 32 * ph + m;
     // the shifted products of the tile in LDS buffer cur
     auto products = [&](int cur, floatx4 (&acc)[4][2]) __attribute__((always_inline)) {
@@ -2027,6 +2031,8 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
         const int64_t p0 = tile * kDP;
         floatx4 acc[4][2];
         products(cur, acc);
+        float areg[4][4];
+        aq_rows(areg);
         bool any = false;
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
@@ -2068,6 +2074,8 @@ __global__ __launch_bounds__(256, 2) void dense_verify_bq_kernel(
     if (threadIdx.x < kDQ && sh.cnt[threadIdx.x] > (uint32_t)kBqList) sh.ovf = 1;
     __syncthreads();
     if (sh.ovf) {
+        float areg[4][4];
+        aq_rows(areg);
         float aov[4][4];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
@@ -2501,9 +2509,11 @@ hipError_t dl_launch_tau(const QueryArgs& a, int64_t T, int kprime, hipStream_t 
 hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     const int64_t ntiles = (a.n + kDP - 1) / kDP;
     const int gx = (a.nqc + kDQ - 1) / kDQ;
-    // at most 8 workgroups per CU in total (four rounds of two per CU, no
-    // partial fifth round); the split count is a multiple of 8 (one per XCD)
-    int64_t gy = 2048 / gx;
+    // whole rounds of resident workgroups: 9 per CU for the BF16 kernel
+    // (three rounds of three), 8 for the others (four rounds of two); the
+    // split count is a multiple of 8 (one per XCD)
+    const bool bq = a.dense_bf16 && a.d % 8 == 0 && a.d <= 128;
+    int64_t gy = (bq ? 2304 : 2048) / gx;
     gy = gy < 8 ? 8 : (gy / 8) * 8;
     if (gy > ((ntiles + 7) / 8) * 8) gy = ((ntiles + 7) / 8) * 8;
     const int64_t tps = (ntiles + gy - 1) / gy;
@@ -2522,7 +2532,7 @@ hipError_t dl_launch_dense(const QueryArgs& a, hipStream_t st) {
     const bool qlds = al && qbytes <= 80 * 1024;
     const size_t shm = qlds ? qbytes : 0;
     const int ks = (a.d + 15) / 16;
-    if (a.dense_bf16 && a.d % 8 == 0 && a.d <= 128) {
+    if (bq) {
 #define DL_DENSE_BQ(NK)                                                                                         \
     hipLaunchKernelGGL((dense_verify_bq_kernel<NK>), dim3((unsigned)blocks), dim3(256), 0, st, a.Xbf, xn, a.n, a.d, \
                        a.Qbf, a.qn, a.nqc, a.bm, a.W, a.tau, a.status, a.margin_c, a.svc, a.sv, a.cap_sv, gx, gy,   \
