@@ -13,7 +13,6 @@
 
 namespace {
 
-constexpr int kMaxK = 32;
 constexpr int kStack = 288;
 
 __global__ void root_key_kernel(const uint8_t* __restrict__ codes_i, int64_t n, int K, int bits,
@@ -58,9 +57,16 @@ __global__ void run_starts_kernel(const uint32_t* __restrict__ flag, const uint3
     if (blockIdx.x == 0 && threadIdx.x == 0) run_start[nruns] = (int32_t)n;
 }
 
-struct Node {
-    int32_t a, b;
-    uint8_t plen[kMaxK];
+// Runs of up to split_cap<K>() points are split inside LDS (loaded once, each
+// leaf written to its final place once); larger runs in place in HBM.
+template <int K>
+constexpr int split_cap() { return K <= 16 ? 1024 : 512; }
+
+template <int K>
+struct NodeK {
+    int32_t a, b;     // the node's positions [a, b) in the run's tree arrays
+    int32_t buf;      // LDS path: the buffer that holds the node's points
+    uint8_t plen[K];  // prefix length of every dimension
 };
 
 // The arrays of the L trees whose runs one split launch serves: tree i owns
@@ -78,12 +84,25 @@ struct SplitTrees {
     int L;
 };
 
+// Adds to loc[j] the next bit of open dimension j of a point's code words w:
+// bit offset off[j] (byte j, then bits - 1 - plen_j), width wid[j] (0 when
+// the dimension's prefix is complete).
+template <int K>
+__device__ __forceinline__ void split_count(const uint32_t (&w)[K / 4], const uint32_t (&off)[K],
+                                            const uint32_t (&wid)[K], uint32_t (&loc)[K]) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) loc[j] += __builtin_amdgcn_ubfe(w[j >> 2], off[j], wid[j]);
+}
+
 // One workgroup per root run, the runs of all L trees in one launch (a tree's
 // time is its largest run's: one launch overlaps the trees' tails).  Leaf
 // records go to slots [s, s + nleaf) of the run's own position range (a run
 // of m points has at most m leaves).
-__global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, int bits, int max_leaf)
+template <int K>
+__global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits, int max_leaf)
 {
+    constexpr int CW = K / 4;                  // 32-bit code words per point
+    constexpr int CAP = split_cap<K>();
     int tree = 0;
     while (tree + 1 < T.L && blockIdx.x >= T.first[tree + 1]) ++tree;
     const int32_t* __restrict__ run_start = T.run_start[tree];
@@ -94,13 +113,15 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, in
     int32_t* __restrict__ rec_start = T.rec_start[tree];
     uint8_t* __restrict__ rec_plen = T.rec_plen[tree];
     uint32_t* __restrict__ nleaf = T.nleaf[tree];
-    __shared__ Node stack[kStack];
+    __shared__ NodeK<K> stack[kStack];
+    __shared__ NodeK<K> cur;
     __shared__ int sp;
-    __shared__ uint32_t ones[kMaxK];
+    __shared__ uint32_t ones[K];
     __shared__ uint32_t wsum[4];
     __shared__ int cnt_leaf;
-    __shared__ Node cur;
     __shared__ int best_j;
+    __shared__ int32_t lperm[2][CAP];          // LDS path: ids and code words, two buffers
+    __shared__ uint32_t lcode[2][CAP * CW];
 
     const int q = (int)(blockIdx.x - T.first[tree]);
     const int32_t s = run_start[q];
@@ -116,11 +137,21 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, in
         }
         return;
     }
+    const bool small = t - s <= CAP;
+    if (small) {
+        for (int r = tid; r < t - s; r += 256) {
+            lperm[0][r] = perm[s + r];
+            const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)(s + r) * K);
+#pragma unroll
+            for (int x = 0; x < CW; ++x) lcode[0][r * CW + x] = sw[x];
+        }
+    }
     if (tid == 0) {
         sp = 1;
         stack[0].a = s;
         stack[0].b = t;
-        for (int j = 0; j < kMaxK; ++j) stack[0].plen[j] = 1;
+        stack[0].buf = 0;
+        for (int j = 0; j < K; ++j) stack[0].plen[j] = 1;
         cnt_leaf = 0;
     }
     __syncthreads();
@@ -132,9 +163,25 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, in
         __syncthreads();
         if (cur.a < 0) break;
         const int a = cur.a, b = cur.b, size = b - a;
+        const int cb = cur.buf;
         bool all_full = true;
-        for (int j = 0; j < K; ++j) all_full = all_full && (cur.plen[j] >= bits);
+        uint32_t off[K], wid[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int pl = cur.plen[j];
+            all_full = all_full && (pl >= bits);
+            off[j] = 8 * (j & 3) + (pl < bits ? bits - 1 - pl : 0);
+            wid[j] = pl < bits ? 1u : 0u;
+        }
         if (size <= max_leaf || all_full) {
+            if (small) {   // the leaf's points go to their final place
+                for (int r = a - s + tid; r < b - s; r += 256) {
+                    perm[s + r] = lperm[cb][r];
+                    uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)(s + r) * K);
+#pragma unroll
+                    for (int x = 0; x < CW; ++x) dw[x] = lcode[cb][r * CW + x];
+                }
+            }
             if (tid == 0) {
                 const int slot = s + cnt_leaf;
                 rec_start[slot] = a;
@@ -145,15 +192,28 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, in
             continue;
         }
         // count ones of the next bit of every open dimension
-        if (tid < kMaxK) ones[tid] = 0;
+        if (tid < K) ones[tid] = 0;
         __syncthreads();
-        uint32_t loc[kMaxK];
+        uint32_t loc[K];
+#pragma unroll
         for (int j = 0; j < K; ++j) loc[j] = 0;
-        for (int r = a + tid; r < b; r += 256) {
-            const uint8_t* c = scodes + (int64_t)r * K;
-            for (int j = 0; j < K; ++j)
-                if (cur.plen[j] < bits) loc[j] += (c[j] >> (bits - 1 - cur.plen[j])) & 1u;
+        if (small) {
+            for (int r = a - s + tid; r < b - s; r += 256) {
+                uint32_t w[CW];
+#pragma unroll
+                for (int x = 0; x < CW; ++x) w[x] = lcode[cb][r * CW + x];
+                split_count<K>(w, off, wid, loc);
+            }
+        } else {
+            for (int r = a + tid; r < b; r += 256) {
+                const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K);
+                uint32_t w[CW];
+#pragma unroll
+                for (int x = 0; x < CW; ++x) w[x] = sw[x];
+                split_count<K>(w, off, wid, loc);
+            }
         }
+#pragma unroll
         for (int j = 0; j < K; ++j) {
             uint32_t v = dl_wave_sum(loc[j]);
             if (lane == 0 && v) atomicAdd(&ones[j], v);
@@ -172,15 +232,20 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, in
         }
         __syncthreads();
         const int j = best_j;
-        const int sh = bits - 1 - cur.plen[j];
+        const int sh = 8 * (j & 3) + bits - 1 - cur.plen[j];   // the bit within code word j / 4
         const int nz = size - (int)ones[j];
-        // stable partition of [a, b) by the bit: zeros to [a, a+nz), ones after
+        // stable partition of [a, b) by the bit: zeros to [a, a+nz), ones
+        // after; the LDS path writes the other buffer, the HBM path the
+        // temporaries and copies back
+        const int nb = cb ^ 1;
         uint32_t zbase = 0, obase = 0;
         for (int c0 = a; c0 < b; c0 += 256) {
             const int r = c0 + tid;
             const bool valid = r < b;
             uint32_t bit = 0;
-            if (valid) bit = (scodes[(int64_t)r * K + j] >> sh) & 1u;
+            if (valid)
+                bit = small ? (lcode[cb][(r - s) * CW + (j >> 2)] >> sh) & 1u
+                            : (reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K)[j >> 2] >> sh) & 1u;
             const uint64_t om = dl_ballot(valid && bit);
             const uint64_t zm = dl_ballot(valid && !bit);
             const int orank = dl_rank_below(om), zrank = dl_rank_below(zm);
@@ -193,31 +258,50 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int K, in
                 otot += o; ztot += z;
             }
             if (valid) {
-                const int64_t dst = bit ? (int64_t)a + nz + obase + opre + orank
-                                        : (int64_t)a + zbase + zpre + zrank;
-                tperm[dst] = perm[r];
-                const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K);
-                uint32_t* dw = reinterpret_cast<uint32_t*>(tcodes + dst * K);
-                for (int w = 0; w < K / 4; ++w) dw[w] = sw[w];
+                const int dst = bit ? a + nz + (int)(obase + opre) + orank : a + (int)(zbase + zpre) + zrank;
+                if (small) {
+                    lperm[nb][dst - s] = lperm[cb][r - s];
+#pragma unroll
+                    for (int x = 0; x < CW; ++x) lcode[nb][(dst - s) * CW + x] = lcode[cb][(r - s) * CW + x];
+                } else {
+                    tperm[dst] = perm[r];
+                    const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K);
+                    uint32_t* dw = reinterpret_cast<uint32_t*>(tcodes + (int64_t)dst * K);
+#pragma unroll
+                    for (int x = 0; x < CW; ++x) dw[x] = sw[x];
+                }
             }
             obase += otot;
             zbase += ztot;
             __syncthreads();
         }
-        for (int r = a + tid; r < b; r += 256) {
-            perm[r] = tperm[r];
-            const uint32_t* sw = reinterpret_cast<const uint32_t*>(tcodes + (int64_t)r * K);
-            uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)r * K);
-            for (int w = 0; w < K / 4; ++w) dw[w] = sw[w];
+        if (!small) {
+            for (int r = a + tid; r < b; r += 256) {
+                perm[r] = tperm[r];
+                const uint32_t* sw = reinterpret_cast<const uint32_t*>(tcodes + (int64_t)r * K);
+                uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)r * K);
+#pragma unroll
+                for (int x = 0; x < CW; ++x) dw[x] = sw[x];
+            }
+            __threadfence_block();
+            __syncthreads();
         }
-        __threadfence_block();
-        __syncthreads();
         if (tid == 0) {
-            Node c1 = cur;
-            c1.plen[j] = (uint8_t)(cur.plen[j] + 1);
-            // push the ones child first so that the zeros child is visited first
-            if (b - (a + nz) > 0 && sp < kStack) { Node o = c1; o.a = a + nz; o.b = b; stack[sp++] = o; }
-            if (nz > 0 && sp < kStack) { Node z = c1; z.a = a; z.b = a + nz; stack[sp++] = z; }
+            // push the ones child first so that the zeros child is visited
+            // first (built in place in LDS: a copy in registers, indexed by j,
+            // would live in scratch memory)
+            const uint8_t pj = (uint8_t)(cur.plen[j] + 1);
+            const int cbuf = small ? nb : 0;
+            if (b - (a + nz) > 0 && sp < kStack) {
+                stack[sp] = cur;
+                stack[sp].a = a + nz; stack[sp].b = b; stack[sp].buf = cbuf; stack[sp].plen[j] = pj;
+                ++sp;
+            }
+            if (nz > 0 && sp < kStack) {
+                stack[sp] = cur;
+                stack[sp].a = a; stack[sp].b = a + nz; stack[sp].buf = cbuf; stack[sp].plen[j] = pj;
+                ++sp;
+            }
         }
         __syncthreads();
     }
@@ -344,8 +428,15 @@ hipError_t dl_tree_split_all(int L, int64_t n, int K, int N_r, int max_leaf, int
         T.nleaf[i] = t.nleaf;
         T.first[i + 1] = T.first[i] + nruns[i];
     }
-    if (T.first[L] > 0)
-        hipLaunchKernelGGL(split_runs_kernel, dim3(T.first[L]), dim3(256), 0, st, T, K, bits, max_leaf);
+    if (T.first[L] > 0) {
+        switch (K) {
+            case 4: hipLaunchKernelGGL(split_runs_kernel<4>, dim3(T.first[L]), dim3(256), 0, st, T, bits, max_leaf); break;
+            case 8: hipLaunchKernelGGL(split_runs_kernel<8>, dim3(T.first[L]), dim3(256), 0, st, T, bits, max_leaf); break;
+            case 16: hipLaunchKernelGGL(split_runs_kernel<16>, dim3(T.first[L]), dim3(256), 0, st, T, bits, max_leaf); break;
+            case 32: hipLaunchKernelGGL(split_runs_kernel<32>, dim3(T.first[L]), dim3(256), 0, st, T, bits, max_leaf); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int i = 0; i < L; ++i) {
