@@ -6,9 +6,11 @@ single-GPU workload: build the index over the n = 10^7, d = 96 normalised
 Gaussian mixture (unit vectors; L = 4, K = 16, N_r = 256, 1% breakpoint
 sample) and answer 10,000 queries from the same generator (k = 10, c = 1.5,
 beta the smallest grid value with recall@10 >= 0.9).  Inputs are resident in
-HBM before the timed region.  Three forms are timed: plain FP32 (the `value`),
-exact FP32 results through a BF16-product screen, and BF16 + rerank (BF16
-projection and products, top 4k reranked in FP32).  Each carries recall@10
+HBM before the timed region.  Three forms are timed: plain FP32, exact FP32
+results through reduced-precision screens (FP16 products in the range
+filter's ball screen, BF16 products in the verification's screen), and
+BF16 + rerank (BF16 projection and products, top 4k reranked in FP32); the
+`value` is the fastest form at recall@10 >= 0.9.  Each carries recall@10
 and the overall ratio (Sec. 6.1) against exact k-NN over all queries and
 against the FP64 oracle's answers on a fixed subset.  Extra keys: the
 SIFT-shaped n = 10^6 workload, the serving form (p50/p99 under Poisson load)
@@ -34,6 +36,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-ops/s without packed FP32: 39.32 T
 FP32_MFMA_PEAK = 157.3           # TFLOP/s dense
 BF16_MFMA_PEAK = 2500.0          # TFLOP/s dense
+F16_MFMA_PEAK = 2500.0           # TFLOP/s dense
 
 
 def log(*a):
@@ -93,13 +96,13 @@ FORMS = {
     "fp32": {"build": {"keep_bf16": False}, "query": {"verify": "dense", "filter": "plain"},
              "dtype": "f32", "what": "plain FP32: FP32 projection, FP32 range filter, FP32-product verification, "
                                      "FP32 ranking"},
-    # the same results bit for bit: BF16-product screens with proven margins
-    # (the range filter's ball screen, and the verification's screen with a
-    # bound widened by the BF16 rounding) decide which pairs reach the exact
-    # FP32 bounds and distances
-    "fp32_bf16screen": {"build": {"keep_bf16": True}, "query": {},
-                        "dtype": "f32", "what": "exact FP32 results through BF16-product screens of the range filter "
-                                                "and the verification (identical answers to plain FP32)"},
+    # the same results bit for bit: reduced-precision screens with proven
+    # margins (FP16 products in the range filter's ball screen, BF16 products
+    # in the verification's screen with a bound widened by the BF16 rounding)
+    # decide which pairs reach the exact FP32 bounds and distances
+    "fp32_screened": {"build": {"keep_bf16": True}, "query": {},
+                      "dtype": "f32", "what": "exact FP32 results through the FP16-product range screen and the "
+                                              "BF16-product verification screen (identical answers to plain FP32)"},
     # BF16 projection and products, top-4k reranked with exact FP32 distances
     "bf16_rerank": {"build": {"keep_bf16": True, "proj_bf16": True}, "query": {"rerank_mult": 4},
                     "dtype": "bf16", "what": "BF16 projection and verification products (FP32 accumulate), "
@@ -144,10 +147,11 @@ def exact_dists(X, Q, ids):
 
 
 # query options of the serving forms on the one resident index (built with its
-# BF16 copy): plain FP32 arithmetic, exact FP32 answers through the BF16
-# screens, and BF16 products with the exact FP32 re-rank of the best 4k
+# BF16 copy): plain FP32 arithmetic, exact FP32 answers through the
+# reduced-precision screens, and BF16 products with the exact FP32 re-rank of
+# the best 4k
 SERVE_FORMS = {"fp32": {"precision": 0, "verify": "dense", "filter": "plain"},
-               "fp32_bf16screen": {"precision": 0},
+               "fp32_screened": {"precision": 0},
                "bf16": {"precision": 1}}
 
 
@@ -200,7 +204,7 @@ def serve_bench(dl, torch, nreq, loads=(0.5, 0.8, 1.1), slots=3, max_batch=512, 
     """Serving form on the resident 256-d mixture index (n = 1,000,000):
     saturation by a closed-loop backlog, then Poisson arrivals at the given
     fractions of it, for the three forms (plain FP32, exact FP32 through the
-    BF16 screens, BF16 + rerank)."""
+    reduced-precision screens, BF16 + rerank)."""
     import synth
     cfg = synth.config("C5")
     dev = torch.device("cuda:0")
@@ -464,6 +468,10 @@ def timed_steps(dl, torch, X, Q, cfg, k, beta, A, sample, form, steps, stream):
     dl.profile_enable(False, reset=False)
     prof = {name: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"], "total_ms": v["ms"]}
             for name, v in dl.profile_read().items() if v["launches"]}
+    cnt = dl.profile_counters()
+    if "range_exact" in prof:
+        prof["range_exact"]["survivors"] = cnt.get("exact_survivors", 0)
+        prof["range_exact"]["candidates"] = cnt.get("exact_candidates", 0)
     return e0.elapsed_time(e1), bsum, last, prof
 
 
@@ -488,14 +496,28 @@ def kernel_roof(name, kern, steps, cfg, nq, n, d, probe_rate, bf16_products=Fals
             r["peak_measured_note"] = ("detlsh_probe_valu: the filter's own bound arithmetic (clamp, difference, "
                                        "fused square-add, tree minima) with nothing else, on this GPU in this run")
     elif name == "range_screen":
-        # per (query, point, tree): one dot product of K + 3 terms, taken in
-        # three BF16 terms (hi.hi + hi.lo + lo.hi) on MFMA
-        fl = 2.0 * L * 3 * (K + 3) * n * per_launch_q
-        kb = 32 * ((3 * (K + 3) + 31) // 32)
-        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": BF16_MFMA_PEAK, "unit": "TFLOP/s",
-             "work": f"2 L 3 (K + 3) = {2 * L * 3 * (K + 3)} flops per (query, point): the ball-screen dot "
-                     f"products in three BF16 terms (issued padded to {kb} terms per tree, "
-                     f"{2 * L * kb} flops); {n} points x {per_launch_q:.0f} queries per launch"}
+        # per (query, point, tree): one dot product of K + 6 FP16 terms on MFMA
+        fl = 2.0 * L * (K + 6) * n * per_launch_q
+        kb = 32 * ((K + 6 + 31) // 32)
+        r = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": F16_MFMA_PEAK, "unit": "TFLOP/s",
+             "work": f"2 L (K + 6) = {2 * L * (K + 6)} flops per (query, point): the ball-screen dot products of "
+                     f"FP16 vectors (issued padded to {kb} terms per tree, {2 * L * kb} flops); {n} points x "
+                     f"{per_launch_q:.0f} queries per launch"}
+    elif name == "range_exact" and kern.get("survivors"):
+        # per launch: the LK-byte code row of every screen survivor (random
+        # gathers), the hit words (8 bytes per query and 64 points), and the
+        # candidates written (id, key and the running minima, 16 bytes at L = 4)
+        surv = kern["survivors"] / kern["launches"]
+        cand = kern["candidates"] / kern["launches"]
+        words = (n + 63) // 64
+        nb = 2 if L >= 3 else 1
+        byts = surv * LK + per_launch_q * words * 8 + cand * (8 + 4 * nb)
+        r = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "work": f"{surv:.4g} screen survivors x {LK} B of codes + {per_launch_q:.0f} queries x {words} hit "
+                     f"words x 8 B + {cand:.4g} candidates x {8 + 4 * nb} B per launch "
+                     f"({surv / (per_launch_q * n):.4f} of the pairs survive the screen, "
+                     f"{cand / (per_launch_q * n):.4f} are candidates)",
+             "algorithmic_bytes": byts}
     elif name == "dense_verify":
         fl = 2.0 * n * d * per_launch_q
         peak = BF16_MFMA_PEAK if bf16_products else FP32_MFMA_PEAK

@@ -477,6 +477,17 @@ detlsh_status detlsh_profile_read(const char** names, int64_t* launches, double*
                                   int32_t max, int32_t* count);
 
 /*
+ * Work counters of the profiled queries, summed over every device while
+ * profiling is enabled: "exact_survivors", the (query, point) pairs that the
+ * range filter's MFMA screen kept and its exact pass evaluated, and
+ * "exact_candidates", those whose exact key passed the threshold (the
+ * candidates of Sec. 5.2's range query).  Copies up to `max` (name, value)
+ * entries and returns their number in *count; waits for the device work the
+ * library has enqueued.  detlsh_profile_enable(..., reset = 1) zeroes them.
+ */
+detlsh_status detlsh_profile_counters(const char** names, int64_t* values, int32_t max, int32_t* count);
+
+/*
  * Measured issue rate of the range filter's bound arithmetic on the current
  * device: `lanes` synthetic cells (a multiple of 256), each against `nq`
  * projected queries with the filter's own per-(tree, dimension) sequence

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import BF16_RERANK, FP32, PROJ_GAUSSIAN, PROJ_PAA, RMIN_FIXED, RMIN_MAGIC, DetlshError, check, lib
 
 __all__ = ["build_index", "import_index", "load_index", "Index", "Server", "DetlshError", "FP32", "BF16_RERANK",
-           "RMIN_MAGIC", "RMIN_FIXED", "PROJ_GAUSSIAN", "PROJ_PAA", "profile_enable", "profile_read",
+           "RMIN_MAGIC", "RMIN_FIXED", "PROJ_GAUSSIAN", "PROJ_PAA", "profile_enable", "profile_read", "profile_counters",
            "trim"]
 
 
@@ -354,6 +354,16 @@ def probe_valu(nq=2048, lanes=256 * 1024 * 3):
     ms = C.c_double()
     check(lib().detlsh_probe_valu(int(nq), int(lanes), C.byref(rate), C.byref(ms)))
     return rate.value, ms.value
+
+
+def profile_counters() -> dict:
+    """Work counters of the profiled queries (see detlsh_profile_counters):
+    {"exact_survivors": n, "exact_candidates": n}."""
+    names = (C.c_char_p * 8)()
+    vals = (C.c_int64 * 8)()
+    cnt = C.c_int32()
+    check(lib().detlsh_profile_counters(names, vals, 8, C.byref(cnt)))
+    return {names[i].decode(): vals[i] for i in range(cnt.value)}
 
 
 def profile_read() -> dict:

@@ -93,6 +93,8 @@ SIGNATURES = {
     "detlsh_index_save": (C.c_int, [P, C.c_char_p]),
     "detlsh_index_load": (C.c_int, [C.c_char_p, P, C.POINTER(P)]),
     "detlsh_profile_enable": (C.c_int, [C.c_int32, C.c_int32]),
+    "detlsh_profile_counters": (C.c_int, [C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.c_int32,
+                                          C.POINTER(C.c_int32)]),
     "detlsh_profile_read": (C.c_int, [C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.c_int32, C.POINTER(C.c_int32)]),
     "detlsh_server_create": (C.c_int, [P, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(P)]),

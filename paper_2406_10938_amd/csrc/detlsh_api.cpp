@@ -247,6 +247,11 @@ struct Profiler {
 };
 Profiler g_prof;
 
+// Profiling counters: one small device array per device, allocated the first
+// time a profiled query runs there and kept until the process ends.
+const char* kStatNames[S_COUNT] = {"exact_survivors", "exact_candidates"};
+unsigned long long* g_stat[64] = {};
+
 void prof_resolve() {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     for (auto& p : g_prof.pending) {
@@ -776,6 +781,21 @@ detlsh_status get(File& fp, Checksum& ck, void* dst, size_t bytes, bool device) 
 
 }  // namespace
 
+unsigned long long* dl_stat_ptr(int dev) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on || dev < 0 || dev >= 64) return nullptr;
+    if (!g_stat[dev]) {
+        int cur = 0;
+        void* p = nullptr;
+        if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(dev) != hipSuccess) return nullptr;
+        if (hipMalloc(&p, S_COUNT * sizeof(unsigned long long)) == hipSuccess &&
+            hipMemset(p, 0, S_COUNT * sizeof(unsigned long long)) == hipSuccess)
+            g_stat[dev] = static_cast<unsigned long long*>(p);
+        (void)hipSetDevice(cur);
+    }
+    return g_stat[dev];
+}
+
 extern "C" {
 
 detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void* stream) {
@@ -1053,11 +1073,45 @@ void detlsh_trim(void) {
 }
 
 detlsh_status detlsh_profile_enable(int32_t on, int32_t reset) {
+    if (reset) prof_resolve();   // work in flight adds to the old totals
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = on != 0;
     if (reset) {
         for (int i = 0; i < T_COUNT; ++i) { g_prof.launches[i] = 0; g_prof.ms[i] = 0; }
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess) {
+            for (int dev = 0; dev < 64; ++dev)
+                if (g_stat[dev] && hipSetDevice(dev) == hipSuccess) {
+                    (void)hipDeviceSynchronize();
+                    (void)hipMemset(g_stat[dev], 0, S_COUNT * sizeof(unsigned long long));
+                }
+            (void)hipSetDevice(cur);
+        }
     }
+    return DETLSH_OK;
+}
+
+detlsh_status detlsh_profile_counters(const char** names, int64_t* values, int32_t max, int32_t* count) {
+    prof_resolve();   // the timed work has finished
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    unsigned long long tot[S_COUNT] = {};
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+        for (int dev = 0; dev < 64; ++dev) {
+            if (!g_stat[dev] || hipSetDevice(dev) != hipSuccess) continue;
+            unsigned long long v[S_COUNT] = {};
+            (void)hipDeviceSynchronize();
+            if (hipMemcpy(v, g_stat[dev], sizeof v, hipMemcpyDeviceToHost) == hipSuccess)
+                for (int i = 0; i < S_COUNT; ++i) tot[i] += v[i];
+        }
+        (void)hipSetDevice(cur);
+    }
+    int c = 0;
+    for (int i = 0; i < S_COUNT && c < max; ++i, ++c) {
+        if (names) names[c] = kStatNames[i];
+        if (values) values[c] = (int64_t)tot[i];
+    }
+    if (count) *count = c;
     return DETLSH_OK;
 }
 
@@ -1288,6 +1342,7 @@ detlsh_status run_queries(detlsh_index_s* ix, const float* Q, const float* Qp, i
     a.Q = Q; a.Qp = Qp; a.G = plan.G; a.gcodes = ix->gcodes.as<uint8_t>(); a.guess_rank = plan.rank;
     a.leaf = plan.leaf ? 1 : 0;
     a.compact_s = implicit_s(plan, dumps) ? 0 : 1;
+    a.stat = dl_stat_ptr(ix->device);
     a.gleaf = ix->gleaf.as<int32_t>();
     a.lt.leaf_of = ix->leaf_of.as<int32_t>();
     a.lt.perm = ix->perm.as<int32_t>();

@@ -111,6 +111,7 @@ struct QueryArgs {
     uint8_t* cand_f8 = nullptr;      // first admitting tree per candidate where the exact stop pass ran
     float* cand_lb = nullptr;        // L bounds per candidate; with an implicit S dl_prefix_mins(L) running minima
     int32_t* status = nullptr;
+    unsigned long long* stat = nullptr;   // profiling counters on the device (null when off): see dl_stat_ptr
     uint32_t* s_count = nullptr;
     float* thr = nullptr;
     int32_t* stop = nullptr;
@@ -202,6 +203,11 @@ struct DlTimer {
     DlTimer(int id_, hipStream_t st_);
     ~DlTimer();
 };
+// Profiling counters on device `dev` (summed by the kernels while profiling
+// is enabled; null otherwise): [0] screen survivors evaluated by the exact
+// pass, [1] those that became candidates.
+enum { S_EXACT_SURVIVORS = 0, S_EXACT_CANDIDATES, S_COUNT };
+unsigned long long* dl_stat_ptr(int dev);
 enum {
     T_PROJECT_SAMPLE = 0, T_BREAKPOINTS, T_ENCODE, T_TREE, T_QPROJECT, T_GUESS, T_FILTER, T_SELECT,
     T_VERIFY, T_BF16, T_TAU, T_DENSE, T_FINAL, T_SCREEN, T_EXACT, T_COUNT

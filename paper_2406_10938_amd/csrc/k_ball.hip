@@ -435,7 +435,7 @@ __global__ __launch_bounds__(kExactThreads, 8) void ball_exact_kernel(
     const float* __restrict__ E, int N_r, const uint8_t* __restrict__ codes_pm, int64_t n,
     const float* __restrict__ Qp, int64_t q0, const float* __restrict__ gthr, int64_t words_per_slice,
     uint32_t* __restrict__ counts, int64_t cap, int32_t* __restrict__ cand_id, float* __restrict__ cand_m,
-    float* __restrict__ cand_lb, const uint64_t* __restrict__ bm, int64_t W)
+    float* __restrict__ cand_lb, const uint64_t* __restrict__ bm, int64_t W, unsigned long long* __restrict__ stat)
 {
     constexpr int LK = L * K;
     constexpr int NB = PREFIX ? dl_prefix_mins(L) : L;
@@ -459,6 +459,7 @@ __global__ __launch_bounds__(kExactThreads, 8) void ball_exact_kernel(
     const int64_t w_hi = (w_lo + words_per_slice < W) ? w_lo + words_per_slice : W;
     const uint64_t* row = bm + (int64_t)t * W;
     __syncthreads();
+    uint64_t nsurv = 0, ncand = 0;   // the workgroup's survivors and candidates (uniform)
     // evaluates ring entries [head, head + cnt), cnt <= kExactThreads, head a
     // multiple of kExactThreads
     auto batch = [&](uint32_t head, uint32_t cnt) {
@@ -513,6 +514,7 @@ __global__ __launch_bounds__(kExactThreads, 8) void ball_exact_kernel(
         }
         uint32_t ctot;
         const uint32_t cpre = wg_flag_prefix<NW>(cand, wtot, &ctot);
+        ncand += ctot;
         if (threadIdx.x == 0) *sbase = ctot ? atomicAdd(&counts[t], ctot) : 0u;
         __syncthreads();
         if (cand) {
@@ -537,6 +539,7 @@ __global__ __launch_bounds__(kExactThreads, 8) void ball_exact_kernel(
         const uint64_t word = (wi < w_hi) ? row[wi] : 0ull;
         uint32_t tot;
         const uint32_t pre = wg_count_prefix<NW>((uint32_t)__popcll(word), wtot, &tot);
+        nsurv += tot;
         for (uint32_t p0 = 0; p0 < tot;) {
             // ranks [p0, p0 + take) of this chunk go to ring positions tail + (r - p0)
             const uint32_t take = min(tot - p0, (uint32_t)kExactList - (tail - head));
@@ -558,6 +561,10 @@ __global__ __launch_bounds__(kExactThreads, 8) void ball_exact_kernel(
         }
     }
     if (tail > head) batch(head, tail - head);
+    if (stat && threadIdx.x == 0) {
+        atomicAdd(&stat[S_EXACT_SURVIVORS], (unsigned long long)nsurv);
+        atomicAdd(&stat[S_EXACT_CANDIDATES], (unsigned long long)ncand);
+    }
 }
 
 template <int L, int K>
@@ -587,11 +594,11 @@ hipError_t launch_ball_exact_lk(const QueryArgs& a, hipStream_t st) {
     if (a.compact_s)
         hipLaunchKernelGGL((ball_exact_kernel<L, K, false>), dim3((unsigned)a.nqc, (unsigned)nsl), dim3(kExactThreads),
                            shm, st, a.E, a.N_r, a.codes_pm, a.n, a.Qp, a.q0, a.gthr, wps, a.counts, a.cap, a.cand_id,
-                           a.cand_m, a.cand_lb, a.bm, a.W);
+                           a.cand_m, a.cand_lb, a.bm, a.W, a.stat);
     else
         hipLaunchKernelGGL((ball_exact_kernel<L, K, true>), dim3((unsigned)a.nqc, (unsigned)nsl), dim3(kExactThreads),
                            shm, st, a.E, a.N_r, a.codes_pm, a.n, a.Qp, a.q0, a.gthr, wps, a.counts, a.cap, a.cand_id,
-                           a.cand_m, a.cand_lb, a.bm, a.W);
+                           a.cand_m, a.cand_lb, a.bm, a.W, a.stat);
     return hipGetLastError();
 }
 
