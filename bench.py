@@ -653,7 +653,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1500)
     ap.add_argument("--serve-only", action="store_true", help="print only the serving-form block")
     ap.add_argument("--cpu-one", type=int, default=2, help="oracle queries timed on one thread")
-    ap.add_argument("--cpu-all", type=int, default=32, help="oracle queries over the worker processes")
+    ap.add_argument("--cpu-all", type=int, default=96,
+                    help="oracle queries over the worker processes (a fixed subset: the first ones)")
     ap.add_argument("--cpu-build-rows", type=int, default=500_000)
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "next"], default=None,
                     help="print only the named workload's beta grid for two forms (c2: SIFT-shaped, k = 10 "
