@@ -90,12 +90,15 @@ def test_breakpoints_and_codes(dl, n, d, N_r, frac, L, K):
     assert hard == 0
 
 
-def test_codes_across_persistent_tiles(dl):
+@pytest.mark.parametrize("d", [16, 64])
+def test_codes_across_persistent_tiles(dl, d):
     """The encode runs a persistent grid whose workgroups each take several
-    512-row tiles once n exceeds 512 x 128 rows; codes past the first tile of
-    every workgroup are compared with the oracle's too (n = 200,000)."""
-    n, d, L, K, N_r = 200_000, 16, 4, 16, 256
-    say(f"codes across persistent tiles n={n}")
+    512-row tiles once n exceeds 512 x 256 rows; codes past the first tile of
+    every workgroup are compared with the oracle's too (n = 200,000).  d = 16
+    takes the FP32 products, d = 64 (a multiple of 32) the exact three-part
+    BF16 split of both operands."""
+    n, L, K, N_r = 200_000, 4, 16, 256
+    say(f"codes across persistent tiles n={n} d={d}")
     c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=0.01, seed=5)
     idx = dl.build_index(c["X"], L, K, N_r, 0.01, A=c["A"], sample_ids=c["sample"])
     ex = idx.export()
