@@ -135,13 +135,14 @@ __device__ __forceinline__ void load_box(const LeafTabs& lt, const int32_t* __re
 // *total_out (sum of all bins; d = -1 when r exceeds it).  Each thread sums
 // its run of nbins/256 bins, a block scan of those sums finds the one thread
 // whose run holds rank r, and it walks its run.  Uses scratch[0..3].
-__device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* scratch, int* d_out,
-                         uint64_t* before_out, uint64_t* total_out) {
+template <typename Cnt>
+__device__ void find_bin_by(Cnt hist, int nbins, uint64_t r, uint32_t* scratch, int* d_out,
+                            uint64_t* before_out, uint64_t* total_out) {
     const int per = nbins / 256;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     uint32_t s = 0;
-    for (int b = 0; b < per; ++b) s += hist[tid * per + b];
+    for (int b = 0; b < per; ++b) s += hist(tid * per + b);
     uint32_t inc = s;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -163,7 +164,7 @@ __device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* 
     if (r > excl && r <= excl + s) {
         uint64_t rr = excl;
         for (int b = 0; b < per; ++b) {
-            const uint32_t c = hist[tid * per + b];
+            const uint32_t c = hist(tid * per + b);
             if (rr + c >= r) {
                 *d_out = tid * per + b;
                 *before_out = rr;
@@ -176,10 +177,15 @@ __device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* 
     __syncthreads();
 }
 
+__device__ void find_bin(const uint32_t* hist, int nbins, uint64_t r, uint32_t* scratch, int* d_out,
+                         uint64_t* before_out, uint64_t* total_out) {
+    find_bin_by([&](int b) { return hist[b]; }, nbins, r, scratch, d_out, before_out, total_out);
+}
+
 // The r-th smallest (1-based) of m 32-bit keys get(0..m), by three radix
 // passes (12, 12, 8 bits).
 struct SelectShared {
-    uint32_t hist[8192];        // 4096 bins, 8192 in the window selection's second pass
+    uint32_t hist[4096];        // 4096 bins; the window selection's second pass packs 8192 16-bit bins
     uint32_t scratch[260];
     int d;
     uint64_t before, total;
@@ -308,14 +314,21 @@ __device__ uint32_t select_rank_u32_upto_v(const uint32_t* __restrict__ arr, int
     if (sh.d < 0) return select_rank_u32(get, m, r, sh);
     const uint64_t r2 = r - nb - sh.before;
     const uint32_t base = lo + ((uint32_t)sh.d << 13);
+    // the second pass counts the keys of bin d in 8192 bins of 16 bits, two
+    // to a word (an add of 1 << 16 to the upper one never carries), which
+    // holds while the bin has fewer than 65536 keys; else three passes
+    const bool wide = sh.hist[sh.d] >= 65536u;
     __syncthreads();
-    for (int b = threadIdx.x; b < 8192; b += 256) sh.hist[b] = 0;
+    if (wide) return select_rank_u32(get, m, r, sh);
+    for (int b = threadIdx.x; b < 4096; b += 256) sh.hist[b] = 0;
     __syncthreads();
     pass([&](uint32_t u) {
-        if (u >= base && u - base < 8192u) atomicAdd(&sh.hist[u - base], 1u);
+        const uint32_t o = u - base;
+        if (u >= base && o < 8192u) atomicAdd(&sh.hist[o >> 1], 1u << (16 * (o & 1u)));
     });
     __syncthreads();
-    find_bin(sh.hist, 8192, r2, sh.scratch, &sh.d, &sh.before, &sh.total);
+    find_bin_by([&](int b) { return (sh.hist[b >> 1] >> (16 * (b & 1))) & 0xffffu; }, 8192, r2, sh.scratch, &sh.d,
+                &sh.before, &sh.total);
     const uint32_t res = base + (uint32_t)sh.d;
     __syncthreads();
     return res;
@@ -675,7 +688,7 @@ __device__ __forceinline__ void load_lbs(const float* __restrict__ src, float (&
 }
 
 template <int L, bool FIXED, bool LEAF>
-__global__ __launch_bounds__(256) void select_kernel(const uint32_t* __restrict__ counts, int64_t cap,
+__global__ __launch_bounds__(256, 6) void select_kernel(const uint32_t* __restrict__ counts, int64_t cap,
                                                      uint64_t N_S, int32_t* __restrict__ cand_id,
                                                      const float* __restrict__ cand_m,
                                                      int32_t* __restrict__ cand_ft, const float* __restrict__ cand_lb,
