@@ -173,7 +173,7 @@ hipError_t dl_launch_valu_probe(const float* qp, int nq, float* out, int64_t lan
 hipError_t dl_launch_fill_f32(float* p, float v, int64_t n, hipStream_t st);
 // the FIXED radius ladder (eps r_t)^2, then (c r_t)^2, r_t = r_min c^t, t < rounds
 hipError_t dl_launch_ladder(float* out, int rounds, double eps, double r_min, double c, hipStream_t st);
-size_t dl_verify_smem(int d);
+size_t dl_verify_smem(int d, int k);   // LDS bytes of the gathered verification
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
 // leaf_of of one tree: out[perm[p]] = the leaf whose run holds position p.
 hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* out,

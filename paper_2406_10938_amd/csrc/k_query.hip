@@ -335,16 +335,23 @@ __device__ uint32_t select_rank_u32_upto_v(const uint32_t* __restrict__ arr, int
 }
 
 // The k smallest of m unique 64-bit keys in buf (global), sorted ascending into
-// out[0..k).  Radix descent on 12-bit digits; as soon as the keys sharing the
-// current prefix fit in LDS they are sorted there.
+// out[0..k) (an LDS array of at least topk_out_len(k) entries).  Radix descent
+// on 12-bit digits; as soon as the keys sharing the current prefix fit in LDS
+// they are sorted there.
 constexpr int kCandCap = 1024;
-constexpr int kOutCap = 1024;
+constexpr int kOutCap = 1024;   // k <= kOutCap
+
+// the bitonic sort of the output pads it to a power of two
+__host__ __device__ constexpr int topk_out_len(int k) {
+    int n = 1;
+    while (n < k) n <<= 1;
+    return n;
+}
 
 struct TopkShared {
     uint32_t hist[4096];
     uint32_t scratch[260];
     uint64_t cand[kCandCap];
-    uint64_t out[kOutCap];
     int d;
     uint64_t before, total;
     uint32_t ncand, nout;
@@ -369,7 +376,7 @@ __device__ void bitonic_sort_u64(uint64_t* a, int cnt) {
     }
 }
 
-__device__ void topk_u64(const uint64_t* buf, int64_t m, int k, TopkShared& sh) {
+__device__ void topk_u64(const uint64_t* buf, int64_t m, int k, TopkShared& sh, uint64_t* out) {
     uint64_t prefix = 0;
     int known = 0;
     uint64_t need = (uint64_t)k;
@@ -398,7 +405,7 @@ __device__ void topk_u64(const uint64_t* buf, int64_t m, int k, TopkShared& sh) 
             __syncthreads();
             bitonic_sort_u64(sh.cand, (int)M);
             const uint32_t base = sh.nout;
-            for (uint64_t j = threadIdx.x; j < need; j += 256) sh.out[base + j] = sh.cand[j];
+            for (uint64_t j = threadIdx.x; j < need; j += 256) out[base + j] = sh.cand[j];
             __syncthreads();
             if (threadIdx.x == 0) sh.nout = base + (uint32_t)need;
             __syncthreads();
@@ -409,14 +416,14 @@ __device__ void topk_u64(const uint64_t* buf, int64_t m, int k, TopkShared& sh) 
             const uint64_t key = buf[i];
             if ((known == 0 || (key >> (64 - known)) == prefix) &&
                 ((uint32_t)(key >> shift) & ((1u << nbits) - 1u)) < dsel)
-                sh.out[atomicAdd(&sh.nout, 1u)] = key;
+                out[atomicAdd(&sh.nout, 1u)] = key;
         }
         need -= sh.before;
         prefix = (prefix << nbits) | dsel;
         known += nbits;
         __syncthreads();
     }
-    bitonic_sort_u64(sh.out, (int)sh.nout);
+    bitonic_sort_u64(out, (int)sh.nout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,8 +1155,10 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
 //   tau != null     : write tau[t] = squared distance of the k-th smallest
 // Queries are processed when status[t] == want.  When `sv_check`, a list with
 // more than `sv_cap` or fewer than k entries marks the query status 2 instead.
+// LDS: TopkShared, the query (d floats), the top-k output (topk_out_len(k)
+// keys); five workgroups per CU.
 template <bool ALIGNED, bool COMP>
-__global__ __launch_bounds__(256) void gather_topk_kernel(
+__global__ __launch_bounds__(256, 5) void gather_topk_kernel(
     const float* __restrict__ X, int d, const float* __restrict__ Q, int64_t q0,
     const int32_t* __restrict__ list, int64_t ld_list, const uint32_t* __restrict__ counts, int64_t use_max,
     int64_t all_n, int32_t* __restrict__ status, int want, int sv_check, int64_t sv_cap,
@@ -1161,6 +1170,7 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     extern __shared__ unsigned char smem[];
     TopkShared& sh = *reinterpret_cast<TopkShared*>(smem);
     float* sq = reinterpret_cast<float*>(smem + sizeof(TopkShared));
+    uint64_t* sout = reinterpret_cast<uint64_t*>(smem + sizeof(TopkShared) + ((size_t)d * 4 + 7) / 8 * 8);
     const int t = blockIdx.x;
     if (!all_n && status[t] != want) return;
     int64_t m = all_n ? all_n : (int64_t)counts[t];
@@ -1193,13 +1203,13 @@ __global__ __launch_bounds__(256) void gather_topk_kernel(
     gather_keys<ALIGNED, COMP>(X, d, sq, all_n ? nullptr : list + (int64_t)t * ld_list, m, buf, implicit_s != 0, ims,
                                m_full);
     if (keys_only) return;
-    topk_u64(buf, m, k, sh);
+    topk_u64(buf, m, k, sh, sout);
     if (tau) {
-        if (threadIdx.x == 0) tau[t] = __uint_as_float((uint32_t)(sh.out[k - 1] >> 32));
+        if (threadIdx.x == 0) tau[t] = __uint_as_float((uint32_t)(sout[k - 1] >> 32));
         return;
     }
     for (int j = threadIdx.x; j < k; j += 256) {
-        const uint64_t key = sh.out[j];
+        const uint64_t key = sout[j];
         out_ids[q * k + j] = (int64_t)(uint32_t)(key & 0xffffffffu);
         out_d[q * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
     }
@@ -2154,6 +2164,7 @@ __global__ __launch_bounds__(256) void fixed_finish_kernel(
     int32_t* __restrict__ stop_out, int32_t* __restrict__ rounds_out)
 {
     __shared__ TopkShared sh;
+    __shared__ uint64_t sout[kOutCap];
     __shared__ uint32_t hist[64];
     __shared__ float sc2[64];
     __shared__ int sstar;
@@ -2225,10 +2236,10 @@ __global__ __launch_bounds__(256) void fixed_finish_kernel(
     }
     __threadfence_block();
     __syncthreads();
-    topk_u64(buf, out, k, sh);
+    topk_u64(buf, out, k, sh, sout);
     const int64_t q = q0 + t;
     for (int j = threadIdx.x; j < k; j += 256) {
-        const uint64_t key = sh.out[j];
+        const uint64_t key = sout[j];
         out_ids[q * k + j] = (int64_t)(uint32_t)(key & 0xffffffffu);
         out_d[q * k + j] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
     }
@@ -2472,7 +2483,7 @@ template <bool AL, bool COMP>
 hipError_t launch_gather_al(const QueryArgs& a, const int32_t* list, int64_t ld_list, const uint32_t* counts,
                             int64_t use_max, int want, int sv_check, int k, float* tau, hipStream_t st,
                             int keys_only, bool members) {
-    const size_t shm = sizeof(TopkShared) + (size_t)a.d * 4 + 64;
+    const size_t shm = dl_verify_smem(a.d, k);
     hipLaunchKernelGGL((gather_topk_kernel<AL, COMP>), dim3(a.nqc), dim3(256), shm, st, a.X, a.d, a.Q, a.q0, list, ld_list,
                        counts, use_max, a.all_n, a.status, want, sv_check, a.cap_sv, a.ws, a.cap, k,
                        tau ? nullptr : a.out_ids, tau ? nullptr : a.out_d, tau, keys_only, members ? 1 : 0,
@@ -2596,7 +2607,9 @@ hipError_t dl_launch_fixed_finish(const QueryArgs& a, int32_t* rounds, hipStream
     return hipGetLastError();
 }
 
-size_t dl_verify_smem(int d) { return sizeof(TopkShared) + (size_t)d * 4 + 64; }
+size_t dl_verify_smem(int d, int k) {
+    return sizeof(TopkShared) + ((size_t)d * 4 + 7) / 8 * 8 + (size_t)topk_out_len(k) * 8;
+}
 
 // ---------------------------------------------------------------------------
 // small stream-ordered fills (no host buffer to keep alive)
