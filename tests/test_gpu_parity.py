@@ -73,7 +73,8 @@ def test_bf16_projection_close(dl, n, d):
 @pytest.mark.parametrize("n,d,N_r,frac,L,K", [(10_000, 128, 256, 0.1, 4, 16), (4097, 64, 64, 0.25, 4, 16),
                                               (3000, 32, 16, 0.1, 2, 8), (2500, 48, 4, 0.05, 8, 4),
                                               (20_000, 16, 256, 0.02, 1, 32), (3000, 48, 64, 0.1, 4, 12),
-                                              (2000, 20, 16, 0.1, 8, 3)])
+                                              (2000, 20, 16, 0.1, 8, 3), (3000, 64, 16, 0.1, 1, 4),
+                                              (3000, 96, 256, 0.1, 8, 8)])
 def test_breakpoints_and_codes(dl, n, d, N_r, frac, L, K):
     say(f"breakpoints/codes n={n} d={d} N_r={N_r} frac={frac} L={L} K={K}")
     c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=frac, seed=n % 97)
@@ -343,6 +344,43 @@ def test_small_stop_tree_on_the_implicit_dense_path(dl, verify, L, K):
             assert ref.stop_tree == 1
         assert int(r["stop_tree"][qi]) == ref.stop_tree
         U.compare_result(ref.ids, ref.dists, X, Q[qi], d_ids[qi].cpu().numpy(), d_d[qi].cpu().numpy(), ref.S, k)
+
+
+@pytest.mark.parametrize("n,beta,near", [(200_000, 0.4, 15_000), (600_000, 0.11, 5_000)])
+def test_selection_with_a_tied_bin_above_65536_keys(dl, n, beta, near):
+    """The selection's second window pass counts the keys of one first-pass bin
+    in 16-bit bins, which holds below 65,536 keys; a bin with more takes the
+    three-pass selection.  Here 66,000 identical points hold the N_S-th
+    smallest m^2 (a few thousand points lie next to the query, the rest at
+    about twice the cluster's m^2, so that the guess threshold stays within
+    the window's four binades of it), so one bin holds at least 66,000 keys
+    while the candidate count stays inside the planned capacity (N_S = 0.4 n:
+    the plain filter; N_S = 0.11 n: the range screen).  The threshold, the
+    stop tree and the answers are the oracle's."""
+    say(f"selection with a tied bin n={n} beta={beta} near={near}")
+    c = U.case(n=n, d=32, L=4, K=16, N_r=256, frac=0.01, kind="mixture", nq=4, seed=43)
+    X, Q = c["X"].copy(), c["Q"].copy()
+    q = Q[0]
+    rng = np.random.default_rng(44)
+    ncl = 66_000
+    X[:near] = q + 1e-3 * rng.standard_normal((near, X.shape[1])).astype(np.float32)
+    X[near:near + ncl] = q + 0.5
+    X[near + ncl:] = q + 0.7 + 0.05 * rng.standard_normal((n - near - ncl, X.shape[1])).astype(np.float32)
+    k = 10
+    idx = dl.build_index(X, 4, 16, 256, 0.01, A=c["A"], sample_ids=c["sample"], keep_bf16=True)
+    Qt = t(Q[:1])
+    ids, dists = idx.query(Qt, k, 1.5, beta)
+    ex = idx.export()
+    Qp = idx.project(Qt).cpu().numpy()
+    r = idx.query_debug(Qt, k, 1.5, beta, Qp=t(Qp))
+    ref = U.oracle_query(X, q, Qp[0], ex["codes"], ex["B"], 4, 16, k, beta)
+    m2 = O.lower_bounds(np.asarray(Qp[0], np.float64), ex["codes"], np.asarray(ex["B"], np.float64), 4, 16).min(axis=1)
+    ties = int(np.count_nonzero(m2 == ref.thr))
+    say(f"  keys tied at the threshold: {ties}")
+    assert ties >= 65_536
+    assert abs(float(r["thr"][0]) - ref.thr) <= U.REL * ref.thr
+    assert int(r["stop_tree"][0]) == ref.stop_tree
+    U.compare_result(ref.ids, ref.dists, X, q, ids[0].cpu().numpy(), dists[0].cpu().numpy(), ref.S, k)
 
 
 @pytest.mark.parametrize("n,d,kind,k,nq", [(70_001, 128, "integer", 10, 150), (66_000, 37, "mixture", 20, 130),
