@@ -95,6 +95,11 @@ typedef struct {
     const int64_t* sample_ids;  /* host, floor(sample_frac*n) distinct ids in [0,n)
                                    used to choose breakpoints (Alg. 1); NULL ->
                                    drawn uniformly without replacement from seed */
+    int32_t borrow_x;           /* 1: the index reads X in place instead of a copy
+                                   of its own; X must then stay allocated and
+                                   unchanged until detlsh_free, or until a
+                                   detlsh_insert, which moves the points into an
+                                   array the index owns.  0: X is copied      */
 } detlsh_build_opts;
 
 /*
@@ -121,8 +126,9 @@ typedef struct {
  * (L, K') limits are the kernels' register budget: the range query is compiled
  * per (L, K'), keeping a point's 2*L*K' cell edges (or its L screen vectors) in
  * registers, 128 of a wave's VGPRs at L*K' = 64.
- * X is copied: the caller may free it when the call returns.  On success
- * *out owns all of its device memory until detlsh_free.
+ * X is copied (the caller may free it when the call returns) unless
+ * opts->borrow_x is set.  On success *out owns all of its other device memory
+ * until detlsh_free.
  */
 detlsh_status detlsh_build_index(const float* X, int64_t n, int32_t d, int32_t L,
                                  int32_t K, int32_t N_r, double sample_frac,

@@ -47,8 +47,9 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, projection=PROJ_GAUSSIAN):
+def _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, projection=PROJ_GAUSSIAN, borrow_x=False):
     o = _lib.BuildOpts()
+    o.borrow_x = int(bool(borrow_x))
     o.projection = {"gaussian": PROJ_GAUSSIAN, "paa": PROJ_PAA}.get(projection, projection)
     o.seed = int(seed)
     o.max_leaf = int(max_leaf)
@@ -96,6 +97,7 @@ class Index:
             except TypeError:   # interpreter shutdown: the module is already torn down
                 pass
             self._h = None
+            self._borrowed_x = None
 
     @property
     def info(self) -> dict:
@@ -303,16 +305,21 @@ class Server:
 
 
 def build_index(X, L=4, K=16, N_r=256, sample_frac=0.01, A=None, sample_ids=None, seed=0, max_leaf=256,
-                keep_bf16=False, proj_bf16=False, projection="gaussian") -> Index:
+                keep_bf16=False, proj_bf16=False, projection="gaussian", borrow_x=False) -> Index:
     """Encoding and indexing phases over X (n x d float32, device or host).
-    projection="paa" with L=1 is DET-ONLY (PAA segment means)."""
+    projection="paa" with L=1 is DET-ONLY (PAA segment means).  borrow_x: the
+    index reads X's device memory in place (no copy); the index holds a
+    reference to the tensor, which must not be modified while the index lives."""
     X = _dev_f32(X, "X")
     keep = []
-    o = _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, projection)
+    o = _build_opts(seed, max_leaf, keep_bf16, proj_bf16, A, sample_ids, keep, projection, borrow_x)
     h = C.c_void_p()
     check(lib().detlsh_build_index(_ptr(X), X.shape[0], X.shape[1], int(L), int(K), int(N_r), float(sample_frac),
                                    C.byref(o), _stream_ptr(), C.byref(h)))
-    return Index(h)
+    idx = Index(h)
+    if borrow_x:
+        idx._borrowed_x = X
+    return idx
 
 
 def import_index(X, A, B, codes, L, K, N_r, max_leaf=256, keep_bf16=False) -> Index:

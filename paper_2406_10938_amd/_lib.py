@@ -27,6 +27,7 @@ class BuildOpts(C.Structure):
         ("projection", C.c_int32),
         ("A", C.POINTER(C.c_float)),
         ("sample_ids", C.POINTER(C.c_int64)),
+        ("borrow_x", C.c_int32),
     ]
 
 

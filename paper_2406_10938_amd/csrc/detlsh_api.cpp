@@ -56,6 +56,7 @@ bool is_device_ptr(const void* p) {
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;   // the caller's memory: never freed or cached here
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -68,9 +69,10 @@ struct DevBuf {
         return e;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
@@ -203,6 +205,10 @@ hipError_t pool_alloc(DevBuf& dst, size_t bytes, int dev) {
 // `after` so far has completed).
 void pool_give(DevBuf& src, int dev, hipStream_t after = nullptr, bool ordered = false) {
     if (!src.p) return;
+    if (src.borrowed) {
+        src.release();
+        return;
+    }
     DevBuf* b = new DevBuf;
     b->p = src.p;
     b->bytes = src.bytes;
@@ -505,7 +511,18 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
 // X == NULL: ix->X and ix->codes are already allocated and filled (index load).
 detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_build_opts* opts, hipStream_t st) {
     const int64_t nd = ix->n * ix->d;
-    if (X) {
+    if (X && opts && opts->borrow_x) {
+        // the kernels read X in place: it must live on the index's device
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, X) != hipSuccess || at.device != ix->device) {
+            (void)hipGetLastError();
+            return fail(DETLSH_EINVAL, "borrow_x: X must be memory of the index's device %d", ix->device);
+        }
+        ix->X.release();
+        ix->X.p = const_cast<float*>(X);
+        ix->X.bytes = (size_t)nd * 4;
+        ix->X.borrowed = true;
+    } else if (X) {
         HCHECK(pool_alloc(ix->X, (size_t)nd * 4, ix->device));
         HCHECK(hipMemcpyAsync(ix->X.p, X, (size_t)nd * 4, hipMemcpyDeviceToDevice, st));
     }
@@ -841,7 +858,7 @@ detlsh_status detlsh_insert(detlsh_index ix, const float* X_new, int64_t m, void
         HCHECK(dl_launch_project(pa, PROJ_ENCODE, st));
     }
     HCHECK(hipStreamSynchronize(st));
-    std::swap(ix->X.p, X.p); std::swap(ix->X.bytes, X.bytes);
+    std::swap(ix->X.p, X.p); std::swap(ix->X.bytes, X.bytes); std::swap(ix->X.borrowed, X.borrowed);
     std::swap(ix->codes.p, codes.p); std::swap(ix->codes.bytes, codes.bytes);
     if (keep_bf16) { std::swap(ix->Xbf.p, Xbf.p); std::swap(ix->Xbf.bytes, Xbf.bytes); }
     ix->n = n1;

@@ -619,3 +619,44 @@ def test_fixed_ladder_without_stop_is_answered_over_D(dl):
         assert np.array_equal(ids[qi].cpu().numpy(), ref_ids)
     with pytest.raises(dl.DetlshError, match="r_min"):
         idx.query(t(cc["Q"]), 7, 1.5, 0.1, rmin_policy=dl.RMIN_FIXED, r_min=0.0)
+
+
+def test_borrowed_x_answers_like_a_copy(dl):
+    """An index that reads X in place (borrow_x) answers bit for bit like one
+    built over a copy, in both precision forms, and leaves X unchanged; an
+    insert moves its points into an array of the index's own, after which it
+    answers like the copy-built index after the same insert, also once the
+    caller's X is gone."""
+    import torch
+    say("borrowed X n=20000 d=64")
+    c = U.case(n=24_000, d=64, L=4, K=16, N_r=64, frac=0.05, kind="mixture", nq=50, seed=91)
+    X1, X2 = c["X"][:20_000], c["X"][20_000:]
+    sample = c["sample"][c["sample"] < 20_000][:1000]
+    Xd = t(X1)
+    before = Xd.clone()
+    Q = t(c["Q"])
+    a = dl.build_index(Xd, 4, 16, 64, len(sample) / 20_000, A=c["A"], sample_ids=sample, keep_bf16=True)
+    b = dl.build_index(Xd, 4, 16, 64, len(sample) / 20_000, A=c["A"], sample_ids=sample, keep_bf16=True,
+                       borrow_x=True)
+    for prec in (dl.FP32, dl.BF16_RERANK):
+        ia, da = a.query(Q, 10, 1.5, 0.1, precision=prec)
+        ib, db = b.query(Q, 10, 1.5, 0.1, precision=prec)
+        assert torch.equal(ia, ib) and torch.equal(da, db)
+    torch.cuda.synchronize()
+    assert torch.equal(Xd, before)
+    a.insert(t(X2))
+    b.insert(t(X2))
+    # the caller's block goes back to torch's cache and is refilled with NaN:
+    # an index still reading it would return NaN distances
+    del Xd
+    b._borrowed_x = None   # the index owns its points now
+    torch.cuda.synchronize()
+    junk = torch.full_like(before, float("nan"))
+    ia, da = a.query(Q, 10, 1.5, 0.1)
+    ib, db = b.query(Q, 10, 1.5, 0.1)
+    assert torch.equal(ia, ib) and torch.equal(da, db)
+    assert not torch.isnan(db).any()
+    a.free()
+    b.free()
+    del junk
+    assert torch.equal(before, t(X1))
