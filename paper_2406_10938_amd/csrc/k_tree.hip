@@ -13,7 +13,6 @@
 
 namespace {
 
-constexpr int kStack = 288;
 
 __global__ void root_key_kernel(const uint8_t* __restrict__ codes_i, int64_t n, int K, int bits,
                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val)
@@ -61,6 +60,12 @@ __global__ void run_starts_kernel(const uint32_t* __restrict__ flag, const uint3
 // leaf written to its final place once); larger runs in place in HBM.
 template <int K>
 constexpr int split_cap() { return K <= 16 ? 1024 : 512; }
+
+// Depth-first stack: every split lengthens one dimension's prefix by a bit
+// (prefixes of 1 .. bits <= 8 bits), so a path has at most K (bits - 1) <= 7K
+// splits, and a pop followed by two pushes adds one entry per level.
+template <int K>
+constexpr int stack_cap() { return 7 * K + 2; }
 
 template <int K>
 struct NodeK {
@@ -113,15 +118,19 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
     int32_t* __restrict__ rec_start = T.rec_start[tree];
     uint8_t* __restrict__ rec_plen = T.rec_plen[tree];
     uint32_t* __restrict__ nleaf = T.nleaf[tree];
-    __shared__ NodeK<K> stack[kStack];
+    constexpr int kStackK = stack_cap<K>();
+    __shared__ NodeK<K> stack[kStackK];
     __shared__ NodeK<K> cur;
     __shared__ int sp;
     __shared__ uint32_t ones[K];
     __shared__ uint32_t wsum[4];
     __shared__ int cnt_leaf;
     __shared__ int best_j;
-    __shared__ int32_t lperm[2][CAP];          // LDS path: ids and code words, two buffers
-    __shared__ uint32_t lcode[2][CAP * CW];
+    // LDS path: the run's ids and code words in load order, once; the
+    // partitions permute 16-bit positions into them between two buffers
+    __shared__ int32_t lperm[CAP];
+    __shared__ uint32_t lcode[CAP * CW];
+    __shared__ uint16_t lidx[2][CAP];
 
     const int q = (int)(blockIdx.x - T.first[tree]);
     const int32_t s = run_start[q];
@@ -140,10 +149,11 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
     const bool small = t - s <= CAP;
     if (small) {
         for (int r = tid; r < t - s; r += 256) {
-            lperm[0][r] = perm[s + r];
+            lperm[r] = perm[s + r];
             const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)(s + r) * K);
 #pragma unroll
-            for (int x = 0; x < CW; ++x) lcode[0][r * CW + x] = sw[x];
+            for (int x = 0; x < CW; ++x) lcode[r * CW + x] = sw[x];
+            lidx[0][r] = (uint16_t)r;
         }
     }
     if (tid == 0) {
@@ -176,10 +186,11 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
         if (size <= max_leaf || all_full) {
             if (small) {   // the leaf's points go to their final place
                 for (int r = a - s + tid; r < b - s; r += 256) {
-                    perm[s + r] = lperm[cb][r];
+                    const int i = lidx[cb][r];
+                    perm[s + r] = lperm[i];
                     uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)(s + r) * K);
 #pragma unroll
-                    for (int x = 0; x < CW; ++x) dw[x] = lcode[cb][r * CW + x];
+                    for (int x = 0; x < CW; ++x) dw[x] = lcode[i * CW + x];
                 }
             }
             if (tid == 0) {
@@ -199,9 +210,10 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
         for (int j = 0; j < K; ++j) loc[j] = 0;
         if (small) {
             for (int r = a - s + tid; r < b - s; r += 256) {
+                const int i = lidx[cb][r];
                 uint32_t w[CW];
 #pragma unroll
-                for (int x = 0; x < CW; ++x) w[x] = lcode[cb][r * CW + x];
+                for (int x = 0; x < CW; ++x) w[x] = lcode[i * CW + x];
                 split_count<K>(w, off, wid, loc);
             }
         } else {
@@ -243,9 +255,12 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             const int r = c0 + tid;
             const bool valid = r < b;
             uint32_t bit = 0;
-            if (valid)
-                bit = small ? (lcode[cb][(r - s) * CW + (j >> 2)] >> sh) & 1u
+            int li = 0;   // LDS path: the point's position in load order
+            if (valid) {
+                if (small) li = lidx[cb][r - s];
+                bit = small ? (lcode[li * CW + (j >> 2)] >> sh) & 1u
                             : (reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K)[j >> 2] >> sh) & 1u;
+            }
             const uint64_t om = dl_ballot(valid && bit);
             const uint64_t zm = dl_ballot(valid && !bit);
             const int orank = dl_rank_below(om), zrank = dl_rank_below(zm);
@@ -260,9 +275,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             if (valid) {
                 const int dst = bit ? a + nz + (int)(obase + opre) + orank : a + (int)(zbase + zpre) + zrank;
                 if (small) {
-                    lperm[nb][dst - s] = lperm[cb][r - s];
-#pragma unroll
-                    for (int x = 0; x < CW; ++x) lcode[nb][(dst - s) * CW + x] = lcode[cb][(r - s) * CW + x];
+                    lidx[nb][dst - s] = (uint16_t)li;
                 } else {
                     tperm[dst] = perm[r];
                     const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K);
@@ -292,12 +305,12 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             // would live in scratch memory)
             const uint8_t pj = (uint8_t)(cur.plen[j] + 1);
             const int cbuf = small ? nb : 0;
-            if (b - (a + nz) > 0 && sp < kStack) {
+            if (b - (a + nz) > 0 && sp < kStackK) {
                 stack[sp] = cur;
                 stack[sp].a = a + nz; stack[sp].b = b; stack[sp].buf = cbuf; stack[sp].plen[j] = pj;
                 ++sp;
             }
-            if (nz > 0 && sp < kStack) {
+            if (nz > 0 && sp < kStackK) {
                 stack[sp] = cur;
                 stack[sp].a = a; stack[sp].b = a + nz; stack[sp].buf = cbuf; stack[sp].plen[j] = pj;
                 ++sp;
