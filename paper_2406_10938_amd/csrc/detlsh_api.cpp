@@ -333,6 +333,7 @@ struct detlsh_index_s {
     int64_t n_s = 0;
     int32_t max_leaf = 256;
     int32_t proj_bf16 = 0;
+    bool xbf_pending = false;     // Xbf allocated, to be written with the row norms
     DevBuf X, Xbf, A, Abf, B, E, codes, perm, scodes, xn, xn_bf, gcodes, leaf_of, gleaf;
     DevBuf ballb;                 // point vectors of the filter's MFMA screen, FP16, [L][n][KB]
     DevBuf codes_pm;              // codes point-major, [n][L*K] (the screen's exact pass)
@@ -423,7 +424,8 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
         HCHECK(pool_alloc(xe, (size_t)ix->n * 4, ix->device));
         HCHECK(pool_alloc(mx, 4, ix->device));
         HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), ix->xn_bf.as<float>(),
-                                   xe.as<float>(), st));
+                                   xe.as<float>(), ix->xbf_pending ? ix->Xbf.as<uint16_t>() : nullptr, st));
+        ix->xbf_pending = false;
         HCHECK(dl_launch_max_f32(xe.as<float>(), ix->n, mx.as<uint32_t>(), st));
         uint32_t bits = 0;
         HCHECK(hipMemcpyAsync(&bits, mx.p, 4, hipMemcpyDeviceToHost, st));
@@ -435,7 +437,7 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
         ix->emax = (float)(std::sqrt((double)e2 * (1.0 + (ix->d + 8.0) * std::ldexp(1.0, -24))) *
                            (1.0 + std::ldexp(1.0, -20)));
     } else {
-        HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), nullptr, nullptr, st));
+        HCHECK(dl_launch_row_norms(ix->X.as<float>(), ix->n, ix->d, ix->xn.as<float>(), nullptr, nullptr, nullptr, st));
     }
     if (dl_ball_supported(ix->L, ix->K)) {
         HCHECK(pool_alloc(ix->ballb, (size_t)ix->n * ix->L * dl_ball_width(ix->K) * 2, ix->device));
@@ -530,8 +532,12 @@ detlsh_status alloc_common(detlsh_index_s* ix, const float* X, const detlsh_buil
     if (want_bf) {
         HCHECK(pool_alloc(ix->Xbf, xbf_bytes(ix->n, ix->d), ix->device));
         HCHECK(hipMemsetAsync(ix->Xbf.as<uint16_t>() + nd, 0, xbf_bytes(ix->n, ix->d) - (size_t)nd * 2, st));
-        DlTimer tm(T_BF16, st);
-        HCHECK(dl_launch_to_bf16(ix->X.as<float>(), ix->Xbf.as<uint16_t>(), nd, st));
+        if (opts->proj_bf16) {   // the BF16 projection reads it
+            DlTimer tm(T_BF16, st);
+            HCHECK(dl_launch_to_bf16(ix->X.as<float>(), ix->Xbf.as<uint16_t>(), nd, st));
+        } else {
+            ix->xbf_pending = true;   // written by the row norms' pass over X (finish_index)
+        }
     }
     HCHECK(pool_alloc(ix->A, (size_t)ix->LK * ix->d * 4, ix->device));
     HCHECK(hipMemcpyAsync(ix->A.p, ix->A_host.data(), (size_t)ix->LK * ix->d * 4, hipMemcpyHostToDevice, st));

@@ -29,7 +29,7 @@ struct ProjectArgs {
 hipError_t dl_launch_project(const ProjectArgs& a, int mode, hipStream_t st);
 hipError_t dl_launch_to_bf16(const float* x, uint16_t* y, int64_t cnt, hipStream_t st);
 // xe (optional): squared norm of each row's BF16 rounding error.
-hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe,
+hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe, uint16_t* xbf,
                                hipStream_t st);
 // Bit pattern of the largest of n non-negative floats into *out (which the
 // launch clears first).

@@ -522,9 +522,11 @@ __global__ void row_norms_kernel(const float* __restrict__ X, int64_t n, int d, 
 // d a multiple of 4: sixteen lanes per row (sixteen rows per workgroup),
 // four-element vector loads, reductions over the sixteen lanes.  The sums'
 // order differs from row_norms_kernel; every use of the norms allows any order.
+// With xbf it also writes the BF16 rounding of every value (the copy the
+// dense verification reads), from the same pass over X.
 __global__ __launch_bounds__(256) void row_norms16_kernel(const float* __restrict__ X, int64_t n, int d,
                                                           float* __restrict__ xn, float* __restrict__ xn_bf,
-                                                          float* __restrict__ xe)
+                                                          float* __restrict__ xe, uint16_t* __restrict__ xbf)
 {
     const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     const int l = threadIdx.x & 15;
@@ -534,14 +536,19 @@ __global__ __launch_bounds__(256) void row_norms16_kernel(const float* __restric
     for (int c = 4 * l; c < d; c += 64) {
         const float4 v4 = *reinterpret_cast<const float4*>(x + c);
         const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+        uint16_t h[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             a = fmaf(v[t], v[t], a);
-            const float w = dl_bf16_to_f32(dl_f32_to_bf16(v[t]));
+            h[t] = dl_f32_to_bf16(v[t]);
+            const float w = dl_bf16_to_f32(h[t]);
             b = fmaf(w, w, b);
             const float r = v[t] - w;
             e = fmaf(r, r, e);
         }
+        if (xbf && live)
+            *reinterpret_cast<uint2*>(xbf + row * d + c) =
+                make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
     }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) {
@@ -556,14 +563,19 @@ __global__ __launch_bounds__(256) void row_norms16_kernel(const float* __restric
     }
 }
 
-hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe,
+hipError_t dl_launch_row_norms(const float* X, int64_t n, int d, float* xn, float* xn_bf, float* xe, uint16_t* xbf,
                                hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (d % 4 == 0)
+    if (d % 4 == 0) {
         hipLaunchKernelGGL(row_norms16_kernel, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, X, n, d, xn, xn_bf,
-                           xe);
-    else
+                           xe, xbf);
+    } else {
+        if (xbf) {
+            const hipError_t e = dl_launch_to_bf16(X, xbf, n * (int64_t)d, st);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, d, xn, xn_bf, xe);
+    }
     return hipGetLastError();
 }
 
