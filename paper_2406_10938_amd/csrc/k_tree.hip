@@ -20,9 +20,15 @@ __global__ void root_key_kernel(const uint8_t* __restrict__ codes_i, int64_t n, 
     int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; o < n; o += stride) {
-        const uint8_t* c = codes_i + o * K;
+        // K is a multiple of 4: the row's codes as K/4 words (byte j of the
+        // row is byte j%4 of word j/4)
+        const uint32_t* c = reinterpret_cast<const uint32_t*>(codes_i + o * K);
         uint32_t k = 0;
-        for (int j = 0; j < K; ++j) k = (k << 1) | ((c[j] >> (bits - 1)) & 1u);
+        for (int w = 0; w < K / 4; ++w) {
+            const uint32_t v = c[w];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) k = (k << 1) | ((v >> (8 * b + bits - 1)) & 1u);
+        }
         key[o] = k;
         val[o] = (uint32_t)o;
     }
@@ -39,9 +45,15 @@ __global__ void gather_runs_kernel(const uint8_t* __restrict__ codes_i, const ui
     for (; r < n; r += stride) {
         const uint32_t o = val[r];
         perm[r] = (int32_t)o;
-        const uint32_t* s = reinterpret_cast<const uint32_t*>(codes_i + (int64_t)o * K);
-        uint32_t* d = reinterpret_cast<uint32_t*>(scodes + r * K);
-        for (int w = 0; w < K / 4; ++w) d[w] = s[w];
+        if (K % 16 == 0) {   // 16-byte rows: one load and one store per 16 codes
+            const uint4* s = reinterpret_cast<const uint4*>(codes_i + (int64_t)o * K);
+            uint4* d = reinterpret_cast<uint4*>(scodes + r * K);
+            for (int w = 0; w < K / 16; ++w) d[w] = s[w];
+        } else {
+            const uint32_t* s = reinterpret_cast<const uint32_t*>(codes_i + (int64_t)o * K);
+            uint32_t* d = reinterpret_cast<uint32_t*>(scodes + r * K);
+            for (int w = 0; w < K / 4; ++w) d[w] = s[w];
+        }
         flag[r] = (r == 0 || key[r] != key[r - 1]) ? 1u : 0u;
     }
 }
