@@ -501,12 +501,14 @@ detlsh_status finish_index(detlsh_index_s* ix, bool keep_bf16, hipStream_t st) {
     // point -> leaf of every tree, and the leaves of the guess subset
     HCHECK(pool_alloc(ix->leaf_of, (size_t)ix->n * ix->L * 4, ix->device));
     HCHECK(pool_alloc(ix->gleaf, (size_t)ix->G * ix->L * 4, ix->device));
+    DevBuf blk;   // first leaf of every 256-position block (scratch, one tree at a time)
+    HCHECK(pool_alloc(blk, (size_t)((ix->n + 255) / 256) * 4, ix->device));
     for (int i = 0; i < ix->L; ++i)
         HCHECK(dl_launch_leaf_of(ix->perm.as<int32_t>() + (int64_t)i * ix->n, ix->leaf_start[i], ix->n_leaves[i],
-                                 ix->n, ix->leaf_of.as<int32_t>() + (int64_t)i * ix->n, st));
+                                 ix->n, blk.as<int32_t>(), ix->leaf_of.as<int32_t>() + (int64_t)i * ix->n, st));
     HCHECK(dl_launch_pack_sample_leaves(ix->leaf_of.as<int32_t>(), ix->n, ix->L, ix->G, ix->gleaf.as<int32_t>(), st));
     HCHECK(hipStreamSynchronize(st));
-    for (DevBuf* b : {&xe, &mx, &tmp, &tot}) pool_give(*b, ix->device);
+    for (DevBuf* b : {&xe, &mx, &tmp, &tot, &blk}) pool_give(*b, ix->device);
     return DETLSH_OK;
 }
 

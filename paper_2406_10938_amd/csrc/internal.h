@@ -176,8 +176,8 @@ hipError_t dl_launch_ladder(float* out, int rounds, double eps, double r_min, do
 size_t dl_verify_smem(int d, int k);   // LDS bytes of the gathered verification
 hipError_t dl_launch_guess(const QueryArgs& a, hipStream_t st);
 // leaf_of of one tree: out[perm[p]] = the leaf whose run holds position p.
-hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* out,
-                             hipStream_t st);
+hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* blk,
+                             int32_t* out, hipStream_t st);   // blk: (n + 255) / 256 int32 of scratch
 // Leaves of the guess subset: out[i*G + p] = leaf_of[i*n + o_p].
 hipError_t dl_launch_pack_sample_leaves(const int32_t* leaf_of, int64_t n, int L, int G, int32_t* out,
                                         hipStream_t st);

@@ -2350,18 +2350,38 @@ hipError_t launch_stop_exact(const QueryArgs& a, hipStream_t st) { DL_LK_DISPATC
 
 namespace {
 
+// The leaves' runs partition the positions [0, n) in order (start[nleaves] =
+// n).  blk[b] = the leaf whose run holds position 256 b: each leaf writes the
+// blocks whose first position it holds.
+__global__ __launch_bounds__(256) void leaf_block_kernel(const int32_t* __restrict__ start, int64_t nleaves,
+                                                         int32_t* __restrict__ blk)
+{
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l >= nleaves) return;
+    const int64_t s = start[l], e = start[l + 1];
+    for (int64_t b = (s + 255) / 256; 256 * b < e; ++b) blk[b] = (int32_t)l;
+}
+
+// Leaf of every position of a 256-position block: the block's first leaf is
+// blk[block] and at most 255 more start inside the block, so the last of the
+// 257 staged run starts at or before the position is its leaf.
 __global__ __launch_bounds__(256) void leaf_of_kernel(const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ start, int64_t nleaves, int64_t n,
-                                                      int32_t* __restrict__ out)
+                                                      const int32_t* __restrict__ blk, int32_t* __restrict__ out)
 {
+    __shared__ int32_t ss[257];
+    const int64_t lo = blk[blockIdx.x];
+    const int m = (int)(nleaves - lo < 257 ? nleaves - lo : 257);
+    for (int x = threadIdx.x; x < m; x += 256) ss[x] = start[lo + x];
+    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
-    int64_t lo = 0, hi = nleaves - 1;   // the last leaf whose run starts at or before p
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= p) lo = mid; else hi = mid - 1;
+    int a = 0, z = m - 1;   // ss[0] <= p
+    while (a < z) {
+        const int mid = (a + z + 1) >> 1;
+        if (ss[mid] <= p) a = mid; else z = mid - 1;
     }
-    out[perm[p]] = (int32_t)lo;
+    out[perm[p]] = (int32_t)(lo + a);
 }
 
 __global__ __launch_bounds__(256) void pack_sample_leaves_kernel(const int32_t* __restrict__ leaf_of, int64_t n,
@@ -2377,11 +2397,13 @@ __global__ __launch_bounds__(256) void pack_sample_leaves_kernel(const int32_t* 
 
 }  // namespace
 
-hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* out,
-                             hipStream_t st) {
+hipError_t dl_launch_leaf_of(const int32_t* perm, const int32_t* start, int64_t nleaves, int64_t n, int32_t* blk,
+                             int32_t* out, hipStream_t st) {
     if (nleaves < 1 || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(leaf_block_kernel, dim3((unsigned)((nleaves + 255) / 256)), dim3(256), 0, st, start, nleaves,
+                       blk);
     hipLaunchKernelGGL(leaf_of_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, start, nleaves, n,
-                       out);
+                       blk, out);
     return hipGetLastError();
 }
 
