@@ -274,7 +274,7 @@ __device__ float select_rank_f32(Get get, int64_t m, uint64_t r, SelectShared& s
 // keys over many bins instead of the few that the top 12 bits (sign,
 // exponent, 3 mantissa bits) give.  When the r-th key is not inside the
 // window (it lies below, or keys exceed hi) the three-pass selection runs.
-// The keys are a contiguous, 16-byte aligned array, read four per load with two
+// The keys are a contiguous, 16-byte aligned array, read four per load with four
 // loads in flight per thread.
 constexpr uint32_t kSelWin = 1u << 25;
 
@@ -284,10 +284,12 @@ __device__ uint32_t select_rank_u32_upto_v(const uint32_t* __restrict__ arr, int
     const int64_t m4 = m >> 2;
     auto pass = [&](auto count) {
         int64_t i = threadIdx.x;
-        for (; i + 256 < m4; i += 512) {
-            const uint4 v = a4[i], w = a4[i + 256];
+        for (; i + 768 < m4; i += 1024) {
+            const uint4 v = a4[i], w = a4[i + 256], x = a4[i + 512], y = a4[i + 768];
             count(v.x); count(v.y); count(v.z); count(v.w);
             count(w.x); count(w.y); count(w.z); count(w.w);
+            count(x.x); count(x.y); count(x.z); count(x.w);
+            count(y.x); count(y.y); count(y.z); count(y.w);
         }
         for (; i < m4; i += 256) {
             const uint4 v = a4[i];
@@ -766,17 +768,10 @@ __global__ __launch_bounds__(256, 6) void select_kernel(const uint32_t* __restri
         const float* pmt = cand_lb + (int64_t)t * cap * NP;
         uint32_t u1 = 0, u2 = 0;   // |U_{L-1}|, |U_{L-2}|
         if (L >= 2) {
-            // NP floats per entry, rows start 16-byte aligned: 16-byte loads
+            // NP floats per entry, rows start 16-byte aligned: 16-byte loads,
+            // two in flight per thread
             const int64_t nf = (int64_t)cnt * NP;
-            for (int64_t f0 = 4 * (int64_t)threadIdx.x; f0 < nf; f0 += 1024) {
-                float v[4];
-                if (f0 + 3 < nf) {
-                    const float4 a4 = *reinterpret_cast<const float4*>(pmt + f0);
-                    v[0] = a4.x; v[1] = a4.y; v[2] = a4.z; v[3] = a4.w;
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j] = f0 + j < nf ? pmt[f0 + j] : INFINITY;
-                }
+            auto tally = [&](const float (&v)[4]) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     // with NP = 2 even slots are p2 and odd slots p1
@@ -785,6 +780,25 @@ __global__ __launch_bounds__(256, 6) void select_kernel(const uint32_t* __restri
                     u1 += (in && is_p1) ? 1u : 0u;
                     u2 += (in && !is_p1) ? 1u : 0u;
                 }
+            };
+            int64_t f0 = 4 * (int64_t)threadIdx.x;
+            for (; f0 + 1024 + 3 < nf; f0 += 2048) {
+                const float4 a4 = *reinterpret_cast<const float4*>(pmt + f0);
+                const float4 b4 = *reinterpret_cast<const float4*>(pmt + f0 + 1024);
+                const float va[4] = {a4.x, a4.y, a4.z, a4.w}, vb[4] = {b4.x, b4.y, b4.z, b4.w};
+                tally(va);
+                tally(vb);
+            }
+            for (; f0 < nf; f0 += 1024) {
+                float v[4];
+                if (f0 + 3 < nf) {
+                    const float4 a4 = *reinterpret_cast<const float4*>(pmt + f0);
+                    v[0] = a4.x; v[1] = a4.y; v[2] = a4.z; v[3] = a4.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = f0 + j < nf ? pmt[f0 + j] : INFINITY;
+                }
+                tally(v);
             }
         }
         u1 = dl_wave_sum(u1);
