@@ -27,42 +27,61 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
 }
 
 // Stable scatter: key i of the tile goes to offs[digit*nblocks+block] + (number of
-// earlier keys of the tile with the same digit).  Keys are taken row by row
-// (row r = keys base + r*256 .. +255), lanes in order, waves in order.
+// earlier keys of the tile with the same digit).  Wave w takes the tile's w-th
+// quarter (16 rows of 64 keys, in index order) into registers and ranks each
+// key among the earlier keys of its quarter with the same digit (lane order
+// within a row, running per-digit counts of the wave in LDS across rows; the
+// wave's own LDS operations stay in order, so no barrier); one pass over the
+// digits then turns the four waves' counts into their starting positions.
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
     const uint32_t* __restrict__ offs, int nblocks)
 {
-    __shared__ uint32_t run[256];        // running output position per digit
-    __shared__ uint32_t wcnt[4][256];    // per-wave digit counts of the current row
+    constexpr int kWaveRows = kSortTile / 4 / 64;   // 16 rows of 64 keys per wave
+    __shared__ uint32_t wc[4][256];                 // per wave and digit: count, then start
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortRows; ++r) {
-        const int64_t i = base + r * kSortThreads + threadIdx.x;
-        const bool valid = i < n;
-        uint32_t k = 0, v = 0;
-        if (valid) { k = kin[i]; v = vin[i]; }
-        const uint32_t dg = (k >> shift) & 0xffu;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0;
-        __syncthreads();
+    for (int w = 0; w < 4; ++w) wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * (kSortTile / 4);
+    uint32_t k[kWaveRows], v[kWaveRows], pos[kWaveRows];
+#pragma unroll
+    for (int r = 0; r < kWaveRows; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        k[r] = i < n ? kin[i] : 0u;
+        v[r] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kWaveRows; ++r) {
+        const bool valid = wbase + r * 64 + lane < n;
+        const uint32_t dg = (k[r] >> shift) & 0xffu;
         const uint64_t peers = dl_match8(dg, valid);
         const int rank = dl_rank_below(peers);
-        if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[dg] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
-            kout[pos] = k;
-            vout[pos] = v;
+        const uint32_t before = wc[wave][dg];
+        pos[r] = before + (uint32_t)rank;
+        if (valid && rank == 0) wc[wave][dg] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;   // digit d: the tile's base, then the waves in order
+        uint32_t acc = offs[(int64_t)d * nblocks + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t c = wc[w][d];
+            wc[w][d] = acc;
+            acc += c;
         }
-        __syncthreads();
-        run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
-                            wcnt[3][threadIdx.x];
-        (void)lane;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kWaveRows; ++r) {
+        if (wbase + r * 64 + lane < n) {
+            const uint32_t p = wc[wave][(k[r] >> shift) & 0xffu] + pos[r];
+            kout[p] = k[r];
+            vout[p] = v[r];
+        }
     }
 }
 
