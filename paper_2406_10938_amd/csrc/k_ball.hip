@@ -116,9 +116,12 @@ __global__ __launch_bounds__(256) void ball_table_kernel(const uint8_t* __restri
         const float* Ee = E + (int64_t)(i * K + j) * ldE;
         const float a = Ee[1], b = Ee[N_r - 1];
         const int code = c[j];
-        const double lo = (double)(clampf(Ee[code], a, b) * sc);       // region 0 starts at -inf
-        const double hi = (double)(clampf(Ee[code + 1], a, b) * sc);   // region N_r-1 ends at +inf
-        const float cj = f16r((float)(0.5 * (lo + hi)));
+        const float lof = clampf(Ee[code], a, b) * sc;       // region 0 starts at -inf
+        const float hif = clampf(Ee[code + 1], a, b) * sc;   // region N_r-1 ends at +inf
+        const double lo = (double)lof, hi = (double)hif;
+        // the midpoint in FP32 (any rounding of it serves: W is measured from
+        // the c^ taken), then to FP16 by the conversion instruction
+        const float cj = f16r(0.5f * (lof + hif));
         const double w = fmax(hi - (double)cj, (double)cj - lo);      // farthest edge from c^ (>= 0)
         v[j] = cj;
         cc += (double)cj * (double)cj;   // exact: FP16 squares

@@ -59,7 +59,7 @@ def table(E, codes, planted=False):
     j = np.arange(K)
     lo = np.clip(E[j, codes], a, b).astype(np.float32) * s
     hi = np.clip(E[j, codes + 1], a, b).astype(np.float32) * s
-    c = f16r((0.5 * (lo.astype(np.float64) + hi.astype(np.float64))).astype(np.float32))
+    c = f16r(np.float32(0.5) * (lo + hi))   # the FP32 midpoint, as the kernel forms it
     w = np.maximum(hi.astype(np.float64) - c, c.astype(np.float64) - lo)
     cc = np.sum(c.astype(np.float64) ** 2, axis=1)
     if planted:
