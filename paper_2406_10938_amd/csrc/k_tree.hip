@@ -82,7 +82,7 @@ constexpr int stack_cap() { return 7 * K + 2; }
 template <int K>
 struct NodeK {
     int32_t a, b;     // the node's positions [a, b) in the run's tree arrays
-    int32_t buf;      // LDS path: the buffer that holds the node's points
+    int32_t buf;      // the LDS buffer that holds the node's points, -1 in HBM
     uint8_t plen[K];  // prefix length of every dimension
 };
 
@@ -138,8 +138,11 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
     __shared__ uint32_t wsum[4];
     __shared__ int cnt_leaf;
     __shared__ int best_j;
-    // LDS path: the run's ids and code words in load order, once; the
-    // partitions permute 16-bit positions into them between two buffers
+    // LDS path: a node's ids and code words in load order, once; the
+    // partitions of its subtree permute 16-bit positions into them between
+    // two buffers.  A node is loaded when it needs a split and fits (the whole
+    // run when it fits); until its subtree is done (depth first) every node
+    // popped is in it, so one base serves them all.
     __shared__ int32_t lperm[CAP];
     __shared__ uint32_t lcode[CAP * CW];
     __shared__ uint16_t lidx[2][CAP];
@@ -158,21 +161,12 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
         }
         return;
     }
-    const bool small = t - s <= CAP;
-    if (small) {
-        for (int r = tid; r < t - s; r += 256) {
-            lperm[r] = perm[s + r];
-            const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)(s + r) * K);
-#pragma unroll
-            for (int x = 0; x < CW; ++x) lcode[r * CW + x] = sw[x];
-            lidx[0][r] = (uint16_t)r;
-        }
-    }
+    int32_t lb = s;   // position of lperm[0] (the loaded node's first position)
     if (tid == 0) {
         sp = 1;
         stack[0].a = s;
         stack[0].b = t;
-        stack[0].buf = 0;
+        stack[0].buf = -1;
         for (int j = 0; j < K; ++j) stack[0].plen[j] = 1;
         cnt_leaf = 0;
     }
@@ -185,7 +179,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
         __syncthreads();
         if (cur.a < 0) break;
         const int a = cur.a, b = cur.b, size = b - a;
-        const int cb = cur.buf;
+        int cb = cur.buf;
         bool all_full = true;
         uint32_t off[K], wid[K];
 #pragma unroll
@@ -196,11 +190,11 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             wid[j] = pl < bits ? 1u : 0u;
         }
         if (size <= max_leaf || all_full) {
-            if (small) {   // the leaf's points go to their final place
-                for (int r = a - s + tid; r < b - s; r += 256) {
+            if (cb >= 0) {   // the leaf's points go to their final place (HBM leaves are in place)
+                for (int r = a - lb + tid; r < b - lb; r += 256) {
                     const int i = lidx[cb][r];
-                    perm[s + r] = lperm[i];
-                    uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)(s + r) * K);
+                    perm[lb + r] = lperm[i];
+                    uint32_t* dw = reinterpret_cast<uint32_t*>(scodes + (int64_t)(lb + r) * K);
 #pragma unroll
                     for (int x = 0; x < CW; ++x) dw[x] = lcode[i * CW + x];
                 }
@@ -214,6 +208,18 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             __syncthreads();
             continue;
         }
+        if (cb < 0 && size <= CAP) {   // the node's subtree is split inside LDS
+            for (int r = tid; r < size; r += 256) {
+                lperm[r] = perm[a + r];
+                const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)(a + r) * K);
+#pragma unroll
+                for (int x = 0; x < CW; ++x) lcode[r * CW + x] = sw[x];
+                lidx[0][r] = (uint16_t)r;
+            }
+            lb = a;
+            cb = 0;
+        }
+        const bool small = cb >= 0;
         // count ones of the next bit of every open dimension
         if (tid < K) ones[tid] = 0;
         __syncthreads();
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
 #pragma unroll
         for (int j = 0; j < K; ++j) loc[j] = 0;
         if (small) {
-            for (int r = a - s + tid; r < b - s; r += 256) {
+            for (int r = a - lb + tid; r < b - lb; r += 256) {
                 const int i = lidx[cb][r];
                 uint32_t w[CW];
 #pragma unroll
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             uint32_t bit = 0;
             int li = 0;   // LDS path: the point's position in load order
             if (valid) {
-                if (small) li = lidx[cb][r - s];
+                if (small) li = lidx[cb][r - lb];
                 bit = small ? (lcode[li * CW + (j >> 2)] >> sh) & 1u
                             : (reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K)[j >> 2] >> sh) & 1u;
             }
@@ -287,7 +293,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             if (valid) {
                 const int dst = bit ? a + nz + (int)(obase + opre) + orank : a + (int)(zbase + zpre) + zrank;
                 if (small) {
-                    lidx[nb][dst - s] = (uint16_t)li;
+                    lidx[nb][dst - lb] = (uint16_t)li;
                 } else {
                     tperm[dst] = perm[r];
                     const uint32_t* sw = reinterpret_cast<const uint32_t*>(scodes + (int64_t)r * K);
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(256) void split_runs_kernel(SplitTrees T, int bits,
             // first (built in place in LDS: a copy in registers, indexed by j,
             // would live in scratch memory)
             const uint8_t pj = (uint8_t)(cur.plen[j] + 1);
-            const int cbuf = small ? nb : 0;
+            const int cbuf = small ? nb : -1;
             if (b - (a + nz) > 0 && sp < kStackK) {
                 stack[sp] = cur;
                 stack[sp].a = a + nz; stack[sp].b = b; stack[sp].buf = cbuf; stack[sp].plen[j] = pj;
