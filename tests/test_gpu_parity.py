@@ -1,7 +1,7 @@
 """GPU parity of every step of the hot path against the FP64 oracle, through
 the C ABI, on seeded inputs that span several tiles and a ragged tail.
 
-Tolerances (BASELINE the benchmark spec): projected coordinates within 1e-5 of the
+Tolerances: projected coordinates within 1e-5 of the
 dot product's magnitude sum_l |a_l o_l|; codes bit-exact except coordinates
 that close to a breakpoint (counted); candidate sets bit-exact when fed the
 oracle's codes, breakpoints and projected queries, except points whose FP64
