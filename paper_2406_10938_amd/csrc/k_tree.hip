@@ -69,7 +69,8 @@ __global__ void run_starts_kernel(const uint32_t* __restrict__ flag, const uint3
 }
 
 // Runs of up to split_cap<K>() points are split inside LDS (loaded once, each
-// leaf written to its final place once); larger runs in place in HBM.
+// leaf written to its final place once); a larger run is split in place in
+// HBM until a node that needs a split fits, which then moves into LDS.
 template <int K>
 constexpr int split_cap() { return K <= 16 ? 1024 : 512; }
 
