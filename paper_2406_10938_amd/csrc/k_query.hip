@@ -1081,14 +1081,14 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
     const int hw = threadIdx.x >> 5;
     constexpr int R = 8;
     for (int64_t s0 = (int64_t)hw * R; s0 < m; s0 += 8 * R) {
-        int64_t id[R];
+        int32_t id[R];   // ids and list entries are below 2^31
         float acc[R], cmp[R];
         bool skip[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t s = s0 + r;
             const int64_t e = (m_full > m) ? (s >> 5) * ((m_full << 5) / m) + (s & 31) : s;   // the list entry
-            id[r] = (s < m) ? (ids ? (int64_t)ids[e] : e) : -1;
+            id[r] = (s < m) ? (ids ? ids[e] : (int32_t)e) : -1;
             skip[r] = false;
             if (use_ims && id[r] >= 0) {
                 if (!ims.member(e)) {
@@ -1105,7 +1105,7 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
                 float4 v[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    v[r] = (id[r] >= 0) ? *reinterpret_cast<const float4*>(X + id[r] * d + c)
+                    v[r] = (id[r] >= 0) ? *reinterpret_cast<const float4*>(X + (int64_t)id[r] * d + c)
                                         : make_float4(0.f, 0.f, 0.f, 0.f);
                 const float q0v = sq[c], q1v = sq[c + 1], q2v = sq[c + 2], q3v = sq[c + 3];
 #pragma unroll
@@ -1126,7 +1126,7 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (id[r] < 0) continue;
-                    const float* x = X + id[r] * d;
+                    const float* x = X + (int64_t)id[r] * d;
                     for (int u = 0; u < 4; ++u) {
                         if (c + u >= d) continue;
                         if constexpr (COMP) {
@@ -1139,23 +1139,50 @@ __device__ __forceinline__ void gather_keys(const float* __restrict__ X, int d, 
                 }
             }
         }
+        if constexpr (COMP) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float a2 = acc[r];
-            if constexpr (COMP) {
-                float c2 = cmp[r];
+            for (int r = 0; r < R; ++r) {
+                float a2 = acc[r], c2 = cmp[r];
 #pragma unroll
                 for (int o2 = 16; o2 > 0; o2 >>= 1) {
                     const float b2 = __shfl_xor(a2, o2, 32), cb2 = __shfl_xor(c2, o2, 32);
                     comp_merge(a2, c2, b2, cb2);
                 }
                 a2 = a2 + c2;
-            } else {
-#pragma unroll
-                for (int o2 = 16; o2 > 0; o2 >>= 1) a2 += __shfl_xor(a2, o2, 32);
+                if (hl == 0 && id[r] >= 0 && !skip[r])
+                    buf[s0 + r] = ((uint64_t)__float_as_uint(a2) << 32) | (uint64_t)(uint32_t)id[r];
             }
-            if (hl == 0 && id[r] >= 0 && !skip[r])
-                buf[s0 + r] = ((uint64_t)__float_as_uint(a2) << 32) | (uint64_t)(uint32_t)id[r];
+        } else {
+            // the R = 8 sums over the half-wave at once: across lanes 16
+            // apart a lane keeps half of its rows and takes the partner's
+            // share of them (4, then 2, then 1 exchange), so lane hl ends with
+            // row 4 h + 2 b + c (h, b, c = bits 4, 3, 2 of hl) summed over
+            // the lanes that agree in those bits; two more exchanges finish
+            // it in every lane of its group of four
+            static_assert(R == 8, "three halving steps");
+            const bool h = (hl & 16) != 0, bb = (hl & 8) != 0, cc = (hl & 4) != 0;
+            float p4[4], p2[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float mine = h ? acc[i + 4] : acc[i], theirs = h ? acc[i] : acc[i + 4];
+                p4[i] = mine + __shfl_xor(theirs, 16, 32);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const float mine = bb ? p4[i + 2] : p4[i], theirs = bb ? p4[i] : p4[i + 2];
+                p2[i] = mine + __shfl_xor(theirs, 8, 32);
+            }
+            float a1 = (cc ? p2[1] : p2[0]) + __shfl_xor(cc ? p2[0] : p2[1], 4, 32);
+            a1 += __shfl_xor(a1, 2, 32);
+            a1 += __shfl_xor(a1, 1, 32);
+            const int r = (h ? 4 : 0) + (bb ? 2 : 0) + (cc ? 1 : 0);
+            int32_t idr = id[0];
+            bool skr = skip[0];
+#pragma unroll
+            for (int i = 1; i < R; ++i)
+                if (r == i) { idr = id[i]; skr = skip[i]; }
+            if ((hl & 3) == 0 && idr >= 0 && !skr)
+                buf[s0 + r] = ((uint64_t)__float_as_uint(a1) << 32) | (uint64_t)(uint32_t)idr;
         }
     }
     __threadfence_block();
