@@ -91,13 +91,14 @@ def test_breakpoints_and_codes(dl, n, d, N_r, frac, L, K):
     assert hard == 0
 
 
-@pytest.mark.parametrize("d", [16, 64])
+@pytest.mark.parametrize("d", [16, 32, 64, 96])
 def test_codes_across_persistent_tiles(dl, d):
     """The encode runs a persistent grid whose workgroups each take several
     512-row tiles once n exceeds 512 x 256 rows; codes past the first tile of
     every workgroup are compared with the oracle's too (n = 200,000).  d = 16
-    takes the FP32 products, d = 64 (a multiple of 32) the exact three-part
-    BF16 split of both operands."""
+    takes the FP32 products; d = 32, 64 and 96 (multiples of 32) the exact
+    three-part BF16 split of both operands, whose 32-wide chunks are loaded
+    two ahead across tile boundaries: one, two and three chunks per row."""
     n, L, K, N_r = 200_000, 4, 16, 256
     say(f"codes across persistent tiles n={n} d={d}")
     c = U.case(n=n, d=d, L=L, K=K, N_r=N_r, frac=0.01, seed=5)
